@@ -1,0 +1,182 @@
+/*
+ * spmm.h - block-sparse x dense matrix multiplication on AMD MI355X (gfx950).
+ *
+ * The operation is the SpMM of PopSparse (arXiv 2303.16999, Section 3):
+ *
+ *     Y = (M o W) * X,    M[i][j] = M_hat[i / b][j / b]
+ *
+ * W is m x k and keeps only the b x b blocks whose entry of the block mask
+ * M_hat (ceil(m/b) x ceil(k/b)) is one; X is k x n and dense; Y is m x n and
+ * dense. m and k are the feature sizes, n the batch size, b the block size
+ * (Section 3). Two modes follow Section 3.2 and 3.3:
+ *
+ *   static   the pattern is known ahead of time; a plan is built once and the
+ *            values are supplied later (Section 3.2);
+ *   dynamic  only a maximum number of nonzero blocks is fixed; the pattern and
+ *            values arrive with every call (Section 3.3, Appendix A.2).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Every function returns spmm_status_t. Nothing throws across the ABI.
+ *   spmm_last_error() returns a thread-local message for the last non-OK
+ *   status returned on the calling thread.
+ * - Argument errors are detected on the host and returned before any work is
+ *   enqueued.
+ * - Dense matrices are row-major with a leading dimension in elements
+ *   (ldx >= n, ldy >= n). X and Y base addresses must be 16-byte aligned and
+ *   ld * element_size must be a multiple of 16 bytes. Only columns [0, n) are
+ *   read from X and written to Y. Y must not overlap X.
+ * - "_dev" pointers are device memory (hipMalloc or a torch CUDA tensor),
+ *   "_host" pointers are host memory. The library never frees caller memory.
+ * - stream is a hipStream_t passed as void* (NULL = the default stream). Run
+ *   calls only enqueue work on that stream and return without synchronising;
+ *   X and Y are borrowed until that work completes.
+ * - beta = 0: Y is fully overwritten; rows without blocks become +0.0.
+ * - m and k need not be multiples of b: edge blocks are stored as full b x b
+ *   blocks and their part outside the matrix is ignored, even if it holds
+ *   non-finite values.
+ * - Accumulation is in FP32 for every dtype; the output is rounded to Y's
+ *   dtype to nearest-even. Results are bitwise reproducible run to run.
+ *
+ * Supported dtype triples (w, x, y):
+ *   (F32, F32, F32)
+ *   (F16, F16, F16 | F32)
+ *   (BF16, BF16, BF16 | F32)
+ *   (FP8_E4M3, F16 | BF16, same as x | F32)   one FP32 scale per block
+ * FP8_E4M3 is the OCP E4M3FN format (bias 7, max 448, no infinities). A block
+ * element stands for decode(code) * scale[block].
+ *
+ * Block sizes: b in {1, 4, 8, 16, 32}.
+ */
+#ifndef SPMM_H_
+#define SPMM_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SPMM_OK = 0,
+  SPMM_ERR_INVALID_ARG = 1,  /* bad pointer, size, alignment, leading dimension */
+  SPMM_ERR_UNSUPPORTED = 2,  /* valid request this build does not implement    */
+  SPMM_ERR_CAPACITY = 3,     /* dynamic nnz above the declared maximum          */
+  SPMM_ERR_BAD_INDEX = 4,    /* dynamic block index outside the block grid      */
+  SPMM_ERR_OOM = 5,          /* device allocation failed                        */
+  SPMM_ERR_HIP = 6,          /* a HIP runtime call failed                       */
+  SPMM_ERR_REJECTED = 7      /* serving admission refused the request           */
+} spmm_status_t;
+
+typedef enum { SPMM_F32 = 0, SPMM_F16 = 1, SPMM_BF16 = 2, SPMM_FP8_E4M3 = 3 } spmm_dtype_t;
+
+/* Plan options. Zero-initialise and set what you need.
+ *   group_rows  block rows one workgroup keeps in registers (0 = choose);
+ *   num_panels  contiguous ranges of row groups, balanced by cost, that one
+ *               workgroup walks in turn (0 = one group per panel);
+ *   n_hint      expected batch size n, used only to choose group_rows. */
+typedef struct {
+  int32_t group_rows;
+  int32_t num_panels;
+  int32_t n_hint;
+  int32_t reserved;
+} spmm_plan_opts;
+
+typedef struct spmm_plan_s* spmm_plan_t;
+typedef struct spmm_dyn_s* spmm_dyn_t;
+typedef struct spmm_group_s* spmm_group_t;
+typedef struct spmm_srv_s* spmm_srv_t;
+
+/* Message for the last non-OK status on this thread ("" if none). The pointer
+ * stays valid until the next library call on the same thread. */
+const char* spmm_last_error(void);
+
+/* ------------------------------------------------------------------ static mode
+ * Static sparsity, Section 3.2: the pattern is known when the plan is built
+ * (the paper's compile time); values are provided afterwards and reordered
+ * once into the plan's layout.
+ *
+ * spmm_plan_static builds the plan on the current HIP device from a host
+ * block mask: block_mask_host is uint8 [ceil(m/b)][ceil(k/b)] row-major,
+ * nonzero = block present. The block-CSR (row_ptr, col_idx), the row groups
+ * and the cost-balanced panels are computed by HIP kernels; the call
+ * synchronises before returning. opts may be NULL.
+ * Errors: INVALID_ARG (m, k < 1, b not in {1,4,8,16,32}, NULL pointers),
+ * UNSUPPORTED (dtype triple), OOM, HIP. On error *out is NULL. */
+spmm_status_t spmm_plan_static(int64_t m, int64_t k, int32_t b, const uint8_t* block_mask_host,
+                               spmm_dtype_t w, spmm_dtype_t x, spmm_dtype_t y,
+                               const spmm_plan_opts* opts, spmm_plan_t* out);
+
+/* Copies the nonzero block values into plan-owned device memory (the plan
+ * keeps them resident; the caller may free its buffer once the copy on
+ * `stream` has completed). values_dev holds nnzb blocks of b x b elements of
+ * dtype w, row-major inside each block, in block-CSR order (block rows in
+ * ascending order, columns ascending within a row: the row-major order of the
+ * mask). block_scales_dev: FP32 [nnzb] for FP8 weights, NULL otherwise.
+ * Must be called before spmm_run_static; may be called again to replace the
+ * values (stream-ordered with later runs on the same stream). */
+spmm_status_t spmm_plan_set_values(spmm_plan_t plan, const void* values_dev,
+                                   const float* block_scales_dev, void* stream);
+
+/* Y = (M o W) * X with the plan's pattern and values. X: k x n of dtype x,
+ * Y: m x n of dtype y. n = 0 is a no-op returning OK.
+ * Errors: INVALID_ARG (values not set, NULL, ld < n, alignment), HIP. */
+spmm_status_t spmm_run_static(spmm_plan_t plan, int64_t n, const void* X, int64_t ldx,
+                              void* Y, int64_t ldy, void* stream);
+
+/* Plan facts: nonzero blocks, block rows per group, number of groups, panels. */
+spmm_status_t spmm_plan_info(spmm_plan_t plan, int64_t* nnzb, int32_t* group_rows,
+                             int32_t* num_groups, int32_t* num_panels);
+
+/* Host copies of the plan arrays, for inspection and tests:
+ * row_ptr int32 [mb + 1], col_idx int32 [nnzb], panel_ptr int32 [num_panels + 1]
+ * (entries are group indices). Any pointer may be NULL to skip that array. */
+spmm_status_t spmm_plan_export(spmm_plan_t plan, int32_t* row_ptr, int32_t* col_idx,
+                               int32_t* panel_ptr);
+
+spmm_status_t spmm_plan_destroy(spmm_plan_t plan);
+
+/* ----------------------------------------------------------------- dynamic mode
+ * Dynamic sparsity, Section 3.3 and Appendix A.2: only the maximum number of
+ * nonzero blocks is fixed at creation (the paper's d_max); all buffers are
+ * sized from it (the paper's bucket sizing), and every call brings a new
+ * pattern as a COO list of blocks that is re-bucketed on the device.
+ *
+ * spmm_dynamic_create allocates capacity for max_nnzb blocks of an m x k,
+ * block size b operand and n up to any value. opts as for plans (num_panels
+ * 0 = one group per panel). */
+spmm_status_t spmm_dynamic_create(int64_t m, int64_t k, int32_t b, int64_t max_nnzb,
+                                  spmm_dtype_t w, spmm_dtype_t x, spmm_dtype_t y,
+                                  const spmm_plan_opts* opts, spmm_dyn_t* out);
+
+/* One dynamic call. nnzb_dev: device int32 holding the number of blocks of
+ * this call (read on the device, so the call can be captured in a graph).
+ * block_row_dev / block_col_dev: int32 [nnzb], any order, duplicates allowed
+ * (summed). values_dev: [nnzb][b][b] of dtype w in the same order as the
+ * indices. scales_dev: FP32 [nnzb] for FP8, else NULL. status_dev: device
+ * int32 that receives SPMM_OK, SPMM_ERR_CAPACITY (nnzb > max_nnzb or < 0) or
+ * SPMM_ERR_BAD_INDEX (an index outside the block grid); on a non-OK status Y
+ * is left untouched. The index and value buffers must hold max_nnzb entries'
+ * worth of readable memory only up to the nnzb actually used. */
+spmm_status_t spmm_run_dynamic(spmm_dyn_t h, const int32_t* nnzb_dev, const int32_t* block_row_dev,
+                               const int32_t* block_col_dev, const void* values_dev,
+                               const float* scales_dev, int64_t n, const void* X, int64_t ldx,
+                               void* Y, int64_t ldy, int32_t* status_dev, void* stream);
+
+/* Host copies of the plan the last spmm_run_dynamic built (synchronises the
+ * handle's work): row_ptr int32 [mb + 1], col_idx int32 [nnzb], src int32
+ * [nnzb] (input index of each CSR entry), panel_ptr int32 [num_panels + 1].
+ * *nnzb receives the block count of that call. */
+spmm_status_t spmm_dynamic_export(spmm_dyn_t h, int32_t* row_ptr, int32_t* col_idx, int32_t* src,
+                                  int32_t* panel_ptr, int64_t* nnzb);
+
+spmm_status_t spmm_dynamic_info(spmm_dyn_t h, int32_t* group_rows, int32_t* num_groups,
+                                int32_t* num_panels);
+
+spmm_status_t spmm_dynamic_destroy(spmm_dyn_t h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPMM_H_ */

@@ -1,0 +1,110 @@
+// Internal declarations shared by the host runtime and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/spmm.h"
+
+namespace spmm {
+
+// ------------------------------------------------------------------ errors
+// Records a thread-local message and returns the status, so call sites read
+// `return fail(SPMM_ERR_INVALID_ARG, "...")`.
+spmm_status_t fail(spmm_status_t st, const std::string& msg);
+spmm_status_t fail_hip(hipError_t e, const char* what);
+void clear_error();
+
+#define SPMM_HIP(call)                                    \
+  do {                                                    \
+    hipError_t e_ = (call);                               \
+    if (e_ != hipSuccess) return ::spmm::fail_hip(e_, #call); \
+  } while (0)
+
+// ------------------------------------------------------------------ sizes
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+int dtype_bytes(spmm_dtype_t t);
+bool dtype_triple_supported(spmm_dtype_t w, spmm_dtype_t x, spmm_dtype_t y);
+
+// ------------------------------------------------------------------ the kernel plan
+// Layout consumed by the compute kernels (static and dynamic build the same):
+//   blocks are bucketed into cells (group g, k-chunk ch, local row lr), cells
+//   ordered (g, ch, lr); inside a cell entries are sorted by (block column,
+//   source index). cell_ptr[NCELL + 1] delimits the cells, ent_col[e] is the
+//   block column of entry e and ent_src[e] the index of its values (the CSR
+//   position for static plans, the input index for dynamic calls).
+struct KernelPlan {
+  int32_t m, k, b;
+  int32_t mb, kb;
+  int32_t group_rows;   // block rows per group (a workgroup's register tile)
+  int32_t num_groups;
+  int32_t chunk_cols;   // block columns per k-chunk
+  int32_t num_chunks;
+  int32_t num_panels;
+  const int32_t* cell_ptr;   // [num_groups * num_chunks * group_rows + 1]
+  const int32_t* ent_col;    // [nnz]
+  const int32_t* ent_src;    // [nnz]
+  const int32_t* panel_ptr;  // [num_panels + 1], group indices
+};
+
+// Device buffers that back a KernelPlan, plus the canonical block-CSR.
+struct PlanBuffers {
+  int32_t* cell_ptr = nullptr;
+  int32_t* ent_col = nullptr;
+  int32_t* ent_src = nullptr;
+  int32_t* panel_ptr = nullptr;
+  int32_t* row_ptr = nullptr;
+  int32_t* col_idx = nullptr;   // CSR columns
+  int32_t* csr_src = nullptr;   // dynamic: input index of each CSR entry
+  int32_t* scratch = nullptr;   // counts / fills / scan partials
+  int64_t* cost_prefix = nullptr;
+  int64_t scratch_ints = 0;
+};
+
+struct Geometry {
+  int32_t group_rows, chunk_cols, num_groups, num_chunks, num_panels;
+  int64_t num_cells;
+};
+
+// Chooses group_rows / chunk_cols for a shape. n_hint steers the row-group size
+// so that groups x n-tiles fills the chip.
+Geometry choose_geometry(int64_t m, int64_t k, int32_t b, int64_t nnz_hint, int64_t n_hint,
+                         const spmm_plan_opts* opts, int num_cus);
+
+// ------------------------------------------------------------------ plan building kernels
+// All of these enqueue on `stream` and do not synchronise.
+spmm_status_t build_static_plan(const uint8_t* mask_dev, int32_t mb, int32_t kb, const Geometry& geo,
+                                PlanBuffers& pb, hipStream_t stream);
+// Dynamic: validates, buckets and sorts a COO list whose length lives on the device.
+spmm_status_t build_dynamic_plan(const int32_t* nnz_dev, const int32_t* rows, const int32_t* cols,
+                                 int32_t max_nnz, int32_t mb, int32_t kb, const Geometry& geo,
+                                 PlanBuffers& pb, int32_t* status_internal, int32_t* status_out,
+                                 hipStream_t stream);
+// CSR (row_ptr, col_idx, csr_src) of a dynamic plan, derived from the cells.
+spmm_status_t dynamic_csr_from_cells(int32_t mb, const Geometry& geo, PlanBuffers& pb,
+                                     const int32_t* status_internal, hipStream_t stream);
+// Static value pack: dst[e] = src[ent_src[e]] (b*b elements), zeroing columns >= k
+// of edge blocks; FP8 scales follow the same permutation.
+spmm_status_t pack_values(const KernelPlan& kp, int64_t nnz, const void* src, void* dst, int elem_bytes,
+                          const float* scales_src, float* scales_dst, hipStream_t stream);
+
+// ------------------------------------------------------------------ compute
+struct RunArgs {
+  KernelPlan plan;
+  const void* W;          // packed (static) or caller's (dynamic) values
+  const float* scales;    // FP8 block scales (same indexing as W), else nullptr
+  bool gather;            // W indexed through ent_src (dynamic) instead of by entry
+  const void* X;
+  void* Y;
+  int64_t ldx, ldy;
+  int32_t n;
+  spmm_dtype_t wt, xt, yt;
+  const int32_t* status;  // skip everything when *status != 0 (dynamic), else nullptr
+};
+spmm_status_t launch_spmm(const RunArgs& a, hipStream_t stream);
+
+int device_cu_count();
+
+}  // namespace spmm

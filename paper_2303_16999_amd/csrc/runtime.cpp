@@ -1,0 +1,469 @@
+// Host side of the C ABI: argument validation, handles, device buffers and
+// kernel dispatch. No arithmetic of the SpMM happens here.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "common.h"
+
+namespace spmm {
+
+static thread_local std::string g_last_error;
+
+spmm_status_t fail(spmm_status_t st, const std::string& msg) {
+  g_last_error = msg;
+  return st;
+}
+spmm_status_t fail_hip(hipError_t e, const char* what) {
+  g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+  return e == hipErrorOutOfMemory ? SPMM_ERR_OOM : SPMM_ERR_HIP;
+}
+void clear_error() { g_last_error.clear(); }
+
+int dtype_bytes(spmm_dtype_t t) {
+  switch (t) {
+    case SPMM_F32: return 4;
+    case SPMM_F16: return 2;
+    case SPMM_BF16: return 2;
+    case SPMM_FP8_E4M3: return 1;
+  }
+  return 0;
+}
+
+bool dtype_triple_supported(spmm_dtype_t w, spmm_dtype_t x, spmm_dtype_t y) {
+  if (w == SPMM_F32) return x == SPMM_F32 && y == SPMM_F32;
+  if (w == SPMM_F16) return x == SPMM_F16 && (y == SPMM_F16 || y == SPMM_F32);
+  if (w == SPMM_BF16) return x == SPMM_BF16 && (y == SPMM_BF16 || y == SPMM_F32);
+  if (w == SPMM_FP8_E4M3) return (x == SPMM_F16 || x == SPMM_BF16) && (y == x || y == SPMM_F32);
+  return false;
+}
+
+int device_cu_count() {
+  int dev = 0, cus = 256;
+  if (hipGetDevice(&dev) == hipSuccess) hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  return cus > 0 ? cus : 256;
+}
+
+static bool valid_block(int32_t b) { return b == 1 || b == 4 || b == 8 || b == 16 || b == 32; }
+
+Geometry choose_geometry(int64_t m, int64_t k, int32_t b, int64_t nnz_hint, int64_t n_hint,
+                         const spmm_plan_opts* opts, int num_cus) {
+  (void)nnz_hint;
+  Geometry g{};
+  const int64_t mb = ceil_div(m, b), kb = ceil_div(k, b);
+  if (n_hint <= 0) n_hint = 1024;
+  int32_t big = 0, small = 0, cw = 0;
+  int32_t ntile = 128;
+  if (b == 16) { big = 32; small = 8; cw = 8; }
+  else if (b == 32) { big = 16; small = 4; cw = 4; }
+  else { big = 64; small = 16; cw = 64 / b; ntile = 64; }  // small-block path
+  int32_t gr = big;
+  if (opts && opts->group_rows > 0) {
+    gr = opts->group_rows;
+  } else {
+    const int64_t units_big = ceil_div(mb, big) * ceil_div(n_hint, ntile);
+    if (units_big < 2 * (int64_t)num_cus) gr = small;
+  }
+  g.group_rows = gr;
+  g.chunk_cols = cw;
+  g.num_groups = (int32_t)ceil_div(mb, gr);
+  g.num_chunks = (int32_t)ceil_div(kb, cw);
+  g.num_panels = (opts && opts->num_panels > 0) ? std::min<int32_t>(opts->num_panels, g.num_groups) : g.num_groups;
+  if (g.num_panels < 1) g.num_panels = 1;
+  g.num_cells = (int64_t)g.num_groups * g.num_chunks * g.group_rows;
+  return g;
+}
+
+static bool geometry_supported(int32_t b, int32_t gr) {
+  if (b == 16) return gr == 32 || gr == 8;
+  if (b == 32) return gr == 16 || gr == 4;
+  return gr == 64 || gr == 16;
+}
+
+spmm_status_t launch_spmm_mfma(const RunArgs& a, hipStream_t s);
+spmm_status_t launch_spmm_small(const RunArgs& a, hipStream_t s);
+
+spmm_status_t launch_spmm(const RunArgs& a, hipStream_t s) {
+  if (a.plan.b >= 16) return launch_spmm_mfma(a, s);
+  return launch_spmm_small(a, s);
+}
+
+static void free_plan_buffers(PlanBuffers& pb) {
+  int32_t* ptrs[] = {pb.cell_ptr, pb.ent_col, pb.ent_src, pb.panel_ptr, pb.row_ptr, pb.col_idx, pb.csr_src, pb.scratch};
+  for (int32_t* p : ptrs)
+    if (p) (void)hipFree(p);
+  if (pb.cost_prefix) (void)hipFree(pb.cost_prefix);
+  pb = PlanBuffers{};
+}
+
+template <typename T>
+static spmm_status_t dev_alloc(T** p, int64_t count) {
+  *p = nullptr;
+  if (count <= 0) count = 1;
+  hipError_t e = hipMalloc((void**)p, (size_t)count * sizeof(T));
+  if (e != hipSuccess) return fail_hip(e, "hipMalloc");
+  return SPMM_OK;
+}
+
+static spmm_status_t alloc_plan_buffers(PlanBuffers& pb, const Geometry& geo, int32_t mb, int64_t nnz, bool dynamic) {
+  spmm_status_t st;
+  const int64_t scan_parts = ceil_div(std::max<int64_t>(std::max<int64_t>(mb, geo.num_cells), 1), 1024) + 16;
+  pb.scratch_ints = (dynamic ? geo.num_cells : 0) + mb + scan_parts + 16;
+  if ((st = dev_alloc(&pb.cell_ptr, geo.num_cells + 1)) != SPMM_OK) return st;
+  if ((st = dev_alloc(&pb.ent_col, nnz)) != SPMM_OK) return st;
+  if ((st = dev_alloc(&pb.ent_src, nnz)) != SPMM_OK) return st;
+  if ((st = dev_alloc(&pb.panel_ptr, (int64_t)geo.num_panels + 1)) != SPMM_OK) return st;
+  if ((st = dev_alloc(&pb.row_ptr, (int64_t)mb + 1)) != SPMM_OK) return st;
+  if ((st = dev_alloc(&pb.col_idx, nnz)) != SPMM_OK) return st;
+  if (dynamic && (st = dev_alloc(&pb.csr_src, nnz)) != SPMM_OK) return st;
+  if ((st = dev_alloc(&pb.scratch, pb.scratch_ints)) != SPMM_OK) return st;
+  if ((st = dev_alloc(&pb.cost_prefix, (int64_t)geo.num_groups + 1)) != SPMM_OK) return st;
+  return SPMM_OK;
+}
+
+static KernelPlan kernel_plan(int64_t m, int64_t k, int32_t b, int32_t mb, int32_t kb, const Geometry& geo,
+                              const PlanBuffers& pb) {
+  KernelPlan kp;
+  kp.m = (int32_t)m;
+  kp.k = (int32_t)k;
+  kp.b = b;
+  kp.mb = mb;
+  kp.kb = kb;
+  kp.group_rows = geo.group_rows;
+  kp.num_groups = geo.num_groups;
+  kp.chunk_cols = geo.chunk_cols;
+  kp.num_chunks = geo.num_chunks;
+  kp.num_panels = geo.num_panels;
+  kp.cell_ptr = pb.cell_ptr;
+  kp.ent_col = pb.ent_col;
+  kp.ent_src = pb.ent_src;
+  kp.panel_ptr = pb.panel_ptr;
+  return kp;
+}
+
+static spmm_status_t check_dense(const void* p, int64_t ld, int64_t n, int elem, const char* name) {
+  if (!p) return fail(SPMM_ERR_INVALID_ARG, std::string(name) + " is NULL");
+  if (ld < n) return fail(SPMM_ERR_INVALID_ARG, std::string("leading dimension of ") + name + " is smaller than n");
+  if (((uintptr_t)p) % 16 != 0) return fail(SPMM_ERR_INVALID_ARG, std::string(name) + " is not 16-byte aligned");
+  if ((ld * elem) % 16 != 0)
+    return fail(SPMM_ERR_INVALID_ARG, std::string("leading dimension of ") + name + " is not a multiple of 16 bytes");
+  return SPMM_OK;
+}
+
+static spmm_status_t check_device(int device) {
+  int cur = -1;
+  SPMM_HIP(hipGetDevice(&cur));
+  if (cur != device) return fail(SPMM_ERR_INVALID_ARG, "handle was created on another device");
+  return SPMM_OK;
+}
+
+}  // namespace spmm
+
+using namespace spmm;
+
+struct spmm_plan_s {
+  int64_t m = 0, k = 0;
+  int32_t b = 0, mb = 0, kb = 0;
+  int64_t nnzb = 0;
+  spmm_dtype_t w = SPMM_F32, x = SPMM_F32, y = SPMM_F32;
+  Geometry geo{};
+  PlanBuffers pb;
+  void* values = nullptr;
+  float* scales = nullptr;
+  bool has_values = false;
+  int device = 0;
+};
+
+struct spmm_dyn_s {
+  int64_t m = 0, k = 0;
+  int32_t b = 0, mb = 0, kb = 0;
+  int64_t max_nnzb = 0;
+  spmm_dtype_t w = SPMM_F32, x = SPMM_F32, y = SPMM_F32;
+  Geometry geo{};
+  PlanBuffers pb;
+  int32_t* status = nullptr;   // internal status word (device)
+  int32_t* nnz_last = nullptr; // device copy of the last call's nnz
+  int device = 0;
+  bool ran = false;
+};
+
+extern "C" {
+
+const char* spmm_last_error(void) { return g_last_error.c_str(); }
+
+spmm_status_t spmm_plan_static(int64_t m, int64_t k, int32_t b, const uint8_t* block_mask_host, spmm_dtype_t w,
+                               spmm_dtype_t x, spmm_dtype_t y, const spmm_plan_opts* opts, spmm_plan_t* out) {
+  clear_error();
+  if (!out) return fail(SPMM_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (m < 1 || k < 1) return fail(SPMM_ERR_INVALID_ARG, "m and k must be positive");
+  if (!valid_block(b)) return fail(SPMM_ERR_INVALID_ARG, "block size must be one of 1, 4, 8, 16, 32");
+  if (!block_mask_host) return fail(SPMM_ERR_INVALID_ARG, "block mask is NULL");
+  if (!dtype_triple_supported(w, x, y)) return fail(SPMM_ERR_UNSUPPORTED, "unsupported dtype combination");
+  if (m > INT32_MAX / 2 || k > INT32_MAX / 2) return fail(SPMM_ERR_UNSUPPORTED, "m or k too large");
+  const int64_t mb = ceil_div(m, b), kb = ceil_div(k, b);
+  int64_t nnzb = 0;
+  for (int64_t i = 0; i < mb * kb; ++i) nnzb += block_mask_host[i] != 0;
+  if (nnzb > INT32_MAX / 2) return fail(SPMM_ERR_UNSUPPORTED, "too many nonzero blocks");
+  if (opts && (opts->group_rows < 0 || opts->num_panels < 0))
+    return fail(SPMM_ERR_INVALID_ARG, "negative plan option");
+
+  spmm_plan_s* p = new (std::nothrow) spmm_plan_s;
+  if (!p) return fail(SPMM_ERR_OOM, "host allocation failed");
+  p->m = m; p->k = k; p->b = b; p->mb = (int32_t)mb; p->kb = (int32_t)kb; p->nnzb = nnzb;
+  p->w = w; p->x = x; p->y = y;
+  p->geo = choose_geometry(m, k, b, nnzb, opts ? opts->n_hint : 0, opts, device_cu_count());
+  if (!geometry_supported(b, p->geo.group_rows)) {
+    delete p;
+    return fail(SPMM_ERR_UNSUPPORTED, "group_rows not available for this block size");
+  }
+  spmm_status_t st = SPMM_OK;
+  uint8_t* mask_dev = nullptr;
+  hipStream_t s = nullptr;
+  hipError_t e = hipGetDevice(&p->device);
+  if (e != hipSuccess) st = fail_hip(e, "hipGetDevice");
+  if (st == SPMM_OK) st = alloc_plan_buffers(p->pb, p->geo, (int32_t)mb, nnzb, false);
+  if (st == SPMM_OK) st = dev_alloc(&mask_dev, mb * kb);
+  if (st == SPMM_OK) {
+    const int64_t vbytes = nnzb * (int64_t)b * b * dtype_bytes(w);
+    e = hipMalloc(&p->values, (size_t)std::max<int64_t>(vbytes, 16));
+    if (e != hipSuccess) st = fail_hip(e, "hipMalloc values");
+  }
+  if (st == SPMM_OK && w == SPMM_FP8_E4M3) st = dev_alloc(&p->scales, nnzb);
+  if (st == SPMM_OK && (e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking)) != hipSuccess)
+    st = fail_hip(e, "hipStreamCreate");
+  if (st == SPMM_OK && (e = hipMemcpyAsync(mask_dev, block_mask_host, (size_t)(mb * kb), hipMemcpyHostToDevice, s)) != hipSuccess)
+    st = fail_hip(e, "mask upload");
+  if (st == SPMM_OK) st = build_static_plan(mask_dev, (int32_t)mb, (int32_t)kb, p->geo, p->pb, s);
+  if (st == SPMM_OK && (e = hipStreamSynchronize(s)) != hipSuccess) st = fail_hip(e, "plan build");
+  if (s) (void)hipStreamDestroy(s);
+  if (mask_dev) (void)hipFree(mask_dev);
+  if (st != SPMM_OK) {
+    free_plan_buffers(p->pb);
+    if (p->values) (void)hipFree(p->values);
+    if (p->scales) (void)hipFree(p->scales);
+    delete p;
+    return st;
+  }
+  *out = p;
+  return SPMM_OK;
+}
+
+spmm_status_t spmm_plan_set_values(spmm_plan_t p, const void* values_dev, const float* scales_dev, void* stream) {
+  clear_error();
+  if (!p) return fail(SPMM_ERR_INVALID_ARG, "plan is NULL");
+  if (p->nnzb > 0 && !values_dev) return fail(SPMM_ERR_INVALID_ARG, "values are NULL");
+  if (p->w == SPMM_FP8_E4M3 && p->nnzb > 0 && !scales_dev) return fail(SPMM_ERR_INVALID_ARG, "FP8 weights need block scales");
+  if (p->w != SPMM_FP8_E4M3 && scales_dev) return fail(SPMM_ERR_INVALID_ARG, "block scales are only for FP8 weights");
+  spmm_status_t st = check_device(p->device);
+  if (st != SPMM_OK) return st;
+  KernelPlan kp = kernel_plan(p->m, p->k, p->b, p->mb, p->kb, p->geo, p->pb);
+  st = pack_values(kp, p->nnzb, values_dev, p->values, dtype_bytes(p->w), scales_dev, p->scales, (hipStream_t)stream);
+  if (st != SPMM_OK) return st;
+  p->has_values = true;
+  return SPMM_OK;
+}
+
+spmm_status_t spmm_run_static(spmm_plan_t p, int64_t n, const void* X, int64_t ldx, void* Y, int64_t ldy,
+                              void* stream) {
+  clear_error();
+  if (!p) return fail(SPMM_ERR_INVALID_ARG, "plan is NULL");
+  if (n < 0) return fail(SPMM_ERR_INVALID_ARG, "n is negative");
+  if (n == 0) return SPMM_OK;
+  if (n > INT32_MAX / 2) return fail(SPMM_ERR_UNSUPPORTED, "n too large");
+  if (!p->has_values) return fail(SPMM_ERR_INVALID_ARG, "values were not set on this plan");
+  spmm_status_t st;
+  if ((st = check_dense(X, ldx, n, dtype_bytes(p->x), "X")) != SPMM_OK) return st;
+  if ((st = check_dense(Y, ldy, n, dtype_bytes(p->y), "Y")) != SPMM_OK) return st;
+  if ((st = check_device(p->device)) != SPMM_OK) return st;
+  RunArgs a;
+  a.plan = kernel_plan(p->m, p->k, p->b, p->mb, p->kb, p->geo, p->pb);
+  a.W = p->values;
+  a.scales = p->scales;
+  a.gather = false;
+  a.X = X;
+  a.Y = Y;
+  a.ldx = ldx;
+  a.ldy = ldy;
+  a.n = (int32_t)n;
+  a.wt = p->w;
+  a.xt = p->x;
+  a.yt = p->y;
+  a.status = nullptr;
+  return launch_spmm(a, (hipStream_t)stream);
+}
+
+spmm_status_t spmm_plan_info(spmm_plan_t p, int64_t* nnzb, int32_t* group_rows, int32_t* num_groups,
+                             int32_t* num_panels) {
+  clear_error();
+  if (!p) return fail(SPMM_ERR_INVALID_ARG, "plan is NULL");
+  if (nnzb) *nnzb = p->nnzb;
+  if (group_rows) *group_rows = p->geo.group_rows;
+  if (num_groups) *num_groups = p->geo.num_groups;
+  if (num_panels) *num_panels = p->geo.num_panels;
+  return SPMM_OK;
+}
+
+spmm_status_t spmm_plan_export(spmm_plan_t p, int32_t* row_ptr, int32_t* col_idx, int32_t* panel_ptr) {
+  clear_error();
+  if (!p) return fail(SPMM_ERR_INVALID_ARG, "plan is NULL");
+  spmm_status_t st = check_device(p->device);
+  if (st != SPMM_OK) return st;
+  if (row_ptr) SPMM_HIP(hipMemcpy(row_ptr, p->pb.row_ptr, sizeof(int32_t) * (p->mb + 1), hipMemcpyDeviceToHost));
+  if (col_idx && p->nnzb)
+    SPMM_HIP(hipMemcpy(col_idx, p->pb.col_idx, sizeof(int32_t) * p->nnzb, hipMemcpyDeviceToHost));
+  if (panel_ptr)
+    SPMM_HIP(hipMemcpy(panel_ptr, p->pb.panel_ptr, sizeof(int32_t) * (p->geo.num_panels + 1), hipMemcpyDeviceToHost));
+  return SPMM_OK;
+}
+
+spmm_status_t spmm_plan_destroy(spmm_plan_t p) {
+  clear_error();
+  if (!p) return SPMM_OK;
+  free_plan_buffers(p->pb);
+  if (p->values) (void)hipFree(p->values);
+  if (p->scales) (void)hipFree(p->scales);
+  delete p;
+  return SPMM_OK;
+}
+
+// ------------------------------------------------------------------ dynamic
+spmm_status_t spmm_dynamic_create(int64_t m, int64_t k, int32_t b, int64_t max_nnzb, spmm_dtype_t w, spmm_dtype_t x,
+                                  spmm_dtype_t y, const spmm_plan_opts* opts, spmm_dyn_t* out) {
+  clear_error();
+  if (!out) return fail(SPMM_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (m < 1 || k < 1) return fail(SPMM_ERR_INVALID_ARG, "m and k must be positive");
+  if (!valid_block(b)) return fail(SPMM_ERR_INVALID_ARG, "block size must be one of 1, 4, 8, 16, 32");
+  if (max_nnzb < 0) return fail(SPMM_ERR_INVALID_ARG, "max_nnzb is negative");
+  if (!dtype_triple_supported(w, x, y)) return fail(SPMM_ERR_UNSUPPORTED, "unsupported dtype combination");
+  if (m > INT32_MAX / 2 || k > INT32_MAX / 2 || max_nnzb > INT32_MAX / 4)
+    return fail(SPMM_ERR_UNSUPPORTED, "size too large");
+  if (opts && (opts->group_rows < 0 || opts->num_panels < 0)) return fail(SPMM_ERR_INVALID_ARG, "negative plan option");
+  spmm_dyn_s* h = new (std::nothrow) spmm_dyn_s;
+  if (!h) return fail(SPMM_ERR_OOM, "host allocation failed");
+  h->m = m; h->k = k; h->b = b;
+  h->mb = (int32_t)ceil_div(m, b);
+  h->kb = (int32_t)ceil_div(k, b);
+  h->max_nnzb = max_nnzb;
+  h->w = w; h->x = x; h->y = y;
+  h->geo = choose_geometry(m, k, b, max_nnzb, opts ? opts->n_hint : 0, opts, device_cu_count());
+  if (!geometry_supported(b, h->geo.group_rows)) {
+    delete h;
+    return fail(SPMM_ERR_UNSUPPORTED, "group_rows not available for this block size");
+  }
+  if (h->geo.num_cells > (int64_t)INT32_MAX / 2) {
+    delete h;
+    return fail(SPMM_ERR_UNSUPPORTED, "block grid too large for the dynamic bucket table");
+  }
+  spmm_status_t st = SPMM_OK;
+  hipError_t e = hipGetDevice(&h->device);
+  if (e != hipSuccess) st = fail_hip(e, "hipGetDevice");
+  if (st == SPMM_OK) st = alloc_plan_buffers(h->pb, h->geo, h->mb, max_nnzb, true);
+  if (st == SPMM_OK) st = dev_alloc(&h->status, 2);
+  if (st == SPMM_OK) st = dev_alloc(&h->nnz_last, 2);
+  if (st == SPMM_OK) {
+    if ((e = hipMemset(h->status, 0, 2 * sizeof(int32_t))) != hipSuccess) st = fail_hip(e, "hipMemset");
+  }
+  if (st != SPMM_OK) {
+    free_plan_buffers(h->pb);
+    if (h->status) (void)hipFree(h->status);
+    if (h->nnz_last) (void)hipFree(h->nnz_last);
+    delete h;
+    return st;
+  }
+  *out = h;
+  return SPMM_OK;
+}
+
+spmm_status_t spmm_run_dynamic(spmm_dyn_t h, const int32_t* nnzb_dev, const int32_t* rows, const int32_t* cols,
+                               const void* values_dev, const float* scales_dev, int64_t n, const void* X, int64_t ldx,
+                               void* Y, int64_t ldy, int32_t* status_dev, void* stream) {
+  clear_error();
+  if (!h) return fail(SPMM_ERR_INVALID_ARG, "handle is NULL");
+  if (!nnzb_dev || !status_dev) return fail(SPMM_ERR_INVALID_ARG, "nnzb_dev and status_dev are required");
+  if (h->max_nnzb > 0 && (!rows || !cols || !values_dev))
+    return fail(SPMM_ERR_INVALID_ARG, "index and value buffers are required");
+  if (h->w == SPMM_FP8_E4M3 && h->max_nnzb > 0 && !scales_dev) return fail(SPMM_ERR_INVALID_ARG, "FP8 weights need block scales");
+  if (h->w != SPMM_FP8_E4M3 && scales_dev) return fail(SPMM_ERR_INVALID_ARG, "block scales are only for FP8 weights");
+  if (n < 0) return fail(SPMM_ERR_INVALID_ARG, "n is negative");
+  if (n > INT32_MAX / 2) return fail(SPMM_ERR_UNSUPPORTED, "n too large");
+  spmm_status_t st;
+  if (n > 0) {
+    if ((st = check_dense(X, ldx, n, dtype_bytes(h->x), "X")) != SPMM_OK) return st;
+    if ((st = check_dense(Y, ldy, n, dtype_bytes(h->y), "Y")) != SPMM_OK) return st;
+  }
+  if (((uintptr_t)values_dev) % 16 != 0) return fail(SPMM_ERR_INVALID_ARG, "values are not 16-byte aligned");
+  if ((st = check_device(h->device)) != SPMM_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  st = build_dynamic_plan(nnzb_dev, rows, cols, (int32_t)h->max_nnzb, h->mb, h->kb, h->geo, h->pb, h->status,
+                          status_dev, s);
+  if (st != SPMM_OK) return st;
+  SPMM_HIP(hipMemcpyAsync(h->nnz_last, nnzb_dev, sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+  h->ran = true;
+  if (n == 0) return SPMM_OK;
+  RunArgs a;
+  a.plan = kernel_plan(h->m, h->k, h->b, h->mb, h->kb, h->geo, h->pb);
+  a.W = values_dev;
+  a.scales = scales_dev;
+  a.gather = true;
+  a.X = X;
+  a.Y = Y;
+  a.ldx = ldx;
+  a.ldy = ldy;
+  a.n = (int32_t)n;
+  a.wt = h->w;
+  a.xt = h->x;
+  a.yt = h->y;
+  a.status = h->status;
+  return launch_spmm(a, s);
+}
+
+spmm_status_t spmm_dynamic_export(spmm_dyn_t h, int32_t* row_ptr, int32_t* col_idx, int32_t* src, int32_t* panel_ptr,
+                                  int64_t* nnzb) {
+  clear_error();
+  if (!h) return fail(SPMM_ERR_INVALID_ARG, "handle is NULL");
+  if (!h->ran) return fail(SPMM_ERR_INVALID_ARG, "no dynamic call has run on this handle");
+  spmm_status_t st = check_device(h->device);
+  if (st != SPMM_OK) return st;
+  SPMM_HIP(hipDeviceSynchronize());
+  int32_t status = 0, nnz = 0;
+  SPMM_HIP(hipMemcpy(&status, h->status, sizeof(int32_t), hipMemcpyDeviceToHost));
+  if (status != 0) return fail((spmm_status_t)status, "the last dynamic call failed on the device");
+  SPMM_HIP(hipMemcpy(&nnz, h->nnz_last, sizeof(int32_t), hipMemcpyDeviceToHost));
+  st = dynamic_csr_from_cells(h->mb, h->geo, h->pb, h->status, nullptr);
+  if (st != SPMM_OK) return st;
+  SPMM_HIP(hipDeviceSynchronize());
+  if (nnzb) *nnzb = nnz;
+  if (row_ptr) SPMM_HIP(hipMemcpy(row_ptr, h->pb.row_ptr, sizeof(int32_t) * (h->mb + 1), hipMemcpyDeviceToHost));
+  if (col_idx && nnz) SPMM_HIP(hipMemcpy(col_idx, h->pb.col_idx, sizeof(int32_t) * nnz, hipMemcpyDeviceToHost));
+  if (src && nnz) SPMM_HIP(hipMemcpy(src, h->pb.csr_src, sizeof(int32_t) * nnz, hipMemcpyDeviceToHost));
+  if (panel_ptr)
+    SPMM_HIP(hipMemcpy(panel_ptr, h->pb.panel_ptr, sizeof(int32_t) * (h->geo.num_panels + 1), hipMemcpyDeviceToHost));
+  return SPMM_OK;
+}
+
+spmm_status_t spmm_dynamic_info(spmm_dyn_t h, int32_t* group_rows, int32_t* num_groups, int32_t* num_panels) {
+  clear_error();
+  if (!h) return fail(SPMM_ERR_INVALID_ARG, "handle is NULL");
+  if (group_rows) *group_rows = h->geo.group_rows;
+  if (num_groups) *num_groups = h->geo.num_groups;
+  if (num_panels) *num_panels = h->geo.num_panels;
+  return SPMM_OK;
+}
+
+spmm_status_t spmm_dynamic_destroy(spmm_dyn_t h) {
+  clear_error();
+  if (!h) return SPMM_OK;
+  free_plan_buffers(h->pb);
+  if (h->status) (void)hipFree(h->status);
+  if (h->nnz_last) (void)hipFree(h->nnz_last);
+  delete h;
+  return SPMM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,205 @@
+"""ctypes binding of libspmm.so (the C ABI in include/spmm.h).
+
+Argument marshalling only: every step of the SpMM runs in the library's HIP
+kernels. torch tensors supply device memory and streams; their data pointers
+are passed straight through. There is no fallback: if the library is missing,
+`lib()` raises.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libspmm.so")
+
+OK, ERR_INVALID_ARG, ERR_UNSUPPORTED, ERR_CAPACITY, ERR_BAD_INDEX, ERR_OOM, ERR_HIP, ERR_REJECTED = range(8)
+F32, F16, BF16, FP8_E4M3 = range(4)
+DTYPE_CODES = {"f32": F32, "f16": F16, "bf16": BF16, "fp8": FP8_E4M3}
+
+# every symbol the header declares, with its ctypes signature
+_c_i64, _c_i32, _vp = ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p
+_pi32, _pi64 = ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64)
+
+
+class PlanOpts(ctypes.Structure):
+    _fields_ = [("group_rows", ctypes.c_int32), ("num_panels", ctypes.c_int32),
+                ("n_hint", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+SIGNATURES = {
+    "spmm_last_error": ([], ctypes.c_char_p),
+    "spmm_plan_static": ([_c_i64, _c_i64, _c_i32, _vp, _c_i32, _c_i32, _c_i32, ctypes.POINTER(PlanOpts),
+                          ctypes.POINTER(_vp)], _c_i32),
+    "spmm_plan_set_values": ([_vp, _vp, _vp, _vp], _c_i32),
+    "spmm_run_static": ([_vp, _c_i64, _vp, _c_i64, _vp, _c_i64, _vp], _c_i32),
+    "spmm_plan_info": ([_vp, _pi64, _pi32, _pi32, _pi32], _c_i32),
+    "spmm_plan_export": ([_vp, _vp, _vp, _vp], _c_i32),
+    "spmm_plan_destroy": ([_vp], _c_i32),
+    "spmm_dynamic_create": ([_c_i64, _c_i64, _c_i32, _c_i64, _c_i32, _c_i32, _c_i32, ctypes.POINTER(PlanOpts),
+                             ctypes.POINTER(_vp)], _c_i32),
+    "spmm_run_dynamic": ([_vp, _vp, _vp, _vp, _vp, _vp, _c_i64, _vp, _c_i64, _vp, _c_i64, _vp, _vp], _c_i32),
+    "spmm_dynamic_export": ([_vp, _vp, _vp, _vp, _vp, _pi64], _c_i32),
+    "spmm_dynamic_info": ([_vp, _pi32, _pi32, _pi32], _c_i32),
+    "spmm_dynamic_destroy": ([_vp], _c_i32),
+}
+
+_LIB = None
+
+
+class SpmmError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__("spmm status %d: %s" % (status, message))
+        self.status = status
+
+
+def lib():
+    """Load libspmm.so (built by paper_2303_16999_amd.build); raise if it is missing."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libspmm.so is not built; run `python -m paper_2303_16999_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (args, res) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        _LIB = L
+    return _LIB
+
+
+def check(status):
+    if status != OK:
+        raise SpmmError(status, lib().spmm_last_error().decode())
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return t
+    return t.data_ptr()
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _opts(group_rows=0, num_panels=0, n_hint=0):
+    return PlanOpts(int(group_rows), int(num_panels), int(n_hint), 0)
+
+
+def torch_dtype(code):
+    import torch
+    return {F32: torch.float32, F16: torch.float16, BF16: torch.bfloat16, FP8_E4M3: torch.uint8}[code]
+
+
+class StaticPlan:
+    """spmm_plan_static / spmm_plan_set_values / spmm_run_static."""
+
+    def __init__(self, m, k, b, block_mask, w="f16", x=None, y=None, group_rows=0, num_panels=0, n_hint=0):
+        x = x or ("f16" if w == "fp8" else w)
+        y = y or x
+        mask = np.ascontiguousarray(np.asarray(block_mask, dtype=np.uint8))
+        self.m, self.k, self.b = int(m), int(k), int(b)
+        self.w, self.x, self.y = DTYPE_CODES[w], DTYPE_CODES[x], DTYPE_CODES[y]
+        h = _vp()
+        opts = _opts(group_rows, num_panels, n_hint)
+        check(lib().spmm_plan_static(self.m, self.k, self.b, mask.ctypes.data_as(_vp), self.w, self.x, self.y,
+                                     ctypes.byref(opts), ctypes.byref(h)))
+        self._h = h
+        self.mb, self.kb = -(-self.m // self.b), -(-self.k // self.b)
+
+    def info(self):
+        nnz, gr, ng, npn = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        check(lib().spmm_plan_info(self._h, ctypes.byref(nnz), ctypes.byref(gr), ctypes.byref(ng), ctypes.byref(npn)))
+        return {"nnzb": nnz.value, "group_rows": gr.value, "num_groups": ng.value, "num_panels": npn.value}
+
+    def set_values(self, values, scales=None, stream=None):
+        check(lib().spmm_plan_set_values(self._h, _ptr(values), _ptr(scales), _stream(stream)))
+
+    def run(self, X, Y, n=None, ldx=None, ldy=None, stream=None):
+        n = X.shape[1] if n is None else n
+        ldx = X.stride(0) if ldx is None else ldx
+        ldy = Y.stride(0) if ldy is None else ldy
+        check(lib().spmm_run_static(self._h, int(n), _ptr(X), int(ldx), _ptr(Y), int(ldy), _stream(stream)))
+        return Y
+
+    def export(self):
+        inf = self.info()
+        row_ptr = np.zeros(self.mb + 1, np.int32)
+        col_idx = np.zeros(max(inf["nnzb"], 1), np.int32)
+        panel_ptr = np.zeros(inf["num_panels"] + 1, np.int32)
+        check(lib().spmm_plan_export(self._h, row_ptr.ctypes.data_as(_vp), col_idx.ctypes.data_as(_vp),
+                                     panel_ptr.ctypes.data_as(_vp)))
+        return {"row_ptr": row_ptr, "col_idx": col_idx[: inf["nnzb"]], "panel_ptr": panel_ptr}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().spmm_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class DynamicHandle:
+    """spmm_dynamic_create / spmm_run_dynamic."""
+
+    def __init__(self, m, k, b, max_nnzb, w="f16", x=None, y=None, group_rows=0, num_panels=0, n_hint=0):
+        x = x or ("f16" if w == "fp8" else w)
+        y = y or x
+        self.m, self.k, self.b, self.max_nnzb = int(m), int(k), int(b), int(max_nnzb)
+        self.w, self.x, self.y = DTYPE_CODES[w], DTYPE_CODES[x], DTYPE_CODES[y]
+        self.mb, self.kb = -(-self.m // self.b), -(-self.k // self.b)
+        h = _vp()
+        opts = _opts(group_rows, num_panels, n_hint)
+        check(lib().spmm_dynamic_create(self.m, self.k, self.b, self.max_nnzb, self.w, self.x, self.y,
+                                        ctypes.byref(opts), ctypes.byref(h)))
+        self._h = h
+
+    def run(self, nnz_dev, rows, cols, values, X, Y, status_dev, scales=None, n=None, ldx=None, ldy=None,
+            stream=None):
+        n = X.shape[1] if n is None else n
+        ldx = X.stride(0) if ldx is None else ldx
+        ldy = Y.stride(0) if ldy is None else ldy
+        check(lib().spmm_run_dynamic(self._h, _ptr(nnz_dev), _ptr(rows), _ptr(cols), _ptr(values), _ptr(scales),
+                                     int(n), _ptr(X), int(ldx), _ptr(Y), int(ldy), _ptr(status_dev),
+                                     _stream(stream)))
+        return Y
+
+    def info(self):
+        gr, ng, npn = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        check(lib().spmm_dynamic_info(self._h, ctypes.byref(gr), ctypes.byref(ng), ctypes.byref(npn)))
+        return {"group_rows": gr.value, "num_groups": ng.value, "num_panels": npn.value}
+
+    def export(self):
+        inf = self.info()
+        row_ptr = np.zeros(self.mb + 1, np.int32)
+        col_idx = np.zeros(max(self.max_nnzb, 1), np.int32)
+        src = np.zeros(max(self.max_nnzb, 1), np.int32)
+        panel_ptr = np.zeros(inf["num_panels"] + 1, np.int32)
+        nnz = ctypes.c_int64()
+        check(lib().spmm_dynamic_export(self._h, row_ptr.ctypes.data_as(_vp), col_idx.ctypes.data_as(_vp),
+                                        src.ctypes.data_as(_vp), panel_ptr.ctypes.data_as(_vp), ctypes.byref(nnz)))
+        z = nnz.value
+        return {"row_ptr": row_ptr, "col_idx": col_idx[:z], "src": src[:z], "panel_ptr": panel_ptr, "nnzb": z}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().spmm_dynamic_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

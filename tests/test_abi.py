@@ -1,0 +1,78 @@
+"""The C-ABI library loads, exports every declared symbol, and rejects bad
+arguments on the host before touching a GPU (runs without a GPU)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2303_16999_amd import spmm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    names = []
+    for fn in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if fn.endswith(".h"):
+            text = open(os.path.join(ROOT, "include", fn)).read()
+            names += re.findall(r"^(?:spmm_status_t|const char\*)\s+(spmm_\w+)\s*\(", text, flags=re.M)
+    return names
+
+
+def test_library_exports_every_declared_symbol():
+    L = spmm.lib()
+    names = _declared_functions()
+    assert len(names) >= 12
+    for name in names:
+        assert hasattr(L, name), name
+        assert name in spmm.SIGNATURES, name
+
+
+def _plan(m=64, k=64, b=16, w=spmm.F16, x=spmm.F16, y=spmm.F16, mask=None, opts=None):
+    L = spmm.lib()
+    if mask is None:
+        mask = np.ones((max(1, -(-m // b)) if b > 0 else 1, max(1, -(-k // b)) if b > 0 else 1), np.uint8)
+    h = ctypes.c_void_p()
+    st = L.spmm_plan_static(m, k, b, mask.ctypes.data_as(ctypes.c_void_p), w, x, y, opts, ctypes.byref(h))
+    return st, h
+
+
+@pytest.mark.parametrize("b", [0, 2, 3, 64, -16])
+def test_bad_block_size_is_invalid_arg(b):
+    st, h = _plan(b=b, mask=np.ones((4, 4), np.uint8))
+    assert st == spmm.ERR_INVALID_ARG and not h.value
+    assert b"block size" in spmm.lib().spmm_last_error()
+
+
+@pytest.mark.parametrize("w,x,y", [(spmm.F16, spmm.BF16, spmm.F16), (spmm.F32, spmm.F16, spmm.F32),
+                                   (spmm.BF16, spmm.BF16, spmm.F16), (spmm.FP8_E4M3, spmm.F32, spmm.F32),
+                                   (7, spmm.F16, spmm.F16)])
+def test_unsupported_dtype_triples(w, x, y):
+    st, h = _plan(w=w, x=x, y=y)
+    assert st == spmm.ERR_UNSUPPORTED and not h.value
+
+
+def test_bad_sizes_and_null_pointers():
+    L = spmm.lib()
+    h = ctypes.c_void_p()
+    assert L.spmm_plan_static(0, 16, 16, None, 1, 1, 1, None, ctypes.byref(h)) == spmm.ERR_INVALID_ARG
+    assert L.spmm_plan_static(16, 16, 16, None, 1, 1, 1, None, ctypes.byref(h)) == spmm.ERR_INVALID_ARG
+    assert L.spmm_plan_static(16, 16, 16, None, 1, 1, 1, None, None) == spmm.ERR_INVALID_ARG
+    assert L.spmm_run_static(None, 4, None, 4, None, 4, None) == spmm.ERR_INVALID_ARG
+    assert L.spmm_plan_set_values(None, None, None, None) == spmm.ERR_INVALID_ARG
+    assert L.spmm_dynamic_create(16, 16, 16, -1, 1, 1, 1, None, ctypes.byref(h)) == spmm.ERR_INVALID_ARG
+    assert L.spmm_dynamic_create(16, 16, 5, 4, 1, 1, 1, None, ctypes.byref(h)) == spmm.ERR_INVALID_ARG
+    assert L.spmm_run_dynamic(None, None, None, None, None, None, 4, None, 4, None, 4, None, None) == spmm.ERR_INVALID_ARG
+    assert L.spmm_plan_destroy(None) == spmm.OK and L.spmm_dynamic_destroy(None) == spmm.OK
+    opts = spmm.PlanOpts(-1, 0, 0, 0)
+    mask = np.ones((1, 1), np.uint8)
+    assert L.spmm_plan_static(16, 16, 16, mask.ctypes.data_as(ctypes.c_void_p), 1, 1, 1, ctypes.byref(opts),
+                              ctypes.byref(h)) == spmm.ERR_INVALID_ARG
+
+
+def test_binding_raises_with_message():
+    with pytest.raises(spmm.SpmmError) as ei:
+        spmm.StaticPlan(64, 64, 3, np.ones((22, 22), np.uint8))
+    assert ei.value.status == spmm.ERR_INVALID_ARG

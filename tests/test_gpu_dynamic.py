@@ -1,0 +1,125 @@
+"""GPU parity of the dynamic path: oracle, static equivalence, status words."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import plan_ref
+from oracle import spmm_ref as O
+from paper_2303_16999_amd import spmm, synth
+from gpu_cases import Case, dev, y_f64
+
+pytestmark = pytest.mark.gpu
+
+
+def _dyn_inputs(rows, cols, vals_store, max_nnz, b):
+    pad = max_nnz - len(rows)
+    r = np.concatenate([rows, np.zeros(pad, np.int32)]).astype(np.int32)
+    c = np.concatenate([cols, np.zeros(pad, np.int32)]).astype(np.int32)
+    v = np.concatenate([vals_store, np.zeros((pad,) + vals_store.shape[1:], vals_store.dtype)])
+    return dev(r), dev(c), dev(v), torch.tensor([len(rows)], dtype=torch.int32, device="cuda")
+
+
+def test_dynamic_matches_oracle_and_static_bitwise():
+    c = Case(48 * 16, 40 * 16, 256, 16, 1 / 8, w="f16", seed=21)
+    plan, Ys = c.run_static(group_rows=8)
+    max_nnz = len(c.rows) + 17
+    perm = np.random.default_rng(5).permutation(len(c.rows))  # COO in random order
+    r, col, v, nnz = _dyn_inputs(c.rows[perm], c.cols[perm], c.vals_store[perm], max_nnz, 16)
+    h = spmm.DynamicHandle(c.m, c.k, 16, max_nnz, "f16", group_rows=8)
+    _, X, _ = c.device_inputs()
+    Yd = c.new_Y()
+    status = torch.full((1,), -1, dtype=torch.int32, device="cuda")
+    h.run(nnz, r, col, v, X, Yd, status, n=c.n)
+    torch.cuda.synchronize()
+    assert status.item() == 0
+    assert torch.equal(Ys[:, : c.n], Yd[:, : c.n])
+    assert O.rel_fro(y_f64(Yd, c), c.oracle()) <= 5e-3
+    ex = h.export()
+    ref = plan_ref.plan_from_coo(h.mb, h.kb, c.rows[perm], c.cols[perm], 8, h.info()["num_panels"])
+    for key in ("row_ptr", "col_idx", "panel_ptr"):
+        assert np.array_equal(ex[key], ref[key]), key
+    assert np.array_equal(ex["src"], ref["src"])
+
+
+def test_dynamic_duplicates_summed_and_ragged():
+    b, m, k, n = 16, 150, 90, 70
+    mb, kb = -(-m // b), -(-k // b)
+    g = np.random.default_rng(3)
+    rows = g.integers(0, mb, 40).astype(np.int32)
+    cols = g.integers(0, kb, 40).astype(np.int32)
+    vals = synth.to_storage(synth.normal((40, b, b), 4), "bf16")
+    X = synth.to_storage(synth.normal((k, n), 5), "bf16")
+    r, c, v, nnz = _dyn_inputs(rows, cols, vals, 64, b)
+    h = spmm.DynamicHandle(m, k, b, 64, "bf16", y="f32")
+    Xd = torch.zeros((k, 72), dtype=torch.bfloat16, device="cuda")
+    Xd[:, :n] = dev(X)
+    Y = torch.full((m, 72), float("nan"), dtype=torch.float32, device="cuda")
+    status = torch.zeros(1, dtype=torch.int32, device="cuda")
+    h.run(nnz, r, c, v, Xd, Y, status, n=n)
+    torch.cuda.synchronize()
+    assert status.item() == 0
+    ref = O.spmm_expand(m, k, b, rows, cols, synth.storage_to_f64(vals, "bf16"), synth.storage_to_f64(X, "bf16"))
+    assert O.rel_fro(Y[:, :n].cpu().numpy(), ref) <= 5e-3
+
+
+def test_dynamic_capacity_and_bad_index_leave_y_untouched():
+    b, m, k, n = 16, 64, 64, 32
+    h = spmm.DynamicHandle(m, k, b, 8, "f16")
+    X = torch.ones((k, n), dtype=torch.float16, device="cuda")
+    v = torch.ones((8, b, b), dtype=torch.float16, device="cuda")
+    status = torch.zeros(1, dtype=torch.int32, device="cuda")
+    for rows, cols, nnz, want in [([0] * 8, [0] * 8, 9, spmm.ERR_CAPACITY), ([0] * 8, [0] * 8, -1, spmm.ERR_CAPACITY),
+                                  ([0, 4] + [0] * 6, [0, 1] + [0] * 6, 2, spmm.ERR_BAD_INDEX),
+                                  ([0, 1] + [0] * 6, [0, -1] + [0] * 6, 2, spmm.ERR_BAD_INDEX)]:
+        Y = torch.full((m, n), 7.0, dtype=torch.float16, device="cuda")
+        r = torch.tensor(rows, dtype=torch.int32, device="cuda")
+        c = torch.tensor(cols, dtype=torch.int32, device="cuda")
+        nz = torch.tensor([nnz], dtype=torch.int32, device="cuda")
+        h.run(nz, r, c, v, X, Y, status)
+        torch.cuda.synchronize()
+        assert status.item() == want
+        assert torch.all(Y == 7.0).item()
+    # the handle recovers on the next valid call
+    nz = torch.tensor([1], dtype=torch.int32, device="cuda")
+    r = torch.zeros(8, dtype=torch.int32, device="cuda")
+    Y = torch.full((m, n), 7.0, dtype=torch.float16, device="cuda")
+    h.run(nz, r, r, v, X, Y, status)
+    torch.cuda.synchronize()
+    assert status.item() == 0
+    assert torch.all(Y[:16] == 16.0).item() and torch.all(Y[16:] == 0).item()
+
+
+@pytest.mark.parametrize("w", ["f16", "fp8"])
+def test_dynamic_call_stream_config3_shape(w):
+    """m=k=4096, n=512, b=16, max density 1/8: a few calls with fresh patterns."""
+    b, m, k, n = 16, 4096, 4096, 512
+    mb = kb = 256
+    max_nnz = mb * kb // 8
+    h = spmm.DynamicHandle(m, k, b, max_nnz, w, x="f16")
+    X_store = synth.to_storage(synth.normal((k, n), 2), "f16")
+    X = dev(X_store)
+    X64 = synth.storage_to_f64(X_store, "f16")
+    cols_s = np.sort(np.random.default_rng(0).choice(n, 64, replace=False))
+    for i in range(3):
+        rows, cols, vals = synth.dynamic_call(mb, kb, b, max_nnz, seed=3 + i, dtype="f16")
+        scales = None
+        if w == "fp8":
+            codes, sc = synth.quantize_e4m3fn_blocks(synth.storage_to_f64(vals, "f16").astype(np.float32))
+            from oracle import fp8_ref
+            v64 = fp8_ref.dequantize_blocks(codes, sc)
+            vals_dev = dev(np.concatenate([codes, np.zeros((max_nnz - len(rows), b, b), np.uint8)]))
+            scales = dev(np.concatenate([sc, np.ones(max_nnz - len(rows), np.float32)]))
+        else:
+            v64 = synth.storage_to_f64(vals, "f16")
+            vals_dev = None
+        r, c, v, nnz = _dyn_inputs(rows, cols, vals if w != "fp8" else np.zeros((len(rows), b, b), np.float16),
+                                   max_nnz, b)
+        if vals_dev is not None:
+            v = vals_dev
+        Y = torch.full((m, n), float("nan"), dtype=torch.float16, device="cuda")
+        status = torch.zeros(1, dtype=torch.int32, device="cuda")
+        h.run(nnz, r, c, v, X, Y, status, scales=scales)
+        torch.cuda.synchronize()
+        assert status.item() == 0
+        ref = O.spmm_blockwise_columns(m, k, b, rows, cols, v64, X64, cols_s)
+        assert O.rel_fro(Y.cpu().numpy().astype(np.float64)[:, cols_s], ref) <= 5e-3

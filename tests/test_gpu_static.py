@@ -1,0 +1,138 @@
+"""GPU parity of the static path against the FP64 oracle (through the C ABI)."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import plan_ref
+from oracle import spmm_ref as O
+from paper_2303_16999_amd import spmm
+from gpu_cases import TOL, Case, dev, round_like, y_f64
+
+pytestmark = pytest.mark.gpu
+
+
+def _check(case, Y, cols=None, tol=None):
+    ref = case.oracle(cols)
+    got = y_f64(Y, case) if cols is None else y_f64(Y, case)[:, cols]
+    err = O.rel_fro(got, ref)
+    assert np.all(np.isfinite(got)), "non-finite output"
+    assert err <= (tol or TOL[case.y if case.y != "f32" or case.x == "f32" else case.x]), err
+    return err
+
+
+def test_config1_fp32_small_static():
+    """W 1024x1024, b=16, d=1/16, FP32 N(0,1); X 1024x64 FP32."""
+    c = Case(1024, 1024, 64, 16, 1 / 16, w="f32", seed=0)
+    _, Y = c.run_static()
+    assert _check(c, Y, tol=1e-5) <= 1e-5
+
+
+@pytest.mark.parametrize("w,y", [("f16", "f16"), ("bf16", "bf16"), ("f16", "f32"), ("bf16", "f32"), ("f32", "f32")])
+@pytest.mark.parametrize("b", [16, 32])
+def test_ragged_shapes_all_dtypes(w, y, b):
+    # several row groups, chunks and n-tiles, with partial edge blocks and an n tail
+    m, k, n = 7 * b + 5, 13 * b + 3, 300
+    c = Case(m, k, n, b, 0.3, w=w, y=y, seed=3)
+    _, Y = c.run_static()
+    _check(c, Y, tol=1e-5 if w == "f32" else 5e-3)
+
+
+@pytest.mark.parametrize("x,y", [("f16", "f16"), ("bf16", "bf16"), ("bf16", "f32"), ("f16", "f32")])
+@pytest.mark.parametrize("b", [16, 32])
+def test_fp8_block_scales(x, y, b):
+    c = Case(9 * b, 11 * b + 7, 200, b, 0.35, w="fp8", x=x, y=y, seed=5, scaled=True)
+    _, Y = c.run_static()
+    _check(c, Y, tol=5e-3)
+
+
+@pytest.mark.parametrize("w", ["f16", "bf16", "f32", "fp8"])
+@pytest.mark.parametrize("b", [16, 32])
+def test_integer_data_bit_exact(w, b):
+    # entries in {-2..2}: every partial sum is an exact small integer, so the
+    # device result must equal the oracle bit for bit after rounding to Y
+    c = Case(6 * b, 10 * b, 130, b, 0.25, w=w, seed=7, integer=True)
+    _, Y = c.run_static()
+    got = y_f64(Y, c)
+    ref = c.oracle()
+    assert np.abs(ref).max() <= 256
+    assert np.array_equal(got, round_like(ref, c.y))
+
+
+@pytest.mark.parametrize("w", ["f16", "bf16", "f32"])
+def test_identity_block_permutation_bit_exact(w):
+    b, nb, n = 16, 24, 96
+    perm = np.random.default_rng(1).permutation(nb)
+    mask = np.zeros((nb, nb), np.uint8)
+    mask[np.arange(nb), perm] = 1
+    c = Case(nb * b, nb * b, n, b, 0.0, w=w, seed=2, mask=mask)
+    eye = np.stack([np.eye(b, dtype=np.float32)] * nb)
+    from paper_2303_16999_amd import synth
+    c.vals_store = synth.to_storage(eye, w)
+    c.vals64 = synth.storage_to_f64(c.vals_store, w)
+    _, Y = c.run_static()
+    got = y_f64(Y, c)
+    expect = np.concatenate([c.X64[col * b:(col + 1) * b] for col in perm])
+    assert np.array_equal(got, expect)
+
+
+def test_density_zero_overwrites_nan():
+    c = Case(100, 70, 50, 16, 0.0, w="f16")
+    _, Y = c.run_static()
+    assert torch.all(Y[:, :50] == 0).item()
+    assert torch.isnan(Y[:, 50:]).all().item() if Y.shape[1] > 50 else True
+
+
+def test_empty_rows_and_untouched_columns_beyond_n():
+    c = Case(160, 96, 40, 16, 0.5, w="f16", seed=4, ldy=64)
+    mask = c.mask.copy()
+    mask[3] = 0
+    c = Case(160, 96, 40, 16, 0.5, w="f16", seed=4, ldy=64, mask=mask)
+    _, Y = c.run_static()
+    _check(c, Y)
+    assert torch.all(Y[48:64, :40] == 0).item()
+    assert torch.isnan(Y[:, 40:]).all().item()  # columns in [n, ldy) are never written
+
+
+def test_deterministic_and_repeatable():
+    c = Case(512, 640, 384, 16, 1 / 8, w="f16", seed=9)
+    plan, Y1 = c.run_static()
+    vals, X, scales = c.device_inputs()
+    Y2 = c.new_Y()
+    plan.run(X, Y2, n=c.n)
+    torch.cuda.synchronize()
+    assert torch.equal(Y1[:, : c.n], Y2[:, : c.n])
+
+
+@pytest.mark.parametrize("P", [1, 2, 5])
+def test_panels_walk_several_groups(P):
+    c = Case(40 * 16, 24 * 16, 200, 16, 0.2, w="bf16", seed=11)
+    plan, Y = c.run_static(group_rows=8, num_panels=P)
+    _check(c, Y)
+    ex = plan.export()
+    ref = plan_ref.plan_from_mask(c.mask, 8, P)
+    for key in ("row_ptr", "col_idx", "panel_ptr"):
+        assert np.array_equal(ex[key], ref[key]), key
+
+
+@pytest.mark.parametrize("b,mb,kb,d,gr,P", [(16, 64, 64, 1 / 16, 32, 2), (16, 33, 70, 0.4, 8, 5),
+                                            (32, 17, 9, 0.5, 4, 3), (32, 64, 40, 0.1, 16, 4),
+                                            (16, 512, 512, 1 / 16, 32, 16), (16, 1, 1, 1.0, 8, 1)])
+def test_gpu_plan_bit_exact_vs_oracle(b, mb, kb, d, gr, P):
+    from paper_2303_16999_amd import synth
+    mask = synth.block_mask(mb, kb, d, seed=mb + kb)
+    plan = spmm.StaticPlan(mb * b, kb * b, b, mask, "f16", group_rows=gr, num_panels=P)
+    ex = plan.export()
+    ref = plan_ref.plan_from_mask(mask, gr, P)
+    for key in ("row_ptr", "col_idx", "panel_ptr"):
+        assert np.array_equal(ex[key], ref[key]), key
+
+
+def test_headline_shape_sampled_columns():
+    """m=k=8192, n=4096, b=16, d=1/16, FP16: 128 seeded columns checked exactly
+    against the oracle (column separability), the rest for finiteness."""
+    c = Case(8192, 8192, 4096, 16, 1 / 16, w="f16", seed=0)
+    _, Y = c.run_static()
+    cols = np.sort(np.random.default_rng(123).choice(4096, 128, replace=False))
+    err = O.rel_fro(y_f64(Y, c)[:, cols], c.oracle(cols))
+    assert err <= 5e-3, err
+    assert torch.isfinite(Y).all().item()
