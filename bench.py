@@ -1,0 +1,379 @@
+"""Benchmark of the block-sparse x dense SpMM on one MI355X.
+
+Default (the driver's contract): one step = one static SpMM Y = W X at the
+static-sweep point m = k = 8192, n = 4096, b = 16, density 1/16, FP16 inputs
+and output with FP32 accumulation (uniformly random blocks, N(0,1) values).
+Inputs are resident in HBM before timing. W untimed warmup steps, then K timed
+steps between device synchronisations; HIP events on the launch stream give
+the average kernel time. Printed as one JSON line with the roofline of the
+kernel, the dense FP16 GEMM of the same shape on the same GPU, and the FP64
+oracle timed on the host cores over a bounded column sample.
+
+Other modes print their own JSON lines:
+  --mode sweep      the static sweep (m = k = 8192, n in {256, 1024, 4096},
+                    b in {16, 32}, densities 1/128..1/4) next to dense FP16
+  --mode dynamic    1000 dynamic calls, m = k = 4096, n = 512, b = 16, d_max 1/8
+  --mode precision  m = k = 16384, n = 2048, b in {16, 32}, BF16 and FP8 weights
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "effective TFLOP/s (nonzero FLOPs) and speedup vs dense FP16 GEMM; serve p50/p99"
+HBM_PEAK_GBS = 8000.0
+MFMA_PEAK_TFLOPS = {"f16": 2500.0, "bf16": 2500.0, "fp8": 2500.0, "f32": 157.3}
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2303_16999_amd", "csrc", "spmm_mfma.hip")
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "spmm_mfma_f16_b16_m8192_n4096_d16_traffic.md")
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--mode", default="headline", choices=["headline", "sweep", "dynamic", "precision", "copy"])
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--no-dense", action="store_true", help="skip the dense FP16 comparator")
+    ap.add_argument("--out", default=None, help="also append JSON lines to this file")
+    ap.add_argument("--calls", type=int, default=1000, help="dynamic mode: number of calls")
+    return ap.parse_args()
+
+
+def emit(rec, out=None):
+    line = json.dumps(rec)
+    print(line, flush=True)
+    if out:
+        with open(out, "a") as fh:
+            fh.write(line + "\n")
+
+
+# ------------------------------------------------------------------ workloads
+
+class StaticProblem:
+    """Seeded static SpMM on the device: pattern s, values s+1, X s+2."""
+
+    def __init__(self, m, k, n, b, d, w="f16", x=None, y=None, seed=0, scaled=False):
+        import torch
+        from paper_2303_16999_amd import spmm, synth
+        x = x or ("f16" if w == "fp8" else w)
+        y = y or x
+        self.m, self.k, self.n, self.b, self.d, self.w, self.x, self.y = m, k, n, b, d, w, x, y
+        self.seed = seed
+        mb, kb = -(-m // b), -(-k // b)
+        self.mask = synth.block_mask(mb, kb, d, seed)
+        self.rows, self.cols = synth.mask_coo(self.mask)
+        self.nnzb = len(self.rows)
+        vals = synth.scaled_block_values(self.nnzb, b, seed + 1) if scaled else synth.normal((self.nnzb, b, b), seed + 1)
+        self.scales_store = None
+        if w == "fp8":
+            self.vals_store, self.scales_store = synth.quantize_e4m3fn_blocks(vals)
+        else:
+            self.vals_store = synth.to_storage(vals, w)
+        self.vals_raw = vals
+        X = synth.normal((k, n), seed + 2)
+        self.X_store = synth.to_storage(X, x)
+        self.plan = spmm.StaticPlan(m, k, b, self.mask, w, x, y, n_hint=n)
+        t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).view(torch.bfloat16) if a.dtype == np.uint16 \
+            else torch.from_numpy(np.ascontiguousarray(a))
+        self.values_dev = t(self.vals_store).cuda()
+        self.scales_dev = t(self.scales_store).cuda() if self.scales_store is not None else None
+        self.X = t(self.X_store).cuda()
+        self.Y = torch.empty((m, n), dtype=spmm.torch_dtype(spmm.DTYPE_CODES[y]), device="cuda")
+        self.plan.set_values(self.values_dev, self.scales_dev)
+        torch.cuda.synchronize()
+
+    def step(self):
+        self.plan.run(self.X, self.Y)
+
+    def flops(self):
+        return 2.0 * self.n * self.nnzb * self.b * self.b  # full blocks at every benchmark shape
+
+    def alg_bytes(self):
+        eb = {"f32": 4, "f16": 2, "bf16": 2, "fp8": 1}
+        B = eb[self.x] * self.k * self.n + eb[self.y] * self.m * self.n
+        B += eb[self.w] * self.nnzb * self.b * self.b + 4 * self.nnzb + 4 * (-(-self.m // self.b) + 1)
+        if self.w == "fp8":
+            B += 4 * self.nnzb
+        return float(B)
+
+
+def time_steps(step, steps, warmup):
+    """Average ms per step with events on the current (launch) stream."""
+    import torch
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        step()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def time_cold(step, reps, flush):
+    """Median ms of single steps with L2 and the Infinity Cache flushed between them."""
+    import torch
+    ts = []
+    for _ in range(reps):
+        flush.add_(1.0)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        step()
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    return float(np.median(ts))
+
+
+def dense_fp16(m, k, n, steps, warmup, useful_flops):
+    import torch
+    g = torch.Generator(device="cuda").manual_seed(1234)
+    A = torch.randn((m, k), device="cuda", dtype=torch.float16, generator=g)
+    B = torch.randn((k, n), device="cuda", dtype=torch.float16, generator=g)
+    C = torch.empty((m, n), device="cuda", dtype=torch.float16)
+    ms = time_steps(lambda: torch.matmul(A, B, out=C), steps, warmup)
+    del A, B, C
+    return {"ms": ms, "tflops_useful": useful_flops / (ms * 1e-3) / 1e12,
+            "tflops_dense": 2.0 * m * k * n / (ms * 1e-3) / 1e12}
+
+
+def cpu_baseline(prob, target_s=10.0):
+    """The FP64 oracle (blockwise form) on a bounded column sample of the same workload."""
+    from oracle import spmm_ref as O
+    from paper_2303_16999_amd import synth
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:
+        threads = 1
+    vals64 = synth.storage_to_f64(prob.vals_store, prob.w) if prob.w != "fp8" else None
+    if vals64 is None:
+        from oracle import fp8_ref
+        vals64 = fp8_ref.dequantize_blocks(prob.vals_store, prob.scales_store)
+    X64 = synth.storage_to_f64(prob.X_store, prob.x)
+    cols = 64
+    while True:
+        sel = np.arange(cols)
+        t0 = time.perf_counter()
+        O.spmm_blockwise_columns(prob.m, prob.k, prob.b, prob.rows, prob.cols, vals64, X64, sel)
+        dt = time.perf_counter() - t0
+        if dt >= target_s / 4 or cols >= prob.n:
+            break
+        cols = min(prob.n, cols * 4)
+    fl = 2.0 * cols * prob.nnzb * prob.b * prob.b
+    return {"value": fl / dt / 1e12, "unit": "TFLOP/s", "cores": int(threads), "kind": "oracle",
+            "sample": "FP64 blockwise oracle on the first %d of %d columns of X (exact by column separability), "
+                      "%.2f s" % (cols, prob.n, dt)}
+
+
+def traffic_from_profile():
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel source; else None."""
+    if not os.path.exists(TRAFFIC_SUMMARY):
+        return None
+    src_hash = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()[:16]
+    fields = {}
+    for line in open(TRAFFIC_SUMMARY):
+        if ":" in line and line.strip().startswith("- "):
+            key, val = line.strip()[2:].split(":", 1)
+            fields[key.strip()] = val.strip()
+    if fields.get("kernel_source_sha256_16") != src_hash:
+        return None
+    try:
+        return float(fields["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+# ------------------------------------------------------------------ modes
+
+def mode_headline(args):
+    import torch
+    prob = StaticProblem(8192, 8192, 4096, 16, 1 / 16, "f16", seed=0)
+    ms = time_steps(prob.step, args.steps, args.warmup)
+    flops, bytes_ = prob.flops(), prob.alg_bytes()
+    tflops = flops / (ms * 1e-3) / 1e12
+    achieved = bytes_ / (ms * 1e-3) / 1e9
+    flush = torch.empty(512 * 1024 * 1024 // 4, dtype=torch.float32, device="cuda")
+    cold_ms = time_cold(prob.step, 10, flush)
+    del flush
+    rec = {
+        "metric": METRIC, "value": round(tflops, 3), "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms, 5), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f16", "data": "synthetic",
+        "config": {"workload": "static block-sparse SpMM, m=k=8192, n=4096, b=16, density 1/16, FP16 in/out, "
+                               "FP32 accumulate (a point of the static sweep)",
+                   "m": 8192, "k": 8192, "n": 4096, "b": 16, "density": 1 / 16, "nnz_blocks": prob.nnzb},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_from_profile()},
+        "mfma_frac": round(tflops / MFMA_PEAK_TFLOPS["f16"], 4),
+        "cold_ms": round(cold_ms, 5),
+        "cold_tflops": round(flops / (cold_ms * 1e-3) / 1e12, 3),
+    }
+    if not args.no_dense:
+        dn = dense_fp16(8192, 8192, 4096, max(5, args.steps // 2), 3, flops)
+        rec["dense_fp16"] = {k: round(v, 4) for k, v in dn.items()}
+        rec["speedup_vs_dense"] = round(dn["ms"] / ms, 3)
+    if not args.no_cpu:
+        rec["cpu_baseline"] = cpu_baseline(prob)
+    emit(rec, args.out)
+
+
+def mode_sweep(args):
+    import torch
+    dense_cache = {}
+    for n in (256, 1024, 4096):
+        for b in (16, 32):
+            for dd in (128, 64, 32, 16, 8, 4):
+                prob = StaticProblem(8192, 8192, n, b, 1.0 / dd, "f16", seed=0)
+                ms = time_steps(prob.step, args.steps, args.warmup)
+                fl = prob.flops()
+                if n not in dense_cache:
+                    dense_cache[n] = dense_fp16(8192, 8192, n, args.steps, args.warmup, 1.0)["ms"]
+                rec = {"mode": "sweep", "m": 8192, "k": 8192, "n": n, "b": b, "density": 1.0 / dd,
+                       "ms": round(ms, 5), "tflops": round(fl / (ms * 1e-3) / 1e12, 3),
+                       "hbm_frac": round(prob.alg_bytes() / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                       "dense_ms": round(dense_cache[n], 5), "speedup_vs_dense": round(dense_cache[n] / ms, 3)}
+                emit(rec, args.out)
+                del prob
+                torch.cuda.empty_cache()
+
+
+def mode_precision(args):
+    import torch
+    from oracle import fp8_ref
+    from oracle import spmm_ref as O
+    from paper_2303_16999_amd import synth
+    for b in (16, 32):
+        for w, y in (("bf16", "bf16"), ("bf16", "f32"), ("fp8", "bf16"), ("fp8", "f32")):
+            prob = StaticProblem(16384, 16384, 2048, b, 1 / 16, w, x="bf16", y=y, seed=0, scaled=True)
+            ms = time_steps(prob.step, args.steps, args.warmup)
+            cols = np.sort(np.random.default_rng(7).choice(2048, 64, replace=False))
+            X64 = synth.storage_to_f64(prob.X_store, "bf16")
+            v64 = fp8_ref.dequantize_blocks(prob.vals_store, prob.scales_store) if w == "fp8" \
+                else synth.storage_to_f64(prob.vals_store, w)
+            ref = O.spmm_blockwise_columns(prob.m, prob.k, b, prob.rows, prob.cols, v64, X64, cols)
+            Yd = prob.Y.float().cpu().numpy().astype(np.float64)[:, cols]
+            rec = {"mode": "precision", "b": b, "w": w, "x": "bf16", "y": y, "ms": round(ms, 5),
+                   "tflops": round(prob.flops() / (ms * 1e-3) / 1e12, 3), "rel_fro_vs_oracle": O.rel_fro(Yd, ref)}
+            if w == "fp8":
+                raw = O.spmm_blockwise_columns(prob.m, prob.k, b, prob.rows, prob.cols,
+                                               prob.vals_raw.astype(np.float64), X64, cols)
+                rec["fp8_quantisation_rel_fro"] = O.rel_fro(ref, raw)
+            emit(rec, args.out)
+            del prob
+            torch.cuda.empty_cache()
+
+
+def mode_dynamic(args):
+    """Dynamic mode: m = k = 4096, n = 512, b = 16, max density 1/8; every call
+    brings a fresh pattern (nnz uniform in [max/2, max]) and fresh FP16 values.
+    All call inputs are uploaded before timing; per-call HIP events."""
+    import torch
+    from paper_2303_16999_amd import spmm, synth
+    m = k = 4096
+    n, b = 512, 16
+    mb = kb = m // b
+    max_nnz = mb * kb // 8
+    calls = args.calls
+    seed = 0
+    g = torch.Generator(device="cuda")
+    rows_d = torch.empty((calls, max_nnz), dtype=torch.int32, device="cuda")
+    cols_d = torch.empty((calls, max_nnz), dtype=torch.int32, device="cuda")
+    vals_d = torch.empty((calls, max_nnz, b, b), dtype=torch.float16, device="cuda")
+    nnz_d = torch.empty((calls, 1), dtype=torch.int32, device="cuda")
+    nnz_h = np.zeros(calls, np.int64)
+    patterns = []
+    for i in range(calls):
+        r = synth.rng(seed + 3 + i)
+        nnz = int(r.integers(max_nnz // 2, max_nnz + 1))
+        flat = r.choice(mb * kb, size=nnz, replace=False)
+        rr, cc = (flat // kb).astype(np.int32), (flat % kb).astype(np.int32)
+        rows_d[i, :nnz] = torch.from_numpy(rr).cuda()
+        cols_d[i, :nnz] = torch.from_numpy(cc).cuda()
+        g.manual_seed(seed + 3 + i)
+        vals_d[i, :nnz] = torch.randn((nnz, b, b), generator=g, device="cuda", dtype=torch.float32).half()
+        nnz_d[i, 0] = nnz
+        nnz_h[i] = nnz
+        if i < 32:
+            patterns.append((rr, cc))
+    X = torch.from_numpy(synth.to_storage(synth.normal((k, n), seed + 2), "f16")).cuda()
+    Y = torch.empty((m, n), dtype=torch.float16, device="cuda")
+    status = torch.zeros((calls, 1), dtype=torch.int32, device="cuda")
+    h = spmm.DynamicHandle(m, k, b, max_nnz, "f16", n_hint=n)
+    call = lambda i: h.run(nnz_d[i], rows_d[i], cols_d[i], vals_d[i], X, Y, status[i])
+    for i in range(min(args.warmup, calls)):
+        call(i)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(calls + 1)]
+    ev[0].record()
+    for i in range(calls):
+        call(i)
+        ev[i + 1].record()
+    torch.cuda.synchronize()
+    per = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(calls)])
+    assert int(status.max().item()) == 0, "a dynamic call reported an error"
+    flops = 2.0 * nnz_h * b * b * n
+    # static path on the same patterns (plans built outside timing)
+    st_ms, dy_ms = [], []
+    for i, (rr, cc) in enumerate(patterns):
+        M = np.zeros((mb, kb), np.uint8)
+        M[rr, cc] = 1
+        order = np.lexsort((cc, rr))
+        plan = spmm.StaticPlan(m, k, b, M, "f16", n_hint=n)
+        plan.set_values(vals_d[i, : len(rr)][torch.from_numpy(order).cuda()].contiguous())
+        st_ms.append(time_steps(lambda: plan.run(X, Y), 10, 2))
+        dy_ms.append(time_steps(lambda: call(i), 10, 2))
+        plan.close()
+    dn = dense_fp16(m, k, n, 20, 5, 1.0)
+    rec = {"mode": "dynamic", "m": m, "k": k, "n": n, "b": b, "max_density": 1 / 8, "calls": calls,
+           "call_ms_mean": round(float(per.mean()), 5), "call_ms_p50": round(float(np.percentile(per, 50)), 5),
+           "call_ms_p99": round(float(np.percentile(per, 99)), 5),
+           "tflops": round(float(flops.sum() / (per.sum() * 1e-3) / 1e12), 3),
+           "static_ms_mean_same_patterns": round(float(np.mean(st_ms)), 5),
+           "dynamic_ms_mean_same_patterns": round(float(np.mean(dy_ms)), 5),
+           "dynamic_over_static_throughput": round(float(np.mean(st_ms) / np.mean(dy_ms)), 3),
+           "dense_fp16_ms": round(dn["ms"], 5), "dynamic_speedup_vs_dense": round(dn["ms"] / float(per.mean()), 3),
+           "static_speedup_vs_dense": round(dn["ms"] / float(np.mean(st_ms)), 3)}
+    emit(rec, args.out)
+
+
+def mode_copy(args):
+    """Plain copy of a known size, for calibrating the HBM byte counters."""
+    import torch
+    x = torch.ones(256 * 1024 * 1024 // 4, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    ms = time_steps(lambda: y.copy_(x), args.steps, args.warmup)
+    emit({"mode": "copy", "bytes_read": x.numel() * 4, "bytes_written": y.numel() * 4, "ms": ms}, args.out)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (requested --gpus %d)" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs an MI355X GPU", file=sys.stderr)
+        sys.exit(1)
+    from paper_2303_16999_amd import spmm
+    spmm.lib()  # fails loudly if the HIP library is missing
+    {"headline": mode_headline, "sweep": mode_sweep, "precision": mode_precision, "copy": mode_copy,
+     "dynamic": mode_dynamic}[args.mode](args)
+
+
+if __name__ == "__main__":
+    main()

@@ -71,7 +71,9 @@ struct Geometry {
 // Chooses group_rows / chunk_cols for a shape. n_hint steers the row-group size
 // so that groups x n-tiles fills the chip.
 Geometry choose_geometry(int64_t m, int64_t k, int32_t b, int64_t nnz_hint, int64_t n_hint,
-                         const spmm_plan_opts* opts, int num_cus);
+                         const spmm_plan_opts* opts, int num_cus, spmm_dtype_t x);
+// True when (b, x dtype) runs on the pipelined kernel, whose k-chunk is 64 rows.
+bool uses_pipe(int32_t b, spmm_dtype_t x);
 
 // ------------------------------------------------------------------ plan building kernels
 // All of these enqueue on `stream` and do not synchronise.
@@ -82,6 +84,12 @@ spmm_status_t build_dynamic_plan(const int32_t* nnz_dev, const int32_t* rows, co
                                  int32_t max_nnz, int32_t mb, int32_t kb, const Geometry& geo,
                                  PlanBuffers& pb, int32_t* status_internal, int32_t* status_out,
                                  hipStream_t stream);
+// Dynamic, block-CSR form: validate, bucket by block row, sort rows by (column,
+// input index), gather values into CSR order, panels from the row groups.
+spmm_status_t build_dynamic_csr(const int32_t* nnz_dev, const int32_t* rows, const int32_t* cols, int32_t max_nnz,
+                                int32_t mb, int32_t kb, int32_t b, int32_t k, const Geometry& geo, PlanBuffers& pb,
+                                const void* vals, void* vals_out, int elem_bytes, const float* scales,
+                                float* scales_out, int32_t* status, int32_t* status_out, hipStream_t stream);
 // CSR (row_ptr, col_idx, csr_src) of a dynamic plan, derived from the cells.
 spmm_status_t dynamic_csr_from_cells(int32_t mb, const Geometry& geo, PlanBuffers& pb,
                                      const int32_t* status_internal, hipStream_t stream);
@@ -89,6 +97,19 @@ spmm_status_t dynamic_csr_from_cells(int32_t mb, const Geometry& geo, PlanBuffer
 // of edge blocks; FP8 scales follow the same permutation.
 spmm_status_t pack_values(const KernelPlan& kp, int64_t nnz, const void* src, void* dst, int elem_bytes,
                           const float* scales_src, float* scales_dst, hipStream_t stream);
+// Dynamic variant: the entry count is read on the device; skipped when *status != 0.
+spmm_status_t pack_values_dyn(const KernelPlan& kp, int64_t max_nnz, const int32_t* nnz_dev, const void* src,
+                              void* dst, int elem_bytes, const float* scales_src, float* scales_dst,
+                              const int32_t* status, hipStream_t stream);
+// Dynamic: *ovf = 1 when some (group, chunk) holds more than wcap blocks, else 0
+// (skipped when *status != 0, ovf left untouched then).
+spmm_status_t chunk_overflow_flag(const KernelPlan& kp, int32_t wcap, const int32_t* status, int32_t* ovf,
+                                  hipStream_t stream);
+// Copy values given in block-CSR order, zeroing the out-of-range part of edge blocks.
+spmm_status_t copy_values_csr(const int32_t* col_idx, int64_t nnz, int32_t b, int32_t k, const void* src, void* dst,
+                              int elem_bytes, const float* ssrc, float* sdst, hipStream_t stream);
+// Largest number of blocks in one (group, chunk) of a plan; synchronous.
+spmm_status_t max_chunk_blocks(const KernelPlan& kp, int32_t* scratch_dev, int32_t* out_host, hipStream_t stream);
 
 // ------------------------------------------------------------------ compute
 struct RunArgs {
@@ -102,8 +123,17 @@ struct RunArgs {
   int32_t n;
   spmm_dtype_t wt, xt, yt;
   const int32_t* status;  // skip everything when *status != 0 (dynamic), else nullptr
+  int64_t nnz;            // entries in W (capacity for dynamic calls)
+  int32_t pipe_ns;        // pipelined kernel: 16-column tiles per workgroup (4 or 8)
+  int32_t pipe_nwv;       // pipelined kernel: 16-byte weight vectors per loading lane (4 or 8)
+  bool fallback;          // run the general kernel even where the pipelined one applies
+  const int32_t* ovf;     // dynamic: device flag, nonzero when a chunk exceeds the pipelined stage
+  int32_t ovf_mode;       // 0: ignore ovf; 1: skip when *ovf != 0; 2: run only when *ovf != 0
 };
 spmm_status_t launch_spmm(const RunArgs& a, hipStream_t stream);
+// Row-wise kernel (16-bit X, b = 16 or 32): W and scales in block-CSR order.
+spmm_status_t launch_spmm_row(const RunArgs& a, const int32_t* row_ptr, const int32_t* col_idx, hipStream_t stream);
+
 
 int device_cu_count();
 

@@ -1,0 +1,195 @@
+// Dynamic-mode re-bucketing straight into block-CSR (PopSparse Section 3.3 and
+// Appendix A.2: the pattern arrives with every run and is distributed into
+// buckets sized from the declared maximum). Here a bucket is a block row:
+//   1. validate indices and count entries per block row (integer atomics);
+//   2. exclusive scan of the counts -> row_ptr (one workgroup);
+//   3. scatter every entry into its row (slots handed out by atomics);
+//   4. sort each row by (block column, input index): the result no longer
+//      depends on the order the atomics handed out slots;
+//   5. gather the values (and FP8 scales) into block-CSR order, zeroing the
+//      part of edge blocks beyond column k;
+// plus the cost-balanced panels of the row groups. Every kernel reads the
+// entry count from device memory and stops when the status word is set.
+#include "common.h"
+
+namespace spmm {
+namespace {
+
+__global__ void k_dyn_zero(int32_t* __restrict__ a, int64_t na, int32_t* __restrict__ status) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) *status = 0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < na; i += (int64_t)gridDim.x * blockDim.x)
+    a[i] = 0;
+}
+
+__global__ void k_dyn_row_count(const int32_t* __restrict__ nnz_dev, int32_t max_nnz, const int32_t* __restrict__ rows,
+                                const int32_t* __restrict__ cols, int32_t mb, int32_t kb, int32_t* __restrict__ row_cnt,
+                                int32_t* __restrict__ status) {
+  const int32_t nnz = *nnz_dev;
+  if (nnz < 0 || nnz > max_nnz) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) atomicMax(status, (int32_t)SPMM_ERR_CAPACITY);
+    return;
+  }
+  for (int32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < nnz; e += gridDim.x * blockDim.x) {
+    const int32_t r = rows[e], c = cols[e];
+    if (r < 0 || r >= mb || c < 0 || c >= kb) {
+      atomicMax(status, (int32_t)SPMM_ERR_BAD_INDEX);
+      continue;
+    }
+    atomicAdd(&row_cnt[r], 1);
+  }
+}
+
+// One workgroup of 1024 threads: exclusive scan of mb counts into row_ptr[0..mb].
+__global__ __launch_bounds__(1024) void k_dyn_scan_rows(const int32_t* __restrict__ cnt, int32_t mb,
+                                                        int32_t* __restrict__ row_ptr,
+                                                        const int32_t* __restrict__ status) {
+  if (*status) return;
+  __shared__ int32_t sh[1024];
+  const int tid = threadIdx.x;
+  const int per = (mb + 1023) / 1024;
+  const int lo = min(mb, tid * per), hi = min(mb, lo + per);
+  int32_t s = 0;
+  for (int i = lo; i < hi; ++i) s += cnt[i];
+  sh[tid] = s;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    const int32_t add = tid >= off ? sh[tid - off] : 0;
+    __syncthreads();
+    sh[tid] += add;
+    __syncthreads();
+  }
+  int32_t run = sh[tid] - s;
+  for (int i = lo; i < hi; ++i) {
+    row_ptr[i] = run;
+    run += cnt[i];
+  }
+  if (tid == 1023) row_ptr[mb] = sh[1023];
+}
+
+__global__ void k_dyn_row_scatter(const int32_t* __restrict__ nnz_dev, const int32_t* __restrict__ rows,
+                                  const int32_t* __restrict__ cols, const int32_t* __restrict__ row_ptr,
+                                  int32_t* __restrict__ fill, int32_t* __restrict__ col_idx, int32_t* __restrict__ src,
+                                  const int32_t* __restrict__ status) {
+  if (*status) return;
+  const int32_t nnz = *nnz_dev;
+  for (int32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < nnz; e += gridDim.x * blockDim.x) {
+    const int32_t r = rows[e];
+    const int32_t pos = row_ptr[r] + atomicAdd(&fill[r], 1);
+    col_idx[pos] = cols[e];
+    src[pos] = e;
+  }
+}
+
+// One workgroup per block row: each thread ranks entries of the row by
+// (column, input index) against all others and writes them into place. Rows
+// that fit are ranked from LDS, longer ones from a global copy.
+constexpr int kSortLds = 2048;
+__global__ __launch_bounds__(256) void k_dyn_row_sort(const int32_t* __restrict__ row_ptr,
+                                                      int32_t* __restrict__ col_idx, int32_t* __restrict__ src,
+                                                      int32_t* __restrict__ tmp_col, int32_t* __restrict__ tmp_src,
+                                                      const int32_t* __restrict__ status) {
+  if (*status) return;
+  __shared__ int32_t sc[kSortLds], ss[kSortLds];
+  const int32_t r = blockIdx.x;
+  const int32_t lo = row_ptr[r], hi = row_ptr[r + 1], len = hi - lo;
+  if (len <= 1) return;
+  const bool in_lds = len <= kSortLds;
+  for (int32_t i = threadIdx.x; i < len; i += blockDim.x) {
+    const int32_t c = col_idx[lo + i], v = src[lo + i];
+    if (in_lds) {
+      sc[i] = c;
+      ss[i] = v;
+    } else {
+      tmp_col[lo + i] = c;
+      tmp_src[lo + i] = v;
+    }
+  }
+  __syncthreads();
+  for (int32_t i = threadIdx.x; i < len; i += blockDim.x) {
+    const int32_t kc = in_lds ? sc[i] : tmp_col[lo + i], ks = in_lds ? ss[i] : tmp_src[lo + i];
+    int32_t rank = 0;
+    for (int32_t t = 0; t < len; ++t) {
+      const int32_t c = in_lds ? sc[t] : tmp_col[lo + t], s2 = in_lds ? ss[t] : tmp_src[lo + t];
+      rank += (c < kc) || (c == kc && s2 < ks);
+    }
+    col_idx[lo + rank] = kc;
+    src[lo + rank] = ks;
+  }
+}
+
+template <typename T>
+__global__ void k_dyn_gather(const int32_t* __restrict__ nnz_dev, const int32_t* __restrict__ src,
+                             const int32_t* __restrict__ col_idx, int32_t b, int32_t k, const T* __restrict__ vin,
+                             T* __restrict__ vout, const float* __restrict__ sin, float* __restrict__ sout,
+                             const int32_t* __restrict__ status) {
+  if (*status) return;
+  const int64_t nnz = *nnz_dev;
+  const int64_t bb = (int64_t)b * b;
+  const int32_t krem = k - (k / b) * b;
+  const int32_t kb_last = (k + b - 1) / b - 1;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nnz * bb; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t e = i / bb, w = i - e * bb;
+    T v = vin[(int64_t)src[e] * bb + w];
+    if (krem && col_idx[e] == kb_last && (int32_t)(w % b) >= krem) v = T(0);
+    vout[i] = v;
+    if (w == 0 && sin) sout[e] = sin[src[e]];
+  }
+}
+
+// Group costs straight from row_ptr, then prefix and panel boundaries.
+__global__ void k_dyn_group_cost(const int32_t* __restrict__ row_ptr, int32_t G, int32_t GR, int32_t mb,
+                                 int64_t* __restrict__ cost, const int32_t* status) {
+  if (*status) return;
+  const int32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= G) return;
+  const int32_t lo = g * GR, hi = min(mb, lo + GR);
+  cost[g] = (int64_t)(row_ptr[hi] - row_ptr[lo]) + (hi - lo);
+}
+
+__global__ void k_dyn_status_out(const int32_t* __restrict__ internal, int32_t* __restrict__ out) {
+  if (threadIdx.x == 0) *out = *internal;
+}
+
+}  // namespace
+
+spmm_status_t build_panels_from_costs(int32_t G, int32_t P, int64_t* cost_prefix, int32_t* panel_ptr,
+                                      const int32_t* status, hipStream_t s);
+
+spmm_status_t build_dynamic_csr(const int32_t* nnz_dev, const int32_t* rows, const int32_t* cols, int32_t max_nnz,
+                                int32_t mb, int32_t kb, int32_t b, int32_t k, const Geometry& geo, PlanBuffers& pb,
+                                const void* vals, void* vals_out, int elem_bytes, const float* scales,
+                                float* scales_out, int32_t* status, int32_t* status_out, hipStream_t s) {
+  if (mb > 1024 * 64) return fail(SPMM_ERR_UNSUPPORTED, "dynamic CSR builder supports at most 65536 block rows");
+  int32_t* row_cnt = pb.scratch;            // [mb]
+  int32_t* fill = pb.scratch + mb;          // [mb]
+  int32_t* tmp_col = pb.ent_col;            // [max_nnz] scratch for the row sort
+  int32_t* tmp_src = pb.ent_src;
+  hipLaunchKernelGGL(k_dyn_zero, dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>(256, ceil_div(2 * mb, 256)))),
+                     dim3(256), 0, s, row_cnt, (int64_t)2 * mb, status);
+  const unsigned egrid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(2048, ceil_div(max_nnz, 256)));
+  hipLaunchKernelGGL(k_dyn_row_count, dim3(egrid), dim3(256), 0, s, nnz_dev, max_nnz, rows, cols, mb, kb, row_cnt,
+                     status);
+  hipLaunchKernelGGL(k_dyn_scan_rows, dim3(1), dim3(1024), 0, s, row_cnt, mb, pb.row_ptr, status);
+  hipLaunchKernelGGL(k_dyn_row_scatter, dim3(egrid), dim3(256), 0, s, nnz_dev, rows, cols, pb.row_ptr, fill,
+                     pb.col_idx, pb.csr_src, status);
+  hipLaunchKernelGGL(k_dyn_row_sort, dim3((unsigned)mb), dim3(256), 0, s, pb.row_ptr, pb.col_idx, pb.csr_src, tmp_col,
+                     tmp_src, status);
+  if (vals_out && max_nnz > 0) {
+    const unsigned vgrid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(4096, ceil_div((int64_t)max_nnz * b * b, 1024)));
+    if (elem_bytes == 1)
+      hipLaunchKernelGGL(k_dyn_gather<uint8_t>, dim3(vgrid), dim3(256), 0, s, nnz_dev, pb.csr_src, pb.col_idx, b, k,
+                         (const uint8_t*)vals, (uint8_t*)vals_out, scales, scales_out, status);
+    else
+      hipLaunchKernelGGL(k_dyn_gather<uint16_t>, dim3(vgrid), dim3(256), 0, s, nnz_dev, pb.csr_src, pb.col_idx, b, k,
+                         (const uint16_t*)vals, (uint16_t*)vals_out, scales, scales_out, status);
+  }
+  hipLaunchKernelGGL(k_dyn_group_cost, dim3((unsigned)ceil_div(geo.num_groups, 256)), dim3(256), 0, s, pb.row_ptr,
+                     geo.num_groups, geo.group_rows, mb, pb.cost_prefix, status);
+  spmm_status_t st = build_panels_from_costs(geo.num_groups, geo.num_panels, pb.cost_prefix, pb.panel_ptr, status, s);
+  if (st != SPMM_OK) return st;
+  if (status_out) hipLaunchKernelGGL(k_dyn_status_out, dim3(1), dim3(64), 0, s, status, status_out);
+  SPMM_HIP(hipGetLastError());
+  return SPMM_OK;
+}
+
+}  // namespace spmm

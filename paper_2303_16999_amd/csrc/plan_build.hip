@@ -208,6 +208,19 @@ __global__ void k_panels(const int64_t* __restrict__ C, int32_t G, int32_t P, in
   panel_ptr[p] = lo;
 }
 
+}  // namespace
+
+spmm_status_t build_panels_from_costs(int32_t G, int32_t P, int64_t* cost_prefix, int32_t* panel_ptr,
+                                      const int32_t* status, hipStream_t s) {
+  hipLaunchKernelGGL(k_cost_scan, dim3(1), dim3(kScanThreads), 0, s, cost_prefix, G, status);
+  hipLaunchKernelGGL(k_panels, dim3((unsigned)ceil_div(P + 1, 256)), dim3(256), 0, s, cost_prefix, G, P, panel_ptr,
+                     status);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? SPMM_OK : fail_hip(e, "panel launch");
+}
+
+namespace {
+
 spmm_status_t build_panels(const Geometry& geo, int32_t mb, PlanBuffers& pb, const int32_t* status, hipStream_t s) {
   const int32_t G = geo.num_groups;
   hipLaunchKernelGGL(k_group_cost, dim3((unsigned)ceil_div(G, 256)), dim3(256), 0, s, pb.cell_ptr, G,
@@ -330,7 +343,118 @@ __global__ void k_pack(const int32_t* __restrict__ ent_src, const int32_t* __res
   }
 }
 
+template <typename T>
+__global__ void k_pack_dyn(const int32_t* __restrict__ ent_src, const int32_t* __restrict__ ent_col,
+                           const int32_t* __restrict__ nnz_dev, int32_t b, int32_t k, const T* __restrict__ src,
+                           T* __restrict__ dst, const float* __restrict__ ssrc, float* __restrict__ sdst,
+                           const int32_t* __restrict__ status) {
+  if (*status) return;
+  const int64_t nnz = *nnz_dev;
+  const int64_t bb = (int64_t)b * b;
+  const int32_t krem = k - (k / b) * b;
+  const int32_t kb_last = (k + b - 1) / b - 1;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nnz * bb; i += (int64_t)gridDim.x * blockDim.x) {
+    int64_t e = i / bb, w = i - e * bb;
+    int32_t col = (int32_t)(w % b);
+    T v = src[(int64_t)ent_src[e] * bb + w];
+    if (krem && ent_col[e] == kb_last && col >= krem) v = T(0);
+    dst[i] = v;
+    if (w == 0 && ssrc) sdst[e] = ssrc[ent_src[e]];
+  }
+}
+
+// Largest block count of one (group, chunk): cells of a chunk are contiguous.
+__global__ void k_max_chunk(const int32_t* __restrict__ cell_ptr, int64_t nchunks_total, int32_t GR,
+                            int32_t* __restrict__ out) {
+  int32_t best = 0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nchunks_total; i += (int64_t)gridDim.x * blockDim.x)
+    best = max(best, cell_ptr[(i + 1) * GR] - cell_ptr[i * GR]);
+  atomicMax(out, best);
+}
+
+__global__ void k_chunk_overflow(const int32_t* __restrict__ cell_ptr, int64_t nchunks_total, int32_t GR,
+                                 int32_t wcap, const int32_t* __restrict__ status, int32_t* __restrict__ ovf) {
+  if (*status) return;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nchunks_total; i += (int64_t)gridDim.x * blockDim.x)
+    if (cell_ptr[(i + 1) * GR] - cell_ptr[i * GR] > wcap) atomicOr(ovf, 1);
+}
+
+// Values in block-CSR order, zeroing the part of edge blocks beyond column k.
+template <typename T>
+__global__ void k_copy_csr(const int32_t* __restrict__ col_idx, int64_t nnz, int32_t b, int32_t k,
+                           const T* __restrict__ src, T* __restrict__ dst, const float* __restrict__ ssrc,
+                           float* __restrict__ sdst) {
+  const int64_t bb = (int64_t)b * b;
+  const int32_t krem = k - (k / b) * b;
+  const int32_t kb_last = (k + b - 1) / b - 1;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nnz * bb; i += (int64_t)gridDim.x * blockDim.x) {
+    int64_t e = i / bb, w = i - e * bb;
+    T v = src[i];
+    if (krem && col_idx[e] == kb_last && (int32_t)(w % b) >= krem) v = T(0);
+    dst[i] = v;
+    if (w == 0 && ssrc) sdst[e] = ssrc[e];
+  }
+}
+
 }  // namespace
+
+spmm_status_t copy_values_csr(const int32_t* col_idx, int64_t nnz, int32_t b, int32_t k, const void* src, void* dst,
+                              int elem_bytes, const float* ssrc, float* sdst, hipStream_t s) {
+  if (nnz == 0) return SPMM_OK;
+  const int64_t total = nnz * (int64_t)b * b;
+  unsigned grid = (unsigned)std::min<int64_t>(8192, ceil_div(total, 256));
+  if (elem_bytes == 1)
+    hipLaunchKernelGGL(k_copy_csr<uint8_t>, dim3(grid), dim3(256), 0, s, col_idx, nnz, b, k, (const uint8_t*)src,
+                       (uint8_t*)dst, ssrc, sdst);
+  else if (elem_bytes == 2)
+    hipLaunchKernelGGL(k_copy_csr<uint16_t>, dim3(grid), dim3(256), 0, s, col_idx, nnz, b, k, (const uint16_t*)src,
+                       (uint16_t*)dst, ssrc, sdst);
+  else
+    hipLaunchKernelGGL(k_copy_csr<uint32_t>, dim3(grid), dim3(256), 0, s, col_idx, nnz, b, k, (const uint32_t*)src,
+                       (uint32_t*)dst, ssrc, sdst);
+  SPMM_HIP(hipGetLastError());
+  return SPMM_OK;
+}
+
+spmm_status_t chunk_overflow_flag(const KernelPlan& kp, int32_t wcap, const int32_t* status, int32_t* ovf,
+                                  hipStream_t s) {
+  const int64_t total = (int64_t)kp.num_groups * kp.num_chunks;
+  hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, ovf, (int64_t)1, 0);
+  unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(1024, ceil_div(total, 256)));
+  hipLaunchKernelGGL(k_chunk_overflow, dim3(grid), dim3(256), 0, s, kp.cell_ptr, total, kp.group_rows, wcap, status, ovf);
+  SPMM_HIP(hipGetLastError());
+  return SPMM_OK;
+}
+
+spmm_status_t pack_values_dyn(const KernelPlan& kp, int64_t max_nnz, const int32_t* nnz_dev, const void* src,
+                              void* dst, int elem_bytes, const float* ssrc, float* sdst, const int32_t* status,
+                              hipStream_t s) {
+  if (max_nnz == 0) return SPMM_OK;
+  const int64_t total = max_nnz * (int64_t)kp.b * kp.b;
+  unsigned grid = (unsigned)std::min<int64_t>(4096, ceil_div(total, 256 * 4));
+  if (elem_bytes == 1)
+    hipLaunchKernelGGL(k_pack_dyn<uint8_t>, dim3(grid), dim3(256), 0, s, kp.ent_src, kp.ent_col, nnz_dev, kp.b, kp.k,
+                       (const uint8_t*)src, (uint8_t*)dst, ssrc, sdst, status);
+  else if (elem_bytes == 2)
+    hipLaunchKernelGGL(k_pack_dyn<uint16_t>, dim3(grid), dim3(256), 0, s, kp.ent_src, kp.ent_col, nnz_dev, kp.b, kp.k,
+                       (const uint16_t*)src, (uint16_t*)dst, ssrc, sdst, status);
+  else
+    hipLaunchKernelGGL(k_pack_dyn<uint32_t>, dim3(grid), dim3(256), 0, s, kp.ent_src, kp.ent_col, nnz_dev, kp.b, kp.k,
+                       (const uint32_t*)src, (uint32_t*)dst, ssrc, sdst, status);
+  SPMM_HIP(hipGetLastError());
+  return SPMM_OK;
+}
+
+spmm_status_t max_chunk_blocks(const KernelPlan& kp, int32_t* scratch_dev, int32_t* out_host, hipStream_t s) {
+  const int64_t total = (int64_t)kp.num_groups * kp.num_chunks;
+  hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, scratch_dev, (int64_t)1, 0);
+  unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(1024, ceil_div(total, 256)));
+  hipLaunchKernelGGL(k_max_chunk, dim3(grid), dim3(256), 0, s, kp.cell_ptr, total, kp.group_rows, scratch_dev);
+  SPMM_HIP(hipGetLastError());
+  SPMM_HIP(hipMemcpyAsync(out_host, scratch_dev, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  SPMM_HIP(hipStreamSynchronize(s));
+  return SPMM_OK;
+}
 
 spmm_status_t build_static_plan(const uint8_t* mask_dev, int32_t mb, int32_t kb, const Geometry& geo,
                                 PlanBuffers& pb, hipStream_t s) {

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -50,24 +51,48 @@ int device_cu_count() {
 
 static bool valid_block(int32_t b) { return b == 1 || b == 4 || b == 8 || b == 16 || b == 32; }
 
+bool uses_pipe(int32_t b, spmm_dtype_t x) { return b >= 16 && (x == SPMM_F16 || x == SPMM_BF16); }
+
 Geometry choose_geometry(int64_t m, int64_t k, int32_t b, int64_t nnz_hint, int64_t n_hint,
-                         const spmm_plan_opts* opts, int num_cus) {
-  (void)nnz_hint;
+                         const spmm_plan_opts* opts, int num_cus, spmm_dtype_t x) {
   Geometry g{};
   const int64_t mb = ceil_div(m, b), kb = ceil_div(k, b);
   if (n_hint <= 0) n_hint = 1024;
-  int32_t big = 0, small = 0, cw = 0;
-  int32_t ntile = 128;
-  if (b == 16) { big = 32; small = 8; cw = 8; }
-  else if (b == 32) { big = 16; small = 4; cw = 4; }
-  else { big = 64; small = 16; cw = 64 / b; ntile = 64; }  // small-block path
-  int32_t gr = big;
-  if (opts && opts->group_rows > 0) {
-    gr = opts->group_rows;
+  int32_t gr = 0, cw = 0;
+  if (uses_pipe(b, x)) {
+    // pipelined kernel: 64 k rows per chunk; the row group is the largest that
+    // keeps a chunk's expected blocks within half the staged capacity and
+    // still gives every CU two work units
+    cw = 64 / b;
+    const double d = std::max(1e-9, (double)nnz_hint / ((double)mb * (double)kb));
+    const double cap = 16384.0 / (2.0 * b * b);  // blocks of the larger weight stage
+    const int32_t cands16[3] = {32, 16, 8}, cands32[2] = {16, 8};
+    const int32_t* cands = b == 16 ? cands16 : cands32;
+    const int nc = b == 16 ? 3 : 2;
+    for (int i = 0; i < nc && !gr; ++i) {
+      const int64_t units = ceil_div(mb, cands[i]) * ceil_div(n_hint, 128);
+      if (cands[i] * cw * d <= 0.5 * cap && units >= 2 * (int64_t)num_cus) gr = cands[i];
+    }
+    if (!gr) {
+      // prefer parallelism: the smallest group that satisfies the capacity bound
+      gr = cands[nc - 1];
+      for (int i = nc - 1; i >= 0; --i)
+        if (cands[i] * cw * d <= 0.5 * cap) { gr = cands[i]; break; }
+    }
   } else {
+    int32_t big = 0, small = 0, ntile = 128;
+    if (b == 16) { big = 32; small = 8; cw = 8; }
+    else if (b == 32) { big = 16; small = 4; cw = 4; }
+    else { big = 64; small = 16; cw = 64 / b; ntile = 64; }  // small-block path
+    gr = big;
     const int64_t units_big = ceil_div(mb, big) * ceil_div(n_hint, ntile);
     if (units_big < 2 * (int64_t)num_cus) gr = small;
   }
+  if (const char* e = getenv("SPMM_GROUP_ROWS")) {  // tuning override
+    const int v = atoi(e);
+    if (v > 0) gr = v;
+  }
+  if (opts && opts->group_rows > 0) gr = opts->group_rows;
   g.group_rows = gr;
   g.chunk_cols = cw;
   g.num_groups = (int32_t)ceil_div(mb, gr);
@@ -78,7 +103,12 @@ Geometry choose_geometry(int64_t m, int64_t k, int32_t b, int64_t nnz_hint, int6
   return g;
 }
 
-static bool geometry_supported(int32_t b, int32_t gr) {
+static bool geometry_supported(int32_t b, int32_t gr, spmm_dtype_t x, int32_t num_chunks) {
+  if (uses_pipe(b, x)) {
+    if (num_chunks > 1024) return false;
+    if (b == 16) return gr == 32 || gr == 16 || gr == 8;
+    return gr == 16 || gr == 8;
+  }
   if (b == 16) return gr == 32 || gr == 8;
   if (b == 32) return gr == 16 || gr == 4;
   return gr == 64 || gr == 16;
@@ -86,10 +116,45 @@ static bool geometry_supported(int32_t b, int32_t gr) {
 
 spmm_status_t launch_spmm_mfma(const RunArgs& a, hipStream_t s);
 spmm_status_t launch_spmm_small(const RunArgs& a, hipStream_t s);
+spmm_status_t launch_pipe_f16(const RunArgs& a, hipStream_t s);
+spmm_status_t launch_pipe_bf16(const RunArgs& a, hipStream_t s);
+spmm_status_t launch_pipe_fp8f16(const RunArgs& a, hipStream_t s);
+spmm_status_t launch_pipe_fp8bf16(const RunArgs& a, hipStream_t s);
 
-spmm_status_t launch_spmm(const RunArgs& a, hipStream_t s) {
-  if (a.plan.b >= 16) return launch_spmm_mfma(a, s);
-  return launch_spmm_small(a, s);
+// blocks the pipelined kernel stages per chunk: nwv 16-byte vectors per lane of a 128-lane pair
+static int32_t pipe_wcap(int32_t b, spmm_dtype_t w, int32_t nwv) {
+  return nwv * 128 * 16 / (b * b * (w == SPMM_FP8_E4M3 ? 1 : 2));
+}
+
+spmm_status_t launch_spmm(const RunArgs& a0, hipStream_t s) {
+  if (!uses_pipe(a0.plan.b, a0.xt) || a0.fallback) {
+    if (a0.plan.b >= 16) return launch_spmm_mfma(a0, s);
+    return launch_spmm_small(a0, s);
+  }
+  RunArgs a = a0;
+  const int64_t units8 = ceil_div(a.n, 128) * (int64_t)a.plan.num_panels;
+  a.pipe_ns = units8 >= device_cu_count() ? 8 : 4;
+  if (const char* e = getenv("SPMM_PIPE_NS")) {  // tuning override: column tile 4 or 8 (x16 columns)
+    const int v = atoi(e);
+    if (v == 4 || v == 8) a.pipe_ns = v;
+  }
+  if (a.plan.group_rows == 8) a.pipe_nwv = 8;  // the one-row-per-wave variants stage the larger set
+  if ((int64_t)a.plan.k * a.ldx * 2 >= (int64_t)INT32_MAX || a.nnz * (int64_t)a.plan.b * a.plan.b * 2 >= (int64_t)INT32_MAX)
+    return fail(SPMM_ERR_UNSUPPORTED, "X or W larger than 2 GiB is not supported by the pipelined kernel");
+  spmm_status_t st;
+  if (a.wt == SPMM_FP8_E4M3) st = a.xt == SPMM_F16 ? launch_pipe_fp8f16(a, s) : launch_pipe_fp8bf16(a, s);
+  else st = a.xt == SPMM_F16 ? launch_pipe_f16(a, s) : launch_pipe_bf16(a, s);
+  if (st != SPMM_OK || a.ovf_mode != 1) return st;
+  // dynamic calls: the general kernel runs only if a chunk overflowed the stage
+  RunArgs f = a0;
+  f.ovf_mode = 2;
+  return launch_spmm_mfma(f, s);
+}
+
+// Kernel choice for 16-bit X: the row-wise kernel unless SPMM_KERNEL=pipe.
+static bool use_row_kernel() {
+  const char* e = getenv("SPMM_KERNEL");
+  return !(e && std::string(e) == "pipe");
 }
 
 static void free_plan_buffers(PlanBuffers& pb) {
@@ -172,10 +237,13 @@ struct spmm_plan_s {
   spmm_dtype_t w = SPMM_F32, x = SPMM_F32, y = SPMM_F32;
   Geometry geo{};
   PlanBuffers pb;
-  void* values = nullptr;
+  void* values = nullptr;      // entry (cell) order, for the pipelined and general kernels
   float* scales = nullptr;
+  void* values_csr = nullptr;  // block-CSR order, for the row-wise kernel
+  float* scales_csr = nullptr;
   bool has_values = false;
   int device = 0;
+  int32_t max_chunk = 0;  // most blocks in one (group, chunk)
 };
 
 struct spmm_dyn_s {
@@ -187,8 +255,12 @@ struct spmm_dyn_s {
   PlanBuffers pb;
   int32_t* status = nullptr;   // internal status word (device)
   int32_t* nnz_last = nullptr; // device copy of the last call's nnz
+  int32_t* ovf = nullptr;      // device flag: a chunk of the last call exceeds the pipelined stage
+  void* packed = nullptr;      // values in entry order, sized for max_nnzb
+  float* packed_scales = nullptr;
   int device = 0;
   bool ran = false;
+  bool csr_path = false;       // the last call built block-CSR directly (row-wise kernel)
 };
 
 extern "C" {
@@ -216,8 +288,8 @@ spmm_status_t spmm_plan_static(int64_t m, int64_t k, int32_t b, const uint8_t* b
   if (!p) return fail(SPMM_ERR_OOM, "host allocation failed");
   p->m = m; p->k = k; p->b = b; p->mb = (int32_t)mb; p->kb = (int32_t)kb; p->nnzb = nnzb;
   p->w = w; p->x = x; p->y = y;
-  p->geo = choose_geometry(m, k, b, nnzb, opts ? opts->n_hint : 0, opts, device_cu_count());
-  if (!geometry_supported(b, p->geo.group_rows)) {
+  p->geo = choose_geometry(m, k, b, nnzb, opts ? opts->n_hint : 0, opts, device_cu_count(), x);
+  if (!geometry_supported(b, p->geo.group_rows, x, p->geo.num_chunks)) {
     delete p;
     return fail(SPMM_ERR_UNSUPPORTED, "group_rows not available for this block size");
   }
@@ -234,18 +306,30 @@ spmm_status_t spmm_plan_static(int64_t m, int64_t k, int32_t b, const uint8_t* b
     if (e != hipSuccess) st = fail_hip(e, "hipMalloc values");
   }
   if (st == SPMM_OK && w == SPMM_FP8_E4M3) st = dev_alloc(&p->scales, nnzb);
+  if (st == SPMM_OK && uses_pipe(b, x)) {
+    const int64_t vbytes = nnzb * (int64_t)b * b * dtype_bytes(w);
+    e = hipMalloc(&p->values_csr, (size_t)std::max<int64_t>(vbytes, 16));
+    if (e != hipSuccess) st = fail_hip(e, "hipMalloc values");
+    if (st == SPMM_OK && w == SPMM_FP8_E4M3) st = dev_alloc(&p->scales_csr, nnzb);
+  }
   if (st == SPMM_OK && (e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking)) != hipSuccess)
     st = fail_hip(e, "hipStreamCreate");
   if (st == SPMM_OK && (e = hipMemcpyAsync(mask_dev, block_mask_host, (size_t)(mb * kb), hipMemcpyHostToDevice, s)) != hipSuccess)
     st = fail_hip(e, "mask upload");
   if (st == SPMM_OK) st = build_static_plan(mask_dev, (int32_t)mb, (int32_t)kb, p->geo, p->pb, s);
   if (st == SPMM_OK && (e = hipStreamSynchronize(s)) != hipSuccess) st = fail_hip(e, "plan build");
+  if (st == SPMM_OK) {
+    KernelPlan kp = kernel_plan(m, k, b, (int32_t)mb, (int32_t)kb, p->geo, p->pb);
+    st = max_chunk_blocks(kp, p->pb.scratch, &p->max_chunk, s);
+  }
   if (s) (void)hipStreamDestroy(s);
   if (mask_dev) (void)hipFree(mask_dev);
   if (st != SPMM_OK) {
     free_plan_buffers(p->pb);
     if (p->values) (void)hipFree(p->values);
     if (p->scales) (void)hipFree(p->scales);
+    if (p->values_csr) (void)hipFree(p->values_csr);
+    if (p->scales_csr) (void)hipFree(p->scales_csr);
     delete p;
     return st;
   }
@@ -264,6 +348,11 @@ spmm_status_t spmm_plan_set_values(spmm_plan_t p, const void* values_dev, const 
   KernelPlan kp = kernel_plan(p->m, p->k, p->b, p->mb, p->kb, p->geo, p->pb);
   st = pack_values(kp, p->nnzb, values_dev, p->values, dtype_bytes(p->w), scales_dev, p->scales, (hipStream_t)stream);
   if (st != SPMM_OK) return st;
+  if (p->values_csr) {
+    st = copy_values_csr(p->pb.col_idx, p->nnzb, p->b, (int32_t)p->k, values_dev, p->values_csr, dtype_bytes(p->w),
+                         scales_dev, p->scales_csr, (hipStream_t)stream);
+    if (st != SPMM_OK) return st;
+  }
   p->has_values = true;
   return SPMM_OK;
 }
@@ -294,6 +383,17 @@ spmm_status_t spmm_run_static(spmm_plan_t p, int64_t n, const void* X, int64_t l
   a.xt = p->x;
   a.yt = p->y;
   a.status = nullptr;
+  a.nnz = p->nnzb;
+  a.pipe_ns = 8;
+  a.pipe_nwv = p->max_chunk <= pipe_wcap(p->b, p->w, 4) ? 4 : 8;
+  a.fallback = p->max_chunk > pipe_wcap(p->b, p->w, 8);
+  a.ovf = nullptr;
+  a.ovf_mode = 0;
+  if (p->values_csr && use_row_kernel()) {
+    a.W = p->values_csr;
+    a.scales = p->scales_csr;
+    return launch_spmm_row(a, p->pb.row_ptr, p->pb.col_idx, (hipStream_t)stream);
+  }
   return launch_spmm(a, (hipStream_t)stream);
 }
 
@@ -327,6 +427,8 @@ spmm_status_t spmm_plan_destroy(spmm_plan_t p) {
   free_plan_buffers(p->pb);
   if (p->values) (void)hipFree(p->values);
   if (p->scales) (void)hipFree(p->scales);
+  if (p->values_csr) (void)hipFree(p->values_csr);
+  if (p->scales_csr) (void)hipFree(p->scales_csr);
   delete p;
   return SPMM_OK;
 }
@@ -351,8 +453,8 @@ spmm_status_t spmm_dynamic_create(int64_t m, int64_t k, int32_t b, int64_t max_n
   h->kb = (int32_t)ceil_div(k, b);
   h->max_nnzb = max_nnzb;
   h->w = w; h->x = x; h->y = y;
-  h->geo = choose_geometry(m, k, b, max_nnzb, opts ? opts->n_hint : 0, opts, device_cu_count());
-  if (!geometry_supported(b, h->geo.group_rows)) {
+  h->geo = choose_geometry(m, k, b, max_nnzb, opts ? opts->n_hint : 0, opts, device_cu_count(), x);
+  if (!geometry_supported(b, h->geo.group_rows, x, h->geo.num_chunks)) {
     delete h;
     return fail(SPMM_ERR_UNSUPPORTED, "group_rows not available for this block size");
   }
@@ -366,6 +468,13 @@ spmm_status_t spmm_dynamic_create(int64_t m, int64_t k, int32_t b, int64_t max_n
   if (st == SPMM_OK) st = alloc_plan_buffers(h->pb, h->geo, h->mb, max_nnzb, true);
   if (st == SPMM_OK) st = dev_alloc(&h->status, 2);
   if (st == SPMM_OK) st = dev_alloc(&h->nnz_last, 2);
+  if (st == SPMM_OK) st = dev_alloc(&h->ovf, 2);
+  if (st == SPMM_OK) {
+    const int64_t vbytes = max_nnzb * (int64_t)b * b * dtype_bytes(w);
+    e = hipMalloc(&h->packed, (size_t)std::max<int64_t>(vbytes, 16));
+    if (e != hipSuccess) st = fail_hip(e, "hipMalloc packed values");
+  }
+  if (st == SPMM_OK && w == SPMM_FP8_E4M3) st = dev_alloc(&h->packed_scales, max_nnzb);
   if (st == SPMM_OK) {
     if ((e = hipMemset(h->status, 0, 2 * sizeof(int32_t))) != hipSuccess) st = fail_hip(e, "hipMemset");
   }
@@ -373,6 +482,9 @@ spmm_status_t spmm_dynamic_create(int64_t m, int64_t k, int32_t b, int64_t max_n
     free_plan_buffers(h->pb);
     if (h->status) (void)hipFree(h->status);
     if (h->nnz_last) (void)hipFree(h->nnz_last);
+    if (h->ovf) (void)hipFree(h->ovf);
+    if (h->packed) (void)hipFree(h->packed);
+    if (h->packed_scales) (void)hipFree(h->packed_scales);
     delete h;
     return st;
   }
@@ -400,17 +512,49 @@ spmm_status_t spmm_run_dynamic(spmm_dyn_t h, const int32_t* nnzb_dev, const int3
   if (((uintptr_t)values_dev) % 16 != 0) return fail(SPMM_ERR_INVALID_ARG, "values are not 16-byte aligned");
   if ((st = check_device(h->device)) != SPMM_OK) return st;
   hipStream_t s = (hipStream_t)stream;
+  if (uses_pipe(h->b, h->x)) {
+    // 16-bit X, b >= 16: re-bucket into block-CSR and run the row-wise kernel
+    // (the same kernel and order as a static plan of the same pattern)
+    st = build_dynamic_csr(nnzb_dev, rows, cols, (int32_t)h->max_nnzb, h->mb, h->kb, h->b, (int32_t)h->k, h->geo,
+                           h->pb, values_dev, h->packed, dtype_bytes(h->w), scales_dev, h->packed_scales, h->status,
+                           status_dev, s);
+    if (st != SPMM_OK) return st;
+    SPMM_HIP(hipMemcpyAsync(h->nnz_last, nnzb_dev, sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    h->ran = true;
+    h->csr_path = true;
+    if (n == 0) return SPMM_OK;
+    RunArgs a{};
+    a.plan = kernel_plan(h->m, h->k, h->b, h->mb, h->kb, h->geo, h->pb);
+    a.W = h->packed;
+    a.scales = h->packed_scales;
+    a.X = X;
+    a.Y = Y;
+    a.ldx = ldx;
+    a.ldy = ldy;
+    a.n = (int32_t)n;
+    a.wt = h->w;
+    a.xt = h->x;
+    a.yt = h->y;
+    a.status = h->status;
+    a.nnz = h->max_nnzb;
+    return launch_spmm_row(a, h->pb.row_ptr, h->pb.col_idx, s);
+  }
   st = build_dynamic_plan(nnzb_dev, rows, cols, (int32_t)h->max_nnzb, h->mb, h->kb, h->geo, h->pb, h->status,
                           status_dev, s);
   if (st != SPMM_OK) return st;
   SPMM_HIP(hipMemcpyAsync(h->nnz_last, nnzb_dev, sizeof(int32_t), hipMemcpyDeviceToDevice, s));
   h->ran = true;
+  h->csr_path = false;
   if (n == 0) return SPMM_OK;
-  RunArgs a;
+  RunArgs a{};
   a.plan = kernel_plan(h->m, h->k, h->b, h->mb, h->kb, h->geo, h->pb);
-  a.W = values_dev;
-  a.scales = scales_dev;
-  a.gather = true;
+  // values into the plan's entry order (the same layout a static plan packs once)
+  st = pack_values_dyn(a.plan, h->max_nnzb, nnzb_dev, values_dev, h->packed, dtype_bytes(h->w), scales_dev,
+                       h->packed_scales, h->status, s);
+  if (st != SPMM_OK) return st;
+  a.W = h->packed;
+  a.scales = h->packed_scales;
+  a.gather = false;
   a.X = X;
   a.Y = Y;
   a.ldx = ldx;
@@ -420,6 +564,8 @@ spmm_status_t spmm_run_dynamic(spmm_dyn_t h, const int32_t* nnzb_dev, const int3
   a.xt = h->x;
   a.yt = h->y;
   a.status = h->status;
+  a.nnz = h->max_nnzb;
+  a.fallback = true;
   return launch_spmm(a, s);
 }
 
@@ -435,8 +581,10 @@ spmm_status_t spmm_dynamic_export(spmm_dyn_t h, int32_t* row_ptr, int32_t* col_i
   SPMM_HIP(hipMemcpy(&status, h->status, sizeof(int32_t), hipMemcpyDeviceToHost));
   if (status != 0) return fail((spmm_status_t)status, "the last dynamic call failed on the device");
   SPMM_HIP(hipMemcpy(&nnz, h->nnz_last, sizeof(int32_t), hipMemcpyDeviceToHost));
-  st = dynamic_csr_from_cells(h->mb, h->geo, h->pb, h->status, nullptr);
-  if (st != SPMM_OK) return st;
+  if (!h->csr_path) {
+    st = dynamic_csr_from_cells(h->mb, h->geo, h->pb, h->status, nullptr);
+    if (st != SPMM_OK) return st;
+  }
   SPMM_HIP(hipDeviceSynchronize());
   if (nnzb) *nnzb = nnz;
   if (row_ptr) SPMM_HIP(hipMemcpy(row_ptr, h->pb.row_ptr, sizeof(int32_t) * (h->mb + 1), hipMemcpyDeviceToHost));
@@ -462,6 +610,9 @@ spmm_status_t spmm_dynamic_destroy(spmm_dyn_t h) {
   free_plan_buffers(h->pb);
   if (h->status) (void)hipFree(h->status);
   if (h->nnz_last) (void)hipFree(h->nnz_last);
+  if (h->ovf) (void)hipFree(h->ovf);
+  if (h->packed) (void)hipFree(h->packed);
+  if (h->packed_scales) (void)hipFree(h->packed_scales);
   delete h;
   return SPMM_OK;
 }

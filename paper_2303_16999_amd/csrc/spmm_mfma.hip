@@ -50,13 +50,19 @@ struct Params {
   int32_t ntiles;
   int32_t num_units;
   const int32_t* status;
+  const int32_t* ovf_only;  // run only when *ovf_only != 0 (fallback for oversized chunks), else nullptr
 };
 
-// Global load for the rare path of blocks that did not fit the LDS stage. It is
-// kept out of line so the compiler cannot merge it with the LDS load of the
-// common path into one generic-address load.
+// Global load for the rare path of blocks that did not fit the LDS stage. A
+// buffer load cannot be folded with the LDS load of the common path into one
+// generic-address load (which the backend miscompiles). Offsets stay below 2 GiB.
 template <typename V>
-__device__ __attribute__((noinline)) V load_slow(const V* ptr) { return *ptr; }
+__device__ __forceinline__ V load_slow(const V* ptr) {
+  __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc((void*)ptr, (short)0, 0x7FFFFFFF, 0x00020000);
+  if constexpr (sizeof(V) == 4) return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b32(r, 0, 0, 0));
+  else if constexpr (sizeof(V) == 8) return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0));
+  else return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b128(r, 0, 0, 0));
+}
 
 __device__ __forceinline__ int32_t uniform(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 
@@ -154,6 +160,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_spmm_mfma(Params p) {
   using C = Cfg<XT, WT, YT, B, WAVES, RW, NS, CW, WCAP, GATHER>;
   extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
   if (p.status && *p.status) return;
+  if (p.ovf_only && !*p.ovf_only) return;
 
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
@@ -497,6 +504,7 @@ spmm_status_t launch_t(const RunArgs& a, hipStream_t stream) {
   p.ldy = a.ldy;
   p.n = a.n;
   p.status = a.status;
+  p.ovf_only = a.ovf_mode == 2 ? a.ovf : nullptr;
   constexpr int NTILE = 16 * NS;
   p.ntiles = (int32_t)ceil_div(a.n, NTILE);
   const int64_t units = (int64_t)p.ntiles * a.plan.num_panels;
@@ -537,6 +545,12 @@ static spmm_status_t dispatch_types(const RunArgs& a, hipStream_t s) {
       if constexpr (F32) return launch_t<XT, WT, YT, 16, 4, 2, 4, 8, 16>(a, s);
       else return wide ? launch_t<XT, WT, YT, 16, 4, 2, 8, 8, 32>(a, s) : launch_t<XT, WT, YT, 16, 4, 2, 4, 8, 32>(a, s);
     }
+    // geometries of the pipelined kernel (64-row chunks): general path for oversized chunks
+    if constexpr (!F32) {
+      if (CW == 4 && GR == 32) return launch_t<XT, WT, YT, 16, 8, 4, 4, 4, 64>(a, s);
+      if (CW == 4 && GR == 16) return launch_t<XT, WT, YT, 16, 8, 2, 4, 4, 64>(a, s);
+      if (CW == 4 && GR == 8) return launch_t<XT, WT, YT, 16, 4, 2, 4, 4, 64>(a, s);
+    }
   } else if (b == 32) {
     if (GR == 16 && CW == 4) {
       if constexpr (F32) return launch_t<XT, WT, YT, 32, 8, 2, 4, 4, 8>(a, s);
@@ -545,6 +559,10 @@ static spmm_status_t dispatch_types(const RunArgs& a, hipStream_t s) {
     if (GR == 4 && CW == 4) {
       if constexpr (F32) return launch_t<XT, WT, YT, 32, 4, 1, 4, 4, 8>(a, s);
       else return wide ? launch_t<XT, WT, YT, 32, 4, 1, 8, 4, 16>(a, s) : launch_t<XT, WT, YT, 32, 4, 1, 4, 4, 16>(a, s);
+    }
+    if constexpr (!F32) {
+      if (CW == 2 && GR == 16) return launch_t<XT, WT, YT, 32, 8, 2, 4, 2, 16>(a, s);
+      if (CW == 2 && GR == 8) return launch_t<XT, WT, YT, 32, 4, 2, 4, 2, 16>(a, s);
     }
   }
   return fail(SPMM_ERR_UNSUPPORTED, "no MFMA kernel variant for this block size / geometry");

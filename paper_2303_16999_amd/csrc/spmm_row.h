@@ -1,0 +1,282 @@
+// Row-wise block-sparse x dense SpMM for 16-bit X (FP16/BF16), block sizes 16
+// and 32, weights in FP16/BF16 or FP8-E4M3 with per-block FP32 scales.
+//
+// Y = (M o W) * X (PopSparse, Section 3), FP32 accumulation.
+//
+// One wave owns one block row and a tile of 16*NS columns and walks the row's
+// nonzero blocks in block-CSR order. There is no LDS and no barrier: every
+// wave is independent, and the latency of its loads is hidden by the other
+// waves resident on the SIMD (the kernel keeps its registers small enough for
+// four waves per SIMD). For each block the wave loads
+//   * its A fragment, W[row][k-range] (8 or 16 bytes per lane, one contiguous
+//     512-byte read per wave for a b = 16 block), and
+//   * its B fragments: lane (g, j) reads 16 bytes of X along n from each of the
+//     k rows its lane group covers and transposes them in registers (v_perm),
+//     so column j of MFMA tile s is physical column 8*j + s of the tile and
+//     the lane ends up holding 8 consecutive output columns per row.
+// Consecutive b = 16 blocks of the row are fused into one 16x16x32 MFMA.
+// Buffer loads return zero out of range, which covers the k and n tails.
+// Workgroups are ordered so that the rows of one n-tile run on one XCD at the
+// same time: the X columns they share stay in that XCD's L2.
+#pragma once
+
+#include "common.h"
+
+namespace spmm {
+namespace row {
+
+typedef _Float16 half4_t __attribute__((ext_vector_type(4)));
+typedef _Float16 half8_t __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef short short4_t __attribute__((ext_vector_type(4)));
+typedef float float4_t __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+struct Fp8 {};  // weights stored as OCP E4M3FN codes
+
+struct Params {
+  const int32_t* row_ptr;  // [mb + 1]
+  const int32_t* col_idx;  // [nnz]
+  const void* W;           // values in block-CSR order
+  const float* scales;     // FP8 block scales in block-CSR order, else nullptr
+  const void* X;
+  void* Y;
+  int64_t ldx, ldy;
+  int32_t m, k, n, mb;
+  int32_t rows_per_wg;     // block rows per workgroup (one per wave)
+  int32_t num_units;
+  uint32_t x_bytes;        // k * ldx * 2
+  const int32_t* status;   // skip when *status != 0 (dynamic), else nullptr
+};
+
+constexpr uint32_t kOOB = 0x80000000u;
+
+__device__ __forceinline__ int32_t uniform(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+
+__device__ __forceinline__ int32_t xcd_unit(int32_t w, int32_t U) {
+  const int32_t q = U >> 3, r = U & 7;
+  const int32_t x = w & 7, local = w >> 3;
+  return x * q + min(x, r) + local;
+}
+
+template <typename XT> struct Mma;
+template <> struct Mma<_Float16> {
+  static __device__ __forceinline__ float4_t k32(u32x4 a, u32x4 b, float4_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(half8_t, a), __builtin_bit_cast(half8_t, b), c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ float4_t k16(u32x2 a, u32x2 b, float4_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x16f16(__builtin_bit_cast(half4_t, a), __builtin_bit_cast(half4_t, b), c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ uint32_t pack2(float lo, float hi) {
+    _Float16 a = (_Float16)lo, b = (_Float16)hi;
+    return (uint32_t)__builtin_bit_cast(uint16_t, a) | ((uint32_t)__builtin_bit_cast(uint16_t, b) << 16);
+  }
+};
+template <> struct Mma<__bf16> {
+  static __device__ __forceinline__ float4_t k32(u32x4 a, u32x4 b, float4_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_t, a), __builtin_bit_cast(bf16x8_t, b), c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ float4_t k16(u32x2 a, u32x2 b, float4_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(short4_t, a), __builtin_bit_cast(short4_t, b), c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ uint32_t pack2(float lo, float hi) {
+    __bf16 a = (__bf16)lo, b = (__bf16)hi;
+    return (uint32_t)__builtin_bit_cast(uint16_t, a) | ((uint32_t)__builtin_bit_cast(uint16_t, b) << 16);
+  }
+};
+
+template <typename XT>
+__device__ __forceinline__ u32x2 fp8x4(uint32_t codes) {
+  auto lo = __builtin_amdgcn_cvt_pk_f32_fp8((int)codes, false);
+  auto hi = __builtin_amdgcn_cvt_pk_f32_fp8((int)codes, true);
+  return u32x2{Mma<XT>::pack2(lo[0], lo[1]), Mma<XT>::pack2(hi[0], hi[1])};
+}
+
+template <typename YT> __device__ __forceinline__ YT to_out(float v);
+template <> __device__ __forceinline__ float to_out<float>(float v) { return v; }
+template <> __device__ __forceinline__ _Float16 to_out<_Float16>(float v) { return (_Float16)v; }
+template <> __device__ __forceinline__ __bf16 to_out<__bf16>(float v) { return (__bf16)v; }
+
+// Four X rows x 16 bytes (8 columns each) -> for each of the 8 columns, the
+// four k values as two dwords (k0,k1) (k2,k3). r[i] holds row i.
+__device__ __forceinline__ void transpose4(const u32x4 (&r)[4], u32x2 (&out)[8]) {
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const uint32_t sel = (q & 1) ? 0x07060302u : 0x05040100u;
+    out[q].x = __builtin_amdgcn_perm(r[1][q >> 1], r[0][q >> 1], sel);
+    out[q].y = __builtin_amdgcn_perm(r[3][q >> 1], r[2][q >> 1], sel);
+  }
+}
+
+template <typename XT, typename WT, typename YT, int B, int NS>
+struct RowKernel {
+  static constexpr bool kFp8 = __is_same(WT, Fp8);
+  static constexpr int NTILE = 8 * 16;             // columns per wave: lane j covers 8 of them
+  static constexpr int WE = kFp8 ? 1 : 2;
+  static constexpr int WB = B * B * WE;
+  static_assert(NS == 8, "one 16-byte X load per lane and k row covers eight column tiles");
+
+  // lane (g, j): X rows kr + 4g + i (i = 0..3) for columns n0 + 8j .. +8, transposed
+  static __device__ __forceinline__ void xfrag(__amdgpu_buffer_rsrc_t xr, const Params& p, int32_t kr, int g, int j,
+                                               int32_t n0, u32x2 (&out)[8]) {
+    u32x4 rows[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int64_t krow = (int64_t)kr + 4 * g + i;
+      const uint32_t off = krow < p.k ? (uint32_t)((krow * p.ldx + n0 + 8 * j) * 2) : kOOB;
+      rows[i] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(xr, off, 0, 0));
+    }
+    transpose4(rows, out);
+  }
+};
+
+template <typename XT, typename WT, typename YT, int B, int NS>
+__global__ __launch_bounds__(256) void k_spmm_row(Params p) {
+  using K = RowKernel<XT, WT, YT, B, NS>;
+  if (p.status && *p.status) return;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int g = lane >> 4, j = lane & 15;
+  const int32_t unit = xcd_unit(blockIdx.x, p.num_units);
+  const int32_t rgroups = (p.mb + p.rows_per_wg - 1) / p.rows_per_wg;
+  const int32_t rg = unit % rgroups;
+  const int32_t n0 = (unit / rgroups) * K::NTILE;
+  const int32_t r = rg * p.rows_per_wg + wave;
+  if (r >= p.mb) return;
+
+  __amdgpu_buffer_rsrc_t xr = __builtin_amdgcn_make_buffer_rsrc((void*)p.X, (short)0, (int)p.x_bytes, 0x00020000);
+  const uint8_t* __restrict__ Wb = (const uint8_t*)p.W;
+  constexpr int H = B / 16;
+  float4_t acc[H][NS];
+#pragma unroll
+  for (int h = 0; h < H; ++h)
+#pragma unroll
+    for (int s = 0; s < NS; ++s) acc[h][s] = float4_t{0.f, 0.f, 0.f, 0.f};
+
+  const int32_t q_lo = uniform(p.row_ptr[r]), q_hi = uniform(p.row_ptr[r + 1]);
+  if constexpr (!K::kFp8 && B == 16) {
+    // pairs of blocks: k slots 0-3 from the first block, 4-7 from the second
+    for (int32_t q = q_lo; q < q_hi; q += 2) {
+      const bool two = q + 1 < q_hi;
+      const int32_t c1 = uniform(p.col_idx[q]);
+      const int32_t c2 = two ? uniform(p.col_idx[q + 1]) : c1;
+      const u32x2 a1 = *(const u32x2*)(Wb + (int64_t)q * K::WB + (j * 16 + g * 4) * 2);
+      const u32x2 a2 = two ? *(const u32x2*)(Wb + (int64_t)(q + 1) * K::WB + (j * 16 + g * 4) * 2) : u32x2{0u, 0u};
+      const u32x4 a = {a1.x, a1.y, a2.x, a2.y};
+      u32x2 b1[8], b2[8];
+      K::xfrag(xr, p, c1 * 16, g, j, n0, b1);
+      if (two) {
+        K::xfrag(xr, p, c2 * 16, g, j, n0, b2);
+      } else {
+#pragma unroll
+        for (int s = 0; s < 8; ++s) b2[s] = u32x2{0u, 0u};
+      }
+#pragma unroll
+      for (int s = 0; s < NS; ++s) acc[0][s] = Mma<XT>::k32(a, u32x4{b1[s].x, b1[s].y, b2[s].x, b2[s].y}, acc[0][s]);
+    }
+  } else if constexpr (!K::kFp8) {  // B == 32: k slots 0-3 and 4-7 are rows 8g..8g+3 and 8g+4..8g+7
+    for (int32_t q = q_lo; q < q_hi; ++q) {
+      const int32_t c = uniform(p.col_idx[q]);
+      u32x2 b1[8], b2[8];
+      K::xfrag(xr, p, c * 32, 2 * g, j, n0, b1);       // rows c*32 + 8g + i
+      K::xfrag(xr, p, c * 32 + 4, 2 * g, j, n0, b2);   // rows c*32 + 8g + 4 + i
+#pragma unroll
+      for (int h = 0; h < H; ++h) {
+        const u32x4 a = *(const u32x4*)(Wb + (int64_t)q * K::WB + ((h * 16 + j) * 32 + g * 8) * 2);
+#pragma unroll
+        for (int s = 0; s < NS; ++s) acc[h][s] = Mma<XT>::k32(a, u32x4{b1[s].x, b1[s].y, b2[s].x, b2[s].y}, acc[h][s]);
+      }
+    }
+  } else {  // FP8 weights with a per-block scale
+    for (int32_t q = q_lo; q < q_hi; ++q) {
+      const int32_t c = uniform(p.col_idx[q]);
+      const float sc = p.scales[q];
+      if constexpr (B == 16) {
+        const u32x2 a = fp8x4<XT>(*(const uint32_t*)(Wb + (int64_t)q * K::WB + j * 16 + g * 4));
+        u32x2 bx[8];
+        K::xfrag(xr, p, c * 16, g, j, n0, bx);
+#pragma unroll
+        for (int s = 0; s < NS; ++s) acc[0][s] += sc * Mma<XT>::k16(a, bx[s], float4_t{0.f, 0.f, 0.f, 0.f});
+      } else {
+        u32x2 b1[8], b2[8];
+        K::xfrag(xr, p, c * 32, 2 * g, j, n0, b1);
+        K::xfrag(xr, p, c * 32 + 4, 2 * g, j, n0, b2);
+#pragma unroll
+        for (int h = 0; h < H; ++h) {
+          const u32x2 codes = *(const u32x2*)(Wb + (int64_t)q * K::WB + (h * 16 + j) * 32 + g * 8);
+          const u32x2 lo = fp8x4<XT>(codes.x), hi = fp8x4<XT>(codes.y);
+          const u32x4 a = {lo.x, lo.y, hi.x, hi.y};
+#pragma unroll
+          for (int s = 0; s < NS; ++s)
+            acc[h][s] += sc * Mma<XT>::k32(a, u32x4{b1[s].x, b1[s].y, b2[s].x, b2[s].y}, float4_t{0.f, 0.f, 0.f, 0.f});
+        }
+      }
+    }
+  }
+
+  // epilogue: lane (g, j) holds rows 4g + i and columns n0 + 8j .. 8j + 7
+  YT* __restrict__ Y = (YT*)p.Y;
+  const int32_t col0 = n0 + 8 * j;
+#pragma unroll
+  for (int h = 0; h < H; ++h) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int64_t row = (int64_t)r * B + h * 16 + 4 * g + i;
+      if (row >= p.m) continue;
+      YT* dst = Y + row * p.ldy + col0;
+      if (col0 + 8 <= p.n) {
+        if constexpr (sizeof(YT) == 4) {
+          const float v0 = acc[h][0][i], v1 = acc[h][1][i], v2 = acc[h][2][i], v3 = acc[h][3][i];
+          const float v4 = acc[h][4][i], v5 = acc[h][5][i], v6 = acc[h][6][i], v7 = acc[h][7][i];
+          ((float4_t*)dst)[0] = float4_t{v0, v1, v2, v3};
+          ((float4_t*)dst)[1] = float4_t{v4, v5, v6, v7};
+        } else {
+          u32x4 w;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const float lo = acc[h][2 * e][i], hi = acc[h][2 * e + 1][i];
+            w[e] = Mma<YT>::pack2(lo, hi);
+          }
+          *(u32x4*)dst = w;
+        }
+      } else {
+#pragma unroll
+        for (int s = 0; s < 8; ++s)
+          if (col0 + s < p.n) {
+            const float v = acc[h][s][i];
+            dst[s] = to_out<YT>(v);
+          }
+      }
+    }
+  }
+}
+
+template <typename XT, typename WT, typename YT, int B>
+spmm_status_t launch_row(const RunArgs& a, const int32_t* row_ptr, const int32_t* col_idx, hipStream_t stream) {
+  Params p;
+  p.row_ptr = row_ptr;
+  p.col_idx = col_idx;
+  p.W = a.W;
+  p.scales = a.scales;
+  p.X = a.X;
+  p.Y = a.Y;
+  p.ldx = a.ldx;
+  p.ldy = a.ldy;
+  p.m = a.plan.m;
+  p.k = a.plan.k;
+  p.n = a.n;
+  p.mb = a.plan.mb;
+  p.rows_per_wg = 4;
+  p.x_bytes = (uint32_t)((int64_t)a.plan.k * a.ldx * 2);
+  p.status = a.status;
+  const int64_t units = ceil_div(a.plan.mb, p.rows_per_wg) * ceil_div(a.n, 128);
+  if (units == 0) return SPMM_OK;
+  if (units > (int64_t)INT32_MAX) return fail(SPMM_ERR_UNSUPPORTED, "too many work units");
+  p.num_units = (int32_t)units;
+  hipLaunchKernelGGL((k_spmm_row<XT, WT, YT, B, 8>), dim3((unsigned)units), dim3(256), 0, stream, p);
+  SPMM_HIP(hipGetLastError());
+  return SPMM_OK;
+}
+
+}  // namespace row
+}  // namespace spmm

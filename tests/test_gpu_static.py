@@ -115,7 +115,7 @@ def test_panels_walk_several_groups(P):
 
 
 @pytest.mark.parametrize("b,mb,kb,d,gr,P", [(16, 64, 64, 1 / 16, 32, 2), (16, 33, 70, 0.4, 8, 5),
-                                            (32, 17, 9, 0.5, 4, 3), (32, 64, 40, 0.1, 16, 4),
+                                            (32, 17, 9, 0.5, 8, 3), (32, 64, 40, 0.1, 16, 4),
                                             (16, 512, 512, 1 / 16, 32, 16), (16, 1, 1, 1.0, 8, 1)])
 def test_gpu_plan_bit_exact_vs_oracle(b, mb, kb, d, gr, P):
     from paper_2303_16999_amd import synth
