@@ -31,8 +31,9 @@ sys.path.insert(0, ROOT)
 METRIC = "effective TFLOP/s (nonzero FLOPs) and speedup vs dense FP16 GEMM; serve p50/p99"
 HBM_PEAK_GBS = 8000.0
 MFMA_PEAK_TFLOPS = {"f16": 2500.0, "bf16": 2500.0, "fp8": 2500.0, "f32": 157.3}
-KERNEL_SOURCE = os.path.join(ROOT, "paper_2303_16999_amd", "csrc", "spmm_mfma.hip")
-TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "spmm_mfma_f16_b16_m8192_n4096_d16_traffic.md")
+# The dominant kernel of the default step and the committed counter summary of it.
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2303_16999_amd", "csrc", f) for f in ("spmm_row.h", "spmm_row.hip")]
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "spmm_row_f16_b16_m8192_n4096_d16_traffic.md")
 
 
 def parse():
@@ -45,6 +46,8 @@ def parse():
     ap.add_argument("--no-dense", action="store_true", help="skip the dense FP16 comparator")
     ap.add_argument("--out", default=None, help="also append JSON lines to this file")
     ap.add_argument("--calls", type=int, default=1000, help="dynamic mode: number of calls")
+    ap.add_argument("--sweep-b", default="1,4,8,16,32", help="sweep mode: block sizes")
+    ap.add_argument("--sweep-n", default="256,1024,4096", help="sweep mode: column counts")
     return ap.parse_args()
 
 
@@ -81,7 +84,11 @@ class StaticProblem:
         self.vals_raw = vals
         X = synth.normal((k, n), seed + 2)
         self.X_store = synth.to_storage(X, x)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
         self.plan = spmm.StaticPlan(m, k, b, self.mask, w, x, y, n_hint=n)
+        torch.cuda.synchronize()
+        self.plan_ms = (time.perf_counter() - t0) * 1e3
         t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).view(torch.bfloat16) if a.dtype == np.uint16 \
             else torch.from_numpy(np.ascontiguousarray(a))
         self.values_dev = t(self.vals_store).cuda()
@@ -119,6 +126,20 @@ def time_steps(step, steps, warmup):
     e1.record()
     torch.cuda.synchronize()
     return e0.elapsed_time(e1) / steps
+
+
+def launch_percentiles(step, reps):
+    """p10/p50/p90 in ms of single back-to-back launches, one event pair each."""
+    import torch
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+    ev[0].record()
+    for i in range(reps):
+        step()
+        ev[i + 1].record()
+    torch.cuda.synchronize()
+    t = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(reps)])
+    return {"p10": round(float(np.percentile(t, 10)), 5), "p50": round(float(np.percentile(t, 50)), 5),
+            "p90": round(float(np.percentile(t, 90)), 5)}
 
 
 def time_cold(step, reps, flush):
@@ -178,12 +199,19 @@ def cpu_baseline(prob, target_s=10.0):
                       "%.2f s" % (cols, prob.n, dt)}
 
 
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
+
+
 def traffic_from_profile():
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it
     was taken on the current kernel source; else None."""
     if not os.path.exists(TRAFFIC_SUMMARY):
         return None
-    src_hash = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()[:16]
+    src_hash = kernel_source_hash()
     fields = {}
     for line in open(TRAFFIC_SUMMARY):
         if ":" in line and line.strip().startswith("- "):
@@ -209,6 +237,7 @@ def mode_headline(args):
     flush = torch.empty(512 * 1024 * 1024 // 4, dtype=torch.float32, device="cuda")
     cold_ms = time_cold(prob.step, 10, flush)
     del flush
+    warm = launch_percentiles(prob.step, 50)
     rec = {
         "metric": METRIC, "value": round(tflops, 3), "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms, 5), "higher_is_better": True, "scaling": "weak",
@@ -221,6 +250,9 @@ def mode_headline(args):
         "mfma_frac": round(tflops / MFMA_PEAK_TFLOPS["f16"], 4),
         "cold_ms": round(cold_ms, 5),
         "cold_tflops": round(flops / (cold_ms * 1e-3) / 1e12, 3),
+        "warm_ms_percentiles": warm,
+        "plan_build_ms": round(prob.plan_ms, 3),
+        "kernel_source_sha256_16": kernel_source_hash(),
     }
     if not args.no_dense:
         dn = dense_fp16(8192, 8192, 4096, max(5, args.steps // 2), 3, flops)
@@ -234,17 +266,22 @@ def mode_headline(args):
 def mode_sweep(args):
     import torch
     dense_cache = {}
-    for n in (256, 1024, 4096):
-        for b in (16, 32):
+    flush = torch.empty(512 * 1024 * 1024 // 4, dtype=torch.float32, device="cuda")
+    for n in [int(v) for v in args.sweep_n.split(",")]:
+        for b in [int(v) for v in args.sweep_b.split(",")]:
             for dd in (128, 64, 32, 16, 8, 4):
                 prob = StaticProblem(8192, 8192, n, b, 1.0 / dd, "f16", seed=0)
                 ms = time_steps(prob.step, args.steps, args.warmup)
+                cold = time_cold(prob.step, 5, flush)
                 fl = prob.flops()
                 if n not in dense_cache:
                     dense_cache[n] = dense_fp16(8192, 8192, n, args.steps, args.warmup, 1.0)["ms"]
                 rec = {"mode": "sweep", "m": 8192, "k": 8192, "n": n, "b": b, "density": 1.0 / dd,
-                       "ms": round(ms, 5), "tflops": round(fl / (ms * 1e-3) / 1e12, 3),
+                       "nnz_blocks": prob.nnzb, "ms": round(ms, 5), "cold_ms": round(cold, 5),
+                       "tflops": round(fl / (ms * 1e-3) / 1e12, 3),
                        "hbm_frac": round(prob.alg_bytes() / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                       "hbm_frac_cold": round(prob.alg_bytes() / (cold * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                       "plan_build_ms": round(prob.plan_ms, 3),
                        "dense_ms": round(dense_cache[n], 5), "speedup_vs_dense": round(dense_cache[n] / ms, 3)}
                 emit(rec, args.out)
                 del prob

@@ -71,15 +71,20 @@ typedef enum {
 typedef enum { SPMM_F32 = 0, SPMM_F16 = 1, SPMM_BF16 = 2, SPMM_FP8_E4M3 = 3 } spmm_dtype_t;
 
 /* Plan options. Zero-initialise and set what you need.
- *   group_rows  block rows one workgroup keeps in registers (0 = choose);
- *   num_panels  contiguous ranges of row groups, balanced by cost, that one
- *               workgroup walks in turn (0 = one group per panel);
- *   n_hint      expected batch size n, used only to choose group_rows. */
+ *   group_rows  block rows per row group of the plan (0 = choose);
+ *   num_panels  contiguous ranges of row groups balanced by cost (0 = one
+ *               group per panel);
+ *   n_hint      expected batch size n, used only to choose group_rows;
+ *   variant     tile variant of the compute kernel (0 = choose: the
+ *               autotuner's result for this n if there is one, else a rule on
+ *               n). For b = 16/32 with 16-bit X: 2, 4 or 8 column tiles of 16
+ *               per wave; for b = 1/4/8 with 16-bit X: 4 or 8 columns per
+ *               lane. Other kernels have one variant and ignore it. */
 typedef struct {
   int32_t group_rows;
   int32_t num_panels;
   int32_t n_hint;
-  int32_t reserved;
+  int32_t variant;
 } spmm_plan_opts;
 
 typedef struct spmm_plan_s* spmm_plan_t;
@@ -136,6 +141,50 @@ spmm_status_t spmm_plan_export(spmm_plan_t plan, int32_t* row_ptr, int32_t* col_
 
 spmm_status_t spmm_plan_destroy(spmm_plan_t plan);
 
+/* ------------------------------------------------------------------ autotuner
+ * The paper's planner fixes the partition of (m, k, n) from the matrix sizes
+ * and the density ahead of time (Appendix A); the analogous choice here is the
+ * compute kernel's tile variant, and it is made by measurement.
+ * spmm_autotune_static runs every variant of the
+ * plan's kernel on the caller's X and Y (n columns; Y receives the result),
+ * times each with HIP events on `stream` (2 warm-up and 5 timed runs), and
+ * records the fastest for n's size class (the power of two at or above n) in
+ * the plan and in a process-wide table keyed by (b, dtypes, density class, n
+ * class). Plans created later with the same key and variant 0 use that table.
+ * Synchronises `stream`. *variant_out (may be NULL) receives the choice;
+ * times_ms_out (may be NULL) receives the mean time of variants 2, 4 and 8,
+ * in that order, -1 for a variant the kernel does not have.
+ * Errors: as spmm_run_static. */
+spmm_status_t spmm_autotune_static(spmm_plan_t plan, int64_t n, const void* X, int64_t ldx, void* Y,
+                                   int64_t ldy, void* stream, int32_t* variant_out, float* times_ms_out);
+
+/* ------------------------------------------------------------------ grouped launch
+ * Many static products with different plans, column counts, X and Y in one
+ * persistent kernel launch. This goes beyond the paper, whose benchmarks run
+ * one product at a time and let n grow to amortise overheads (Sections 4
+ * and 5); here
+ * the columns of many small products share one launch instead. The problem
+ * table is written into pinned host memory, copied to the device and read by
+ * the kernel, and the copy + kernel pair is a captured HIP graph that is
+ * replayed for every call, so a call costs one graph launch.
+ *
+ * spmm_group_create makes a handle for up to max_problems problems.
+ * spmm_group_run: problem i computes Y[i] = (M o W)_plans[i] * X[i] with
+ * n[i] columns (0 = skipped), leading dimensions ldx[i] and ldy[i], and
+ * applies max(0, .) before rounding when relu is non-NULL and relu[i] != 0.
+ * Every plan must have values set and share block size (16 or 32) and dtype
+ * triple, with 16-bit W and X (FP8 weights: UNSUPPORTED). Each problem uses
+ * its plan's tile variant for its n. The handle double-buffers its table: a
+ * call waits on the host until the call two before it has finished on the
+ * device. Calls on one handle must not overlap on different streams.
+ * Errors: INVALID_ARG (count > max_problems, NULL, alignment, ld < n, values
+ * not set, mixed block size or dtypes), UNSUPPORTED, HIP. */
+spmm_status_t spmm_group_create(int32_t max_problems, spmm_group_t* out);
+spmm_status_t spmm_group_run(spmm_group_t g, int32_t count, const spmm_plan_t* plans, const int64_t* n,
+                             const void* const* X, const int64_t* ldx, void* const* Y, const int64_t* ldy,
+                             const uint8_t* relu, void* stream);
+spmm_status_t spmm_group_destroy(spmm_group_t g);
+
 /* ----------------------------------------------------------------- dynamic mode
  * Dynamic sparsity, Section 3.3 and Appendix A.2: only the maximum number of
  * nonzero blocks is fixed at creation (the paper's d_max); all buffers are
@@ -174,6 +223,100 @@ spmm_status_t spmm_dynamic_info(spmm_dyn_t h, int32_t* group_rows, int32_t* num_
                                 int32_t* num_panels);
 
 spmm_status_t spmm_dynamic_destroy(spmm_dyn_t h);
+
+/* ------------------------------------------------------------------ serving
+ * A request loop for a chain of sparse layers whose weights stay resident on
+ * the device: y = f_L(... f_1(x)), f_l(v) = act_l((M o W)_l v), where act_l is
+ * ReLU when relu_after[l] != 0 and the identity otherwise. The paper's closing
+ * motivation is faster inference of large sparse models (Section 6); this loop
+ * is built on its static products.
+ *
+ * A request is n columns (tokens): x_host is [dims[0] x n] row-major, y_host
+ * [dims[L] x n] row-major, both host memory the caller keeps valid until the
+ * request is reported done. Activations live in a device pool of
+ * mem_budget_bytes; a request holds two ping-pong buffers of
+ * n8 * (largest even-side dim + largest odd-side dim) elements (n8 = n rounded
+ * up to a multiple of 8) from admission to completion.
+ *
+ * CONTINUOUS mode (continuous batching): requests are admitted in arrival
+ * order whenever the pool and max_active allow, also while others are in
+ * flight; every step advances each admitted request by one layer, all of them
+ * in one grouped launch (spmm_group_run, fused ReLU), so requests at different
+ * layers share the device. PLAIN mode is the one-call-per-request reference:
+ * one request at a time, in arrival order, one spmm_run_static plus one ReLU
+ * kernel per layer.
+ *
+ * A worker thread runs the steps unless opts.manual is set; then the caller
+ * drives them with spmm_serve_step. opts.simulate runs the scheduler without
+ * any device work (plans may be NULL; dims are required): admission, memory
+ * accounting and completion order are those of a real run, outputs are not
+ * written. */
+typedef enum { SPMM_SERVE_CONTINUOUS = 0, SPMM_SERVE_PLAIN = 1 } spmm_serve_mode_t;
+
+typedef struct {
+  int64_t mem_budget_bytes;  /* device activation pool */
+  int32_t max_active;        /* requests in flight at most (CONTINUOUS) */
+  int32_t mode;              /* spmm_serve_mode_t */
+  int32_t manual;            /* nonzero: no worker thread; call spmm_serve_step */
+  int32_t simulate;          /* nonzero: scheduler only, no device work */
+} spmm_serve_opts;
+
+typedef struct {
+  uint64_t id;
+  int64_t n;
+  double submit_s;  /* spmm_serve_clock() at submission */
+  double admit_s;   /* ... at admission (activation memory granted) */
+  double done_s;    /* ... when the output was in y_host */
+} spmm_serve_done_t;
+
+typedef struct {
+  int64_t steps;           /* grouped steps (CONTINUOUS) or requests run (PLAIN) */
+  int64_t requests_done;
+  int64_t tokens_done;
+  int64_t problems_run;    /* layer products executed */
+  int64_t peak_pool_bytes; /* most activation memory held at once */
+  int32_t peak_active;     /* most requests in flight at once */
+  int32_t pending;         /* submitted, not yet admitted */
+  int32_t active;          /* admitted, not yet done */
+  int32_t reserved;
+  double busy_s;           /* wall time spent inside steps */
+} spmm_serve_stats_t;
+
+/* layer_plans: [num_layers] plans with values set (NULL allowed only when
+ * simulating); dims: [num_layers + 1] feature sizes, dims[l] = k of layer l
+ * and dims[l + 1] = m of layer l (checked against the plans); relu_after:
+ * [num_layers] or NULL (no activation). The plans must chain (m of layer l =
+ * k of layer l + 1, y dtype of l = x dtype of l + 1) and, in CONTINUOUS mode,
+ * satisfy spmm_group_run's conditions. The plans must outlive the server.
+ * Errors: INVALID_ARG, UNSUPPORTED, OOM, HIP. */
+spmm_status_t spmm_serve_create(const spmm_plan_t* layer_plans, int32_t num_layers, const int64_t* dims,
+                                const uint8_t* relu_after, const spmm_serve_opts* opts, spmm_srv_t* out);
+
+/* Queues a request. Returns REJECTED when its activation buffers exceed the
+ * whole pool (it could never be admitted), INVALID_ARG for n < 1 or NULL
+ * buffers (outside simulation), HIP/... if the server has failed. */
+spmm_status_t spmm_serve_submit(spmm_srv_t srv, uint64_t id, int64_t n, const void* x_host, void* y_host);
+
+/* Moves up to max finished requests into out (completion order) and sets
+ * *num_done. Never blocks. */
+spmm_status_t spmm_serve_poll(spmm_srv_t srv, spmm_serve_done_t* out, int32_t max, int32_t* num_done);
+
+/* Manual mode: one step (admission + one layer for every admitted request in
+ * CONTINUOUS mode, one whole request in PLAIN mode), synchronous. *active_out
+ * (may be NULL) receives the requests still in flight or pending. */
+spmm_status_t spmm_serve_step(spmm_srv_t srv, int32_t* active_out);
+
+/* Blocks until every submitted request is done (worker mode), or runs steps
+ * until then (manual mode). Returns the server's failure status if any. */
+spmm_status_t spmm_serve_drain(spmm_srv_t srv);
+
+spmm_status_t spmm_serve_stats(spmm_srv_t srv, spmm_serve_stats_t* out);
+
+/* Stops the worker after its current step; requests not done are dropped. */
+spmm_status_t spmm_serve_destroy(spmm_srv_t srv);
+
+/* The server's clock: seconds on a monotonic host clock. */
+double spmm_serve_clock(void);
 
 #ifdef __cplusplus
 }

@@ -129,10 +129,24 @@ struct RunArgs {
   bool fallback;          // run the general kernel even where the pipelined one applies
   const int32_t* ovf;     // dynamic: device flag, nonzero when a chunk exceeds the pipelined stage
   int32_t ovf_mode;       // 0: ignore ovf; 1: skip when *ovf != 0; 2: run only when *ovf != 0
+  bool relu = false;      // block-CSR kernels: max(0, y) before the output cast
+  int32_t ns = 8;         // row-wise kernel: column tiles of 16 per wave (2, 4 or 8)
 };
 spmm_status_t launch_spmm(const RunArgs& a, hipStream_t stream);
 // Row-wise kernel (16-bit X, b = 16 or 32): W and scales in block-CSR order.
 spmm_status_t launch_spmm_row(const RunArgs& a, const int32_t* row_ptr, const int32_t* col_idx, hipStream_t stream);
+// Grouped persistent row-wise launch over a device table of problem
+// descriptors (header_dev = {count, total units}); 16-bit W and X, b = 16/32.
+spmm_status_t launch_spmm_row_grouped(spmm_dtype_t xt, spmm_dtype_t yt, int32_t b, const void* probs_dev,
+                                      const int32_t* header_dev, int32_t grid, hipStream_t stream);
+size_t row_problem_size();
+int32_t row_grouped_grid(spmm_dtype_t xt, spmm_dtype_t yt, int32_t b);
+void fill_row_problem(void* dst, const RunArgs& a, const int32_t* row_ptr, const int32_t* col_idx,
+                      int32_t unit_begin);
+// Small-block kernel (b = 1, 4, 8, every dtype triple): W and scales in block-CSR order.
+spmm_status_t launch_spmm_small(const RunArgs& a, const int32_t* row_ptr, const int32_t* col_idx, hipStream_t stream);
+// True when (b, x dtype) runs on a block-CSR kernel (row-wise MFMA or small-block).
+bool uses_csr(int32_t b, spmm_dtype_t x);
 
 
 int device_cu_count();

@@ -179,9 +179,12 @@ spmm_status_t build_dynamic_csr(const int32_t* nnz_dev, const int32_t* rows, con
     if (elem_bytes == 1)
       hipLaunchKernelGGL(k_dyn_gather<uint8_t>, dim3(vgrid), dim3(256), 0, s, nnz_dev, pb.csr_src, pb.col_idx, b, k,
                          (const uint8_t*)vals, (uint8_t*)vals_out, scales, scales_out, status);
-    else
+    else if (elem_bytes == 2)
       hipLaunchKernelGGL(k_dyn_gather<uint16_t>, dim3(vgrid), dim3(256), 0, s, nnz_dev, pb.csr_src, pb.col_idx, b, k,
                          (const uint16_t*)vals, (uint16_t*)vals_out, scales, scales_out, status);
+    else
+      hipLaunchKernelGGL(k_dyn_gather<uint32_t>, dim3(vgrid), dim3(256), 0, s, nnz_dev, pb.csr_src, pb.col_idx, b, k,
+                         (const uint32_t*)vals, (uint32_t*)vals_out, scales, scales_out, status);
   }
   hipLaunchKernelGGL(k_dyn_group_cost, dim3((unsigned)ceil_div(geo.num_groups, 256)), dim3(256), 0, s, pb.row_ptr,
                      geo.num_groups, geo.group_rows, mb, pb.cost_prefix, status);

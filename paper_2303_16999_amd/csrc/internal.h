@@ -1,0 +1,42 @@
+// Host-side handle layouts shared by the C-ABI implementation files
+// (runtime.cpp: plans and dynamic handles; group.cpp: grouped launches;
+// serve.cpp: the serving loop).
+#pragma once
+
+#include "common.h"
+
+struct spmm_plan_s {
+  int64_t m = 0, k = 0;
+  int32_t b = 0, mb = 0, kb = 0;
+  int64_t nnzb = 0;
+  spmm_dtype_t w = SPMM_F32, x = SPMM_F32, y = SPMM_F32;
+  spmm::Geometry geo{};
+  spmm::PlanBuffers pb;
+  void* values = nullptr;      // entry (cell) order, for the pipelined and general kernels
+  float* scales = nullptr;
+  void* values_csr = nullptr;  // block-CSR order, for the block-CSR kernels
+  float* scales_csr = nullptr;
+  bool has_values = false;
+  int device = 0;
+  int32_t max_chunk = 0;       // most blocks in one (group, chunk)
+  int32_t variant_opt = 0;     // fixed tile variant from the options, 0 = choose
+  int8_t tuned[32] = {};       // autotuned variant per n class, 0 = none
+};
+
+namespace spmm {
+
+// n class of the autotuner: the exponent of the power of two at or above n.
+int n_class(int64_t n);
+// Tile variant for a run of `p` with n columns: fixed option, else the plan's
+// tuned value, else the process-wide tuned table, else the rule on n.
+int32_t plan_variant(const spmm_plan_s* p, int64_t n);
+// Whether the plan runs on the row-wise MFMA kernel (b = 16/32, 16-bit X).
+bool plan_uses_row_kernel(const spmm_plan_s* p);
+// Enqueues Y = (M o W) X for a validated plan (no argument checks).
+spmm_status_t run_plan(const spmm_plan_s* p, int64_t n, const void* X, int64_t ldx, void* Y, int64_t ldy,
+                       int32_t variant, bool relu, hipStream_t stream);
+spmm_status_t check_dense(const void* p, int64_t ld, int64_t n, int elem, const char* name);
+spmm_status_t check_device(int device);
+int32_t default_ns(int64_t n);
+
+}  // namespace spmm

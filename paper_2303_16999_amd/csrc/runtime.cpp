@@ -3,13 +3,17 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
 #include <string>
+#include <tuple>
 #include <vector>
 
-#include "common.h"
+#include "internal.h"
 
 namespace spmm {
 
@@ -52,6 +56,7 @@ int device_cu_count() {
 static bool valid_block(int32_t b) { return b == 1 || b == 4 || b == 8 || b == 16 || b == 32; }
 
 bool uses_pipe(int32_t b, spmm_dtype_t x) { return b >= 16 && (x == SPMM_F16 || x == SPMM_BF16); }
+bool uses_csr(int32_t b, spmm_dtype_t x) { return b < 16 || uses_pipe(b, x); }
 
 Geometry choose_geometry(int64_t m, int64_t k, int32_t b, int64_t nnz_hint, int64_t n_hint,
                          const spmm_plan_opts* opts, int num_cus, spmm_dtype_t x) {
@@ -115,7 +120,6 @@ static bool geometry_supported(int32_t b, int32_t gr, spmm_dtype_t x, int32_t nu
 }
 
 spmm_status_t launch_spmm_mfma(const RunArgs& a, hipStream_t s);
-spmm_status_t launch_spmm_small(const RunArgs& a, hipStream_t s);
 spmm_status_t launch_pipe_f16(const RunArgs& a, hipStream_t s);
 spmm_status_t launch_pipe_bf16(const RunArgs& a, hipStream_t s);
 spmm_status_t launch_pipe_fp8f16(const RunArgs& a, hipStream_t s);
@@ -127,10 +131,8 @@ static int32_t pipe_wcap(int32_t b, spmm_dtype_t w, int32_t nwv) {
 }
 
 spmm_status_t launch_spmm(const RunArgs& a0, hipStream_t s) {
-  if (!uses_pipe(a0.plan.b, a0.xt) || a0.fallback) {
-    if (a0.plan.b >= 16) return launch_spmm_mfma(a0, s);
-    return launch_spmm_small(a0, s);
-  }
+  if (a0.plan.b < 16) return fail(SPMM_ERR_UNSUPPORTED, "block sizes below 16 run on the block-CSR kernel only");
+  if (!uses_pipe(a0.plan.b, a0.xt) || a0.fallback) return launch_spmm_mfma(a0, s);
   RunArgs a = a0;
   const int64_t units8 = ceil_div(a.n, 128) * (int64_t)a.plan.num_panels;
   a.pipe_ns = units8 >= device_cu_count() ? 8 : 4;
@@ -150,6 +152,10 @@ spmm_status_t launch_spmm(const RunArgs& a0, hipStream_t s) {
   f.ovf_mode = 2;
   return launch_spmm_mfma(f, s);
 }
+
+// Column tiles of 16 per wave for the row-wise kernel: the widest tile that
+// the n columns fill at least half of.
+int32_t default_ns(int64_t n) { return n > 64 ? 8 : (n > 32 ? 4 : 2); }
 
 // Kernel choice for 16-bit X: the row-wise kernel unless SPMM_KERNEL=pipe.
 static bool use_row_kernel() {
@@ -210,7 +216,7 @@ static KernelPlan kernel_plan(int64_t m, int64_t k, int32_t b, int32_t mb, int32
   return kp;
 }
 
-static spmm_status_t check_dense(const void* p, int64_t ld, int64_t n, int elem, const char* name) {
+spmm_status_t check_dense(const void* p, int64_t ld, int64_t n, int elem, const char* name) {
   if (!p) return fail(SPMM_ERR_INVALID_ARG, std::string(name) + " is NULL");
   if (ld < n) return fail(SPMM_ERR_INVALID_ARG, std::string("leading dimension of ") + name + " is smaller than n");
   if (((uintptr_t)p) % 16 != 0) return fail(SPMM_ERR_INVALID_ARG, std::string(name) + " is not 16-byte aligned");
@@ -219,32 +225,96 @@ static spmm_status_t check_dense(const void* p, int64_t ld, int64_t n, int elem,
   return SPMM_OK;
 }
 
-static spmm_status_t check_device(int device) {
+spmm_status_t check_device(int device) {
   int cur = -1;
   SPMM_HIP(hipGetDevice(&cur));
   if (cur != device) return fail(SPMM_ERR_INVALID_ARG, "handle was created on another device");
   return SPMM_OK;
 }
 
+
+// ------------------------------------------------------------------ tile variants
+int n_class(int64_t n) {
+  int c = 0;
+  while (c < 31 && ((int64_t)1 << c) < n) ++c;
+  return c;
+}
+
+bool plan_uses_row_kernel(const spmm_plan_s* p) {
+  return p->values_csr && p->b >= 16 && use_row_kernel();
+}
+
+// Process-wide autotuner table: (b, w, x, y, density class, n class) -> variant.
+using TuneKey = std::tuple<int, int, int, int, int, int>;
+static std::mutex g_tune_mu;
+static std::map<TuneKey, int32_t> g_tune;
+
+static TuneKey tune_key(const spmm_plan_s* p, int64_t n) {
+  const double cells = (double)p->mb * (double)p->kb;
+  const double d = cells > 0 ? (double)p->nnzb / cells : 0.0;
+  const int dclass = d > 0 ? (int)std::lround(-std::log2(d)) : 64;
+  return TuneKey(p->b, (int)p->w, (int)p->x, (int)p->y, dclass, n_class(n));
+}
+
+static void tune_table_put(const spmm_plan_s* p, int64_t n, int32_t v) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune[tune_key(p, n)] = v;
+}
+
+int32_t plan_variant(const spmm_plan_s* p, int64_t n) {
+  if (p->variant_opt) return p->variant_opt;
+  const int8_t t = p->tuned[n_class(n)];
+  if (t) return t;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(tune_key(p, n));
+    if (it != g_tune.end()) return it->second;
+  }
+  return 0;
+}
+
+spmm_status_t run_plan(const spmm_plan_s* p, int64_t n, const void* X, int64_t ldx, void* Y, int64_t ldy,
+                       int32_t variant, bool relu, hipStream_t stream) {
+  RunArgs a{};
+  a.plan = kernel_plan(p->m, p->k, p->b, p->mb, p->kb, p->geo, p->pb);
+  a.W = p->values;
+  a.scales = p->scales;
+  a.gather = false;
+  a.X = X;
+  a.Y = Y;
+  a.ldx = ldx;
+  a.ldy = ldy;
+  a.n = (int32_t)n;
+  a.wt = p->w;
+  a.xt = p->x;
+  a.yt = p->y;
+  a.status = nullptr;
+  a.nnz = p->nnzb;
+  a.pipe_ns = 8;
+  a.pipe_nwv = p->max_chunk <= pipe_wcap(p->b, p->w, 4) ? 4 : 8;
+  a.fallback = p->max_chunk > pipe_wcap(p->b, p->w, 8);
+  a.ovf = nullptr;
+  a.ovf_mode = 0;
+  a.relu = relu;
+  if (p->b < 16) {
+    a.W = p->values_csr;
+    a.scales = p->scales_csr;
+    a.ns = variant;  // 0: the kernel's rule on n
+    return launch_spmm_small(a, p->pb.row_ptr, p->pb.col_idx, stream);
+  }
+  if (plan_uses_row_kernel(p)) {
+    a.W = p->values_csr;
+    a.scales = p->scales_csr;
+    a.ns = variant ? variant : default_ns(n);
+    return launch_spmm_row(a, p->pb.row_ptr, p->pb.col_idx, stream);
+  }
+  if (relu) return fail(SPMM_ERR_UNSUPPORTED, "fused ReLU needs a block-CSR kernel");
+  return launch_spmm(a, stream);
+}
+
 }  // namespace spmm
 
 using namespace spmm;
-
-struct spmm_plan_s {
-  int64_t m = 0, k = 0;
-  int32_t b = 0, mb = 0, kb = 0;
-  int64_t nnzb = 0;
-  spmm_dtype_t w = SPMM_F32, x = SPMM_F32, y = SPMM_F32;
-  Geometry geo{};
-  PlanBuffers pb;
-  void* values = nullptr;      // entry (cell) order, for the pipelined and general kernels
-  float* scales = nullptr;
-  void* values_csr = nullptr;  // block-CSR order, for the row-wise kernel
-  float* scales_csr = nullptr;
-  bool has_values = false;
-  int device = 0;
-  int32_t max_chunk = 0;  // most blocks in one (group, chunk)
-};
 
 struct spmm_dyn_s {
   int64_t m = 0, k = 0;
@@ -283,11 +353,15 @@ spmm_status_t spmm_plan_static(int64_t m, int64_t k, int32_t b, const uint8_t* b
   if (nnzb > INT32_MAX / 2) return fail(SPMM_ERR_UNSUPPORTED, "too many nonzero blocks");
   if (opts && (opts->group_rows < 0 || opts->num_panels < 0))
     return fail(SPMM_ERR_INVALID_ARG, "negative plan option");
+  if (opts && opts->variant && opts->variant != 2 && opts->variant != 4 && opts->variant != 8)
+    return fail(SPMM_ERR_INVALID_ARG, "variant must be 0, 2, 4 or 8");
+  if (opts && opts->variant == 2 && b < 16) return fail(SPMM_ERR_INVALID_ARG, "variant 2 needs b = 16 or 32");
 
   spmm_plan_s* p = new (std::nothrow) spmm_plan_s;
   if (!p) return fail(SPMM_ERR_OOM, "host allocation failed");
   p->m = m; p->k = k; p->b = b; p->mb = (int32_t)mb; p->kb = (int32_t)kb; p->nnzb = nnzb;
   p->w = w; p->x = x; p->y = y;
+  p->variant_opt = opts ? opts->variant : 0;
   p->geo = choose_geometry(m, k, b, nnzb, opts ? opts->n_hint : 0, opts, device_cu_count(), x);
   if (!geometry_supported(b, p->geo.group_rows, x, p->geo.num_chunks)) {
     delete p;
@@ -306,7 +380,7 @@ spmm_status_t spmm_plan_static(int64_t m, int64_t k, int32_t b, const uint8_t* b
     if (e != hipSuccess) st = fail_hip(e, "hipMalloc values");
   }
   if (st == SPMM_OK && w == SPMM_FP8_E4M3) st = dev_alloc(&p->scales, nnzb);
-  if (st == SPMM_OK && uses_pipe(b, x)) {
+  if (st == SPMM_OK && uses_csr(b, x)) {
     const int64_t vbytes = nnzb * (int64_t)b * b * dtype_bytes(w);
     e = hipMalloc(&p->values_csr, (size_t)std::max<int64_t>(vbytes, 16));
     if (e != hipSuccess) st = fail_hip(e, "hipMalloc values");
@@ -369,32 +443,79 @@ spmm_status_t spmm_run_static(spmm_plan_t p, int64_t n, const void* X, int64_t l
   if ((st = check_dense(X, ldx, n, dtype_bytes(p->x), "X")) != SPMM_OK) return st;
   if ((st = check_dense(Y, ldy, n, dtype_bytes(p->y), "Y")) != SPMM_OK) return st;
   if ((st = check_device(p->device)) != SPMM_OK) return st;
-  RunArgs a;
-  a.plan = kernel_plan(p->m, p->k, p->b, p->mb, p->kb, p->geo, p->pb);
-  a.W = p->values;
-  a.scales = p->scales;
-  a.gather = false;
-  a.X = X;
-  a.Y = Y;
-  a.ldx = ldx;
-  a.ldy = ldy;
-  a.n = (int32_t)n;
-  a.wt = p->w;
-  a.xt = p->x;
-  a.yt = p->y;
-  a.status = nullptr;
-  a.nnz = p->nnzb;
-  a.pipe_ns = 8;
-  a.pipe_nwv = p->max_chunk <= pipe_wcap(p->b, p->w, 4) ? 4 : 8;
-  a.fallback = p->max_chunk > pipe_wcap(p->b, p->w, 8);
-  a.ovf = nullptr;
-  a.ovf_mode = 0;
-  if (p->values_csr && use_row_kernel()) {
-    a.W = p->values_csr;
-    a.scales = p->scales_csr;
-    return launch_spmm_row(a, p->pb.row_ptr, p->pb.col_idx, (hipStream_t)stream);
+  return run_plan(p, n, X, ldx, Y, ldy, plan_variant(p, n), false, (hipStream_t)stream);
+}
+
+// Candidate tile variants of the plan's kernel (0-terminated).
+static void plan_candidates(const spmm_plan_s* p, int32_t (&c)[4]) {
+  c[0] = c[1] = c[2] = c[3] = 0;
+  if (plan_uses_row_kernel(p)) {
+    c[0] = 2; c[1] = 4; c[2] = 8;
+  } else if (p->b < 16 && p->x != SPMM_F32) {
+    c[0] = 4; c[1] = 8;
   }
-  return launch_spmm(a, (hipStream_t)stream);
+}
+
+spmm_status_t spmm_autotune_static(spmm_plan_t p, int64_t n, const void* X, int64_t ldx, void* Y, int64_t ldy,
+                                   void* stream, int32_t* variant_out, float* times_ms_out) {
+  clear_error();
+  if (!p) return fail(SPMM_ERR_INVALID_ARG, "plan is NULL");
+  if (n <= 0) return fail(SPMM_ERR_INVALID_ARG, "n must be positive for tuning");
+  if (n > INT32_MAX / 2) return fail(SPMM_ERR_UNSUPPORTED, "n too large");
+  if (!p->has_values) return fail(SPMM_ERR_INVALID_ARG, "values were not set on this plan");
+  spmm_status_t st;
+  if ((st = check_dense(X, ldx, n, dtype_bytes(p->x), "X")) != SPMM_OK) return st;
+  if ((st = check_dense(Y, ldy, n, dtype_bytes(p->y), "Y")) != SPMM_OK) return st;
+  if ((st = check_device(p->device)) != SPMM_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  int32_t cand[4];
+  plan_candidates(p, cand);
+  float times[3] = {-1.f, -1.f, -1.f};
+  int32_t best = 0;
+  float best_ms = 0.f;
+  if (cand[0]) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    SPMM_HIP(hipEventCreate(&e0));
+    hipError_t he = hipEventCreate(&e1);
+    if (he != hipSuccess) {
+      (void)hipEventDestroy(e0);
+      return fail_hip(he, "hipEventCreate");
+    }
+    for (int c = 0; c < 4 && cand[c] && st == SPMM_OK; ++c) {
+      for (int i = 0; i < 2 && st == SPMM_OK; ++i) st = run_plan(p, n, X, ldx, Y, ldy, cand[c], false, s);
+      if (st != SPMM_OK) break;
+      he = hipEventRecord(e0, s);
+      for (int i = 0; i < 5 && st == SPMM_OK && he == hipSuccess; ++i) st = run_plan(p, n, X, ldx, Y, ldy, cand[c], false, s);
+      if (he == hipSuccess) he = hipEventRecord(e1, s);
+      if (he == hipSuccess) he = hipEventSynchronize(e1);
+      float ms = 0.f;
+      if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+      if (he != hipSuccess) st = fail_hip(he, "autotune timing");
+      if (st != SPMM_OK) break;
+      ms /= 5.f;
+      const int slot = cand[c] == 2 ? 0 : (cand[c] == 4 ? 1 : 2);
+      times[slot] = ms;
+      if (!best || ms < best_ms) {
+        best = cand[c];
+        best_ms = ms;
+      }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != SPMM_OK) return st;
+    // leave Y holding the result of the chosen variant
+    if ((st = run_plan(p, n, X, ldx, Y, ldy, best, false, s)) != SPMM_OK) return st;
+    SPMM_HIP(hipStreamSynchronize(s));
+    p->tuned[n_class(n)] = (int8_t)best;
+    tune_table_put(p, n, best);
+  } else {
+    if ((st = run_plan(p, n, X, ldx, Y, ldy, 0, false, s)) != SPMM_OK) return st;
+    SPMM_HIP(hipStreamSynchronize(s));
+  }
+  if (variant_out) *variant_out = best;
+  if (times_ms_out)
+    for (int i = 0; i < 3; ++i) times_ms_out[i] = times[i];
+  return SPMM_OK;
 }
 
 spmm_status_t spmm_plan_info(spmm_plan_t p, int64_t* nnzb, int32_t* group_rows, int32_t* num_groups,
@@ -512,9 +633,9 @@ spmm_status_t spmm_run_dynamic(spmm_dyn_t h, const int32_t* nnzb_dev, const int3
   if (((uintptr_t)values_dev) % 16 != 0) return fail(SPMM_ERR_INVALID_ARG, "values are not 16-byte aligned");
   if ((st = check_device(h->device)) != SPMM_OK) return st;
   hipStream_t s = (hipStream_t)stream;
-  if (uses_pipe(h->b, h->x)) {
-    // 16-bit X, b >= 16: re-bucket into block-CSR and run the row-wise kernel
-    // (the same kernel and order as a static plan of the same pattern)
+  if (uses_csr(h->b, h->x)) {
+    // re-bucket into block-CSR and run the block-CSR kernel (the same kernel
+    // and order as a static plan of the same pattern)
     st = build_dynamic_csr(nnzb_dev, rows, cols, (int32_t)h->max_nnzb, h->mb, h->kb, h->b, (int32_t)h->k, h->geo,
                            h->pb, values_dev, h->packed, dtype_bytes(h->w), scales_dev, h->packed_scales, h->status,
                            status_dev, s);
@@ -537,6 +658,8 @@ spmm_status_t spmm_run_dynamic(spmm_dyn_t h, const int32_t* nnzb_dev, const int3
     a.yt = h->y;
     a.status = h->status;
     a.nnz = h->max_nnzb;
+    a.ns = h->b < 16 ? 0 : default_ns(n);
+    if (h->b < 16) return launch_spmm_small(a, h->pb.row_ptr, h->pb.col_idx, s);
     return launch_spmm_row(a, h->pb.row_ptr, h->pb.col_idx, s);
   }
   st = build_dynamic_plan(nnzb_dev, rows, cols, (int32_t)h->max_nnzb, h->mb, h->kb, h->geo, h->pb, h->status,

@@ -1,0 +1,494 @@
+// Serving loop (C ABI): continuous batching of requests through a chain of
+// resident sparse layers, or the plain one-request-at-a-time reference path.
+//
+// The scheduler is host C++: a FIFO of submitted requests, an activation pool
+// with first-fit allocation, the set of admitted requests and a completion
+// list. A step admits from the FIFO head while memory and max_active allow,
+// then advances every admitted request by one layer in one grouped launch
+// (CONTINUOUS) or runs one whole request layer by layer (PLAIN).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <new>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "internal.h"
+
+using namespace spmm;
+
+namespace {
+
+double now_s() {
+  using clk = std::chrono::steady_clock;
+  return std::chrono::duration<double>(clk::now().time_since_epoch()).count();
+}
+
+// ReLU in place over rows x n of a row-major matrix (the plain path's separate pass).
+template <typename T>
+__global__ void k_relu(T* __restrict__ a, int64_t rows, int64_t n, int64_t ld) {
+  const int64_t total = rows * n;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = i / n, c = i - r * n;
+    T* p = a + r * ld + c;
+    const float v = (float)*p;
+    if (!(v > 0.f)) *p = T(0.f);
+  }
+}
+
+spmm_status_t launch_relu(spmm_dtype_t t, void* a, int64_t rows, int64_t n, int64_t ld, hipStream_t s) {
+  const int64_t total = rows * n;
+  const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(4096, ceil_div(total, 256)));
+  if (t == SPMM_F16) hipLaunchKernelGGL(k_relu<_Float16>, dim3(grid), dim3(256), 0, s, (_Float16*)a, rows, n, ld);
+  else if (t == SPMM_BF16) hipLaunchKernelGGL(k_relu<__bf16>, dim3(grid), dim3(256), 0, s, (__bf16*)a, rows, n, ld);
+  else hipLaunchKernelGGL(k_relu<float>, dim3(grid), dim3(256), 0, s, (float*)a, rows, n, ld);
+  SPMM_HIP(hipGetLastError());
+  return SPMM_OK;
+}
+
+// First-fit allocator over [0, size) in 256-byte units, with coalescing.
+class Pool {
+ public:
+  explicit Pool(int64_t size) : size_(size) {
+    if (size > 0) free_[0] = size;
+  }
+  // returns the offset, or -1 if no free range is large enough
+  int64_t alloc(int64_t bytes) {
+    bytes = round(bytes);
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second >= bytes) {
+        const int64_t off = it->first, len = it->second;
+        free_.erase(it);
+        if (len > bytes) free_[off + bytes] = len - bytes;
+        used_ += bytes;
+        return off;
+      }
+    }
+    return -1;
+  }
+  void release(int64_t off, int64_t bytes) {
+    bytes = round(bytes);
+    used_ -= bytes;
+    auto next = free_.lower_bound(off);
+    if (next != free_.end() && off + bytes == next->first) {
+      bytes += next->second;
+      next = free_.erase(next);
+    }
+    if (next != free_.begin()) {
+      auto prev = std::prev(next);
+      if (prev->first + prev->second == off) {
+        prev->second += bytes;
+        return;
+      }
+    }
+    free_[off] = bytes;
+  }
+  int64_t used() const { return used_; }
+  static int64_t round(int64_t b) { return (b + 255) / 256 * 256; }
+
+ private:
+  int64_t size_;
+  int64_t used_ = 0;
+  std::map<int64_t, int64_t> free_;
+};
+
+struct Request {
+  uint64_t id = 0;
+  int64_t n = 0, ld = 0;
+  const void* x_host = nullptr;
+  void* y_host = nullptr;
+  double submit_s = 0, admit_s = 0;
+  int layer = 0;
+  int64_t off = -1, bytes = 0;  // pool range: buffer 0 at off, buffer 1 after it
+};
+
+}  // namespace
+
+struct spmm_srv_s {
+  std::vector<const spmm_plan_s*> plans;
+  std::vector<int64_t> dims;
+  std::vector<uint8_t> relu;
+  int L = 0;
+  spmm_serve_opts opts{};
+  spmm_dtype_t act = SPMM_F16;  // activation dtype (x of layer 0, y of every layer)
+  int elem = 2;
+  int64_t side0 = 0, side1 = 0;  // rows of ping-pong buffers 0 and 1
+  int device = 0;
+
+  std::mutex mu;
+  std::condition_variable cv;       // wakes the worker (submit, stop)
+  std::condition_variable done_cv;  // wakes drain
+  std::deque<Request> pending;
+  std::vector<Request> active;
+  std::deque<spmm_serve_done_t> done;
+  int64_t outstanding = 0;          // submitted and not yet done
+  spmm_status_t failed = SPMM_OK;
+  std::string fail_msg;
+  bool stop = false;
+  std::thread worker;
+
+  Pool* pool = nullptr;
+  uint8_t* pool_dev = nullptr;
+  hipStream_t stream = nullptr;
+  spmm_group_t group = nullptr;
+  spmm_serve_stats_t stats{};
+
+  // scratch for grouped runs
+  std::vector<spmm_plan_t> g_plans;
+  std::vector<int64_t> g_n, g_ldx, g_ldy;
+  std::vector<const void*> g_x;
+  std::vector<void*> g_y;
+  std::vector<uint8_t> g_relu;
+};
+
+static int64_t request_bytes(const spmm_srv_s* s, int64_t n) {
+  const int64_t ld = (n + 7) / 8 * 8;
+  return Pool::round(s->side0 * ld * s->elem) + Pool::round(s->side1 * ld * s->elem);
+}
+
+static void* buffer(spmm_srv_s* s, const Request& r, int which) {
+  if (s->opts.simulate) return nullptr;
+  uint8_t* base = s->pool_dev + r.off;
+  return which == 0 ? (void*)base : (void*)(base + Pool::round(s->side0 * r.ld * s->elem));
+}
+
+// Admission from the FIFO head (caller holds mu). Returns the admitted requests.
+static std::vector<Request> admit_locked(spmm_srv_s* s, int limit) {
+  std::vector<Request> out;
+  while (!s->pending.empty() && (int)(s->active.size() + out.size()) < limit) {
+    Request& r = s->pending.front();
+    const int64_t off = s->pool->alloc(r.bytes);
+    if (off < 0) break;  // head-of-line: later requests wait for the head
+    r.off = off;
+    r.admit_s = now_s();
+    out.push_back(r);
+    s->pending.pop_front();
+  }
+  return out;
+}
+
+static spmm_status_t upload_input(spmm_srv_s* s, const Request& r) {
+  if (s->opts.simulate) return SPMM_OK;
+  SPMM_HIP(hipMemcpy2DAsync(buffer(s, r, 0), (size_t)(r.ld * s->elem), r.x_host, (size_t)(r.n * s->elem),
+                            (size_t)(r.n * s->elem), (size_t)s->dims[0], hipMemcpyHostToDevice, s->stream));
+  return SPMM_OK;
+}
+
+static spmm_status_t download_output(spmm_srv_s* s, const Request& r) {
+  if (s->opts.simulate) return SPMM_OK;
+  SPMM_HIP(hipMemcpy2DAsync(r.y_host, (size_t)(r.n * s->elem), buffer(s, r, s->L % 2), (size_t)(r.ld * s->elem),
+                            (size_t)(r.n * s->elem), (size_t)s->dims[s->L], hipMemcpyDeviceToHost, s->stream));
+  return SPMM_OK;
+}
+
+static void finish_locked(spmm_srv_s* s, const Request& r, double t) {
+  s->pool->release(r.off, r.bytes);
+  spmm_serve_done_t d;
+  d.id = r.id;
+  d.n = r.n;
+  d.submit_s = r.submit_s;
+  d.admit_s = r.admit_s;
+  d.done_s = t;
+  s->done.push_back(d);
+  s->stats.requests_done += 1;
+  s->stats.tokens_done += r.n;
+  s->outstanding -= 1;
+}
+
+// One step; returns the number of requests still pending or active.
+static spmm_status_t do_step(spmm_srv_s* s, int32_t* remaining) {
+  const double t0 = now_s();
+  spmm_status_t st = SPMM_OK;
+  std::vector<Request> admitted;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->failed != SPMM_OK) return s->failed;
+    admitted = admit_locked(s, s->opts.mode == SPMM_SERVE_PLAIN ? 1 : s->opts.max_active);
+  }
+  for (const Request& r : admitted)
+    if (st == SPMM_OK) st = upload_input(s, r);
+  for (Request& r : admitted) s->active.push_back(r);  // only the stepping thread touches `active`
+  int64_t pool_used = 0;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    pool_used = s->pool->used();
+  }
+  if (pool_used > s->stats.peak_pool_bytes) s->stats.peak_pool_bytes = pool_used;
+  if ((int32_t)s->active.size() > s->stats.peak_active) s->stats.peak_active = (int32_t)s->active.size();
+
+  std::vector<Request> finished;
+  if (st == SPMM_OK && !s->active.empty()) {
+    if (s->opts.mode == SPMM_SERVE_PLAIN) {
+      // the one admitted request, every layer with its own launches
+      Request& r = s->active.front();
+      for (int l = 0; l < s->L && st == SPMM_OK; ++l) {
+        if (!s->opts.simulate) {
+          void* X = buffer(s, r, l % 2);
+          void* Y = buffer(s, r, (l + 1) % 2);
+          st = run_plan(s->plans[l], r.n, X, r.ld, Y, r.ld, plan_variant(s->plans[l], r.n), false, s->stream);
+          if (st == SPMM_OK && s->relu[l]) st = launch_relu(s->act, Y, s->dims[l + 1], r.n, r.ld, s->stream);
+        }
+        s->stats.problems_run += 1;
+      }
+      r.layer = s->L;
+    } else {
+      const size_t cnt = s->active.size();
+      s->g_plans.resize(cnt);
+      s->g_n.resize(cnt);
+      s->g_ldx.resize(cnt);
+      s->g_ldy.resize(cnt);
+      s->g_x.resize(cnt);
+      s->g_y.resize(cnt);
+      s->g_relu.resize(cnt);
+      for (size_t i = 0; i < cnt; ++i) {
+        const Request& r = s->active[i];
+        s->g_plans[i] = s->opts.simulate ? nullptr : const_cast<spmm_plan_s*>(s->plans[r.layer]);
+        s->g_n[i] = r.n;
+        s->g_ldx[i] = r.ld;
+        s->g_ldy[i] = r.ld;
+        s->g_x[i] = buffer(s, r, r.layer % 2);
+        s->g_y[i] = buffer(s, r, (r.layer + 1) % 2);
+        s->g_relu[i] = s->relu[r.layer];
+      }
+      if (!s->opts.simulate)
+        st = spmm_group_run(s->group, (int32_t)cnt, s->g_plans.data(), s->g_n.data(), s->g_x.data(), s->g_ldx.data(),
+                            s->g_y.data(), s->g_ldy.data(), s->g_relu.data(), s->stream);
+      s->stats.problems_run += (int64_t)cnt;
+      for (Request& r : s->active) r.layer += 1;
+    }
+    for (const Request& r : s->active)
+      if (r.layer == s->L && st == SPMM_OK) st = download_output(s, r);
+    if (st == SPMM_OK && !s->opts.simulate) {
+      hipError_t e = hipStreamSynchronize(s->stream);
+      if (e != hipSuccess) st = fail_hip(e, "serving step");
+    }
+    size_t w = 0;
+    for (size_t i = 0; i < s->active.size(); ++i) {
+      if (s->active[i].layer == s->L) finished.push_back(s->active[i]);
+      else s->active[w++] = s->active[i];
+    }
+    s->active.resize(w);
+    s->stats.steps += 1;
+  }
+  const double t1 = now_s();
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (st != SPMM_OK) {
+      s->failed = st;
+      s->fail_msg = spmm_last_error();
+    }
+    for (const Request& r : finished) finish_locked(s, r, t1);
+    s->stats.busy_s += t1 - t0;
+    if (remaining) *remaining = (int32_t)(s->pending.size() + s->active.size());
+  }
+  s->done_cv.notify_all();
+  return st;
+}
+
+static void worker_main(spmm_srv_s* s) {
+  (void)hipSetDevice(s->device);
+  for (;;) {
+    {
+      std::unique_lock<std::mutex> lk(s->mu);
+      s->cv.wait(lk, [&] { return s->stop || !s->pending.empty() || !s->active.empty(); });
+      if (s->stop) return;
+      if (s->failed != SPMM_OK) {
+        s->done_cv.notify_all();
+        s->cv.wait(lk, [&] { return s->stop; });
+        return;
+      }
+    }
+    int32_t rem = 0;
+    (void)do_step(s, &rem);
+  }
+}
+
+static void destroy_server(spmm_srv_s* s) {
+  if (s->worker.joinable()) {
+    {
+      std::lock_guard<std::mutex> lk(s->mu);
+      s->stop = true;
+    }
+    s->cv.notify_all();
+    s->worker.join();
+  }
+  if (s->stream) {
+    (void)hipStreamSynchronize(s->stream);
+    (void)hipStreamDestroy(s->stream);
+  }
+  if (s->group) (void)spmm_group_destroy(s->group);
+  if (s->pool_dev) (void)hipFree(s->pool_dev);
+  delete s->pool;
+  delete s;
+}
+
+extern "C" {
+
+double spmm_serve_clock(void) { return now_s(); }
+
+spmm_status_t spmm_serve_create(const spmm_plan_t* layer_plans, int32_t num_layers, const int64_t* dims,
+                                const uint8_t* relu_after, const spmm_serve_opts* opts, spmm_srv_t* out) {
+  clear_error();
+  if (!out) return fail(SPMM_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (!opts) return fail(SPMM_ERR_INVALID_ARG, "opts is NULL");
+  if (num_layers < 1 || num_layers > 4096) return fail(SPMM_ERR_INVALID_ARG, "num_layers must be in [1, 4096]");
+  if (!dims) return fail(SPMM_ERR_INVALID_ARG, "dims is NULL");
+  if (opts->mode != SPMM_SERVE_CONTINUOUS && opts->mode != SPMM_SERVE_PLAIN)
+    return fail(SPMM_ERR_INVALID_ARG, "unknown serving mode");
+  if (opts->mem_budget_bytes <= 0) return fail(SPMM_ERR_INVALID_ARG, "mem_budget_bytes must be positive");
+  if (opts->max_active < 1 || opts->max_active > 65536) return fail(SPMM_ERR_INVALID_ARG, "max_active must be in [1, 65536]");
+  for (int l = 0; l <= num_layers; ++l)
+    if (dims[l] < 1) return fail(SPMM_ERR_INVALID_ARG, "feature sizes must be positive");
+  if (!opts->simulate) {
+    if (!layer_plans) return fail(SPMM_ERR_INVALID_ARG, "layer_plans is NULL");
+    for (int l = 0; l < num_layers; ++l) {
+      const spmm_plan_s* p = layer_plans[l];
+      if (!p) return fail(SPMM_ERR_INVALID_ARG, "a layer plan is NULL");
+      if (!p->has_values) return fail(SPMM_ERR_INVALID_ARG, "values were not set on a layer plan");
+      if (p->k != dims[l] || p->m != dims[l + 1]) return fail(SPMM_ERR_INVALID_ARG, "plan shapes do not match dims");
+      if (l > 0 && layer_plans[l - 1]->y != p->x)
+        return fail(SPMM_ERR_INVALID_ARG, "output dtype of a layer differs from the next layer's input dtype");
+      if (p->y != layer_plans[0]->x) return fail(SPMM_ERR_INVALID_ARG, "all activations must share one dtype");
+    }
+  }
+  spmm_srv_s* s = new (std::nothrow) spmm_srv_s;
+  if (!s) return fail(SPMM_ERR_OOM, "host allocation failed");
+  s->L = num_layers;
+  s->opts = *opts;
+  s->dims.assign(dims, dims + num_layers + 1);
+  s->relu.assign(num_layers, 0);
+  if (relu_after)
+    for (int l = 0; l < num_layers; ++l) s->relu[l] = relu_after[l] ? 1 : 0;
+  if (!opts->simulate) {
+    s->plans.assign(layer_plans, layer_plans + num_layers);
+    s->act = s->plans[0]->x;
+    s->elem = dtype_bytes(s->act);
+  }
+  // buffer 0 holds the inputs of even layers and outputs of odd ones; buffer 1 the rest
+  for (int l = 0; l < num_layers; ++l) {
+    int64_t& in_side = (l % 2 == 0) ? s->side0 : s->side1;
+    int64_t& out_side = (l % 2 == 0) ? s->side1 : s->side0;
+    in_side = std::max(in_side, dims[l]);
+    out_side = std::max(out_side, dims[l + 1]);
+  }
+  s->pool = new (std::nothrow) Pool(opts->mem_budget_bytes);
+  spmm_status_t st = s->pool ? SPMM_OK : fail(SPMM_ERR_OOM, "host allocation failed");
+  if (st == SPMM_OK && !opts->simulate) {
+    hipError_t e = hipGetDevice(&s->device);
+    if (e != hipSuccess) st = fail_hip(e, "hipGetDevice");
+    if (st == SPMM_OK && (e = hipMalloc((void**)&s->pool_dev, (size_t)opts->mem_budget_bytes)) != hipSuccess)
+      st = fail_hip(e, "hipMalloc activation pool");
+    if (st == SPMM_OK && (e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking)) != hipSuccess)
+      st = fail_hip(e, "hipStreamCreate");
+    if (st == SPMM_OK && opts->mode == SPMM_SERVE_CONTINUOUS) {
+      for (int l = 0; l < num_layers && st == SPMM_OK; ++l)
+        if (!plan_uses_row_kernel(s->plans[l]) || s->plans[l]->w == SPMM_FP8_E4M3 ||
+            s->plans[l]->b != s->plans[0]->b || s->plans[l]->w != s->plans[0]->w || s->plans[l]->y != s->plans[0]->y)
+          st = fail(SPMM_ERR_UNSUPPORTED,
+                    "continuous batching needs layers of one block size (16 or 32) and one 16-bit dtype");
+      if (st == SPMM_OK) st = spmm_group_create(opts->max_active, &s->group);
+    }
+  }
+  if (st == SPMM_OK && !opts->manual) {
+    try {
+      s->worker = std::thread(worker_main, s);
+    } catch (...) {
+      st = fail(SPMM_ERR_OOM, "could not start the serving thread");
+    }
+  }
+  if (st != SPMM_OK) {
+    destroy_server(s);
+    return st;
+  }
+  *out = s;
+  return SPMM_OK;
+}
+
+spmm_status_t spmm_serve_submit(spmm_srv_t s, uint64_t id, int64_t n, const void* x_host, void* y_host) {
+  clear_error();
+  if (!s) return fail(SPMM_ERR_INVALID_ARG, "server is NULL");
+  if (n < 1 || n > (1 << 24)) return fail(SPMM_ERR_INVALID_ARG, "n must be in [1, 2^24]");
+  if (!s->opts.simulate && (!x_host || !y_host)) return fail(SPMM_ERR_INVALID_ARG, "x_host and y_host are required");
+  Request r;
+  r.id = id;
+  r.n = n;
+  r.ld = (n + 7) / 8 * 8;
+  r.x_host = x_host;
+  r.y_host = y_host;
+  r.bytes = request_bytes(s, n);
+  if (r.bytes > s->opts.mem_budget_bytes) return fail(SPMM_ERR_REJECTED, "request exceeds the activation memory budget");
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->failed != SPMM_OK) return fail(s->failed, s->fail_msg);
+    r.submit_s = now_s();
+    s->pending.push_back(r);
+    s->outstanding += 1;
+  }
+  s->cv.notify_one();
+  return SPMM_OK;
+}
+
+spmm_status_t spmm_serve_poll(spmm_srv_t s, spmm_serve_done_t* out, int32_t max, int32_t* num_done) {
+  clear_error();
+  if (!s || !num_done) return fail(SPMM_ERR_INVALID_ARG, "server or num_done is NULL");
+  if (max > 0 && !out) return fail(SPMM_ERR_INVALID_ARG, "out is NULL");
+  std::lock_guard<std::mutex> lk(s->mu);
+  int32_t k = 0;
+  while (k < max && !s->done.empty()) {
+    out[k++] = s->done.front();
+    s->done.pop_front();
+  }
+  *num_done = k;
+  return SPMM_OK;
+}
+
+spmm_status_t spmm_serve_step(spmm_srv_t s, int32_t* active_out) {
+  clear_error();
+  if (!s) return fail(SPMM_ERR_INVALID_ARG, "server is NULL");
+  if (!s->opts.manual) return fail(SPMM_ERR_INVALID_ARG, "spmm_serve_step is for manual servers");
+  return do_step(s, active_out);
+}
+
+spmm_status_t spmm_serve_drain(spmm_srv_t s) {
+  clear_error();
+  if (!s) return fail(SPMM_ERR_INVALID_ARG, "server is NULL");
+  if (s->opts.manual) {
+    int32_t rem = 1;
+    while (rem > 0) {
+      spmm_status_t st = do_step(s, &rem);
+      if (st != SPMM_OK) return st;
+    }
+    return SPMM_OK;
+  }
+  std::unique_lock<std::mutex> lk(s->mu);
+  s->done_cv.wait(lk, [&] { return s->outstanding == 0 || s->failed != SPMM_OK; });
+  if (s->failed != SPMM_OK) return fail(s->failed, s->fail_msg);
+  return SPMM_OK;
+}
+
+spmm_status_t spmm_serve_stats(spmm_srv_t s, spmm_serve_stats_t* out) {
+  clear_error();
+  if (!s || !out) return fail(SPMM_ERR_INVALID_ARG, "server or out is NULL");
+  std::lock_guard<std::mutex> lk(s->mu);
+  *out = s->stats;
+  out->pending = (int32_t)s->pending.size();
+  out->active = (int32_t)(s->outstanding - (int64_t)s->pending.size());
+  return SPMM_OK;
+}
+
+spmm_status_t spmm_serve_destroy(spmm_srv_t s) {
+  clear_error();
+  if (!s) return SPMM_OK;
+  destroy_server(s);
+  return SPMM_OK;
+}
+
+}  // extern "C"

@@ -30,12 +30,15 @@ typedef _Float16 half8_t __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef short short4_t __attribute__((ext_vector_type(4)));
 typedef float float4_t __attribute__((ext_vector_type(4)));
+typedef float float2_t __attribute__((ext_vector_type(2)));
 typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 struct Fp8 {};  // weights stored as OCP E4M3FN codes
 
-struct Params {
+// One SpMM as the row-wise kernel sees it (also an entry of the grouped
+// launch's descriptor table in device memory).
+struct RowProblem {
   const int32_t* row_ptr;  // [mb + 1]
   const int32_t* col_idx;  // [nnz]
   const void* W;           // values in block-CSR order
@@ -44,11 +47,19 @@ struct Params {
   void* Y;
   int64_t ldx, ldy;
   int32_t m, k, n, mb;
-  int32_t rows_per_wg;     // block rows per workgroup (one per wave)
+  uint32_t x_bytes;        // k * ldx * 2, < 2^31
+  int32_t relu;            // nonzero: max(0, y) before the output cast
+  int32_t ns;              // column tiles of 16 per wave: 2, 4 or 8
+  int32_t unit_begin;      // grouped launch: first work unit of this problem
+};
+
+struct Params {
+  RowProblem pr;
   int32_t num_units;
-  uint32_t x_bytes;        // k * ldx * 2
   const int32_t* status;   // skip when *status != 0 (dynamic), else nullptr
 };
+
+constexpr int kRowsPerWg = 4;  // one block row per wave
 
 constexpr uint32_t kOOB = 0x80000000u;
 
@@ -98,55 +109,52 @@ template <> __device__ __forceinline__ float to_out<float>(float v) { return v; 
 template <> __device__ __forceinline__ _Float16 to_out<_Float16>(float v) { return (_Float16)v; }
 template <> __device__ __forceinline__ __bf16 to_out<__bf16>(float v) { return (__bf16)v; }
 
-// Four X rows x 16 bytes (8 columns each) -> for each of the 8 columns, the
-// four k values as two dwords (k0,k1) (k2,k3). r[i] holds row i.
-__device__ __forceinline__ void transpose4(const u32x4 (&r)[4], u32x2 (&out)[8]) {
+// Four X rows x NS columns (NS/2 dwords each) -> for each of the NS columns,
+// the four k values as two dwords (k0,k1) (k2,k3). r[i] holds row i.
+template <int NS>
+__device__ __forceinline__ void transpose4(const uint32_t (&r)[4][NS / 2], u32x2 (&out)[NS]) {
 #pragma unroll
-  for (int q = 0; q < 8; ++q) {
+  for (int q = 0; q < NS; ++q) {
     const uint32_t sel = (q & 1) ? 0x07060302u : 0x05040100u;
     out[q].x = __builtin_amdgcn_perm(r[1][q >> 1], r[0][q >> 1], sel);
     out[q].y = __builtin_amdgcn_perm(r[3][q >> 1], r[2][q >> 1], sel);
   }
 }
 
-template <typename XT, typename WT, typename YT, int B, int NS>
-struct RowKernel {
-  static constexpr bool kFp8 = __is_same(WT, Fp8);
-  static constexpr int NTILE = 8 * 16;             // columns per wave: lane j covers 8 of them
-  static constexpr int WE = kFp8 ? 1 : 2;
-  static constexpr int WB = B * B * WE;
-  static_assert(NS == 8, "one 16-byte X load per lane and k row covers eight column tiles");
-
-  // lane (g, j): X rows kr + 4g + i (i = 0..3) for columns n0 + 8j .. +8, transposed
-  static __device__ __forceinline__ void xfrag(__amdgpu_buffer_rsrc_t xr, const Params& p, int32_t kr, int g, int j,
-                                               int32_t n0, u32x2 (&out)[8]) {
-    u32x4 rows[4];
+// lane (g, j): X rows kr + 4g + i (i = 0..3) for columns n0 + NS*j .. +NS, transposed
+template <int NS>
+__device__ __forceinline__ void xfrag(__amdgpu_buffer_rsrc_t xr, const RowProblem& p, int32_t kr, int g, int j,
+                                      int32_t n0, u32x2 (&out)[NS]) {
+  uint32_t rows[4][NS / 2];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int64_t krow = (int64_t)kr + 4 * g + i;
-      const uint32_t off = krow < p.k ? (uint32_t)((krow * p.ldx + n0 + 8 * j) * 2) : kOOB;
-      rows[i] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(xr, off, 0, 0));
+  for (int i = 0; i < 4; ++i) {
+    const int64_t krow = (int64_t)kr + 4 * g + i;
+    const uint32_t off = krow < p.k ? (uint32_t)((krow * p.ldx + n0 + NS * j) * 2) : kOOB;
+    if constexpr (NS == 8) {
+      const u32x4 v = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(xr, off, 0, 0));
+#pragma unroll
+      for (int e = 0; e < 4; ++e) rows[i][e] = v[e];
+    } else if constexpr (NS == 4) {
+      const u32x2 v = __builtin_bit_cast(u32x2, __builtin_amdgcn_raw_buffer_load_b64(xr, off, 0, 0));
+      rows[i][0] = v.x;
+      rows[i][1] = v.y;
+    } else {
+      rows[i][0] = __builtin_amdgcn_raw_buffer_load_b32(xr, off, 0, 0);
     }
-    transpose4(rows, out);
   }
-};
+  transpose4<NS>(rows, out);
+}
 
+// The work of one wave: block row r of problem p, columns n0 .. n0 + 16*NS.
 template <typename XT, typename WT, typename YT, int B, int NS>
-__global__ __launch_bounds__(256) void k_spmm_row(Params p) {
-  using K = RowKernel<XT, WT, YT, B, NS>;
-  if (p.status && *p.status) return;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+__device__ __forceinline__ void row_tile(const RowProblem& p, int32_t r, int32_t n0, int lane) {
+  static_assert(NS == 2 || NS == 4 || NS == 8, "column tiles per wave");
+  constexpr bool kFp8 = __is_same(WT, Fp8);
+  constexpr int WB = B * B * (kFp8 ? 1 : 2);  // bytes per block
+  constexpr int H = B / 16;
   const int g = lane >> 4, j = lane & 15;
-  const int32_t unit = xcd_unit(blockIdx.x, p.num_units);
-  const int32_t rgroups = (p.mb + p.rows_per_wg - 1) / p.rows_per_wg;
-  const int32_t rg = unit % rgroups;
-  const int32_t n0 = (unit / rgroups) * K::NTILE;
-  const int32_t r = rg * p.rows_per_wg + wave;
-  if (r >= p.mb) return;
-
   __amdgpu_buffer_rsrc_t xr = __builtin_amdgcn_make_buffer_rsrc((void*)p.X, (short)0, (int)p.x_bytes, 0x00020000);
   const uint8_t* __restrict__ Wb = (const uint8_t*)p.W;
-  constexpr int H = B / 16;
   float4_t acc[H][NS];
 #pragma unroll
   for (int h = 0; h < H; ++h)
@@ -154,35 +162,35 @@ __global__ __launch_bounds__(256) void k_spmm_row(Params p) {
     for (int s = 0; s < NS; ++s) acc[h][s] = float4_t{0.f, 0.f, 0.f, 0.f};
 
   const int32_t q_lo = uniform(p.row_ptr[r]), q_hi = uniform(p.row_ptr[r + 1]);
-  if constexpr (!K::kFp8 && B == 16) {
+  if constexpr (!kFp8 && B == 16) {
     // pairs of blocks: k slots 0-3 from the first block, 4-7 from the second
     for (int32_t q = q_lo; q < q_hi; q += 2) {
       const bool two = q + 1 < q_hi;
       const int32_t c1 = uniform(p.col_idx[q]);
       const int32_t c2 = two ? uniform(p.col_idx[q + 1]) : c1;
-      const u32x2 a1 = *(const u32x2*)(Wb + (int64_t)q * K::WB + (j * 16 + g * 4) * 2);
-      const u32x2 a2 = two ? *(const u32x2*)(Wb + (int64_t)(q + 1) * K::WB + (j * 16 + g * 4) * 2) : u32x2{0u, 0u};
+      const u32x2 a1 = *(const u32x2*)(Wb + (int64_t)q * WB + (j * 16 + g * 4) * 2);
+      const u32x2 a2 = two ? *(const u32x2*)(Wb + (int64_t)(q + 1) * WB + (j * 16 + g * 4) * 2) : u32x2{0u, 0u};
       const u32x4 a = {a1.x, a1.y, a2.x, a2.y};
-      u32x2 b1[8], b2[8];
-      K::xfrag(xr, p, c1 * 16, g, j, n0, b1);
+      u32x2 b1[NS], b2[NS];
+      xfrag<NS>(xr, p, c1 * 16, g, j, n0, b1);
       if (two) {
-        K::xfrag(xr, p, c2 * 16, g, j, n0, b2);
+        xfrag<NS>(xr, p, c2 * 16, g, j, n0, b2);
       } else {
 #pragma unroll
-        for (int s = 0; s < 8; ++s) b2[s] = u32x2{0u, 0u};
+        for (int s = 0; s < NS; ++s) b2[s] = u32x2{0u, 0u};
       }
 #pragma unroll
       for (int s = 0; s < NS; ++s) acc[0][s] = Mma<XT>::k32(a, u32x4{b1[s].x, b1[s].y, b2[s].x, b2[s].y}, acc[0][s]);
     }
-  } else if constexpr (!K::kFp8) {  // B == 32: k slots 0-3 and 4-7 are rows 8g..8g+3 and 8g+4..8g+7
+  } else if constexpr (!kFp8) {  // B == 32: k slots 0-3 and 4-7 are rows 8g..8g+3 and 8g+4..8g+7
     for (int32_t q = q_lo; q < q_hi; ++q) {
       const int32_t c = uniform(p.col_idx[q]);
-      u32x2 b1[8], b2[8];
-      K::xfrag(xr, p, c * 32, 2 * g, j, n0, b1);       // rows c*32 + 8g + i
-      K::xfrag(xr, p, c * 32 + 4, 2 * g, j, n0, b2);   // rows c*32 + 8g + 4 + i
+      u32x2 b1[NS], b2[NS];
+      xfrag<NS>(xr, p, c * 32, 2 * g, j, n0, b1);      // rows c*32 + 8g + i
+      xfrag<NS>(xr, p, c * 32 + 4, 2 * g, j, n0, b2);  // rows c*32 + 8g + 4 + i
 #pragma unroll
       for (int h = 0; h < H; ++h) {
-        const u32x4 a = *(const u32x4*)(Wb + (int64_t)q * K::WB + ((h * 16 + j) * 32 + g * 8) * 2);
+        const u32x4 a = *(const u32x4*)(Wb + (int64_t)q * WB + ((h * 16 + j) * 32 + g * 8) * 2);
 #pragma unroll
         for (int s = 0; s < NS; ++s) acc[h][s] = Mma<XT>::k32(a, u32x4{b1[s].x, b1[s].y, b2[s].x, b2[s].y}, acc[h][s]);
       }
@@ -192,18 +200,18 @@ __global__ __launch_bounds__(256) void k_spmm_row(Params p) {
       const int32_t c = uniform(p.col_idx[q]);
       const float sc = p.scales[q];
       if constexpr (B == 16) {
-        const u32x2 a = fp8x4<XT>(*(const uint32_t*)(Wb + (int64_t)q * K::WB + j * 16 + g * 4));
-        u32x2 bx[8];
-        K::xfrag(xr, p, c * 16, g, j, n0, bx);
+        const u32x2 a = fp8x4<XT>(*(const uint32_t*)(Wb + (int64_t)q * WB + j * 16 + g * 4));
+        u32x2 bx[NS];
+        xfrag<NS>(xr, p, c * 16, g, j, n0, bx);
 #pragma unroll
         for (int s = 0; s < NS; ++s) acc[0][s] += sc * Mma<XT>::k16(a, bx[s], float4_t{0.f, 0.f, 0.f, 0.f});
       } else {
-        u32x2 b1[8], b2[8];
-        K::xfrag(xr, p, c * 32, 2 * g, j, n0, b1);
-        K::xfrag(xr, p, c * 32 + 4, 2 * g, j, n0, b2);
+        u32x2 b1[NS], b2[NS];
+        xfrag<NS>(xr, p, c * 32, 2 * g, j, n0, b1);
+        xfrag<NS>(xr, p, c * 32 + 4, 2 * g, j, n0, b2);
 #pragma unroll
         for (int h = 0; h < H; ++h) {
-          const u32x2 codes = *(const u32x2*)(Wb + (int64_t)q * K::WB + (h * 16 + j) * 32 + g * 8);
+          const u32x2 codes = *(const u32x2*)(Wb + (int64_t)q * WB + (h * 16 + j) * 32 + g * 8);
           const u32x2 lo = fp8x4<XT>(codes.x), hi = fp8x4<XT>(codes.y);
           const u32x4 a = {lo.x, lo.y, hi.x, hi.y};
 #pragma unroll
@@ -214,9 +222,17 @@ __global__ __launch_bounds__(256) void k_spmm_row(Params p) {
     }
   }
 
-  // epilogue: lane (g, j) holds rows 4g + i and columns n0 + 8j .. 8j + 7
+  // epilogue: lane (g, j) holds rows 4g + i and columns n0 + NS*j .. +NS
+  if (p.relu) {
+#pragma unroll
+    for (int h = 0; h < H; ++h)
+#pragma unroll
+      for (int s = 0; s < NS; ++s)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) acc[h][s][i] = acc[h][s][i] > 0.f ? acc[h][s][i] : 0.f;
+  }
   YT* __restrict__ Y = (YT*)p.Y;
-  const int32_t col0 = n0 + 8 * j;
+  const int32_t col0 = n0 + NS * j;
 #pragma unroll
   for (int h = 0; h < H; ++h) {
 #pragma unroll
@@ -224,24 +240,30 @@ __global__ __launch_bounds__(256) void k_spmm_row(Params p) {
       const int64_t row = (int64_t)r * B + h * 16 + 4 * g + i;
       if (row >= p.m) continue;
       YT* dst = Y + row * p.ldy + col0;
-      if (col0 + 8 <= p.n) {
-        if constexpr (sizeof(YT) == 4) {
-          const float v0 = acc[h][0][i], v1 = acc[h][1][i], v2 = acc[h][2][i], v3 = acc[h][3][i];
-          const float v4 = acc[h][4][i], v5 = acc[h][5][i], v6 = acc[h][6][i], v7 = acc[h][7][i];
-          ((float4_t*)dst)[0] = float4_t{v0, v1, v2, v3};
-          ((float4_t*)dst)[1] = float4_t{v4, v5, v6, v7};
-        } else {
-          u32x4 w;
+      if (col0 + NS <= p.n) {
+        if constexpr (sizeof(YT) == 4 && NS == 2) {
+          const float v0 = acc[h][0][i], v1 = acc[h][1][i];
+          *(float2_t*)dst = float2_t{v0, v1};
+        } else if constexpr (sizeof(YT) == 4) {
 #pragma unroll
-          for (int e = 0; e < 4; ++e) {
+          for (int s = 0; s < NS; s += 4) {
+            const float v0 = acc[h][s][i], v1 = acc[h][s + 1][i], v2 = acc[h][s + 2][i], v3 = acc[h][s + 3][i];
+            *(float4_t*)(dst + s) = float4_t{v0, v1, v2, v3};
+          }
+        } else {
+          uint32_t w[NS / 2];
+#pragma unroll
+          for (int e = 0; e < NS / 2; ++e) {
             const float lo = acc[h][2 * e][i], hi = acc[h][2 * e + 1][i];
             w[e] = Mma<YT>::pack2(lo, hi);
           }
-          *(u32x4*)dst = w;
+          if constexpr (NS == 8) *(u32x4*)dst = u32x4{w[0], w[1], w[2], w[3]};
+          else if constexpr (NS == 4) *(u32x2*)dst = u32x2{w[0], w[1]};
+          else *(uint32_t*)dst = w[0];
         }
       } else {
 #pragma unroll
-        for (int s = 0; s < 8; ++s)
+        for (int s = 0; s < NS; ++s)
           if (col0 + s < p.n) {
             const float v = acc[h][s][i];
             dst[s] = to_out<YT>(v);
@@ -251,9 +273,54 @@ __global__ __launch_bounds__(256) void k_spmm_row(Params p) {
   }
 }
 
+template <typename XT, typename WT, typename YT, int B, int NS>
+__global__ __launch_bounds__(256) void k_spmm_row(Params prm) {
+  if (prm.status && *prm.status) return;
+  const RowProblem& p = prm.pr;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int32_t unit = xcd_unit(blockIdx.x, prm.num_units);
+  const int32_t rgroups = (p.mb + kRowsPerWg - 1) / kRowsPerWg;
+  const int32_t rg = unit % rgroups;
+  const int32_t n0 = (unit / rgroups) * (16 * NS);
+  const int32_t r = rg * kRowsPerWg + wave;
+  if (r >= p.mb) return;
+  row_tile<XT, WT, YT, B, NS>(p, r, n0, lane);
+}
+
+// Grouped persistent launch: the descriptor table holds `count` problems
+// (header[0]) and `total` work units (header[1]), both read from device
+// memory so that one captured launch serves any table written before it.
+// Workgroup w takes logical units w, w + grid, ... in the XCD-aware order;
+// a unit is (problem, group of 4 block rows, column tile of 16*ns).
 template <typename XT, typename WT, typename YT, int B>
-spmm_status_t launch_row(const RunArgs& a, const int32_t* row_ptr, const int32_t* col_idx, hipStream_t stream) {
-  Params p;
+__global__ __launch_bounds__(256) void k_spmm_row_grouped(const RowProblem* __restrict__ probs,
+                                                          const int32_t* __restrict__ header) {
+  const int32_t count = uniform(header[0]), total = uniform(header[1]);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int32_t u = blockIdx.x; u < total; u += gridDim.x) {
+    const int32_t unit = xcd_unit(u, total);
+    int32_t lo = 0, hi = count - 1;  // last problem with unit_begin <= unit
+    while (lo < hi) {
+      const int32_t mid = (lo + hi + 1) >> 1;
+      if (uniform(probs[mid].unit_begin) <= unit) lo = mid;
+      else hi = mid - 1;
+    }
+    const RowProblem& p = probs[lo];
+    const int32_t local = unit - uniform(p.unit_begin);
+    const int32_t rgroups = (uniform(p.mb) + kRowsPerWg - 1) / kRowsPerWg;
+    const int32_t ns = uniform(p.ns);
+    const int32_t rg = local % rgroups;
+    const int32_t r = rg * kRowsPerWg + wave;
+    if (r >= p.mb) continue;
+    const int32_t n0 = (local / rgroups) * (16 * ns);
+    if (ns == 8) row_tile<XT, WT, YT, B, 8>(p, r, n0, lane);
+    else if (ns == 4) row_tile<XT, WT, YT, B, 4>(p, r, n0, lane);
+    else row_tile<XT, WT, YT, B, 2>(p, r, n0, lane);
+  }
+}
+
+inline RowProblem row_problem(const RunArgs& a, const int32_t* row_ptr, const int32_t* col_idx) {
+  RowProblem p{};
   p.row_ptr = row_ptr;
   p.col_idx = col_idx;
   p.W = a.W;
@@ -266,14 +333,38 @@ spmm_status_t launch_row(const RunArgs& a, const int32_t* row_ptr, const int32_t
   p.k = a.plan.k;
   p.n = a.n;
   p.mb = a.plan.mb;
-  p.rows_per_wg = 4;
   p.x_bytes = (uint32_t)((int64_t)a.plan.k * a.ldx * 2);
-  p.status = a.status;
-  const int64_t units = ceil_div(a.plan.mb, p.rows_per_wg) * ceil_div(a.n, 128);
+  p.relu = a.relu ? 1 : 0;
+  p.ns = a.ns;
+  p.unit_begin = 0;
+  return p;
+}
+
+template <typename XT, typename WT, typename YT, int B>
+spmm_status_t launch_row(const RunArgs& a, const int32_t* row_ptr, const int32_t* col_idx, hipStream_t stream) {
+  if ((int64_t)a.plan.k * a.ldx * 2 >= (int64_t)INT32_MAX)
+    return fail(SPMM_ERR_UNSUPPORTED, "X larger than 2 GiB is not supported");
+  Params prm;
+  prm.pr = row_problem(a, row_ptr, col_idx);
+  prm.status = a.status;
+  const int ns = prm.pr.ns;
+  const int64_t units = ceil_div(a.plan.mb, kRowsPerWg) * ceil_div(a.n, 16 * ns);
   if (units == 0) return SPMM_OK;
   if (units > (int64_t)INT32_MAX) return fail(SPMM_ERR_UNSUPPORTED, "too many work units");
-  p.num_units = (int32_t)units;
-  hipLaunchKernelGGL((k_spmm_row<XT, WT, YT, B, 8>), dim3((unsigned)units), dim3(256), 0, stream, p);
+  prm.num_units = (int32_t)units;
+  if (ns == 8) hipLaunchKernelGGL((k_spmm_row<XT, WT, YT, B, 8>), dim3((unsigned)units), dim3(256), 0, stream, prm);
+  else if (ns == 4) hipLaunchKernelGGL((k_spmm_row<XT, WT, YT, B, 4>), dim3((unsigned)units), dim3(256), 0, stream, prm);
+  else if (ns == 2) hipLaunchKernelGGL((k_spmm_row<XT, WT, YT, B, 2>), dim3((unsigned)units), dim3(256), 0, stream, prm);
+  else return fail(SPMM_ERR_INVALID_ARG, "column tile variant must be 2, 4 or 8");
+  SPMM_HIP(hipGetLastError());
+  return SPMM_OK;
+}
+
+template <typename XT, typename WT, typename YT, int B>
+spmm_status_t launch_row_grouped(const RowProblem* probs_dev, const int32_t* header_dev, int32_t grid,
+                                 hipStream_t stream) {
+  hipLaunchKernelGGL((k_spmm_row_grouped<XT, WT, YT, B>), dim3((unsigned)grid), dim3(256), 0, stream, probs_dev,
+                     header_dev);
   SPMM_HIP(hipGetLastError());
   return SPMM_OK;
 }

@@ -24,8 +24,27 @@ _pi32, _pi64 = ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64)
 
 class PlanOpts(ctypes.Structure):
     _fields_ = [("group_rows", ctypes.c_int32), ("num_panels", ctypes.c_int32),
-                ("n_hint", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("n_hint", ctypes.c_int32), ("variant", ctypes.c_int32)]
 
+
+class ServeOpts(ctypes.Structure):
+    _fields_ = [("mem_budget_bytes", ctypes.c_int64), ("max_active", ctypes.c_int32), ("mode", ctypes.c_int32),
+                ("manual", ctypes.c_int32), ("simulate", ctypes.c_int32)]
+
+
+class ServeDone(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_uint64), ("n", ctypes.c_int64), ("submit_s", ctypes.c_double),
+                ("admit_s", ctypes.c_double), ("done_s", ctypes.c_double)]
+
+
+class ServeStats(ctypes.Structure):
+    _fields_ = [("steps", ctypes.c_int64), ("requests_done", ctypes.c_int64), ("tokens_done", ctypes.c_int64),
+                ("problems_run", ctypes.c_int64), ("peak_pool_bytes", ctypes.c_int64),
+                ("peak_active", ctypes.c_int32), ("pending", ctypes.c_int32), ("active", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("busy_s", ctypes.c_double)]
+
+
+SERVE_CONTINUOUS, SERVE_PLAIN = 0, 1
 
 SIGNATURES = {
     "spmm_last_error": ([], ctypes.c_char_p),
@@ -42,6 +61,19 @@ SIGNATURES = {
     "spmm_dynamic_export": ([_vp, _vp, _vp, _vp, _vp, _pi64], _c_i32),
     "spmm_dynamic_info": ([_vp, _pi32, _pi32, _pi32], _c_i32),
     "spmm_dynamic_destroy": ([_vp], _c_i32),
+    "spmm_autotune_static": ([_vp, _c_i64, _vp, _c_i64, _vp, _c_i64, _vp, _pi32, ctypes.POINTER(ctypes.c_float)],
+                             _c_i32),
+    "spmm_group_create": ([_c_i32, ctypes.POINTER(_vp)], _c_i32),
+    "spmm_group_run": ([_vp, _c_i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp], _c_i32),
+    "spmm_group_destroy": ([_vp], _c_i32),
+    "spmm_serve_create": ([_vp, _c_i32, _vp, _vp, ctypes.POINTER(ServeOpts), ctypes.POINTER(_vp)], _c_i32),
+    "spmm_serve_submit": ([_vp, ctypes.c_uint64, _c_i64, _vp, _vp], _c_i32),
+    "spmm_serve_poll": ([_vp, ctypes.POINTER(ServeDone), _c_i32, _pi32], _c_i32),
+    "spmm_serve_step": ([_vp, _pi32], _c_i32),
+    "spmm_serve_drain": ([_vp], _c_i32),
+    "spmm_serve_stats": ([_vp, ctypes.POINTER(ServeStats)], _c_i32),
+    "spmm_serve_destroy": ([_vp], _c_i32),
+    "spmm_serve_clock": ([], ctypes.c_double),
 }
 
 _LIB = None
@@ -90,8 +122,8 @@ def _stream(stream):
     return stream.cuda_stream
 
 
-def _opts(group_rows=0, num_panels=0, n_hint=0):
-    return PlanOpts(int(group_rows), int(num_panels), int(n_hint), 0)
+def _opts(group_rows=0, num_panels=0, n_hint=0, variant=0):
+    return PlanOpts(int(group_rows), int(num_panels), int(n_hint), int(variant))
 
 
 def torch_dtype(code):
@@ -102,14 +134,15 @@ def torch_dtype(code):
 class StaticPlan:
     """spmm_plan_static / spmm_plan_set_values / spmm_run_static."""
 
-    def __init__(self, m, k, b, block_mask, w="f16", x=None, y=None, group_rows=0, num_panels=0, n_hint=0):
+    def __init__(self, m, k, b, block_mask, w="f16", x=None, y=None, group_rows=0, num_panels=0, n_hint=0,
+                 variant=0):
         x = x or ("f16" if w == "fp8" else w)
         y = y or x
         mask = np.ascontiguousarray(np.asarray(block_mask, dtype=np.uint8))
         self.m, self.k, self.b = int(m), int(k), int(b)
         self.w, self.x, self.y = DTYPE_CODES[w], DTYPE_CODES[x], DTYPE_CODES[y]
         h = _vp()
-        opts = _opts(group_rows, num_panels, n_hint)
+        opts = _opts(group_rows, num_panels, n_hint, variant)
         check(lib().spmm_plan_static(self.m, self.k, self.b, mask.ctypes.data_as(_vp), self.w, self.x, self.y,
                                      ctypes.byref(opts), ctypes.byref(h)))
         self._h = h
@@ -129,6 +162,17 @@ class StaticPlan:
         ldy = Y.stride(0) if ldy is None else ldy
         check(lib().spmm_run_static(self._h, int(n), _ptr(X), int(ldx), _ptr(Y), int(ldy), _stream(stream)))
         return Y
+
+    def autotune(self, X, Y, n=None, ldx=None, ldy=None, stream=None):
+        """spmm_autotune_static: returns (chosen variant, {variant: mean ms})."""
+        n = X.shape[1] if n is None else n
+        ldx = X.stride(0) if ldx is None else ldx
+        ldy = Y.stride(0) if ldy is None else ldy
+        v = ctypes.c_int32()
+        t = (ctypes.c_float * 3)()
+        check(lib().spmm_autotune_static(self._h, int(n), _ptr(X), int(ldx), _ptr(Y), int(ldy), _stream(stream),
+                                         ctypes.byref(v), t))
+        return v.value, {var: float(ms) for var, ms in zip((2, 4, 8), t) if ms >= 0}
 
     def export(self):
         inf = self.info()
@@ -203,3 +247,103 @@ class DynamicHandle:
             self.close()
         except Exception:
             pass
+
+
+class Group:
+    """spmm_group_create / spmm_group_run: many static products in one persistent launch."""
+
+    def __init__(self, max_problems):
+        h = _vp()
+        check(lib().spmm_group_create(int(max_problems), ctypes.byref(h)))
+        self._h = h
+        self.max_problems = int(max_problems)
+
+    def run(self, plans, Xs, Ys, ns=None, relu=None, stream=None):
+        cnt = len(plans)
+        P = (_vp * cnt)(*[p._h.value for p in plans])
+        N = (ctypes.c_int64 * cnt)(*[(X.shape[1] if ns is None else ns[i]) for i, X in enumerate(Xs)])
+        XP = (_vp * cnt)(*[_ptr(X) for X in Xs])
+        YP = (_vp * cnt)(*[_ptr(Y) for Y in Ys])
+        LX = (ctypes.c_int64 * cnt)(*[X.stride(0) for X in Xs])
+        LY = (ctypes.c_int64 * cnt)(*[Y.stride(0) for Y in Ys])
+        R = (ctypes.c_uint8 * cnt)(*[1 if (relu and relu[i]) else 0 for i in range(cnt)]) if relu is not None else None
+        check(lib().spmm_group_run(self._h, cnt, P, N, XP, LX, YP, LY, R, _stream(stream)))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().spmm_group_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """spmm_serve_*: a request loop over a chain of resident sparse layers.
+
+    plans: StaticPlan per layer (None entries allowed when simulate=True);
+    dims: feature sizes [num_layers + 1]; relu: per-layer flags."""
+
+    def __init__(self, plans, dims, relu=None, mem_budget_bytes=1 << 30, max_active=64, mode=SERVE_CONTINUOUS,
+                 manual=False, simulate=False):
+        L = len(dims) - 1
+        self._plans = plans  # keep the plans alive as long as the server
+        P = (_vp * L)(*[(p._h.value if p is not None else None) for p in plans]) if plans is not None else None
+        D = (ctypes.c_int64 * (L + 1))(*[int(d) for d in dims])
+        R = (ctypes.c_uint8 * L)(*[1 if (relu and relu[i]) else 0 for i in range(L)]) if relu is not None else None
+        opts = ServeOpts(int(mem_budget_bytes), int(max_active), int(mode), int(bool(manual)), int(bool(simulate)))
+        h = _vp()
+        check(lib().spmm_serve_create(P, L, D, R, ctypes.byref(opts), ctypes.byref(h)))
+        self._h = h
+        self._keep = {}  # request id -> host buffers kept alive until done
+
+    def submit(self, req_id, n, x_host=None, y_host=None):
+        """x_host / y_host: C-contiguous numpy arrays [dims[0], n] and [dims[-1], n] (or None when simulating)."""
+        xp = x_host.ctypes.data_as(_vp) if x_host is not None else None
+        yp = y_host.ctypes.data_as(_vp) if y_host is not None else None
+        st = lib().spmm_serve_submit(self._h, int(req_id), int(n), xp, yp)
+        check(st)
+        self._keep[int(req_id)] = (x_host, y_host)
+
+    def poll(self, max_items=4096):
+        buf = (ServeDone * max_items)()
+        k = ctypes.c_int32()
+        check(lib().spmm_serve_poll(self._h, buf, int(max_items), ctypes.byref(k)))
+        out = []
+        for i in range(k.value):
+            d = buf[i]
+            self._keep.pop(int(d.id), None)
+            out.append({"id": int(d.id), "n": int(d.n), "submit_s": d.submit_s, "admit_s": d.admit_s,
+                        "done_s": d.done_s})
+        return out
+
+    def step(self):
+        k = ctypes.c_int32()
+        check(lib().spmm_serve_step(self._h, ctypes.byref(k)))
+        return k.value
+
+    def drain(self):
+        check(lib().spmm_serve_drain(self._h))
+
+    def stats(self):
+        st = ServeStats()
+        check(lib().spmm_serve_stats(self._h, ctypes.byref(st)))
+        return {f: getattr(st, f) for f, _ in ServeStats._fields_ if f != "reserved"}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().spmm_serve_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def clock():
+    return lib().spmm_serve_clock()

@@ -76,3 +76,22 @@ def test_binding_raises_with_message():
     with pytest.raises(spmm.SpmmError) as ei:
         spmm.StaticPlan(64, 64, 3, np.ones((22, 22), np.uint8))
     assert ei.value.status == spmm.ERR_INVALID_ARG
+
+
+def test_plan_variant_option_checked_on_host():
+    for variant, b in [(3, 16), (16, 16), (-2, 16), (2, 8)]:
+        opts = spmm.PlanOpts(0, 0, 0, variant)
+        st, h = _plan(b=b, opts=ctypes.byref(opts))
+        assert st == spmm.ERR_INVALID_ARG and not h.value, (variant, b)
+        assert b"variant" in spmm.lib().spmm_last_error()
+
+
+def test_autotune_and_group_reject_bad_arguments():
+    L = spmm.lib()
+    v = ctypes.c_int32()
+    assert L.spmm_autotune_static(None, 64, None, 64, None, 64, None, ctypes.byref(v), None) == spmm.ERR_INVALID_ARG
+    h = ctypes.c_void_p()
+    assert L.spmm_group_create(0, ctypes.byref(h)) == spmm.ERR_INVALID_ARG and not h.value
+    assert L.spmm_group_create(4, None) == spmm.ERR_INVALID_ARG
+    assert L.spmm_group_run(None, 1, None, None, None, None, None, None, None, None) == spmm.ERR_INVALID_ARG
+    assert L.spmm_group_destroy(None) == spmm.OK

@@ -1,0 +1,130 @@
+"""GPU tests of the tile variants, the autotuner and the grouped persistent launch."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import spmm_ref as O
+from paper_2303_16999_amd import spmm
+from gpu_cases import Case, round_like, y_f64
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("b,w,y", [(16, "f16", "f16"), (32, "bf16", "f32"), (4, "f16", "f16"), (8, "bf16", "bf16"),
+                                   (1, "f16", "f32")])
+def test_variants_agree_bitwise_and_match_oracle(b, w, y):
+    # the variants change the column tiling only, never the order of the sums
+    c = Case(23 * b + 3, 17 * b + 1, 301, b, 0.3, w=w, y=y, seed=50 + b)
+    variants = (2, 4, 8) if b >= 16 else (4, 8)
+    outs = []
+    for v in variants:
+        plan = spmm.StaticPlan(c.m, c.k, b, c.mask, w, y=y, variant=v)
+        vals, X, _ = c.device_inputs()
+        plan.set_values(vals)
+        Y = c.new_Y()
+        plan.run(X, Y, n=c.n)
+        torch.cuda.synchronize()
+        outs.append(Y)
+        plan.close()
+    for Y in outs[1:]:
+        assert torch.equal(outs[0][:, : c.n], Y[:, : c.n])
+    assert O.rel_fro(y_f64(outs[0], c), c.oracle()) <= 5e-3
+
+
+@pytest.mark.parametrize("b", [16, 8])
+def test_autotune_picks_a_variant_and_keeps_results(b):
+    c = Case(64 * b, 48 * b, 96, b, 1 / 8, w="f16", seed=61)
+    plan, Y0 = c.run_static()
+    vals, X, _ = c.device_inputs()
+    Y1 = c.new_Y()
+    v, times = plan.autotune(X, Y1, n=c.n)
+    assert v in ((2, 4, 8) if b >= 16 else (4, 8))
+    assert set(times) == ({2, 4, 8} if b >= 16 else {4, 8}) and all(t > 0 for t in times.values())
+    assert torch.equal(Y0[:, : c.n], Y1[:, : c.n])
+    Y2 = c.new_Y()
+    plan.run(X, Y2, n=c.n)  # now on the tuned variant
+    torch.cuda.synchronize()
+    assert torch.equal(Y0[:, : c.n], Y2[:, : c.n])
+
+
+def _group_cases(b, w, y, ns, seed):
+    cases = []
+    for i, n in enumerate(ns):
+        m = (5 + 3 * i) * b + (i % 3)
+        k = (7 + 2 * i) * b + (i % 2)
+        cases.append(Case(m, k, max(n, 1), b, 0.15 + 0.05 * i, w=w, y=y, seed=seed + i))
+    return cases
+
+
+@pytest.mark.parametrize("b,w,y", [(16, "f16", "f16"), (32, "bf16", "f32"), (16, "bf16", "bf16")])
+def test_group_matches_single_launches_and_oracle(b, w, y):
+    ns = [1, 17, 64, 200, 513, 0, 33]
+    cases = _group_cases(b, w, y, ns, seed=70)
+    relu = [i % 2 for i in range(len(cases))]
+    plans, Xs, Ys, ref_single = [], [], [], []
+    for c in cases:
+        plan, Ys_single = c.run_static()
+        vals, X, _ = c.device_inputs()
+        plans.append(plan)
+        Xs.append(X)
+        Ys.append(c.new_Y())
+        ref_single.append(Ys_single)
+    g = spmm.Group(16)
+    g.run(plans, Xs, Ys, ns=ns, relu=relu)
+    torch.cuda.synchronize()
+    for i, c in enumerate(cases):
+        if ns[i] == 0:
+            assert torch.isnan(Ys[i]).all().item()  # skipped problem left untouched
+            continue
+        single = ref_single[i][:, : c.n]
+        if relu[i]:
+            single = torch.clamp(single, min=0)
+        assert torch.equal(Ys[i][:, : c.n], single), i
+        ref = c.oracle()
+        if relu[i]:
+            ref = np.maximum(ref, 0.0)
+        assert O.rel_fro(y_f64(Ys[i], c), ref) <= 5e-3, i
+
+
+def test_group_graph_replays_with_new_tables():
+    """Replay the captured graph many times with different n, X and Y; eager work
+    and synchronisations between the replays; every replay checked."""
+    b = 16
+    cases = _group_cases(b, "f16", "f16", [40, 300, 7, 129], seed=90)
+    plans = [c.run_static()[0] for c in cases]
+    singles = {}
+    g = spmm.Group(8)
+    rng = np.random.default_rng(0)
+    for rep in range(6):
+        sel = [int(i) for i in rng.permutation(len(cases))[: 2 + rep % 3]]
+        ns = [int(rng.integers(1, cases[i].n + 1)) for i in sel]
+        Xs = [cases[i].device_inputs()[1] for i in sel]
+        Ys = [cases[i].new_Y() for i in sel]
+        g.run([plans[i] for i in sel], Xs, Ys, ns=ns)
+        torch.cuda.synchronize()
+        junk = torch.randn(1000, device="cuda").sum()  # eager work between replays
+        torch.cuda.synchronize()
+        for j, i in enumerate(sel):
+            key = (i, ns[j])
+            if key not in singles:
+                Yr = cases[i].new_Y()
+                plans[i].run(Xs[j], Yr, n=ns[j])
+                torch.cuda.synchronize()
+                singles[key] = Yr[:, : ns[j]].clone()
+            assert torch.equal(Ys[j][:, : ns[j]], singles[key]), (rep, i)
+        del junk
+
+
+def test_group_rejects_mixed_plans():
+    a = Case(64, 64, 32, 16, 0.5, w="f16", seed=1)
+    bcase = Case(64, 64, 32, 32, 0.5, w="f16", seed=2)
+    pa, _ = a.run_static()
+    pb, _ = bcase.run_static()
+    g = spmm.Group(4)
+    Xa, Xb = a.device_inputs()[1], bcase.device_inputs()[1]
+    with pytest.raises(spmm.SpmmError) as e:
+        g.run([pa, pb], [Xa, Xb], [a.new_Y(), bcase.new_Y()])
+    assert e.value.status == spmm.ERR_INVALID_ARG
+    with pytest.raises(spmm.SpmmError) as e:
+        g.run([pa] * 5, [Xa] * 5, [a.new_Y() for _ in range(5)])
+    assert e.value.status == spmm.ERR_INVALID_ARG
