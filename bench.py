@@ -41,7 +41,12 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--mode", default="headline", choices=["headline", "sweep", "dynamic", "precision", "copy"])
+    ap.add_argument("--mode", default="headline",
+                    choices=["headline", "sweep", "dynamic", "precision", "copy", "serve", "group"])
+    ap.add_argument("--requests", type=int, default=2000, help="serve mode: measured requests per run")
+    ap.add_argument("--rho", default="0.5,0.8", help="serve mode: offered load as fractions of the saturated rate")
+    ap.add_argument("--max-tokens", default="4096,16384,0",
+                    help="serve mode: per-step token budgets of the continuous path (0 = none)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-dense", action="store_true", help="skip the dense FP16 comparator")
     ap.add_argument("--out", default=None, help="also append JSON lines to this file")
@@ -387,6 +392,175 @@ def mode_dynamic(args):
     emit(rec, args.out)
 
 
+def mlp_plans(layers=8, d_in=4096, d_hid=16384, b=16, d=1 / 16, seed=0):
+    """The serving model: `layers` x (W1 d_hid x d_in, ReLU, W2 d_in x d_hid), FP16
+    block-sparse weights resident on the device, scaled so activations stay O(1)."""
+    import torch
+    from paper_2303_16999_amd import spmm, synth
+    plans, dims, relu = [], [d_in], []
+    for l in range(2 * layers):
+        k, m = (d_in, d_hid) if l % 2 == 0 else (d_hid, d_in)
+        mask = synth.block_mask(m // b, k // b, d, seed + 2 * l)
+        nnz = int(mask.sum())
+        scale = (1.0 if l % 2 == 0 else math.sqrt(2.0)) / math.sqrt(k * d)
+        g = torch.Generator(device="cuda").manual_seed(seed + 2 * l + 1)
+        vals = (torch.randn((nnz, b, b), generator=g, device="cuda", dtype=torch.float32) * scale).half()
+        plan = spmm.StaticPlan(m, k, b, mask, "f16", n_hint=256)
+        plan.set_values(vals)
+        plans.append(plan)
+        dims.append(m)
+        relu.append(1 if l % 2 == 0 else 0)
+    torch.cuda.synchronize()
+    return plans, dims, relu
+
+
+def run_trace(srv, arrivals, ns, x_host, y_hosts, t_start=None):
+    """Open-loop driver: submit request i at arrivals[i] (seconds from start), poll
+    completions; returns the completion records in id order."""
+    from paper_2303_16999_amd import spmm
+    done = {}
+    t0 = spmm.clock() if t_start is None else t_start
+    nreq = len(ns)
+    i = 0
+    while len(done) < nreq:
+        now = spmm.clock() - t0
+        while i < nreq and arrivals[i] <= now:
+            n = int(ns[i])
+            srv.submit(i, n, _view(x_host, n), _view(y_hosts[i % len(y_hosts)], n))
+            i += 1
+        for d in srv.poll():
+            done[d["id"]] = d
+        if i < nreq:
+            wait = arrivals[i] - (spmm.clock() - t0)
+            if wait > 0:
+                time.sleep(min(wait, 0.0005))
+        else:
+            time.sleep(0.0002)
+    return [done[j] for j in range(nreq)], t0
+
+
+def _view(buf, n, rows=4096):
+    """[rows x n8] view (n8 = n rounded up to a multiple of 8: the device layout)
+    over the front of a flat pinned host buffer."""
+    n8 = -(-n // 8) * 8
+    return buf[: rows * n8].view(rows, n8)
+
+
+def mode_serve(args):
+    """Serving: 8-layer sparse MLP (4096 -> 16384 -> 4096 per layer, b = 16,
+    density 1/16, FP16 weights resident), Poisson arrivals, n ~ log-uniform
+    [1, 2048]; continuous batching through grouped launches against the plain
+    one-request-at-a-time path on the same trace."""
+    import torch
+    from paper_2303_16999_amd import spmm, synth
+    plans, dims, relu = mlp_plans()
+    flop_per_token = sum(2.0 * dims[l] * dims[l + 1] / 16 for l in range(len(dims) - 1))
+    # pinned host buffers in the device layout, so request copies are plain DMA
+    x_host = torch.empty(4096 * 2048, dtype=torch.float16, pin_memory=True)
+    x_host.copy_(torch.from_numpy(synth.to_storage(synth.normal((4096 * 2048,), 7), "f16")))
+    y_hosts = [torch.zeros(4096 * 2048, dtype=torch.float16, pin_memory=True) for _ in range(8)]
+    budget = 32768 * (4096 + 16384) * 2  # 32,768 tokens of activations in flight
+    warm = 200
+    nmeas = args.requests
+
+    def make_server(mode, max_tokens=0):
+        return spmm.Server(plans, dims, relu=relu, mem_budget_bytes=budget, max_active=256, mode=mode,
+                           max_tokens=max_tokens)
+
+    # accuracy: the two paths agree bit for bit on a sample of requests
+    sample_n = [1, 7, 64, 300, 2048]
+    outs = {}
+    for mode in (spmm.SERVE_CONTINUOUS, spmm.SERVE_PLAIN):
+        srv = make_server(mode)
+        ys = [torch.zeros((4096, -(-n // 8) * 8), dtype=torch.float16, pin_memory=True) for n in sample_n]
+        for i, n in enumerate(sample_n):
+            srv.submit(i, n, _view(x_host, n), ys[i])
+        srv.drain()
+        srv.poll()
+        srv.close()
+        outs[mode] = [y[:, :n].clone() for y, n in zip(ys, sample_n)]
+    same = all(torch.equal(a, b) for a, b in zip(outs[spmm.SERVE_CONTINUOUS], outs[spmm.SERVE_PLAIN]))
+    finite = all(torch.isfinite(y.float()).all().item() for y in outs[spmm.SERVE_CONTINUOUS])
+
+    # saturated rates: every request arrives at once
+    _, n_sat = synth.serving_trace(600, 1.0, seed=11)
+    token_caps = [int(v) for v in args.max_tokens.split(",")]
+    sat = {}
+    for mode, name, cap in [(spmm.SERVE_CONTINUOUS, "continuous", c) for c in token_caps] + [(spmm.SERVE_PLAIN, "plain", 0)]:
+        srv = make_server(mode, cap)
+        t0 = spmm.clock()
+        recs, _ = run_trace(srv, np.zeros(len(n_sat)), n_sat, x_host, y_hosts, t0)
+        t_sat = max(r["done_s"] for r in recs) - t0
+        st = srv.stats()
+        srv.close()
+        sat[(name, cap)] = len(n_sat) / t_sat
+        emit({"mode": "serve_saturation", "path": name, "max_tokens": cap, "requests": len(n_sat),
+              "tokens": int(n_sat.sum()), "seconds": round(t_sat, 4), "req_per_s": round(len(n_sat) / t_sat, 2),
+              "tokens_per_s": round(n_sat.sum() / t_sat, 1),
+              "effective_tflops": round(n_sat.sum() * flop_per_token / t_sat / 1e12, 3),
+              "steps": st["steps"], "problems_per_step": round(st["problems_run"] / max(1, st["steps"]), 2),
+              "paths_bitwise_equal": bool(same), "outputs_finite": bool(finite)}, args.out)
+    mu_max = max(v for (name, cap), v in sat.items() if name == "continuous")
+
+    for rho in [float(v) for v in args.rho.split(",")]:
+        arrivals, ns = synth.serving_trace(warm + nmeas, rho * mu_max, seed=12)
+        runs = [(spmm.SERVE_CONTINUOUS, "continuous", c) for c in token_caps] + [(spmm.SERVE_PLAIN, "plain", 0)]
+        for mode, name, cap in runs:
+            srv = make_server(mode, cap)
+            recs, t0 = run_trace(srv, arrivals, ns, x_host, y_hosts)
+            st = srv.stats()
+            srv.close()
+            meas = recs[warm:]
+            lat = np.array([r["done_s"] - r["submit_s"] for r in meas]) * 1e3
+            t_first = min(r["submit_s"] for r in meas)
+            t_last = max(r["done_s"] for r in meas)
+            toks = sum(r["n"] for r in meas)
+            emit({"mode": "serve", "path": name, "max_tokens": cap, "rho": rho,
+                  "rate_req_per_s": round(rho * mu_max, 2), "requests": len(meas), "tokens": int(toks),
+                  "tokens_per_s": round(toks / (t_last - t_first), 1),
+                  "req_per_s": round(len(meas) / (t_last - t_first), 2),
+                  "effective_tflops": round(toks * flop_per_token / (t_last - t_first) / 1e12, 3),
+                  "latency_ms_p50": round(float(np.percentile(lat, 50)), 3),
+                  "latency_ms_p99": round(float(np.percentile(lat, 99)), 3),
+                  "latency_ms_mean": round(float(lat.mean()), 3),
+                  "steps": st["steps"], "peak_active": st["peak_active"],
+                  "peak_pool_mib": round(st["peak_pool_bytes"] / 2**20, 1)}, args.out)
+    for p in plans:
+        p.close()
+    torch.cuda.synchronize()
+
+
+def mode_group(args):
+    """The 16 serving matrices with n_i ~ log-uniform [1, 2048]: one grouped
+    persistent launch (graph replay) against 16 separate launches."""
+    import torch
+    from paper_2303_16999_amd import spmm, synth
+    plans, dims, relu = mlp_plans()
+    g = synth.rng(21)
+    for trial in range(3):
+        ns = [int(v) for v in np.clip(np.floor(np.exp(g.uniform(0, math.log(2049), size=16))), 1, 2048)]
+        Xs = [torch.randn((dims[l], ns[l] + (-ns[l]) % 8), device="cuda").half() for l in range(16)]
+        Ys = [torch.empty((dims[l + 1], ns[l] + (-ns[l]) % 8), device="cuda", dtype=torch.float16) for l in range(16)]
+        grp = spmm.Group(16)
+
+        def grouped():
+            grp.run(plans, Xs, Ys, ns=ns, relu=relu)
+
+        def separate():
+            for l in range(16):
+                plans[l].run(Xs[l], Ys[l], n=ns[l])
+
+        ms_g = time_steps(grouped, args.steps * 5, args.warmup)
+        ms_s = time_steps(separate, args.steps * 5, args.warmup)
+        fl = sum(2.0 * dims[l] * dims[l + 1] / 16 * ns[l] for l in range(16))
+        emit({"mode": "group", "n": ns, "grouped_ms": round(ms_g, 5), "separate_ms": round(ms_s, 5),
+              "speedup": round(ms_s / ms_g, 3), "grouped_tflops": round(fl / (ms_g * 1e-3) / 1e12, 3),
+              "separate_tflops": round(fl / (ms_s * 1e-3) / 1e12, 3)}, args.out)
+        grp.close()
+    for p in plans:
+        p.close()
+
+
 def mode_copy(args):
     """Plain copy of a known size, for calibrating the HBM byte counters."""
     import torch
@@ -409,7 +583,7 @@ def main():
     from paper_2303_16999_amd import spmm
     spmm.lib()  # fails loudly if the HIP library is missing
     {"headline": mode_headline, "sweep": mode_sweep, "precision": mode_precision, "copy": mode_copy,
-     "dynamic": mode_dynamic}[args.mode](args)
+     "dynamic": mode_dynamic, "serve": mode_serve, "group": mode_group}[args.mode](args)
 
 
 if __name__ == "__main__":

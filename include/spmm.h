@@ -231,9 +231,12 @@ spmm_status_t spmm_dynamic_destroy(spmm_dyn_t h);
  * motivation is faster inference of large sparse models (Section 6); this loop
  * is built on its static products.
  *
- * A request is n columns (tokens): x_host is [dims[0] x n] row-major, y_host
- * [dims[L] x n] row-major, both host memory the caller keeps valid until the
- * request is reported done. Activations live in a device pool of
+ * A request is n columns (tokens): x_host is [dims[0] x n] and y_host
+ * [dims[L] x n], row-major with leading dimension ld_host >= n (elements),
+ * host memory the caller keeps valid until the request is reported done.
+ * Copies are asynchronous DMA when the buffers are pinned (hipHostMalloc) and
+ * ld_host is n rounded up to a multiple of 8 (the device layout); other
+ * layouts take a strided copy. Activations live in a device pool of
  * mem_budget_bytes; a request holds two ping-pong buffers of
  * n8 * (largest even-side dim + largest odd-side dim) elements (n8 = n rounded
  * up to a multiple of 8) from admission to completion.
@@ -247,7 +250,9 @@ spmm_status_t spmm_dynamic_destroy(spmm_dyn_t h);
  * kernel per layer.
  *
  * A worker thread runs the steps unless opts.manual is set; then the caller
- * drives them with spmm_serve_step. opts.simulate runs the scheduler without
+ * drives them with spmm_serve_step. The worker keeps up to two steps enqueued
+ * on the device ahead of the one that completes; a manual step completes
+ * before it returns. opts.simulate runs the scheduler without
  * any device work (plans may be NULL; dims are required): admission, memory
  * accounting and completion order are those of a real run, outputs are not
  * written. */
@@ -259,6 +264,8 @@ typedef struct {
   int32_t mode;              /* spmm_serve_mode_t */
   int32_t manual;            /* nonzero: no worker thread; call spmm_serve_step */
   int32_t simulate;          /* nonzero: scheduler only, no device work */
+  int64_t max_tokens;        /* CONTINUOUS: tokens of all admitted requests at most
+                                (0 = no limit; a lone request is always admitted) */
 } spmm_serve_opts;
 
 typedef struct {
@@ -293,9 +300,10 @@ spmm_status_t spmm_serve_create(const spmm_plan_t* layer_plans, int32_t num_laye
                                 const uint8_t* relu_after, const spmm_serve_opts* opts, spmm_srv_t* out);
 
 /* Queues a request. Returns REJECTED when its activation buffers exceed the
- * whole pool (it could never be admitted), INVALID_ARG for n < 1 or NULL
- * buffers (outside simulation), HIP/... if the server has failed. */
-spmm_status_t spmm_serve_submit(spmm_srv_t srv, uint64_t id, int64_t n, const void* x_host, void* y_host);
+ * whole pool (it could never be admitted), INVALID_ARG for n < 1, ld_host < n
+ * or NULL buffers (outside simulation), HIP/... if the server has failed. */
+spmm_status_t spmm_serve_submit(spmm_srv_t srv, uint64_t id, int64_t n, const void* x_host, void* y_host,
+                                int64_t ld_host);
 
 /* Moves up to max finished requests into out (completion order) and sets
  * *num_done. Never blocks. */

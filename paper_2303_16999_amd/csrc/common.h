@@ -90,6 +90,13 @@ spmm_status_t build_dynamic_csr(const int32_t* nnz_dev, const int32_t* rows, con
                                 int32_t mb, int32_t kb, int32_t b, int32_t k, const Geometry& geo, PlanBuffers& pb,
                                 const void* vals, void* vals_out, int elem_bytes, const float* scales,
                                 float* scales_out, int32_t* status, int32_t* status_out, hipStream_t stream);
+// The same encode in one workgroup with the entries in LDS (block-CSR, sources
+// and panels only; the values stay where the caller put them and the kernels
+// read them through csr_src). Applies when dynamic_small_fits().
+bool dynamic_small_fits(int32_t max_nnz, int32_t mb, int32_t kb, int32_t num_groups);
+spmm_status_t build_dynamic_csr_small(const int32_t* nnz_dev, const int32_t* rows, const int32_t* cols,
+                                      int32_t max_nnz, int32_t mb, int32_t kb, const Geometry& geo, PlanBuffers& pb,
+                                      int32_t* status, int32_t* status_out, int32_t* nnz_last, hipStream_t stream);
 // CSR (row_ptr, col_idx, csr_src) of a dynamic plan, derived from the cells.
 spmm_status_t dynamic_csr_from_cells(int32_t mb, const Geometry& geo, PlanBuffers& pb,
                                      const int32_t* status_internal, hipStream_t stream);
@@ -130,6 +137,7 @@ struct RunArgs {
   const int32_t* ovf;     // dynamic: device flag, nonzero when a chunk exceeds the pipelined stage
   int32_t ovf_mode;       // 0: ignore ovf; 1: skip when *ovf != 0; 2: run only when *ovf != 0
   bool relu = false;      // block-CSR kernels: max(0, y) before the output cast
+  const int32_t* w_index = nullptr;  // block-CSR kernels: values (and scales) of entry q at w_index[q], else q
   int32_t ns = 8;         // row-wise kernel: column tiles of 16 per wave (2, 4 or 8)
 };
 spmm_status_t launch_spmm(const RunArgs& a, hipStream_t stream);

@@ -150,7 +150,166 @@ __global__ void k_dyn_status_out(const int32_t* __restrict__ internal, int32_t* 
   if (threadIdx.x == 0) *out = *internal;
 }
 
+// ------------------------------------------------------------------ one-workgroup builder
+// The whole encode of one dynamic call in a single workgroup of 1024 threads,
+// with the entries staged in LDS: validate and count per row (LDS atomics),
+// exclusive scan, scatter into LDS, rank each row's entries by (column, input
+// index) and write them to block-CSR in place, group costs, their prefix and
+// the panel boundaries, then the status words. Used when the capacity fits in
+// LDS; the result is identical to the multi-kernel path's.
+constexpr int kSmallThreads = 1024;
+
+// Exclusive scan of v[0..n) into out[0..n] (out[n] = total) by 1024 threads,
+// each owning a contiguous chunk; part[] holds 1024 partial sums.
+template <typename T, typename S>
+__device__ void block_exscan_chunks(const S* v, int32_t n, T* out, T* part) {
+  const int tid = threadIdx.x;
+  const int32_t per = (n + kSmallThreads - 1) / kSmallThreads;
+  const int32_t lo = min(n, tid * per), hi = min(n, lo + per);
+  T sum = 0;
+  for (int32_t i = lo; i < hi; ++i) sum += (T)v[i];
+  part[tid] = sum;
+  __syncthreads();
+  for (int off = 1; off < kSmallThreads; off <<= 1) {
+    const T add = tid >= off ? part[tid - off] : (T)0;
+    __syncthreads();
+    part[tid] += add;
+    __syncthreads();
+  }
+  T run = part[tid] - sum;
+  for (int32_t i = lo; i < hi; ++i) {
+    const T x = (T)v[i];
+    out[i] = run;
+    run += x;
+  }
+  if (tid == kSmallThreads - 1) out[n] = part[kSmallThreads - 1];
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(1024) void k_dyn_small(const int32_t* __restrict__ nnz_dev, int32_t max_nnz,
+                                                    const int32_t* __restrict__ rows, const int32_t* __restrict__ cols,
+                                                    int32_t mb, int32_t kb, int32_t GR, int32_t G, int32_t P,
+                                                    int32_t* __restrict__ row_ptr, int32_t* __restrict__ col_idx,
+                                                    int32_t* __restrict__ src, int32_t* __restrict__ panel_ptr,
+                                                    int32_t* __restrict__ status, int32_t* __restrict__ status_out,
+                                                    int32_t* __restrict__ nnz_last) {
+  extern __shared__ int64_t lds64[];
+  int64_t* C = lds64;                          // [G + 1] group cost prefix
+  int64_t* part64 = C + (G + 1);               // [1024]
+  int32_t* cnt = (int32_t*)(part64 + kSmallThreads);  // [mb] counts, then fill positions
+  int32_t* rp = cnt + mb;                      // [mb + 1]
+  int32_t* part = rp + mb + 1;                 // [1024]
+  int32_t* flag = part + kSmallThreads;        // [0] error, [1] nnz
+  uint32_t* ekey = (uint32_t*)(flag + 2);      // [max_nnz] (column << 16) | input index
+  uint16_t* erow = (uint16_t*)(ekey + max_nnz); // [max_nnz] block row of each staged entry
+  const int tid = threadIdx.x;
+  if (tid == 0) {
+    const int32_t nnz = *nnz_dev;
+    flag[0] = (nnz < 0 || nnz > max_nnz) ? (int32_t)SPMM_ERR_CAPACITY : 0;
+    flag[1] = nnz;
+  }
+  for (int32_t r = tid; r < mb; r += kSmallThreads) cnt[r] = 0;
+  __syncthreads();
+  const int32_t nnz = flag[1];
+  if (flag[0] == 0) {
+    for (int32_t e = tid; e < nnz; e += kSmallThreads) {
+      const int32_t r = rows[e], c = cols[e];
+      if (r < 0 || r >= mb || c < 0 || c >= kb) atomicMax(&flag[0], (int32_t)SPMM_ERR_BAD_INDEX);
+      else atomicAdd(&cnt[r], 1);
+    }
+  }
+  __syncthreads();
+  const int32_t err = flag[0];
+  if (err) {
+    if (tid == 0) {
+      *status = err;
+      if (status_out) *status_out = err;
+    }
+    return;
+  }
+  block_exscan_chunks<int32_t, int32_t>(cnt, mb, rp, part);
+  for (int32_t r = tid; r < mb; r += kSmallThreads) cnt[r] = rp[r];
+  __syncthreads();
+  for (int32_t e = tid; e < nnz; e += kSmallThreads) {
+    const int32_t r = rows[e];
+    const int32_t pos = atomicAdd(&cnt[r], 1);
+    ekey[pos] = ((uint32_t)cols[e] << 16) | (uint32_t)e;
+    erow[pos] = (uint16_t)r;
+  }
+  __syncthreads();
+  // every staged entry is ranked within its row by (column, input index),
+  // which is the order of the packed keys; the rank is its final position
+  for (int32_t i = tid; i < nnz; i += kSmallThreads) {
+    const uint32_t key = ekey[i];
+    const int32_t r = erow[i];
+    const int32_t lo = rp[r], hi = rp[r + 1];
+    int32_t rank = 0;
+    int32_t t = lo;
+    for (; t + 4 <= hi; t += 4)
+      rank += (ekey[t] < key) + (ekey[t + 1] < key) + (ekey[t + 2] < key) + (ekey[t + 3] < key);
+    for (; t < hi; ++t) rank += ekey[t] < key;
+    col_idx[lo + rank] = (int32_t)(key >> 16);
+    src[lo + rank] = (int32_t)(key & 0xFFFFu);
+  }
+  for (int32_t i = tid; i <= mb; i += kSmallThreads) row_ptr[i] = rp[i];
+  // group costs (blocks + rows), their prefix, panel boundaries
+  for (int32_t g = tid; g < G; g += kSmallThreads) {
+    const int32_t glo = g * GR, ghi = min(mb, glo + GR);
+    cnt[g] = (rp[ghi] - rp[glo]) + (ghi - glo);  // G <= mb: cnt is free again
+  }
+  __syncthreads();
+  block_exscan_chunks<int64_t, int32_t>(cnt, G, C, part64);
+  for (int32_t p = tid; p <= P; p += kSmallThreads) {
+    int32_t v;
+    if (p == 0) v = 0;
+    else if (p == P) v = G;
+    else {
+      const int64_t target = ((int64_t)p * C[G]) / P;
+      int32_t lo = 0, hi = G;
+      while (lo < hi) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (C[mid] >= target) hi = mid;
+        else lo = mid + 1;
+      }
+      v = lo;
+    }
+    panel_ptr[p] = v;
+  }
+  if (tid == 0) {
+    *status = 0;
+    if (status_out) *status_out = 0;
+    *nnz_last = nnz;
+  }
+}
+
+size_t dyn_small_lds_bytes(int32_t max_nnz, int32_t mb, int32_t G) {
+  return sizeof(int64_t) * ((size_t)G + 1 + kSmallThreads) +
+         sizeof(int32_t) * ((size_t)mb + mb + 1 + kSmallThreads + 2 + (size_t)max_nnz) + sizeof(uint16_t) * (size_t)max_nnz;
+}
+
 }  // namespace
+
+constexpr size_t kDynSmallLdsMax = 64 * 1024;
+
+// The packed keys need block columns and input indices below 2^16, the staged
+// rows block rows below 2^16.
+bool dynamic_small_fits(int32_t max_nnz, int32_t mb, int32_t kb, int32_t G) {
+  return G <= mb && mb <= 65536 && kb <= 65536 && max_nnz <= 65536 &&
+         dyn_small_lds_bytes(max_nnz, mb, G) <= kDynSmallLdsMax;
+}
+
+spmm_status_t build_dynamic_csr_small(const int32_t* nnz_dev, const int32_t* rows, const int32_t* cols,
+                                      int32_t max_nnz, int32_t mb, int32_t kb, const Geometry& geo, PlanBuffers& pb,
+                                      int32_t* status, int32_t* status_out, int32_t* nnz_last, hipStream_t s) {
+  const size_t lds = dyn_small_lds_bytes(max_nnz, mb, geo.num_groups);
+  if (!dynamic_small_fits(max_nnz, mb, kb, geo.num_groups))
+    return fail(SPMM_ERR_UNSUPPORTED, "dynamic capacity too large for the one-workgroup builder");
+  hipLaunchKernelGGL(k_dyn_small, dim3(1), dim3(kSmallThreads), lds, s, nnz_dev, max_nnz, rows, cols, mb, kb,
+                     geo.group_rows, geo.num_groups, geo.num_panels, pb.row_ptr, pb.col_idx, pb.csr_src, pb.panel_ptr,
+                     status, status_out, nnz_last);
+  SPMM_HIP(hipGetLastError());
+  return SPMM_OK;
+}
 
 spmm_status_t build_panels_from_costs(int32_t G, int32_t P, int64_t* cost_prefix, int32_t* panel_ptr,
                                       const int32_t* status, hipStream_t s);

@@ -157,8 +157,10 @@ spmm_status_t spmm_group_run(spmm_group_t g, int32_t count, const spmm_plan_t* p
   for (int32_t i = 0; i < count; ++i) {
     if (n[i] == 0) continue;
     const spmm_plan_s* p = plans[i];
+    // the tuned variant if any, else the widest tile n fills at least half of
+    // (the group as a whole fills the chip, so no narrowing for occupancy)
     int32_t ns = plan_variant(p, n[i]);
-    if (ns != 2 && ns != 4 && ns != 8) ns = default_ns(n[i]);
+    if (ns != 2 && ns != 4 && ns != 8) ns = n[i] > 64 ? 8 : (n[i] > 32 ? 4 : 2);
     RunArgs a{};
     a.plan.m = (int32_t)p->m;
     a.plan.k = (int32_t)p->k;

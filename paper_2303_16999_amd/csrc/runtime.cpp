@@ -48,9 +48,13 @@ bool dtype_triple_supported(spmm_dtype_t w, spmm_dtype_t x, spmm_dtype_t y) {
 }
 
 int device_cu_count() {
+  static int cached[64] = {};
   int dev = 0, cus = 256;
-  if (hipGetDevice(&dev) == hipSuccess) hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  return cus > 0 ? cus : 256;
+  if (hipGetDevice(&dev) != hipSuccess) return cus;
+  if (dev >= 0 && dev < 64 && cached[dev] > 0) return cached[dev];
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) cus = 256;
+  if (dev >= 0 && dev < 64) cached[dev] = cus;
+  return cus;
 }
 
 static bool valid_block(int32_t b) { return b == 1 || b == 4 || b == 8 || b == 16 || b == 32; }
@@ -154,8 +158,21 @@ spmm_status_t launch_spmm(const RunArgs& a0, hipStream_t s) {
 }
 
 // Column tiles of 16 per wave for the row-wise kernel: the widest tile that
-// the n columns fill at least half of.
-int32_t default_ns(int64_t n) { return n > 64 ? 8 : (n > 32 ? 4 : 2); }
+// the n columns fill at least half of, narrowed while the launch would give
+// the chip fewer than two workgroups (eight waves) per CU.
+int32_t default_ns(int64_t n, int64_t mb) {
+  int32_t ns = n > 64 ? 8 : (n > 32 ? 4 : 2);
+  const int64_t target = 2 * (int64_t)device_cu_count();
+  while (ns > 2 && ceil_div(mb, 4) * ceil_div(n, 16 * ns) < target) ns /= 2;
+  return ns;
+}
+
+// Dynamic encode: the one-workgroup builder where it applies, unless
+// SPMM_DYN_BUILDER=multi asks for the multi-kernel one (for comparisons).
+static bool use_one_wg_builder() {
+  const char* e = getenv("SPMM_DYN_BUILDER");
+  return !(e && std::string(e) == "multi");
+}
 
 // Kernel choice for 16-bit X: the row-wise kernel unless SPMM_KERNEL=pipe.
 static bool use_row_kernel() {
@@ -305,7 +322,7 @@ spmm_status_t run_plan(const spmm_plan_s* p, int64_t n, const void* X, int64_t l
   if (plan_uses_row_kernel(p)) {
     a.W = p->values_csr;
     a.scales = p->scales_csr;
-    a.ns = variant ? variant : default_ns(n);
+    a.ns = variant ? variant : default_ns(n, p->mb);
     return launch_spmm_row(a, p->pb.row_ptr, p->pb.col_idx, stream);
   }
   if (relu) return fail(SPMM_ERR_UNSUPPORTED, "fused ReLU needs a block-CSR kernel");
@@ -635,19 +652,30 @@ spmm_status_t spmm_run_dynamic(spmm_dyn_t h, const int32_t* nnzb_dev, const int3
   hipStream_t s = (hipStream_t)stream;
   if (uses_csr(h->b, h->x)) {
     // re-bucket into block-CSR and run the block-CSR kernel (the same kernel
-    // and order as a static plan of the same pattern)
-    st = build_dynamic_csr(nnzb_dev, rows, cols, (int32_t)h->max_nnzb, h->mb, h->kb, h->b, (int32_t)h->k, h->geo,
-                           h->pb, values_dev, h->packed, dtype_bytes(h->w), scales_dev, h->packed_scales, h->status,
-                           status_dev, s);
-    if (st != SPMM_OK) return st;
-    SPMM_HIP(hipMemcpyAsync(h->nnz_last, nnzb_dev, sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    // and order as a static plan of the same pattern). Small capacities encode
+    // in one workgroup and leave the values in place (read through csr_src);
+    // edge blocks that cross k need the copying path, which zeroes their tail.
+    const bool one_wg = h->k % h->b == 0 && use_one_wg_builder() &&
+                        dynamic_small_fits((int32_t)h->max_nnzb, h->mb, h->kb, h->geo.num_groups);
+    if (one_wg) {
+      st = build_dynamic_csr_small(nnzb_dev, rows, cols, (int32_t)h->max_nnzb, h->mb, h->kb, h->geo, h->pb,
+                                   h->status, status_dev, h->nnz_last, s);
+      if (st != SPMM_OK) return st;
+    } else {
+      st = build_dynamic_csr(nnzb_dev, rows, cols, (int32_t)h->max_nnzb, h->mb, h->kb, h->b, (int32_t)h->k, h->geo,
+                             h->pb, values_dev, h->packed, dtype_bytes(h->w), scales_dev, h->packed_scales, h->status,
+                             status_dev, s);
+      if (st != SPMM_OK) return st;
+      SPMM_HIP(hipMemcpyAsync(h->nnz_last, nnzb_dev, sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    }
     h->ran = true;
     h->csr_path = true;
     if (n == 0) return SPMM_OK;
     RunArgs a{};
     a.plan = kernel_plan(h->m, h->k, h->b, h->mb, h->kb, h->geo, h->pb);
-    a.W = h->packed;
-    a.scales = h->packed_scales;
+    a.W = one_wg ? values_dev : h->packed;
+    a.scales = one_wg ? scales_dev : h->packed_scales;
+    a.w_index = one_wg ? h->pb.csr_src : nullptr;
     a.X = X;
     a.Y = Y;
     a.ldx = ldx;
@@ -658,7 +686,7 @@ spmm_status_t spmm_run_dynamic(spmm_dyn_t h, const int32_t* nnzb_dev, const int3
     a.yt = h->y;
     a.status = h->status;
     a.nnz = h->max_nnzb;
-    a.ns = h->b < 16 ? 0 : default_ns(n);
+    a.ns = h->b < 16 ? 0 : default_ns(n, h->mb);
     if (h->b < 16) return launch_spmm_small(a, h->pb.row_ptr, h->pb.col_idx, s);
     return launch_spmm_row(a, h->pb.row_ptr, h->pb.col_idx, s);
   }

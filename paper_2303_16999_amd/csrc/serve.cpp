@@ -104,6 +104,7 @@ struct Request {
   int64_t n = 0, ld = 0;
   const void* x_host = nullptr;
   void* y_host = nullptr;
+  int64_t ld_host = 0;
   double submit_s = 0, admit_s = 0;
   int layer = 0;
   int64_t off = -1, bytes = 0;  // pool range: buffer 0 at off, buffer 1 after it
@@ -140,6 +141,16 @@ struct spmm_srv_s {
   spmm_group_t group = nullptr;
   spmm_serve_stats_t stats{};
 
+  // steps enqueued on the device and not yet retired (worker mode): the event
+  // recorded after the step and the requests whose output it copies back
+  struct InFlight {
+    hipEvent_t ev = nullptr;
+    std::vector<Request> finished;
+  };
+  std::deque<InFlight> inflight;
+  std::vector<hipEvent_t> free_events;
+  int64_t active_tokens = 0;        // sum of n over `active`
+
   // scratch for grouped runs
   std::vector<spmm_plan_t> g_plans;
   std::vector<int64_t> g_n, g_ldx, g_ldy;
@@ -160,31 +171,49 @@ static void* buffer(spmm_srv_s* s, const Request& r, int which) {
 }
 
 // Admission from the FIFO head (caller holds mu). Returns the admitted requests.
+// A request waits while the slots, the pool or the per-step token budget
+// (tokens of all admitted requests; a lone request is always admitted) is
+// exhausted; later requests wait behind it.
 static std::vector<Request> admit_locked(spmm_srv_s* s, int limit) {
   std::vector<Request> out;
+  int64_t tokens = s->active_tokens;
   while (!s->pending.empty() && (int)(s->active.size() + out.size()) < limit) {
     Request& r = s->pending.front();
+    const bool alone = s->active.empty() && out.empty();
+    if (s->opts.max_tokens > 0 && !alone && tokens + r.n > s->opts.max_tokens) break;
     const int64_t off = s->pool->alloc(r.bytes);
     if (off < 0) break;  // head-of-line: later requests wait for the head
     r.off = off;
     r.admit_s = now_s();
+    tokens += r.n;
     out.push_back(r);
     s->pending.pop_front();
   }
   return out;
 }
 
+// Host <-> device copies of a request's input and output: one contiguous copy
+// when the host layout equals the device layout, else a strided one.
 static spmm_status_t upload_input(spmm_srv_s* s, const Request& r) {
   if (s->opts.simulate) return SPMM_OK;
-  SPMM_HIP(hipMemcpy2DAsync(buffer(s, r, 0), (size_t)(r.ld * s->elem), r.x_host, (size_t)(r.n * s->elem),
-                            (size_t)(r.n * s->elem), (size_t)s->dims[0], hipMemcpyHostToDevice, s->stream));
+  if (r.ld_host == r.ld)
+    SPMM_HIP(hipMemcpyAsync(buffer(s, r, 0), r.x_host, (size_t)(s->dims[0] * r.ld * s->elem), hipMemcpyHostToDevice,
+                            s->stream));
+  else
+    SPMM_HIP(hipMemcpy2DAsync(buffer(s, r, 0), (size_t)(r.ld * s->elem), r.x_host, (size_t)(r.ld_host * s->elem),
+                              (size_t)(r.n * s->elem), (size_t)s->dims[0], hipMemcpyHostToDevice, s->stream));
   return SPMM_OK;
 }
 
 static spmm_status_t download_output(spmm_srv_s* s, const Request& r) {
   if (s->opts.simulate) return SPMM_OK;
-  SPMM_HIP(hipMemcpy2DAsync(r.y_host, (size_t)(r.n * s->elem), buffer(s, r, s->L % 2), (size_t)(r.ld * s->elem),
-                            (size_t)(r.n * s->elem), (size_t)s->dims[s->L], hipMemcpyDeviceToHost, s->stream));
+  if (r.ld_host == r.ld)
+    SPMM_HIP(hipMemcpyAsync(r.y_host, buffer(s, r, s->L % 2), (size_t)(s->dims[s->L] * r.ld * s->elem),
+                            hipMemcpyDeviceToHost, s->stream));
+  else
+    SPMM_HIP(hipMemcpy2DAsync(r.y_host, (size_t)(r.ld_host * s->elem), buffer(s, r, s->L % 2),
+                              (size_t)(r.ld * s->elem), (size_t)(r.n * s->elem), (size_t)s->dims[s->L],
+                              hipMemcpyDeviceToHost, s->stream));
   return SPMM_OK;
 }
 
@@ -202,19 +231,54 @@ static void finish_locked(spmm_srv_s* s, const Request& r, double t) {
   s->outstanding -= 1;
 }
 
-// One step; returns the number of requests still pending or active.
+// Retires enqueued steps whose event has completed (all of them when `wait`):
+// their finished requests release their memory and are reported done.
+static spmm_status_t retire(spmm_srv_s* s, bool wait_all, bool wait_one) {
+  spmm_status_t st = SPMM_OK;
+  while (!s->inflight.empty()) {
+    spmm_srv_s::InFlight& f = s->inflight.front();
+    hipError_t e = hipEventQuery(f.ev);
+    if (e == hipErrorNotReady) {
+      if (!wait_all && !wait_one) break;
+      e = hipEventSynchronize(f.ev);
+      wait_one = false;
+    }
+    if (e != hipSuccess) {
+      st = fail_hip(e, "serving step");
+      break;
+    }
+    const double t = now_s();
+    {
+      std::lock_guard<std::mutex> lk(s->mu);
+      for (const Request& r : f.finished) finish_locked(s, r, t);
+    }
+    s->free_events.push_back(f.ev);
+    s->inflight.pop_front();
+    s->done_cv.notify_all();
+  }
+  return st;
+}
+
+// One step. Manual and simulated servers complete each step before returning
+// (requests finishing in it are done on return); the worker enqueues steps and
+// retires them as their events complete, at most two steps ahead of the device.
 static spmm_status_t do_step(spmm_srv_s* s, int32_t* remaining) {
   const double t0 = now_s();
+  const bool async = !s->opts.manual && !s->opts.simulate && s->opts.mode == SPMM_SERVE_CONTINUOUS;
   spmm_status_t st = SPMM_OK;
+  if (async) st = retire(s, false, s->inflight.size() >= 2);
   std::vector<Request> admitted;
   {
     std::lock_guard<std::mutex> lk(s->mu);
     if (s->failed != SPMM_OK) return s->failed;
-    admitted = admit_locked(s, s->opts.mode == SPMM_SERVE_PLAIN ? 1 : s->opts.max_active);
+    if (st == SPMM_OK) admitted = admit_locked(s, s->opts.mode == SPMM_SERVE_PLAIN ? 1 : s->opts.max_active);
   }
   for (const Request& r : admitted)
     if (st == SPMM_OK) st = upload_input(s, r);
-  for (Request& r : admitted) s->active.push_back(r);  // only the stepping thread touches `active`
+  for (Request& r : admitted) {  // only the stepping thread touches `active`
+    s->active.push_back(r);
+    s->active_tokens += r.n;
+  }
   int64_t pool_used = 0;
   {
     std::lock_guard<std::mutex> lk(s->mu);
@@ -265,17 +329,42 @@ static spmm_status_t do_step(spmm_srv_s* s, int32_t* remaining) {
     }
     for (const Request& r : s->active)
       if (r.layer == s->L && st == SPMM_OK) st = download_output(s, r);
-    if (st == SPMM_OK && !s->opts.simulate) {
-      hipError_t e = hipStreamSynchronize(s->stream);
-      if (e != hipSuccess) st = fail_hip(e, "serving step");
-    }
     size_t w = 0;
     for (size_t i = 0; i < s->active.size(); ++i) {
-      if (s->active[i].layer == s->L) finished.push_back(s->active[i]);
-      else s->active[w++] = s->active[i];
+      if (s->active[i].layer == s->L) {
+        finished.push_back(s->active[i]);
+        s->active_tokens -= s->active[i].n;
+      } else {
+        s->active[w++] = s->active[i];
+      }
     }
     s->active.resize(w);
     s->stats.steps += 1;
+    if (st == SPMM_OK && async) {
+      spmm_srv_s::InFlight f;
+      if (!s->free_events.empty()) {
+        f.ev = s->free_events.back();
+        s->free_events.pop_back();
+      } else {
+        hipError_t e = hipEventCreateWithFlags(&f.ev, hipEventDisableTiming);
+        if (e != hipSuccess) st = fail_hip(e, "hipEventCreate");
+      }
+      if (st == SPMM_OK) {
+        hipError_t e = hipEventRecord(f.ev, s->stream);
+        if (e != hipSuccess) st = fail_hip(e, "hipEventRecord");
+      }
+      if (st == SPMM_OK) {
+        f.finished.swap(finished);
+        s->inflight.push_back(std::move(f));
+      } else if (f.ev) {
+        s->free_events.push_back(f.ev);
+      }
+    } else if (st == SPMM_OK && !s->opts.simulate) {
+      hipError_t e = hipStreamSynchronize(s->stream);
+      if (e != hipSuccess) st = fail_hip(e, "serving step");
+    }
+  } else if (st == SPMM_OK && async && !s->inflight.empty()) {
+    st = retire(s, false, true);  // nothing to enqueue: wait for the oldest step
   }
   const double t1 = now_s();
   {
@@ -286,7 +375,7 @@ static spmm_status_t do_step(spmm_srv_s* s, int32_t* remaining) {
     }
     for (const Request& r : finished) finish_locked(s, r, t1);
     s->stats.busy_s += t1 - t0;
-    if (remaining) *remaining = (int32_t)(s->pending.size() + s->active.size());
+    if (remaining) *remaining = (int32_t)(s->pending.size() + s->active.size() + s->inflight.size());
   }
   s->done_cv.notify_all();
   return st;
@@ -297,7 +386,7 @@ static void worker_main(spmm_srv_s* s) {
   for (;;) {
     {
       std::unique_lock<std::mutex> lk(s->mu);
-      s->cv.wait(lk, [&] { return s->stop || !s->pending.empty() || !s->active.empty(); });
+      s->cv.wait(lk, [&] { return s->stop || !s->pending.empty() || !s->active.empty() || !s->inflight.empty(); });
       if (s->stop) return;
       if (s->failed != SPMM_OK) {
         s->done_cv.notify_all();
@@ -323,6 +412,8 @@ static void destroy_server(spmm_srv_s* s) {
     (void)hipStreamSynchronize(s->stream);
     (void)hipStreamDestroy(s->stream);
   }
+  for (auto& f : s->inflight) (void)hipEventDestroy(f.ev);
+  for (hipEvent_t e : s->free_events) (void)hipEventDestroy(e);
   if (s->group) (void)spmm_group_destroy(s->group);
   if (s->pool_dev) (void)hipFree(s->pool_dev);
   delete s->pool;
@@ -412,10 +503,12 @@ spmm_status_t spmm_serve_create(const spmm_plan_t* layer_plans, int32_t num_laye
   return SPMM_OK;
 }
 
-spmm_status_t spmm_serve_submit(spmm_srv_t s, uint64_t id, int64_t n, const void* x_host, void* y_host) {
+spmm_status_t spmm_serve_submit(spmm_srv_t s, uint64_t id, int64_t n, const void* x_host, void* y_host,
+                                int64_t ld_host) {
   clear_error();
   if (!s) return fail(SPMM_ERR_INVALID_ARG, "server is NULL");
   if (n < 1 || n > (1 << 24)) return fail(SPMM_ERR_INVALID_ARG, "n must be in [1, 2^24]");
+  if (ld_host < n) return fail(SPMM_ERR_INVALID_ARG, "ld_host is smaller than n");
   if (!s->opts.simulate && (!x_host || !y_host)) return fail(SPMM_ERR_INVALID_ARG, "x_host and y_host are required");
   Request r;
   r.id = id;
@@ -423,6 +516,7 @@ spmm_status_t spmm_serve_submit(spmm_srv_t s, uint64_t id, int64_t n, const void
   r.ld = (n + 7) / 8 * 8;
   r.x_host = x_host;
   r.y_host = y_host;
+  r.ld_host = ld_host;
   r.bytes = request_bytes(s, n);
   if (r.bytes > s->opts.mem_budget_bytes) return fail(SPMM_ERR_REJECTED, "request exceeds the activation memory budget");
   {

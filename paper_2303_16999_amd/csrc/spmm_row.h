@@ -41,8 +41,9 @@ struct Fp8 {};  // weights stored as OCP E4M3FN codes
 struct RowProblem {
   const int32_t* row_ptr;  // [mb + 1]
   const int32_t* col_idx;  // [nnz]
-  const void* W;           // values in block-CSR order
-  const float* scales;     // FP8 block scales in block-CSR order, else nullptr
+  const void* W;           // values in block-CSR order (or indexed by w_index)
+  const float* scales;     // FP8 block scales, indexed like W, else nullptr
+  const int32_t* w_index;  // entry q's values are block w_index[q] of W; nullptr: block q
   const void* X;
   void* Y;
   int64_t ldx, ldy;
@@ -162,14 +163,16 @@ __device__ __forceinline__ void row_tile(const RowProblem& p, int32_t r, int32_t
     for (int s = 0; s < NS; ++s) acc[h][s] = float4_t{0.f, 0.f, 0.f, 0.f};
 
   const int32_t q_lo = uniform(p.row_ptr[r]), q_hi = uniform(p.row_ptr[r + 1]);
+  const int32_t* __restrict__ widx = p.w_index;
+  auto wq = [&](int32_t q) -> int64_t { return widx ? (int64_t)uniform(widx[q]) : (int64_t)q; };
   if constexpr (!kFp8 && B == 16) {
     // pairs of blocks: k slots 0-3 from the first block, 4-7 from the second
     for (int32_t q = q_lo; q < q_hi; q += 2) {
       const bool two = q + 1 < q_hi;
       const int32_t c1 = uniform(p.col_idx[q]);
       const int32_t c2 = two ? uniform(p.col_idx[q + 1]) : c1;
-      const u32x2 a1 = *(const u32x2*)(Wb + (int64_t)q * WB + (j * 16 + g * 4) * 2);
-      const u32x2 a2 = two ? *(const u32x2*)(Wb + (int64_t)(q + 1) * WB + (j * 16 + g * 4) * 2) : u32x2{0u, 0u};
+      const u32x2 a1 = *(const u32x2*)(Wb + wq(q) * WB + (j * 16 + g * 4) * 2);
+      const u32x2 a2 = two ? *(const u32x2*)(Wb + wq(q + 1) * WB + (j * 16 + g * 4) * 2) : u32x2{0u, 0u};
       const u32x4 a = {a1.x, a1.y, a2.x, a2.y};
       u32x2 b1[NS], b2[NS];
       xfrag<NS>(xr, p, c1 * 16, g, j, n0, b1);
@@ -190,7 +193,7 @@ __device__ __forceinline__ void row_tile(const RowProblem& p, int32_t r, int32_t
       xfrag<NS>(xr, p, c * 32 + 4, 2 * g, j, n0, b2);  // rows c*32 + 8g + 4 + i
 #pragma unroll
       for (int h = 0; h < H; ++h) {
-        const u32x4 a = *(const u32x4*)(Wb + (int64_t)q * WB + ((h * 16 + j) * 32 + g * 8) * 2);
+        const u32x4 a = *(const u32x4*)(Wb + wq(q) * WB + ((h * 16 + j) * 32 + g * 8) * 2);
 #pragma unroll
         for (int s = 0; s < NS; ++s) acc[h][s] = Mma<XT>::k32(a, u32x4{b1[s].x, b1[s].y, b2[s].x, b2[s].y}, acc[h][s]);
       }
@@ -198,9 +201,10 @@ __device__ __forceinline__ void row_tile(const RowProblem& p, int32_t r, int32_t
   } else {  // FP8 weights with a per-block scale
     for (int32_t q = q_lo; q < q_hi; ++q) {
       const int32_t c = uniform(p.col_idx[q]);
-      const float sc = p.scales[q];
+      const int64_t qv = wq(q);
+      const float sc = p.scales[qv];
       if constexpr (B == 16) {
-        const u32x2 a = fp8x4<XT>(*(const uint32_t*)(Wb + (int64_t)q * WB + j * 16 + g * 4));
+        const u32x2 a = fp8x4<XT>(*(const uint32_t*)(Wb + qv * WB + j * 16 + g * 4));
         u32x2 bx[NS];
         xfrag<NS>(xr, p, c * 16, g, j, n0, bx);
 #pragma unroll
@@ -211,7 +215,7 @@ __device__ __forceinline__ void row_tile(const RowProblem& p, int32_t r, int32_t
         xfrag<NS>(xr, p, c * 32 + 4, 2 * g, j, n0, b2);
 #pragma unroll
         for (int h = 0; h < H; ++h) {
-          const u32x2 codes = *(const u32x2*)(Wb + (int64_t)q * WB + (h * 16 + j) * 32 + g * 8);
+          const u32x2 codes = *(const u32x2*)(Wb + qv * WB + (h * 16 + j) * 32 + g * 8);
           const u32x2 lo = fp8x4<XT>(codes.x), hi = fp8x4<XT>(codes.y);
           const u32x4 a = {lo.x, lo.y, hi.x, hi.y};
 #pragma unroll
@@ -293,7 +297,7 @@ __global__ __launch_bounds__(256) void k_spmm_row(Params prm) {
 // Workgroup w takes logical units w, w + grid, ... in the XCD-aware order;
 // a unit is (problem, group of 4 block rows, column tile of 16*ns).
 template <typename XT, typename WT, typename YT, int B>
-__global__ __launch_bounds__(256) void k_spmm_row_grouped(const RowProblem* __restrict__ probs,
+__global__ __launch_bounds__(256, B == 16 ? 4 : 3) void k_spmm_row_grouped(const RowProblem* __restrict__ probs,
                                                           const int32_t* __restrict__ header) {
   const int32_t count = uniform(header[0]), total = uniform(header[1]);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -305,7 +309,7 @@ __global__ __launch_bounds__(256) void k_spmm_row_grouped(const RowProblem* __re
       if (uniform(probs[mid].unit_begin) <= unit) lo = mid;
       else hi = mid - 1;
     }
-    const RowProblem& p = probs[lo];
+    const RowProblem p = probs[lo];  // by value: the fields live in scalar registers
     const int32_t local = unit - uniform(p.unit_begin);
     const int32_t rgroups = (uniform(p.mb) + kRowsPerWg - 1) / kRowsPerWg;
     const int32_t ns = uniform(p.ns);
@@ -325,6 +329,7 @@ inline RowProblem row_problem(const RunArgs& a, const int32_t* row_ptr, const in
   p.col_idx = col_idx;
   p.W = a.W;
   p.scales = a.scales;
+  p.w_index = a.w_index;
   p.X = a.X;
   p.Y = a.Y;
   p.ldx = a.ldx;

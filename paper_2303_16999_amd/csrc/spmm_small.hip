@@ -33,8 +33,9 @@ struct Fp8 {};  // weights stored as OCP E4M3FN codes
 struct SParams {
   const int32_t* row_ptr;  // [mb + 1]
   const int32_t* col_idx;  // [nnz]
-  const void* W;           // values in block-CSR order, row-major b x b per block
-  const float* scales;     // FP8 block scales in block-CSR order, else nullptr
+  const void* W;           // values in block-CSR order (or indexed by w_index), row-major b x b per block
+  const float* scales;     // FP8 block scales, indexed like W, else nullptr
+  const int32_t* w_index;  // entry q's values are block w_index[q] of W; nullptr: block q
   const void* X;
   void* Y;
   int64_t ldx, ldy;
@@ -154,8 +155,9 @@ __global__ __launch_bounds__(256) void k_spmm_small(SParams p) {
       const int32_t cv = have ? p.col_idx[q0 + lane] : -1;
       uint32_t wv = 0;  // 16-bit weight bits, or float bits
       if (have) {
-        if constexpr (kDot) wv = ((const uint16_t*)Wb)[q0 + lane];
-        else wv = __builtin_bit_cast(uint32_t, w_elem<XT, WT>(Wb, q0 + lane, __is_same(WT, Fp8) ? p.scales[q0 + lane] : 1.f));
+        const int32_t qi = p.w_index ? p.w_index[q0 + lane] : q0 + lane;
+        if constexpr (kDot) wv = ((const uint16_t*)Wb)[qi];
+        else wv = __builtin_bit_cast(uint32_t, w_elem<XT, WT>(Wb, qi, __is_same(WT, Fp8) ? p.scales[qi] : 1.f));
       }
       for (int32_t t = 0; t < cnt; t += 8) {
         uint32_t xd[8][DW];
@@ -195,7 +197,8 @@ __global__ __launch_bounds__(256) void k_spmm_small(SParams p) {
     constexpr int WD = B * B / 2;  // dwords per block
     for (int32_t q = q_lo; q < q_hi; ++q) {
       const int32_t c = uniform(p.col_idx[q]);
-      const uint32_t* __restrict__ wq = (const uint32_t*)(Wb + (int64_t)q * B * B * 2);
+      const int64_t qv = p.w_index ? (int64_t)uniform(p.w_index[q]) : (int64_t)q;
+      const uint32_t* __restrict__ wq = (const uint32_t*)(Wb + qv * B * B * 2);
       uint32_t wd[WD];
 #pragma unroll
       for (int i = 0; i < WD; ++i) wd[i] = wq[i];
@@ -217,12 +220,13 @@ __global__ __launch_bounds__(256) void k_spmm_small(SParams p) {
     // FP32 or FP8 weights: FP32 FMAs
     for (int32_t q = q_lo; q < q_hi; ++q) {
       const int32_t c = uniform(p.col_idx[q]);
-      const float sc = __is_same(WT, Fp8) ? p.scales[q] : 1.f;
+      const int64_t qv = p.w_index ? (int64_t)uniform(p.w_index[q]) : (int64_t)q;
+      const float sc = __is_same(WT, Fp8) ? p.scales[qv] : 1.f;
       float w[B][B];
 #pragma unroll
       for (int i = 0; i < B; ++i)
 #pragma unroll
-        for (int kk = 0; kk < B; ++kk) w[i][kk] = w_elem<XT, WT>(Wb, (int64_t)q * B * B + i * B + kk, sc);
+        for (int kk = 0; kk < B; ++kk) w[i][kk] = w_elem<XT, WT>(Wb, qv * B * B + i * B + kk, sc);
 #pragma unroll
       for (int kk = 0; kk < B; ++kk) {
         uint32_t xd[DW];
@@ -281,6 +285,7 @@ spmm_status_t launch_small(const RunArgs& a, const int32_t* row_ptr, const int32
   p.col_idx = col_idx;
   p.W = a.W;
   p.scales = a.scales;
+  p.w_index = a.w_index;
   p.X = a.X;
   p.Y = a.Y;
   p.ldx = a.ldx;

@@ -29,7 +29,7 @@ class PlanOpts(ctypes.Structure):
 
 class ServeOpts(ctypes.Structure):
     _fields_ = [("mem_budget_bytes", ctypes.c_int64), ("max_active", ctypes.c_int32), ("mode", ctypes.c_int32),
-                ("manual", ctypes.c_int32), ("simulate", ctypes.c_int32)]
+                ("manual", ctypes.c_int32), ("simulate", ctypes.c_int32), ("max_tokens", ctypes.c_int64)]
 
 
 class ServeDone(ctypes.Structure):
@@ -67,7 +67,7 @@ SIGNATURES = {
     "spmm_group_run": ([_vp, _c_i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp], _c_i32),
     "spmm_group_destroy": ([_vp], _c_i32),
     "spmm_serve_create": ([_vp, _c_i32, _vp, _vp, ctypes.POINTER(ServeOpts), ctypes.POINTER(_vp)], _c_i32),
-    "spmm_serve_submit": ([_vp, ctypes.c_uint64, _c_i64, _vp, _vp], _c_i32),
+    "spmm_serve_submit": ([_vp, ctypes.c_uint64, _c_i64, _vp, _vp, _c_i64], _c_i32),
     "spmm_serve_poll": ([_vp, ctypes.POINTER(ServeDone), _c_i32, _pi32], _c_i32),
     "spmm_serve_step": ([_vp, _pi32], _c_i32),
     "spmm_serve_drain": ([_vp], _c_i32),
@@ -288,24 +288,34 @@ class Server:
     dims: feature sizes [num_layers + 1]; relu: per-layer flags."""
 
     def __init__(self, plans, dims, relu=None, mem_budget_bytes=1 << 30, max_active=64, mode=SERVE_CONTINUOUS,
-                 manual=False, simulate=False):
+                 manual=False, simulate=False, max_tokens=0):
         L = len(dims) - 1
         self._plans = plans  # keep the plans alive as long as the server
         P = (_vp * L)(*[(p._h.value if p is not None else None) for p in plans]) if plans is not None else None
         D = (ctypes.c_int64 * (L + 1))(*[int(d) for d in dims])
         R = (ctypes.c_uint8 * L)(*[1 if (relu and relu[i]) else 0 for i in range(L)]) if relu is not None else None
-        opts = ServeOpts(int(mem_budget_bytes), int(max_active), int(mode), int(bool(manual)), int(bool(simulate)))
+        opts = ServeOpts(int(mem_budget_bytes), int(max_active), int(mode), int(bool(manual)), int(bool(simulate)),
+                         int(max_tokens))
         h = _vp()
         check(lib().spmm_serve_create(P, L, D, R, ctypes.byref(opts), ctypes.byref(h)))
         self._h = h
         self._keep = {}  # request id -> host buffers kept alive until done
 
     def submit(self, req_id, n, x_host=None, y_host=None):
-        """x_host / y_host: C-contiguous numpy arrays [dims[0], n] and [dims[-1], n] (or None when simulating)."""
-        xp = x_host.ctypes.data_as(_vp) if x_host is not None else None
-        yp = y_host.ctypes.data_as(_vp) if y_host is not None else None
-        st = lib().spmm_serve_submit(self._h, int(req_id), int(n), xp, yp)
-        check(st)
+        """x_host / y_host: C-contiguous [dims[0], ld] and [dims[-1], ld] host arrays
+        (numpy arrays, or torch CPU tensors, pinned for asynchronous copies) with
+        ld >= n; None when simulating."""
+        def ptr_ld(a):
+            if a is None:
+                return None, int(n)
+            if hasattr(a, "data_ptr"):
+                return a.data_ptr(), int(a.stride(0))
+            return a.ctypes.data, int(a.strides[0] // a.itemsize)
+        xp, ldx = ptr_ld(x_host)
+        yp, ldy = ptr_ld(y_host)
+        if ldx != ldy:
+            raise ValueError("x_host and y_host must share one leading dimension")
+        check(lib().spmm_serve_submit(self._h, int(req_id), int(n), xp, yp, ldx))
         self._keep[int(req_id)] = (x_host, y_host)
 
     def poll(self, max_items=4096):

@@ -123,3 +123,43 @@ def test_dynamic_call_stream_config3_shape(w):
         assert status.item() == 0
         ref = O.spmm_blockwise_columns(m, k, b, rows, cols, v64, X64, cols_s)
         assert O.rel_fro(Y.cpu().numpy().astype(np.float64)[:, cols_s], ref) <= 5e-3
+
+
+@pytest.mark.parametrize("w,b", [("f16", 16), ("fp8", 16), ("bf16", 32)])
+def test_one_workgroup_encoder_equals_multi_kernel_encoder(w, b, monkeypatch):
+    """Both dynamic encoders give the same plan (and the oracle's) and the same Y bit for bit."""
+    m = k = 64 * b
+    mb = kb = 64
+    max_nnz = mb * kb // 8
+    x = "bf16" if w == "fp8" else None
+    h = spmm.DynamicHandle(m, k, b, max_nnz, w, x=x, group_rows=8 if b == 16 else 0, num_panels=5)
+    rows, cols, vals = synth.dynamic_call(mb, kb, b, max_nnz, seed=17, dtype="f16")
+    scales = None
+    if w == "fp8":
+        codes, sc = synth.quantize_e4m3fn_blocks(synth.storage_to_f64(vals, "f16").astype(np.float32))
+        pad = max_nnz - len(rows)
+        v = dev(np.concatenate([codes, np.zeros((pad, b, b), np.uint8)]))
+        scales = dev(np.concatenate([sc, np.ones(pad, np.float32)]))
+        r, c, _, nnz = _dyn_inputs(rows, cols, np.zeros((len(rows), b, b), np.float16), max_nnz, b)
+    else:
+        vals = synth.to_storage(synth.storage_to_f64(vals, "f16"), w)
+        r, c, v, nnz = _dyn_inputs(rows, cols, vals, max_nnz, b)
+    X = dev(synth.to_storage(synth.normal((k, 192), 3), x or w))
+    outs, exports = [], []
+    for builder in (None, "multi"):
+        if builder:
+            monkeypatch.setenv("SPMM_DYN_BUILDER", builder)
+        else:
+            monkeypatch.delenv("SPMM_DYN_BUILDER", raising=False)
+        Y = torch.full((m, 192), float("nan"), dtype=X.dtype, device="cuda")
+        status = torch.full((1,), -1, dtype=torch.int32, device="cuda")
+        h.run(nnz, r, c, v, X, Y, status, scales=scales)
+        torch.cuda.synchronize()
+        assert status.item() == 0
+        outs.append(Y)
+        exports.append(h.export())
+    assert torch.equal(outs[0], outs[1])
+    ref = plan_ref.plan_from_coo(mb, kb, rows, cols, h.info()["group_rows"], h.info()["num_panels"])
+    for ex in exports:
+        for key in ("row_ptr", "col_idx", "src", "panel_ptr"):
+            assert np.array_equal(ex[key], ref[key]), key

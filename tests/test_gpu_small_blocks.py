@@ -98,10 +98,11 @@ def test_small_sweep_shape_sampled_columns(b):
     assert torch.isfinite(Y).all().item()
 
 
+@pytest.mark.parametrize("k_tail", [0, 1])  # k % b == 0 takes the one-workgroup encoder
 @pytest.mark.parametrize("w", ["f16", "f32"])
 @pytest.mark.parametrize("b", SMALL)
-def test_small_dynamic_equals_static_bitwise(w, b):
-    c = Case(70 * b, 50 * b + 1, 300, b, 1 / 6, w=w, seed=40 + b)
+def test_small_dynamic_equals_static_bitwise(w, b, k_tail):
+    c = Case(70 * b, 50 * b + k_tail, 300, b, 1 / 6, w=w, seed=40 + b)
     _, Ys = c.run_static()
     max_nnz = len(c.rows) + 9
     perm = np.random.default_rng(6).permutation(len(c.rows))

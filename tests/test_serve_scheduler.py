@@ -134,3 +134,24 @@ def test_worker_thread_drains_everything_once():
     assert all(d["submit_s"] <= d["admit_s"] <= d["done_s"] for d in done)
     assert s.stats()["peak_active"] <= 8
     s.close()
+
+
+def test_token_budget_limits_admission_but_never_blocks_a_lone_request():
+    s = _server(max_tokens=100)
+    s.submit(1, 60)
+    s.submit(2, 60)   # 60 + 60 > 100: waits for 1
+    s.submit(3, 30)   # FIFO: stays behind 2
+    s.step()
+    st = s.stats()
+    assert st["active"] == 1 and st["pending"] == 2
+    for _ in range(L - 1):
+        s.step()
+    assert [d["id"] for d in s.poll()] == [1]
+    s.step()          # 2 and 3 fit together now (90 tokens)
+    assert s.stats()["active"] == 2
+    s.drain()
+    assert [d["id"] for d in s.poll()] == [2, 3]
+    big = _server(max_tokens=16)
+    big.submit(7, 500)  # larger than the budget, admitted alone
+    big.step()
+    assert big.stats()["active"] == 1
