@@ -42,7 +42,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--mode", default="headline",
-                    choices=["headline", "sweep", "dynamic", "precision", "copy", "serve", "group"])
+                    choices=["headline", "sweep", "dynamic", "precision", "copy", "serve", "group", "table3"])
     ap.add_argument("--requests", type=int, default=2000, help="serve mode: measured requests per run")
     ap.add_argument("--rho", default="0.5,0.8", help="serve mode: offered load as fractions of the saturated rate")
     ap.add_argument("--max-tokens", default="4096,16384,0",
@@ -272,9 +272,11 @@ def mode_sweep(args):
     import torch
     dense_cache = {}
     flush = torch.empty(512 * 1024 * 1024 // 4, dtype=torch.float32, device="cuda")
+    points = []
     for n in [int(v) for v in args.sweep_n.split(",")]:
         for b in [int(v) for v in args.sweep_b.split(",")]:
-            for dd in (128, 64, 32, 16, 8, 4):
+            # b = 16 continues to d = 1/2 and 1 to locate its crossover with dense
+            for dd in (128, 64, 32, 16, 8, 4) + ((2, 1) if b == 16 else ()):
                 prob = StaticProblem(8192, 8192, n, b, 1.0 / dd, "f16", seed=0)
                 ms = time_steps(prob.step, args.steps, args.warmup)
                 cold = time_cold(prob.step, 5, flush)
@@ -289,8 +291,29 @@ def mode_sweep(args):
                        "plan_build_ms": round(prob.plan_ms, 3),
                        "dense_ms": round(dense_cache[n], 5), "speedup_vs_dense": round(dense_cache[n] / ms, 3)}
                 emit(rec, args.out)
+                points.append(rec)
                 del prob
                 torch.cuda.empty_cache()
+    for n in sorted({p["n"] for p in points}):
+        for b in sorted({p["b"] for p in points}):
+            pts = sorted((p["density"], p["speedup_vs_dense"]) for p in points if p["n"] == n and p["b"] == b)
+            if pts:
+                emit({"mode": "crossover", "n": n, "b": b, "crossover_density": crossover_density(pts)}, args.out)
+
+
+def crossover_density(pts):
+    """Density at which the sparse/dense speedup falls to 1, interpolated
+    linearly in (log d, log speedup) between the bracketing measured points;
+    a string bound when every measured point is on one side."""
+    for (d0, s0), (d1, s1) in zip(pts, pts[1:]):
+        if s0 >= 1.0 > s1:
+            t = math.log(s0) / (math.log(s0) - math.log(s1))
+            return round(math.exp(math.log(d0) + t * (math.log(d1) - math.log(d0))), 5)
+    if all(s >= 1.0 for _, s in pts):
+        return "above %g" % pts[-1][0]
+    if all(s < 1.0 for _, s in pts):
+        return "below %g" % pts[0][0]
+    return None
 
 
 def mode_precision(args):
@@ -561,6 +584,42 @@ def mode_group(args):
         p.close()
 
 
+def mode_table3(args):
+    """Static and dynamic sparse against dense FP16 at m = k = 4096, d = 1/16,
+    b in {1, 4, 16}, best over n: the shape of the paper's static-vs-dynamic
+    comparison. The dynamic call re-encodes the static pattern (COO in random
+    order) on every call."""
+    import torch
+    from paper_2303_16999_amd import spmm
+    m = k = 4096
+    for b in (1, 4, 16):
+        best = {"static": 0.0, "dynamic": 0.0}
+        for n in (1024, 4096, 16384):
+            prob = StaticProblem(m, k, n, b, 1 / 16, "f16", seed=0)
+            ms_s = time_steps(prob.step, args.steps, args.warmup)
+            perm = np.random.default_rng(1).permutation(prob.nnzb)
+            r = torch.from_numpy(prob.rows[perm].copy()).cuda()
+            c = torch.from_numpy(prob.cols[perm].copy()).cuda()
+            v = prob.values_dev[torch.from_numpy(perm).cuda()].contiguous()
+            nnz = torch.tensor([prob.nnzb], dtype=torch.int32, device="cuda")
+            status = torch.zeros(1, dtype=torch.int32, device="cuda")
+            h = spmm.DynamicHandle(m, k, b, prob.nnzb, "f16", n_hint=n)
+            ms_d = time_steps(lambda: h.run(nnz, r, c, v, prob.X, prob.Y, status), args.steps, args.warmup)
+            assert int(status.item()) == 0
+            dn = dense_fp16(m, k, n, args.steps, args.warmup, 1.0)["ms"]
+            rec = {"mode": "table3", "m": m, "k": k, "n": n, "b": b, "density": 1 / 16,
+                   "static_ms": round(ms_s, 5), "dynamic_ms": round(ms_d, 5), "dense_ms": round(dn, 5),
+                   "static_over_dense": round(dn / ms_s, 3), "dynamic_over_dense": round(dn / ms_d, 3),
+                   "static_tflops": round(prob.flops() / (ms_s * 1e-3) / 1e12, 3)}
+            emit(rec, args.out)
+            best["static"] = max(best["static"], rec["static_over_dense"])
+            best["dynamic"] = max(best["dynamic"], rec["dynamic_over_dense"])
+            del prob, h, v
+            torch.cuda.empty_cache()
+        emit({"mode": "table3_best_over_n", "b": b, "static_over_dense": best["static"],
+              "dynamic_over_dense": best["dynamic"]}, args.out)
+
+
 def mode_copy(args):
     """Plain copy of a known size, for calibrating the HBM byte counters."""
     import torch
@@ -583,7 +642,7 @@ def main():
     from paper_2303_16999_amd import spmm
     spmm.lib()  # fails loudly if the HIP library is missing
     {"headline": mode_headline, "sweep": mode_sweep, "precision": mode_precision, "copy": mode_copy,
-     "dynamic": mode_dynamic, "serve": mode_serve, "group": mode_group}[args.mode](args)
+     "dynamic": mode_dynamic, "serve": mode_serve, "group": mode_group, "table3": mode_table3}[args.mode](args)
 
 
 if __name__ == "__main__":

@@ -160,13 +160,15 @@ spmm_status_t spmm_autotune_static(spmm_plan_t plan, int64_t n, const void* X, i
 
 /* ------------------------------------------------------------------ grouped launch
  * Many static products with different plans, column counts, X and Y in one
- * persistent kernel launch. This goes beyond the paper, whose benchmarks run
- * one product at a time and let n grow to amortise overheads (Sections 4
- * and 5); here
- * the columns of many small products share one launch instead. The problem
- * table is written into pinned host memory, copied to the device and read by
- * the kernel, and the copy + kernel pair is a captured HIP graph that is
- * replayed for every call, so a call costs one graph launch.
+ * kernel launch: one workgroup per work unit of all the problems. This goes
+ * beyond the paper, whose benchmarks run one product at a time and let n grow
+ * to amortise overheads (Sections 4 and 5); here the columns of many small
+ * products share one launch instead. Up to 32 problems travel in the kernel
+ * arguments, and the call replays a captured one-node HIP graph after
+ * updating that node's arguments and grid. Larger groups go through a ring of
+ * four pinned host + device tables: the call copies its table and launches
+ * on it, and waits on the host only when the slot it needs is still in use by
+ * the call four before.
  *
  * spmm_group_create makes a handle for up to max_problems problems.
  * spmm_group_run: problem i computes Y[i] = (M o W)_plans[i] * X[i] with
@@ -174,9 +176,9 @@ spmm_status_t spmm_autotune_static(spmm_plan_t plan, int64_t n, const void* X, i
  * applies max(0, .) before rounding when relu is non-NULL and relu[i] != 0.
  * Every plan must have values set and share block size (16 or 32) and dtype
  * triple, with 16-bit W and X (FP8 weights: UNSUPPORTED). Each problem uses
- * its plan's tile variant for its n. The handle double-buffers its table: a
- * call waits on the host until the call two before it has finished on the
- * device. Calls on one handle must not overlap on different streams.
+ * its plan's tile variant for its n, so its result equals its own
+ * spmm_run_static bit for bit. Calls on one handle must not overlap on
+ * different streams.
  * Errors: INVALID_ARG (count > max_problems, NULL, alignment, ld < n, values
  * not set, mixed block size or dtypes), UNSUPPORTED, HIP. */
 spmm_status_t spmm_group_create(int32_t max_problems, spmm_group_t* out);

@@ -143,14 +143,22 @@ struct RunArgs {
 spmm_status_t launch_spmm(const RunArgs& a, hipStream_t stream);
 // Row-wise kernel (16-bit X, b = 16 or 32): W and scales in block-CSR order.
 spmm_status_t launch_spmm_row(const RunArgs& a, const int32_t* row_ptr, const int32_t* col_idx, hipStream_t stream);
-// Grouped persistent row-wise launch over a device table of problem
-// descriptors (header_dev = {count, total units}); 16-bit W and X, b = 16/32.
-spmm_status_t launch_spmm_row_grouped(spmm_dtype_t xt, spmm_dtype_t yt, int32_t b, const void* probs_dev,
-                                      const int32_t* header_dev, int32_t grid, hipStream_t stream);
+// Grouped row-wise launches (16-bit W and X, b = 16/32): one workgroup per
+// work unit of all problems. The table of problem descriptors is either in
+// the kernel arguments (at most group_inline_max() problems; built with
+// group_args_header / group_args_problem / fill_row_problem) or in device memory.
+int32_t group_inline_max();
+size_t group_args_bytes();
 size_t row_problem_size();
-int32_t row_grouped_grid(spmm_dtype_t xt, spmm_dtype_t yt, int32_t b);
+void group_args_header(void* args, int32_t count, int32_t total);
+void* group_args_problem(void* args, int32_t i);
 void fill_row_problem(void* dst, const RunArgs& a, const int32_t* row_ptr, const int32_t* col_idx,
                       int32_t unit_begin);
+const void* row_grouped_args_kernel(spmm_dtype_t xt, spmm_dtype_t yt, int32_t b);
+spmm_status_t launch_spmm_row_grouped_args(spmm_dtype_t xt, spmm_dtype_t yt, int32_t b, const void* args,
+                                           int32_t total, hipStream_t stream);
+spmm_status_t launch_spmm_row_grouped(spmm_dtype_t xt, spmm_dtype_t yt, int32_t b, const void* probs_dev,
+                                      int32_t count, int32_t total, hipStream_t stream);
 // Small-block kernel (b = 1, 4, 8, every dtype triple): W and scales in block-CSR order.
 spmm_status_t launch_spmm_small(const RunArgs& a, const int32_t* row_ptr, const int32_t* col_idx, hipStream_t stream);
 // True when (b, x dtype) runs on a block-CSR kernel (row-wise MFMA or small-block).

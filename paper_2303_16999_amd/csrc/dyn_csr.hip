@@ -159,30 +159,44 @@ __global__ void k_dyn_status_out(const int32_t* __restrict__ internal, int32_t* 
 // LDS; the result is identical to the multi-kernel path's.
 constexpr int kSmallThreads = 1024;
 
+// Inclusive scan across the 64 lanes of a wave (shuffles, no LDS).
+template <typename T>
+__device__ __forceinline__ T wave_incl_scan(T v) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const T t = __shfl_up(v, off, 64);
+    if (lane >= off) v += t;
+  }
+  return v;
+}
+
 // Exclusive scan of v[0..n) into out[0..n] (out[n] = total) by 1024 threads,
-// each owning a contiguous chunk; part[] holds 1024 partial sums.
+// each owning a contiguous chunk: chunk sums are scanned within each wave by
+// shuffles, the 16 wave totals by one wave; wsum[] holds 16 values.
 template <typename T, typename S>
-__device__ void block_exscan_chunks(const S* v, int32_t n, T* out, T* part) {
-  const int tid = threadIdx.x;
+__device__ void block_exscan_chunks(const S* v, int32_t n, T* out, T* wsum) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int32_t per = (n + kSmallThreads - 1) / kSmallThreads;
   const int32_t lo = min(n, tid * per), hi = min(n, lo + per);
   T sum = 0;
   for (int32_t i = lo; i < hi; ++i) sum += (T)v[i];
-  part[tid] = sum;
+  const T incl = wave_incl_scan<T>(sum);
+  if (lane == 63) wsum[wave] = incl;
   __syncthreads();
-  for (int off = 1; off < kSmallThreads; off <<= 1) {
-    const T add = tid >= off ? part[tid - off] : (T)0;
-    __syncthreads();
-    part[tid] += add;
-    __syncthreads();
+  if (wave == 0) {
+    T w = lane < kSmallThreads / 64 ? wsum[lane] : (T)0;
+    w = wave_incl_scan<T>(w);
+    if (lane < kSmallThreads / 64) wsum[lane] = w;
   }
-  T run = part[tid] - sum;
+  __syncthreads();
+  T run = incl - sum + (wave > 0 ? wsum[wave - 1] : (T)0);
   for (int32_t i = lo; i < hi; ++i) {
     const T x = (T)v[i];
     out[i] = run;
     run += x;
   }
-  if (tid == kSmallThreads - 1) out[n] = part[kSmallThreads - 1];
+  if (tid == kSmallThreads - 1) out[n] = wsum[kSmallThreads / 64 - 1];
   __syncthreads();
 }
 

@@ -1,8 +1,12 @@
-// Grouped persistent launch (C ABI): many static products in one launch of
-// the row-wise kernel. The problem table is double-buffered: slot s has a
-// pinned host staging copy, a device copy and an event recorded after the
-// kernel that read it; a call fills the free slot, then replays the captured
-// graph [copy host table s -> device table s; persistent kernel on table s].
+// Grouped launch (C ABI): many static products in one launch of the row-wise
+// kernel, one workgroup per work unit of all problems.
+//
+// Up to group_inline_max() problems travel in the kernel arguments: the call
+// builds the table on the host and replays a captured one-node graph after
+// updating that node's arguments and grid. Larger groups write the table into
+// a pinned staging slot, copy it to the device and launch on it; the slots
+// form a ring of kSlots, each reused only after the launch that read it has
+// completed (an event per slot).
 #include <hip/hip_runtime.h>
 
 #include <cstdlib>
@@ -11,13 +15,14 @@
 #include <new>
 #include <string>
 #include <tuple>
+#include <vector>
 
 #include "internal.h"
 
 using namespace spmm;
 
 namespace {
-constexpr size_t kHeaderBytes = 256;  // {count, total units}, padded so descriptors stay aligned
+constexpr int kSlots = 4;
 }
 
 struct spmm_group_s {
@@ -25,19 +30,27 @@ struct spmm_group_s {
   int device = 0;
   size_t desc_bytes = 0;
   size_t table_bytes = 0;
-  uint8_t* host[2] = {nullptr, nullptr};  // pinned staging
-  uint8_t* dev[2] = {nullptr, nullptr};
-  hipEvent_t done[2] = {nullptr, nullptr};
-  bool pending[2] = {false, false};
+  uint8_t* host[kSlots] = {};  // pinned staging
+  uint8_t* dev[kSlots] = {};
+  hipEvent_t done[kSlots] = {};
+  bool pending[kSlots] = {};
   int slot = 0;
+  std::vector<uint8_t> args;    // argument-form table
   hipStream_t capture = nullptr;  // private stream used only to capture graphs
-  std::map<std::tuple<int, int, int, int>, hipGraphExec_t> graphs;  // (x, y, b, slot)
-  std::map<std::tuple<int, int, int>, int32_t> grids;               // (x, y, b)
+  struct Graph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipGraphNode_t node = nullptr;
+  };
+  std::map<std::tuple<int, int, int>, Graph> graphs;  // (x, y, b)
 };
 
 static void destroy_group(spmm_group_s* g) {
-  for (auto& kv : g->graphs) (void)hipGraphExecDestroy(kv.second);
-  for (int s = 0; s < 2; ++s) {
+  for (auto& kv : g->graphs) {
+    if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+    if (kv.second.graph) (void)hipGraphDestroy(kv.second.graph);
+  }
+  for (int s = 0; s < kSlots; ++s) {
     if (g->pending[s] && g->done[s]) (void)hipEventSynchronize(g->done[s]);
     if (g->done[s]) (void)hipEventDestroy(g->done[s]);
     if (g->host[s]) (void)hipHostFree(g->host[s]);
@@ -52,36 +65,34 @@ static bool use_graphs() {
   return !(e && std::string(e) == "0");
 }
 
-// Enqueues [table copy, grouped kernel] for slot s directly on `stream`.
-static spmm_status_t enqueue_direct(spmm_group_s* g, int s, spmm_dtype_t x, spmm_dtype_t y, int32_t b, int32_t grid,
-                                    hipStream_t stream) {
-  SPMM_HIP(hipMemcpyAsync(g->dev[s], g->host[s], g->table_bytes, hipMemcpyHostToDevice, stream));
-  return launch_spmm_row_grouped(x, y, b, g->dev[s] + kHeaderBytes, (const int32_t*)g->dev[s], grid, stream);
-}
-
-static spmm_status_t graph_for(spmm_group_s* g, int s, spmm_dtype_t x, spmm_dtype_t y, int32_t b, int32_t grid,
-                               hipGraphExec_t* out) {
-  const auto key = std::make_tuple((int)x, (int)y, (int)b, s);
+// The captured one-node graph of the argument form for a dtype class: captured
+// once with the current arguments, then only its node parameters change.
+static spmm_status_t graph_for(spmm_group_s* g, spmm_dtype_t x, spmm_dtype_t y, int32_t b, int32_t total,
+                               spmm_group_s::Graph** out) {
+  const auto key = std::make_tuple((int)x, (int)y, (int)b);
   auto it = g->graphs.find(key);
   if (it != g->graphs.end()) {
-    *out = it->second;
+    *out = &it->second;
     return SPMM_OK;
   }
+  spmm_group_s::Graph gr;
   SPMM_HIP(hipStreamBeginCapture(g->capture, hipStreamCaptureModeThreadLocal));
-  spmm_status_t st = enqueue_direct(g, s, x, y, b, grid, g->capture);
-  hipGraph_t graph = nullptr;
-  hipError_t e = hipStreamEndCapture(g->capture, &graph);
+  spmm_status_t st = launch_spmm_row_grouped_args(x, y, b, g->args.data(), total, g->capture);
+  hipError_t e = hipStreamEndCapture(g->capture, &gr.graph);
   if (st != SPMM_OK) {
-    if (graph) (void)hipGraphDestroy(graph);
+    if (gr.graph) (void)hipGraphDestroy(gr.graph);
     return st;
   }
   if (e != hipSuccess) return fail_hip(e, "hipStreamEndCapture");
-  hipGraphExec_t exec = nullptr;
-  e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-  (void)hipGraphDestroy(graph);
-  if (e != hipSuccess) return fail_hip(e, "hipGraphInstantiate");
-  g->graphs[key] = exec;
-  *out = exec;
+  size_t nodes = 1;
+  e = hipGraphGetNodes(gr.graph, &gr.node, &nodes);
+  if (e == hipSuccess && nodes != 1) e = hipErrorInvalidValue;
+  if (e == hipSuccess) e = hipGraphInstantiate(&gr.exec, gr.graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(gr.graph);
+    return fail_hip(e, "grouped graph");
+  }
+  *out = &(g->graphs[key] = gr);
   return SPMM_OK;
 }
 
@@ -96,18 +107,23 @@ spmm_status_t spmm_group_create(int32_t max_problems, spmm_group_t* out) {
   if (!g) return fail(SPMM_ERR_OOM, "host allocation failed");
   g->max_problems = max_problems;
   g->desc_bytes = row_problem_size();
-  g->table_bytes = kHeaderBytes + (size_t)max_problems * g->desc_bytes;
+  g->table_bytes = (size_t)max_problems * g->desc_bytes;
   spmm_status_t st = SPMM_OK;
+  try {
+    g->args.assign(group_args_bytes(), 0);
+  } catch (...) {
+    st = fail(SPMM_ERR_OOM, "host allocation failed");
+  }
   hipError_t e = hipGetDevice(&g->device);
-  if (e != hipSuccess) st = fail_hip(e, "hipGetDevice");
-  for (int s = 0; s < 2 && st == SPMM_OK; ++s) {
+  if (st == SPMM_OK && e != hipSuccess) st = fail_hip(e, "hipGetDevice");
+  const bool table = max_problems > group_inline_max();
+  for (int s = 0; s < kSlots && st == SPMM_OK && table; ++s) {
     if ((e = hipHostMalloc((void**)&g->host[s], g->table_bytes, hipHostMallocDefault)) != hipSuccess)
       st = fail_hip(e, "hipHostMalloc");
     else if ((e = hipMalloc((void**)&g->dev[s], g->table_bytes)) != hipSuccess)
       st = fail_hip(e, "hipMalloc");
     else if ((e = hipEventCreateWithFlags(&g->done[s], hipEventDisableTiming)) != hipSuccess)
       st = fail_hip(e, "hipEventCreate");
-    if (st == SPMM_OK) std::memset(g->host[s], 0, g->table_bytes);
   }
   if (st == SPMM_OK && (e = hipStreamCreateWithFlags(&g->capture, hipStreamNonBlocking)) != hipSuccess)
     st = fail_hip(e, "hipStreamCreate");
@@ -133,6 +149,7 @@ spmm_status_t spmm_group_run(spmm_group_t g, int32_t count, const spmm_plan_t* p
   if (!p0) return fail(SPMM_ERR_INVALID_ARG, "plan 0 is NULL");
   if (!plan_uses_row_kernel(p0) || p0->w == SPMM_FP8_E4M3)
     return fail(SPMM_ERR_UNSUPPORTED, "grouped launch needs b = 16 or 32 with 16-bit W and X");
+  int32_t used = 0;
   for (int32_t i = 0; i < count; ++i) {
     const spmm_plan_s* p = plans[i];
     if (!p) return fail(SPMM_ERR_INVALID_ARG, "a plan is NULL");
@@ -145,22 +162,24 @@ spmm_status_t spmm_group_run(spmm_group_t g, int32_t count, const spmm_plan_t* p
     if ((st = check_dense(X[i], ldx[i], n[i], dtype_bytes(p->x), "X")) != SPMM_OK) return st;
     if ((st = check_dense(Y[i], ldy[i], n[i], dtype_bytes(p->y), "Y")) != SPMM_OK) return st;
     if (p->k * ldx[i] * 2 >= (int64_t)INT32_MAX) return fail(SPMM_ERR_UNSUPPORTED, "X larger than 2 GiB");
+    ++used;
   }
+  if (used == 0) return SPMM_OK;
+  const bool inline_table = used <= group_inline_max();
   const int s = g->slot;
-  if (g->pending[s]) {
+  if (!inline_table && g->pending[s]) {
     SPMM_HIP(hipEventSynchronize(g->done[s]));
     g->pending[s] = false;
   }
-  uint8_t* tab = g->host[s];
+  // descriptors, in call order, with the prefix of their work units
   int64_t total = 0;
-  int32_t used = 0;
+  int32_t k = 0;
   for (int32_t i = 0; i < count; ++i) {
     if (n[i] == 0) continue;
     const spmm_plan_s* p = plans[i];
-    // the tuned variant if any, else the widest tile n fills at least half of
-    // (the group as a whole fills the chip, so no narrowing for occupancy)
+    // the tuned variant if any, else the rule on n
     int32_t ns = plan_variant(p, n[i]);
-    if (ns != 2 && ns != 4 && ns != 8) ns = n[i] > 64 ? 8 : (n[i] > 32 ? 4 : 2);
+    if (ns != 2 && ns != 4 && ns != 8) ns = default_ns(n[i]);
     RunArgs a{};
     a.plan.m = (int32_t)p->m;
     a.plan.k = (int32_t)p->k;
@@ -176,35 +195,35 @@ spmm_status_t spmm_group_run(spmm_group_t g, int32_t count, const spmm_plan_t* p
     a.n = (int32_t)n[i];
     a.relu = relu && relu[i];
     a.ns = ns;
-    fill_row_problem(tab + kHeaderBytes + (size_t)used * g->desc_bytes, a, p->pb.row_ptr, p->pb.col_idx,
-                     (int32_t)total);
+    void* dst = inline_table ? group_args_problem(g->args.data(), k) : (void*)(g->host[s] + (size_t)k * g->desc_bytes);
+    fill_row_problem(dst, a, p->pb.row_ptr, p->pb.col_idx, (int32_t)total);
     total += ceil_div(p->mb, 4) * ceil_div(n[i], 16 * ns);
     if (total >= (int64_t)INT32_MAX) return fail(SPMM_ERR_UNSUPPORTED, "too many work units in one group");
-    ++used;
-  }
-  if (used == 0) return SPMM_OK;
-  ((int32_t*)tab)[0] = used;
-  ((int32_t*)tab)[1] = (int32_t)total;
-  const auto gk = std::make_tuple((int)p0->x, (int)p0->y, (int)p0->b);
-  auto git = g->grids.find(gk);
-  int32_t grid;
-  if (git == g->grids.end()) {
-    grid = row_grouped_grid(p0->x, p0->y, p0->b);
-    g->grids[gk] = grid;
-  } else {
-    grid = git->second;
+    ++k;
   }
   hipStream_t strm = (hipStream_t)stream;
-  if (use_graphs()) {
-    hipGraphExec_t exec = nullptr;
-    if ((st = graph_for(g, s, p0->x, p0->y, p0->b, grid, &exec)) != SPMM_OK) return st;
-    SPMM_HIP(hipGraphLaunch(exec, strm));
-  } else {
-    if ((st = enqueue_direct(g, s, p0->x, p0->y, p0->b, grid, strm)) != SPMM_OK) return st;
+  if (inline_table) {
+    group_args_header(g->args.data(), used, (int32_t)total);
+    if (!use_graphs()) return launch_spmm_row_grouped_args(p0->x, p0->y, p0->b, g->args.data(), (int32_t)total, strm);
+    spmm_group_s::Graph* gr = nullptr;
+    if ((st = graph_for(g, p0->x, p0->y, p0->b, (int32_t)total, &gr)) != SPMM_OK) return st;
+    void* params[1] = {g->args.data()};
+    hipKernelNodeParams kp{};
+    kp.func = const_cast<void*>(row_grouped_args_kernel(p0->x, p0->y, p0->b));
+    kp.gridDim = dim3((unsigned)total);
+    kp.blockDim = dim3(256);
+    kp.sharedMemBytes = 0;
+    kp.kernelParams = params;
+    kp.extra = nullptr;
+    SPMM_HIP(hipGraphExecKernelNodeSetParams(gr->exec, gr->node, &kp));
+    SPMM_HIP(hipGraphLaunch(gr->exec, strm));
+    return SPMM_OK;
   }
+  SPMM_HIP(hipMemcpyAsync(g->dev[s], g->host[s], (size_t)used * g->desc_bytes, hipMemcpyHostToDevice, strm));
+  if ((st = launch_spmm_row_grouped(p0->x, p0->y, p0->b, g->dev[s], used, (int32_t)total, strm)) != SPMM_OK) return st;
   SPMM_HIP(hipEventRecord(g->done[s], strm));
   g->pending[s] = true;
-  g->slot = s ^ 1;
+  g->slot = (s + 1) % kSlots;
   return SPMM_OK;
 }
 

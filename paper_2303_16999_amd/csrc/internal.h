@@ -37,6 +37,6 @@ spmm_status_t run_plan(const spmm_plan_s* p, int64_t n, const void* X, int64_t l
                        int32_t variant, bool relu, hipStream_t stream);
 spmm_status_t check_dense(const void* p, int64_t ld, int64_t n, int elem, const char* name);
 spmm_status_t check_device(int device);
-int32_t default_ns(int64_t n, int64_t mb);
+int32_t default_ns(int64_t n);
 
 }  // namespace spmm

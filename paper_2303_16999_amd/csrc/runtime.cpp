@@ -158,14 +158,10 @@ spmm_status_t launch_spmm(const RunArgs& a0, hipStream_t s) {
 }
 
 // Column tiles of 16 per wave for the row-wise kernel: the widest tile that
-// the n columns fill at least half of, narrowed while the launch would give
-// the chip fewer than two workgroups (eight waves) per CU.
-int32_t default_ns(int64_t n, int64_t mb) {
-  int32_t ns = n > 64 ? 8 : (n > 32 ? 4 : 2);
-  const int64_t target = 2 * (int64_t)device_cu_count();
-  while (ns > 2 && ceil_div(mb, 4) * ceil_div(n, 16 * ns) < target) ns /= 2;
-  return ns;
-}
+// the n columns fill at least half of. (Measured on MI355X, the widest tile is
+// also fastest when a launch has only one workgroup per CU: narrower tiles
+// re-read the weights more often than the extra occupancy pays back.)
+int32_t default_ns(int64_t n) { return n > 64 ? 8 : (n > 32 ? 4 : 2); }
 
 // Dynamic encode: the one-workgroup builder where it applies, unless
 // SPMM_DYN_BUILDER=multi asks for the multi-kernel one (for comparisons).
@@ -322,7 +318,7 @@ spmm_status_t run_plan(const spmm_plan_s* p, int64_t n, const void* X, int64_t l
   if (plan_uses_row_kernel(p)) {
     a.W = p->values_csr;
     a.scales = p->scales_csr;
-    a.ns = variant ? variant : default_ns(n, p->mb);
+    a.ns = variant ? variant : default_ns(n);
     return launch_spmm_row(a, p->pb.row_ptr, p->pb.col_idx, stream);
   }
   if (relu) return fail(SPMM_ERR_UNSUPPORTED, "fused ReLU needs a block-CSR kernel");
@@ -686,7 +682,7 @@ spmm_status_t spmm_run_dynamic(spmm_dyn_t h, const int32_t* nnzb_dev, const int3
     a.yt = h->y;
     a.status = h->status;
     a.nnz = h->max_nnzb;
-    a.ns = h->b < 16 ? 0 : default_ns(n, h->mb);
+    a.ns = h->b < 16 ? 0 : default_ns(n);
     if (h->b < 16) return launch_spmm_small(a, h->pb.row_ptr, h->pb.col_idx, s);
     return launch_spmm_row(a, h->pb.row_ptr, h->pb.col_idx, s);
   }

@@ -291,38 +291,6 @@ __global__ __launch_bounds__(256) void k_spmm_row(Params prm) {
   row_tile<XT, WT, YT, B, NS>(p, r, n0, lane);
 }
 
-// Grouped persistent launch: the descriptor table holds `count` problems
-// (header[0]) and `total` work units (header[1]), both read from device
-// memory so that one captured launch serves any table written before it.
-// Workgroup w takes logical units w, w + grid, ... in the XCD-aware order;
-// a unit is (problem, group of 4 block rows, column tile of 16*ns).
-template <typename XT, typename WT, typename YT, int B>
-__global__ __launch_bounds__(256, B == 16 ? 4 : 3) void k_spmm_row_grouped(const RowProblem* __restrict__ probs,
-                                                          const int32_t* __restrict__ header) {
-  const int32_t count = uniform(header[0]), total = uniform(header[1]);
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int32_t u = blockIdx.x; u < total; u += gridDim.x) {
-    const int32_t unit = xcd_unit(u, total);
-    int32_t lo = 0, hi = count - 1;  // last problem with unit_begin <= unit
-    while (lo < hi) {
-      const int32_t mid = (lo + hi + 1) >> 1;
-      if (uniform(probs[mid].unit_begin) <= unit) lo = mid;
-      else hi = mid - 1;
-    }
-    const RowProblem p = probs[lo];  // by value: the fields live in scalar registers
-    const int32_t local = unit - uniform(p.unit_begin);
-    const int32_t rgroups = (uniform(p.mb) + kRowsPerWg - 1) / kRowsPerWg;
-    const int32_t ns = uniform(p.ns);
-    const int32_t rg = local % rgroups;
-    const int32_t r = rg * kRowsPerWg + wave;
-    if (r >= p.mb) continue;
-    const int32_t n0 = (local / rgroups) * (16 * ns);
-    if (ns == 8) row_tile<XT, WT, YT, B, 8>(p, r, n0, lane);
-    else if (ns == 4) row_tile<XT, WT, YT, B, 4>(p, r, n0, lane);
-    else row_tile<XT, WT, YT, B, 2>(p, r, n0, lane);
-  }
-}
-
 inline RowProblem row_problem(const RunArgs& a, const int32_t* row_ptr, const int32_t* col_idx) {
   RowProblem p{};
   p.row_ptr = row_ptr;
@@ -361,15 +329,6 @@ spmm_status_t launch_row(const RunArgs& a, const int32_t* row_ptr, const int32_t
   else if (ns == 4) hipLaunchKernelGGL((k_spmm_row<XT, WT, YT, B, 4>), dim3((unsigned)units), dim3(256), 0, stream, prm);
   else if (ns == 2) hipLaunchKernelGGL((k_spmm_row<XT, WT, YT, B, 2>), dim3((unsigned)units), dim3(256), 0, stream, prm);
   else return fail(SPMM_ERR_INVALID_ARG, "column tile variant must be 2, 4 or 8");
-  SPMM_HIP(hipGetLastError());
-  return SPMM_OK;
-}
-
-template <typename XT, typename WT, typename YT, int B>
-spmm_status_t launch_row_grouped(const RowProblem* probs_dev, const int32_t* header_dev, int32_t grid,
-                                 hipStream_t stream) {
-  hipLaunchKernelGGL((k_spmm_row_grouped<XT, WT, YT, B>), dim3((unsigned)grid), dim3(256), 0, stream, probs_dev,
-                     header_dev);
   SPMM_HIP(hipGetLastError());
   return SPMM_OK;
 }

@@ -1,0 +1,137 @@
+// Grouped launch of the row-wise kernel: one launch runs the work units of many
+// problems listed in a table, passed in the kernel arguments (up to 32
+// problems) or in device memory.
+#include "spmm_row.h"
+
+namespace spmm {
+namespace row {
+
+constexpr int kInlineProblems = 32;
+
+// Problem table passed in the kernel arguments (at most kInlineProblems
+// problems, 3.3 KB): no copy precedes the launch.
+struct GroupArgs {
+  int32_t count, total;
+  int32_t pad[2];
+  RowProblem probs[kInlineProblems];
+};
+
+// One workgroup per work unit of the group, in the XCD-aware order; a unit is
+// (problem, group of 4 block rows, column tile of 16*ns). The problem of a
+// unit is the last one whose first unit is at or before it.
+template <typename XT, typename WT, typename YT, int B>
+__device__ __forceinline__ void group_unit(const RowProblem* __restrict__ probs, int32_t count, int32_t total) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int32_t unit = xcd_unit(blockIdx.x, total);
+  int32_t lo = 0, hi = count - 1;
+  while (lo < hi) {
+    const int32_t mid = (lo + hi + 1) >> 1;
+    if (uniform(probs[mid].unit_begin) <= unit) lo = mid;
+    else hi = mid - 1;
+  }
+  const RowProblem p = probs[lo];  // by value: the fields live in scalar registers
+  const int32_t local = unit - uniform(p.unit_begin);
+  const int32_t rgroups = (uniform(p.mb) + kRowsPerWg - 1) / kRowsPerWg;
+  const int32_t ns = uniform(p.ns);
+  const int32_t r = (local % rgroups) * kRowsPerWg + wave;
+  if (r >= p.mb) return;
+  const int32_t n0 = (local / rgroups) * (16 * ns);
+  if (ns == 8) row_tile<XT, WT, YT, B, 8>(p, r, n0, lane);
+  else if (ns == 4) row_tile<XT, WT, YT, B, 4>(p, r, n0, lane);
+  else row_tile<XT, WT, YT, B, 2>(p, r, n0, lane);
+}
+
+// Table in device memory (any number of problems).
+template <typename XT, typename WT, typename YT, int B>
+__global__ __launch_bounds__(256, B == 16 ? 4 : 3) void k_spmm_row_grouped(const RowProblem* __restrict__ probs,
+                                                                          int32_t count, int32_t total) {
+  group_unit<XT, WT, YT, B>(probs, count, total);
+}
+
+// Table in the kernel arguments.
+template <typename XT, typename WT, typename YT, int B>
+__global__ __launch_bounds__(256, B == 16 ? 4 : 3) void k_spmm_row_grouped_args(GroupArgs args) {
+  group_unit<XT, WT, YT, B>(args.probs, args.count, args.total);
+}
+
+}  // namespace row
+}  // namespace spmm
+
+namespace spmm {
+
+namespace {
+template <typename XT, typename YT>
+const void* args_kernel_b(int32_t b) {
+  if (b == 16) return reinterpret_cast<const void*>(&row::k_spmm_row_grouped_args<XT, XT, YT, 16>);
+  return reinterpret_cast<const void*>(&row::k_spmm_row_grouped_args<XT, XT, YT, 32>);
+}
+
+template <typename XT, typename YT>
+void table_launch_b(int32_t b, const row::RowProblem* probs, int32_t count, int32_t total, hipStream_t s) {
+  if (b == 16)
+    hipLaunchKernelGGL((row::k_spmm_row_grouped<XT, XT, YT, 16>), dim3((unsigned)total), dim3(256), 0, s, probs, count,
+                       total);
+  else
+    hipLaunchKernelGGL((row::k_spmm_row_grouped<XT, XT, YT, 32>), dim3((unsigned)total), dim3(256), 0, s, probs, count,
+                       total);
+}
+}  // namespace
+
+int32_t group_inline_max() { return row::kInlineProblems; }
+size_t group_args_bytes() { return sizeof(row::GroupArgs); }
+size_t row_problem_size() { return sizeof(row::RowProblem); }
+
+void group_args_header(void* args, int32_t count, int32_t total) {
+  row::GroupArgs* g = (row::GroupArgs*)args;
+  g->count = count;
+  g->total = total;
+  g->pad[0] = g->pad[1] = 0;
+}
+
+void* group_args_problem(void* args, int32_t i) { return &((row::GroupArgs*)args)->probs[i]; }
+
+// Fills one problem descriptor (host side; layout shared with the kernels).
+void fill_row_problem(void* dst, const RunArgs& a, const int32_t* row_ptr, const int32_t* col_idx,
+                      int32_t unit_begin) {
+  row::RowProblem p = row::row_problem(a, row_ptr, col_idx);
+  p.unit_begin = unit_begin;
+  *(row::RowProblem*)dst = p;
+}
+
+// Kernel of the argument-table form for a dtype class (16-bit W = X), or nullptr.
+const void* row_grouped_args_kernel(spmm_dtype_t xt, spmm_dtype_t yt, int32_t b) {
+  using bf = __bf16;
+  if (b != 16 && b != 32) return nullptr;
+  if (xt == SPMM_F16) return yt == SPMM_F32 ? args_kernel_b<_Float16, float>(b) : args_kernel_b<_Float16, _Float16>(b);
+  if (xt == SPMM_BF16) return yt == SPMM_F32 ? args_kernel_b<bf, float>(b) : args_kernel_b<bf, bf>(b);
+  return nullptr;
+}
+
+spmm_status_t launch_spmm_row_grouped_args(spmm_dtype_t xt, spmm_dtype_t yt, int32_t b, const void* args, int32_t total,
+                                           hipStream_t s) {
+  const void* fn = row_grouped_args_kernel(xt, yt, b);
+  if (!fn) return fail(SPMM_ERR_UNSUPPORTED, "grouped launch needs 16-bit X and b = 16 or 32");
+  void* params[1] = {const_cast<void*>(args)};
+  SPMM_HIP(hipLaunchKernel(fn, dim3((unsigned)total), dim3(256), params, 0, s));
+  return SPMM_OK;
+}
+
+spmm_status_t launch_spmm_row_grouped(spmm_dtype_t xt, spmm_dtype_t yt, int32_t b, const void* probs_dev,
+                                      int32_t count, int32_t total, hipStream_t s) {
+  using bf = __bf16;
+  const row::RowProblem* pr = (const row::RowProblem*)probs_dev;
+  if (b != 16 && b != 32) return fail(SPMM_ERR_UNSUPPORTED, "grouped launch handles block sizes 16 and 32");
+  if (xt == SPMM_F16) {
+    if (yt == SPMM_F32) table_launch_b<_Float16, float>(b, pr, count, total, s);
+    else table_launch_b<_Float16, _Float16>(b, pr, count, total, s);
+  } else if (xt == SPMM_BF16) {
+    if (yt == SPMM_F32) table_launch_b<bf, float>(b, pr, count, total, s);
+    else table_launch_b<bf, bf>(b, pr, count, total, s);
+  } else {
+    return fail(SPMM_ERR_UNSUPPORTED, "grouped launch needs 16-bit X");
+  }
+  SPMM_HIP(hipGetLastError());
+  return SPMM_OK;
+}
+
+}  // namespace spmm

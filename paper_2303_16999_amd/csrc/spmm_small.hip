@@ -278,6 +278,129 @@ __global__ __launch_bounds__(256) void k_spmm_small(SParams p) {
   }
 }
 
+// ------------------------------------------------------------------ b = 4 / 8 on MFMA
+// With 16-bit weights and X, b = 4 and 8 run on 16x16x32 MFMAs: 32 / b blocks
+// of one block row fill the 32 k slots of one instruction (lane group g takes
+// 8 / b of them), the block row's b rows occupy the first b of the 16 A rows
+// (the rest are zero). Per lane group the B operand is 8 X rows (the k rows of
+// its blocks) x 8 columns, loaded as 16-byte rows and transposed with v_perm,
+// so that MFMA tile s covers physical columns 8j + s as in the row-wise
+// kernel. Half (b = 8) or a quarter (b = 4) of each MFMA is useful work, which
+// still leaves the matrix cores far from being the limit: these block sizes
+// are bound by the X reads (b FLOPs per byte from L2).
+typedef _Float16 half8_t __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+
+template <typename XT> struct Mfma;
+template <> struct Mfma<_Float16> {
+  static __device__ __forceinline__ float4_t k32(u32x4 a, u32x4 b, float4_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(half8_t, a), __builtin_bit_cast(half8_t, b), c, 0, 0, 0);
+  }
+};
+template <> struct Mfma<__bf16> {
+  static __device__ __forceinline__ float4_t k32(u32x4 a, u32x4 b, float4_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_t, a), __builtin_bit_cast(bf16x8_t, b), c, 0, 0, 0);
+  }
+};
+
+template <typename XT, typename YT, int B>
+__global__ __launch_bounds__(256) void k_spmm_small_mfma(SParams p) {
+  static_assert(B == 4 || B == 8, "MFMA form of the small block sizes");
+  constexpr int BPM = 32 / B;  // blocks per MFMA
+  constexpr int BPG = 8 / B;   // blocks per lane group
+  if (p.status && *p.status) return;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int g = lane >> 4, j = lane & 15;
+  const int32_t unit = xcd_unit(blockIdx.x, p.num_units);
+  const int32_t rgroups = (p.mb + kRowsPerWg - 1) / kRowsPerWg;
+  const int32_t r = (unit % rgroups) * kRowsPerWg + wave;
+  const int32_t n0 = (unit / rgroups) * 128;
+  if (r >= p.mb) return;
+  __amdgpu_buffer_rsrc_t xr = __builtin_amdgcn_make_buffer_rsrc((void*)p.X, (short)0, (int)p.x_bytes, 0x00020000);
+  const uint8_t* __restrict__ Wb = (const uint8_t*)p.W;
+  const uint32_t lane_off = (uint32_t)((n0 + 8 * j) * 2);
+  float4_t acc[8];
+#pragma unroll
+  for (int s = 0; s < 8; ++s) acc[s] = float4_t{0.f, 0.f, 0.f, 0.f};
+  const int32_t q_lo = uniform(p.row_ptr[r]), q_hi = uniform(p.row_ptr[r + 1]);
+  for (int32_t q = q_lo; q < q_hi; q += BPM) {
+    // this lane group's blocks: q + g*BPG + t
+    uint32_t adw[4] = {0u, 0u, 0u, 0u};
+    uint32_t rows[8][4];
+#pragma unroll
+    for (int t = 0; t < BPG; ++t) {
+      const int32_t qb = q + g * BPG + t;
+      const bool ok = qb < q_hi;
+      const int32_t c = ok ? p.col_idx[qb] : 0;
+      const int64_t qv = ok ? (p.w_index ? (int64_t)p.w_index[qb] : (int64_t)qb) : 0;
+      if (ok && j < B) {
+        // row j of block qb: B 16-bit weights
+        const uint8_t* src = Wb + qv * (B * B * 2) + j * (B * 2);
+        if constexpr (B == 8) {
+          const u32x4 w = *(const u32x4*)src;
+          adw[0] = w[0]; adw[1] = w[1]; adw[2] = w[2]; adw[3] = w[3];
+        } else {
+          const u32x2 w = *(const u32x2*)src;
+          adw[2 * t] = w.x;
+          adw[2 * t + 1] = w.y;
+        }
+      }
+#pragma unroll
+      for (int e = 0; e < B; ++e) {
+        const int32_t krow = c * B + e;
+        const uint32_t off = (ok && krow < p.k) ? (uint32_t)((int64_t)krow * p.ldx * 2) + lane_off : kOOB;
+        const u32x4 v = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(xr, off, 0, 0));
+#pragma unroll
+        for (int d = 0; d < 4; ++d) rows[t * B + e][d] = v[d];
+      }
+    }
+    const u32x4 a = {adw[0], adw[1], adw[2], adw[3]};
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+      const uint32_t sel = (s & 1) ? 0x07060302u : 0x05040100u;
+      u32x4 bv;
+#pragma unroll
+      for (int d = 0; d < 4; ++d) bv[d] = __builtin_amdgcn_perm(rows[2 * d + 1][s >> 1], rows[2 * d][s >> 1], sel);
+      acc[s] = Mfma<XT>::k32(a, bv, acc[s]);
+    }
+  }
+  // epilogue: lane (g, j) holds rows 4g + i (valid below B), columns n0 + 8j .. +8
+  if (4 * g >= B) return;
+  if (p.relu) {
+#pragma unroll
+    for (int s = 0; s < 8; ++s)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) acc[s][i] = acc[s][i] > 0.f ? acc[s][i] : 0.f;
+  }
+  YT* __restrict__ Y = (YT*)p.Y;
+  const int32_t col0 = n0 + 8 * j;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int64_t row = (int64_t)r * B + 4 * g + i;
+    if (row >= p.m) continue;
+    YT* dst = Y + row * p.ldy + col0;
+    if (col0 + 8 <= p.n) {
+      if constexpr (sizeof(YT) == 4) {
+        *(float4_t*)dst = float4_t{acc[0][i], acc[1][i], acc[2][i], acc[3][i]};
+        *(float4_t*)(dst + 4) = float4_t{acc[4][i], acc[5][i], acc[6][i], acc[7][i]};
+      } else {
+        uint32_t o[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          o[e] = (uint32_t)Num<YT>::store(acc[2 * e][i]) | ((uint32_t)Num<YT>::store(acc[2 * e + 1][i]) << 16);
+        *(u32x4*)dst = u32x4{o[0], o[1], o[2], o[3]};
+      }
+    } else {
+#pragma unroll
+      for (int s = 0; s < 8; ++s)
+        if (col0 + s < p.n) {
+          if constexpr (sizeof(YT) == 4) dst[s] = acc[s][i];
+          else ((uint16_t*)dst)[s] = Num<YT>::store(acc[s][i]);
+        }
+    }
+  }
+}
+
 template <typename XT, typename WT, typename YT, int B, int V>
 spmm_status_t launch_small(const RunArgs& a, const int32_t* row_ptr, const int32_t* col_idx, hipStream_t s) {
   SParams p;
@@ -299,11 +422,16 @@ spmm_status_t launch_small(const RunArgs& a, const int32_t* row_ptr, const int32
   const int64_t xb = (int64_t)a.plan.k * a.ldx * (int64_t)sizeof(XT);
   if (xb >= (int64_t)INT32_MAX) return fail(SPMM_ERR_UNSUPPORTED, "X larger than 2 GiB is not supported");
   p.x_bytes = (uint32_t)xb;
-  const int64_t units = ceil_div(a.plan.mb, kRowsPerWg) * ceil_div(a.n, 64 * V);
+  constexpr bool kMfma = (B == 4 || B == 8) && sizeof(XT) == 2 && __is_same(XT, WT);
+  const int64_t tile = kMfma ? 128 : 64 * V;
+  const int64_t units = ceil_div(a.plan.mb, kRowsPerWg) * ceil_div(a.n, tile);
   if (units == 0) return SPMM_OK;
   if (units > (int64_t)INT32_MAX) return fail(SPMM_ERR_UNSUPPORTED, "too many work units");
   p.num_units = (int32_t)units;
-  hipLaunchKernelGGL((k_spmm_small<XT, WT, YT, B, V>), dim3((unsigned)units), dim3(256), 0, s, p);
+  if constexpr (kMfma)
+    hipLaunchKernelGGL((k_spmm_small_mfma<XT, YT, B>), dim3((unsigned)units), dim3(256), 0, s, p);
+  else
+    hipLaunchKernelGGL((k_spmm_small<XT, WT, YT, B, V>), dim3((unsigned)units), dim3(256), 0, s, p);
   SPMM_HIP(hipGetLastError());
   return SPMM_OK;
 }
@@ -313,6 +441,7 @@ spmm_status_t launch_small(const RunArgs& a, const int32_t* row_ptr, const int32
 template <typename XT, typename WT, typename YT, int B>
 spmm_status_t small_v(const RunArgs& a, const int32_t* rp, const int32_t* ci, hipStream_t s) {
   if constexpr (sizeof(XT) == 4) return launch_small<XT, WT, YT, B, 4>(a, rp, ci, s);
+  else if constexpr ((B == 4 || B == 8) && __is_same(XT, WT)) return launch_small<XT, WT, YT, B, 8>(a, rp, ci, s);
   else {
     const int v = (a.ns == 4 || a.ns == 8) ? a.ns : (a.n <= 256 ? 4 : 8);
     if (v == 4) return launch_small<XT, WT, YT, B, 4>(a, rp, ci, s);

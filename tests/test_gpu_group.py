@@ -128,3 +128,48 @@ def test_group_rejects_mixed_plans():
     with pytest.raises(spmm.SpmmError) as e:
         g.run([pa] * 5, [Xa] * 5, [a.new_Y() for _ in range(5)])
     assert e.value.status == spmm.ERR_INVALID_ARG
+
+
+def test_group_device_table_form_matches_single_launches():
+    """More problems than fit in the kernel arguments: the table goes through device memory."""
+    b = 16
+    cases = [Case((3 + i % 5) * b, (4 + i % 3) * b + i % 2, 1 + (i * 37) % 150, b, 0.3, w="f16", seed=200 + i)
+             for i in range(40)]
+    plans, Xs, singles = [], [], []
+    for c in cases:
+        plan, Ys = c.run_static()
+        plans.append(plan)
+        Xs.append(c.device_inputs()[1])
+        singles.append(Ys[:, : c.n].clone())
+    g = spmm.Group(64)
+    for rep in range(3):  # several calls walk the ring of tables
+        Ys = [c.new_Y() for c in cases]
+        g.run(plans, Xs, Ys, ns=[c.n for c in cases])
+        torch.cuda.synchronize()
+        for i, c in enumerate(cases):
+            assert torch.equal(Ys[i][:, : c.n], singles[i]), (rep, i)
+
+
+@pytest.mark.parametrize("count", [3, 40])  # argument table and device table
+def test_group_back_to_back_calls_keep_their_own_tables(count):
+    """Calls issued without synchronising in between, each with other n, X and Y:
+    every output must be the one its own call asked for."""
+    b = 16
+    cases = [Case((3 + i % 4) * b, (5 + i % 3) * b, 64 + 8 * (i % 7), b, 0.3, w="f16", seed=300 + i)
+             for i in range(count)]
+    plans = [c.run_static()[0] for c in cases]
+    g = spmm.Group(64)
+    calls = []
+    for rep in range(6):
+        ns = [1 + (rep * 13 + 5 * i) % c.n for i, c in enumerate(cases)]
+        Xs = [torch.randn((c.k, c.ldx), device="cuda").half() for c in cases]
+        Ys = [c.new_Y() for c in cases]
+        g.run(plans, Xs, Ys, ns=ns)
+        calls.append((ns, Xs, Ys))
+    torch.cuda.synchronize()
+    for ns, Xs, Ys in calls:
+        for i, c in enumerate(cases):
+            Yr = c.new_Y()
+            plans[i].run(Xs[i], Yr, n=ns[i])
+            torch.cuda.synchronize()
+            assert torch.equal(Ys[i][:, : ns[i]], Yr[:, : ns[i]]), i
