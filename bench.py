@@ -42,7 +42,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--mode", default="headline",
-                    choices=["headline", "sweep", "dynamic", "precision", "copy", "serve", "group", "table3"])
+                    choices=["headline", "sweep", "dynamic", "precision", "copy", "serve", "group", "table3", "small"])
     ap.add_argument("--requests", type=int, default=2000, help="serve mode: measured requests per run")
     ap.add_argument("--rho", default="0.5,0.8", help="serve mode: offered load as fractions of the saturated rate")
     ap.add_argument("--max-tokens", default="4096,16384,0",
@@ -620,6 +620,25 @@ def mode_table3(args):
               "dynamic_over_dense": best["dynamic"]}, args.out)
 
 
+def mode_small(args):
+    """The small FP32 case: m = k = 1024, n = 64, b = 16, density 1/16 (general
+    MFMA kernel, FP32 16x16x4): latency and error against the FP64 oracle."""
+    from oracle import spmm_ref as O
+    from paper_2303_16999_amd import synth
+    prob = StaticProblem(1024, 1024, 64, 16, 1 / 16, "f32", seed=0)
+    ms = time_steps(prob.step, max(args.steps, 50), args.warmup)
+    pct = launch_percentiles(prob.step, 50)
+    prob.step()
+    import torch
+    torch.cuda.synchronize()
+    ref = O.spmm_blockwise(1024, 1024, 16, prob.rows, prob.cols, prob.vals_store.astype(np.float64),
+                           prob.X_store.astype(np.float64))
+    err = O.rel_fro(prob.Y.cpu().numpy().astype(np.float64), ref)
+    emit({"mode": "small_fp32", "m": 1024, "k": 1024, "n": 64, "b": 16, "density": 1 / 16, "ms": round(ms, 5),
+          "launch_ms_percentiles": pct, "tflops": round(prob.flops() / (ms * 1e-3) / 1e12, 3),
+          "rel_fro_vs_oracle": err, "bound": 1e-5}, args.out)
+
+
 def mode_copy(args):
     """Plain copy of a known size, for calibrating the HBM byte counters."""
     import torch
@@ -642,7 +661,8 @@ def main():
     from paper_2303_16999_amd import spmm
     spmm.lib()  # fails loudly if the HIP library is missing
     {"headline": mode_headline, "sweep": mode_sweep, "precision": mode_precision, "copy": mode_copy,
-     "dynamic": mode_dynamic, "serve": mode_serve, "group": mode_group, "table3": mode_table3}[args.mode](args)
+     "dynamic": mode_dynamic, "serve": mode_serve, "group": mode_group, "table3": mode_table3,
+     "small": mode_small}[args.mode](args)
 
 
 if __name__ == "__main__":

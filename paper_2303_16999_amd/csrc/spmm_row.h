@@ -166,24 +166,39 @@ __device__ __forceinline__ void row_tile(const RowProblem& p, int32_t r, int32_t
   const int32_t* __restrict__ widx = p.w_index;
   auto wq = [&](int32_t q) -> int64_t { return widx ? (int64_t)uniform(widx[q]) : (int64_t)q; };
   if constexpr (!kFp8 && B == 16) {
-    // pairs of blocks: k slots 0-3 from the first block, 4-7 from the second
-    for (int32_t q = q_lo; q < q_hi; q += 2) {
-      const bool two = q + 1 < q_hi;
-      const int32_t c1 = uniform(p.col_idx[q]);
-      const int32_t c2 = two ? uniform(p.col_idx[q + 1]) : c1;
-      const u32x2 a1 = *(const u32x2*)(Wb + wq(q) * WB + (j * 16 + g * 4) * 2);
-      const u32x2 a2 = two ? *(const u32x2*)(Wb + wq(q + 1) * WB + (j * 16 + g * 4) * 2) : u32x2{0u, 0u};
-      const u32x4 a = {a1.x, a1.y, a2.x, a2.y};
-      u32x2 b1[NS], b2[NS];
-      xfrag<NS>(xr, p, c1 * 16, g, j, n0, b1);
-      if (two) {
-        xfrag<NS>(xr, p, c2 * 16, g, j, n0, b2);
-      } else {
+    // pairs of blocks: k slots 0-3 from the first block, 4-7 from the second.
+    // PF pairs are loaded before their MFMAs (more loads in flight where the
+    // column tile, and so each pair's register footprint, is narrow); the
+    // MFMAs still run pair after pair, so the sums do not depend on PF.
+    constexpr int PF = 8 / NS;
+    for (int32_t q0 = q_lo; q0 < q_hi; q0 += 2 * PF) {
+      u32x4 a[PF];
+      u32x2 b1[PF][NS], b2[PF][NS];
 #pragma unroll
-        for (int s = 0; s < NS; ++s) b2[s] = u32x2{0u, 0u};
+      for (int f = 0; f < PF; ++f) {
+        const int32_t q = q0 + 2 * f;
+        if (f > 0 && q >= q_hi) break;
+        const bool two = q + 1 < q_hi;
+        const int32_t c1 = uniform(p.col_idx[q]);
+        const int32_t c2 = two ? uniform(p.col_idx[q + 1]) : c1;
+        const u32x2 a1 = *(const u32x2*)(Wb + wq(q) * WB + (j * 16 + g * 4) * 2);
+        const u32x2 a2 = two ? *(const u32x2*)(Wb + wq(q + 1) * WB + (j * 16 + g * 4) * 2) : u32x2{0u, 0u};
+        a[f] = u32x4{a1.x, a1.y, a2.x, a2.y};
+        xfrag<NS>(xr, p, c1 * 16, g, j, n0, b1[f]);
+        if (two) {
+          xfrag<NS>(xr, p, c2 * 16, g, j, n0, b2[f]);
+        } else {
+#pragma unroll
+          for (int s = 0; s < NS; ++s) b2[f][s] = u32x2{0u, 0u};
+        }
       }
 #pragma unroll
-      for (int s = 0; s < NS; ++s) acc[0][s] = Mma<XT>::k32(a, u32x4{b1[s].x, b1[s].y, b2[s].x, b2[s].y}, acc[0][s]);
+      for (int f = 0; f < PF; ++f) {
+        if (f > 0 && q0 + 2 * f >= q_hi) break;
+#pragma unroll
+        for (int s = 0; s < NS; ++s)
+          acc[0][s] = Mma<XT>::k32(a[f], u32x4{b1[f][s].x, b1[f][s].y, b2[f][s].x, b2[f][s].y}, acc[0][s]);
+      }
     }
   } else if constexpr (!kFp8) {  // B == 32: k slots 0-3 and 4-7 are rows 8g..8g+3 and 8g+4..8g+7
     for (int32_t q = q_lo; q < q_hi; ++q) {

@@ -136,3 +136,14 @@ def test_headline_shape_sampled_columns():
     err = O.rel_fro(y_f64(Y, c)[:, cols], c.oracle(cols))
     assert err <= 5e-3, err
     assert torch.isfinite(Y).all().item()
+
+
+@pytest.mark.parametrize("w,b", [("f16", 16), ("bf16", 32), ("fp8", 16)])
+def test_lds_pipelined_kernel_matches_oracle_and_row_kernel(w, b, monkeypatch):
+    """The LDS-staged pipelined kernel (opt-in) against the oracle and the default kernel."""
+    c = Case(40 * b + 3, 30 * b + 5, 300, b, 0.2, w=w, x="bf16" if w == "fp8" else None, seed=13, scaled=w == "fp8")
+    _, Y_row = c.run_static()
+    monkeypatch.setenv("SPMM_KERNEL", "pipe")
+    _, Y_pipe = c.run_static()
+    _check(c, Y_pipe, tol=5e-3)
+    assert O.rel_fro(y_f64(Y_pipe, c), y_f64(Y_row, c)) <= 5e-3
