@@ -38,6 +38,52 @@ def block_mask(mb, kb, d, seed):
     return M.reshape(mb, kb)
 
 
+def skewed_mask(mb, kb, d, alpha, seed):
+    """Mask with exactly round(d * mb * kb) blocks whose row counts follow a
+    power law: row of rank t (ranks in random order) gets a share of
+    (t + 1)^-alpha, capped at kb; columns uniform without replacement."""
+    g = rng(seed)
+    nnzb = nnzb_for_density(mb, kb, d)
+    w = (np.arange(mb, dtype=np.float64) + 1.0) ** (-float(alpha))
+    w = w[g.permutation(mb)]
+    counts = np.zeros(mb, np.int64)
+    left = nnzb
+    free = np.ones(mb, bool)
+    while left > 0 and free.any():
+        share = w * free
+        raw = left * share / share.sum()
+        add = np.minimum(np.floor(raw).astype(np.int64), kb - counts)
+        rem = left - int(add.sum())
+        if rem > 0:  # largest remainders among rows with room
+            frac = np.where(free & (counts + add < kb), raw - np.floor(raw), -1.0)
+            for r in np.argsort(-frac, kind="stable")[:rem]:
+                if frac[r] >= 0:
+                    add[r] += 1
+        counts += add
+        left = nnzb - int(counts.sum())
+        free = counts < kb
+    M = np.zeros((mb, kb), np.uint8)
+    for r in range(mb):
+        if counts[r]:
+            M[r, g.choice(kb, size=int(counts[r]), replace=False)] = 1
+    return M
+
+
+def concentrated_mask(mb, kb, d, seed):
+    """Mask with exactly round(d * mb * kb) blocks packed into as few block
+    rows as possible (random rows, fully dense but the last): the load-balance
+    worst case of a partitioned SpMM."""
+    g = rng(seed)
+    nnzb = nnzb_for_density(mb, kb, d)
+    rows = g.permutation(mb)
+    M = np.zeros((mb, kb), np.uint8)
+    full, rest = divmod(nnzb, kb)
+    M[rows[:full]] = 1
+    if rest:
+        M[rows[full], g.choice(kb, size=rest, replace=False)] = 1
+    return M
+
+
 def mask_coo(M):
     """Row-major (CSR-order) list of the nonzero blocks of a mask."""
     rr, cc = np.nonzero(np.asarray(M))
