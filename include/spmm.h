@@ -129,9 +129,16 @@ spmm_status_t spmm_plan_set_values(spmm_plan_t plan, const void* values_dev,
 spmm_status_t spmm_run_static(spmm_plan_t plan, int64_t n, const void* X, int64_t ldx,
                               void* Y, int64_t ldy, void* stream);
 
-/* Plan facts: nonzero blocks, block rows per group, number of groups, panels. */
+/* Plan facts: nonzero blocks, block rows per group, number of groups, panels,
+ * and the number of block rows the row-wise kernel (b = 16, 16-bit X)
+ * splits over the four waves of a workgroup: rows with more than
+ * max(64, 4 x the mean) blocks, found when the plan is built. A split row's
+ * four partial sums are added in a fixed order, so results stay bitwise
+ * reproducible (and equal between spmm_run_static and spmm_group_run), but a
+ * dynamic call of the same pattern, which never splits, may differ from it in
+ * the last bits. Any pointer may be NULL. */
 spmm_status_t spmm_plan_info(spmm_plan_t plan, int64_t* nnzb, int32_t* group_rows,
-                             int32_t* num_groups, int32_t* num_panels);
+                             int32_t* num_groups, int32_t* num_panels, int32_t* num_split_rows);
 
 /* Host copies of the plan arrays, for inspection and tests:
  * row_ptr int32 [mb + 1], col_idx int32 [nnzb], panel_ptr int32 [num_panels + 1]
@@ -140,6 +147,32 @@ spmm_status_t spmm_plan_export(spmm_plan_t plan, int32_t* row_ptr, int32_t* col_
                                int32_t* panel_ptr);
 
 spmm_status_t spmm_plan_destroy(spmm_plan_t plan);
+
+/* ------------------------------------------------------------------ training-direction products
+ * Differentiating Y = (M o W) X (Section 3; sparse training motivates the
+ * paper, Section 1) gives the data gradient dX = (M o W)^T dY, the same
+ * block structure transposed, and the weight gradient dW = (dY X^T) o M, a
+ * product sampled at the mask's blocks.
+ *
+ * spmm_plan_transpose builds, on the current device, the plan of W^T (k x m):
+ * block (r, c) of W becomes block (c, r) with its values transposed. The
+ * source plan must have values set; they are copied (later set_values calls
+ * on the source do not reach the transposed plan). spmm_run_static on the
+ * result computes (M o W)^T dY. opts as for spmm_plan_static. Synchronises.
+ * Errors: INVALID_ARG (NULL, values not set), OOM, HIP.
+ *
+ * spmm_sddmm: G[e] = dY[rows of r] * X[rows of c]^T for every nonzero block
+ * e = (r, c) of the plan, in its block-CSR order (the order of
+ * spmm_plan_set_values). dY is m x n with the plan's y dtype, X is k x n with
+ * its x dtype (both FP16 or both BF16), row-major, leading dimensions lddy and
+ * ldx; G is FP32 [nnzb][b][b] row-major on the device (caller-owned). Rows
+ * and columns of edge blocks outside m x k come out 0. b = 16 or 32. FP32
+ * accumulation over n.
+ * Errors: INVALID_ARG (NULL, ld < n, alignment), UNSUPPORTED (block size,
+ * dtypes), HIP. */
+spmm_status_t spmm_plan_transpose(spmm_plan_t plan, const spmm_plan_opts* opts, spmm_plan_t* out);
+spmm_status_t spmm_sddmm(spmm_plan_t plan, int64_t n, const void* dY, int64_t lddy, const void* X, int64_t ldx,
+                         float* G, void* stream);
 
 /* ------------------------------------------------------------------ autotuner
  * The paper's planner fixes the partition of (m, k, n) from the matrix sizes

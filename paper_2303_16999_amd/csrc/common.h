@@ -138,6 +138,9 @@ struct RunArgs {
   int32_t ovf_mode;       // 0: ignore ovf; 1: skip when *ovf != 0; 2: run only when *ovf != 0
   bool relu = false;      // block-CSR kernels: max(0, y) before the output cast
   const int32_t* w_index = nullptr;  // block-CSR kernels: values (and scales) of entry q at w_index[q], else q
+  int32_t num_heavy = 0;             // row-wise kernel: block rows split over a workgroup's four waves
+  const uint8_t* heavy_flag = nullptr;  // [mb] nonzero for a split row
+  const int32_t* heavy_rows = nullptr;  // [num_heavy]
   int32_t ns = 8;         // row-wise kernel: column tiles of 16 per wave (2, 4 or 8)
 };
 spmm_status_t launch_spmm(const RunArgs& a, hipStream_t stream);
@@ -156,9 +159,19 @@ void fill_row_problem(void* dst, const RunArgs& a, const int32_t* row_ptr, const
                       int32_t unit_begin);
 const void* row_grouped_args_kernel(spmm_dtype_t xt, spmm_dtype_t yt, int32_t b);
 spmm_status_t launch_spmm_row_grouped_args(spmm_dtype_t xt, spmm_dtype_t yt, int32_t b, const void* args,
-                                           int32_t total, hipStream_t stream);
+                                           int32_t total, unsigned lds, hipStream_t stream);
 spmm_status_t launch_spmm_row_grouped(spmm_dtype_t xt, spmm_dtype_t yt, int32_t b, const void* probs_dev,
-                                      int32_t count, int32_t total, hipStream_t stream);
+                                      int32_t count, int32_t total, unsigned lds, hipStream_t stream);
+// LDS bytes of a grouped launch with split rows; work units of one problem.
+unsigned group_split_lds(int32_t b);
+int64_t group_problem_units(int32_t mb, int64_t n, int32_t ns, int32_t num_heavy);
+// SDDMM (b = 16/32, FP16/BF16 dY and X): G[e] = dY[rows of r] X[rows of c]^T
+// for the tasks of a plan (block row, first entry, up to sddmm_task_blocks(b)
+// blocks each), FP32 output in CSR order.
+int32_t sddmm_task_blocks(int32_t b);
+spmm_status_t launch_sddmm(spmm_dtype_t t, int32_t b, const int32_t* row_ptr, const int32_t* col_idx,
+                           const int32_t* tasks, int32_t num_tasks, int64_t m, int64_t k, int64_t n, const void* dY,
+                           int64_t lddy, const void* X, int64_t ldx, float* G, hipStream_t stream);
 // Small-block kernel (b = 1, 4, 8, every dtype triple): W and scales in block-CSR order.
 spmm_status_t launch_spmm_small(const RunArgs& a, const int32_t* row_ptr, const int32_t* col_idx, hipStream_t stream);
 // True when (b, x dtype) runs on a block-CSR kernel (row-wise MFMA or small-block).

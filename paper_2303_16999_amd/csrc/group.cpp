@@ -77,7 +77,7 @@ static spmm_status_t graph_for(spmm_group_s* g, spmm_dtype_t x, spmm_dtype_t y, 
   }
   spmm_group_s::Graph gr;
   SPMM_HIP(hipStreamBeginCapture(g->capture, hipStreamCaptureModeThreadLocal));
-  spmm_status_t st = launch_spmm_row_grouped_args(x, y, b, g->args.data(), total, g->capture);
+  spmm_status_t st = launch_spmm_row_grouped_args(x, y, b, g->args.data(), total, 0, g->capture);
   hipError_t e = hipStreamEndCapture(g->capture, &gr.graph);
   if (st != SPMM_OK) {
     if (gr.graph) (void)hipGraphDestroy(gr.graph);
@@ -174,6 +174,7 @@ spmm_status_t spmm_group_run(spmm_group_t g, int32_t count, const spmm_plan_t* p
   // descriptors, in call order, with the prefix of their work units
   int64_t total = 0;
   int32_t k = 0;
+  bool any_heavy = false;
   for (int32_t i = 0; i < count; ++i) {
     if (n[i] == 0) continue;
     const spmm_plan_s* p = plans[i];
@@ -195,16 +196,22 @@ spmm_status_t spmm_group_run(spmm_group_t g, int32_t count, const spmm_plan_t* p
     a.n = (int32_t)n[i];
     a.relu = relu && relu[i];
     a.ns = ns;
+    a.num_heavy = p->num_heavy;
+    a.heavy_flag = p->heavy_flag;
+    a.heavy_rows = p->heavy_rows;
+    any_heavy = any_heavy || p->num_heavy > 0;
     void* dst = inline_table ? group_args_problem(g->args.data(), k) : (void*)(g->host[s] + (size_t)k * g->desc_bytes);
     fill_row_problem(dst, a, p->pb.row_ptr, p->pb.col_idx, (int32_t)total);
-    total += ceil_div(p->mb, 4) * ceil_div(n[i], 16 * ns);
+    total += group_problem_units(p->mb, n[i], ns, p->num_heavy);
     if (total >= (int64_t)INT32_MAX) return fail(SPMM_ERR_UNSUPPORTED, "too many work units in one group");
     ++k;
   }
   hipStream_t strm = (hipStream_t)stream;
+  const unsigned lds = any_heavy ? group_split_lds(p0->b) : 0u;
   if (inline_table) {
     group_args_header(g->args.data(), used, (int32_t)total);
-    if (!use_graphs()) return launch_spmm_row_grouped_args(p0->x, p0->y, p0->b, g->args.data(), (int32_t)total, strm);
+    if (!use_graphs())
+      return launch_spmm_row_grouped_args(p0->x, p0->y, p0->b, g->args.data(), (int32_t)total, lds, strm);
     spmm_group_s::Graph* gr = nullptr;
     if ((st = graph_for(g, p0->x, p0->y, p0->b, (int32_t)total, &gr)) != SPMM_OK) return st;
     void* params[1] = {g->args.data()};
@@ -212,7 +219,7 @@ spmm_status_t spmm_group_run(spmm_group_t g, int32_t count, const spmm_plan_t* p
     kp.func = const_cast<void*>(row_grouped_args_kernel(p0->x, p0->y, p0->b));
     kp.gridDim = dim3((unsigned)total);
     kp.blockDim = dim3(256);
-    kp.sharedMemBytes = 0;
+    kp.sharedMemBytes = lds;
     kp.kernelParams = params;
     kp.extra = nullptr;
     SPMM_HIP(hipGraphExecKernelNodeSetParams(gr->exec, gr->node, &kp));
@@ -220,7 +227,8 @@ spmm_status_t spmm_group_run(spmm_group_t g, int32_t count, const spmm_plan_t* p
     return SPMM_OK;
   }
   SPMM_HIP(hipMemcpyAsync(g->dev[s], g->host[s], (size_t)used * g->desc_bytes, hipMemcpyHostToDevice, strm));
-  if ((st = launch_spmm_row_grouped(p0->x, p0->y, p0->b, g->dev[s], used, (int32_t)total, strm)) != SPMM_OK) return st;
+  if ((st = launch_spmm_row_grouped(p0->x, p0->y, p0->b, g->dev[s], used, (int32_t)total, lds, strm)) != SPMM_OK)
+    return st;
   SPMM_HIP(hipEventRecord(g->done[s], strm));
   g->pending[s] = true;
   g->slot = (s + 1) % kSlots;

@@ -21,6 +21,11 @@ struct spmm_plan_s {
   int32_t max_chunk = 0;       // most blocks in one (group, chunk)
   int32_t variant_opt = 0;     // fixed tile variant from the options, 0 = choose
   int8_t tuned[32] = {};       // autotuned variant per n class, 0 = none
+  int32_t num_heavy = 0;       // block rows the row-wise kernel splits over four waves
+  uint8_t* heavy_flag = nullptr;   // device [mb]
+  int32_t* heavy_rows = nullptr;   // device [num_heavy]
+  int32_t* sddmm_tasks = nullptr;  // device [sddmm_num_tasks][2] (b = 16/32)
+  int32_t sddmm_num_tasks = 0;
 };
 
 namespace spmm {

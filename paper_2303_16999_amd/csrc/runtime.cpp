@@ -254,7 +254,7 @@ int n_class(int64_t n) {
 }
 
 bool plan_uses_row_kernel(const spmm_plan_s* p) {
-  return p->values_csr && p->b >= 16 && use_row_kernel();
+  return uses_pipe(p->b, p->x) && use_row_kernel();
 }
 
 // Process-wide autotuner table: (b, w, x, y, density class, n class) -> variant.
@@ -319,10 +319,59 @@ spmm_status_t run_plan(const spmm_plan_s* p, int64_t n, const void* X, int64_t l
     a.W = p->values_csr;
     a.scales = p->scales_csr;
     a.ns = variant ? variant : default_ns(n);
+    a.num_heavy = p->num_heavy;
+    a.heavy_flag = p->heavy_flag;
+    a.heavy_rows = p->heavy_rows;
     return launch_spmm_row(a, p->pb.row_ptr, p->pb.col_idx, stream);
   }
   if (relu) return fail(SPMM_ERR_UNSUPPORTED, "fused ReLU needs a block-CSR kernel");
   return launch_spmm(a, stream);
+}
+
+// Block rows longer than max(64, 4 x the mean row) are split over the four
+// waves of a workgroup by the row-wise kernel for b = 16 (a long row would
+// otherwise be one wave's serial chain). SPMM_SPLIT=0 turns this off (for
+// comparisons).
+// SDDMM tasks of a plan with b = 16/32: (block row, first entry) for every run
+// of up to sddmm_task_blocks(b) consecutive blocks of one row.
+static spmm_status_t build_sddmm_tasks(spmm_plan_s* p, const std::vector<int32_t>& rp) {
+  const int32_t per = sddmm_task_blocks(p->b);
+  std::vector<int32_t> tasks;
+  for (int32_t r = 0; r < p->mb; ++r)
+    for (int32_t q = rp[r]; q < rp[r + 1]; q += per) {
+      tasks.push_back(r);
+      tasks.push_back(q);
+    }
+  p->sddmm_num_tasks = (int32_t)(tasks.size() / 2);
+  if (tasks.empty()) return SPMM_OK;
+  spmm_status_t st = dev_alloc(&p->sddmm_tasks, (int64_t)tasks.size());
+  if (st != SPMM_OK) return st;
+  SPMM_HIP(hipMemcpy(p->sddmm_tasks, tasks.data(), sizeof(int32_t) * tasks.size(), hipMemcpyHostToDevice));
+  return SPMM_OK;
+}
+
+static spmm_status_t classify_heavy_rows(spmm_plan_s* p, const std::vector<int32_t>& rp) {
+  const char* e = getenv("SPMM_SPLIT");
+  if (e && std::string(e) == "0") return SPMM_OK;
+  if (p->mb == 0 || p->nnzb == 0) return SPMM_OK;
+  const int64_t mean = ceil_div(p->nnzb, p->mb);
+  const int64_t limit = std::max<int64_t>(64, 4 * mean);
+  std::vector<int32_t> heavy;
+  std::vector<uint8_t> flag((size_t)p->mb, 0);
+  for (int32_t r = 0; r < p->mb; ++r)
+    if (rp[r + 1] - rp[r] > limit) {
+      heavy.push_back(r);
+      flag[r] = 1;
+    }
+  if (heavy.empty()) return SPMM_OK;
+  spmm_status_t st = dev_alloc(&p->heavy_rows, (int64_t)heavy.size());
+  if (st != SPMM_OK) return st;
+  hipError_t err = hipMalloc((void**)&p->heavy_flag, (size_t)p->mb);
+  if (err != hipSuccess) return fail_hip(err, "hipMalloc");
+  SPMM_HIP(hipMemcpy(p->heavy_rows, heavy.data(), sizeof(int32_t) * heavy.size(), hipMemcpyHostToDevice));
+  SPMM_HIP(hipMemcpy(p->heavy_flag, flag.data(), flag.size(), hipMemcpyHostToDevice));
+  p->num_heavy = (int32_t)heavy.size();
+  return SPMM_OK;
 }
 
 }  // namespace spmm
@@ -393,7 +442,7 @@ spmm_status_t spmm_plan_static(int64_t m, int64_t k, int32_t b, const uint8_t* b
     if (e != hipSuccess) st = fail_hip(e, "hipMalloc values");
   }
   if (st == SPMM_OK && w == SPMM_FP8_E4M3) st = dev_alloc(&p->scales, nnzb);
-  if (st == SPMM_OK && uses_csr(b, x)) {
+  if (st == SPMM_OK) {  // block-CSR copy of the values (CSR kernels, transposed plans)
     const int64_t vbytes = nnzb * (int64_t)b * b * dtype_bytes(w);
     e = hipMalloc(&p->values_csr, (size_t)std::max<int64_t>(vbytes, 16));
     if (e != hipSuccess) st = fail_hip(e, "hipMalloc values");
@@ -409,6 +458,14 @@ spmm_status_t spmm_plan_static(int64_t m, int64_t k, int32_t b, const uint8_t* b
     KernelPlan kp = kernel_plan(m, k, b, (int32_t)mb, (int32_t)kb, p->geo, p->pb);
     st = max_chunk_blocks(kp, p->pb.scratch, &p->max_chunk, s);
   }
+  if (st == SPMM_OK && b >= 16) {
+    // host copy of the row pointers: long rows to split, SDDMM tasks
+    std::vector<int32_t> rp((size_t)mb + 1);
+    e = hipMemcpy(rp.data(), p->pb.row_ptr, sizeof(int32_t) * rp.size(), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) st = fail_hip(e, "row pointer download");
+    if (st == SPMM_OK && uses_pipe(b, x) && b == 16) st = classify_heavy_rows(p, rp);
+    if (st == SPMM_OK) st = build_sddmm_tasks(p, rp);
+  }
   if (s) (void)hipStreamDestroy(s);
   if (mask_dev) (void)hipFree(mask_dev);
   if (st != SPMM_OK) {
@@ -417,6 +474,9 @@ spmm_status_t spmm_plan_static(int64_t m, int64_t k, int32_t b, const uint8_t* b
     if (p->scales) (void)hipFree(p->scales);
     if (p->values_csr) (void)hipFree(p->values_csr);
     if (p->scales_csr) (void)hipFree(p->scales_csr);
+    if (p->heavy_flag) (void)hipFree(p->heavy_flag);
+    if (p->heavy_rows) (void)hipFree(p->heavy_rows);
+    if (p->sddmm_tasks) (void)hipFree(p->sddmm_tasks);
     delete p;
     return st;
   }
@@ -532,9 +592,10 @@ spmm_status_t spmm_autotune_static(spmm_plan_t p, int64_t n, const void* X, int6
 }
 
 spmm_status_t spmm_plan_info(spmm_plan_t p, int64_t* nnzb, int32_t* group_rows, int32_t* num_groups,
-                             int32_t* num_panels) {
+                             int32_t* num_panels, int32_t* num_split_rows) {
   clear_error();
   if (!p) return fail(SPMM_ERR_INVALID_ARG, "plan is NULL");
+  if (num_split_rows) *num_split_rows = p->num_heavy;
   if (nnzb) *nnzb = p->nnzb;
   if (group_rows) *group_rows = p->geo.group_rows;
   if (num_groups) *num_groups = p->geo.num_groups;
@@ -563,6 +624,9 @@ spmm_status_t spmm_plan_destroy(spmm_plan_t p) {
   if (p->scales) (void)hipFree(p->scales);
   if (p->values_csr) (void)hipFree(p->values_csr);
   if (p->scales_csr) (void)hipFree(p->scales_csr);
+  if (p->heavy_flag) (void)hipFree(p->heavy_flag);
+  if (p->heavy_rows) (void)hipFree(p->heavy_rows);
+  if (p->sddmm_tasks) (void)hipFree(p->sddmm_tasks);
   delete p;
   return SPMM_OK;
 }

@@ -52,6 +52,9 @@ struct RowProblem {
   int32_t relu;            // nonzero: max(0, y) before the output cast
   int32_t ns;              // column tiles of 16 per wave: 2, 4 or 8
   int32_t unit_begin;      // grouped launch: first work unit of this problem
+  int32_t num_heavy;       // block rows split over the 4 waves of a workgroup
+  const uint8_t* heavy_flag;  // [mb] nonzero for a split row (nullptr when num_heavy == 0)
+  const int32_t* heavy_rows;  // [num_heavy] the split rows
 };
 
 struct Params {
@@ -65,6 +68,14 @@ constexpr int kRowsPerWg = 4;  // one block row per wave
 constexpr uint32_t kOOB = 0x80000000u;
 
 __device__ __forceinline__ int32_t uniform(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// Wave-uniform load of an index array that no kernel writes while it runs:
+// read through the constant address space, so it becomes a scalar load that
+// does not wait for the vector loads in flight.
+__device__ __forceinline__ int32_t sload(const int32_t* base, int64_t i) {
+  typedef const __attribute__((address_space(4))) int32_t* cptr;
+  return uniform(((cptr)base)[i]);
+}
 
 __device__ __forceinline__ int32_t xcd_unit(int32_t w, int32_t U) {
   const int32_t q = U >> 3, r = U & 7;
@@ -146,9 +157,11 @@ __device__ __forceinline__ void xfrag(__amdgpu_buffer_rsrc_t xr, const RowProble
   transpose4<NS>(rows, out);
 }
 
-// The work of one wave: block row r of problem p, columns n0 .. n0 + 16*NS.
-template <typename XT, typename WT, typename YT, int B, int NS>
-__device__ __forceinline__ void row_tile(const RowProblem& p, int32_t r, int32_t n0, int lane) {
+// Accumulates the blocks q_lo .. q_hi of one block row (in CSR order) for
+// columns n0 .. n0 + 16*NS into acc (one wave; acc starts at zero).
+template <typename XT, typename WT, int B, int NS>
+__device__ __forceinline__ void row_acc(const RowProblem& p, int32_t q_lo, int32_t q_hi, int32_t n0, int lane,
+                                        float4_t (&acc)[B / 16][NS]) {
   static_assert(NS == 2 || NS == 4 || NS == 8, "column tiles per wave");
   constexpr bool kFp8 = __is_same(WT, Fp8);
   constexpr int WB = B * B * (kFp8 ? 1 : 2);  // bytes per block
@@ -156,15 +169,12 @@ __device__ __forceinline__ void row_tile(const RowProblem& p, int32_t r, int32_t
   const int g = lane >> 4, j = lane & 15;
   __amdgpu_buffer_rsrc_t xr = __builtin_amdgcn_make_buffer_rsrc((void*)p.X, (short)0, (int)p.x_bytes, 0x00020000);
   const uint8_t* __restrict__ Wb = (const uint8_t*)p.W;
-  float4_t acc[H][NS];
 #pragma unroll
   for (int h = 0; h < H; ++h)
 #pragma unroll
     for (int s = 0; s < NS; ++s) acc[h][s] = float4_t{0.f, 0.f, 0.f, 0.f};
-
-  const int32_t q_lo = uniform(p.row_ptr[r]), q_hi = uniform(p.row_ptr[r + 1]);
   const int32_t* __restrict__ widx = p.w_index;
-  auto wq = [&](int32_t q) -> int64_t { return widx ? (int64_t)uniform(widx[q]) : (int64_t)q; };
+  auto wq = [&](int32_t q) -> int64_t { return widx ? (int64_t)sload(widx, q) : (int64_t)q; };
   if constexpr (!kFp8 && B == 16) {
     // pairs of blocks: k slots 0-3 from the first block, 4-7 from the second.
     // PF pairs are loaded before their MFMAs (more loads in flight where the
@@ -179,8 +189,8 @@ __device__ __forceinline__ void row_tile(const RowProblem& p, int32_t r, int32_t
         const int32_t q = q0 + 2 * f;
         if (f > 0 && q >= q_hi) break;
         const bool two = q + 1 < q_hi;
-        const int32_t c1 = uniform(p.col_idx[q]);
-        const int32_t c2 = two ? uniform(p.col_idx[q + 1]) : c1;
+        const int32_t c1 = sload(p.col_idx, q);
+        const int32_t c2 = two ? sload(p.col_idx, q + 1) : c1;
         const u32x2 a1 = *(const u32x2*)(Wb + wq(q) * WB + (j * 16 + g * 4) * 2);
         const u32x2 a2 = two ? *(const u32x2*)(Wb + wq(q + 1) * WB + (j * 16 + g * 4) * 2) : u32x2{0u, 0u};
         a[f] = u32x4{a1.x, a1.y, a2.x, a2.y};
@@ -202,7 +212,7 @@ __device__ __forceinline__ void row_tile(const RowProblem& p, int32_t r, int32_t
     }
   } else if constexpr (!kFp8) {  // B == 32: k slots 0-3 and 4-7 are rows 8g..8g+3 and 8g+4..8g+7
     for (int32_t q = q_lo; q < q_hi; ++q) {
-      const int32_t c = uniform(p.col_idx[q]);
+      const int32_t c = sload(p.col_idx, q);
       u32x2 b1[NS], b2[NS];
       xfrag<NS>(xr, p, c * 32, 2 * g, j, n0, b1);      // rows c*32 + 8g + i
       xfrag<NS>(xr, p, c * 32 + 4, 2 * g, j, n0, b2);  // rows c*32 + 8g + 4 + i
@@ -215,7 +225,7 @@ __device__ __forceinline__ void row_tile(const RowProblem& p, int32_t r, int32_t
     }
   } else {  // FP8 weights with a per-block scale
     for (int32_t q = q_lo; q < q_hi; ++q) {
-      const int32_t c = uniform(p.col_idx[q]);
+      const int32_t c = sload(p.col_idx, q);
       const int64_t qv = wq(q);
       const float sc = p.scales[qv];
       if constexpr (B == 16) {
@@ -241,7 +251,15 @@ __device__ __forceinline__ void row_tile(const RowProblem& p, int32_t r, int32_t
     }
   }
 
-  // epilogue: lane (g, j) holds rows 4g + i and columns n0 + NS*j .. +NS
+}
+
+// Stores one wave's accumulators for block row r: lane (g, j) holds rows
+// 4g + i (+16h) and columns n0 + NS*j .. +NS.
+template <typename YT, int B, int NS>
+__device__ __forceinline__ void row_store(const RowProblem& p, int32_t r, int32_t n0, int lane,
+                                          float4_t (&acc)[B / 16][NS]) {
+  constexpr int H = B / 16;
+  const int g = lane >> 4, j = lane & 15;
   if (p.relu) {
 #pragma unroll
     for (int h = 0; h < H; ++h)
@@ -292,18 +310,89 @@ __device__ __forceinline__ void row_tile(const RowProblem& p, int32_t r, int32_t
   }
 }
 
+// The work of one wave: block row r of problem p, columns n0 .. n0 + 16*NS.
+template <typename XT, typename WT, typename YT, int B, int NS>
+__device__ __forceinline__ void row_tile(const RowProblem& p, int32_t r, int32_t n0, int lane) {
+  float4_t acc[B / 16][NS];
+  row_acc<XT, WT, B, NS>(p, sload(p.row_ptr, r), sload(p.row_ptr, r + 1), n0, lane, acc);
+  row_store<YT, B, NS>(p, r, n0, lane, acc);
+}
+
+// Work units of a problem: heavy units first (one split row times a column
+// tile, so the longest units start early), then light units (4 block rows,
+// one per wave, times a column tile; split rows are skipped there).
+__device__ __forceinline__ int32_t heavy_units(const RowProblem& p, int ns) {
+  return p.num_heavy * ((p.n + 16 * ns - 1) / (16 * ns));
+}
+
+// Bytes of LDS a workgroup needs to reduce a split row: three waves' partial
+// accumulators (the fourth keeps its own).
+__host__ __device__ constexpr int split_lds_bytes(int B, int NS) { return 3 * (B / 16) * NS * 64 * 16; }
+
+// One work unit of problem p (local index `unit`). A split row's blocks are cut
+// into four pair-aligned ranges, one per wave; waves 1-3 leave their partial
+// sums in LDS and wave 0 adds them in wave order, so the result does not depend
+// on timing. red: split_lds_bytes(B, NS) of LDS, used only by heavy units.
+template <typename XT, typename WT, typename YT, int B, int NS>
+__device__ __forceinline__ void row_unit(const RowProblem& p, int32_t unit, int lane, int wave, float4_t* red) {
+  constexpr int H = B / 16;
+  const int32_t hus = B == 16 ? heavy_units(p, NS) : 0;  // rows are split for b = 16 only
+  if (unit >= hus) {
+    const int32_t lu = unit - hus;
+    const int32_t rgroups = (p.mb + kRowsPerWg - 1) / kRowsPerWg;
+    const int32_t r = (lu % rgroups) * kRowsPerWg + wave;
+    if (r >= p.mb) return;
+    if (B == 16 && p.num_heavy && p.heavy_flag[r]) return;
+    row_tile<XT, WT, YT, B, NS>(p, r, (lu / rgroups) * (16 * NS), lane);
+    return;
+  }
+  if constexpr (B == 16) {
+  const int32_t hu = unit;
+  const int32_t r = sload(p.heavy_rows, hu % p.num_heavy);
+  const int32_t n0 = (hu / p.num_heavy) * (16 * NS);
+  const int32_t lo = sload(p.row_ptr, r), hi = sload(p.row_ptr, r + 1);
+  const int32_t seg = (((hi - lo) + 7) / 8) * 2;  // a quarter of the row, rounded up to whole pairs
+  const int32_t qa = min(hi, lo + wave * seg), qb = min(hi, qa + seg);
+  float4_t acc[H][NS];
+  row_acc<XT, WT, B, NS>(p, qa, qb, n0, lane, acc);
+  if (wave > 0) {
+#pragma unroll
+    for (int h = 0; h < H; ++h)
+#pragma unroll
+      for (int s = 0; s < NS; ++s) red[(((wave - 1) * H + h) * NS + s) * 64 + lane] = acc[h][s];
+  }
+  __syncthreads();
+  if (wave == 0) {
+#pragma unroll
+    for (int w = 0; w < 3; ++w)
+#pragma unroll
+      for (int h = 0; h < H; ++h)
+#pragma unroll
+        for (int s = 0; s < NS; ++s) acc[h][s] += red[((w * H + h) * NS + s) * 64 + lane];
+    row_store<YT, B, NS>(p, r, n0, lane, acc);
+  }
+  }
+}
+
 template <typename XT, typename WT, typename YT, int B, int NS>
 __global__ __launch_bounds__(256) void k_spmm_row(Params prm) {
   if (prm.status && *prm.status) return;
+  extern __shared__ float4_t row_red[];
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  // Heavy units take the first workgroups (spread over the XCDs by the
+  // dispatcher's round robin), padded to a multiple of 8 so the light units
+  // keep their XCD-contiguous order.
   const RowProblem& p = prm.pr;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int32_t unit = xcd_unit(blockIdx.x, prm.num_units);
-  const int32_t rgroups = (p.mb + kRowsPerWg - 1) / kRowsPerWg;
-  const int32_t rg = unit % rgroups;
-  const int32_t n0 = (unit / rgroups) * (16 * NS);
-  const int32_t r = rg * kRowsPerWg + wave;
-  if (r >= p.mb) return;
-  row_tile<XT, WT, YT, B, NS>(p, r, n0, lane);
+  const int32_t hus = B == 16 ? heavy_units(p, NS) : 0;
+  const int32_t hpad = (hus + 7) & ~7;
+  int32_t unit;
+  if ((int32_t)blockIdx.x < hpad) {
+    if ((int32_t)blockIdx.x >= hus) return;
+    unit = blockIdx.x;
+  } else {
+    unit = hus + xcd_unit(blockIdx.x - hpad, prm.num_units - hus);
+  }
+  row_unit<XT, WT, YT, B, NS>(p, unit, lane, wave, row_red);
 }
 
 inline RowProblem row_problem(const RunArgs& a, const int32_t* row_ptr, const int32_t* col_idx) {
@@ -325,7 +414,15 @@ inline RowProblem row_problem(const RunArgs& a, const int32_t* row_ptr, const in
   p.relu = a.relu ? 1 : 0;
   p.ns = a.ns;
   p.unit_begin = 0;
+  p.num_heavy = a.heavy_rows ? a.num_heavy : 0;
+  p.heavy_flag = p.num_heavy ? a.heavy_flag : nullptr;
+  p.heavy_rows = p.num_heavy ? a.heavy_rows : nullptr;
   return p;
+}
+
+// Work units of a problem (light and heavy) for a column-tile variant.
+inline int64_t problem_units(int32_t mb, int64_t n, int32_t ns, int32_t num_heavy) {
+  return (ceil_div(mb, kRowsPerWg) + num_heavy) * ceil_div(n, 16 * ns);
 }
 
 template <typename XT, typename WT, typename YT, int B>
@@ -336,13 +433,17 @@ spmm_status_t launch_row(const RunArgs& a, const int32_t* row_ptr, const int32_t
   prm.pr = row_problem(a, row_ptr, col_idx);
   prm.status = a.status;
   const int ns = prm.pr.ns;
-  const int64_t units = ceil_div(a.plan.mb, kRowsPerWg) * ceil_div(a.n, 16 * ns);
+  const int64_t units = problem_units(a.plan.mb, a.n, ns, prm.pr.num_heavy);
   if (units == 0) return SPMM_OK;
   if (units > (int64_t)INT32_MAX) return fail(SPMM_ERR_UNSUPPORTED, "too many work units");
   prm.num_units = (int32_t)units;
-  if (ns == 8) hipLaunchKernelGGL((k_spmm_row<XT, WT, YT, B, 8>), dim3((unsigned)units), dim3(256), 0, stream, prm);
-  else if (ns == 4) hipLaunchKernelGGL((k_spmm_row<XT, WT, YT, B, 4>), dim3((unsigned)units), dim3(256), 0, stream, prm);
-  else if (ns == 2) hipLaunchKernelGGL((k_spmm_row<XT, WT, YT, B, 2>), dim3((unsigned)units), dim3(256), 0, stream, prm);
+  const int64_t hus = B == 16 ? (int64_t)prm.pr.num_heavy * ceil_div(a.n, 16 * ns) : 0;
+  const int64_t grid = units + (((hus + 7) & ~(int64_t)7) - hus);
+  if (grid > (int64_t)INT32_MAX) return fail(SPMM_ERR_UNSUPPORTED, "too many work units");
+  const unsigned lds = prm.pr.num_heavy ? (unsigned)split_lds_bytes(B, ns) : 0u;
+  if (ns == 8) hipLaunchKernelGGL((k_spmm_row<XT, WT, YT, B, 8>), dim3((unsigned)grid), dim3(256), lds, stream, prm);
+  else if (ns == 4) hipLaunchKernelGGL((k_spmm_row<XT, WT, YT, B, 4>), dim3((unsigned)grid), dim3(256), lds, stream, prm);
+  else if (ns == 2) hipLaunchKernelGGL((k_spmm_row<XT, WT, YT, B, 2>), dim3((unsigned)grid), dim3(256), lds, stream, prm);
   else return fail(SPMM_ERR_INVALID_ARG, "column tile variant must be 2, 4 or 8");
   SPMM_HIP(hipGetLastError());
   return SPMM_OK;

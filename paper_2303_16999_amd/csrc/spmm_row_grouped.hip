@@ -20,8 +20,9 @@ struct GroupArgs {
 // (problem, group of 4 block rows, column tile of 16*ns). The problem of a
 // unit is the last one whose first unit is at or before it.
 template <typename XT, typename WT, typename YT, int B>
-__device__ __forceinline__ void group_unit(const RowProblem* __restrict__ probs, int32_t count, int32_t total) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+__device__ __forceinline__ void group_unit(const RowProblem* __restrict__ probs, int32_t count, int32_t total,
+                                           float4_t* red) {
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int32_t unit = xcd_unit(blockIdx.x, total);
   int32_t lo = 0, hi = count - 1;
   while (lo < hi) {
@@ -31,27 +32,25 @@ __device__ __forceinline__ void group_unit(const RowProblem* __restrict__ probs,
   }
   const RowProblem p = probs[lo];  // by value: the fields live in scalar registers
   const int32_t local = unit - uniform(p.unit_begin);
-  const int32_t rgroups = (uniform(p.mb) + kRowsPerWg - 1) / kRowsPerWg;
   const int32_t ns = uniform(p.ns);
-  const int32_t r = (local % rgroups) * kRowsPerWg + wave;
-  if (r >= p.mb) return;
-  const int32_t n0 = (local / rgroups) * (16 * ns);
-  if (ns == 8) row_tile<XT, WT, YT, B, 8>(p, r, n0, lane);
-  else if (ns == 4) row_tile<XT, WT, YT, B, 4>(p, r, n0, lane);
-  else row_tile<XT, WT, YT, B, 2>(p, r, n0, lane);
+  if (ns == 8) row_unit<XT, WT, YT, B, 8>(p, local, lane, wave, red);
+  else if (ns == 4) row_unit<XT, WT, YT, B, 4>(p, local, lane, wave, red);
+  else row_unit<XT, WT, YT, B, 2>(p, local, lane, wave, red);
 }
 
 // Table in device memory (any number of problems).
 template <typename XT, typename WT, typename YT, int B>
 __global__ __launch_bounds__(256, B == 16 ? 4 : 3) void k_spmm_row_grouped(const RowProblem* __restrict__ probs,
                                                                           int32_t count, int32_t total) {
-  group_unit<XT, WT, YT, B>(probs, count, total);
+  extern __shared__ float4_t grp_red[];
+  group_unit<XT, WT, YT, B>(probs, count, total, grp_red);
 }
 
 // Table in the kernel arguments.
 template <typename XT, typename WT, typename YT, int B>
 __global__ __launch_bounds__(256, B == 16 ? 4 : 3) void k_spmm_row_grouped_args(GroupArgs args) {
-  group_unit<XT, WT, YT, B>(args.probs, args.count, args.total);
+  extern __shared__ float4_t grp_red[];
+  group_unit<XT, WT, YT, B>(args.probs, args.count, args.total, grp_red);
 }
 
 }  // namespace row
@@ -67,13 +66,13 @@ const void* args_kernel_b(int32_t b) {
 }
 
 template <typename XT, typename YT>
-void table_launch_b(int32_t b, const row::RowProblem* probs, int32_t count, int32_t total, hipStream_t s) {
+void table_launch_b(int32_t b, const row::RowProblem* probs, int32_t count, int32_t total, unsigned lds, hipStream_t s) {
   if (b == 16)
-    hipLaunchKernelGGL((row::k_spmm_row_grouped<XT, XT, YT, 16>), dim3((unsigned)total), dim3(256), 0, s, probs, count,
-                       total);
+    hipLaunchKernelGGL((row::k_spmm_row_grouped<XT, XT, YT, 16>), dim3((unsigned)total), dim3(256), lds, s, probs,
+                       count, total);
   else
-    hipLaunchKernelGGL((row::k_spmm_row_grouped<XT, XT, YT, 32>), dim3((unsigned)total), dim3(256), 0, s, probs, count,
-                       total);
+    hipLaunchKernelGGL((row::k_spmm_row_grouped<XT, XT, YT, 32>), dim3((unsigned)total), dim3(256), lds, s, probs,
+                       count, total);
 }
 }  // namespace
 
@@ -108,25 +107,32 @@ const void* row_grouped_args_kernel(spmm_dtype_t xt, spmm_dtype_t yt, int32_t b)
 }
 
 spmm_status_t launch_spmm_row_grouped_args(spmm_dtype_t xt, spmm_dtype_t yt, int32_t b, const void* args, int32_t total,
-                                           hipStream_t s) {
+                                           unsigned lds, hipStream_t s) {
   const void* fn = row_grouped_args_kernel(xt, yt, b);
   if (!fn) return fail(SPMM_ERR_UNSUPPORTED, "grouped launch needs 16-bit X and b = 16 or 32");
   void* params[1] = {const_cast<void*>(args)};
-  SPMM_HIP(hipLaunchKernel(fn, dim3((unsigned)total), dim3(256), params, 0, s));
+  SPMM_HIP(hipLaunchKernel(fn, dim3((unsigned)total), dim3(256), params, lds, s));
   return SPMM_OK;
 }
 
+// LDS of a grouped launch whose problems include split rows.
+unsigned group_split_lds(int32_t b) { return (unsigned)row::split_lds_bytes(b, 8); }
+
+int64_t group_problem_units(int32_t mb, int64_t n, int32_t ns, int32_t num_heavy) {
+  return row::problem_units(mb, n, ns, num_heavy);
+}
+
 spmm_status_t launch_spmm_row_grouped(spmm_dtype_t xt, spmm_dtype_t yt, int32_t b, const void* probs_dev,
-                                      int32_t count, int32_t total, hipStream_t s) {
+                                      int32_t count, int32_t total, unsigned lds, hipStream_t s) {
   using bf = __bf16;
   const row::RowProblem* pr = (const row::RowProblem*)probs_dev;
   if (b != 16 && b != 32) return fail(SPMM_ERR_UNSUPPORTED, "grouped launch handles block sizes 16 and 32");
   if (xt == SPMM_F16) {
-    if (yt == SPMM_F32) table_launch_b<_Float16, float>(b, pr, count, total, s);
-    else table_launch_b<_Float16, _Float16>(b, pr, count, total, s);
+    if (yt == SPMM_F32) table_launch_b<_Float16, float>(b, pr, count, total, lds, s);
+    else table_launch_b<_Float16, _Float16>(b, pr, count, total, lds, s);
   } else if (xt == SPMM_BF16) {
-    if (yt == SPMM_F32) table_launch_b<bf, float>(b, pr, count, total, s);
-    else table_launch_b<bf, bf>(b, pr, count, total, s);
+    if (yt == SPMM_F32) table_launch_b<bf, float>(b, pr, count, total, lds, s);
+    else table_launch_b<bf, bf>(b, pr, count, total, lds, s);
   } else {
     return fail(SPMM_ERR_UNSUPPORTED, "grouped launch needs 16-bit X");
   }

@@ -52,7 +52,7 @@ SIGNATURES = {
                           ctypes.POINTER(_vp)], _c_i32),
     "spmm_plan_set_values": ([_vp, _vp, _vp, _vp], _c_i32),
     "spmm_run_static": ([_vp, _c_i64, _vp, _c_i64, _vp, _c_i64, _vp], _c_i32),
-    "spmm_plan_info": ([_vp, _pi64, _pi32, _pi32, _pi32], _c_i32),
+    "spmm_plan_info": ([_vp, _pi64, _pi32, _pi32, _pi32, _pi32], _c_i32),
     "spmm_plan_export": ([_vp, _vp, _vp, _vp], _c_i32),
     "spmm_plan_destroy": ([_vp], _c_i32),
     "spmm_dynamic_create": ([_c_i64, _c_i64, _c_i32, _c_i64, _c_i32, _c_i32, _c_i32, ctypes.POINTER(PlanOpts),
@@ -74,6 +74,8 @@ SIGNATURES = {
     "spmm_serve_stats": ([_vp, ctypes.POINTER(ServeStats)], _c_i32),
     "spmm_serve_destroy": ([_vp], _c_i32),
     "spmm_serve_clock": ([], ctypes.c_double),
+    "spmm_plan_transpose": ([_vp, ctypes.POINTER(PlanOpts), ctypes.POINTER(_vp)], _c_i32),
+    "spmm_sddmm": ([_vp, _c_i64, _vp, _c_i64, _vp, _c_i64, _vp, _vp], _c_i32),
 }
 
 _LIB = None
@@ -149,9 +151,11 @@ class StaticPlan:
         self.mb, self.kb = -(-self.m // self.b), -(-self.k // self.b)
 
     def info(self):
-        nnz, gr, ng, npn = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
-        check(lib().spmm_plan_info(self._h, ctypes.byref(nnz), ctypes.byref(gr), ctypes.byref(ng), ctypes.byref(npn)))
-        return {"nnzb": nnz.value, "group_rows": gr.value, "num_groups": ng.value, "num_panels": npn.value}
+        nnz, gr, ng, npn, nh = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        check(lib().spmm_plan_info(self._h, ctypes.byref(nnz), ctypes.byref(gr), ctypes.byref(ng), ctypes.byref(npn),
+                                   ctypes.byref(nh)))
+        return {"nnzb": nnz.value, "group_rows": gr.value, "num_groups": ng.value, "num_panels": npn.value,
+                "num_split_rows": nh.value}
 
     def set_values(self, values, scales=None, stream=None):
         check(lib().spmm_plan_set_values(self._h, _ptr(values), _ptr(scales), _stream(stream)))
@@ -182,6 +186,25 @@ class StaticPlan:
         check(lib().spmm_plan_export(self._h, row_ptr.ctypes.data_as(_vp), col_idx.ctypes.data_as(_vp),
                                      panel_ptr.ctypes.data_as(_vp)))
         return {"row_ptr": row_ptr, "col_idx": col_idx[: inf["nnzb"]], "panel_ptr": panel_ptr}
+
+    def transpose(self, group_rows=0, num_panels=0, n_hint=0, variant=0):
+        """spmm_plan_transpose: the plan of W^T (k x m) with the values transposed."""
+        h = _vp()
+        opts = _opts(group_rows, num_panels, n_hint, variant)
+        check(lib().spmm_plan_transpose(self._h, ctypes.byref(opts), ctypes.byref(h)))
+        t = StaticPlan.__new__(StaticPlan)
+        t._h = h
+        t.m, t.k, t.b = self.k, self.m, self.b
+        t.w, t.x, t.y = self.w, self.x, self.y
+        t.mb, t.kb = self.kb, self.mb
+        return t
+
+    def sddmm(self, dY, X, G, n=None, stream=None):
+        """spmm_sddmm: G[e] = dY[rows of r] X[rows of c]^T on the plan's blocks (FP32 [nnzb, b, b])."""
+        n = X.shape[1] if n is None else n
+        check(lib().spmm_sddmm(self._h, int(n), _ptr(dY), int(dY.stride(0)), _ptr(X), int(X.stride(0)), _ptr(G),
+                               _stream(stream)))
+        return G
 
     def close(self):
         if getattr(self, "_h", None):
