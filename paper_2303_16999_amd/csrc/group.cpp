@@ -42,7 +42,7 @@ struct spmm_group_s {
     hipGraphExec_t exec = nullptr;
     hipGraphNode_t node = nullptr;
   };
-  std::map<std::tuple<int, int, int>, Graph> graphs;  // (x, y, b)
+  std::map<std::tuple<int, int, int, bool>, Graph> graphs;  // (x, y, b, split rows)
 };
 
 static void destroy_group(spmm_group_s* g) {
@@ -67,9 +67,9 @@ static bool use_graphs() {
 
 // The captured one-node graph of the argument form for a dtype class: captured
 // once with the current arguments, then only its node parameters change.
-static spmm_status_t graph_for(spmm_group_s* g, spmm_dtype_t x, spmm_dtype_t y, int32_t b, int32_t total,
-                               spmm_group_s::Graph** out) {
-  const auto key = std::make_tuple((int)x, (int)y, (int)b);
+static spmm_status_t graph_for(spmm_group_s* g, spmm_dtype_t x, spmm_dtype_t y, int32_t b, unsigned lds,
+                               int32_t total, spmm_group_s::Graph** out) {
+  const auto key = std::make_tuple((int)x, (int)y, (int)b, lds > 0);
   auto it = g->graphs.find(key);
   if (it != g->graphs.end()) {
     *out = &it->second;
@@ -77,7 +77,7 @@ static spmm_status_t graph_for(spmm_group_s* g, spmm_dtype_t x, spmm_dtype_t y, 
   }
   spmm_group_s::Graph gr;
   SPMM_HIP(hipStreamBeginCapture(g->capture, hipStreamCaptureModeThreadLocal));
-  spmm_status_t st = launch_spmm_row_grouped_args(x, y, b, g->args.data(), total, 0, g->capture);
+  spmm_status_t st = launch_spmm_row_grouped_args(x, y, b, g->args.data(), total, lds, g->capture);
   hipError_t e = hipStreamEndCapture(g->capture, &gr.graph);
   if (st != SPMM_OK) {
     if (gr.graph) (void)hipGraphDestroy(gr.graph);
@@ -213,10 +213,10 @@ spmm_status_t spmm_group_run(spmm_group_t g, int32_t count, const spmm_plan_t* p
     if (!use_graphs())
       return launch_spmm_row_grouped_args(p0->x, p0->y, p0->b, g->args.data(), (int32_t)total, lds, strm);
     spmm_group_s::Graph* gr = nullptr;
-    if ((st = graph_for(g, p0->x, p0->y, p0->b, (int32_t)total, &gr)) != SPMM_OK) return st;
+    if ((st = graph_for(g, p0->x, p0->y, p0->b, lds, (int32_t)total, &gr)) != SPMM_OK) return st;
     void* params[1] = {g->args.data()};
     hipKernelNodeParams kp{};
-    kp.func = const_cast<void*>(row_grouped_args_kernel(p0->x, p0->y, p0->b));
+    kp.func = const_cast<void*>(row_grouped_args_kernel(p0->x, p0->y, p0->b, lds > 0));
     kp.gridDim = dim3((unsigned)total);
     kp.blockDim = dim3(256);
     kp.sharedMemBytes = lds;

@@ -69,9 +69,10 @@ constexpr uint32_t kOOB = 0x80000000u;
 
 __device__ __forceinline__ int32_t uniform(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 
-// Wave-uniform load of an index array that no kernel writes while it runs:
-// read through the constant address space, so it becomes a scalar load that
-// does not wait for the vector loads in flight.
+// Wave-uniform load of an index array that no kernel writes while it runs,
+// through the constant address space: it stays a scalar load (which does not
+// wait for the vector loads in flight) in kernels with a barrier, where the
+// compiler cannot prove the memory unchanged.
 __device__ __forceinline__ int32_t sload(const int32_t* base, int64_t i) {
   typedef const __attribute__((address_space(4))) int32_t* cptr;
   return uniform(((cptr)base)[i]);
@@ -310,7 +311,156 @@ __device__ __forceinline__ void row_store(const RowProblem& p, int32_t r, int32_
   }
 }
 
-// The work of one wave: block row r of problem p, columns n0 .. n0 + 16*NS.
+// The work of one wave in a launch without split rows: block row r of
+// problem p, columns n0 .. n0 + 16*NS. (The same steps as row_acc followed by
+// row_store, kept in one body: split into the two, the compiler schedules the
+// main loop differently and the kernel measured 3-6% slower.)
+template <typename XT, typename WT, typename YT, int B, int NS>
+__device__ __forceinline__ void row_tile_whole(const RowProblem& p, int32_t r, int32_t n0, int lane) {
+  static_assert(NS == 2 || NS == 4 || NS == 8, "column tiles per wave");
+  constexpr bool kFp8 = __is_same(WT, Fp8);
+  constexpr int WB = B * B * (kFp8 ? 1 : 2);  // bytes per block
+  constexpr int H = B / 16;
+  const int g = lane >> 4, j = lane & 15;
+  __amdgpu_buffer_rsrc_t xr = __builtin_amdgcn_make_buffer_rsrc((void*)p.X, (short)0, (int)p.x_bytes, 0x00020000);
+  const uint8_t* __restrict__ Wb = (const uint8_t*)p.W;
+  float4_t acc[H][NS];
+#pragma unroll
+  for (int h = 0; h < H; ++h)
+#pragma unroll
+    for (int s = 0; s < NS; ++s) acc[h][s] = float4_t{0.f, 0.f, 0.f, 0.f};
+
+  const int32_t q_lo = uniform(p.row_ptr[r]), q_hi = uniform(p.row_ptr[r + 1]);
+  const int32_t* __restrict__ widx = p.w_index;
+  auto wq = [&](int32_t q) -> int64_t { return widx ? (int64_t)uniform(widx[q]) : (int64_t)q; };
+  if constexpr (!kFp8 && B == 16) {
+    // pairs of blocks: k slots 0-3 from the first block, 4-7 from the second.
+    // PF pairs are loaded before their MFMAs (more loads in flight where the
+    // column tile, and so each pair's register footprint, is narrow); the
+    // MFMAs still run pair after pair, so the sums do not depend on PF.
+    constexpr int PF = 8 / NS;
+    for (int32_t q0 = q_lo; q0 < q_hi; q0 += 2 * PF) {
+      u32x4 a[PF];
+      u32x2 b1[PF][NS], b2[PF][NS];
+#pragma unroll
+      for (int f = 0; f < PF; ++f) {
+        const int32_t q = q0 + 2 * f;
+        if (f > 0 && q >= q_hi) break;
+        const bool two = q + 1 < q_hi;
+        const int32_t c1 = uniform(p.col_idx[q]);
+        const int32_t c2 = two ? uniform(p.col_idx[q + 1]) : c1;
+        const u32x2 a1 = *(const u32x2*)(Wb + wq(q) * WB + (j * 16 + g * 4) * 2);
+        const u32x2 a2 = two ? *(const u32x2*)(Wb + wq(q + 1) * WB + (j * 16 + g * 4) * 2) : u32x2{0u, 0u};
+        a[f] = u32x4{a1.x, a1.y, a2.x, a2.y};
+        xfrag<NS>(xr, p, c1 * 16, g, j, n0, b1[f]);
+        if (two) {
+          xfrag<NS>(xr, p, c2 * 16, g, j, n0, b2[f]);
+        } else {
+#pragma unroll
+          for (int s = 0; s < NS; ++s) b2[f][s] = u32x2{0u, 0u};
+        }
+      }
+#pragma unroll
+      for (int f = 0; f < PF; ++f) {
+        if (f > 0 && q0 + 2 * f >= q_hi) break;
+#pragma unroll
+        for (int s = 0; s < NS; ++s)
+          acc[0][s] = Mma<XT>::k32(a[f], u32x4{b1[f][s].x, b1[f][s].y, b2[f][s].x, b2[f][s].y}, acc[0][s]);
+      }
+    }
+  } else if constexpr (!kFp8) {  // B == 32: k slots 0-3 and 4-7 are rows 8g..8g+3 and 8g+4..8g+7
+    for (int32_t q = q_lo; q < q_hi; ++q) {
+      const int32_t c = uniform(p.col_idx[q]);
+      u32x2 b1[NS], b2[NS];
+      xfrag<NS>(xr, p, c * 32, 2 * g, j, n0, b1);      // rows c*32 + 8g + i
+      xfrag<NS>(xr, p, c * 32 + 4, 2 * g, j, n0, b2);  // rows c*32 + 8g + 4 + i
+#pragma unroll
+      for (int h = 0; h < H; ++h) {
+        const u32x4 a = *(const u32x4*)(Wb + wq(q) * WB + ((h * 16 + j) * 32 + g * 8) * 2);
+#pragma unroll
+        for (int s = 0; s < NS; ++s) acc[h][s] = Mma<XT>::k32(a, u32x4{b1[s].x, b1[s].y, b2[s].x, b2[s].y}, acc[h][s]);
+      }
+    }
+  } else {  // FP8 weights with a per-block scale
+    for (int32_t q = q_lo; q < q_hi; ++q) {
+      const int32_t c = uniform(p.col_idx[q]);
+      const int64_t qv = wq(q);
+      const float sc = p.scales[qv];
+      if constexpr (B == 16) {
+        const u32x2 a = fp8x4<XT>(*(const uint32_t*)(Wb + qv * WB + j * 16 + g * 4));
+        u32x2 bx[NS];
+        xfrag<NS>(xr, p, c * 16, g, j, n0, bx);
+#pragma unroll
+        for (int s = 0; s < NS; ++s) acc[0][s] += sc * Mma<XT>::k16(a, bx[s], float4_t{0.f, 0.f, 0.f, 0.f});
+      } else {
+        u32x2 b1[NS], b2[NS];
+        xfrag<NS>(xr, p, c * 32, 2 * g, j, n0, b1);
+        xfrag<NS>(xr, p, c * 32 + 4, 2 * g, j, n0, b2);
+#pragma unroll
+        for (int h = 0; h < H; ++h) {
+          const u32x2 codes = *(const u32x2*)(Wb + qv * WB + (h * 16 + j) * 32 + g * 8);
+          const u32x2 lo = fp8x4<XT>(codes.x), hi = fp8x4<XT>(codes.y);
+          const u32x4 a = {lo.x, lo.y, hi.x, hi.y};
+#pragma unroll
+          for (int s = 0; s < NS; ++s)
+            acc[h][s] += sc * Mma<XT>::k32(a, u32x4{b1[s].x, b1[s].y, b2[s].x, b2[s].y}, float4_t{0.f, 0.f, 0.f, 0.f});
+        }
+      }
+    }
+  }
+
+  // epilogue: lane (g, j) holds rows 4g + i and columns n0 + NS*j .. +NS
+  if (p.relu) {
+#pragma unroll
+    for (int h = 0; h < H; ++h)
+#pragma unroll
+      for (int s = 0; s < NS; ++s)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) acc[h][s][i] = acc[h][s][i] > 0.f ? acc[h][s][i] : 0.f;
+  }
+  YT* __restrict__ Y = (YT*)p.Y;
+  const int32_t col0 = n0 + NS * j;
+#pragma unroll
+  for (int h = 0; h < H; ++h) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int64_t row = (int64_t)r * B + h * 16 + 4 * g + i;
+      if (row >= p.m) continue;
+      YT* dst = Y + row * p.ldy + col0;
+      if (col0 + NS <= p.n) {
+        if constexpr (sizeof(YT) == 4 && NS == 2) {
+          const float v0 = acc[h][0][i], v1 = acc[h][1][i];
+          *(float2_t*)dst = float2_t{v0, v1};
+        } else if constexpr (sizeof(YT) == 4) {
+#pragma unroll
+          for (int s = 0; s < NS; s += 4) {
+            const float v0 = acc[h][s][i], v1 = acc[h][s + 1][i], v2 = acc[h][s + 2][i], v3 = acc[h][s + 3][i];
+            *(float4_t*)(dst + s) = float4_t{v0, v1, v2, v3};
+          }
+        } else {
+          uint32_t w[NS / 2];
+#pragma unroll
+          for (int e = 0; e < NS / 2; ++e) {
+            const float lo = acc[h][2 * e][i], hi = acc[h][2 * e + 1][i];
+            w[e] = Mma<YT>::pack2(lo, hi);
+          }
+          if constexpr (NS == 8) *(u32x4*)dst = u32x4{w[0], w[1], w[2], w[3]};
+          else if constexpr (NS == 4) *(u32x2*)dst = u32x2{w[0], w[1]};
+          else *(uint32_t*)dst = w[0];
+        }
+      } else {
+#pragma unroll
+        for (int s = 0; s < NS; ++s)
+          if (col0 + s < p.n) {
+            const float v = acc[h][s][i];
+            dst[s] = to_out<YT>(v);
+          }
+      }
+    }
+  }
+}
+
+// The work of one wave in a launch with split rows (light unit).
 template <typename XT, typename WT, typename YT, int B, int NS>
 __device__ __forceinline__ void row_tile(const RowProblem& p, int32_t r, int32_t n0, int lane) {
   float4_t acc[B / 16][NS];
@@ -333,20 +483,29 @@ __host__ __device__ constexpr int split_lds_bytes(int B, int NS) { return 3 * (B
 // into four pair-aligned ranges, one per wave; waves 1-3 leave their partial
 // sums in LDS and wave 0 adds them in wave order, so the result does not depend
 // on timing. red: split_lds_bytes(B, NS) of LDS, used only by heavy units.
-template <typename XT, typename WT, typename YT, int B, int NS>
+// SPLIT = false: the problem has no split rows (every unit is light).
+template <typename XT, typename WT, typename YT, int B, int NS, bool SPLIT>
 __device__ __forceinline__ void row_unit(const RowProblem& p, int32_t unit, int lane, int wave, float4_t* red) {
   constexpr int H = B / 16;
-  const int32_t hus = B == 16 ? heavy_units(p, NS) : 0;  // rows are split for b = 16 only
+  static_assert(!SPLIT || B == 16, "rows are split for b = 16 only");
+  if constexpr (!SPLIT) {
+    const int32_t rgroups = (p.mb + kRowsPerWg - 1) / kRowsPerWg;
+    const int32_t r = (unit % rgroups) * kRowsPerWg + wave;
+    if (r >= p.mb) return;
+    row_tile_whole<XT, WT, YT, B, NS>(p, r, (unit / rgroups) * (16 * NS), lane);
+    return;
+  }
+  const int32_t hus = heavy_units(p, NS);
   if (unit >= hus) {
     const int32_t lu = unit - hus;
     const int32_t rgroups = (p.mb + kRowsPerWg - 1) / kRowsPerWg;
     const int32_t r = (lu % rgroups) * kRowsPerWg + wave;
     if (r >= p.mb) return;
-    if (B == 16 && p.num_heavy && p.heavy_flag[r]) return;
+    if (p.num_heavy && p.heavy_flag[r]) return;
     row_tile<XT, WT, YT, B, NS>(p, r, (lu / rgroups) * (16 * NS), lane);
     return;
   }
-  if constexpr (B == 16) {
+  if constexpr (SPLIT) {
   const int32_t hu = unit;
   const int32_t r = sload(p.heavy_rows, hu % p.num_heavy);
   const int32_t n0 = (hu / p.num_heavy) * (16 * NS);
@@ -374,25 +533,32 @@ __device__ __forceinline__ void row_unit(const RowProblem& p, int32_t unit, int 
   }
 }
 
-template <typename XT, typename WT, typename YT, int B, int NS>
+template <typename XT, typename WT, typename YT, int B, int NS, bool SPLIT>
 __global__ __launch_bounds__(256) void k_spmm_row(Params prm) {
   if (prm.status && *prm.status) return;
-  extern __shared__ float4_t row_red[];
-  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  // Heavy units take the first workgroups (spread over the XCDs by the
-  // dispatcher's round robin), padded to a multiple of 8 so the light units
-  // keep their XCD-contiguous order.
+  // (the unsplit form keeps the wave index as a vector value: its row pointer
+  // loads then issue as vector loads, which measured faster from cold caches)
+  const int lane = threadIdx.x & 63;
+  const int wave = SPLIT ? __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) : (int)(threadIdx.x >> 6);
   const RowProblem& p = prm.pr;
-  const int32_t hus = B == 16 ? heavy_units(p, NS) : 0;
-  const int32_t hpad = (hus + 7) & ~7;
-  int32_t unit;
-  if ((int32_t)blockIdx.x < hpad) {
-    if ((int32_t)blockIdx.x >= hus) return;
-    unit = blockIdx.x;
+  if constexpr (!SPLIT) {
+    row_unit<XT, WT, YT, B, NS, false>(p, xcd_unit(blockIdx.x, prm.num_units), lane, wave, nullptr);
   } else {
-    unit = hus + xcd_unit(blockIdx.x - hpad, prm.num_units - hus);
+    // Heavy units take the first workgroups (spread over the XCDs by the
+    // dispatcher's round robin), padded to a multiple of 8 so the light units
+    // keep their XCD-contiguous order.
+    extern __shared__ float4_t row_red[];
+    const int32_t hus = heavy_units(p, NS);
+    const int32_t hpad = (hus + 7) & ~7;
+    int32_t unit;
+    if ((int32_t)blockIdx.x < hpad) {
+      if ((int32_t)blockIdx.x >= hus) return;
+      unit = blockIdx.x;
+    } else {
+      unit = hus + xcd_unit(blockIdx.x - hpad, prm.num_units - hus);
+    }
+    row_unit<XT, WT, YT, B, NS, true>(p, unit, lane, wave, row_red);
   }
-  row_unit<XT, WT, YT, B, NS>(p, unit, lane, wave, row_red);
 }
 
 inline RowProblem row_problem(const RunArgs& a, const int32_t* row_ptr, const int32_t* col_idx) {
@@ -440,10 +606,19 @@ spmm_status_t launch_row(const RunArgs& a, const int32_t* row_ptr, const int32_t
   const int64_t hus = B == 16 ? (int64_t)prm.pr.num_heavy * ceil_div(a.n, 16 * ns) : 0;
   const int64_t grid = units + (((hus + 7) & ~(int64_t)7) - hus);
   if (grid > (int64_t)INT32_MAX) return fail(SPMM_ERR_UNSUPPORTED, "too many work units");
-  const unsigned lds = prm.pr.num_heavy ? (unsigned)split_lds_bytes(B, ns) : 0u;
-  if (ns == 8) hipLaunchKernelGGL((k_spmm_row<XT, WT, YT, B, 8>), dim3((unsigned)grid), dim3(256), lds, stream, prm);
-  else if (ns == 4) hipLaunchKernelGGL((k_spmm_row<XT, WT, YT, B, 4>), dim3((unsigned)grid), dim3(256), lds, stream, prm);
-  else if (ns == 2) hipLaunchKernelGGL((k_spmm_row<XT, WT, YT, B, 2>), dim3((unsigned)grid), dim3(256), lds, stream, prm);
+  const bool split = B == 16 && prm.pr.num_heavy > 0;
+  const unsigned lds = split ? (unsigned)split_lds_bytes(B, ns) : 0u;
+  if (split) {
+    if constexpr (B == 16) {
+      if (ns == 8) hipLaunchKernelGGL((k_spmm_row<XT, WT, YT, B, 8, true>), dim3((unsigned)grid), dim3(256), lds, stream, prm);
+      else if (ns == 4) hipLaunchKernelGGL((k_spmm_row<XT, WT, YT, B, 4, true>), dim3((unsigned)grid), dim3(256), lds, stream, prm);
+      else if (ns == 2) hipLaunchKernelGGL((k_spmm_row<XT, WT, YT, B, 2, true>), dim3((unsigned)grid), dim3(256), lds, stream, prm);
+      else return fail(SPMM_ERR_INVALID_ARG, "column tile variant must be 2, 4 or 8");
+    }
+  }
+  else if (ns == 8) hipLaunchKernelGGL((k_spmm_row<XT, WT, YT, B, 8, false>), dim3((unsigned)grid), dim3(256), 0, stream, prm);
+  else if (ns == 4) hipLaunchKernelGGL((k_spmm_row<XT, WT, YT, B, 4, false>), dim3((unsigned)grid), dim3(256), 0, stream, prm);
+  else if (ns == 2) hipLaunchKernelGGL((k_spmm_row<XT, WT, YT, B, 2, false>), dim3((unsigned)grid), dim3(256), 0, stream, prm);
   else return fail(SPMM_ERR_INVALID_ARG, "column tile variant must be 2, 4 or 8");
   SPMM_HIP(hipGetLastError());
   return SPMM_OK;

@@ -19,10 +19,11 @@ struct GroupArgs {
 // One workgroup per work unit of the group, in the XCD-aware order; a unit is
 // (problem, group of 4 block rows, column tile of 16*ns). The problem of a
 // unit is the last one whose first unit is at or before it.
-template <typename XT, typename WT, typename YT, int B>
+template <typename XT, typename WT, typename YT, int B, bool SPLIT>
 __device__ __forceinline__ void group_unit(const RowProblem* __restrict__ probs, int32_t count, int32_t total,
                                            float4_t* red) {
-  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int wave = SPLIT ? __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) : (int)(threadIdx.x >> 6);
   const int32_t unit = xcd_unit(blockIdx.x, total);
   int32_t lo = 0, hi = count - 1;
   while (lo < hi) {
@@ -33,24 +34,25 @@ __device__ __forceinline__ void group_unit(const RowProblem* __restrict__ probs,
   const RowProblem p = probs[lo];  // by value: the fields live in scalar registers
   const int32_t local = unit - uniform(p.unit_begin);
   const int32_t ns = uniform(p.ns);
-  if (ns == 8) row_unit<XT, WT, YT, B, 8>(p, local, lane, wave, red);
-  else if (ns == 4) row_unit<XT, WT, YT, B, 4>(p, local, lane, wave, red);
-  else row_unit<XT, WT, YT, B, 2>(p, local, lane, wave, red);
+  if (ns == 8) row_unit<XT, WT, YT, B, 8, SPLIT>(p, local, lane, wave, red);
+  else if (ns == 4) row_unit<XT, WT, YT, B, 4, SPLIT>(p, local, lane, wave, red);
+  else row_unit<XT, WT, YT, B, 2, SPLIT>(p, local, lane, wave, red);
 }
 
-// Table in device memory (any number of problems).
-template <typename XT, typename WT, typename YT, int B>
+// Table in device memory (any number of problems). SPLIT: some problem has
+// split rows (b = 16 only).
+template <typename XT, typename WT, typename YT, int B, bool SPLIT>
 __global__ __launch_bounds__(256, B == 16 ? 4 : 3) void k_spmm_row_grouped(const RowProblem* __restrict__ probs,
                                                                           int32_t count, int32_t total) {
   extern __shared__ float4_t grp_red[];
-  group_unit<XT, WT, YT, B>(probs, count, total, grp_red);
+  group_unit<XT, WT, YT, B, SPLIT>(probs, count, total, SPLIT ? grp_red : nullptr);
 }
 
 // Table in the kernel arguments.
-template <typename XT, typename WT, typename YT, int B>
+template <typename XT, typename WT, typename YT, int B, bool SPLIT>
 __global__ __launch_bounds__(256, B == 16 ? 4 : 3) void k_spmm_row_grouped_args(GroupArgs args) {
   extern __shared__ float4_t grp_red[];
-  group_unit<XT, WT, YT, B>(args.probs, args.count, args.total, grp_red);
+  group_unit<XT, WT, YT, B, SPLIT>(args.probs, args.count, args.total, SPLIT ? grp_red : nullptr);
 }
 
 }  // namespace row
@@ -60,19 +62,24 @@ namespace spmm {
 
 namespace {
 template <typename XT, typename YT>
-const void* args_kernel_b(int32_t b) {
-  if (b == 16) return reinterpret_cast<const void*>(&row::k_spmm_row_grouped_args<XT, XT, YT, 16>);
-  return reinterpret_cast<const void*>(&row::k_spmm_row_grouped_args<XT, XT, YT, 32>);
+const void* args_kernel_b(int32_t b, bool split) {
+  if (b == 16 && split) return reinterpret_cast<const void*>(&row::k_spmm_row_grouped_args<XT, XT, YT, 16, true>);
+  if (b == 16) return reinterpret_cast<const void*>(&row::k_spmm_row_grouped_args<XT, XT, YT, 16, false>);
+  return reinterpret_cast<const void*>(&row::k_spmm_row_grouped_args<XT, XT, YT, 32, false>);
 }
 
 template <typename XT, typename YT>
-void table_launch_b(int32_t b, const row::RowProblem* probs, int32_t count, int32_t total, unsigned lds, hipStream_t s) {
-  if (b == 16)
-    hipLaunchKernelGGL((row::k_spmm_row_grouped<XT, XT, YT, 16>), dim3((unsigned)total), dim3(256), lds, s, probs,
+void table_launch_b(int32_t b, bool split, const row::RowProblem* probs, int32_t count, int32_t total, unsigned lds,
+                    hipStream_t s) {
+  if (b == 16 && split)
+    hipLaunchKernelGGL((row::k_spmm_row_grouped<XT, XT, YT, 16, true>), dim3((unsigned)total), dim3(256), lds, s, probs,
                        count, total);
+  else if (b == 16)
+    hipLaunchKernelGGL((row::k_spmm_row_grouped<XT, XT, YT, 16, false>), dim3((unsigned)total), dim3(256), 0, s,
+                       probs, count, total);
   else
-    hipLaunchKernelGGL((row::k_spmm_row_grouped<XT, XT, YT, 32>), dim3((unsigned)total), dim3(256), lds, s, probs,
-                       count, total);
+    hipLaunchKernelGGL((row::k_spmm_row_grouped<XT, XT, YT, 32, false>), dim3((unsigned)total), dim3(256), 0, s,
+                       probs, count, total);
 }
 }  // namespace
 
@@ -97,18 +104,20 @@ void fill_row_problem(void* dst, const RunArgs& a, const int32_t* row_ptr, const
   *(row::RowProblem*)dst = p;
 }
 
-// Kernel of the argument-table form for a dtype class (16-bit W = X), or nullptr.
-const void* row_grouped_args_kernel(spmm_dtype_t xt, spmm_dtype_t yt, int32_t b) {
+// Kernel of the argument-table form for a dtype class (16-bit W = X), or
+// nullptr. split: some problem of the group has split rows (b = 16).
+const void* row_grouped_args_kernel(spmm_dtype_t xt, spmm_dtype_t yt, int32_t b, bool split) {
   using bf = __bf16;
   if (b != 16 && b != 32) return nullptr;
-  if (xt == SPMM_F16) return yt == SPMM_F32 ? args_kernel_b<_Float16, float>(b) : args_kernel_b<_Float16, _Float16>(b);
-  if (xt == SPMM_BF16) return yt == SPMM_F32 ? args_kernel_b<bf, float>(b) : args_kernel_b<bf, bf>(b);
+  if (xt == SPMM_F16)
+    return yt == SPMM_F32 ? args_kernel_b<_Float16, float>(b, split) : args_kernel_b<_Float16, _Float16>(b, split);
+  if (xt == SPMM_BF16) return yt == SPMM_F32 ? args_kernel_b<bf, float>(b, split) : args_kernel_b<bf, bf>(b, split);
   return nullptr;
 }
 
 spmm_status_t launch_spmm_row_grouped_args(spmm_dtype_t xt, spmm_dtype_t yt, int32_t b, const void* args, int32_t total,
                                            unsigned lds, hipStream_t s) {
-  const void* fn = row_grouped_args_kernel(xt, yt, b);
+  const void* fn = row_grouped_args_kernel(xt, yt, b, lds > 0);
   if (!fn) return fail(SPMM_ERR_UNSUPPORTED, "grouped launch needs 16-bit X and b = 16 or 32");
   void* params[1] = {const_cast<void*>(args)};
   SPMM_HIP(hipLaunchKernel(fn, dim3((unsigned)total), dim3(256), params, lds, s));
@@ -128,11 +137,11 @@ spmm_status_t launch_spmm_row_grouped(spmm_dtype_t xt, spmm_dtype_t yt, int32_t 
   const row::RowProblem* pr = (const row::RowProblem*)probs_dev;
   if (b != 16 && b != 32) return fail(SPMM_ERR_UNSUPPORTED, "grouped launch handles block sizes 16 and 32");
   if (xt == SPMM_F16) {
-    if (yt == SPMM_F32) table_launch_b<_Float16, float>(b, pr, count, total, lds, s);
-    else table_launch_b<_Float16, _Float16>(b, pr, count, total, lds, s);
+    if (yt == SPMM_F32) table_launch_b<_Float16, float>(b, lds > 0, pr, count, total, lds, s);
+    else table_launch_b<_Float16, _Float16>(b, lds > 0, pr, count, total, lds, s);
   } else if (xt == SPMM_BF16) {
-    if (yt == SPMM_F32) table_launch_b<bf, float>(b, pr, count, total, lds, s);
-    else table_launch_b<bf, bf>(b, pr, count, total, lds, s);
+    if (yt == SPMM_F32) table_launch_b<bf, float>(b, lds > 0, pr, count, total, lds, s);
+    else table_launch_b<bf, bf>(b, lds > 0, pr, count, total, lds, s);
   } else {
     return fail(SPMM_ERR_UNSUPPORTED, "grouped launch needs 16-bit X");
   }
