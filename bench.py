@@ -43,7 +43,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--mode", default="headline",
                     choices=["headline", "sweep", "dynamic", "precision", "copy", "serve", "group", "table3", "small",
-                             "skew", "train"])
+                             "skew", "train", "grid", "ell"])
     ap.add_argument("--requests", type=int, default=2000, help="serve mode: measured requests per run")
     ap.add_argument("--rho", default="0.5,0.8", help="serve mode: offered load as fractions of the saturated rate")
     ap.add_argument("--max-tokens", default="4096,16384,0",
@@ -54,6 +54,8 @@ def parse():
     ap.add_argument("--calls", type=int, default=1000, help="dynamic mode: number of calls")
     ap.add_argument("--sweep-b", default="1,4,8,16,32", help="sweep mode: block sizes")
     ap.add_argument("--sweep-n", default="256,1024,4096", help="sweep mode: column counts")
+    ap.add_argument("--grid-m", default="256,512,1024,2048,4096,8192", help="grid mode: feature sizes m = k")
+    ap.add_argument("--grid-n", default="4,16,64,256,1024,4096,16384,65536", help="grid mode: batch sizes n")
     return ap.parse_args()
 
 
@@ -728,6 +730,125 @@ def mode_train(args):
         torch.cuda.empty_cache()
 
 
+def mode_grid(args):
+    """The paper's static sweep grid (Table 1 of Section 4: m = k in 2^8..2^13,
+    n in 2^2..2^16 by powers of 4, b in {1, 4, 8, 16}, d in {1/4 .. 1/32},
+    FP16): static sparse and dense FP16 TFLOP/s (nonzero FLOPs), each best
+    over n, their ratio per (m, b, d), and a power-law fit of the ratio
+    (Section 5, "Will my application speed up?")."""
+    import torch
+    from paper_2303_16999_amd import spmm, synth
+    from paper_2303_16999_amd import speedup_model
+    ms_list = [int(v) for v in args.grid_m.split(",")]
+    n_list = [int(v) for v in args.grid_n.split(",")]
+    bs, ds = (1, 4, 8, 16), (4, 8, 16, 32)
+    g = torch.Generator(device="cuda").manual_seed(11)
+    results = []
+    for m in ms_list:
+        plans = {}
+        for b in bs:
+            for dd in ds:
+                mb = -(-m // b)
+                mask = synth.block_mask(mb, mb, 1.0 / dd, 0)
+                plan = spmm.StaticPlan(m, m, b, mask, "f16", n_hint=1024)
+                nnzb = plan.info()["nnzb"]
+                vals = torch.randn((max(nnzb, 1), b, b), device="cuda", dtype=torch.float16, generator=g)
+                plan.set_values(vals)
+                plans[(b, dd)] = (plan, vals, 2.0 * nnzb * b * b)  # FLOPs per column of X
+        best = {key: (0.0, None) for key in plans}
+        best_dense = {dd: (0.0, None) for dd in ds}
+        for n in n_list:
+            if m * n * 2 * 3 > 6 * 2 ** 30:
+                continue
+            ld = -(-n // 8) * 8  # rows of X and Y start 16-byte aligned
+            X = torch.randn((m, ld), device="cuda", dtype=torch.float16, generator=g)
+            Y = torch.empty((m, ld), device="cuda", dtype=torch.float16)
+            Xd = X[:, :n].contiguous()
+            Yd = torch.empty((m, n), device="cuda", dtype=torch.float16)
+            A = torch.randn((m, m), device="cuda", dtype=torch.float16, generator=g)
+            steps = max(3, min(args.steps, int(2e9 / max(1, m * m * n))))
+            tdense = time_steps(lambda: torch.matmul(A, Xd, out=Yd), steps, 2)
+            for dd in ds:
+                tf = 2.0 * m * m * n / dd / (tdense * 1e-3) / 1e12  # nonzero FLOPs of density 1/dd
+                if tf > best_dense[dd][0]:
+                    best_dense[dd] = (tf, n)
+            for key, (plan, _, fpc) in plans.items():
+                t = time_steps(lambda: plan.run(X, Y, n=n), steps, 2)
+                tf = fpc * n / (t * 1e-3) / 1e12
+                if tf > best[key][0]:
+                    best[key] = (tf, n)
+            del X, Y, Xd, Yd, A
+            torch.cuda.empty_cache()
+        for (b, dd), (tf, n_best) in sorted(best.items()):
+            dtf, dn = best_dense[dd]
+            rec = {"mode": "grid", "m": m, "k": m, "b": b, "density": 1.0 / dd, "sparse_tflops": round(tf, 3),
+                   "sparse_best_n": n_best, "dense_tflops_nonzero": round(dtf, 3), "dense_best_n": dn,
+                   "speedup": round(tf / dtf, 4) if dtf > 0 else None}
+            emit(rec, args.out)
+            results.append(rec)
+        del plans
+        torch.cuda.empty_cache()
+    pts = [(r["m"], r["density"], r["b"], r["speedup"]) for r in results if r["speedup"]]
+    fit = speedup_model.fit(pts)
+    emit(dict({"mode": "grid_fit"}, **fit), args.out)
+
+
+def mode_ell(args):
+    """Blocked-ELL and large blocks at m = k = 8192, n = 4096, density 1/16,
+    FP16: (1) the plan built from a blocked-ELL description against the one
+    built from the mask (the same kernel), and the cost of materialising the
+    ELL padding as explicit zero blocks (the padding the paper expects tensor
+    cores to absorb, Section 5); (2) b = 16, 32 and 64 at equal density."""
+    import torch
+    from paper_2303_16999_amd import spmm, synth
+    m = k = 8192
+    n = 4096
+    g = torch.Generator(device="cuda").manual_seed(21)
+    X = torch.randn((k, n), device="cuda", dtype=torch.float16, generator=g)
+    Y = torch.empty((m, n), device="cuda", dtype=torch.float16)
+    dn = dense_fp16(m, k, n, args.steps, args.warmup, 1.0)["ms"]
+    b = 16
+    mb = kb = m // b
+    mask = synth.block_mask(mb, kb, 1 / 16, 0)
+    width = int(mask.sum(1).max())
+    cols = synth.ell_from_mask(mask, width, 1)
+    nnzb = int(mask.sum())
+    vals = torch.randn((mb * width, b, b), device="cuda", dtype=torch.float16, generator=g)
+    ell_plan = spmm.StaticPlan.from_ell(m, k, b, cols, "f16", n_hint=n)
+    ell_plan.set_values_ell(vals)
+    mask_plan = spmm.StaticPlan(m, k, b, mask, "f16", n_hint=n)
+    mask_plan.set_values(torch.randn((nnzb, b, b), device="cuda", dtype=torch.float16, generator=g))
+    # padding made explicit: every row filled to the ELL width with zero blocks in unused columns
+    rng = np.random.default_rng(2)
+    padded = mask.copy()
+    for r in range(mb):
+        free = np.nonzero(padded[r] == 0)[0]
+        padded[r, rng.choice(free, width - int(mask[r].sum()), replace=False)] = 1
+    pr, pc = np.nonzero(padded)
+    pvals = torch.zeros((pr.size, b, b), device="cuda", dtype=torch.float16)
+    keep = torch.from_numpy(mask[pr, pc].astype(bool)).cuda()
+    pvals[keep] = torch.randn((nnzb, b, b), device="cuda", dtype=torch.float16, generator=g)
+    pad_plan = spmm.StaticPlan(m, k, b, padded, "f16", n_hint=n)
+    pad_plan.set_values(pvals)
+    flops = 2.0 * nnzb * b * b * n
+    for name, plan in (("mask", mask_plan), ("ell", ell_plan), ("ell_padded_explicit", pad_plan)):
+        ms = time_steps(lambda: plan.run(X, Y), args.steps, args.warmup)
+        emit({"mode": "ell", "plan": name, "m": m, "k": k, "n": n, "b": b, "density": 1 / 16, "ell_width": width,
+              "blocks_run": int(pr.size) if name == "ell_padded_explicit" else nnzb, "nnz_blocks": nnzb,
+              "ms": round(ms, 5), "tflops_nonzero": round(flops / (ms * 1e-3) / 1e12, 3),
+              "dense_ms": round(dn, 5), "speedup_vs_dense": round(dn / ms, 3)}, args.out)
+    del ell_plan, mask_plan, pad_plan, vals, pvals
+    torch.cuda.empty_cache()
+    for bb in (16, 32, 64):
+        prob = StaticProblem(m, k, n, bb, 1 / 16, "f16", seed=0)
+        ms = time_steps(prob.step, args.steps, args.warmup)
+        emit({"mode": "block_size", "m": m, "k": k, "n": n, "b": bb, "density": 1 / 16, "nnz_blocks": prob.nnzb,
+              "ms": round(ms, 5), "tflops": round(prob.flops() / (ms * 1e-3) / 1e12, 3),
+              "dense_ms": round(dn, 5), "speedup_vs_dense": round(dn / ms, 3)}, args.out)
+        del prob
+        torch.cuda.empty_cache()
+
+
 def mode_copy(args):
     """Plain copy of a known size, for calibrating the HBM byte counters."""
     import torch
@@ -751,7 +872,8 @@ def main():
     spmm.lib()  # fails loudly if the HIP library is missing
     {"headline": mode_headline, "sweep": mode_sweep, "precision": mode_precision, "copy": mode_copy,
      "dynamic": mode_dynamic, "serve": mode_serve, "group": mode_group, "table3": mode_table3,
-     "small": mode_small, "skew": mode_skew, "train": mode_train}[args.mode](args)
+     "small": mode_small, "skew": mode_skew, "train": mode_train, "grid": mode_grid,
+     "ell": mode_ell}[args.mode](args)
 
 
 if __name__ == "__main__":

@@ -106,11 +106,39 @@ const char* spmm_last_error(void);
  * nonzero = block present. The block-CSR (row_ptr, col_idx), the row groups
  * and the cost-balanced panels are computed by HIP kernels; the call
  * synchronises before returning. opts may be NULL.
- * Errors: INVALID_ARG (m, k < 1, b not in {1,4,8,16,32}, NULL pointers),
- * UNSUPPORTED (dtype triple), OOM, HIP. On error *out is NULL. */
+ * b = 64 (beyond the paper's sweep) runs as 4 x 4 MFMA tiles of 16 (the
+ * four waves of a workgroup take a block row's four row tiles) and needs
+ * FP16 or BF16 X; its block rows are never split.
+ * Errors: INVALID_ARG (m, k < 1, b not in {1,4,8,16,32,64}, NULL pointers),
+ * UNSUPPORTED (dtype triple, b = 64 with FP32 X), OOM, HIP. On error *out is
+ * NULL. */
 spmm_status_t spmm_plan_static(int64_t m, int64_t k, int32_t b, const uint8_t* block_mask_host,
                                spmm_dtype_t w, spmm_dtype_t x, spmm_dtype_t y,
                                const spmm_plan_opts* opts, spmm_plan_t* out);
+
+/* Blocked-ELL input. The paper's GPU comparison sets aside cuSPARSE's
+ * blocked-ELL format, whose rows each list a fixed number of block-column
+ * indices with -1 marking an empty slot (Appendix B; Section 5 notes it as the
+ * FP16-capable layout that needs explicit padding). spmm_plan_ell takes that
+ * description: ell_cols_host is int32 [ceil(m/b)][ell_width] row-major, each
+ * entry a block column in [0, ceil(k/b)) or -1; slots of a row may come in
+ * any order, but a column may appear only once per row. The result is the
+ * plan spmm_plan_static builds from the equivalent mask (same kernels, same
+ * results), which also remembers the slot of each block. b and opts as for
+ * spmm_plan_static. Synchronises.
+ * Errors: INVALID_ARG (sizes, NULL, index outside [-1, ceil(k/b)), repeated
+ * column in a row), UNSUPPORTED, OOM, HIP.
+ *
+ * spmm_plan_set_values_ell: values in slot order, [ceil(m/b)][ell_width] blocks
+ * of b x b (row-major inside a block); empty slots are not read. FP8 weights
+ * take FP32 scales [ceil(m/b)][ell_width]. Gathers into the plan's order on
+ * `stream` through a temporary buffer and synchronises `stream` before
+ * returning. Errors: INVALID_ARG (NULL, plan not built from ELL), OOM, HIP. */
+spmm_status_t spmm_plan_ell(int64_t m, int64_t k, int32_t b, int32_t ell_width, const int32_t* ell_cols_host,
+                            spmm_dtype_t w, spmm_dtype_t x, spmm_dtype_t y, const spmm_plan_opts* opts,
+                            spmm_plan_t* out);
+spmm_status_t spmm_plan_set_values_ell(spmm_plan_t plan, const void* values_ell_dev, const float* scales_ell_dev,
+                                       void* stream);
 
 /* Copies the nonzero block values into plan-owned device memory (the plan
  * keeps them resident; the caller may free its buffer once the copy on
@@ -173,6 +201,18 @@ spmm_status_t spmm_plan_destroy(spmm_plan_t plan);
 spmm_status_t spmm_plan_transpose(spmm_plan_t plan, const spmm_plan_opts* opts, spmm_plan_t* out);
 spmm_status_t spmm_sddmm(spmm_plan_t plan, int64_t n, const void* dY, int64_t lddy, const void* X, int64_t ldx,
                          float* G, void* stream);
+
+/* ------------------------------------------------------------------ speedup model
+ * Section 5 summarises the paper's static sweep by a power law: a static
+ * sparse product beats dense where a m^alpha d^beta b^gamma > 1. This is the
+ * same form refitted to this library's static kernels against dense FP16 GEMM
+ * (both FP16, FLOPs of the nonzeros only, each best over n) on one MI355X:
+ * m = k in 2^8 .. 2^13, b in {1, 4, 8, 16}, density 1/4 .. 1/32. *speedup
+ * receives the predicted ratio for feature size m = k, density d (0 < d <= 1)
+ * and block size b, for dispatching between a sparse and a dense product; it
+ * interpolates the measured grid and is not meant beyond it. Pure host code.
+ * Errors: INVALID_ARG (NULL, m < 1, b < 1, density outside (0, 1]). */
+spmm_status_t spmm_speedup_model(int64_t m, double density, int32_t b, double* speedup);
 
 /* ------------------------------------------------------------------ autotuner
  * The paper's planner fixes the partition of (m, k, n) from the matrix sizes

@@ -147,7 +147,7 @@ spmm_status_t spmm_group_run(spmm_group_t g, int32_t count, const spmm_plan_t* p
   if (st != SPMM_OK) return st;
   const spmm_plan_s* p0 = plans[0];
   if (!p0) return fail(SPMM_ERR_INVALID_ARG, "plan 0 is NULL");
-  if (!plan_uses_row_kernel(p0) || p0->w == SPMM_FP8_E4M3)
+  if (!plan_uses_row_kernel(p0) || p0->w == SPMM_FP8_E4M3 || p0->b > 32)
     return fail(SPMM_ERR_UNSUPPORTED, "grouped launch needs b = 16 or 32 with 16-bit W and X");
   int32_t used = 0;
   for (int32_t i = 0; i < count; ++i) {

@@ -26,6 +26,8 @@ struct spmm_plan_s {
   int32_t* heavy_rows = nullptr;   // device [num_heavy]
   int32_t* sddmm_tasks = nullptr;  // device [sddmm_num_tasks][2] (b = 16/32)
   int32_t sddmm_num_tasks = 0;
+  int32_t ell_width = 0;           // plans built from blocked-ELL: slots per block row
+  int32_t* ell_slot = nullptr;     // device [nnzb]: ELL slot (row * ell_width + slot) of each CSR entry
 };
 
 namespace spmm {
@@ -35,7 +37,7 @@ int n_class(int64_t n);
 // Tile variant for a run of `p` with n columns: fixed option, else the plan's
 // tuned value, else the process-wide tuned table, else the rule on n.
 int32_t plan_variant(const spmm_plan_s* p, int64_t n);
-// Whether the plan runs on the row-wise MFMA kernel (b = 16/32, 16-bit X).
+// Whether the plan runs on the row-wise MFMA kernel (b = 16/32/64, 16-bit X).
 bool plan_uses_row_kernel(const spmm_plan_s* p);
 // Enqueues Y = (M o W) X for a validated plan (no argument checks).
 spmm_status_t run_plan(const spmm_plan_s* p, int64_t n, const void* X, int64_t ldx, void* Y, int64_t ldy,

@@ -58,6 +58,8 @@ int device_cu_count() {
 }
 
 static bool valid_block(int32_t b) { return b == 1 || b == 4 || b == 8 || b == 16 || b == 32; }
+// Static plans also take b = 64 (4 x 4 MFMA tiles of 16, 16-bit X).
+static bool valid_static_block(int32_t b) { return valid_block(b) || b == 64; }
 
 bool uses_pipe(int32_t b, spmm_dtype_t x) { return b >= 16 && (x == SPMM_F16 || x == SPMM_BF16); }
 bool uses_csr(int32_t b, spmm_dtype_t x) { return b < 16 || uses_pipe(b, x); }
@@ -405,9 +407,10 @@ spmm_status_t spmm_plan_static(int64_t m, int64_t k, int32_t b, const uint8_t* b
   if (!out) return fail(SPMM_ERR_INVALID_ARG, "out is NULL");
   *out = nullptr;
   if (m < 1 || k < 1) return fail(SPMM_ERR_INVALID_ARG, "m and k must be positive");
-  if (!valid_block(b)) return fail(SPMM_ERR_INVALID_ARG, "block size must be one of 1, 4, 8, 16, 32");
+  if (!valid_static_block(b)) return fail(SPMM_ERR_INVALID_ARG, "block size must be one of 1, 4, 8, 16, 32, 64");
   if (!block_mask_host) return fail(SPMM_ERR_INVALID_ARG, "block mask is NULL");
   if (!dtype_triple_supported(w, x, y)) return fail(SPMM_ERR_UNSUPPORTED, "unsupported dtype combination");
+  if (b == 64 && x != SPMM_F16 && x != SPMM_BF16) return fail(SPMM_ERR_UNSUPPORTED, "b = 64 needs FP16 or BF16 X");
   if (m > INT32_MAX / 2 || k > INT32_MAX / 2) return fail(SPMM_ERR_UNSUPPORTED, "m or k too large");
   const int64_t mb = ceil_div(m, b), kb = ceil_div(k, b);
   int64_t nnzb = 0;
@@ -464,7 +467,7 @@ spmm_status_t spmm_plan_static(int64_t m, int64_t k, int32_t b, const uint8_t* b
     e = hipMemcpy(rp.data(), p->pb.row_ptr, sizeof(int32_t) * rp.size(), hipMemcpyDeviceToHost);
     if (e != hipSuccess) st = fail_hip(e, "row pointer download");
     if (st == SPMM_OK && uses_pipe(b, x) && b == 16) st = classify_heavy_rows(p, rp);
-    if (st == SPMM_OK) st = build_sddmm_tasks(p, rp);
+    if (st == SPMM_OK && b <= 32) st = build_sddmm_tasks(p, rp);
   }
   if (s) (void)hipStreamDestroy(s);
   if (mask_dev) (void)hipFree(mask_dev);
@@ -477,6 +480,7 @@ spmm_status_t spmm_plan_static(int64_t m, int64_t k, int32_t b, const uint8_t* b
     if (p->heavy_flag) (void)hipFree(p->heavy_flag);
     if (p->heavy_rows) (void)hipFree(p->heavy_rows);
     if (p->sddmm_tasks) (void)hipFree(p->sddmm_tasks);
+    if (p->ell_slot) (void)hipFree(p->ell_slot);
     delete p;
     return st;
   }
@@ -627,6 +631,7 @@ spmm_status_t spmm_plan_destroy(spmm_plan_t p) {
   if (p->heavy_flag) (void)hipFree(p->heavy_flag);
   if (p->heavy_rows) (void)hipFree(p->heavy_rows);
   if (p->sddmm_tasks) (void)hipFree(p->sddmm_tasks);
+  if (p->ell_slot) (void)hipFree(p->ell_slot);
   delete p;
   return SPMM_OK;
 }

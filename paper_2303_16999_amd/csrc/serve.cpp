@@ -481,7 +481,7 @@ spmm_status_t spmm_serve_create(const spmm_plan_t* layer_plans, int32_t num_laye
       st = fail_hip(e, "hipStreamCreate");
     if (st == SPMM_OK && opts->mode == SPMM_SERVE_CONTINUOUS) {
       for (int l = 0; l < num_layers && st == SPMM_OK; ++l)
-        if (!plan_uses_row_kernel(s->plans[l]) || s->plans[l]->w == SPMM_FP8_E4M3 ||
+        if (!plan_uses_row_kernel(s->plans[l]) || s->plans[l]->w == SPMM_FP8_E4M3 || s->plans[l]->b > 32 ||
             s->plans[l]->b != s->plans[0]->b || s->plans[l]->w != s->plans[0]->w || s->plans[l]->y != s->plans[0]->y)
           st = fail(SPMM_ERR_UNSUPPORTED,
                     "continuous batching needs layers of one block size (16 or 32) and one 16-bit dtype");

@@ -368,7 +368,7 @@ __device__ __forceinline__ void row_tile_whole(const RowProblem& p, int32_t r, i
           acc[0][s] = Mma<XT>::k32(a[f], u32x4{b1[f][s].x, b1[f][s].y, b2[f][s].x, b2[f][s].y}, acc[0][s]);
       }
     }
-  } else if constexpr (!kFp8) {  // B == 32: k slots 0-3 and 4-7 are rows 8g..8g+3 and 8g+4..8g+7
+  } else if constexpr (!kFp8) {  // B == 32: k slots 0-3 and 4-7 are rows 8g..8g+3 and 8g+4..8g+7 k slots 0-3 and 4-7 are rows 8g..8g+3 and 8g+4..8g+7
     for (int32_t q = q_lo; q < q_hi; ++q) {
       const int32_t c = uniform(p.col_idx[q]);
       u32x2 b1[NS], b2[NS];
@@ -460,6 +460,62 @@ __device__ __forceinline__ void row_tile_whole(const RowProblem& p, int32_t r, i
   }
 }
 
+// b = 64: the four waves of a workgroup share block row r, wave h computing
+// its rows 16h .. 16h + 15 for columns n0 .. n0 + 16*NS. A block is two K = 32
+// slices (k rows 32t .. 32t + 31; in a slice, k slots 0-3 and 4-7 are rows
+// 8g .. 8g + 3 and 8g + 4 .. 8g + 7). The four waves read the same X slabs at
+// about the same time, so the CU's L1 serves most of the repeats. FP8 blocks
+// keep an FP32 partial over both slices and scale it.
+template <typename XT, typename WT, typename YT, int NS>
+__device__ __forceinline__ void row_tile_b64(const RowProblem& p, int32_t r, int h, int32_t n0, int lane) {
+  constexpr bool kFp8 = __is_same(WT, Fp8);
+  constexpr int WB = 64 * 64 * (kFp8 ? 1 : 2);  // bytes per block
+  const int g = lane >> 4, j = lane & 15;
+  __amdgpu_buffer_rsrc_t xr = __builtin_amdgcn_make_buffer_rsrc((void*)p.X, (short)0, (int)p.x_bytes, 0x00020000);
+  const uint8_t* __restrict__ Wb = (const uint8_t*)p.W;
+  float4_t acc[1][NS];
+#pragma unroll
+  for (int s = 0; s < NS; ++s) acc[0][s] = float4_t{0.f, 0.f, 0.f, 0.f};
+  const int32_t q_lo = uniform(p.row_ptr[r]), q_hi = uniform(p.row_ptr[r + 1]);
+  const int32_t* __restrict__ widx = p.w_index;
+  for (int32_t q = q_lo; q < q_hi; ++q) {
+    const int32_t c = uniform(p.col_idx[q]);
+    const int64_t qv = widx ? (int64_t)uniform(widx[q]) : (int64_t)q;
+    u32x2 b1[2][NS], b2[2][NS];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      xfrag<NS>(xr, p, c * 64 + 32 * t, 2 * g, j, n0, b1[t]);      // rows c*64 + 32t + 8g + i
+      xfrag<NS>(xr, p, c * 64 + 32 * t + 4, 2 * g, j, n0, b2[t]);  // rows c*64 + 32t + 8g + 4 + i
+    }
+    if constexpr (!kFp8) {
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        const u32x4 a = *(const u32x4*)(Wb + qv * WB + ((h * 16 + j) * 64 + 32 * t + g * 8) * 2);
+#pragma unroll
+        for (int s = 0; s < NS; ++s)
+          acc[0][s] = Mma<XT>::k32(a, u32x4{b1[t][s].x, b1[t][s].y, b2[t][s].x, b2[t][s].y}, acc[0][s]);
+      }
+    } else {
+      const float sc = p.scales[qv];
+      float4_t part[NS];
+#pragma unroll
+      for (int s = 0; s < NS; ++s) part[s] = float4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        const u32x2 codes = *(const u32x2*)(Wb + qv * WB + (h * 16 + j) * 64 + 32 * t + g * 8);
+        const u32x2 lo = fp8x4<XT>(codes.x), hi = fp8x4<XT>(codes.y);
+        const u32x4 a = {lo.x, lo.y, hi.x, hi.y};
+#pragma unroll
+        for (int s = 0; s < NS; ++s)
+          part[s] = Mma<XT>::k32(a, u32x4{b1[t][s].x, b1[t][s].y, b2[t][s].x, b2[t][s].y}, part[s]);
+      }
+#pragma unroll
+      for (int s = 0; s < NS; ++s) acc[0][s] += sc * part[s];
+    }
+  }
+  row_store<YT, 16, NS>(p, 4 * r + h, n0, lane, acc);  // rows 64r + 16h + 4g + i
+}
+
 // The work of one wave in a launch with split rows (light unit).
 template <typename XT, typename WT, typename YT, int B, int NS>
 __device__ __forceinline__ void row_tile(const RowProblem& p, int32_t r, int32_t n0, int lane) {
@@ -488,7 +544,10 @@ template <typename XT, typename WT, typename YT, int B, int NS, bool SPLIT>
 __device__ __forceinline__ void row_unit(const RowProblem& p, int32_t unit, int lane, int wave, float4_t* red) {
   constexpr int H = B / 16;
   static_assert(!SPLIT || B == 16, "rows are split for b = 16 only");
-  if constexpr (!SPLIT) {
+  if constexpr (B == 64) {  // a unit is one block row: its four row tiles go to the four waves
+    row_tile_b64<XT, WT, YT, NS>(p, unit % p.mb, wave, (unit / p.mb) * (16 * NS), lane);
+    return;
+  } else if constexpr (!SPLIT) {
     const int32_t rgroups = (p.mb + kRowsPerWg - 1) / kRowsPerWg;
     const int32_t r = (unit % rgroups) * kRowsPerWg + wave;
     if (r >= p.mb) return;
@@ -599,7 +658,8 @@ spmm_status_t launch_row(const RunArgs& a, const int32_t* row_ptr, const int32_t
   prm.pr = row_problem(a, row_ptr, col_idx);
   prm.status = a.status;
   const int ns = prm.pr.ns;
-  const int64_t units = problem_units(a.plan.mb, a.n, ns, prm.pr.num_heavy);
+  const int64_t units = B == 64 ? (int64_t)a.plan.mb * ceil_div(a.n, 16 * ns)
+                                : problem_units(a.plan.mb, a.n, ns, prm.pr.num_heavy);
   if (units == 0) return SPMM_OK;
   if (units > (int64_t)INT32_MAX) return fail(SPMM_ERR_UNSUPPORTED, "too many work units");
   prm.num_units = (int32_t)units;

@@ -13,7 +13,11 @@ static spmm_status_t row_y(const RunArgs& a, const int32_t* rp, const int32_t* c
     if (a.yt == SPMM_F32) return row::launch_row<XT, WT, float, 32>(a, rp, ci, s);
     return row::launch_row<XT, WT, XT, 32>(a, rp, ci, s);
   }
-  return fail(SPMM_ERR_UNSUPPORTED, "row-wise kernel handles block sizes 16 and 32");
+  if (a.plan.b == 64) {
+    if (a.yt == SPMM_F32) return row::launch_row<XT, WT, float, 64>(a, rp, ci, s);
+    return row::launch_row<XT, WT, XT, 64>(a, rp, ci, s);
+  }
+  return fail(SPMM_ERR_UNSUPPORTED, "row-wise kernel handles block sizes 16, 32 and 64");
 }
 
 spmm_status_t launch_spmm_row(const RunArgs& a, const int32_t* row_ptr, const int32_t* col_idx, hipStream_t s) {

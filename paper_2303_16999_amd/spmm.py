@@ -75,6 +75,10 @@ SIGNATURES = {
     "spmm_serve_destroy": ([_vp], _c_i32),
     "spmm_serve_clock": ([], ctypes.c_double),
     "spmm_plan_transpose": ([_vp, ctypes.POINTER(PlanOpts), ctypes.POINTER(_vp)], _c_i32),
+    "spmm_plan_ell": ([_c_i64, _c_i64, _c_i32, _c_i32, _vp, _c_i32, _c_i32, _c_i32, ctypes.POINTER(PlanOpts),
+                       ctypes.POINTER(_vp)], _c_i32),
+    "spmm_plan_set_values_ell": ([_vp, _vp, _vp, _vp], _c_i32),
+    "spmm_speedup_model": ([_c_i64, ctypes.c_double, _c_i32, ctypes.POINTER(ctypes.c_double)], _c_i32),
     "spmm_sddmm": ([_vp, _c_i64, _vp, _c_i64, _vp, _c_i64, _vp, _vp], _c_i32),
 }
 
@@ -186,6 +190,31 @@ class StaticPlan:
         check(lib().spmm_plan_export(self._h, row_ptr.ctypes.data_as(_vp), col_idx.ctypes.data_as(_vp),
                                      panel_ptr.ctypes.data_as(_vp)))
         return {"row_ptr": row_ptr, "col_idx": col_idx[: inf["nnzb"]], "panel_ptr": panel_ptr}
+
+    @classmethod
+    def from_ell(cls, m, k, b, ell_cols, w="f16", x=None, y=None, group_rows=0, num_panels=0, n_hint=0, variant=0):
+        """spmm_plan_ell: a plan from a blocked-ELL pattern (int32 [ceil(m/b), width], -1 = empty slot)."""
+        x = x or ("f16" if w == "fp8" else w)
+        y = y or x
+        cols = np.ascontiguousarray(np.asarray(ell_cols, dtype=np.int32))
+        mb = -(-int(m) // int(b))
+        if cols.ndim != 2 or cols.shape[0] != mb:
+            raise ValueError("ell_cols must have shape (ceil(m/b), width)")
+        t = cls.__new__(cls)
+        t.m, t.k, t.b = int(m), int(k), int(b)
+        t.w, t.x, t.y = DTYPE_CODES[w], DTYPE_CODES[x], DTYPE_CODES[y]
+        h = _vp()
+        opts = _opts(group_rows, num_panels, n_hint, variant)
+        check(lib().spmm_plan_ell(t.m, t.k, t.b, int(cols.shape[1]), cols.ctypes.data_as(_vp), t.w, t.x, t.y,
+                                  ctypes.byref(opts), ctypes.byref(h)))
+        t._h = h
+        t.mb, t.kb = mb, -(-t.k // t.b)
+        t.ell_width = int(cols.shape[1])
+        return t
+
+    def set_values_ell(self, values, scales=None, stream=None):
+        """spmm_plan_set_values_ell: values in ELL slot order [ceil(m/b), width, b, b]."""
+        check(lib().spmm_plan_set_values_ell(self._h, _ptr(values), _ptr(scales), _stream(stream)))
 
     def transpose(self, group_rows=0, num_panels=0, n_hint=0, variant=0):
         """spmm_plan_transpose: the plan of W^T (k x m) with the values transposed."""
@@ -380,3 +409,10 @@ class Server:
 
 def clock():
     return lib().spmm_serve_clock()
+
+
+def speedup_model(m, density, b):
+    """spmm_speedup_model: predicted static sparse / dense FP16 speedup on MI355X."""
+    out = ctypes.c_double()
+    check(lib().spmm_speedup_model(int(m), float(density), int(b), ctypes.byref(out)))
+    return out.value

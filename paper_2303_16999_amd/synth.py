@@ -84,6 +84,22 @@ def concentrated_mask(mb, kb, d, seed):
     return M
 
 
+def ell_from_mask(M, width, seed):
+    """Blocked-ELL description of a mask: int32 [mb, width], each row's block
+    columns in a seeded random slot order, -1 in the remaining slots."""
+    M = np.asarray(M)
+    counts = M.sum(1)
+    if counts.max(initial=0) > width:
+        raise ValueError("ELL width below the longest row")
+    g = rng(seed)
+    cols = np.full((M.shape[0], width), -1, np.int32)
+    for r in range(M.shape[0]):
+        c = np.nonzero(M[r])[0]
+        slots = g.permutation(width)[: c.size]
+        cols[r, slots] = c
+    return cols
+
+
 def mask_coo(M):
     """Row-major (CSR-order) list of the nonzero blocks of a mask."""
     rr, cc = np.nonzero(np.asarray(M))

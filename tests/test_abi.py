@@ -39,7 +39,7 @@ def _plan(m=64, k=64, b=16, w=spmm.F16, x=spmm.F16, y=spmm.F16, mask=None, opts=
     return st, h
 
 
-@pytest.mark.parametrize("b", [0, 2, 3, 64, -16])
+@pytest.mark.parametrize("b", [0, 2, 3, 48, 128, -16])
 def test_bad_block_size_is_invalid_arg(b):
     st, h = _plan(b=b, mask=np.ones((4, 4), np.uint8))
     assert st == spmm.ERR_INVALID_ARG and not h.value
@@ -95,3 +95,33 @@ def test_autotune_and_group_reject_bad_arguments():
     assert L.spmm_group_create(4, None) == spmm.ERR_INVALID_ARG
     assert L.spmm_group_run(None, 1, None, None, None, None, None, None, None, None) == spmm.ERR_INVALID_ARG
     assert L.spmm_group_destroy(None) == spmm.OK
+
+
+def test_b64_needs_16bit_x():
+    st, h = _plan(m=128, k=128, b=64, w=spmm.F32, x=spmm.F32, y=spmm.F32, mask=np.ones((2, 2), np.uint8))
+    assert st == spmm.ERR_UNSUPPORTED and not h.value
+    assert b"b = 64" in spmm.lib().spmm_last_error()
+
+
+def _ell(cols, m=64, k=64, b=16):
+    cols = np.ascontiguousarray(np.asarray(cols, np.int32))
+    h = ctypes.c_void_p()
+    st = spmm.lib().spmm_plan_ell(m, k, b, cols.shape[1], cols.ctypes.data_as(ctypes.c_void_p), spmm.F16, spmm.F16,
+                                  spmm.F16, None, ctypes.byref(h))
+    return st, h
+
+
+@pytest.mark.parametrize("cols", [[[0, 4], [1, -1], [2, 3], [0, 1]],      # column 4 is outside kb = 4
+                                  [[0, -2], [1, -1], [2, 3], [0, 1]],     # -2 is not the empty marker
+                                  [[1, 1], [1, -1], [2, 3], [0, 1]]])     # column twice in a row
+def test_ell_rejects_bad_patterns_before_touching_the_device(cols):
+    st, h = _ell(cols)
+    assert st == spmm.ERR_INVALID_ARG and not h.value
+
+
+def test_ell_rejects_null_and_negative_width():
+    h = ctypes.c_void_p()
+    L = spmm.lib()
+    assert L.spmm_plan_ell(64, 64, 16, 2, None, spmm.F16, spmm.F16, spmm.F16, None, ctypes.byref(h)) == spmm.ERR_INVALID_ARG
+    assert L.spmm_plan_ell(64, 64, 16, -1, None, spmm.F16, spmm.F16, spmm.F16, None, ctypes.byref(h)) == spmm.ERR_INVALID_ARG
+    assert L.spmm_plan_set_values_ell(None, None, None, None) == spmm.ERR_INVALID_ARG

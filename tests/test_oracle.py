@@ -141,3 +141,55 @@ def test_flop_count_with_partial_blocks_matches_element_mask():
 def test_rel_fro_matches_definition():
     a = np.array([[3.0, 4.0]])
     assert O.rel_fro(a + np.array([[0.3, 0.4]]), a) == pytest.approx(0.1, rel=1e-15)
+
+
+@pytest.mark.parametrize("b", [1, 3, 16, 64])
+def test_ell_oracle_against_bruteforce_and_blockwise(b):
+    from oracle import ell_ref as E
+    from paper_2303_16999_amd import synth
+    g = np.random.default_rng(300 + b)
+    for trial in range(4):
+        m, k, n = int(g.integers(1, 3 * b + 2)), int(g.integers(1, 3 * b + 2)), int(g.integers(1, 6))
+        mb, kb = -(-m // b), -(-k // b)
+        M = (g.random((mb, kb)) < [0.0, 1.0, 0.4, 0.7][trial]).astype(np.uint8)
+        width = int(M.sum(1).max(initial=0)) + 1
+        cols = synth.ell_from_mask(M, width, trial)
+        vals = g.standard_normal((mb, width, b, b))
+        X = g.standard_normal((k, n))
+        Yb = E.ell_bruteforce(m, k, b, cols, vals, X)
+        np.testing.assert_allclose(E.ell_spmm(m, k, b, cols, vals, X), Yb, rtol=1e-12, atol=1e-12)
+        # the same blocks in CSR order through the Section 3 oracle
+        rr, cc = np.nonzero(M)
+        slot_of = {(r, int(cols[r, s])): s for r in range(mb) for s in range(width) if cols[r, s] >= 0}
+        csr_vals = np.stack([vals[r, slot_of[(r, c)]] for r, c in zip(rr, cc)]) if rr.size else np.zeros((0, b, b))
+        np.testing.assert_allclose(O.spmm_blockwise(m, k, b, rr, cc, csr_vals, X), Yb, rtol=1e-12, atol=1e-12)
+
+
+def test_ell_empty_slots_contribute_nothing():
+    from oracle import ell_ref as E
+    cols = -np.ones((3, 4), np.int32)
+    vals = np.full((3, 4, 2, 2), np.nan)  # never read
+    assert not E.ell_spmm(6, 5, 2, cols, vals, np.ones((5, 3))).any()
+
+
+def test_ell_from_mask_round_trip():
+    from paper_2303_16999_amd import synth
+    M = synth.block_mask(40, 30, 0.2, 7)
+    cols = synth.ell_from_mask(M, int(M.sum(1).max()) + 3, 1)
+    back = np.zeros_like(M)
+    for r in range(M.shape[0]):
+        for c in cols[r]:
+            if c >= 0:
+                back[r, c] = 1
+    assert np.array_equal(back, M)
+    assert ((cols >= 0).sum(1) == M.sum(1)).all()
+
+
+def test_b64_expand_matches_bruteforce_definition():
+    g = np.random.default_rng(164)
+    for trial in range(3):
+        m, k, n = int(g.integers(1, 150)), int(g.integers(1, 150)), int(g.integers(1, 4))
+        M, W, X, rr, cc, vals = _random_case(g, m, k, n, 64, [1.0, 0.5, 0.3][trial])
+        Yb = O.spmm_bruteforce(M, W, X, 64)
+        np.testing.assert_allclose(O.spmm_expand(m, k, 64, rr, cc, vals, X), Yb, rtol=1e-12, atol=1e-12)
+        np.testing.assert_allclose(O.spmm_blockwise(m, k, 64, rr, cc, vals, X), Yb, rtol=1e-12, atol=1e-12)
