@@ -146,6 +146,8 @@ struct RunArgs {
 spmm_status_t launch_spmm(const RunArgs& a, hipStream_t stream);
 // Row-wise kernel (16-bit X, b = 16 or 32): W and scales in block-CSR order.
 spmm_status_t launch_spmm_row(const RunArgs& a, const int32_t* row_ptr, const int32_t* col_idx, hipStream_t stream);
+// Row-wise FP32 kernel (FP32 W, X, Y; b = 16 or 32): W in block-CSR order.
+spmm_status_t launch_spmm_row_f32(const RunArgs& a, const int32_t* row_ptr, const int32_t* col_idx, hipStream_t stream);
 // Grouped row-wise launches (16-bit W and X, b = 16/32): one workgroup per
 // work unit of all problems. The table of problem descriptors is either in
 // the kernel arguments (at most group_inline_max() problems; built with

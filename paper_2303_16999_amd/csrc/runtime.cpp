@@ -178,6 +178,13 @@ static bool use_row_kernel() {
   return !(e && std::string(e) == "pipe");
 }
 
+// FP32 plans with b = 16/32 run on the row-wise FP32 kernel unless
+// SPMM_KERNEL=general (for comparisons) asks for the LDS-staged kernel.
+static bool use_row_kernel_f32() {
+  const char* e = getenv("SPMM_KERNEL");
+  return !(e && (std::string(e) == "general" || std::string(e) == "pipe"));
+}
+
 static void free_plan_buffers(PlanBuffers& pb) {
   int32_t* ptrs[] = {pb.cell_ptr, pb.ent_col, pb.ent_src, pb.panel_ptr, pb.row_ptr, pb.col_idx, pb.csr_src, pb.scratch};
   for (int32_t* p : ptrs)
@@ -325,6 +332,10 @@ spmm_status_t run_plan(const spmm_plan_s* p, int64_t n, const void* X, int64_t l
     a.heavy_flag = p->heavy_flag;
     a.heavy_rows = p->heavy_rows;
     return launch_spmm_row(a, p->pb.row_ptr, p->pb.col_idx, stream);
+  }
+  if (p->x == SPMM_F32 && p->b >= 16 && use_row_kernel_f32()) {
+    a.W = p->values_csr;
+    return launch_spmm_row_f32(a, p->pb.row_ptr, p->pb.col_idx, stream);
   }
   if (relu) return fail(SPMM_ERR_UNSUPPORTED, "fused ReLU needs a block-CSR kernel");
   return launch_spmm(a, stream);
