@@ -178,6 +178,21 @@ def dense_fp16(m, k, n, steps, warmup, useful_flops):
             "tflops_dense": 2.0 * m * k * n / (ms * 1e-3) / 1e12}
 
 
+def dense_gemm(m, k, n, steps, warmup, dt):
+    """ms of the dense GEMM (m x k) @ (k x n) in dtype dt on the GPU (FP32 without TF32)."""
+    import torch
+    if dt == "f16":
+        return dense_fp16(m, k, n, steps, warmup, 1.0)["ms"]
+    torch.backends.cuda.matmul.allow_tf32 = False
+    g = torch.Generator(device="cuda").manual_seed(1234)
+    A = torch.randn((m, k), device="cuda", dtype=torch.float32, generator=g)
+    B = torch.randn((k, n), device="cuda", dtype=torch.float32, generator=g)
+    C = torch.empty((m, n), device="cuda", dtype=torch.float32)
+    ms = time_steps(lambda: torch.matmul(A, B, out=C), steps, warmup)
+    del A, B, C
+    return ms
+
+
 def cpu_baseline(prob, target_s=10.0):
     """The FP64 oracle (blockwise form) on a bounded column sample of the same workload."""
     from oracle import spmm_ref as O
@@ -594,17 +609,18 @@ def mode_group(args):
 
 
 def mode_table3(args):
-    """Static and dynamic sparse against dense FP16 at m = k = 4096, d = 1/16,
-    b in {1, 4, 16}, best over n: the shape of the paper's static-vs-dynamic
-    comparison. The dynamic call re-encodes the static pattern (COO in random
-    order) on every call."""
+    """Static and dynamic sparse against dense at m = k = 4096, d = 1/16,
+    b in {1, 4, 16}, FP16 and FP32, best over n: the shape of the paper's
+    static-vs-dynamic comparison (Table 3; dense of the same dtype). The
+    dynamic call re-encodes the static pattern (COO in random order) on every
+    call."""
     import torch
     from paper_2303_16999_amd import spmm
     m = k = 4096
-    for b in (1, 4, 16):
+    for dt, b in [("f16", 1), ("f16", 4), ("f16", 16), ("f32", 1), ("f32", 4), ("f32", 16)]:
         best = {"static": 0.0, "dynamic": 0.0}
         for n in (1024, 4096, 16384):
-            prob = StaticProblem(m, k, n, b, 1 / 16, "f16", seed=0)
+            prob = StaticProblem(m, k, n, b, 1 / 16, dt, seed=0)
             ms_s = time_steps(prob.step, args.steps, args.warmup)
             perm = np.random.default_rng(1).permutation(prob.nnzb)
             r = torch.from_numpy(prob.rows[perm].copy()).cuda()
@@ -612,11 +628,11 @@ def mode_table3(args):
             v = prob.values_dev[torch.from_numpy(perm).cuda()].contiguous()
             nnz = torch.tensor([prob.nnzb], dtype=torch.int32, device="cuda")
             status = torch.zeros(1, dtype=torch.int32, device="cuda")
-            h = spmm.DynamicHandle(m, k, b, prob.nnzb, "f16", n_hint=n)
+            h = spmm.DynamicHandle(m, k, b, prob.nnzb, dt, n_hint=n)
             ms_d = time_steps(lambda: h.run(nnz, r, c, v, prob.X, prob.Y, status), args.steps, args.warmup)
             assert int(status.item()) == 0
-            dn = dense_fp16(m, k, n, args.steps, args.warmup, 1.0)["ms"]
-            rec = {"mode": "table3", "m": m, "k": k, "n": n, "b": b, "density": 1 / 16,
+            dn = dense_gemm(m, k, n, args.steps, args.warmup, dt)
+            rec = {"mode": "table3", "dtype": dt, "m": m, "k": k, "n": n, "b": b, "density": 1 / 16,
                    "static_ms": round(ms_s, 5), "dynamic_ms": round(ms_d, 5), "dense_ms": round(dn, 5),
                    "static_over_dense": round(dn / ms_s, 3), "dynamic_over_dense": round(dn / ms_d, 3),
                    "static_tflops": round(prob.flops() / (ms_s * 1e-3) / 1e12, 3)}
@@ -625,7 +641,7 @@ def mode_table3(args):
             best["dynamic"] = max(best["dynamic"], rec["dynamic_over_dense"])
             del prob, h, v
             torch.cuda.empty_cache()
-        emit({"mode": "table3_best_over_n", "b": b, "static_over_dense": best["static"],
+        emit({"mode": "table3_best_over_n", "dtype": dt, "b": b, "static_over_dense": best["static"],
               "dynamic_over_dense": best["dynamic"]}, args.out)
 
 

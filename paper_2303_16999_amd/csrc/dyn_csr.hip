@@ -158,6 +158,7 @@ __global__ void k_dyn_status_out(const int32_t* __restrict__ internal, int32_t* 
 // the panel boundaries, then the status words. Used when the capacity fits in
 // LDS; the result is identical to the multi-kernel path's.
 constexpr int kSmallThreads = 1024;
+constexpr int kSmallU = 8;  // entries per thread per chunk
 
 // Inclusive scan across the 64 lanes of a wave (shuffles, no LDS).
 template <typename T>
@@ -225,11 +226,26 @@ __global__ __launch_bounds__(1024) void k_dyn_small(const int32_t* __restrict__ 
   for (int32_t r = tid; r < mb; r += kSmallThreads) cnt[r] = 0;
   __syncthreads();
   const int32_t nnz = flag[1];
+  // Entries are read in chunks of kSmallU per thread, all loads of a chunk
+  // issued before its LDS atomics (a load-atomic chain per entry would pay
+  // the global latency once per entry). Up to kSmallThreads * kSmallU entries
+  // the chunk stays in registers for the scatter pass below.
+  int32_t er[kSmallU], ec[kSmallU];
   if (flag[0] == 0) {
-    for (int32_t e = tid; e < nnz; e += kSmallThreads) {
-      const int32_t r = rows[e], c = cols[e];
-      if (r < 0 || r >= mb || c < 0 || c >= kb) atomicMax(&flag[0], (int32_t)SPMM_ERR_BAD_INDEX);
-      else atomicAdd(&cnt[r], 1);
+    for (int32_t base = 0; base < nnz; base += kSmallThreads * kSmallU) {
+#pragma unroll
+      for (int u = 0; u < kSmallU; ++u) {
+        const int32_t e = base + u * kSmallThreads + tid;
+        er[u] = e < nnz ? rows[e] : 0;
+        ec[u] = e < nnz ? cols[e] : 0;
+      }
+#pragma unroll
+      for (int u = 0; u < kSmallU; ++u) {
+        const int32_t e = base + u * kSmallThreads + tid;
+        if (e >= nnz) continue;
+        if (er[u] < 0 || er[u] >= mb || ec[u] < 0 || ec[u] >= kb) atomicMax(&flag[0], (int32_t)SPMM_ERR_BAD_INDEX);
+        else atomicAdd(&cnt[er[u]], 1);
+      }
     }
   }
   __syncthreads();
@@ -244,11 +260,24 @@ __global__ __launch_bounds__(1024) void k_dyn_small(const int32_t* __restrict__ 
   block_exscan_chunks<int32_t, int32_t>(cnt, mb, rp, part);
   for (int32_t r = tid; r < mb; r += kSmallThreads) cnt[r] = rp[r];
   __syncthreads();
-  for (int32_t e = tid; e < nnz; e += kSmallThreads) {
-    const int32_t r = rows[e];
-    const int32_t pos = atomicAdd(&cnt[r], 1);
-    ekey[pos] = ((uint32_t)cols[e] << 16) | (uint32_t)e;
-    erow[pos] = (uint16_t)r;
+  const bool in_regs = nnz <= kSmallThreads * kSmallU;
+  for (int32_t base = 0; base < nnz; base += kSmallThreads * kSmallU) {
+    if (!in_regs) {
+#pragma unroll
+      for (int u = 0; u < kSmallU; ++u) {
+        const int32_t e = base + u * kSmallThreads + tid;
+        er[u] = e < nnz ? rows[e] : 0;
+        ec[u] = e < nnz ? cols[e] : 0;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kSmallU; ++u) {
+      const int32_t e = base + u * kSmallThreads + tid;
+      if (e >= nnz) continue;
+      const int32_t pos = atomicAdd(&cnt[er[u]], 1);
+      ekey[pos] = ((uint32_t)ec[u] << 16) | (uint32_t)e;
+      erow[pos] = (uint16_t)er[u];
+    }
   }
   __syncthreads();
   // every staged entry is ranked within its row by (column, input index),

@@ -62,7 +62,7 @@ static bool valid_block(int32_t b) { return b == 1 || b == 4 || b == 8 || b == 1
 static bool valid_static_block(int32_t b) { return valid_block(b) || b == 64; }
 
 bool uses_pipe(int32_t b, spmm_dtype_t x) { return b >= 16 && (x == SPMM_F16 || x == SPMM_BF16); }
-bool uses_csr(int32_t b, spmm_dtype_t x) { return b < 16 || uses_pipe(b, x); }
+bool uses_csr(int32_t b, spmm_dtype_t x) { return b < 16 || uses_pipe(b, x) || (x == SPMM_F32 && b <= 32); }
 
 Geometry choose_geometry(int64_t m, int64_t k, int32_t b, int64_t nnz_hint, int64_t n_hint,
                          const spmm_plan_opts* opts, int num_cus, spmm_dtype_t x) {
@@ -764,6 +764,7 @@ spmm_status_t spmm_run_dynamic(spmm_dyn_t h, const int32_t* nnzb_dev, const int3
     a.nnz = h->max_nnzb;
     a.ns = h->b < 16 ? 0 : default_ns(n);
     if (h->b < 16) return launch_spmm_small(a, h->pb.row_ptr, h->pb.col_idx, s);
+    if (h->x == SPMM_F32) return launch_spmm_row_f32(a, h->pb.row_ptr, h->pb.col_idx, s);
     return launch_spmm_row(a, h->pb.row_ptr, h->pb.col_idx, s);
   }
   st = build_dynamic_plan(nnzb_dev, rows, cols, (int32_t)h->max_nnzb, h->mb, h->kb, h->geo, h->pb, h->status,

@@ -25,6 +25,8 @@ constexpr int kRows = 4;  // block rows per workgroup, one per wave
 struct P32 {
   const int32_t* row_ptr;
   const int32_t* col_idx;
+  const int32_t* w_index;  // dynamic mode: value block of each CSR entry (nullptr: the entry itself)
+  const int32_t* status;   // dynamic mode: skip everything unless *status == 0 (nullptr: run)
   const float* W;
   const float* X;
   float* Y;
@@ -59,6 +61,7 @@ __device__ __forceinline__ void load_x(__amdgpu_buffer_rsrc_t xr, int64_t row, i
 template <int B, int NS>
 __global__ __launch_bounds__(256) void k_spmm_row_f32(P32 p) {
   constexpr int H = B / 16, KS = B / 4;  // row tiles, MFMAs (k slices of one per lane group) per block
+  if (p.status && *p.status) return;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int g = lane >> 4, j = lane & 15;
   const int32_t unit = xcd_unit(blockIdx.x, p.num_units);
@@ -76,12 +79,13 @@ __global__ __launch_bounds__(256) void k_spmm_row_f32(P32 p) {
   const int32_t q_lo = uniform(p.row_ptr[r]), q_hi = uniform(p.row_ptr[r + 1]);
   for (int32_t q = q_lo; q < q_hi; ++q) {
     const int32_t c = uniform(p.col_idx[q]);
+    const int64_t qv = p.w_index ? (int64_t)uniform(p.w_index[q]) : (int64_t)q;
     float xv[KS][NS];
 #pragma unroll
     for (int t = 0; t < KS; ++t) load_x<NS>(xr, (int64_t)c * B + g * KS + t, p.k, p.ldx, col, xv[t]);
 #pragma unroll
     for (int h = 0; h < H; ++h) {
-      const float* wrow = p.W + (int64_t)q * B * B + (int64_t)(16 * h + j) * B + g * KS;
+      const float* wrow = p.W + qv * B * B + (int64_t)(16 * h + j) * B + g * KS;
       float wv[KS];
 #pragma unroll
       for (int t = 0; t < KS; t += 4) {
@@ -126,6 +130,8 @@ spmm_status_t launch_spmm_row_f32(const RunArgs& a, const int32_t* row_ptr, cons
   P32 p;
   p.row_ptr = row_ptr;
   p.col_idx = col_idx;
+  p.w_index = a.w_index;
+  p.status = a.status;
   p.W = (const float*)a.W;
   p.X = (const float*)a.X;
   p.Y = (float*)a.Y;

@@ -163,3 +163,41 @@ def test_one_workgroup_encoder_equals_multi_kernel_encoder(w, b, monkeypatch):
     for ex in exports:
         for key in ("row_ptr", "col_idx", "src", "panel_ptr"):
             assert np.array_equal(ex[key], ref[key]), key
+
+
+@pytest.mark.parametrize("b", [16, 32])
+@pytest.mark.parametrize("ragged", [False, True])
+def test_dynamic_fp32_matches_static_and_oracle(b, ragged):
+    # FP32 dynamic calls run the row-wise FP32 kernel: bitwise equal to the static plan of the same
+    # pattern; a k that b does not divide goes through the copying encoder
+    m, k = 37 * b + (5 if ragged else 0), 29 * b + (b // 2 if ragged else 0)
+    c = Case(m, k, 150, b, 1 / 6, w="f32", seed=300 + b)
+    plan, Ys = c.run_static()
+    max_nnz = len(c.rows) + 9
+    perm = np.random.default_rng(6).permutation(len(c.rows))
+    r, col, v, nnz = _dyn_inputs(c.rows[perm], c.cols[perm], c.vals_store[perm], max_nnz, b)
+    h = spmm.DynamicHandle(c.m, c.k, b, max_nnz, "f32")
+    _, X, _ = c.device_inputs()
+    Yd = c.new_Y()
+    status = torch.full((1,), -1, dtype=torch.int32, device="cuda")
+    h.run(nnz, r, col, v, X, Yd, status, n=c.n)
+    torch.cuda.synchronize()
+    assert status.item() == 0
+    assert torch.equal(Ys[:, : c.n], Yd[:, : c.n])
+    assert O.rel_fro(y_f64(Yd, c), c.oracle()) <= 1e-5
+
+
+def test_dynamic_fp32_bad_index_leaves_y_untouched():
+    b, m, k = 16, 160, 160
+    h = spmm.DynamicHandle(m, k, b, 8, "f32")
+    r = torch.tensor([0, 1, 99, 0, 0, 0, 0, 0], dtype=torch.int32, device="cuda")
+    c = torch.zeros(8, dtype=torch.int32, device="cuda")
+    v = torch.ones((8, b, b), dtype=torch.float32, device="cuda")
+    nnz = torch.tensor([3], dtype=torch.int32, device="cuda")
+    X = torch.ones((k, 16), dtype=torch.float32, device="cuda")
+    Y = torch.full((m, 16), 7.0, dtype=torch.float32, device="cuda")
+    status = torch.zeros(1, dtype=torch.int32, device="cuda")
+    h.run(nnz, r, c, v, X, Y, status)
+    torch.cuda.synchronize()
+    assert status.item() == spmm.ERR_BAD_INDEX
+    assert bool((Y == 7.0).all())
