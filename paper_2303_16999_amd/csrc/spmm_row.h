@@ -603,16 +603,16 @@ __global__ __launch_bounds__(256) void k_spmm_row(Params prm) {
   if constexpr (!SPLIT) {
     row_unit<XT, WT, YT, B, NS, false>(p, xcd_unit(blockIdx.x, prm.num_units), lane, wave, nullptr);
   } else {
-    // Heavy units take the first workgroups (spread over the XCDs by the
-    // dispatcher's round robin), padded to a multiple of 8 so the light units
-    // keep their XCD-contiguous order.
+    // Heavy units take the first workgroups, padded to a multiple of 8; both
+    // ranges are numbered so that each XCD runs consecutive units (the same
+    // few column tiles of X) and keeps them in its L2.
     extern __shared__ float4_t row_red[];
     const int32_t hus = heavy_units(p, NS);
     const int32_t hpad = (hus + 7) & ~7;
     int32_t unit;
     if ((int32_t)blockIdx.x < hpad) {
       if ((int32_t)blockIdx.x >= hus) return;
-      unit = blockIdx.x;
+      unit = xcd_unit(blockIdx.x, hus);
     } else {
       unit = hus + xcd_unit(blockIdx.x - hpad, prm.num_units - hus);
     }
