@@ -11,9 +11,19 @@ oracle timed on the host cores over a bounded column sample.
 
 Other modes print their own JSON lines:
   --mode sweep      the static sweep (m = k = 8192, n in {256, 1024, 4096},
-                    b in {16, 32}, densities 1/128..1/4) next to dense FP16
+                    b in {1, 4, 8, 16, 32}, densities 1/128..1/4, b = 16 up to
+                    d = 1) next to dense FP16, and the crossover densities
   --mode dynamic    1000 dynamic calls, m = k = 4096, n = 512, b = 16, d_max 1/8
   --mode precision  m = k = 16384, n = 2048, b in {16, 32}, BF16 and FP8 weights
+  --mode small      the small FP32 case (m = k = 1024, n = 64), two kernels
+  --mode table3     static and dynamic against dense at m = k = 4096, d = 1/16
+  --mode serve      the 8-layer serving loop against one request at a time
+  --mode group      one grouped launch of 16 products against 16 launches
+  --mode skew       power-law and concentrated patterns, rows split or not
+  --mode train      forward, data gradient and weight gradient of one layer
+  --mode ell        blocked-ELL plans, explicit padding, b = 16/32/64
+  --mode grid       the paper's sweep grid best over n and its power-law fit
+  --mode copy       a 256 MiB device copy (counter calibration)
 """
 import argparse
 import hashlib
