@@ -320,7 +320,9 @@ def mode_sweep(args):
                 rec = {"mode": "sweep", "m": 8192, "k": 8192, "n": n, "b": b, "density": 1.0 / dd,
                        "nnz_blocks": prob.nnzb, "ms": round(ms, 5), "cold_ms": round(cold, 5),
                        "tflops": round(fl / (ms * 1e-3) / 1e12, 3),
+                       "hbm_gbs": round(prob.alg_bytes() / (ms * 1e-3) / 1e9, 1),
                        "hbm_frac": round(prob.alg_bytes() / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                       "mfma_frac": round(fl / (ms * 1e-3) / 1e12 / MFMA_PEAK_TFLOPS["f16"], 4),
                        "hbm_frac_cold": round(prob.alg_bytes() / (cold * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                        "plan_build_ms": round(prob.plan_ms, 3),
                        "dense_ms": round(dense_cache[n], 5), "speedup_vs_dense": round(dense_cache[n] / ms, 3)}
@@ -436,8 +438,48 @@ def mode_dynamic(args):
         st_ms.append(time_steps(lambda: plan.run(X, Y), 10, 2))
         dy_ms.append(time_steps(lambda: call(i), 10, 2))
         plan.close()
+    # end to end: each call's COO and values come from pinned host memory over PCIe first
+    ne = min(32, calls)
+    rows_h = torch.empty((ne, max_nnz), dtype=torch.int32, pin_memory=True)
+    cols_h = torch.empty((ne, max_nnz), dtype=torch.int32, pin_memory=True)
+    vals_h = torch.empty((ne, max_nnz, b, b), dtype=torch.float16, pin_memory=True)
+    nnz_hh = torch.empty((ne, 1), dtype=torch.int32, pin_memory=True)
+    rows_h.copy_(rows_d[:ne])
+    cols_h.copy_(cols_d[:ne])
+    vals_h.copy_(vals_d[:ne])
+    nnz_hh.copy_(nnz_d[:ne])
+    r_st, c_st, v_st, n_st = (torch.empty_like(rows_d[0]), torch.empty_like(cols_d[0]), torch.empty_like(vals_d[0]),
+                              torch.empty_like(nnz_d[0]))
+
+    def call_e2e(i):
+        j = i % ne
+        q = int(nnz_h[j])  # only the call's own entries cross PCIe
+        n_st.copy_(nnz_hh[j], non_blocking=True)
+        r_st[:q].copy_(rows_h[j, :q], non_blocking=True)
+        c_st[:q].copy_(cols_h[j, :q], non_blocking=True)
+        v_st[:q].copy_(vals_h[j, :q], non_blocking=True)
+        h.run(n_st, r_st, c_st, v_st, X, Y, status[0])
+
+    reps = 4 * ne
+    for i in range(4):
+        call_e2e(i)
+    torch.cuda.synchronize()
+    ev2 = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+    ev2[0].record()
+    for i in range(reps):
+        call_e2e(i)
+        ev2[i + 1].record()
+    torch.cuda.synchronize()
+    per2 = np.array([ev2[i].elapsed_time(ev2[i + 1]) for i in range(reps)])
+    assert int(status[0].item()) == 0
+    e2e_flops = np.array([2.0 * nnz_h[i % ne] * b * b * n for i in range(reps)])
+    e2e_bytes = np.array([float(nnz_h[i % ne]) * (8 + 2 * b * b) + 4 for i in range(reps)])
     dn = dense_fp16(m, k, n, 20, 5, 1.0)
     rec = {"mode": "dynamic", "m": m, "k": k, "n": n, "b": b, "max_density": 1 / 8, "calls": calls,
+           "e2e_ms_mean": round(float(per2.mean()), 5), "e2e_ms_p50": round(float(np.percentile(per2, 50)), 5),
+           "e2e_ms_p99": round(float(np.percentile(per2, 99)), 5),
+           "e2e_tflops": round(float(e2e_flops.sum() / (per2.sum() * 1e-3) / 1e12), 3),
+           "e2e_h2d_gbs": round(float(e2e_bytes.sum() / (per2.sum() * 1e-3) / 1e9), 2),
            "call_ms_mean": round(float(per.mean()), 5), "call_ms_p50": round(float(np.percentile(per, 50)), 5),
            "call_ms_p99": round(float(np.percentile(per, 99)), 5),
            "tflops": round(float(flops.sum() / (per.sum() * 1e-3) / 1e12), 3),
