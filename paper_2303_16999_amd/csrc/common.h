@@ -158,7 +158,7 @@ size_t row_problem_size();
 void group_args_header(void* args, int32_t count, int32_t total);
 void* group_args_problem(void* args, int32_t i);
 void fill_row_problem(void* dst, const RunArgs& a, const int32_t* row_ptr, const int32_t* col_idx,
-                      int32_t unit_begin);
+                      int32_t unit_begin, int32_t num_units);
 const void* row_grouped_args_kernel(spmm_dtype_t xt, spmm_dtype_t yt, int32_t b, bool split);
 spmm_status_t launch_spmm_row_grouped_args(spmm_dtype_t xt, spmm_dtype_t yt, int32_t b, const void* args,
                                            int32_t total, unsigned lds, hipStream_t stream);

@@ -201,8 +201,10 @@ spmm_status_t spmm_group_run(spmm_group_t g, int32_t count, const spmm_plan_t* p
     a.heavy_rows = p->heavy_rows;
     any_heavy = any_heavy || p->num_heavy > 0;
     void* dst = inline_table ? group_args_problem(g->args.data(), k) : (void*)(g->host[s] + (size_t)k * g->desc_bytes);
-    fill_row_problem(dst, a, p->pb.row_ptr, p->pb.col_idx, (int32_t)total);
-    total += group_problem_units(p->mb, n[i], ns, p->num_heavy);
+    const int64_t units = group_problem_units(p->mb, n[i], ns, p->num_heavy);
+    if (units >= (int64_t)INT32_MAX) return fail(SPMM_ERR_UNSUPPORTED, "too many work units in one group");
+    fill_row_problem(dst, a, p->pb.row_ptr, p->pb.col_idx, (int32_t)total, (int32_t)units);
+    total += (units + 7) & ~(int64_t)7;  // each problem's range starts at a multiple of 8
     if (total >= (int64_t)INT32_MAX) return fail(SPMM_ERR_UNSUPPORTED, "too many work units in one group");
     ++k;
   }

@@ -51,8 +51,9 @@ struct RowProblem {
   uint32_t x_bytes;        // k * ldx * 2, < 2^31
   int32_t relu;            // nonzero: max(0, y) before the output cast
   int32_t ns;              // column tiles of 16 per wave: 2, 4 or 8
-  int32_t unit_begin;      // grouped launch: first work unit of this problem
+  int32_t unit_begin;      // grouped launch: first workgroup of this problem (a multiple of 8)
   int32_t num_heavy;       // block rows split over the 4 waves of a workgroup
+  int32_t num_units;       // grouped launch: work units of this problem
   const uint8_t* heavy_flag;  // [mb] nonzero for a split row (nullptr when num_heavy == 0)
   const int32_t* heavy_rows;  // [num_heavy] the split rows
 };

@@ -16,23 +16,29 @@ struct GroupArgs {
   RowProblem probs[kInlineProblems];
 };
 
-// One workgroup per work unit of the group, in the XCD-aware order; a unit is
-// (problem, group of 4 block rows, column tile of 16*ns). The problem of a
-// unit is the last one whose first unit is at or before it.
+// One workgroup per work unit of the group; a unit is (problem, group of 4
+// block rows, column tile of 16*ns). Each problem owns a range of workgroups
+// starting at a multiple of 8, so the dispatcher's round robin spreads every
+// problem evenly over the 8 XCDs (as a launch of its own would be); inside
+// the range the units are numbered XCD-contiguously. The problem of a
+// workgroup is the last one whose range starts at or before it.
 template <typename XT, typename WT, typename YT, int B, bool SPLIT>
 __device__ __forceinline__ void group_unit(const RowProblem* __restrict__ probs, int32_t count, int32_t total,
                                            float4_t* red) {
   const int lane = threadIdx.x & 63;
   const int wave = SPLIT ? __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) : (int)(threadIdx.x >> 6);
-  const int32_t unit = xcd_unit(blockIdx.x, total);
+  const int32_t wg = blockIdx.x;
   int32_t lo = 0, hi = count - 1;
   while (lo < hi) {
     const int32_t mid = (lo + hi + 1) >> 1;
-    if (uniform(probs[mid].unit_begin) <= unit) lo = mid;
+    if (uniform(probs[mid].unit_begin) <= wg) lo = mid;
     else hi = mid - 1;
   }
   const RowProblem p = probs[lo];  // by value: the fields live in scalar registers
-  const int32_t local = unit - uniform(p.unit_begin);
+  const int32_t nu = uniform(p.num_units);
+  const int32_t w = wg - uniform(p.unit_begin);
+  if (w >= nu) return;  // padding up to the next multiple of 8
+  const int32_t local = xcd_unit(w, nu);
   const int32_t ns = uniform(p.ns);
   if (ns == 8) row_unit<XT, WT, YT, B, 8, SPLIT>(p, local, lane, wave, red);
   else if (ns == 4) row_unit<XT, WT, YT, B, 4, SPLIT>(p, local, lane, wave, red);
@@ -98,9 +104,10 @@ void* group_args_problem(void* args, int32_t i) { return &((row::GroupArgs*)args
 
 // Fills one problem descriptor (host side; layout shared with the kernels).
 void fill_row_problem(void* dst, const RunArgs& a, const int32_t* row_ptr, const int32_t* col_idx,
-                      int32_t unit_begin) {
+                      int32_t unit_begin, int32_t num_units) {
   row::RowProblem p = row::row_problem(a, row_ptr, col_idx);
   p.unit_begin = unit_begin;
+  p.num_units = num_units;
   *(row::RowProblem*)dst = p;
 }
 
