@@ -145,6 +145,8 @@ class StaticPlan:
         x = x or ("f16" if w == "fp8" else w)
         y = y or x
         mask = np.ascontiguousarray(np.asarray(block_mask, dtype=np.uint8))
+        if b > 0 and mask.size != (-(-int(m) // int(b))) * (-(-int(k) // int(b))):
+            raise ValueError("block_mask must have ceil(m/b) x ceil(k/b) entries")
         self.m, self.k, self.b = int(m), int(k), int(b)
         self.w, self.x, self.y = DTYPE_CODES[w], DTYPE_CODES[x], DTYPE_CODES[y]
         h = _vp()

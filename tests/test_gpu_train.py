@@ -242,3 +242,28 @@ def test_sddmm_many_tasks_one_wave_per_task():
     assert np.array_equal(G1, G2)
     ref = TR.sddmm_blockwise(c.m, c.k, 16, c.rows, c.cols, dY64, c.X64)
     assert O.rel_fro(G1, ref) <= 1e-5
+
+
+def test_transpose_of_column_concentrated_pattern_has_split_rows():
+    # all blocks in a few block columns: the transposed plan's rows are long and get split
+    mb, kb, b = 300, 24, 16
+    mask = synth.concentrated_mask(kb, mb, 1 / 8, 5).T.copy()  # concentrated in columns
+    c = Case(mb * b, kb * b - 7, 180, b, 0.0, w="f16", seed=121, mask=mask)
+    plan = _plan(c)
+    t = plan.transpose()
+    assert t.info()["num_split_rows"] > 0
+    dY, dY64 = _dY(c, 122)
+    err = O.rel_fro(_run_transposed(c, t, dY), _oracle_transposed(c, dY64))
+    assert err <= 5e-3, err
+
+
+def test_sddmm_on_concentrated_rows():
+    # rows of hundreds of blocks: many tasks per row
+    mb, kb, b = 20, 400, 16
+    mask = synth.concentrated_mask(mb, kb, 1 / 5, 9)
+    c = Case(mb * b, kb * b, 70, b, 0.0, w="bf16", seed=131, mask=mask)
+    plan = _plan(c)
+    _, X, _ = c.device_inputs()
+    dY, dY64 = _dY(c, 132)
+    G = _sddmm(c, plan, dY, X)
+    assert O.rel_fro(G, TR.sddmm_blockwise(c.m, c.k, b, c.rows, c.cols, dY64, c.X64)) <= 1e-5
