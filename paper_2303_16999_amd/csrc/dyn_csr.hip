@@ -10,6 +10,9 @@
 //      part of edge blocks beyond column k;
 // plus the cost-balanced panels of the row groups. Every kernel reads the
 // entry count from device memory and stops when the status word is set.
+#include <algorithm>
+#include <cstdlib>
+
 #include "common.h"
 
 namespace spmm {
@@ -157,6 +160,17 @@ __global__ void k_dyn_status_out(const int32_t* __restrict__ internal, int32_t* 
 // index) and write them to block-CSR in place, group costs, their prefix and
 // the panel boundaries, then the status words. Used when the capacity fits in
 // LDS; the result is identical to the multi-kernel path's.
+//
+// Column bitmap form (use_bm): while counting, every entry also sets the bit
+// of its column in a bitmap of its row (ceil(kb/32) words per row, in the LDS
+// that the staged entries use otherwise). When no bit was set twice, i.e. no
+// (row, column) pair repeats, the rank of an entry within its row is the
+// number of set bits below its column: an exclusive scan of the bit counts of
+// all bitmap words (row-major) gives each word the block-CSR position of its
+// first entry, so each entry goes straight to its position in LDS, and the
+// finished arrays are copied out with coalesced stores. The scatter, the
+// pairwise ranking and its scattered global stores are skipped. A repeated
+// pair switches the call to the ranking path.
 constexpr int kSmallThreads = 1024;
 constexpr int kSmallU = 8;  // entries per thread per chunk
 
@@ -207,23 +221,30 @@ __global__ __launch_bounds__(1024) void k_dyn_small(const int32_t* __restrict__ 
                                                     int32_t* __restrict__ row_ptr, int32_t* __restrict__ col_idx,
                                                     int32_t* __restrict__ src, int32_t* __restrict__ panel_ptr,
                                                     int32_t* __restrict__ status, int32_t* __restrict__ status_out,
-                                                    int32_t* __restrict__ nnz_last) {
+                                                    int32_t* __restrict__ nnz_last, int32_t use_bm) {
   extern __shared__ int64_t lds64[];
   int64_t* C = lds64;                          // [G + 1] group cost prefix
   int64_t* part64 = C + (G + 1);               // [1024]
   int32_t* cnt = (int32_t*)(part64 + kSmallThreads);  // [mb] counts, then fill positions
   int32_t* rp = cnt + mb;                      // [mb + 1]
   int32_t* part = rp + mb + 1;                 // [1024]
-  int32_t* flag = part + kSmallThreads;        // [0] error, [1] nnz
-  uint32_t* ekey = (uint32_t*)(flag + 2);      // [max_nnz] (column << 16) | input index
+  int32_t* flag = part + kSmallThreads;        // [0] error, [1] nnz, [2] a (row, column) pair repeats
+  uint32_t* ekey = (uint32_t*)(flag + 4);      // [max_nnz] (column << 16) | input index
   uint16_t* erow = (uint16_t*)(ekey + max_nnz); // [max_nnz] block row of each staged entry
+  const int32_t wpr = (kb + 31) >> 5;
+  uint32_t* bm = ekey;                         // [mb * wpr] column bitmaps (use_bm), in place of ekey/erow
+  int32_t* wpos = (int32_t*)(bm + mb * wpr);   // [mb * wpr + 1] CSR position of each bitmap word's first entry (use_bm)
+  uint32_t* okey = (uint32_t*)(wpos + mb * wpr + 1);  // [max_nnz] (column << 16) | input index in CSR order (use_bm)
   const int tid = threadIdx.x;
   if (tid == 0) {
     const int32_t nnz = *nnz_dev;
     flag[0] = (nnz < 0 || nnz > max_nnz) ? (int32_t)SPMM_ERR_CAPACITY : 0;
     flag[1] = nnz;
+    flag[2] = 0;
   }
   for (int32_t r = tid; r < mb; r += kSmallThreads) cnt[r] = 0;
+  if (use_bm)
+    for (int32_t i = tid; i < mb * wpr; i += kSmallThreads) bm[i] = 0;
   __syncthreads();
   const int32_t nnz = flag[1];
   // Entries are read in chunks of kSmallU per thread, all loads of a chunk
@@ -243,8 +264,15 @@ __global__ __launch_bounds__(1024) void k_dyn_small(const int32_t* __restrict__ 
       for (int u = 0; u < kSmallU; ++u) {
         const int32_t e = base + u * kSmallThreads + tid;
         if (e >= nnz) continue;
-        if (er[u] < 0 || er[u] >= mb || ec[u] < 0 || ec[u] >= kb) atomicMax(&flag[0], (int32_t)SPMM_ERR_BAD_INDEX);
-        else atomicAdd(&cnt[er[u]], 1);
+        if (er[u] < 0 || er[u] >= mb || ec[u] < 0 || ec[u] >= kb) {
+          atomicMax(&flag[0], (int32_t)SPMM_ERR_BAD_INDEX);
+          continue;
+        }
+        atomicAdd(&cnt[er[u]], 1);
+        if (use_bm) {
+          const uint32_t bit = 1u << (ec[u] & 31);
+          if (atomicOr(&bm[er[u] * wpr + (ec[u] >> 5)], bit) & bit) flag[2] = 1;
+        }
       }
     }
   }
@@ -257,10 +285,46 @@ __global__ __launch_bounds__(1024) void k_dyn_small(const int32_t* __restrict__ 
     }
     return;
   }
+  const bool fast = use_bm && flag[2] == 0;  // read after the barrier: the same in every thread
+  const bool in_regs = nnz <= kSmallThreads * kSmallU;
+  if (fast) {
+    // With every (row, column) pair once, the bitmaps in row-major order list
+    // block-CSR: the exclusive scan of their words' bit counts gives each word
+    // the position of its first entry, and the row pointers at row starts.
+    const int32_t nw = mb * wpr;
+    for (int32_t i = tid; i < nw; i += kSmallThreads) wpos[i] = __popc(bm[i]);
+    __syncthreads();
+    block_exscan_chunks<int32_t, int32_t>(wpos, nw, wpos, part);
+    for (int32_t r = tid; r <= mb; r += kSmallThreads) rp[r] = wpos[r * wpr];
+    for (int32_t base = 0; base < nnz; base += kSmallThreads * kSmallU) {
+      if (!in_regs) {
+#pragma unroll
+        for (int u = 0; u < kSmallU; ++u) {
+          const int32_t e = base + u * kSmallThreads + tid;
+          er[u] = e < nnz ? rows[e] : 0;
+          ec[u] = e < nnz ? cols[e] : 0;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kSmallU; ++u) {
+        const int32_t e = base + u * kSmallThreads + tid;
+        if (e >= nnz) continue;
+        const int32_t wi = er[u] * wpr + (ec[u] >> 5);
+        const int32_t pos = wpos[wi] + __popc(bm[wi] & ((1u << (ec[u] & 31)) - 1u));
+        okey[pos] = ((uint32_t)ec[u] << 16) | (uint32_t)e;
+      }
+    }
+    // block-CSR leaves LDS in order: consecutive threads write consecutive words
+    __syncthreads();
+    for (int32_t i = tid; i < nnz; i += kSmallThreads) {
+      const uint32_t key = okey[i];
+      col_idx[i] = (int32_t)(key >> 16);
+      src[i] = (int32_t)(key & 0xFFFFu);
+    }
+  } else {
   block_exscan_chunks<int32_t, int32_t>(cnt, mb, rp, part);
   for (int32_t r = tid; r < mb; r += kSmallThreads) cnt[r] = rp[r];
   __syncthreads();
-  const bool in_regs = nnz <= kSmallThreads * kSmallU;
   for (int32_t base = 0; base < nnz; base += kSmallThreads * kSmallU) {
     if (!in_regs) {
 #pragma unroll
@@ -294,6 +358,7 @@ __global__ __launch_bounds__(1024) void k_dyn_small(const int32_t* __restrict__ 
     col_idx[lo + rank] = (int32_t)(key >> 16);
     src[lo + rank] = (int32_t)(key & 0xFFFFu);
   }
+  }
   for (int32_t i = tid; i <= mb; i += kSmallThreads) row_ptr[i] = rp[i];
   // group costs (blocks + rows), their prefix, panel boundaries
   for (int32_t g = tid; g < G; g += kSmallThreads) {
@@ -325,10 +390,19 @@ __global__ __launch_bounds__(1024) void k_dyn_small(const int32_t* __restrict__ 
   }
 }
 
-size_t dyn_small_lds_bytes(int32_t max_nnz, int32_t mb, int32_t G) {
+// LDS of the one-workgroup builder; with bm_words > 0 the staged-entry region
+// also holds the bitmap form's column bitmaps (bm_words words), their scanned
+// bit counts (bm_words + 1) and the packed block-CSR (max_nnz words).
+size_t dyn_small_lds_bytes(int32_t max_nnz, int32_t mb, int32_t G, int64_t bm_words = 0) {
+  const size_t stage = sizeof(uint32_t) * (size_t)max_nnz + sizeof(uint16_t) * (size_t)max_nnz;
+  const size_t region = std::max(stage, bm_words ? sizeof(uint32_t) * (2 * (size_t)bm_words + 1 + max_nnz) : 0);
   return sizeof(int64_t) * ((size_t)G + 1 + kSmallThreads) +
-         sizeof(int32_t) * ((size_t)mb + mb + 1 + kSmallThreads + 2 + (size_t)max_nnz) + sizeof(uint16_t) * (size_t)max_nnz;
+         sizeof(int32_t) * ((size_t)mb + mb + 1 + kSmallThreads + 4) + region;
 }
+
+// Column bitmap form: at most 32 words (1024 block columns) per row, and the
+// bitmaps within the builder's LDS limit.
+constexpr int32_t kBmMaxWordsPerRow = 32;
 
 }  // namespace
 
@@ -344,12 +418,16 @@ bool dynamic_small_fits(int32_t max_nnz, int32_t mb, int32_t kb, int32_t G) {
 spmm_status_t build_dynamic_csr_small(const int32_t* nnz_dev, const int32_t* rows, const int32_t* cols,
                                       int32_t max_nnz, int32_t mb, int32_t kb, const Geometry& geo, PlanBuffers& pb,
                                       int32_t* status, int32_t* status_out, int32_t* nnz_last, hipStream_t s) {
-  const size_t lds = dyn_small_lds_bytes(max_nnz, mb, geo.num_groups);
   if (!dynamic_small_fits(max_nnz, mb, kb, geo.num_groups))
     return fail(SPMM_ERR_UNSUPPORTED, "dynamic capacity too large for the one-workgroup builder");
+  const int64_t wpr = ((int64_t)kb + 31) / 32, bm_words = (int64_t)mb * wpr;
+  const char* rank_env = getenv("SPMM_DYN_RANK");  // "pairwise": always rank by comparisons (for tests)
+  const bool use_bm = !(rank_env && std::string(rank_env) == "pairwise") && wpr <= kBmMaxWordsPerRow &&
+                      dyn_small_lds_bytes(max_nnz, mb, geo.num_groups, bm_words) <= kDynSmallLdsMax;
+  const size_t lds = dyn_small_lds_bytes(max_nnz, mb, geo.num_groups, use_bm ? bm_words : 0);
   hipLaunchKernelGGL(k_dyn_small, dim3(1), dim3(kSmallThreads), lds, s, nnz_dev, max_nnz, rows, cols, mb, kb,
                      geo.group_rows, geo.num_groups, geo.num_panels, pb.row_ptr, pb.col_idx, pb.csr_src, pb.panel_ptr,
-                     status, status_out, nnz_last);
+                     status, status_out, nnz_last, use_bm ? 1 : 0);
   SPMM_HIP(hipGetLastError());
   return SPMM_OK;
 }

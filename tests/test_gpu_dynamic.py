@@ -201,3 +201,58 @@ def test_dynamic_fp32_bad_index_leaves_y_untouched():
     torch.cuda.synchronize()
     assert status.item() == spmm.ERR_BAD_INDEX
     assert bool((Y == 7.0).all())
+
+
+@pytest.mark.parametrize("case", ["config3", "chunked", "wide", "repeats"])
+def test_bitmap_rank_equals_pairwise_rank(case, monkeypatch):
+    """The one-workgroup encoder's column-bitmap ranking and its pairwise ranking
+    give the oracle's plan and the same Y bit for bit: at the dynamic benchmark's
+    grid (256 x 256 blocks), above the entries one pass keeps in registers
+    (8800 > 8192), past the bitmap's 1024-column limit (the pairwise path then
+    runs in both), and with repeated (row, column) pairs (which switch the
+    bitmap form to the pairwise ranking inside the kernel)."""
+    b, n = 16, 96
+    g = np.random.default_rng(91)
+    if case == "config3":
+        mb, kb, max_nnz = 256, 256, 8192
+        rows, cols, vals = synth.dynamic_call(mb, kb, b, max_nnz, seed=92)
+    elif case == "chunked":
+        mb, kb, max_nnz = 16, 600, 8800
+        rows, cols, vals = synth.dynamic_call(mb, kb, b, max_nnz, seed=93, lo_frac=1.0)
+    elif case == "wide":
+        mb, kb, max_nnz = 8, 1100, 2000
+        rows, cols, vals = synth.dynamic_call(mb, kb, b, max_nnz, seed=94)
+    else:
+        mb, kb, max_nnz = 40, 40, 600
+        rows = g.integers(0, mb, 500).astype(np.int32)
+        cols = g.integers(0, kb, 500).astype(np.int32)
+        rows[100:120], cols[100:120] = rows[:20], cols[:20]  # certain repeats
+        vals = synth.to_storage(synth.normal((500, b, b), 95), "f16")
+    assert len(rows) <= max_nnz
+    m, k = mb * b, kb * b
+    h = spmm.DynamicHandle(m, k, b, max_nnz, "f16", num_panels=7)
+    r, c, v, nnz = _dyn_inputs(rows, cols, vals, max_nnz, b)
+    X = dev(synth.to_storage(synth.normal((k, n), 96), "f16"))
+    outs, exports = [], []
+    for rank in (None, "pairwise"):
+        if rank:
+            monkeypatch.setenv("SPMM_DYN_RANK", rank)
+        else:
+            monkeypatch.delenv("SPMM_DYN_RANK", raising=False)
+        Y = torch.full((m, n), float("nan"), dtype=torch.float16, device="cuda")
+        status = torch.full((1,), -1, dtype=torch.int32, device="cuda")
+        h.run(nnz, r, c, v, X, Y, status)
+        torch.cuda.synchronize()
+        assert status.item() == 0
+        outs.append(Y)
+        exports.append(h.export())
+    assert torch.equal(outs[0], outs[1])
+    ref = plan_ref.plan_from_coo(mb, kb, rows, cols, h.info()["group_rows"], h.info()["num_panels"])
+    for ex in exports:
+        for key in ("row_ptr", "col_idx", "src", "panel_ptr"):
+            assert np.array_equal(ex[key], ref[key]), key
+    if case == "repeats":
+        v64 = synth.storage_to_f64(vals, "f16")
+        X64 = synth.storage_to_f64(synth.to_storage(synth.normal((k, n), 96), "f16"), "f16")
+        assert O.rel_fro(outs[0].cpu().numpy().astype(np.float64),
+                         O.spmm_blockwise(m, k, b, rows, cols, v64, X64)) <= 5e-3
