@@ -147,9 +147,9 @@ spmm_status_t launch_spmm(const RunArgs& a, hipStream_t stream);
 // Row-wise kernel (16-bit X, b = 16 or 32): W and scales in block-CSR order.
 spmm_status_t launch_spmm_row(const RunArgs& a, const int32_t* row_ptr, const int32_t* col_idx, hipStream_t stream);
 // Row-wise kernel with a software-pipelined block loop, for launches of at
-// most two workgroups per CU (b = 16, W in the X type; no split rows). The
-// same results as launch_spmm_row, bit for bit.
-bool row_pp_preferred(int32_t mb, int64_t n, int32_t ns, int64_t nnz, int num_cus);
+// most two workgroups per CU (b = 16 or 32, W in the X type; no split rows).
+// The same results as launch_spmm_row, bit for bit.
+bool row_pp_preferred(int32_t b, int32_t mb, int64_t n, int32_t ns, int64_t nnz, int num_cus);
 spmm_status_t launch_spmm_row_pp(const RunArgs& a, const int32_t* row_ptr, const int32_t* col_idx,
                                  hipStream_t stream);
 // Row-wise FP32 kernel (FP32 W, X, Y; b = 16 or 32): W in block-CSR order.

@@ -331,7 +331,7 @@ spmm_status_t run_plan(const spmm_plan_s* p, int64_t n, const void* X, int64_t l
     a.num_heavy = p->num_heavy;
     a.heavy_flag = p->heavy_flag;
     a.heavy_rows = p->heavy_rows;
-    if (p->b == 16 && p->w == p->x && p->num_heavy == 0 && row_pp_preferred(p->mb, n, a.ns, p->nnzb, device_cu_count()))
+    if (p->w == p->x && p->num_heavy == 0 && row_pp_preferred(p->b, p->mb, n, a.ns, p->nnzb, device_cu_count()))
       return launch_spmm_row_pp(a, p->pb.row_ptr, p->pb.col_idx, stream);
     return launch_spmm_row(a, p->pb.row_ptr, p->pb.col_idx, stream);
   }
@@ -767,7 +767,7 @@ spmm_status_t spmm_run_dynamic(spmm_dyn_t h, const int32_t* nnzb_dev, const int3
     a.ns = h->b < 16 ? 0 : default_ns(n);
     if (h->b < 16) return launch_spmm_small(a, h->pb.row_ptr, h->pb.col_idx, s);
     if (h->x == SPMM_F32) return launch_spmm_row_f32(a, h->pb.row_ptr, h->pb.col_idx, s);
-    if (h->b == 16 && h->w == h->x && row_pp_preferred(h->mb, n, a.ns, h->max_nnzb, device_cu_count()))
+    if (h->w == h->x && row_pp_preferred(h->b, h->mb, n, a.ns, h->max_nnzb, device_cu_count()))
       return launch_spmm_row_pp(a, h->pb.row_ptr, h->pb.col_idx, s);
     return launch_spmm_row(a, h->pb.row_ptr, h->pb.col_idx, s);
   }

@@ -24,10 +24,11 @@ def _static(c, variant, pp, monkeypatch):
 
 @pytest.mark.parametrize("w,y", [("f16", "f16"), ("bf16", "f32"), ("bf16", "bf16"), ("f16", "f32")])
 @pytest.mark.parametrize("variant", [2, 4, 8])
-def test_pp_equals_row_kernel_and_oracle(w, y, variant, monkeypatch):
+@pytest.mark.parametrize("b", [16, 32])
+def test_pp_equals_row_kernel_and_oracle(w, y, variant, b, monkeypatch):
     # ragged m, k and n; d = 0.45 over 150 block columns gives rows of about 67
     # blocks (more than one 64-block chunk, odd and even counts)
-    c = Case(16 * 37 + 5, 16 * 150 - 3, 203, 16, 0.45, w=w, y=y, seed=61 + variant)
+    c = Case(b * 37 + 5, b * 150 - 3, 203, b, 0.45, w=w, y=y, seed=61 + variant)
     assert c.mask.sum(1).max() > 64
     Yp = _static(c, variant, True, monkeypatch)
     Yr = _static(c, variant, False, monkeypatch)
@@ -59,11 +60,12 @@ def test_pp_integer_data_bit_exact(monkeypatch):
     assert np.array_equal(y_f64(Yp, c), ref)
 
 
-@pytest.mark.parametrize("w", ["f16", "bf16"])
-def test_pp_dynamic_equals_row_kernel(w, monkeypatch):
-    # the dynamic benchmark's shape: 256 x 256 blocks, n = 512, up to 8192 blocks
-    b, mb, kb, n = 16, 256, 256, 512
-    max_nnz = 8192
+@pytest.mark.parametrize("w,b", [("f16", 16), ("bf16", 16), ("bf16", 32)])
+def test_pp_dynamic_equals_row_kernel(w, b, monkeypatch):
+    # b = 16: the dynamic benchmark's shape, 256 x 256 blocks, n = 512, up to
+    # 8192 blocks; b = 32: 96 x 80 blocks, up to 1920
+    mb, kb, n = (256, 256, 512) if b == 16 else (96, 80, 512)
+    max_nnz = mb * kb // 8 if b == 16 else mb * kb // 4
     rows, cols, vals = synth.dynamic_call(mb, kb, b, max_nnz, seed=44, dtype="f16")
     vals = synth.to_storage(synth.storage_to_f64(vals, "f16"), w)
     pad = max_nnz - len(rows)
