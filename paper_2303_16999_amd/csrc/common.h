@@ -61,7 +61,12 @@ struct PlanBuffers {
   int32_t* scratch = nullptr;   // counts / fills / scan partials
   int64_t* cost_prefix = nullptr;
   int64_t scratch_ints = 0;
+  int32_t* hist = nullptr;      // dynamic: per-workgroup block-row histograms [hist_wgs][mb]
+  int32_t hist_wgs = 0;         // workgroups of the histogram encode (0: global-atomic encode)
 };
+// Workgroups of the dynamic histogram encode for a capacity and block-row
+// count (0 where its LDS histogram of mb rows does not fit).
+int32_t dyn_hist_wgs(int64_t max_nnz, int32_t mb);
 
 struct Geometry {
   int32_t group_rows, chunk_cols, num_groups, num_chunks, num_panels;

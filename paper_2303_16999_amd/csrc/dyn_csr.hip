@@ -83,19 +83,196 @@ __global__ void k_dyn_row_scatter(const int32_t* __restrict__ nnz_dev, const int
   }
 }
 
-// One workgroup per block row: each thread ranks entries of the row by
-// (column, input index) against all others and writes them into place. Rows
-// that fit are ranked from LDS, longer ones from a global copy.
+// ------------------------------------------------------------------ histogram encode
+// The multi-kernel encode without global atomics (a counting sort by block
+// row): workgroup w takes entries [w chunk, (w + 1) chunk) and counts them per
+// block row in LDS; a scan over the workgroups, per block row, turns the
+// counts into each workgroup's first slot within the row and the row totals;
+// the row totals are scanned into row_ptr; each workgroup then places its
+// entries from its own slots with LDS atomics. The order inside a row is
+// canonicalised by k_dyn_row_sort afterwards.
+constexpr int kHistU = 8;        // entries per thread loaded together
+constexpr int kHistChunk = 4096; // entries per workgroup (at most 256 workgroups)
+
+__global__ __launch_bounds__(256) void k_dyn_hist(const int32_t* __restrict__ nnz_dev, int32_t max_nnz,
+                                                  const int32_t* __restrict__ rows, const int32_t* __restrict__ cols,
+                                                  int32_t mb, int32_t kb, int32_t chunk, int32_t* __restrict__ hist,
+                                                  int32_t* __restrict__ status) {
+  extern __shared__ int32_t hcnt[];  // [mb]
+  const int32_t nnz = *nnz_dev;
+  if (nnz < 0 || nnz > max_nnz) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) atomicMax(status, (int32_t)SPMM_ERR_CAPACITY);
+    return;
+  }
+  const int tid = threadIdx.x;
+  for (int32_t r = tid; r < mb; r += 256) hcnt[r] = 0;
+  __syncthreads();
+  const int64_t lo = (int64_t)blockIdx.x * chunk, hi = min((int64_t)nnz, lo + chunk);
+  for (int64_t base = lo; base < hi; base += 256 * kHistU) {
+    int32_t er[kHistU], ec[kHistU];
+#pragma unroll
+    for (int u = 0; u < kHistU; ++u) {
+      const int64_t e = base + u * 256 + tid;
+      er[u] = e < hi ? rows[e] : 0;
+      ec[u] = e < hi ? cols[e] : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < kHistU; ++u) {
+      if (base + u * 256 + tid >= hi) continue;
+      if (er[u] < 0 || er[u] >= mb || ec[u] < 0 || ec[u] >= kb) {
+        atomicMax(status, (int32_t)SPMM_ERR_BAD_INDEX);
+        continue;
+      }
+      atomicAdd(&hcnt[er[u]], 1);
+    }
+  }
+  __syncthreads();
+  for (int32_t r = tid; r < mb; r += 256) hist[(int64_t)blockIdx.x * mb + r] = hcnt[r];
+}
+
+// One thread per block row: hist[w][r] becomes the entries of row r in the
+// workgroups before w; row_cnt[r] the row's total.
+__global__ void k_dyn_hist_scan(int32_t* __restrict__ hist, int32_t wgs, int32_t mb, int32_t* __restrict__ row_cnt,
+                                const int32_t* __restrict__ status) {
+  if (*status) return;
+  const int32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= mb) return;
+  int32_t run = 0;
+  int32_t w = 0;
+  for (; w + 8 <= wgs; w += 8) {
+    int32_t v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = hist[(int64_t)(w + u) * mb + r];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      hist[(int64_t)(w + u) * mb + r] = run;
+      run += v[u];
+    }
+  }
+  for (; w < wgs; ++w) {
+    const int32_t v = hist[(int64_t)w * mb + r];
+    hist[(int64_t)w * mb + r] = run;
+    run += v;
+  }
+  row_cnt[r] = run;
+}
+
+__global__ __launch_bounds__(256) void k_dyn_hist_scatter(const int32_t* __restrict__ nnz_dev,
+                                                          const int32_t* __restrict__ rows,
+                                                          const int32_t* __restrict__ cols, int32_t mb, int32_t chunk,
+                                                          const int32_t* __restrict__ hist,
+                                                          const int32_t* __restrict__ row_ptr,
+                                                          int32_t* __restrict__ col_idx, int32_t* __restrict__ src,
+                                                          const int32_t* __restrict__ status) {
+  if (*status) return;
+  extern __shared__ int32_t slot[];  // [mb] next free position of each block row for this workgroup
+  const int tid = threadIdx.x;
+  for (int32_t r = tid; r < mb; r += 256) slot[r] = row_ptr[r] + hist[(int64_t)blockIdx.x * mb + r];
+  __syncthreads();
+  const int32_t nnz = *nnz_dev;
+  const int64_t lo = (int64_t)blockIdx.x * chunk, hi = min((int64_t)nnz, lo + chunk);
+  for (int64_t base = lo; base < hi; base += 256 * kHistU) {
+    int32_t er[kHistU], ec[kHistU];
+#pragma unroll
+    for (int u = 0; u < kHistU; ++u) {
+      const int64_t e = base + u * 256 + tid;
+      er[u] = e < hi ? rows[e] : 0;
+      ec[u] = e < hi ? cols[e] : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < kHistU; ++u) {
+      const int64_t e = base + u * 256 + tid;
+      if (e >= hi) continue;
+      const int32_t pos = atomicAdd(&slot[er[u]], 1);
+      col_idx[pos] = ec[u];
+      src[pos] = (int32_t)e;
+    }
+  }
+}
+
+// One workgroup per block row orders the row's entries by (column, input
+// index). Rows of at most kRowBmMax entries whose block columns all differ
+// (the usual case) are placed through a column bitmap: each entry sets its
+// column's bit (a repeated column is detected there), an exclusive scan of
+// the words' bit counts gives each word the rank of its first entry, and an
+// entry's rank is that plus the set bits below its column in its word. All
+// of the row is read before any of it is written back in place. Other rows rank each entry against all others of the row, from LDS
+// when the row fits, else from a global copy.
 constexpr int kSortLds = 2048;
+constexpr int kRowBmU = 8;                    // entries per thread
+constexpr int kRowBmMax = 256 * kRowBmU;      // longest row placed through the bitmap
+constexpr int kRowBmWords = 2048;             // bitmap words: block columns up to 65536
 __global__ __launch_bounds__(256) void k_dyn_row_sort(const int32_t* __restrict__ row_ptr,
                                                       int32_t* __restrict__ col_idx, int32_t* __restrict__ src,
                                                       int32_t* __restrict__ tmp_col, int32_t* __restrict__ tmp_src,
-                                                      const int32_t* __restrict__ status) {
+                                                      int32_t kb, const int32_t* __restrict__ status) {
   if (*status) return;
   __shared__ int32_t sc[kSortLds], ss[kSortLds];
+  __shared__ uint32_t bm[kRowBmWords];
+  __shared__ int32_t wsum[4];
+  __shared__ int32_t repeat;
   const int32_t r = blockIdx.x;
   const int32_t lo = row_ptr[r], hi = row_ptr[r + 1], len = hi - lo;
   if (len <= 1) return;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int32_t wpr = (kb + 31) >> 5;
+  if (len <= kRowBmMax && wpr <= kRowBmWords) {
+    for (int32_t i = tid; i < wpr; i += 256) bm[i] = 0;
+    if (tid == 0) repeat = 0;
+    __syncthreads();
+    int32_t ec[kRowBmU], es[kRowBmU];
+#pragma unroll
+    for (int u = 0; u < kRowBmU; ++u) {
+      const int32_t i = u * 256 + tid;
+      ec[u] = i < len ? col_idx[lo + i] : 0;
+      es[u] = i < len ? src[lo + i] : 0;
+    }
+    // every read of the row completes before the barrier (the columns feed the
+    // bitmap, the sources are staged in LDS), so the in-place writes after it
+    // cannot overtake a read
+#pragma unroll
+    for (int u = 0; u < kRowBmU; ++u) {
+      if (u * 256 + tid >= len) continue;
+      sc[u * 256 + tid] = es[u];
+      const uint32_t bit = 1u << (ec[u] & 31);
+      if (atomicOr(&bm[ec[u] >> 5], bit) & bit) repeat = 1;
+    }
+    __syncthreads();
+    if (!repeat) {
+      // exclusive scan of the words' bit counts: each thread a contiguous chunk
+      int32_t* wpos = ss;  // [wpr] (ss is free on this path)
+      const int32_t per = (wpr + 255) / 256;
+      const int32_t a = min(wpr, tid * per), b = min(wpr, a + per);
+      int32_t sum = 0;
+      for (int32_t i = a; i < b; ++i) sum += __popc(bm[i]);
+      int32_t incl = sum;
+#pragma unroll
+      for (int off = 1; off < 64; off <<= 1) {
+        const int32_t t = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += t;
+      }
+      if (lane == 63) wsum[wave] = incl;
+      __syncthreads();
+      int32_t run = incl - sum;
+      for (int w = 0; w < wave; ++w) run += wsum[w];
+      for (int32_t i = a; i < b; ++i) {
+        wpos[i] = run;
+        run += __popc(bm[i]);
+      }
+      __syncthreads();
+#pragma unroll
+      for (int u = 0; u < kRowBmU; ++u) {
+        if (u * 256 + tid >= len) continue;
+        const int32_t w = ec[u] >> 5;
+        const int32_t pos = lo + wpos[w] + __popc(bm[w] & ((1u << (ec[u] & 31)) - 1u));
+        col_idx[pos] = ec[u];
+        src[pos] = sc[u * 256 + tid];
+      }
+      return;
+    }
+    // a repeated column: the pairwise ranking below (all threads read `repeat`
+    // after the same barrier, so the whole workgroup takes it)
+  }
   const bool in_lds = len <= kSortLds;
   for (int32_t i = threadIdx.x; i < len; i += blockDim.x) {
     const int32_t c = col_idx[lo + i], v = src[lo + i];
@@ -415,6 +592,11 @@ bool dynamic_small_fits(int32_t max_nnz, int32_t mb, int32_t kb, int32_t G) {
          dyn_small_lds_bytes(max_nnz, mb, G) <= kDynSmallLdsMax;
 }
 
+int32_t dyn_hist_wgs(int64_t max_nnz, int32_t mb) {
+  if (mb < 1 || (int64_t)mb * (int64_t)sizeof(int32_t) > 64 * 1024) return 0;
+  return (int32_t)std::min<int64_t>(256, std::max<int64_t>(1, ceil_div(max_nnz, kHistChunk)));
+}
+
 spmm_status_t build_dynamic_csr_small(const int32_t* nnz_dev, const int32_t* rows, const int32_t* cols,
                                       int32_t max_nnz, int32_t mb, int32_t kb, const Geometry& geo, PlanBuffers& pb,
                                       int32_t* status, int32_t* status_out, int32_t* nnz_last, hipStream_t s) {
@@ -446,14 +628,28 @@ spmm_status_t build_dynamic_csr(const int32_t* nnz_dev, const int32_t* rows, con
   int32_t* tmp_src = pb.ent_src;
   hipLaunchKernelGGL(k_dyn_zero, dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>(256, ceil_div(2 * mb, 256)))),
                      dim3(256), 0, s, row_cnt, (int64_t)2 * mb, status);
-  const unsigned egrid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(2048, ceil_div(max_nnz, 256)));
-  hipLaunchKernelGGL(k_dyn_row_count, dim3(egrid), dim3(256), 0, s, nnz_dev, max_nnz, rows, cols, mb, kb, row_cnt,
-                     status);
-  hipLaunchKernelGGL(k_dyn_scan_rows, dim3(1), dim3(1024), 0, s, row_cnt, mb, pb.row_ptr, status);
-  hipLaunchKernelGGL(k_dyn_row_scatter, dim3(egrid), dim3(256), 0, s, nnz_dev, rows, cols, pb.row_ptr, fill,
-                     pb.col_idx, pb.csr_src, status);
+  const int32_t wgs = dyn_hist_wgs(max_nnz, mb);
+  if (pb.hist && wgs > 0 && wgs <= pb.hist_wgs && !(getenv("SPMM_DYN_HIST") && getenv("SPMM_DYN_HIST")[0] == '0')) {
+    // counting sort by block row, no global atomics
+    const int32_t chunk = (int32_t)ceil_div(std::max(max_nnz, 1), wgs);
+    const size_t lds = sizeof(int32_t) * (size_t)mb;
+    hipLaunchKernelGGL(k_dyn_hist, dim3((unsigned)wgs), dim3(256), lds, s, nnz_dev, max_nnz, rows, cols, mb, kb, chunk,
+                       pb.hist, status);
+    hipLaunchKernelGGL(k_dyn_hist_scan, dim3((unsigned)ceil_div(mb, 256)), dim3(256), 0, s, pb.hist, wgs, mb, row_cnt,
+                       status);
+    hipLaunchKernelGGL(k_dyn_scan_rows, dim3(1), dim3(1024), 0, s, row_cnt, mb, pb.row_ptr, status);
+    hipLaunchKernelGGL(k_dyn_hist_scatter, dim3((unsigned)wgs), dim3(256), lds, s, nnz_dev, rows, cols, mb, chunk,
+                       pb.hist, pb.row_ptr, pb.col_idx, pb.csr_src, status);
+  } else {
+    const unsigned egrid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(2048, ceil_div(max_nnz, 256)));
+    hipLaunchKernelGGL(k_dyn_row_count, dim3(egrid), dim3(256), 0, s, nnz_dev, max_nnz, rows, cols, mb, kb, row_cnt,
+                       status);
+    hipLaunchKernelGGL(k_dyn_scan_rows, dim3(1), dim3(1024), 0, s, row_cnt, mb, pb.row_ptr, status);
+    hipLaunchKernelGGL(k_dyn_row_scatter, dim3(egrid), dim3(256), 0, s, nnz_dev, rows, cols, pb.row_ptr, fill,
+                       pb.col_idx, pb.csr_src, status);
+  }
   hipLaunchKernelGGL(k_dyn_row_sort, dim3((unsigned)mb), dim3(256), 0, s, pb.row_ptr, pb.col_idx, pb.csr_src, tmp_col,
-                     tmp_src, status);
+                     tmp_src, kb, status);
   if (vals_out && max_nnz > 0) {
     const unsigned vgrid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(4096, ceil_div((int64_t)max_nnz * b * b, 1024)));
     if (elem_bytes == 1)

@@ -186,7 +186,8 @@ static bool use_row_kernel_f32() {
 }
 
 static void free_plan_buffers(PlanBuffers& pb) {
-  int32_t* ptrs[] = {pb.cell_ptr, pb.ent_col, pb.ent_src, pb.panel_ptr, pb.row_ptr, pb.col_idx, pb.csr_src, pb.scratch};
+  int32_t* ptrs[] = {pb.cell_ptr, pb.ent_col, pb.ent_src, pb.panel_ptr, pb.row_ptr, pb.col_idx, pb.csr_src, pb.scratch,
+                     pb.hist};
   for (int32_t* p : ptrs)
     if (p) (void)hipFree(p);
   if (pb.cost_prefix) (void)hipFree(pb.cost_prefix);
@@ -215,6 +216,9 @@ static spmm_status_t alloc_plan_buffers(PlanBuffers& pb, const Geometry& geo, in
   if (dynamic && (st = dev_alloc(&pb.csr_src, nnz)) != SPMM_OK) return st;
   if ((st = dev_alloc(&pb.scratch, pb.scratch_ints)) != SPMM_OK) return st;
   if ((st = dev_alloc(&pb.cost_prefix, (int64_t)geo.num_groups + 1)) != SPMM_OK) return st;
+  if (dynamic && (pb.hist_wgs = dyn_hist_wgs(nnz, mb)) > 0 &&
+      (st = dev_alloc(&pb.hist, (int64_t)pb.hist_wgs * mb)) != SPMM_OK)
+    return st;
   return SPMM_OK;
 }
 

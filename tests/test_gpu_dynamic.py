@@ -256,3 +256,76 @@ def test_bitmap_rank_equals_pairwise_rank(case, monkeypatch):
         X64 = synth.storage_to_f64(synth.to_storage(synth.normal((k, n), 96), "f16"), "f16")
         assert O.rel_fro(outs[0].cpu().numpy().astype(np.float64),
                          O.spmm_blockwise(m, k, b, rows, cols, v64, X64)) <= 5e-3
+
+
+def test_multi_kernel_encoder_row_bitmap_and_fallbacks(monkeypatch):
+    """The multi-kernel encoder's per-row ordering: rows placed through the column
+    bitmap, rows with repeated (row, column) pairs and a row longer than 2048
+    entries (both ranked pairwise) all give the oracle's plan, and Y matches the
+    oracle (b = 1, 2048 x 4096 block grid)."""
+    monkeypatch.setenv("SPMM_DYN_BUILDER", "multi")
+    b, mb, kb, n = 1, 2048, 4096, 40
+    g = np.random.default_rng(123)
+    flat = g.choice(mb * kb, size=60000, replace=False)
+    rows, cols = (flat // kb).astype(np.int32), (flat % kb).astype(np.int32)
+    long_cols = g.choice(kb, size=3000, replace=False).astype(np.int32)  # row 7: 3000 entries
+    rows = np.concatenate([rows[rows != 7], np.full(3000, 7, np.int32)])
+    cols = np.concatenate([cols[flat // kb != 7], long_cols])
+    rep = np.nonzero(np.isin(rows, [11, 500, 2047]))[0][:12]  # repeat some pairs of three rows
+    rows, cols = np.concatenate([rows, rows[rep]]), np.concatenate([cols, cols[rep]])
+    perm = g.permutation(len(rows))
+    rows, cols = rows[perm], cols[perm]
+    nnz = len(rows)
+    vals = synth.to_storage(synth.normal((nnz, b, b), 124), "f16")
+    Xs = synth.to_storage(synth.normal((kb * b, n), 125), "f16")
+    h = spmm.DynamicHandle(mb * b, kb * b, b, nnz, "f16")
+    ref = plan_ref.plan_from_coo(mb, kb, rows, cols, h.info()["group_rows"], h.info()["num_panels"])
+    Y64 = O.spmm_blockwise(mb * b, kb * b, b, rows, cols, synth.storage_to_f64(vals, "f16"),
+                           synth.storage_to_f64(Xs, "f16"))
+    outs = []
+    # the per-workgroup histogram count and scatter, then the global-atomic one
+    for hist in (None, "0"):
+        if hist:
+            monkeypatch.setenv("SPMM_DYN_HIST", hist)
+        else:
+            monkeypatch.delenv("SPMM_DYN_HIST", raising=False)
+        Y = torch.full((mb * b, n), float("nan"), dtype=torch.float16, device="cuda")
+        status = torch.full((1,), -1, dtype=torch.int32, device="cuda")
+        h.run(torch.tensor([nnz], dtype=torch.int32, device="cuda"), dev(rows), dev(cols), dev(vals), dev(Xs), Y,
+              status)
+        torch.cuda.synchronize()
+        assert status.item() == 0
+        ex = h.export()
+        for key in ("row_ptr", "col_idx", "src", "panel_ptr"):
+            assert np.array_equal(ex[key], ref[key]), key
+        assert O.rel_fro(Y.cpu().numpy().astype(np.float64), Y64) <= 5e-3
+        outs.append(Y)
+    assert torch.equal(outs[0], outs[1])
+
+
+def test_multi_kernel_encoder_status_words(monkeypatch):
+    """The histogram encode reports capacity and index errors and leaves Y untouched."""
+    monkeypatch.setenv("SPMM_DYN_BUILDER", "multi")
+    b, m, k, n, cap = 4, 64, 80, 16, 3000
+    h = spmm.DynamicHandle(m, k, b, cap, "f16")
+    X = torch.ones((k, n), dtype=torch.float16, device="cuda")
+    v = torch.ones((cap, b, b), dtype=torch.float16, device="cuda")
+    g = np.random.default_rng(5)
+    rows = g.integers(0, m // b, cap).astype(np.int32)
+    cols = g.integers(0, k // b, cap).astype(np.int32)
+    bad_row, bad_col = rows.copy(), cols.copy()
+    bad_row[2999] = m // b
+    bad_col[1234] = -1
+    status = torch.zeros(1, dtype=torch.int32, device="cuda")
+    for r, c, nnz, want in [(rows, cols, cap + 1, spmm.ERR_CAPACITY), (bad_row, cols, cap, spmm.ERR_BAD_INDEX),
+                            (rows, bad_col, cap, spmm.ERR_BAD_INDEX), (rows, cols, cap, 0)]:
+        Y = torch.full((m, n), 3.0, dtype=torch.float16, device="cuda")
+        h.run(torch.tensor([nnz], dtype=torch.int32, device="cuda"), dev(r), dev(c), v, X, Y, status)
+        torch.cuda.synchronize()
+        assert status.item() == want
+        if want:
+            assert torch.all(Y == 3.0).item()
+    ref = plan_ref.plan_from_coo(m // b, k // b, rows, cols, h.info()["group_rows"], h.info()["num_panels"])
+    ex = h.export()
+    for key in ("row_ptr", "col_idx", "src", "panel_ptr"):
+        assert np.array_equal(ex[key], ref[key]), key
