@@ -24,6 +24,7 @@ Other modes print their own JSON lines:
   --mode ell        blocked-ELL plans, explicit padding, b = 16/32/64
   --mode grid       the paper's sweep grid best over n and its power-law fit
   --mode copy       a 256 MiB device copy (counter calibration)
+  --mode peaks      measured HBM bandwidth (copy, read) and dense FP16/BF16 GEMM rate
 """
 import argparse
 import hashlib
@@ -56,7 +57,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--mode", default="headline",
                     choices=["headline", "sweep", "dynamic", "precision", "copy", "serve", "group", "table3", "small",
-                             "skew", "train", "grid", "ell"])
+                             "skew", "train", "grid", "ell", "peaks"])
     ap.add_argument("--requests", type=int, default=2000, help="serve mode: measured requests per run")
     ap.add_argument("--rho", default="0.5,0.8", help="serve mode: offered load as fractions of the saturated rate")
     ap.add_argument("--max-tokens", default="4096,16384,0",
@@ -958,6 +959,39 @@ def mode_copy(args):
     emit({"mode": "copy", "bytes_read": x.numel() * 4, "bytes_written": y.numel() * 4, "ms": ms}, args.out)
 
 
+def mode_peaks(args):
+    """Measured peaks for the roofline: HBM bandwidth of a 1 GiB device copy
+    (bytes read + written) and of a 2 GiB read-only reduction, and the dense
+    FP16 / BF16 matrix-core rate of hipBLASLt GEMMs (torch.matmul) at
+    8192 x 8192 x 8192. Library kernels, used only as yardsticks."""
+    import torch
+    n = 1024 * 1024 * 1024 // 4
+    x = torch.ones(n, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    ms = time_steps(lambda: y.copy_(x), args.steps, args.warmup)
+    emit({"mode": "peaks", "what": "hbm_copy", "bytes": 2 * n * 4, "ms": round(ms, 4),
+          "gbs": round(2 * n * 4 / (ms * 1e-3) / 1e9, 1), "datasheet_gbs": HBM_PEAK_GBS}, args.out)
+    del y
+    z = torch.ones(2 * n, dtype=torch.float32, device="cuda")
+    out = torch.empty((), dtype=torch.float32, device="cuda")
+    ms = time_steps(lambda: torch.sum(z, dim=0, out=out), args.steps, args.warmup)
+    emit({"mode": "peaks", "what": "hbm_read", "bytes": 2 * n * 4, "ms": round(ms, 4),
+          "gbs": round(2 * n * 4 / (ms * 1e-3) / 1e9, 1), "datasheet_gbs": HBM_PEAK_GBS}, args.out)
+    del x, z
+    torch.cuda.empty_cache()
+    for dt, name in ((torch.float16, "f16"), (torch.bfloat16, "bf16")):
+        m = 8192
+        a = torch.randn((m, m), device="cuda").to(dt)
+        b = torch.randn((m, m), device="cuda").to(dt)
+        c = torch.empty((m, m), device="cuda", dtype=dt)
+        ms = time_steps(lambda: torch.matmul(a, b, out=c), args.steps, args.warmup)
+        emit({"mode": "peaks", "what": "gemm_" + name, "m": m, "n": m, "k": m, "ms": round(ms, 4),
+              "tflops": round(2.0 * m ** 3 / (ms * 1e-3) / 1e12, 1),
+              "datasheet_tflops": MFMA_PEAK_TFLOPS[name]}, args.out)
+        del a, b, c
+        torch.cuda.empty_cache()
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -973,7 +1007,7 @@ def main():
     {"headline": mode_headline, "sweep": mode_sweep, "precision": mode_precision, "copy": mode_copy,
      "dynamic": mode_dynamic, "serve": mode_serve, "group": mode_group, "table3": mode_table3,
      "small": mode_small, "skew": mode_skew, "train": mode_train, "grid": mode_grid,
-     "ell": mode_ell}[args.mode](args)
+     "ell": mode_ell, "peaks": mode_peaks}[args.mode](args)
 
 
 if __name__ == "__main__":
