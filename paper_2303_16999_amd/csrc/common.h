@@ -90,11 +90,13 @@ spmm_status_t build_dynamic_plan(const int32_t* nnz_dev, const int32_t* rows, co
                                  PlanBuffers& pb, int32_t* status_internal, int32_t* status_out,
                                  hipStream_t stream);
 // Dynamic, block-CSR form: validate, bucket by block row, sort rows by (column,
-// input index), gather values into CSR order, panels from the row groups.
+// input index), gather values into CSR order, panels from the row groups;
+// then the caller's status word and (when nnz_last is not NULL) the entry count.
 spmm_status_t build_dynamic_csr(const int32_t* nnz_dev, const int32_t* rows, const int32_t* cols, int32_t max_nnz,
                                 int32_t mb, int32_t kb, int32_t b, int32_t k, const Geometry& geo, PlanBuffers& pb,
                                 const void* vals, void* vals_out, int elem_bytes, const float* scales,
-                                float* scales_out, int32_t* status, int32_t* status_out, hipStream_t stream);
+                                float* scales_out, int32_t* status, int32_t* status_out, int32_t* nnz_last,
+                                hipStream_t stream);
 // The same encode in one workgroup with the entries in LDS (block-CSR, sources
 // and panels only; the values stay where the caller put them and the kernels
 // read them through csr_src). Applies when dynamic_small_fits().

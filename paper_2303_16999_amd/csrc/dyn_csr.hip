@@ -316,20 +316,6 @@ __global__ void k_dyn_gather(const int32_t* __restrict__ nnz_dev, const int32_t*
   }
 }
 
-// Group costs straight from row_ptr, then prefix and panel boundaries.
-__global__ void k_dyn_group_cost(const int32_t* __restrict__ row_ptr, int32_t G, int32_t GR, int32_t mb,
-                                 int64_t* __restrict__ cost, const int32_t* status) {
-  if (*status) return;
-  const int32_t g = blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= G) return;
-  const int32_t lo = g * GR, hi = min(mb, lo + GR);
-  cost[g] = (int64_t)(row_ptr[hi] - row_ptr[lo]) + (hi - lo);
-}
-
-__global__ void k_dyn_status_out(const int32_t* __restrict__ internal, int32_t* __restrict__ out) {
-  if (threadIdx.x == 0) *out = *internal;
-}
-
 // ------------------------------------------------------------------ one-workgroup builder
 // The whole encode of one dynamic call in a single workgroup of 1024 threads,
 // with the entries staged in LDS: validate and count per row (LDS atomics),
@@ -567,6 +553,48 @@ __global__ __launch_bounds__(1024) void k_dyn_small(const int32_t* __restrict__ 
   }
 }
 
+// The end of the multi-kernel encode in one workgroup: group costs (blocks +
+// rows of each group of GR block rows) from row_ptr, their exclusive scan in
+// place (C[G] the total), the panel boundaries (smallest g with
+// C[g] >= floor(p C[G] / P)), then the caller's status word and the entry
+// count of the call. The costs and panels are skipped when the status is set.
+__global__ __launch_bounds__(1024) void k_dyn_tail(const int32_t* __restrict__ row_ptr, int32_t G, int32_t GR,
+                                                   int32_t mb, int32_t P, int64_t* C, int32_t* __restrict__ panel_ptr,
+                                                   const int32_t* __restrict__ nnz_dev, const int32_t* status,
+                                                   int32_t* __restrict__ status_out, int32_t* __restrict__ nnz_last) {
+  __shared__ int64_t part64[kSmallThreads];
+  const int tid = threadIdx.x;
+  const int32_t st = *status;
+  if (st == 0) {
+    for (int32_t g = tid; g < G; g += kSmallThreads) {
+      const int32_t lo = g * GR, hi = min(mb, lo + GR);
+      C[g] = (int64_t)(row_ptr[hi] - row_ptr[lo]) + (hi - lo);
+    }
+    __syncthreads();
+    block_exscan_chunks<int64_t, int64_t>(C, G, C, part64);
+    for (int32_t p = tid; p <= P; p += kSmallThreads) {
+      int32_t v;
+      if (p == 0) v = 0;
+      else if (p == P) v = G;
+      else {
+        const int64_t target = ((int64_t)p * C[G]) / P;
+        int32_t lo = 0, hi = G;
+        while (lo < hi) {
+          const int32_t mid = (lo + hi) >> 1;
+          if (C[mid] >= target) hi = mid;
+          else lo = mid + 1;
+        }
+        v = lo;
+      }
+      panel_ptr[p] = v;
+    }
+  }
+  if (tid == 0) {
+    if (status_out) *status_out = st;
+    if (nnz_last) *nnz_last = *nnz_dev;
+  }
+}
+
 // LDS of the one-workgroup builder; with bm_words > 0 the staged-entry region
 // also holds the bitmap form's column bitmaps (bm_words words), their scanned
 // bit counts (bm_words + 1) and the packed block-CSR (max_nnz words).
@@ -614,13 +642,13 @@ spmm_status_t build_dynamic_csr_small(const int32_t* nnz_dev, const int32_t* row
   return SPMM_OK;
 }
 
-spmm_status_t build_panels_from_costs(int32_t G, int32_t P, int64_t* cost_prefix, int32_t* panel_ptr,
-                                      const int32_t* status, hipStream_t s);
+
 
 spmm_status_t build_dynamic_csr(const int32_t* nnz_dev, const int32_t* rows, const int32_t* cols, int32_t max_nnz,
                                 int32_t mb, int32_t kb, int32_t b, int32_t k, const Geometry& geo, PlanBuffers& pb,
                                 const void* vals, void* vals_out, int elem_bytes, const float* scales,
-                                float* scales_out, int32_t* status, int32_t* status_out, hipStream_t s) {
+                                float* scales_out, int32_t* status, int32_t* status_out, int32_t* nnz_last,
+                                hipStream_t s) {
   if (mb > 1024 * 64) return fail(SPMM_ERR_UNSUPPORTED, "dynamic CSR builder supports at most 65536 block rows");
   int32_t* row_cnt = pb.scratch;            // [mb]
   int32_t* fill = pb.scratch + mb;          // [mb]
@@ -662,11 +690,8 @@ spmm_status_t build_dynamic_csr(const int32_t* nnz_dev, const int32_t* rows, con
       hipLaunchKernelGGL(k_dyn_gather<uint32_t>, dim3(vgrid), dim3(256), 0, s, nnz_dev, pb.csr_src, pb.col_idx, b, k,
                          (const uint32_t*)vals, (uint32_t*)vals_out, scales, scales_out, status);
   }
-  hipLaunchKernelGGL(k_dyn_group_cost, dim3((unsigned)ceil_div(geo.num_groups, 256)), dim3(256), 0, s, pb.row_ptr,
-                     geo.num_groups, geo.group_rows, mb, pb.cost_prefix, status);
-  spmm_status_t st = build_panels_from_costs(geo.num_groups, geo.num_panels, pb.cost_prefix, pb.panel_ptr, status, s);
-  if (st != SPMM_OK) return st;
-  if (status_out) hipLaunchKernelGGL(k_dyn_status_out, dim3(1), dim3(64), 0, s, status, status_out);
+  hipLaunchKernelGGL(k_dyn_tail, dim3(1), dim3(kSmallThreads), 0, s, pb.row_ptr, geo.num_groups, geo.group_rows, mb,
+                     geo.num_panels, pb.cost_prefix, pb.panel_ptr, nnz_dev, status, status_out, nnz_last);
   SPMM_HIP(hipGetLastError());
   return SPMM_OK;
 }

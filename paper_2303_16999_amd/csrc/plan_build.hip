@@ -210,14 +210,6 @@ __global__ void k_panels(const int64_t* __restrict__ C, int32_t G, int32_t P, in
 
 }  // namespace
 
-spmm_status_t build_panels_from_costs(int32_t G, int32_t P, int64_t* cost_prefix, int32_t* panel_ptr,
-                                      const int32_t* status, hipStream_t s) {
-  hipLaunchKernelGGL(k_cost_scan, dim3(1), dim3(kScanThreads), 0, s, cost_prefix, G, status);
-  hipLaunchKernelGGL(k_panels, dim3((unsigned)ceil_div(P + 1, 256)), dim3(256), 0, s, cost_prefix, G, P, panel_ptr,
-                     status);
-  hipError_t e = hipGetLastError();
-  return e == hipSuccess ? SPMM_OK : fail_hip(e, "panel launch");
-}
 
 namespace {
 

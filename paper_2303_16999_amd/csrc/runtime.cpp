@@ -746,9 +746,8 @@ spmm_status_t spmm_run_dynamic(spmm_dyn_t h, const int32_t* nnzb_dev, const int3
     } else {
       st = build_dynamic_csr(nnzb_dev, rows, cols, (int32_t)h->max_nnzb, h->mb, h->kb, h->b, (int32_t)h->k, h->geo,
                              h->pb, values_dev, h->packed, dtype_bytes(h->w), scales_dev, h->packed_scales, h->status,
-                             status_dev, s);
+                             status_dev, h->nnz_last, s);
       if (st != SPMM_OK) return st;
-      SPMM_HIP(hipMemcpyAsync(h->nnz_last, nnzb_dev, sizeof(int32_t), hipMemcpyDeviceToDevice, s));
     }
     h->ran = true;
     h->csr_path = true;
