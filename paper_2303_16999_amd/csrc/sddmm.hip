@@ -28,7 +28,11 @@ typedef float float4_t __attribute__((ext_vector_type(4)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr uint32_t kOOB = 0x80000000u;
-constexpr int kTaskBlocks = 4;  // blocks of one row per task (b = 16; b = 32 takes 1)
+// Blocks of one row per task: 4 for b = 16 (8 measured no faster: the dY
+// fragment's reuse gains less than the halved occupancy costs), 2 for b = 32
+// (16% faster than 1 at m = k = 8192, n = 4096, d = 1/16).
+template <int B>
+__host__ __device__ constexpr int task_blocks() { return B == 16 ? 4 : 2; }
 
 struct SddmmParams {
   const int32_t* row_ptr;
@@ -93,13 +97,13 @@ __device__ __forceinline__ int32_t xcd_task(int32_t w, int32_t U) {
 
 template <int B>
 __host__ __device__ constexpr int sddmm_lds_bytes() {
-  return 4 * (kTaskBlocks / ((B / 16) * (B / 16))) * (B / 16) * (B / 16) * 64 * 16;
+  return 4 * task_blocks<B>() * (B / 16) * (B / 16) * 64 * 16;
 }
 
 template <typename T, int B, bool SPLIT>
 __global__ __launch_bounds__(256) void k_sddmm(SddmmParams p) {
   constexpr int H = B / 16;
-  constexpr int G = kTaskBlocks / (H * H);  // blocks per task
+  constexpr int G = task_blocks<B>();  // blocks per task
   extern __shared__ float4_t sd_red[];      // [wave][G][H][H][64 lanes]
   const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int g = lane >> 4, j = lane & 15;
@@ -240,7 +244,7 @@ spmm_status_t launch_t(const SddmmParams& p, int32_t b, hipStream_t s) {
 
 }  // namespace
 
-int32_t sddmm_task_blocks(int32_t b) { return kTaskBlocks / ((b / 16) * (b / 16)); }
+int32_t sddmm_task_blocks(int32_t b) { return b == 16 ? task_blocks<16>() : task_blocks<32>(); }
 
 spmm_status_t launch_sddmm(spmm_dtype_t t, int32_t b, const int32_t* row_ptr, const int32_t* col_idx,
                            const int32_t* tasks, int32_t num_tasks, int64_t m, int64_t k, int64_t n, const void* dY,
