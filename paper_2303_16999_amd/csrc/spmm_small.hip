@@ -17,6 +17,8 @@
 // pair is two consecutive nonzeros of the row. FP32 and FP8 weights take FP32
 // FMAs (an FP8 weight is decoded exactly and multiplied by its block scale).
 // Workgroups are ordered XCD-aware, as in the row-wise MFMA kernel.
+#include <cstdlib>
+
 #include "common.h"
 
 namespace spmm {
@@ -401,6 +403,150 @@ __global__ __launch_bounds__(256) void k_spmm_small_mfma(SParams p) {
   }
 }
 
+// The same computation with its block loop software-pipelined, for launches
+// with few workgroups per CU, where nothing else hides the loads' latency:
+// the next group of blocks is loaded into a second buffer while the current
+// group's MFMAs run. As in the pipelined row-wise kernel, every load is
+// unconditional (indices clamped, X offsets out of range past the row's end,
+// weight rows clamped and masked at MFMA time), the X rows are transposed only
+// at MFMA time, and the column and value indices of up to 64 blocks come from
+// one vector load, handed to each lane group with a lane permute. Chunks of 64
+// blocks start at multiples of 32 / b blocks from the row's start, so the
+// groups, and the MFMA inputs, are those of the plain kernel: the results are
+// the same bit for bit.
+template <int B>
+struct SmallBuf {
+  uint32_t adw[4];     // A operand: row j of this lane group's blocks (unmasked)
+  uint32_t rows[8][4]; // raw X rows of this lane group's blocks
+};
+
+template <typename XT, typename YT, int B>
+__global__ __launch_bounds__(256) void k_spmm_small_mfma_pp(SParams p) {
+  static_assert(B == 4 || B == 8, "MFMA form of the small block sizes");
+  constexpr int BPM = 32 / B;  // blocks per MFMA
+  constexpr int BPG = 8 / B;   // blocks per lane group
+  if (p.status && *p.status) return;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int g = lane >> 4, j = lane & 15;
+  const int32_t unit = xcd_unit(blockIdx.x, p.num_units);
+  const int32_t rgroups = (p.mb + kRowsPerWg - 1) / kRowsPerWg;
+  const int32_t r = (unit % rgroups) * kRowsPerWg + wave;
+  const int32_t n0 = (unit / rgroups) * 128;
+  if (r >= p.mb) return;
+  __amdgpu_buffer_rsrc_t xr = __builtin_amdgcn_make_buffer_rsrc((void*)p.X, (short)0, (int)p.x_bytes, 0x00020000);
+  const uint8_t* __restrict__ Wb = (const uint8_t*)p.W;
+  const uint32_t lane_off = (uint32_t)((n0 + 8 * j) * 2);
+  const int jj = j < B ? j : B - 1;  // weight row read by this lane (rows j >= B are masked)
+  float4_t acc[8];
+#pragma unroll
+  for (int s = 0; s < 8; ++s) acc[s] = float4_t{0.f, 0.f, 0.f, 0.f};
+  const int32_t q_lo = uniform(p.row_ptr[r]), q_hi = uniform(p.row_ptr[r + 1]);
+  for (int32_t c0 = q_lo; c0 < q_hi; c0 += 64) {
+    const int32_t cn = min(64, q_hi - c0);
+    const int32_t civ = lane < cn ? p.col_idx[c0 + lane] : 0;
+    const int32_t wiv = p.w_index ? (lane < cn ? p.w_index[c0 + lane] : 0) : c0 + lane;
+    // the group of BPM blocks starting at chunk offset t; lane group g takes BPG of them
+    auto load = [&](int32_t t, SmallBuf<B>& S) {
+#pragma unroll
+      for (int tt = 0; tt < BPG; ++tt) {
+        const int32_t idx = t + g * BPG + tt;
+        const int32_t ic = min(idx, cn - 1);
+        const int32_t c = __shfl(civ, ic, 64);
+        const int64_t qv = __shfl(wiv, ic, 64);
+        const uint8_t* src = Wb + qv * (B * B * 2) + jj * (B * 2);
+        if constexpr (B == 8) {
+          const u32x4 w = *(const u32x4*)src;
+          S.adw[0] = w[0]; S.adw[1] = w[1]; S.adw[2] = w[2]; S.adw[3] = w[3];
+        } else {
+          const u32x2 w = *(const u32x2*)src;
+          S.adw[2 * tt] = w.x;
+          S.adw[2 * tt + 1] = w.y;
+        }
+#pragma unroll
+        for (int e = 0; e < B; ++e) {
+          const int32_t krow = c * B + e;
+          const uint32_t off = (idx < cn && krow < p.k) ? (uint32_t)((int64_t)krow * p.ldx * 2) + lane_off : kOOB;
+          const u32x4 v = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(xr, off, 0, 0));
+#pragma unroll
+          for (int d = 0; d < 4; ++d) S.rows[tt * B + e][d] = v[d];
+        }
+      }
+    };
+    auto mma = [&](int32_t t, const SmallBuf<B>& S) {
+      // A: zero for lanes j >= B and for blocks past the row's end, as in the plain kernel
+      u32x4 a;
+#pragma unroll
+      for (int d = 0; d < 4; ++d) {
+        const int tt = B == 8 ? 0 : d / 2;
+        a[d] = (j < B && t + g * BPG + tt < cn) ? S.adw[d] : 0u;
+      }
+#pragma unroll
+      for (int s = 0; s < 8; ++s) {
+        const uint32_t sel = (s & 1) ? 0x07060302u : 0x05040100u;
+        u32x4 bv;
+#pragma unroll
+        for (int d = 0; d < 4; ++d) bv[d] = __builtin_amdgcn_perm(S.rows[2 * d + 1][s >> 1], S.rows[2 * d][s >> 1], sel);
+        acc[s] = Mfma<XT>::k32(a, bv, acc[s]);
+      }
+    };
+    SmallBuf<B> A, Bf;
+    load(0, A);
+    for (int32_t t = 0; t < cn; t += 2 * BPM) {
+      load(t + BPM, Bf);
+      mma(t, A);
+      if (t + BPM >= cn) break;
+      load(t + 2 * BPM, A);
+      mma(t + BPM, Bf);
+    }
+  }
+  // epilogue: as in the plain kernel
+  if (4 * g >= B) return;
+  if (p.relu) {
+#pragma unroll
+    for (int s = 0; s < 8; ++s)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) acc[s][i] = acc[s][i] > 0.f ? acc[s][i] : 0.f;
+  }
+  YT* __restrict__ Y = (YT*)p.Y;
+  const int32_t col0 = n0 + 8 * j;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int64_t row = (int64_t)r * B + 4 * g + i;
+    if (row >= p.m) continue;
+    YT* dst = Y + row * p.ldy + col0;
+    if (col0 + 8 <= p.n) {
+      if constexpr (sizeof(YT) == 4) {
+        *(float4_t*)dst = float4_t{acc[0][i], acc[1][i], acc[2][i], acc[3][i]};
+        *(float4_t*)(dst + 4) = float4_t{acc[4][i], acc[5][i], acc[6][i], acc[7][i]};
+      } else {
+        uint32_t o[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          o[e] = (uint32_t)Num<YT>::store(acc[2 * e][i]) | ((uint32_t)Num<YT>::store(acc[2 * e + 1][i]) << 16);
+        *(u32x4*)dst = u32x4{o[0], o[1], o[2], o[3]};
+      }
+    } else {
+#pragma unroll
+      for (int s = 0; s < 8; ++s)
+        if (col0 + s < p.n) {
+          if constexpr (sizeof(YT) == 4) dst[s] = acc[s][i];
+          else ((uint16_t*)dst)[s] = Num<YT>::store(acc[s][i]);
+        }
+    }
+  }
+}
+
+// The pipelined MFMA form for launches of at most eight workgroups per CU
+// whose rows average at least four groups of 32 / b blocks. Measured at
+// m = k = 8192: n = 256, b = 8 (512 workgroups) 11 - 22% faster, b = 4 (1024)
+// 13%, n = 1024, b = 8 (2048) 6%; one loss, m = k = 2048, n = 1024, b = 4
+// (1024 workgroups, rows of 64 blocks), 5% slower. SPMM_SMALL_PP=0/1 forces
+// the choice (for comparisons).
+bool small_pp_preferred(int32_t b, int64_t units, int32_t mb, int64_t nnz, int num_cus) {
+  if (const char* e = getenv("SPMM_SMALL_PP")) return e[0] == '1';
+  return units <= 8 * (int64_t)num_cus && nnz >= 4 * (32 / b) * (int64_t)mb;
+}
+
 template <typename XT, typename WT, typename YT, int B, int V>
 spmm_status_t launch_small(const RunArgs& a, const int32_t* row_ptr, const int32_t* col_idx, hipStream_t s) {
   SParams p;
@@ -428,8 +574,12 @@ spmm_status_t launch_small(const RunArgs& a, const int32_t* row_ptr, const int32
   if (units == 0) return SPMM_OK;
   if (units > (int64_t)INT32_MAX) return fail(SPMM_ERR_UNSUPPORTED, "too many work units");
   p.num_units = (int32_t)units;
-  if constexpr (kMfma)
-    hipLaunchKernelGGL((k_spmm_small_mfma<XT, YT, B>), dim3((unsigned)units), dim3(256), 0, s, p);
+  if constexpr (kMfma) {
+    if (small_pp_preferred(B, units, a.plan.mb, a.nnz, device_cu_count()))
+      hipLaunchKernelGGL((k_spmm_small_mfma_pp<XT, YT, B>), dim3((unsigned)units), dim3(256), 0, s, p);
+    else
+      hipLaunchKernelGGL((k_spmm_small_mfma<XT, YT, B>), dim3((unsigned)units), dim3(256), 0, s, p);
+  }
   else
     hipLaunchKernelGGL((k_spmm_small<XT, WT, YT, B, V>), dim3((unsigned)units), dim3(256), 0, s, p);
   SPMM_HIP(hipGetLastError());
