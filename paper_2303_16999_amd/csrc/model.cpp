@@ -10,9 +10,9 @@ using namespace spmm;
 namespace {
 // Least-squares fit of log(speedup) over the grid m = k in 2^8 .. 2^13,
 // b in {1, 4, 8, 16}, d in {1/4, 1/8, 1/16, 1/32}, FP16, sparse and dense each
-// best over n in 4^1 .. 4^8 (96 points, R^2 = 0.905, rms error of log speedup
+// best over n in 4^1 .. 4^8 (96 points, R^2 = 0.909, rms error of log speedup
 // 0.29).
-constexpr double kA = 0.08495, kAlpha = -0.05305, kBeta = -0.6427, kGamma = 0.7181;
+constexpr double kA = 0.07649, kAlpha = -0.04109, kBeta = -0.6541, kGamma = 0.7269;
 }  // namespace
 
 extern "C" {

@@ -19,7 +19,7 @@ import numpy as np
 PAPER_FIT = {"a": 0.0013, "alpha": 0.59, "beta": -0.54, "gamma": 0.50}
 # The same form fitted to this library on one MI355X (bench.py --mode grid, 96
 # points; the C ABI's spmm_speedup_model carries these numbers).
-MI355X_FIT = {"a": 0.08495, "alpha": -0.05305, "beta": -0.6427, "gamma": 0.7181}
+MI355X_FIT = {"a": 0.07649, "alpha": -0.04109, "beta": -0.6541, "gamma": 0.7269}
 
 
 def fit(points):
