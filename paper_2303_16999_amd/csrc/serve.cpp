@@ -137,7 +137,10 @@ struct spmm_srv_s {
 
   Pool* pool = nullptr;
   uint8_t* pool_dev = nullptr;
-  hipStream_t stream = nullptr;
+  hipStream_t stream = nullptr;       // the layers' kernels
+  hipStream_t copy_stream = nullptr;  // request inputs and outputs over PCIe, overlapping the kernels
+  hipEvent_t up_ev = nullptr;         // a step's uploads done (the kernels wait for it)
+  hipEvent_t done_ev = nullptr;       // a step's kernels done (the downloads wait for it)
   spmm_group_t group = nullptr;
   spmm_serve_stats_t stats{};
 
@@ -192,16 +195,20 @@ static std::vector<Request> admit_locked(spmm_srv_s* s, int limit) {
   return out;
 }
 
-// Host <-> device copies of a request's input and output: one contiguous copy
-// when the host layout equals the device layout, else a strided one.
+// Host <-> device copies of a request's input and output, on the copy stream:
+// one contiguous copy when the host layout equals the device layout, else a
+// strided one. A step's uploads are fenced by up_ev before its kernels, its
+// downloads wait for done_ev after them, and the step's completion event is
+// recorded on the copy stream, so a request's memory returns to the pool only
+// once its output has left the device.
 static spmm_status_t upload_input(spmm_srv_s* s, const Request& r) {
   if (s->opts.simulate) return SPMM_OK;
   if (r.ld_host == r.ld)
     SPMM_HIP(hipMemcpyAsync(buffer(s, r, 0), r.x_host, (size_t)(s->dims[0] * r.ld * s->elem), hipMemcpyHostToDevice,
-                            s->stream));
+                            s->copy_stream));
   else
     SPMM_HIP(hipMemcpy2DAsync(buffer(s, r, 0), (size_t)(r.ld * s->elem), r.x_host, (size_t)(r.ld_host * s->elem),
-                              (size_t)(r.n * s->elem), (size_t)s->dims[0], hipMemcpyHostToDevice, s->stream));
+                              (size_t)(r.n * s->elem), (size_t)s->dims[0], hipMemcpyHostToDevice, s->copy_stream));
   return SPMM_OK;
 }
 
@@ -209,11 +216,11 @@ static spmm_status_t download_output(spmm_srv_s* s, const Request& r) {
   if (s->opts.simulate) return SPMM_OK;
   if (r.ld_host == r.ld)
     SPMM_HIP(hipMemcpyAsync(r.y_host, buffer(s, r, s->L % 2), (size_t)(s->dims[s->L] * r.ld * s->elem),
-                            hipMemcpyDeviceToHost, s->stream));
+                            hipMemcpyDeviceToHost, s->copy_stream));
   else
     SPMM_HIP(hipMemcpy2DAsync(r.y_host, (size_t)(r.ld_host * s->elem), buffer(s, r, s->L % 2),
                               (size_t)(r.ld * s->elem), (size_t)(r.n * s->elem), (size_t)s->dims[s->L],
-                              hipMemcpyDeviceToHost, s->stream));
+                              hipMemcpyDeviceToHost, s->copy_stream));
   return SPMM_OK;
 }
 
@@ -275,6 +282,11 @@ static spmm_status_t do_step(spmm_srv_s* s, int32_t* remaining) {
   }
   for (const Request& r : admitted)
     if (st == SPMM_OK) st = upload_input(s, r);
+  if (st == SPMM_OK && !admitted.empty() && !s->opts.simulate) {
+    hipError_t e = hipEventRecord(s->up_ev, s->copy_stream);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s->stream, s->up_ev, 0);
+    if (e != hipSuccess) st = fail_hip(e, "upload fence");
+  }
   for (Request& r : admitted) {  // only the stepping thread touches `active`
     s->active.push_back(r);
     s->active_tokens += r.n;
@@ -327,6 +339,11 @@ static spmm_status_t do_step(spmm_srv_s* s, int32_t* remaining) {
       s->stats.problems_run += (int64_t)cnt;
       for (Request& r : s->active) r.layer += 1;
     }
+    if (st == SPMM_OK && !s->opts.simulate) {
+      hipError_t e = hipEventRecord(s->done_ev, s->stream);
+      if (e == hipSuccess) e = hipStreamWaitEvent(s->copy_stream, s->done_ev, 0);
+      if (e != hipSuccess) st = fail_hip(e, "step fence");
+    }
     for (const Request& r : s->active)
       if (r.layer == s->L && st == SPMM_OK) st = download_output(s, r);
     size_t w = 0;
@@ -350,7 +367,7 @@ static spmm_status_t do_step(spmm_srv_s* s, int32_t* remaining) {
         if (e != hipSuccess) st = fail_hip(e, "hipEventCreate");
       }
       if (st == SPMM_OK) {
-        hipError_t e = hipEventRecord(f.ev, s->stream);
+        hipError_t e = hipEventRecord(f.ev, s->copy_stream);  // after the step's kernels and downloads
         if (e != hipSuccess) st = fail_hip(e, "hipEventRecord");
       }
       if (st == SPMM_OK) {
@@ -361,6 +378,7 @@ static spmm_status_t do_step(spmm_srv_s* s, int32_t* remaining) {
       }
     } else if (st == SPMM_OK && !s->opts.simulate) {
       hipError_t e = hipStreamSynchronize(s->stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(s->copy_stream);
       if (e != hipSuccess) st = fail_hip(e, "serving step");
     }
   } else if (st == SPMM_OK && async && !s->inflight.empty()) {
@@ -412,6 +430,12 @@ static void destroy_server(spmm_srv_s* s) {
     (void)hipStreamSynchronize(s->stream);
     (void)hipStreamDestroy(s->stream);
   }
+  if (s->copy_stream) {
+    (void)hipStreamSynchronize(s->copy_stream);
+    (void)hipStreamDestroy(s->copy_stream);
+  }
+  if (s->up_ev) (void)hipEventDestroy(s->up_ev);
+  if (s->done_ev) (void)hipEventDestroy(s->done_ev);
   for (auto& f : s->inflight) (void)hipEventDestroy(f.ev);
   for (hipEvent_t e : s->free_events) (void)hipEventDestroy(e);
   if (s->group) (void)spmm_group_destroy(s->group);
@@ -479,6 +503,12 @@ spmm_status_t spmm_serve_create(const spmm_plan_t* layer_plans, int32_t num_laye
       st = fail_hip(e, "hipMalloc activation pool");
     if (st == SPMM_OK && (e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking)) != hipSuccess)
       st = fail_hip(e, "hipStreamCreate");
+    if (st == SPMM_OK && (e = hipStreamCreateWithFlags(&s->copy_stream, hipStreamNonBlocking)) != hipSuccess)
+      st = fail_hip(e, "hipStreamCreate");
+    if (st == SPMM_OK && (e = hipEventCreateWithFlags(&s->up_ev, hipEventDisableTiming)) != hipSuccess)
+      st = fail_hip(e, "hipEventCreate");
+    if (st == SPMM_OK && (e = hipEventCreateWithFlags(&s->done_ev, hipEventDisableTiming)) != hipSuccess)
+      st = fail_hip(e, "hipEventCreate");
     if (st == SPMM_OK && opts->mode == SPMM_SERVE_CONTINUOUS) {
       for (int l = 0; l < num_layers && st == SPMM_OK; ++l)
         if (!plan_uses_row_kernel(s->plans[l]) || s->plans[l]->w == SPMM_FP8_E4M3 || s->plans[l]->b > 32 ||
