@@ -60,6 +60,8 @@ def parse():
                              "skew", "train", "grid", "ell", "peaks"])
     ap.add_argument("--requests", type=int, default=2000, help="serve mode: measured requests per run")
     ap.add_argument("--rho", default="0.5,0.8", help="serve mode: offered load as fractions of the saturated rate")
+    ap.add_argument("--rate-base", type=float, default=0.0,
+                    help="serve mode: requests/s that rho multiplies instead of the measured saturated rate")
     ap.add_argument("--max-tokens", default="4096,16384,0",
                     help="serve mode: per-step token budgets of the continuous path (0 = none)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
@@ -621,6 +623,8 @@ def mode_serve(args):
               "steps": st["steps"], "problems_per_step": round(st["problems_run"] / max(1, st["steps"]), 2),
               "paths_bitwise_equal": bool(same), "outputs_finite": bool(finite)}, args.out)
     mu_max = max(v for (name, cap), v in sat.items() if name == "continuous")
+    if args.rate_base > 0:  # a fixed base rate, so that runs offer the same load
+        mu_max = args.rate_base
 
     for rho in [float(v) for v in args.rho.split(",")]:
         arrivals, ns = synth.serving_trace(warm + nmeas, rho * mu_max, seed=12)

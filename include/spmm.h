@@ -237,8 +237,9 @@ spmm_status_t spmm_autotune_static(spmm_plan_t plan, int64_t n, const void* X, i
  * beyond the paper, whose benchmarks run one product at a time and let n grow
  * to amortise overheads (Sections 4 and 5); here the columns of many small
  * products share one launch instead. Up to 32 problems travel in the kernel
- * arguments, and the call replays a captured one-node HIP graph after
- * updating that node's arguments and grid. Larger groups go through a ring of
+ * arguments of one direct launch (with SPMM_GROUP_GRAPH=1 in the environment,
+ * the call instead replays a captured one-node HIP graph after updating that
+ * node's arguments and grid). Larger groups go through a ring of
  * four pinned host + device tables: the call copies its table and launches
  * on it, and waits on the host only when the slot it needs is still in use by
  * the call four before.

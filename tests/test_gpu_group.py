@@ -86,9 +86,12 @@ def test_group_matches_single_launches_and_oracle(b, w, y):
         assert O.rel_fro(y_f64(Ys[i], c), ref) <= 5e-3, i
 
 
-def test_group_graph_replays_with_new_tables():
-    """Replay the captured graph many times with different n, X and Y; eager work
-    and synchronisations between the replays; every replay checked."""
+@pytest.mark.parametrize("graph", ["1", "0"])
+def test_group_graph_replays_with_new_tables(graph, monkeypatch):
+    """Replay the captured graph (or, with SPMM_GROUP_GRAPH=0, launch directly)
+    many times with different n, X and Y; eager work and synchronisations
+    between the calls; every call checked."""
+    monkeypatch.setenv("SPMM_GROUP_GRAPH", graph)
     b = 16
     cases = _group_cases(b, "f16", "f16", [40, 300, 7, 129], seed=90)
     plans = [c.run_static()[0] for c in cases]
