@@ -656,7 +656,8 @@ def mode_serve(args):
 
 def mode_group(args):
     """The 16 serving matrices with n_i ~ log-uniform [1, 2048]: one grouped
-    persistent launch (graph replay) against 16 separate launches."""
+    persistent launch (a direct launch; SPMM_GROUP_GRAPH=1 replays a graph)
+    against 16 separate launches."""
     import torch
     from paper_2303_16999_amd import spmm, synth
     plans, dims, relu = mlp_plans()
