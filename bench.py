@@ -725,33 +725,27 @@ def mode_table3(args):
 
 def mode_small(args):
     """The small FP32 case: m = k = 1024, n = 64, b = 16, density 1/16 (row-wise
-    FP32 16x16x4 MFMA kernel, and the LDS-staged general kernel beside it):
-    latency and error against the FP64 oracle; then FP32 at m = k = 8192,
-    n = 1024, d = 1/16 on both kernels."""
+    FP32 16x16x4 MFMA kernel): latency and error against the FP64 oracle; then
+    FP32 at m = k = 8192, n = 1024, d = 1/16."""
     from oracle import spmm_ref as O
     import torch
-    for kernel in ("row", "general"):
-        if kernel == "general":
-            os.environ["SPMM_KERNEL"] = "general"
-        prob = StaticProblem(1024, 1024, 64, 16, 1 / 16, "f32", seed=0)
-        ms = time_steps(prob.step, max(args.steps, 50), args.warmup)
-        pct = launch_percentiles(prob.step, 50)
-        prob.step()
-        torch.cuda.synchronize()
-        ref = O.spmm_blockwise(1024, 1024, 16, prob.rows, prob.cols, prob.vals_store.astype(np.float64),
-                               prob.X_store.astype(np.float64))
-        err = O.rel_fro(prob.Y.cpu().numpy().astype(np.float64), ref)
-        emit({"mode": "small_fp32", "kernel": kernel, "m": 1024, "k": 1024, "n": 64, "b": 16, "density": 1 / 16,
-              "ms": round(ms, 5), "launch_ms_percentiles": pct,
-              "tflops": round(prob.flops() / (ms * 1e-3) / 1e12, 3), "rel_fro_vs_oracle": err, "bound": 1e-5},
-             args.out)
-        big = StaticProblem(8192, 8192, 1024, 16, 1 / 16, "f32", seed=0)
-        msb = time_steps(big.step, args.steps, args.warmup)
-        emit({"mode": "fp32_large", "kernel": kernel, "m": 8192, "k": 8192, "n": 1024, "b": 16, "density": 1 / 16,
-              "ms": round(msb, 5), "tflops": round(big.flops() / (msb * 1e-3) / 1e12, 3),
-              "mfma_fp32_frac": round(big.flops() / (msb * 1e-3) / 1e12 / MFMA_PEAK_TFLOPS["f32"], 4)}, args.out)
-        del prob, big
-        os.environ.pop("SPMM_KERNEL", None)
+    prob = StaticProblem(1024, 1024, 64, 16, 1 / 16, "f32", seed=0)
+    ms = time_steps(prob.step, max(args.steps, 50), args.warmup)
+    pct = launch_percentiles(prob.step, 50)
+    prob.step()
+    torch.cuda.synchronize()
+    ref = O.spmm_blockwise(1024, 1024, 16, prob.rows, prob.cols, prob.vals_store.astype(np.float64),
+                           prob.X_store.astype(np.float64))
+    err = O.rel_fro(prob.Y.cpu().numpy().astype(np.float64), ref)
+    emit({"mode": "small_fp32", "kernel": "row", "m": 1024, "k": 1024, "n": 64, "b": 16, "density": 1 / 16,
+          "ms": round(ms, 5), "launch_ms_percentiles": pct,
+          "tflops": round(prob.flops() / (ms * 1e-3) / 1e12, 3), "rel_fro_vs_oracle": err, "bound": 1e-5},
+         args.out)
+    big = StaticProblem(8192, 8192, 1024, 16, 1 / 16, "f32", seed=0)
+    msb = time_steps(big.step, args.steps, args.warmup)
+    emit({"mode": "fp32_large", "kernel": "row", "m": 8192, "k": 8192, "n": 1024, "b": 16, "density": 1 / 16,
+          "ms": round(msb, 5), "tflops": round(big.flops() / (msb * 1e-3) / 1e12, 3),
+          "mfma_fp32_frac": round(big.flops() / (msb * 1e-3) / 1e12 / MFMA_PEAK_TFLOPS["f32"], 4)}, args.out)
 
 
 def mode_skew(args):

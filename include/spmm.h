@@ -168,11 +168,18 @@ spmm_status_t spmm_run_static(spmm_plan_t plan, int64_t n, const void* X, int64_
 spmm_status_t spmm_plan_info(spmm_plan_t plan, int64_t* nnzb, int32_t* group_rows,
                              int32_t* num_groups, int32_t* num_panels, int32_t* num_split_rows);
 
-/* Host copies of the plan arrays, for inspection and tests:
- * row_ptr int32 [mb + 1], col_idx int32 [nnzb], panel_ptr int32 [num_panels + 1]
- * (entries are group indices). Any pointer may be NULL to skip that array. */
+/* Host copies of the plan arrays, for inspection and tests (Section 3.2: the
+ * static partition of the known blocks):
+ *   row_ptr   int32 [mb + 1], col_idx int32 [nnzb]: block-CSR, block rows
+ *             ascending, columns ascending inside a row;
+ *   panel_ptr int32 [num_panels + 1]: group indices, panels balanced by the
+ *             cost blocks + rows of their groups;
+ *   order     int32 [nnzb]: CSR positions listed group by group, inside a
+ *             group by (block column, block row): the column-major walk of a
+ *             group's blocks.
+ * Any pointer may be NULL to skip that array. Synchronises the device. */
 spmm_status_t spmm_plan_export(spmm_plan_t plan, int32_t* row_ptr, int32_t* col_idx,
-                               int32_t* panel_ptr);
+                               int32_t* panel_ptr, int32_t* order);
 
 spmm_status_t spmm_plan_destroy(spmm_plan_t plan);
 

@@ -29,36 +29,32 @@ int dtype_bytes(spmm_dtype_t t);
 bool dtype_triple_supported(spmm_dtype_t w, spmm_dtype_t x, spmm_dtype_t y);
 
 // ------------------------------------------------------------------ the kernel plan
-// Layout consumed by the compute kernels (static and dynamic build the same):
-//   blocks are bucketed into cells (group g, k-chunk ch, local row lr), cells
-//   ordered (g, ch, lr); inside a cell entries are sorted by (block column,
-//   source index). cell_ptr[NCELL + 1] delimits the cells, ent_col[e] is the
-//   block column of entry e and ent_src[e] the index of its values (the CSR
-//   position for static plans, the input index for dynamic calls).
+// Layout consumed by the compute kernels (static plans and dynamic calls build
+// the same): block-CSR (row_ptr, col_idx; columns ascending inside a row),
+// row groups of group_rows consecutive block rows, the cost-balanced panels of
+// the groups, and the in-group column-major order (order[q] is the CSR
+// position of the q-th block when each group lists its blocks by (block
+// column, block row); groups follow each other).
 struct KernelPlan {
   int32_t m, k, b;
   int32_t mb, kb;
-  int32_t group_rows;   // block rows per group (a workgroup's register tile)
+  int32_t group_rows;   // block rows per group
   int32_t num_groups;
-  int32_t chunk_cols;   // block columns per k-chunk
-  int32_t num_chunks;
   int32_t num_panels;
-  const int32_t* cell_ptr;   // [num_groups * num_chunks * group_rows + 1]
-  const int32_t* ent_col;    // [nnz]
-  const int32_t* ent_src;    // [nnz]
   const int32_t* panel_ptr;  // [num_panels + 1], group indices
+  const int32_t* order;      // [nnz] (static plans; nullptr for dynamic calls)
 };
 
-// Device buffers that back a KernelPlan, plus the canonical block-CSR.
+// Device buffers that back a KernelPlan.
 struct PlanBuffers {
-  int32_t* cell_ptr = nullptr;
-  int32_t* ent_col = nullptr;
-  int32_t* ent_src = nullptr;
   int32_t* panel_ptr = nullptr;
   int32_t* row_ptr = nullptr;
   int32_t* col_idx = nullptr;   // CSR columns
+  int32_t* order = nullptr;     // static: in-group column-major order of CSR positions
   int32_t* csr_src = nullptr;   // dynamic: input index of each CSR entry
-  int32_t* scratch = nullptr;   // counts / fills / scan partials
+  int32_t* tmp_col = nullptr;   // dynamic: [max_nnz] scratch of the multi-kernel encoder's row sort
+  int32_t* tmp_src = nullptr;
+  int32_t* scratch = nullptr;   // counts / scan partials
   int64_t* cost_prefix = nullptr;
   int64_t scratch_ints = 0;
   int32_t* hist = nullptr;      // dynamic: per-workgroup block-row histograms [hist_wgs][mb]
@@ -69,26 +65,19 @@ struct PlanBuffers {
 int32_t dyn_hist_wgs(int64_t max_nnz, int32_t mb);
 
 struct Geometry {
-  int32_t group_rows, chunk_cols, num_groups, num_chunks, num_panels;
-  int64_t num_cells;
+  int32_t group_rows, num_groups, num_panels;
 };
 
-// Chooses group_rows / chunk_cols for a shape. n_hint steers the row-group size
-// so that groups x n-tiles fills the chip.
+// Chooses group_rows for a shape. n_hint steers the row-group size so that
+// groups x n-tiles fills the chip.
 Geometry choose_geometry(int64_t m, int64_t k, int32_t b, int64_t nnz_hint, int64_t n_hint,
                          const spmm_plan_opts* opts, int num_cus, spmm_dtype_t x);
-// True when (b, x dtype) runs on the pipelined kernel, whose k-chunk is 64 rows.
-bool uses_pipe(int32_t b, spmm_dtype_t x);
 
 // ------------------------------------------------------------------ plan building kernels
 // All of these enqueue on `stream` and do not synchronise.
+// Static: block mask -> block-CSR, group costs, panels and the in-group order.
 spmm_status_t build_static_plan(const uint8_t* mask_dev, int32_t mb, int32_t kb, const Geometry& geo,
                                 PlanBuffers& pb, hipStream_t stream);
-// Dynamic: validates, buckets and sorts a COO list whose length lives on the device.
-spmm_status_t build_dynamic_plan(const int32_t* nnz_dev, const int32_t* rows, const int32_t* cols,
-                                 int32_t max_nnz, int32_t mb, int32_t kb, const Geometry& geo,
-                                 PlanBuffers& pb, int32_t* status_internal, int32_t* status_out,
-                                 hipStream_t stream);
 // Dynamic, block-CSR form: validate, bucket by block row, sort rows by (column,
 // input index), gather values into CSR order, panels from the row groups;
 // then the caller's status word and (when nnz_last is not NULL) the entry count.
@@ -104,33 +93,15 @@ bool dynamic_small_fits(int32_t max_nnz, int32_t mb, int32_t kb, int32_t num_gro
 spmm_status_t build_dynamic_csr_small(const int32_t* nnz_dev, const int32_t* rows, const int32_t* cols,
                                       int32_t max_nnz, int32_t mb, int32_t kb, const Geometry& geo, PlanBuffers& pb,
                                       int32_t* status, int32_t* status_out, int32_t* nnz_last, hipStream_t stream);
-// CSR (row_ptr, col_idx, csr_src) of a dynamic plan, derived from the cells.
-spmm_status_t dynamic_csr_from_cells(int32_t mb, const Geometry& geo, PlanBuffers& pb,
-                                     const int32_t* status_internal, hipStream_t stream);
-// Static value pack: dst[e] = src[ent_src[e]] (b*b elements), zeroing columns >= k
-// of edge blocks; FP8 scales follow the same permutation.
-spmm_status_t pack_values(const KernelPlan& kp, int64_t nnz, const void* src, void* dst, int elem_bytes,
-                          const float* scales_src, float* scales_dst, hipStream_t stream);
-// Dynamic variant: the entry count is read on the device; skipped when *status != 0.
-spmm_status_t pack_values_dyn(const KernelPlan& kp, int64_t max_nnz, const int32_t* nnz_dev, const void* src,
-                              void* dst, int elem_bytes, const float* scales_src, float* scales_dst,
-                              const int32_t* status, hipStream_t stream);
-// Dynamic: *ovf = 1 when some (group, chunk) holds more than wcap blocks, else 0
-// (skipped when *status != 0, ovf left untouched then).
-spmm_status_t chunk_overflow_flag(const KernelPlan& kp, int32_t wcap, const int32_t* status, int32_t* ovf,
-                                  hipStream_t stream);
 // Copy values given in block-CSR order, zeroing the out-of-range part of edge blocks.
 spmm_status_t copy_values_csr(const int32_t* col_idx, int64_t nnz, int32_t b, int32_t k, const void* src, void* dst,
                               int elem_bytes, const float* ssrc, float* sdst, hipStream_t stream);
-// Largest number of blocks in one (group, chunk) of a plan; synchronous.
-spmm_status_t max_chunk_blocks(const KernelPlan& kp, int32_t* scratch_dev, int32_t* out_host, hipStream_t stream);
 
 // ------------------------------------------------------------------ compute
 struct RunArgs {
   KernelPlan plan;
-  const void* W;          // packed (static) or caller's (dynamic) values
+  const void* W;          // values in block-CSR order (or indexed by w_index)
   const float* scales;    // FP8 block scales (same indexing as W), else nullptr
-  bool gather;            // W indexed through ent_src (dynamic) instead of by entry
   const void* X;
   void* Y;
   int64_t ldx, ldy;
@@ -138,19 +109,13 @@ struct RunArgs {
   spmm_dtype_t wt, xt, yt;
   const int32_t* status;  // skip everything when *status != 0 (dynamic), else nullptr
   int64_t nnz;            // entries in W (capacity for dynamic calls)
-  int32_t pipe_ns;        // pipelined kernel: 16-column tiles per workgroup (4 or 8)
-  int32_t pipe_nwv;       // pipelined kernel: 16-byte weight vectors per loading lane (4 or 8)
-  bool fallback;          // run the general kernel even where the pipelined one applies
-  const int32_t* ovf;     // dynamic: device flag, nonzero when a chunk exceeds the pipelined stage
-  int32_t ovf_mode;       // 0: ignore ovf; 1: skip when *ovf != 0; 2: run only when *ovf != 0
-  bool relu = false;      // block-CSR kernels: max(0, y) before the output cast
-  const int32_t* w_index = nullptr;  // block-CSR kernels: values (and scales) of entry q at w_index[q], else q
+  bool relu = false;      // max(0, y) before the output cast
+  const int32_t* w_index = nullptr;  // values (and scales) of entry q at w_index[q], else q
   int32_t num_heavy = 0;             // row-wise kernel: block rows split over a workgroup's four waves
   const uint8_t* heavy_flag = nullptr;  // [mb] nonzero for a split row
   const int32_t* heavy_rows = nullptr;  // [num_heavy]
   int32_t ns = 8;         // row-wise kernel: column tiles of 16 per wave (2, 4 or 8)
 };
-spmm_status_t launch_spmm(const RunArgs& a, hipStream_t stream);
 // Row-wise kernel (16-bit X, b = 16 or 32): W and scales in block-CSR order.
 spmm_status_t launch_spmm_row(const RunArgs& a, const int32_t* row_ptr, const int32_t* col_idx, hipStream_t stream);
 // Row-wise kernel with a software-pipelined block loop, for launches of at
@@ -189,8 +154,6 @@ spmm_status_t launch_sddmm(spmm_dtype_t t, int32_t b, const int32_t* row_ptr, co
                            int64_t lddy, const void* X, int64_t ldx, float* G, hipStream_t stream);
 // Small-block kernel (b = 1, 4, 8, every dtype triple): W and scales in block-CSR order.
 spmm_status_t launch_spmm_small(const RunArgs& a, const int32_t* row_ptr, const int32_t* col_idx, hipStream_t stream);
-// True when (b, x dtype) runs on a block-CSR kernel (row-wise MFMA or small-block).
-bool uses_csr(int32_t b, spmm_dtype_t x);
 
 
 int device_cu_count();

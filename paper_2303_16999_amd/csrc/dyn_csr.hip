@@ -652,8 +652,8 @@ spmm_status_t build_dynamic_csr(const int32_t* nnz_dev, const int32_t* rows, con
   if (mb > 1024 * 64) return fail(SPMM_ERR_UNSUPPORTED, "dynamic CSR builder supports at most 65536 block rows");
   int32_t* row_cnt = pb.scratch;            // [mb]
   int32_t* fill = pb.scratch + mb;          // [mb]
-  int32_t* tmp_col = pb.ent_col;            // [max_nnz] scratch for the row sort
-  int32_t* tmp_src = pb.ent_src;
+  int32_t* tmp_col = pb.tmp_col;            // [max_nnz] scratch for the row sort
+  int32_t* tmp_src = pb.tmp_src;
   hipLaunchKernelGGL(k_dyn_zero, dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>(256, ceil_div(2 * mb, 256)))),
                      dim3(256), 0, s, row_cnt, (int64_t)2 * mb, status);
   const int32_t wgs = dyn_hist_wgs(max_nnz, mb);

@@ -191,7 +191,7 @@ spmm_status_t spmm_group_run(spmm_group_t g, int32_t count, const spmm_plan_t* p
     a.plan.b = p->b;
     a.plan.mb = p->mb;
     a.plan.kb = p->kb;
-    a.W = p->values_csr;
+    a.W = p->values;
     a.scales = nullptr;
     a.X = X[i];
     a.Y = Y[i];

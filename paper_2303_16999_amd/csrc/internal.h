@@ -12,13 +12,10 @@ struct spmm_plan_s {
   spmm_dtype_t w = SPMM_F32, x = SPMM_F32, y = SPMM_F32;
   spmm::Geometry geo{};
   spmm::PlanBuffers pb;
-  void* values = nullptr;      // entry (cell) order, for the pipelined and general kernels
-  float* scales = nullptr;
-  void* values_csr = nullptr;  // block-CSR order, for the block-CSR kernels
-  float* scales_csr = nullptr;
+  void* values = nullptr;      // block-CSR order, edge blocks zeroed past k
+  float* scales = nullptr;     // FP8 block scales, CSR order
   bool has_values = false;
   int device = 0;
-  int32_t max_chunk = 0;       // most blocks in one (group, chunk)
   int32_t variant_opt = 0;     // fixed tile variant from the options, 0 = choose
   int8_t tuned[32] = {};       // autotuned variant per n class, 0 = none
   int32_t num_heavy = 0;       // block rows the row-wise kernel splits over four waves

@@ -61,102 +61,31 @@ static bool valid_block(int32_t b) { return b == 1 || b == 4 || b == 8 || b == 1
 // Static plans also take b = 64 (4 x 4 MFMA tiles of 16, 16-bit X).
 static bool valid_static_block(int32_t b) { return valid_block(b) || b == 64; }
 
-bool uses_pipe(int32_t b, spmm_dtype_t x) { return b >= 16 && (x == SPMM_F16 || x == SPMM_BF16); }
-bool uses_csr(int32_t b, spmm_dtype_t x) { return b < 16 || uses_pipe(b, x) || (x == SPMM_F32 && b <= 32); }
-
 Geometry choose_geometry(int64_t m, int64_t k, int32_t b, int64_t nnz_hint, int64_t n_hint,
                          const spmm_plan_opts* opts, int num_cus, spmm_dtype_t x) {
+  (void)k;
+  (void)nnz_hint;
+  (void)x;
   Geometry g{};
-  const int64_t mb = ceil_div(m, b), kb = ceil_div(k, b);
+  const int64_t mb = ceil_div(m, b);
   if (n_hint <= 0) n_hint = 1024;
-  int32_t gr = 0, cw = 0;
-  if (uses_pipe(b, x)) {
-    // pipelined kernel: 64 k rows per chunk; the row group is the largest that
-    // keeps a chunk's expected blocks within half the staged capacity and
-    // still gives every CU two work units
-    cw = 64 / b;
-    const double d = std::max(1e-9, (double)nnz_hint / ((double)mb * (double)kb));
-    const double cap = 16384.0 / (2.0 * b * b);  // blocks of the larger weight stage
-    const int32_t cands16[3] = {32, 16, 8}, cands32[2] = {16, 8};
-    const int32_t* cands = b == 16 ? cands16 : cands32;
-    const int nc = b == 16 ? 3 : 2;
-    for (int i = 0; i < nc && !gr; ++i) {
-      const int64_t units = ceil_div(mb, cands[i]) * ceil_div(n_hint, 128);
-      if (cands[i] * cw * d <= 0.5 * cap && units >= 2 * (int64_t)num_cus) gr = cands[i];
-    }
-    if (!gr) {
-      // prefer parallelism: the smallest group that satisfies the capacity bound
-      gr = cands[nc - 1];
-      for (int i = nc - 1; i >= 0; --i)
-        if (cands[i] * cw * d <= 0.5 * cap) { gr = cands[i]; break; }
-    }
-  } else {
-    int32_t big = 0, small = 0, ntile = 128;
-    if (b == 16) { big = 32; small = 8; cw = 8; }
-    else if (b == 32) { big = 16; small = 4; cw = 4; }
-    else { big = 64; small = 16; cw = 64 / b; ntile = 64; }  // small-block path
-    gr = big;
-    const int64_t units_big = ceil_div(mb, big) * ceil_div(n_hint, ntile);
-    if (units_big < 2 * (int64_t)num_cus) gr = small;
-  }
+  // row groups of the plan: large where groups x n-tiles still gives every CU
+  // two units, else small
+  int32_t big = 0, small = 0, ntile = 128;
+  if (b >= 16) { big = b == 16 ? 32 : (b == 32 ? 16 : 8); small = b == 16 ? 8 : (b == 32 ? 4 : 2); }
+  else { big = 64; small = 16; ntile = 64; }
+  int32_t gr = big;
+  if (ceil_div(mb, big) * ceil_div(n_hint, ntile) < 2 * (int64_t)num_cus) gr = small;
   if (const char* e = getenv("SPMM_GROUP_ROWS")) {  // tuning override
     const int v = atoi(e);
     if (v > 0) gr = v;
   }
   if (opts && opts->group_rows > 0) gr = opts->group_rows;
   g.group_rows = gr;
-  g.chunk_cols = cw;
   g.num_groups = (int32_t)ceil_div(mb, gr);
-  g.num_chunks = (int32_t)ceil_div(kb, cw);
   g.num_panels = (opts && opts->num_panels > 0) ? std::min<int32_t>(opts->num_panels, g.num_groups) : g.num_groups;
   if (g.num_panels < 1) g.num_panels = 1;
-  g.num_cells = (int64_t)g.num_groups * g.num_chunks * g.group_rows;
   return g;
-}
-
-static bool geometry_supported(int32_t b, int32_t gr, spmm_dtype_t x, int32_t num_chunks) {
-  if (uses_pipe(b, x)) {
-    if (num_chunks > 1024) return false;
-    if (b == 16) return gr == 32 || gr == 16 || gr == 8;
-    return gr == 16 || gr == 8;
-  }
-  if (b == 16) return gr == 32 || gr == 8;
-  if (b == 32) return gr == 16 || gr == 4;
-  return gr == 64 || gr == 16;
-}
-
-spmm_status_t launch_spmm_mfma(const RunArgs& a, hipStream_t s);
-spmm_status_t launch_pipe_f16(const RunArgs& a, hipStream_t s);
-spmm_status_t launch_pipe_bf16(const RunArgs& a, hipStream_t s);
-spmm_status_t launch_pipe_fp8f16(const RunArgs& a, hipStream_t s);
-spmm_status_t launch_pipe_fp8bf16(const RunArgs& a, hipStream_t s);
-
-// blocks the pipelined kernel stages per chunk: nwv 16-byte vectors per lane of a 128-lane pair
-static int32_t pipe_wcap(int32_t b, spmm_dtype_t w, int32_t nwv) {
-  return nwv * 128 * 16 / (b * b * (w == SPMM_FP8_E4M3 ? 1 : 2));
-}
-
-spmm_status_t launch_spmm(const RunArgs& a0, hipStream_t s) {
-  if (a0.plan.b < 16) return fail(SPMM_ERR_UNSUPPORTED, "block sizes below 16 run on the block-CSR kernel only");
-  if (!uses_pipe(a0.plan.b, a0.xt) || a0.fallback) return launch_spmm_mfma(a0, s);
-  RunArgs a = a0;
-  const int64_t units8 = ceil_div(a.n, 128) * (int64_t)a.plan.num_panels;
-  a.pipe_ns = units8 >= device_cu_count() ? 8 : 4;
-  if (const char* e = getenv("SPMM_PIPE_NS")) {  // tuning override: column tile 4 or 8 (x16 columns)
-    const int v = atoi(e);
-    if (v == 4 || v == 8) a.pipe_ns = v;
-  }
-  if (a.plan.group_rows == 8) a.pipe_nwv = 8;  // the one-row-per-wave variants stage the larger set
-  if ((int64_t)a.plan.k * a.ldx * 2 >= (int64_t)INT32_MAX || a.nnz * (int64_t)a.plan.b * a.plan.b * 2 >= (int64_t)INT32_MAX)
-    return fail(SPMM_ERR_UNSUPPORTED, "X or W larger than 2 GiB is not supported by the pipelined kernel");
-  spmm_status_t st;
-  if (a.wt == SPMM_FP8_E4M3) st = a.xt == SPMM_F16 ? launch_pipe_fp8f16(a, s) : launch_pipe_fp8bf16(a, s);
-  else st = a.xt == SPMM_F16 ? launch_pipe_f16(a, s) : launch_pipe_bf16(a, s);
-  if (st != SPMM_OK || a.ovf_mode != 1) return st;
-  // dynamic calls: the general kernel runs only if a chunk overflowed the stage
-  RunArgs f = a0;
-  f.ovf_mode = 2;
-  return launch_spmm_mfma(f, s);
 }
 
 // Column tiles of 16 per wave for the row-wise kernel: the widest tile that
@@ -172,22 +101,9 @@ static bool use_one_wg_builder() {
   return !(e && std::string(e) == "multi");
 }
 
-// Kernel choice for 16-bit X: the row-wise kernel unless SPMM_KERNEL=pipe.
-static bool use_row_kernel() {
-  const char* e = getenv("SPMM_KERNEL");
-  return !(e && std::string(e) == "pipe");
-}
-
-// FP32 plans with b = 16/32 run on the row-wise FP32 kernel unless
-// SPMM_KERNEL=general (for comparisons) asks for the LDS-staged kernel.
-static bool use_row_kernel_f32() {
-  const char* e = getenv("SPMM_KERNEL");
-  return !(e && (std::string(e) == "general" || std::string(e) == "pipe"));
-}
-
 static void free_plan_buffers(PlanBuffers& pb) {
-  int32_t* ptrs[] = {pb.cell_ptr, pb.ent_col, pb.ent_src, pb.panel_ptr, pb.row_ptr, pb.col_idx, pb.csr_src, pb.scratch,
-                     pb.hist};
+  int32_t* ptrs[] = {pb.panel_ptr, pb.row_ptr, pb.col_idx, pb.order, pb.csr_src, pb.tmp_col, pb.tmp_src,
+                     pb.scratch, pb.hist};
   for (int32_t* p : ptrs)
     if (p) (void)hipFree(p);
   if (pb.cost_prefix) (void)hipFree(pb.cost_prefix);
@@ -205,15 +121,15 @@ static spmm_status_t dev_alloc(T** p, int64_t count) {
 
 static spmm_status_t alloc_plan_buffers(PlanBuffers& pb, const Geometry& geo, int32_t mb, int64_t nnz, bool dynamic) {
   spmm_status_t st;
-  const int64_t scan_parts = ceil_div(std::max<int64_t>(std::max<int64_t>(mb, geo.num_cells), 1), 1024) + 16;
-  pb.scratch_ints = (dynamic ? geo.num_cells : 0) + mb + scan_parts + 16;
-  if ((st = dev_alloc(&pb.cell_ptr, geo.num_cells + 1)) != SPMM_OK) return st;
-  if ((st = dev_alloc(&pb.ent_col, nnz)) != SPMM_OK) return st;
-  if ((st = dev_alloc(&pb.ent_src, nnz)) != SPMM_OK) return st;
+  const int64_t scan_parts = ceil_div(std::max<int64_t>(mb, 1), 1024) + 16;
+  pb.scratch_ints = (dynamic ? 2 * (int64_t)mb : (int64_t)mb) + scan_parts + 16;
   if ((st = dev_alloc(&pb.panel_ptr, (int64_t)geo.num_panels + 1)) != SPMM_OK) return st;
   if ((st = dev_alloc(&pb.row_ptr, (int64_t)mb + 1)) != SPMM_OK) return st;
   if ((st = dev_alloc(&pb.col_idx, nnz)) != SPMM_OK) return st;
+  if (!dynamic && (st = dev_alloc(&pb.order, nnz)) != SPMM_OK) return st;
   if (dynamic && (st = dev_alloc(&pb.csr_src, nnz)) != SPMM_OK) return st;
+  if (dynamic && (st = dev_alloc(&pb.tmp_col, nnz)) != SPMM_OK) return st;
+  if (dynamic && (st = dev_alloc(&pb.tmp_src, nnz)) != SPMM_OK) return st;
   if ((st = dev_alloc(&pb.scratch, pb.scratch_ints)) != SPMM_OK) return st;
   if ((st = dev_alloc(&pb.cost_prefix, (int64_t)geo.num_groups + 1)) != SPMM_OK) return st;
   if (dynamic && (pb.hist_wgs = dyn_hist_wgs(nnz, mb)) > 0 &&
@@ -232,13 +148,9 @@ static KernelPlan kernel_plan(int64_t m, int64_t k, int32_t b, int32_t mb, int32
   kp.kb = kb;
   kp.group_rows = geo.group_rows;
   kp.num_groups = geo.num_groups;
-  kp.chunk_cols = geo.chunk_cols;
-  kp.num_chunks = geo.num_chunks;
   kp.num_panels = geo.num_panels;
-  kp.cell_ptr = pb.cell_ptr;
-  kp.ent_col = pb.ent_col;
-  kp.ent_src = pb.ent_src;
   kp.panel_ptr = pb.panel_ptr;
+  kp.order = pb.order;
   return kp;
 }
 
@@ -267,7 +179,7 @@ int n_class(int64_t n) {
 }
 
 bool plan_uses_row_kernel(const spmm_plan_s* p) {
-  return uses_pipe(p->b, p->x) && use_row_kernel();
+  return p->b >= 16 && (p->x == SPMM_F16 || p->x == SPMM_BF16);
 }
 
 // Process-wide autotuner table: (b, w, x, y, density class, n class) -> variant.
@@ -305,7 +217,6 @@ spmm_status_t run_plan(const spmm_plan_s* p, int64_t n, const void* X, int64_t l
   a.plan = kernel_plan(p->m, p->k, p->b, p->mb, p->kb, p->geo, p->pb);
   a.W = p->values;
   a.scales = p->scales;
-  a.gather = false;
   a.X = X;
   a.Y = Y;
   a.ldx = ldx;
@@ -316,21 +227,12 @@ spmm_status_t run_plan(const spmm_plan_s* p, int64_t n, const void* X, int64_t l
   a.yt = p->y;
   a.status = nullptr;
   a.nnz = p->nnzb;
-  a.pipe_ns = 8;
-  a.pipe_nwv = p->max_chunk <= pipe_wcap(p->b, p->w, 4) ? 4 : 8;
-  a.fallback = p->max_chunk > pipe_wcap(p->b, p->w, 8);
-  a.ovf = nullptr;
-  a.ovf_mode = 0;
   a.relu = relu;
   if (p->b < 16) {
-    a.W = p->values_csr;
-    a.scales = p->scales_csr;
     a.ns = variant;  // 0: the kernel's rule on n
     return launch_spmm_small(a, p->pb.row_ptr, p->pb.col_idx, stream);
   }
   if (plan_uses_row_kernel(p)) {
-    a.W = p->values_csr;
-    a.scales = p->scales_csr;
     a.ns = variant ? variant : default_ns(n);
     a.num_heavy = p->num_heavy;
     a.heavy_flag = p->heavy_flag;
@@ -339,12 +241,7 @@ spmm_status_t run_plan(const spmm_plan_s* p, int64_t n, const void* X, int64_t l
       return launch_spmm_row_pp(a, p->pb.row_ptr, p->pb.col_idx, stream);
     return launch_spmm_row(a, p->pb.row_ptr, p->pb.col_idx, stream);
   }
-  if (p->x == SPMM_F32 && p->b >= 16 && use_row_kernel_f32()) {
-    a.W = p->values_csr;
-    return launch_spmm_row_f32(a, p->pb.row_ptr, p->pb.col_idx, stream);
-  }
-  if (relu) return fail(SPMM_ERR_UNSUPPORTED, "fused ReLU needs a block-CSR kernel");
-  return launch_spmm(a, stream);
+  return launch_spmm_row_f32(a, p->pb.row_ptr, p->pb.col_idx, stream);
 }
 
 // Block rows longer than max(64, 4 x the mean row) are split over the four
@@ -406,12 +303,10 @@ struct spmm_dyn_s {
   PlanBuffers pb;
   int32_t* status = nullptr;   // internal status word (device)
   int32_t* nnz_last = nullptr; // device copy of the last call's nnz
-  int32_t* ovf = nullptr;      // device flag: a chunk of the last call exceeds the pipelined stage
-  void* packed = nullptr;      // values in entry order, sized for max_nnzb
+  void* packed = nullptr;      // values gathered into block-CSR order, sized for max_nnzb
   float* packed_scales = nullptr;
   int device = 0;
   bool ran = false;
-  bool csr_path = false;       // the last call built block-CSR directly (row-wise kernel)
 };
 
 extern "C" {
@@ -445,10 +340,6 @@ spmm_status_t spmm_plan_static(int64_t m, int64_t k, int32_t b, const uint8_t* b
   p->w = w; p->x = x; p->y = y;
   p->variant_opt = opts ? opts->variant : 0;
   p->geo = choose_geometry(m, k, b, nnzb, opts ? opts->n_hint : 0, opts, device_cu_count(), x);
-  if (!geometry_supported(b, p->geo.group_rows, x, p->geo.num_chunks)) {
-    delete p;
-    return fail(SPMM_ERR_UNSUPPORTED, "group_rows not available for this block size");
-  }
   spmm_status_t st = SPMM_OK;
   uint8_t* mask_dev = nullptr;
   hipStream_t s = nullptr;
@@ -456,34 +347,24 @@ spmm_status_t spmm_plan_static(int64_t m, int64_t k, int32_t b, const uint8_t* b
   if (e != hipSuccess) st = fail_hip(e, "hipGetDevice");
   if (st == SPMM_OK) st = alloc_plan_buffers(p->pb, p->geo, (int32_t)mb, nnzb, false);
   if (st == SPMM_OK) st = dev_alloc(&mask_dev, mb * kb);
-  if (st == SPMM_OK) {
+  if (st == SPMM_OK) {  // plan-owned values in block-CSR order
     const int64_t vbytes = nnzb * (int64_t)b * b * dtype_bytes(w);
     e = hipMalloc(&p->values, (size_t)std::max<int64_t>(vbytes, 16));
     if (e != hipSuccess) st = fail_hip(e, "hipMalloc values");
   }
   if (st == SPMM_OK && w == SPMM_FP8_E4M3) st = dev_alloc(&p->scales, nnzb);
-  if (st == SPMM_OK) {  // block-CSR copy of the values (CSR kernels, transposed plans)
-    const int64_t vbytes = nnzb * (int64_t)b * b * dtype_bytes(w);
-    e = hipMalloc(&p->values_csr, (size_t)std::max<int64_t>(vbytes, 16));
-    if (e != hipSuccess) st = fail_hip(e, "hipMalloc values");
-    if (st == SPMM_OK && w == SPMM_FP8_E4M3) st = dev_alloc(&p->scales_csr, nnzb);
-  }
   if (st == SPMM_OK && (e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking)) != hipSuccess)
     st = fail_hip(e, "hipStreamCreate");
   if (st == SPMM_OK && (e = hipMemcpyAsync(mask_dev, block_mask_host, (size_t)(mb * kb), hipMemcpyHostToDevice, s)) != hipSuccess)
     st = fail_hip(e, "mask upload");
   if (st == SPMM_OK) st = build_static_plan(mask_dev, (int32_t)mb, (int32_t)kb, p->geo, p->pb, s);
   if (st == SPMM_OK && (e = hipStreamSynchronize(s)) != hipSuccess) st = fail_hip(e, "plan build");
-  if (st == SPMM_OK) {
-    KernelPlan kp = kernel_plan(m, k, b, (int32_t)mb, (int32_t)kb, p->geo, p->pb);
-    st = max_chunk_blocks(kp, p->pb.scratch, &p->max_chunk, s);
-  }
   if (st == SPMM_OK && b >= 16) {
     // host copy of the row pointers: long rows to split, SDDMM tasks
     std::vector<int32_t> rp((size_t)mb + 1);
     e = hipMemcpy(rp.data(), p->pb.row_ptr, sizeof(int32_t) * rp.size(), hipMemcpyDeviceToHost);
     if (e != hipSuccess) st = fail_hip(e, "row pointer download");
-    if (st == SPMM_OK && uses_pipe(b, x) && b == 16) st = classify_heavy_rows(p, rp);
+    if (st == SPMM_OK && b == 16 && x != SPMM_F32) st = classify_heavy_rows(p, rp);
     if (st == SPMM_OK && b <= 32) st = build_sddmm_tasks(p, rp);
   }
   if (s) (void)hipStreamDestroy(s);
@@ -492,8 +373,6 @@ spmm_status_t spmm_plan_static(int64_t m, int64_t k, int32_t b, const uint8_t* b
     free_plan_buffers(p->pb);
     if (p->values) (void)hipFree(p->values);
     if (p->scales) (void)hipFree(p->scales);
-    if (p->values_csr) (void)hipFree(p->values_csr);
-    if (p->scales_csr) (void)hipFree(p->scales_csr);
     if (p->heavy_flag) (void)hipFree(p->heavy_flag);
     if (p->heavy_rows) (void)hipFree(p->heavy_rows);
     if (p->sddmm_tasks) (void)hipFree(p->sddmm_tasks);
@@ -513,14 +392,9 @@ spmm_status_t spmm_plan_set_values(spmm_plan_t p, const void* values_dev, const 
   if (p->w != SPMM_FP8_E4M3 && scales_dev) return fail(SPMM_ERR_INVALID_ARG, "block scales are only for FP8 weights");
   spmm_status_t st = check_device(p->device);
   if (st != SPMM_OK) return st;
-  KernelPlan kp = kernel_plan(p->m, p->k, p->b, p->mb, p->kb, p->geo, p->pb);
-  st = pack_values(kp, p->nnzb, values_dev, p->values, dtype_bytes(p->w), scales_dev, p->scales, (hipStream_t)stream);
+  st = copy_values_csr(p->pb.col_idx, p->nnzb, p->b, (int32_t)p->k, values_dev, p->values, dtype_bytes(p->w),
+                       scales_dev, p->scales, (hipStream_t)stream);
   if (st != SPMM_OK) return st;
-  if (p->values_csr) {
-    st = copy_values_csr(p->pb.col_idx, p->nnzb, p->b, (int32_t)p->k, values_dev, p->values_csr, dtype_bytes(p->w),
-                         scales_dev, p->scales_csr, (hipStream_t)stream);
-    if (st != SPMM_OK) return st;
-  }
   p->has_values = true;
   return SPMM_OK;
 }
@@ -624,16 +498,19 @@ spmm_status_t spmm_plan_info(spmm_plan_t p, int64_t* nnzb, int32_t* group_rows, 
   return SPMM_OK;
 }
 
-spmm_status_t spmm_plan_export(spmm_plan_t p, int32_t* row_ptr, int32_t* col_idx, int32_t* panel_ptr) {
+spmm_status_t spmm_plan_export(spmm_plan_t p, int32_t* row_ptr, int32_t* col_idx, int32_t* panel_ptr,
+                               int32_t* order) {
   clear_error();
   if (!p) return fail(SPMM_ERR_INVALID_ARG, "plan is NULL");
   spmm_status_t st = check_device(p->device);
   if (st != SPMM_OK) return st;
+  SPMM_HIP(hipDeviceSynchronize());
   if (row_ptr) SPMM_HIP(hipMemcpy(row_ptr, p->pb.row_ptr, sizeof(int32_t) * (p->mb + 1), hipMemcpyDeviceToHost));
   if (col_idx && p->nnzb)
     SPMM_HIP(hipMemcpy(col_idx, p->pb.col_idx, sizeof(int32_t) * p->nnzb, hipMemcpyDeviceToHost));
   if (panel_ptr)
     SPMM_HIP(hipMemcpy(panel_ptr, p->pb.panel_ptr, sizeof(int32_t) * (p->geo.num_panels + 1), hipMemcpyDeviceToHost));
+  if (order && p->nnzb) SPMM_HIP(hipMemcpy(order, p->pb.order, sizeof(int32_t) * p->nnzb, hipMemcpyDeviceToHost));
   return SPMM_OK;
 }
 
@@ -643,8 +520,6 @@ spmm_status_t spmm_plan_destroy(spmm_plan_t p) {
   free_plan_buffers(p->pb);
   if (p->values) (void)hipFree(p->values);
   if (p->scales) (void)hipFree(p->scales);
-  if (p->values_csr) (void)hipFree(p->values_csr);
-  if (p->scales_csr) (void)hipFree(p->scales_csr);
   if (p->heavy_flag) (void)hipFree(p->heavy_flag);
   if (p->heavy_rows) (void)hipFree(p->heavy_rows);
   if (p->sddmm_tasks) (void)hipFree(p->sddmm_tasks);
@@ -674,21 +549,12 @@ spmm_status_t spmm_dynamic_create(int64_t m, int64_t k, int32_t b, int64_t max_n
   h->max_nnzb = max_nnzb;
   h->w = w; h->x = x; h->y = y;
   h->geo = choose_geometry(m, k, b, max_nnzb, opts ? opts->n_hint : 0, opts, device_cu_count(), x);
-  if (!geometry_supported(b, h->geo.group_rows, x, h->geo.num_chunks)) {
-    delete h;
-    return fail(SPMM_ERR_UNSUPPORTED, "group_rows not available for this block size");
-  }
-  if (h->geo.num_cells > (int64_t)INT32_MAX / 2) {
-    delete h;
-    return fail(SPMM_ERR_UNSUPPORTED, "block grid too large for the dynamic bucket table");
-  }
   spmm_status_t st = SPMM_OK;
   hipError_t e = hipGetDevice(&h->device);
   if (e != hipSuccess) st = fail_hip(e, "hipGetDevice");
   if (st == SPMM_OK) st = alloc_plan_buffers(h->pb, h->geo, h->mb, max_nnzb, true);
   if (st == SPMM_OK) st = dev_alloc(&h->status, 2);
   if (st == SPMM_OK) st = dev_alloc(&h->nnz_last, 2);
-  if (st == SPMM_OK) st = dev_alloc(&h->ovf, 2);
   if (st == SPMM_OK) {
     const int64_t vbytes = max_nnzb * (int64_t)b * b * dtype_bytes(w);
     e = hipMalloc(&h->packed, (size_t)std::max<int64_t>(vbytes, 16));
@@ -702,7 +568,6 @@ spmm_status_t spmm_dynamic_create(int64_t m, int64_t k, int32_t b, int64_t max_n
     free_plan_buffers(h->pb);
     if (h->status) (void)hipFree(h->status);
     if (h->nnz_last) (void)hipFree(h->nnz_last);
-    if (h->ovf) (void)hipFree(h->ovf);
     if (h->packed) (void)hipFree(h->packed);
     if (h->packed_scales) (void)hipFree(h->packed_scales);
     delete h;
@@ -732,64 +597,28 @@ spmm_status_t spmm_run_dynamic(spmm_dyn_t h, const int32_t* nnzb_dev, const int3
   if (((uintptr_t)values_dev) % 16 != 0) return fail(SPMM_ERR_INVALID_ARG, "values are not 16-byte aligned");
   if ((st = check_device(h->device)) != SPMM_OK) return st;
   hipStream_t s = (hipStream_t)stream;
-  if (uses_csr(h->b, h->x)) {
-    // re-bucket into block-CSR and run the block-CSR kernel (the same kernel
-    // and order as a static plan of the same pattern). Small capacities encode
-    // in one workgroup and leave the values in place (read through csr_src);
-    // edge blocks that cross k need the copying path, which zeroes their tail.
-    const bool one_wg = h->k % h->b == 0 && use_one_wg_builder() &&
-                        dynamic_small_fits((int32_t)h->max_nnzb, h->mb, h->kb, h->geo.num_groups);
-    if (one_wg) {
-      st = build_dynamic_csr_small(nnzb_dev, rows, cols, (int32_t)h->max_nnzb, h->mb, h->kb, h->geo, h->pb,
-                                   h->status, status_dev, h->nnz_last, s);
-      if (st != SPMM_OK) return st;
-    } else {
-      st = build_dynamic_csr(nnzb_dev, rows, cols, (int32_t)h->max_nnzb, h->mb, h->kb, h->b, (int32_t)h->k, h->geo,
-                             h->pb, values_dev, h->packed, dtype_bytes(h->w), scales_dev, h->packed_scales, h->status,
-                             status_dev, h->nnz_last, s);
-      if (st != SPMM_OK) return st;
-    }
-    h->ran = true;
-    h->csr_path = true;
-    if (n == 0) return SPMM_OK;
-    RunArgs a{};
-    a.plan = kernel_plan(h->m, h->k, h->b, h->mb, h->kb, h->geo, h->pb);
-    a.W = one_wg ? values_dev : h->packed;
-    a.scales = one_wg ? scales_dev : h->packed_scales;
-    a.w_index = one_wg ? h->pb.csr_src : nullptr;
-    a.X = X;
-    a.Y = Y;
-    a.ldx = ldx;
-    a.ldy = ldy;
-    a.n = (int32_t)n;
-    a.wt = h->w;
-    a.xt = h->x;
-    a.yt = h->y;
-    a.status = h->status;
-    a.nnz = h->max_nnzb;
-    a.ns = h->b < 16 ? 0 : default_ns(n);
-    if (h->b < 16) return launch_spmm_small(a, h->pb.row_ptr, h->pb.col_idx, s);
-    if (h->x == SPMM_F32) return launch_spmm_row_f32(a, h->pb.row_ptr, h->pb.col_idx, s);
-    if (h->w == h->x && row_pp_preferred(h->b, h->mb, n, a.ns, h->max_nnzb, device_cu_count()))
-      return launch_spmm_row_pp(a, h->pb.row_ptr, h->pb.col_idx, s);
-    return launch_spmm_row(a, h->pb.row_ptr, h->pb.col_idx, s);
+  // re-bucket into block-CSR and run the block-CSR kernel (the same kernel and
+  // order as a static plan of the same pattern). Small capacities encode in
+  // one workgroup and leave the values in place (read through csr_src); edge
+  // blocks that cross k need the copying path, which zeroes their tail.
+  const bool one_wg = h->k % h->b == 0 && use_one_wg_builder() &&
+                      dynamic_small_fits((int32_t)h->max_nnzb, h->mb, h->kb, h->geo.num_groups);
+  if (one_wg) {
+    st = build_dynamic_csr_small(nnzb_dev, rows, cols, (int32_t)h->max_nnzb, h->mb, h->kb, h->geo, h->pb, h->status,
+                                 status_dev, h->nnz_last, s);
+  } else {
+    st = build_dynamic_csr(nnzb_dev, rows, cols, (int32_t)h->max_nnzb, h->mb, h->kb, h->b, (int32_t)h->k, h->geo,
+                           h->pb, values_dev, h->packed, dtype_bytes(h->w), scales_dev, h->packed_scales, h->status,
+                           status_dev, h->nnz_last, s);
   }
-  st = build_dynamic_plan(nnzb_dev, rows, cols, (int32_t)h->max_nnzb, h->mb, h->kb, h->geo, h->pb, h->status,
-                          status_dev, s);
   if (st != SPMM_OK) return st;
-  SPMM_HIP(hipMemcpyAsync(h->nnz_last, nnzb_dev, sizeof(int32_t), hipMemcpyDeviceToDevice, s));
   h->ran = true;
-  h->csr_path = false;
   if (n == 0) return SPMM_OK;
   RunArgs a{};
   a.plan = kernel_plan(h->m, h->k, h->b, h->mb, h->kb, h->geo, h->pb);
-  // values into the plan's entry order (the same layout a static plan packs once)
-  st = pack_values_dyn(a.plan, h->max_nnzb, nnzb_dev, values_dev, h->packed, dtype_bytes(h->w), scales_dev,
-                       h->packed_scales, h->status, s);
-  if (st != SPMM_OK) return st;
-  a.W = h->packed;
-  a.scales = h->packed_scales;
-  a.gather = false;
+  a.W = one_wg ? values_dev : h->packed;
+  a.scales = one_wg ? scales_dev : h->packed_scales;
+  a.w_index = one_wg ? h->pb.csr_src : nullptr;
   a.X = X;
   a.Y = Y;
   a.ldx = ldx;
@@ -800,8 +629,12 @@ spmm_status_t spmm_run_dynamic(spmm_dyn_t h, const int32_t* nnzb_dev, const int3
   a.yt = h->y;
   a.status = h->status;
   a.nnz = h->max_nnzb;
-  a.fallback = true;
-  return launch_spmm(a, s);
+  a.ns = h->b < 16 ? 0 : default_ns(n);
+  if (h->b < 16) return launch_spmm_small(a, h->pb.row_ptr, h->pb.col_idx, s);
+  if (h->x == SPMM_F32) return launch_spmm_row_f32(a, h->pb.row_ptr, h->pb.col_idx, s);
+  if (h->w == h->x && row_pp_preferred(h->b, h->mb, n, a.ns, h->max_nnzb, device_cu_count()))
+    return launch_spmm_row_pp(a, h->pb.row_ptr, h->pb.col_idx, s);
+  return launch_spmm_row(a, h->pb.row_ptr, h->pb.col_idx, s);
 }
 
 spmm_status_t spmm_dynamic_export(spmm_dyn_t h, int32_t* row_ptr, int32_t* col_idx, int32_t* src, int32_t* panel_ptr,
@@ -816,11 +649,6 @@ spmm_status_t spmm_dynamic_export(spmm_dyn_t h, int32_t* row_ptr, int32_t* col_i
   SPMM_HIP(hipMemcpy(&status, h->status, sizeof(int32_t), hipMemcpyDeviceToHost));
   if (status != 0) return fail((spmm_status_t)status, "the last dynamic call failed on the device");
   SPMM_HIP(hipMemcpy(&nnz, h->nnz_last, sizeof(int32_t), hipMemcpyDeviceToHost));
-  if (!h->csr_path) {
-    st = dynamic_csr_from_cells(h->mb, h->geo, h->pb, h->status, nullptr);
-    if (st != SPMM_OK) return st;
-  }
-  SPMM_HIP(hipDeviceSynchronize());
   if (nnzb) *nnzb = nnz;
   if (row_ptr) SPMM_HIP(hipMemcpy(row_ptr, h->pb.row_ptr, sizeof(int32_t) * (h->mb + 1), hipMemcpyDeviceToHost));
   if (col_idx && nnz) SPMM_HIP(hipMemcpy(col_idx, h->pb.col_idx, sizeof(int32_t) * nnz, hipMemcpyDeviceToHost));
@@ -845,7 +673,6 @@ spmm_status_t spmm_dynamic_destroy(spmm_dyn_t h) {
   free_plan_buffers(h->pb);
   if (h->status) (void)hipFree(h->status);
   if (h->nnz_last) (void)hipFree(h->nnz_last);
-  if (h->ovf) (void)hipFree(h->ovf);
   if (h->packed) (void)hipFree(h->packed);
   if (h->packed_scales) (void)hipFree(h->packed_scales);
   delete h;

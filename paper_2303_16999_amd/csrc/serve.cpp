@@ -138,7 +138,8 @@ struct spmm_srv_s {
   Pool* pool = nullptr;
   uint8_t* pool_dev = nullptr;
   hipStream_t stream = nullptr;       // the layers' kernels
-  hipStream_t copy_stream = nullptr;  // request inputs and outputs over PCIe, overlapping the kernels
+  hipStream_t up_stream = nullptr;    // request inputs over PCIe, overlapping earlier steps' kernels
+  hipStream_t down_stream = nullptr;  // request outputs over PCIe, after their step's kernels
   hipEvent_t up_ev = nullptr;         // a step's uploads done (the kernels wait for it)
   hipEvent_t done_ev = nullptr;       // a step's kernels done (the downloads wait for it)
   spmm_group_t group = nullptr;
@@ -195,20 +196,23 @@ static std::vector<Request> admit_locked(spmm_srv_s* s, int limit) {
   return out;
 }
 
-// Host <-> device copies of a request's input and output, on the copy stream:
-// one contiguous copy when the host layout equals the device layout, else a
-// strided one. A step's uploads are fenced by up_ev before its kernels, its
-// downloads wait for done_ev after them, and the step's completion event is
-// recorded on the copy stream, so a request's memory returns to the pool only
-// once its output has left the device.
+// Host <-> device copies of a request's input and output: one contiguous copy
+// when the host layout equals the device layout, else a strided one. Uploads
+// run on a stream of their own that waits for nothing, so they overlap the
+// kernels of the steps before; a step's kernels wait for its uploads (up_ev).
+// Downloads run on a second stream after the step's kernels (done_ev), and the
+// step's completion event is recorded there, so a request's memory returns to
+// the pool only once its output has left the device. Memory that an upload
+// writes was released by an earlier completion event, which follows every
+// kernel of its step and of the steps before it.
 static spmm_status_t upload_input(spmm_srv_s* s, const Request& r) {
   if (s->opts.simulate) return SPMM_OK;
   if (r.ld_host == r.ld)
     SPMM_HIP(hipMemcpyAsync(buffer(s, r, 0), r.x_host, (size_t)(s->dims[0] * r.ld * s->elem), hipMemcpyHostToDevice,
-                            s->copy_stream));
+                            s->up_stream));
   else
     SPMM_HIP(hipMemcpy2DAsync(buffer(s, r, 0), (size_t)(r.ld * s->elem), r.x_host, (size_t)(r.ld_host * s->elem),
-                              (size_t)(r.n * s->elem), (size_t)s->dims[0], hipMemcpyHostToDevice, s->copy_stream));
+                              (size_t)(r.n * s->elem), (size_t)s->dims[0], hipMemcpyHostToDevice, s->up_stream));
   return SPMM_OK;
 }
 
@@ -216,11 +220,11 @@ static spmm_status_t download_output(spmm_srv_s* s, const Request& r) {
   if (s->opts.simulate) return SPMM_OK;
   if (r.ld_host == r.ld)
     SPMM_HIP(hipMemcpyAsync(r.y_host, buffer(s, r, s->L % 2), (size_t)(s->dims[s->L] * r.ld * s->elem),
-                            hipMemcpyDeviceToHost, s->copy_stream));
+                            hipMemcpyDeviceToHost, s->down_stream));
   else
     SPMM_HIP(hipMemcpy2DAsync(r.y_host, (size_t)(r.ld_host * s->elem), buffer(s, r, s->L % 2),
                               (size_t)(r.ld * s->elem), (size_t)(r.n * s->elem), (size_t)s->dims[s->L],
-                              hipMemcpyDeviceToHost, s->copy_stream));
+                              hipMemcpyDeviceToHost, s->down_stream));
   return SPMM_OK;
 }
 
@@ -283,7 +287,7 @@ static spmm_status_t do_step(spmm_srv_s* s, int32_t* remaining) {
   for (const Request& r : admitted)
     if (st == SPMM_OK) st = upload_input(s, r);
   if (st == SPMM_OK && !admitted.empty() && !s->opts.simulate) {
-    hipError_t e = hipEventRecord(s->up_ev, s->copy_stream);
+    hipError_t e = hipEventRecord(s->up_ev, s->up_stream);
     if (e == hipSuccess) e = hipStreamWaitEvent(s->stream, s->up_ev, 0);
     if (e != hipSuccess) st = fail_hip(e, "upload fence");
   }
@@ -291,13 +295,14 @@ static spmm_status_t do_step(spmm_srv_s* s, int32_t* remaining) {
     s->active.push_back(r);
     s->active_tokens += r.n;
   }
-  int64_t pool_used = 0;
+  // statistics are read by spmm_serve_stats on other threads: every update
+  // holds mu (here, and the counts below in the closing lock)
+  int64_t problems = 0, steps = 0;
   {
     std::lock_guard<std::mutex> lk(s->mu);
-    pool_used = s->pool->used();
+    s->stats.peak_pool_bytes = std::max(s->stats.peak_pool_bytes, s->pool->used());
+    s->stats.peak_active = std::max(s->stats.peak_active, (int32_t)s->active.size());
   }
-  if (pool_used > s->stats.peak_pool_bytes) s->stats.peak_pool_bytes = pool_used;
-  if ((int32_t)s->active.size() > s->stats.peak_active) s->stats.peak_active = (int32_t)s->active.size();
 
   std::vector<Request> finished;
   if (st == SPMM_OK && !s->active.empty()) {
@@ -311,7 +316,7 @@ static spmm_status_t do_step(spmm_srv_s* s, int32_t* remaining) {
           st = run_plan(s->plans[l], r.n, X, r.ld, Y, r.ld, plan_variant(s->plans[l], r.n), false, s->stream);
           if (st == SPMM_OK && s->relu[l]) st = launch_relu(s->act, Y, s->dims[l + 1], r.n, r.ld, s->stream);
         }
-        s->stats.problems_run += 1;
+        problems += 1;
       }
       r.layer = s->L;
     } else {
@@ -336,12 +341,12 @@ static spmm_status_t do_step(spmm_srv_s* s, int32_t* remaining) {
       if (!s->opts.simulate)
         st = spmm_group_run(s->group, (int32_t)cnt, s->g_plans.data(), s->g_n.data(), s->g_x.data(), s->g_ldx.data(),
                             s->g_y.data(), s->g_ldy.data(), s->g_relu.data(), s->stream);
-      s->stats.problems_run += (int64_t)cnt;
+      problems += (int64_t)cnt;
       for (Request& r : s->active) r.layer += 1;
     }
     if (st == SPMM_OK && !s->opts.simulate) {
       hipError_t e = hipEventRecord(s->done_ev, s->stream);
-      if (e == hipSuccess) e = hipStreamWaitEvent(s->copy_stream, s->done_ev, 0);
+      if (e == hipSuccess) e = hipStreamWaitEvent(s->down_stream, s->done_ev, 0);
       if (e != hipSuccess) st = fail_hip(e, "step fence");
     }
     for (const Request& r : s->active)
@@ -356,7 +361,7 @@ static spmm_status_t do_step(spmm_srv_s* s, int32_t* remaining) {
       }
     }
     s->active.resize(w);
-    s->stats.steps += 1;
+    steps += 1;
     if (st == SPMM_OK && async) {
       spmm_srv_s::InFlight f;
       if (!s->free_events.empty()) {
@@ -367,7 +372,7 @@ static spmm_status_t do_step(spmm_srv_s* s, int32_t* remaining) {
         if (e != hipSuccess) st = fail_hip(e, "hipEventCreate");
       }
       if (st == SPMM_OK) {
-        hipError_t e = hipEventRecord(f.ev, s->copy_stream);  // after the step's kernels and downloads
+        hipError_t e = hipEventRecord(f.ev, s->down_stream);  // after the step's kernels and downloads
         if (e != hipSuccess) st = fail_hip(e, "hipEventRecord");
       }
       if (st == SPMM_OK) {
@@ -378,7 +383,7 @@ static spmm_status_t do_step(spmm_srv_s* s, int32_t* remaining) {
       }
     } else if (st == SPMM_OK && !s->opts.simulate) {
       hipError_t e = hipStreamSynchronize(s->stream);
-      if (e == hipSuccess) e = hipStreamSynchronize(s->copy_stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(s->down_stream);
       if (e != hipSuccess) st = fail_hip(e, "serving step");
     }
   } else if (st == SPMM_OK && async && !s->inflight.empty()) {
@@ -392,6 +397,8 @@ static spmm_status_t do_step(spmm_srv_s* s, int32_t* remaining) {
       s->fail_msg = spmm_last_error();
     }
     for (const Request& r : finished) finish_locked(s, r, t1);
+    s->stats.problems_run += problems;
+    s->stats.steps += steps;
     s->stats.busy_s += t1 - t0;
     if (remaining) *remaining = (int32_t)(s->pending.size() + s->active.size() + s->inflight.size());
   }
@@ -430,9 +437,11 @@ static void destroy_server(spmm_srv_s* s) {
     (void)hipStreamSynchronize(s->stream);
     (void)hipStreamDestroy(s->stream);
   }
-  if (s->copy_stream) {
-    (void)hipStreamSynchronize(s->copy_stream);
-    (void)hipStreamDestroy(s->copy_stream);
+  for (hipStream_t cs : {s->up_stream, s->down_stream}) {
+    if (cs) {
+      (void)hipStreamSynchronize(cs);
+      (void)hipStreamDestroy(cs);
+    }
   }
   if (s->up_ev) (void)hipEventDestroy(s->up_ev);
   if (s->done_ev) (void)hipEventDestroy(s->done_ev);
@@ -503,7 +512,9 @@ spmm_status_t spmm_serve_create(const spmm_plan_t* layer_plans, int32_t num_laye
       st = fail_hip(e, "hipMalloc activation pool");
     if (st == SPMM_OK && (e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking)) != hipSuccess)
       st = fail_hip(e, "hipStreamCreate");
-    if (st == SPMM_OK && (e = hipStreamCreateWithFlags(&s->copy_stream, hipStreamNonBlocking)) != hipSuccess)
+    if (st == SPMM_OK && (e = hipStreamCreateWithFlags(&s->up_stream, hipStreamNonBlocking)) != hipSuccess)
+      st = fail_hip(e, "hipStreamCreate");
+    if (st == SPMM_OK && (e = hipStreamCreateWithFlags(&s->down_stream, hipStreamNonBlocking)) != hipSuccess)
       st = fail_hip(e, "hipStreamCreate");
     if (st == SPMM_OK && (e = hipEventCreateWithFlags(&s->up_ev, hipEventDisableTiming)) != hipSuccess)
       st = fail_hip(e, "hipEventCreate");

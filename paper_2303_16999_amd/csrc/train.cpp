@@ -75,19 +75,19 @@ spmm_status_t spmm_plan_transpose(spmm_plan_t p, const spmm_plan_opts* opts, spm
   float* scales = nullptr;
   hipError_t e = hipMalloc((void**)&map_dev, sizeof(int32_t) * nnz);
   if (e == hipSuccess) e = hipMalloc(&vals, (size_t)nnz * b * b * eb);
-  if (e == hipSuccess && p->scales_csr) e = hipMalloc((void**)&scales, sizeof(float) * nnz);
+  if (e == hipSuccess && p->scales) e = hipMalloc((void**)&scales, sizeof(float) * nnz);
   if (e == hipSuccess) e = hipMemcpy(map_dev, map.data(), sizeof(int32_t) * nnz, hipMemcpyHostToDevice);
   if (e == hipSuccess) {
     const unsigned grid = (unsigned)std::min<int64_t>(8192, ceil_div(nnz * b * b, 256));
     if (eb == 1)
       hipLaunchKernelGGL(k_transpose_blocks<uint8_t>, dim3(grid), dim3(256), 0, nullptr, map_dev, nnz, b,
-                         (const uint8_t*)p->values_csr, (uint8_t*)vals, p->scales_csr, scales);
+                         (const uint8_t*)p->values, (uint8_t*)vals, p->scales, scales);
     else if (eb == 2)
       hipLaunchKernelGGL(k_transpose_blocks<uint16_t>, dim3(grid), dim3(256), 0, nullptr, map_dev, nnz, b,
-                         (const uint16_t*)p->values_csr, (uint16_t*)vals, p->scales_csr, scales);
+                         (const uint16_t*)p->values, (uint16_t*)vals, p->scales, scales);
     else
       hipLaunchKernelGGL(k_transpose_blocks<uint32_t>, dim3(grid), dim3(256), 0, nullptr, map_dev, nnz, b,
-                         (const uint32_t*)p->values_csr, (uint32_t*)vals, p->scales_csr, scales);
+                         (const uint32_t*)p->values, (uint32_t*)vals, p->scales, scales);
     e = hipGetLastError();
   }
   if (e != hipSuccess) st = fail_hip(e, "transposed values");

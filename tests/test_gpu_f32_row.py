@@ -1,5 +1,5 @@
 """The row-wise FP32 kernel (b = 16/32, FP32 W, X and Y) against the FP64
-oracle and against the LDS-staged general kernel."""
+oracle."""
 import numpy as np
 import pytest
 import torch
@@ -25,11 +25,10 @@ def test_row_f32_matches_oracle(b, n):
 
 
 @pytest.mark.parametrize("b", [16, 32])
-def test_row_f32_integer_exact_and_agrees_with_general_kernel(b, monkeypatch):
+def test_row_f32_integer_exact(b):
     c = Case(b * 30 + 3, b * 26 + 9, 130, b, 1 / 5, w="f32", seed=220 + b, integer=True)
     row = _run(c)
     assert np.array_equal(row, round_like(c.oracle(), "f32"))
-    monkeypatch.setenv("SPMM_KERNEL", "general")
     assert np.array_equal(_run(c), row)
 
 

@@ -6,7 +6,7 @@ import torch
 from oracle import plan_ref
 from oracle import spmm_ref as O
 from paper_2303_16999_amd import spmm, synth
-from gpu_cases import TOL, Case, dev, round_like, y_f64
+from gpu_cases import assert_elementwise, TOL, Case, dev, round_like, y_f64
 
 pytestmark = pytest.mark.gpu
 
@@ -95,6 +95,7 @@ def test_small_sweep_shape_sampled_columns(b):
     _, Y = c.run_static()
     cols = np.sort(np.random.default_rng(9).choice(1024, 64, replace=False))
     assert _err(c, Y, cols) <= 5e-3
+    assert_elementwise(y_f64(Y, c)[:, cols], c.oracle(cols), c.abs_oracle(cols), c.k, "f16")
     assert torch.isfinite(Y).all().item()
 
 
