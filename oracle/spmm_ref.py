@@ -114,12 +114,6 @@ def rel_fro(Y_dev, Y_ref):
     return float(np.linalg.norm(Y_dev - Y_ref) / den)
 
 
-def mask_from_blocks(mb, kb, rows, cols):
-    M = np.zeros((mb, kb), dtype=np.uint8)
-    M[np.asarray(rows, dtype=np.int64), np.asarray(cols, dtype=np.int64)] = 1
-    return M
-
-
 def useful_flops(m, k, n, b, block_mask):
     """2 * n * (number of ones of the element mask M).
 

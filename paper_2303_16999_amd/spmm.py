@@ -53,7 +53,7 @@ SIGNATURES = {
     "spmm_plan_set_values": ([_vp, _vp, _vp, _vp], _c_i32),
     "spmm_run_static": ([_vp, _c_i64, _vp, _c_i64, _vp, _c_i64, _vp], _c_i32),
     "spmm_plan_info": ([_vp, _pi64, _pi32, _pi32, _pi32, _pi32], _c_i32),
-    "spmm_plan_export": ([_vp, _vp, _vp, _vp], _c_i32),
+    "spmm_plan_export": ([_vp, _vp, _vp, _vp, _vp], _c_i32),
     "spmm_plan_destroy": ([_vp], _c_i32),
     "spmm_dynamic_create": ([_c_i64, _c_i64, _c_i32, _c_i64, _c_i32, _c_i32, _c_i32, ctypes.POINTER(PlanOpts),
                              ctypes.POINTER(_vp)], _c_i32),
@@ -137,6 +137,69 @@ def torch_dtype(code):
     return {F32: torch.float32, F16: torch.float16, BF16: torch.bfloat16, FP8_E4M3: torch.uint8}[code]
 
 
+_ELEM_BYTES = {F32: 4, F16: 2, BF16: 2, FP8_E4M3: 1}
+
+
+def check_dense(t, rows, n, code, name, on_gpu=True):
+    """Rejects a dense operand (X or Y) that the kernels would read or write
+    past its end: a 2-D torch tensor of the plan's dtype with unit column
+    stride, at least `rows` rows and n columns, on the GPU (on_gpu=False
+    leaves that last check to the caller). Only shapes, strides, dtypes and
+    the device are looked at."""
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("%s must be a torch tensor" % name)
+    if t.dim() != 2:
+        raise ValueError("%s must be 2-D, got %d dimensions" % (name, t.dim()))
+    if t.dtype != torch_dtype(code):
+        raise ValueError("%s has dtype %s, the plan needs %s" % (name, t.dtype, torch_dtype(code)))
+    if t.shape[1] > 1 and t.stride(1) != 1:
+        raise ValueError("%s must have unit column stride" % name)
+    if t.shape[0] < rows:
+        raise ValueError("%s has %d rows, the plan needs %d" % (name, t.shape[0], rows))
+    if n < 0 or n > t.shape[1]:
+        raise ValueError("n = %d does not fit the %d columns of %s" % (n, t.shape[1], name))
+    if on_gpu:
+        check_gpu(t, name)
+
+
+def check_gpu(t, name):
+    if not t.is_cuda:
+        raise ValueError("%s must be a GPU tensor" % name)
+
+
+def check_flat(t, count, elem_bytes, name, dtype=None, on_gpu=True):
+    """Rejects a device buffer of fewer than `count` elements of `elem_bytes`
+    bytes (values, scales, indices), of the wrong dtype, or not on the GPU."""
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("%s must be a torch tensor" % name)
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError("%s has dtype %s, expected %s" % (name, t.dtype, dtype))
+    if t.element_size() != elem_bytes:
+        raise ValueError("%s has %d-byte elements, expected %d" % (name, t.element_size(), elem_bytes))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if t.numel() < count:
+        raise ValueError("%s holds %d elements, %d are needed" % (name, t.numel(), count))
+    if on_gpu:
+        check_gpu(t, name)
+
+
+def _ncols(t):
+    """Columns of a 2-D operand (0 for anything else, which the checks reject)."""
+    shape = getattr(t, "shape", ())
+    return int(shape[1]) if len(shape) == 2 else 0
+
+
+def _ld(t, ld, name):
+    if ld is None:
+        return int(t.stride(0))
+    if int(ld) != int(t.stride(0)):
+        raise ValueError("leading dimension of %s must be its row stride %d" % (name, t.stride(0)))
+    return int(ld)
+
+
 class StaticPlan:
     """spmm_plan_static / spmm_plan_set_values / spmm_run_static."""
 
@@ -163,21 +226,40 @@ class StaticPlan:
         return {"nnzb": nnz.value, "group_rows": gr.value, "num_groups": ng.value, "num_panels": npn.value,
                 "num_split_rows": nh.value}
 
+    def _nnzb(self):
+        if getattr(self, "_nnzb_cache", None) is None:
+            self._nnzb_cache = self.info()["nnzb"]
+        return self._nnzb_cache
+
     def set_values(self, values, scales=None, stream=None):
+        import torch
+        nnzb = self._nnzb()
+        if nnzb:
+            check_flat(values, nnzb * self.b * self.b, _ELEM_BYTES[self.w], "values", on_gpu=False)
+            if scales is not None:
+                check_flat(scales, nnzb, 4, "scales", torch.float32, on_gpu=False)
+            check_gpu(values, "values")
+            if scales is not None:
+                check_gpu(scales, "scales")
         check(lib().spmm_plan_set_values(self._h, _ptr(values), _ptr(scales), _stream(stream)))
 
+    def _operands(self, X, Y, n, ldx, ldy):
+        n = _ncols(X) if n is None else int(n)
+        check_dense(X, self.k, n, self.x, "X", on_gpu=False)
+        check_dense(Y, self.m, n, self.y, "Y", on_gpu=False)
+        ldx, ldy = _ld(X, ldx, "X"), _ld(Y, ldy, "Y")
+        check_gpu(X, "X")
+        check_gpu(Y, "Y")
+        return n, ldx, ldy
+
     def run(self, X, Y, n=None, ldx=None, ldy=None, stream=None):
-        n = X.shape[1] if n is None else n
-        ldx = X.stride(0) if ldx is None else ldx
-        ldy = Y.stride(0) if ldy is None else ldy
-        check(lib().spmm_run_static(self._h, int(n), _ptr(X), int(ldx), _ptr(Y), int(ldy), _stream(stream)))
+        n, ldx, ldy = self._operands(X, Y, n, ldx, ldy)
+        check(lib().spmm_run_static(self._h, n, _ptr(X), ldx, _ptr(Y), ldy, _stream(stream)))
         return Y
 
     def autotune(self, X, Y, n=None, ldx=None, ldy=None, stream=None):
         """spmm_autotune_static: returns (chosen variant, {variant: mean ms})."""
-        n = X.shape[1] if n is None else n
-        ldx = X.stride(0) if ldx is None else ldx
-        ldy = Y.stride(0) if ldy is None else ldy
+        n, ldx, ldy = self._operands(X, Y, n, ldx, ldy)
         v = ctypes.c_int32()
         t = (ctypes.c_float * 3)()
         check(lib().spmm_autotune_static(self._h, int(n), _ptr(X), int(ldx), _ptr(Y), int(ldy), _stream(stream),
@@ -189,9 +271,11 @@ class StaticPlan:
         row_ptr = np.zeros(self.mb + 1, np.int32)
         col_idx = np.zeros(max(inf["nnzb"], 1), np.int32)
         panel_ptr = np.zeros(inf["num_panels"] + 1, np.int32)
+        order = np.zeros(max(inf["nnzb"], 1), np.int32)
         check(lib().spmm_plan_export(self._h, row_ptr.ctypes.data_as(_vp), col_idx.ctypes.data_as(_vp),
-                                     panel_ptr.ctypes.data_as(_vp)))
-        return {"row_ptr": row_ptr, "col_idx": col_idx[: inf["nnzb"]], "panel_ptr": panel_ptr}
+                                     panel_ptr.ctypes.data_as(_vp), order.ctypes.data_as(_vp)))
+        return {"row_ptr": row_ptr, "col_idx": col_idx[: inf["nnzb"]], "panel_ptr": panel_ptr,
+                "order": order[: inf["nnzb"]]}
 
     @classmethod
     def from_ell(cls, m, k, b, ell_cols, w="f16", x=None, y=None, group_rows=0, num_panels=0, n_hint=0, variant=0):
@@ -216,6 +300,12 @@ class StaticPlan:
 
     def set_values_ell(self, values, scales=None, stream=None):
         """spmm_plan_set_values_ell: values in ELL slot order [ceil(m/b), width, b, b]."""
+        import torch
+        slots = self.mb * self.ell_width
+        if slots:
+            check_flat(values, slots * self.b * self.b, _ELEM_BYTES[self.w], "values")
+            if scales is not None:
+                check_flat(scales, slots, 4, "scales", torch.float32)
         check(lib().spmm_plan_set_values_ell(self._h, _ptr(values), _ptr(scales), _stream(stream)))
 
     def transpose(self, group_rows=0, num_panels=0, n_hint=0, variant=0):
@@ -228,12 +318,19 @@ class StaticPlan:
         t.m, t.k, t.b = self.k, self.m, self.b
         t.w, t.x, t.y = self.w, self.x, self.y
         t.mb, t.kb = self.kb, self.mb
+        t._nnzb_cache = None
         return t
 
     def sddmm(self, dY, X, G, n=None, stream=None):
         """spmm_sddmm: G[e] = dY[rows of r] X[rows of c]^T on the plan's blocks (FP32 [nnzb, b, b])."""
-        n = X.shape[1] if n is None else n
-        check(lib().spmm_sddmm(self._h, int(n), _ptr(dY), int(dY.stride(0)), _ptr(X), int(X.stride(0)), _ptr(G),
+        import torch
+        n = _ncols(X) if n is None else int(n)
+        check_dense(dY, self.m, n, self.y, "dY", on_gpu=False)
+        check_dense(X, self.k, n, self.x, "X", on_gpu=False)
+        check_flat(G, self._nnzb() * self.b * self.b, 4, "G", torch.float32, on_gpu=False)
+        for t, name in ((dY, "dY"), (X, "X"), (G, "G")):
+            check_gpu(t, name)
+        check(lib().spmm_sddmm(self._h, n, _ptr(dY), int(dY.stride(0)), _ptr(X), int(X.stride(0)), _ptr(G),
                                _stream(stream)))
         return G
 
@@ -266,12 +363,24 @@ class DynamicHandle:
 
     def run(self, nnz_dev, rows, cols, values, X, Y, status_dev, scales=None, n=None, ldx=None, ldy=None,
             stream=None):
-        n = X.shape[1] if n is None else n
-        ldx = X.stride(0) if ldx is None else ldx
-        ldy = Y.stride(0) if ldy is None else ldy
+        import torch
+        n = _ncols(X) if n is None else int(n)
+        check_dense(X, self.k, n, self.x, "X", on_gpu=False)
+        check_dense(Y, self.m, n, self.y, "Y", on_gpu=False)
+        ldx, ldy = _ld(X, ldx, "X"), _ld(Y, ldy, "Y")
+        # the index and value buffers are read only up to the device-side count,
+        # which the host cannot see; their dtypes and devices are checked
+        flat = [(nnz_dev, 1, 4, "nnz_dev", torch.int32), (status_dev, 1, 4, "status_dev", torch.int32),
+                (rows, 0, 4, "rows", torch.int32), (cols, 0, 4, "cols", torch.int32),
+                (values, 0, _ELEM_BYTES[self.w], "values", None)]
+        if scales is not None:
+            flat.append((scales, 0, 4, "scales", torch.float32))
+        for t, cnt, eb, name, dt in flat:
+            check_flat(t, cnt, eb, name, dt, on_gpu=False)
+        for t, name in [(X, "X"), (Y, "Y")] + [(f[0], f[3]) for f in flat]:
+            check_gpu(t, name)
         check(lib().spmm_run_dynamic(self._h, _ptr(nnz_dev), _ptr(rows), _ptr(cols), _ptr(values), _ptr(scales),
-                                     int(n), _ptr(X), int(ldx), _ptr(Y), int(ldy), _ptr(status_dev),
-                                     _stream(stream)))
+                                     n, _ptr(X), ldx, _ptr(Y), ldy, _ptr(status_dev), _stream(stream)))
         return Y
 
     def info(self):
@@ -304,7 +413,7 @@ class DynamicHandle:
 
 
 class Group:
-    """spmm_group_create / spmm_group_run: many static products in one persistent launch."""
+    """spmm_group_create / spmm_group_run: many static products in one launch."""
 
     def __init__(self, max_problems):
         h = _vp()
@@ -314,6 +423,15 @@ class Group:
 
     def run(self, plans, Xs, Ys, ns=None, relu=None, stream=None):
         cnt = len(plans)
+        if len(Xs) != cnt or len(Ys) != cnt or (ns is not None and len(ns) != cnt):
+            raise ValueError("plans, Xs, Ys and ns must have one entry per problem")
+        for i, (p, X, Y) in enumerate(zip(plans, Xs, Ys)):
+            n = _ncols(X) if ns is None else int(ns[i])
+            check_dense(X, p.k, n, p.x, "X[%d]" % i, on_gpu=False)
+            check_dense(Y, p.m, n, p.y, "Y[%d]" % i, on_gpu=False)
+        for i, (X, Y) in enumerate(zip(Xs, Ys)):
+            check_gpu(X, "X[%d]" % i)
+            check_gpu(Y, "Y[%d]" % i)
         P = (_vp * cnt)(*[p._h.value for p in plans])
         N = (ctypes.c_int64 * cnt)(*[(X.shape[1] if ns is None else ns[i]) for i, X in enumerate(Xs)])
         XP = (_vp * cnt)(*[_ptr(X) for X in Xs])
@@ -354,19 +472,39 @@ class Server:
         check(lib().spmm_serve_create(P, L, D, R, ctypes.byref(opts), ctypes.byref(h)))
         self._h = h
         self._keep = {}  # request id -> host buffers kept alive until done
+        self.dims = [int(d) for d in dims]
+        live = [p for p in (plans or []) if p is not None]
+        self._x_bytes = _ELEM_BYTES[live[0].x] if live else None
+        self._y_bytes = _ELEM_BYTES[live[-1].y] if live else None
 
     def submit(self, req_id, n, x_host=None, y_host=None):
         """x_host / y_host: C-contiguous [dims[0], ld] and [dims[-1], ld] host arrays
         (numpy arrays, or torch CPU tensors, pinned for asynchronous copies) with
         ld >= n; None when simulating."""
-        def ptr_ld(a):
+        def ptr_ld(a, rows, elem, name):
             if a is None:
                 return None, int(n)
             if hasattr(a, "data_ptr"):
-                return a.data_ptr(), int(a.stride(0))
-            return a.ctypes.data, int(a.strides[0] // a.itemsize)
-        xp, ldx = ptr_ld(x_host)
-        yp, ldy = ptr_ld(y_host)
+                if a.is_cuda:
+                    raise ValueError("%s must be host memory" % name)
+                shape, itemsize = tuple(a.shape), a.element_size()
+                strides = tuple(st * itemsize for st in a.stride())
+                ptr = a.data_ptr()
+            else:
+                shape, itemsize, strides, ptr = a.shape, a.itemsize, a.strides, a.ctypes.data
+            if len(shape) != 2:
+                raise ValueError("%s must be 2-D" % name)
+            if elem is not None and itemsize != elem:
+                raise ValueError("%s has %d-byte elements, the layer needs %d" % (name, itemsize, elem))
+            if shape[1] > 1 and strides[1] != itemsize:
+                raise ValueError("%s must have contiguous rows" % name)
+            if shape[0] < rows:
+                raise ValueError("%s has %d rows, the model needs %d" % (name, shape[0], rows))
+            if int(n) > shape[1]:
+                raise ValueError("n = %d does not fit the %d columns of %s" % (int(n), shape[1], name))
+            return ptr, int(strides[0] // itemsize)
+        xp, ldx = ptr_ld(x_host, self.dims[0], self._x_bytes, "x_host")
+        yp, ldy = ptr_ld(y_host, self.dims[-1], self._y_bytes, "y_host")
         if ldx != ldy:
             raise ValueError("x_host and y_host must share one leading dimension")
         check(lib().spmm_serve_submit(self._h, int(req_id), int(n), xp, yp, ldx))

@@ -76,6 +76,15 @@ class Case:
             return O.spmm_blockwise(self.m, self.k, self.b, self.rows, self.cols, self.vals64, self.X64)
         return O.spmm_blockwise_columns(self.m, self.k, self.b, self.rows, self.cols, self.vals64, self.X64, cols)
 
+    def abs_oracle(self, cols=None):
+        """(|M o W|) |X| in FP64 on the same columns: the scale of each output's
+        rounding error."""
+        X = np.abs(self.X64)
+        V = np.abs(self.vals64)
+        if cols is None:
+            return O.spmm_blockwise(self.m, self.k, self.b, self.rows, self.cols, V, X)
+        return O.spmm_blockwise_columns(self.m, self.k, self.b, self.rows, self.cols, V, X, cols)
+
     def run_static(self, group_rows=0, num_panels=0, n_hint=0, Y=None):
         plan = spmm.StaticPlan(self.m, self.k, self.b, self.mask, self.w, self.x, self.y, group_rows=group_rows,
                                num_panels=num_panels, n_hint=n_hint or self.n)
@@ -104,3 +113,29 @@ def round_like(Y64, code):
     t = torch.from_numpy(Y64)
     dt = {"f32": torch.float32, "f16": torch.float16, "bf16": torch.bfloat16}[code]
     return t.to(dt).to(torch.float64).numpy()
+
+
+# unit roundoff and the smallest subnormal spacing of each output type
+_UNIT = {"f32": 2.0 ** -24, "f16": 2.0 ** -11, "bf16": 2.0 ** -8}
+_ETA = {"f32": 2.0 ** -150, "f16": 2.0 ** -25, "bf16": 2.0 ** -134}
+
+
+def elementwise_bound(Y_ref, A, terms, code):
+    """Per-element bound on |Y_dev - Y_ref| for a sum of `terms` products
+    accumulated in FP32 in any order, then rounded once to `code`:
+    |s - y| <= g A with g = t u32 / (1 - t u32) (A = (|W| |X|) of the element),
+    and the final rounding adds u |s| + eta, with |s| <= |y| + g A."""
+    u32 = 2.0 ** -24
+    g = terms * u32 / (1.0 - terms * u32)
+    u, eta = _UNIT[code], _ETA[code]
+    return u * np.abs(Y_ref) + (1.0 + u) * g * A + eta
+
+
+def assert_elementwise(Y_dev, Y_ref, A, terms, code):
+    """Every element within elementwise_bound; reports the worst offender."""
+    bound = elementwise_bound(Y_ref, A, terms, code)
+    excess = np.abs(Y_dev - Y_ref) - bound
+    if not np.all(excess <= 0):
+        i = np.unravel_index(np.argmax(excess), excess.shape)
+        raise AssertionError("element %s: got %r, oracle %r, bound %r (%d elements out of bound)"
+                             % (i, Y_dev[i], Y_ref[i], bound[i], int(np.sum(excess > 0))))

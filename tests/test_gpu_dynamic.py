@@ -6,7 +6,7 @@ import torch
 from oracle import plan_ref
 from oracle import spmm_ref as O
 from paper_2303_16999_amd import spmm, synth
-from gpu_cases import Case, dev, y_f64
+from gpu_cases import assert_elementwise, Case, dev, y_f64
 
 pytestmark = pytest.mark.gpu
 
@@ -122,7 +122,10 @@ def test_dynamic_call_stream_config3_shape(w):
         torch.cuda.synchronize()
         assert status.item() == 0
         ref = O.spmm_blockwise_columns(m, k, b, rows, cols, v64, X64, cols_s)
-        assert O.rel_fro(Y.cpu().numpy().astype(np.float64)[:, cols_s], ref) <= 5e-3
+        got = Y.cpu().numpy().astype(np.float64)[:, cols_s]
+        assert O.rel_fro(got, ref) <= 5e-3
+        A = O.spmm_blockwise_columns(m, k, b, rows, cols, np.abs(v64), np.abs(X64), cols_s)
+        assert_elementwise(got, ref, A, 2 * k if w == "fp8" else k, "f16")
 
 
 @pytest.mark.parametrize("w,b", [("f16", 16), ("fp8", 16), ("bf16", 32)])

@@ -153,10 +153,13 @@ def test_group_device_table_form_matches_single_launches():
             assert torch.equal(Ys[i][:, : c.n], singles[i]), (rep, i)
 
 
-@pytest.mark.parametrize("count", [3, 40])  # argument table and device table
-def test_group_back_to_back_calls_keep_their_own_tables(count):
+@pytest.mark.parametrize("count,graph", [(3, "0"), (40, "0"), (3, "1")])  # argument table, device table, graph
+def test_group_back_to_back_calls_keep_their_own_tables(count, graph, monkeypatch):
     """Calls issued without synchronising in between, each with other n, X and Y:
-    every output must be the one its own call asked for."""
+    every output must be the one its own call asked for. With
+    SPMM_GROUP_GRAPH=1 the captured graph's node is updated while the previous
+    replay of the same executable may still be running."""
+    monkeypatch.setenv("SPMM_GROUP_GRAPH", graph)
     b = 16
     cases = [Case((3 + i % 4) * b, (5 + i % 3) * b, 64 + 8 * (i % 7), b, 0.3, w="f16", seed=300 + i)
              for i in range(count)]

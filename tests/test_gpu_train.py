@@ -203,9 +203,10 @@ def test_sddmm_rejects_unsupported_plans(b, w, x, y):
     plan = _plan(c)
     G = torch.zeros((plan.info()["nnzb"], b, b), device="cuda")
     X = torch.zeros((c.k, 32), dtype=spmm.torch_dtype(spmm.DTYPE_CODES[x]), device="cuda")
-    dY = torch.zeros((c.m, 32), dtype=spmm.torch_dtype(spmm.DTYPE_CODES[x]), device="cuda")
-    with pytest.raises(spmm.SpmmError):
+    dY = torch.zeros((c.m, 32), dtype=spmm.torch_dtype(spmm.DTYPE_CODES[y]), device="cuda")
+    with pytest.raises(spmm.SpmmError) as e:
         plan.sddmm(dY, X, G)
+    assert e.value.status == spmm.ERR_UNSUPPORTED
 
 
 def test_training_step_products_at_full_size_sampled():
