@@ -307,6 +307,31 @@ spmm_status_t spmm_dynamic_info(spmm_dyn_t h, int32_t* group_rows, int32_t* num_
 
 spmm_status_t spmm_dynamic_destroy(spmm_dyn_t h);
 
+/* ------------------------------------------------------- allocation-free dynamic call
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc. The same
+ * call as spmm_run_dynamic (same kernels, same results bit for bit) without a
+ * handle: the shape and capacity come as arguments, and the encoder's buffers
+ * (block-CSR of the call, input indices, panels, status) live in a fixed
+ * array of SPMM_NOALLOC_SCRATCH_BYTES of device memory that the library
+ * holds on every GPU it runs on until the process ends. Nothing is
+ * allocated, ever. Limits: b must divide k, and the call must fit the
+ * one-workgroup encoder and the array: (mb + 1) + 2 max_nnzb + (panels + 1) + 64
+ * int32 words (for example m = k = 4096, b = 16, max_nnzb = 8192 uses about 65 KiB);
+ * beyond them the call returns SPMM_ERR_CAPACITY before enqueueing anything.
+ * Every call on one GPU uses the same array: calls that overlap on one GPU
+ * (different streams, or threads) race and must be ordered by the caller.
+ * The values are read in place (not copied), so they must stay valid until
+ * the call's work on `stream` completes. Other arguments, errors and the
+ * device status word as for spmm_run_dynamic. */
+#define SPMM_NOALLOC_SCRATCH_BYTES (256 * 1024)
+spmm_status_t spmm_run_dynamic_noalloc(int64_t m, int64_t k, int32_t b, int64_t max_nnzb,
+                                       spmm_dtype_t w, spmm_dtype_t x, spmm_dtype_t y,
+                                       const int32_t* nnzb_dev, const int32_t* block_row_dev,
+                                       const int32_t* block_col_dev, const void* values_dev,
+                                       const float* scales_dev, int64_t n, const void* X, int64_t ldx,
+                                       void* Y, int64_t ldy, int32_t* status_dev, void* stream);
+
 /* ------------------------------------------------------------------ serving
  * A request loop for a chain of sparse layers whose weights stay resident on
  * the device: y = f_L(... f_1(x)), f_l(v) = act_l((M o W)_l v), where act_l is

@@ -244,6 +244,17 @@ spmm_status_t run_plan(const spmm_plan_s* p, int64_t n, const void* X, int64_t l
   return launch_spmm_row_f32(a, p->pb.row_ptr, p->pb.col_idx, stream);
 }
 
+// The compute kernel of a dynamic call on its block-CSR (never split rows).
+spmm_status_t run_dynamic_kernel(RunArgs& a, const int32_t* row_ptr, const int32_t* col_idx, hipStream_t s) {
+  const int32_t b = a.plan.b;
+  a.ns = b < 16 ? 0 : default_ns(a.n);
+  if (b < 16) return launch_spmm_small(a, row_ptr, col_idx, s);
+  if (a.xt == SPMM_F32) return launch_spmm_row_f32(a, row_ptr, col_idx, s);
+  if (a.wt == a.xt && row_pp_preferred(b, a.plan.mb, a.n, a.ns, a.nnz, device_cu_count()))
+    return launch_spmm_row_pp(a, row_ptr, col_idx, s);
+  return launch_spmm_row(a, row_ptr, col_idx, s);
+}
+
 // Block rows longer than max(64, 4 x the mean row) are split over the four
 // waves of a workgroup by the row-wise kernel for b = 16 (a long row would
 // otherwise be one wave's serial chain). SPMM_SPLIT=0 turns this off (for
@@ -629,12 +640,7 @@ spmm_status_t spmm_run_dynamic(spmm_dyn_t h, const int32_t* nnzb_dev, const int3
   a.yt = h->y;
   a.status = h->status;
   a.nnz = h->max_nnzb;
-  a.ns = h->b < 16 ? 0 : default_ns(n);
-  if (h->b < 16) return launch_spmm_small(a, h->pb.row_ptr, h->pb.col_idx, s);
-  if (h->x == SPMM_F32) return launch_spmm_row_f32(a, h->pb.row_ptr, h->pb.col_idx, s);
-  if (h->w == h->x && row_pp_preferred(h->b, h->mb, n, a.ns, h->max_nnzb, device_cu_count()))
-    return launch_spmm_row_pp(a, h->pb.row_ptr, h->pb.col_idx, s);
-  return launch_spmm_row(a, h->pb.row_ptr, h->pb.col_idx, s);
+  return run_dynamic_kernel(a, h->pb.row_ptr, h->pb.col_idx, s);
 }
 
 spmm_status_t spmm_dynamic_export(spmm_dyn_t h, int32_t* row_ptr, int32_t* col_idx, int32_t* src, int32_t* panel_ptr,

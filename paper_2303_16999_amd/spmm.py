@@ -61,6 +61,8 @@ SIGNATURES = {
     "spmm_dynamic_export": ([_vp, _vp, _vp, _vp, _vp, _pi64], _c_i32),
     "spmm_dynamic_info": ([_vp, _pi32, _pi32, _pi32], _c_i32),
     "spmm_dynamic_destroy": ([_vp], _c_i32),
+    "spmm_run_dynamic_noalloc": ([_c_i64, _c_i64, _c_i32, _c_i64, _c_i32, _c_i32, _c_i32, _vp, _vp, _vp, _vp, _vp,
+                                  _c_i64, _vp, _c_i64, _vp, _c_i64, _vp, _vp], _c_i32),
     "spmm_autotune_static": ([_vp, _c_i64, _vp, _c_i64, _vp, _c_i64, _vp, _pi32, ctypes.POINTER(ctypes.c_float)],
                              _c_i32),
     "spmm_group_create": ([_c_i32, ctypes.POINTER(_vp)], _c_i32),
@@ -545,6 +547,32 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+def run_dynamic_noalloc(m, k, b, max_nnzb, nnz_dev, rows, cols, values, X, Y, status_dev, w="f16", x=None, y=None,
+                        scales=None, n=None, stream=None):
+    """spmm_run_dynamic_noalloc: a dynamic call without a handle; the library
+    allocates nothing (its scratch is a fixed device array)."""
+    import torch
+    x = x or ("f16" if w == "fp8" else w)
+    y = y or x
+    wc, xc, yc = DTYPE_CODES[w], DTYPE_CODES[x], DTYPE_CODES[y]
+    n = _ncols(X) if n is None else int(n)
+    check_dense(X, int(k), n, xc, "X", on_gpu=False)
+    check_dense(Y, int(m), n, yc, "Y", on_gpu=False)
+    flat = [(nnz_dev, 1, 4, "nnz_dev", torch.int32), (status_dev, 1, 4, "status_dev", torch.int32),
+            (rows, 0, 4, "rows", torch.int32), (cols, 0, 4, "cols", torch.int32),
+            (values, 0, _ELEM_BYTES[wc], "values", None)]
+    if scales is not None:
+        flat.append((scales, 0, 4, "scales", torch.float32))
+    for t, cnt, eb, name, dt in flat:
+        check_flat(t, cnt, eb, name, dt, on_gpu=False)
+    for t, name in [(X, "X"), (Y, "Y")] + [(f[0], f[3]) for f in flat]:
+        check_gpu(t, name)
+    check(lib().spmm_run_dynamic_noalloc(int(m), int(k), int(b), int(max_nnzb), wc, xc, yc, _ptr(nnz_dev), _ptr(rows),
+                                         _ptr(cols), _ptr(values), _ptr(scales), n, _ptr(X), int(X.stride(0)),
+                                         _ptr(Y), int(Y.stride(0)), _ptr(status_dev), _stream(stream)))
+    return Y
 
 
 def clock():
