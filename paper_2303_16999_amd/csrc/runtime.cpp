@@ -229,6 +229,9 @@ spmm_status_t run_plan(const spmm_plan_s* p, int64_t n, const void* X, int64_t l
   a.nnz = p->nnzb;
   a.relu = relu;
   if (p->b < 16) {
+    if (small_lds_preferred(p->b, p->w, p->x, p->nnzb, p->mb, p->kb))
+      return launch_spmm_small_lds(a, p->pb.row_ptr, p->pb.col_idx,
+                                   small_lds_rows_per_wave(p->b, p->mb, n, device_cu_count()), stream);
     a.ns = variant;  // 0: the kernel's rule on n
     return launch_spmm_small(a, p->pb.row_ptr, p->pb.col_idx, stream);
   }
@@ -248,6 +251,8 @@ spmm_status_t run_plan(const spmm_plan_s* p, int64_t n, const void* X, int64_t l
 spmm_status_t run_dynamic_kernel(RunArgs& a, const int32_t* row_ptr, const int32_t* col_idx, hipStream_t s) {
   const int32_t b = a.plan.b;
   a.ns = b < 16 ? 0 : default_ns(a.n);
+  if (b < 16 && small_lds_preferred(b, a.wt, a.xt, a.nnz, a.plan.mb, a.plan.kb))
+    return launch_spmm_small_lds(a, row_ptr, col_idx, small_lds_rows_per_wave(b, a.plan.mb, a.n, device_cu_count()), s);
   if (b < 16) return launch_spmm_small(a, row_ptr, col_idx, s);
   if (a.xt == SPMM_F32) return launch_spmm_row_f32(a, row_ptr, col_idx, s);
   if (a.wt == a.xt && row_pp_preferred(b, a.plan.mb, a.n, a.ns, a.nnz, device_cu_count()))

@@ -13,6 +13,7 @@ pytestmark = pytest.mark.gpu
 
 def _static(c, pp, monkeypatch):
     monkeypatch.setenv("SPMM_SMALL_PP", "1" if pp else "0")
+    monkeypatch.setenv("SPMM_SMALL_LDS", "0")  # the kernel without LDS, whose two forms these tests compare
     plan = spmm.StaticPlan(c.m, c.k, c.b, c.mask, c.w, c.x, c.y)
     vals, X, scales = c.device_inputs()
     plan.set_values(vals, scales)
@@ -71,6 +72,7 @@ def test_small_pp_dynamic_equals_plain(b, monkeypatch):
     Xs = synth.to_storage(synth.normal((kb * b, n), 81), "f16")
     h = spmm.DynamicHandle(mb * b, kb * b, b, max_nnz, "f16")
     outs = []
+    monkeypatch.setenv("SPMM_SMALL_LDS", "0")
     for pp in ("1", "0"):
         monkeypatch.setenv("SPMM_SMALL_PP", pp)
         Y = torch.full((mb * b, n), float("nan"), dtype=torch.float16, device="cuda")
