@@ -142,6 +142,13 @@ spmm_status_t launch_spmm_row_grouped_args(spmm_dtype_t xt, spmm_dtype_t yt, int
                                            int32_t total, unsigned lds, hipStream_t stream);
 spmm_status_t launch_spmm_row_grouped(spmm_dtype_t xt, spmm_dtype_t yt, int32_t b, const void* probs_dev,
                                       int32_t count, int32_t total, unsigned lds, hipStream_t stream);
+// Persistent grouped launch: `grid` workgroups (group_persist_grid, a
+// multiple of 8) walk the units of the table (args: the argument form, else
+// probs_dev in device memory) on a static per-XCD schedule.
+int32_t group_persist_grid(int32_t total_units, int per_cu);
+spmm_status_t launch_spmm_row_grouped_persist(spmm_dtype_t xt, spmm_dtype_t yt, int32_t b, const void* args,
+                                              const void* probs_dev, int32_t count, int32_t grid, unsigned lds,
+                                              hipStream_t stream);
 // LDS bytes of a grouped launch with split rows; work units of one problem.
 unsigned group_split_lds(int32_t b);
 int64_t group_problem_units(int32_t mb, int64_t n, int32_t ns, int32_t num_heavy);

@@ -69,6 +69,14 @@ static bool use_graphs() {
   return e && std::string(e) == "1";
 }
 
+// SPMM_GROUP_PERSIST=1 runs the persistent form (a CU-sized grid walking the
+// units on a static per-XCD schedule), 0 the launch with one workgroup per
+// unit.
+static bool use_persist() {
+  const char* e = getenv("SPMM_GROUP_PERSIST");
+  return e && std::string(e) == "1";
+}
+
 // The captured one-node graph of the argument form for a dtype class: captured
 // once with the current arguments, then only its node parameters change.
 static spmm_status_t graph_for(spmm_group_s* g, spmm_dtype_t x, spmm_dtype_t y, int32_t b, unsigned lds,
@@ -131,6 +139,7 @@ spmm_status_t spmm_group_create(int32_t max_problems, spmm_group_t* out) {
   }
   if (st == SPMM_OK && (e = hipStreamCreateWithFlags(&g->capture, hipStreamNonBlocking)) != hipSuccess)
     st = fail_hip(e, "hipStreamCreate");
+
   if (st != SPMM_OK) {
     destroy_group(g);
     return st;
@@ -176,7 +185,7 @@ spmm_status_t spmm_group_run(spmm_group_t g, int32_t count, const spmm_plan_t* p
     g->pending[s] = false;
   }
   // descriptors, in call order, with the prefix of their work units
-  int64_t total = 0;
+  int64_t total = 0, real_units = 0;
   int32_t k = 0;
   bool any_heavy = false;
   for (int32_t i = 0; i < count; ++i) {
@@ -208,14 +217,19 @@ spmm_status_t spmm_group_run(spmm_group_t g, int32_t count, const spmm_plan_t* p
     const int64_t units = group_problem_units(p->mb, n[i], ns, p->num_heavy);
     if (units >= (int64_t)INT32_MAX) return fail(SPMM_ERR_UNSUPPORTED, "too many work units in one group");
     fill_row_problem(dst, a, p->pb.row_ptr, p->pb.col_idx, (int32_t)total, (int32_t)units);
+    real_units += units;
     total += (units + 7) & ~(int64_t)7;  // each problem's range starts at a multiple of 8
     if (total >= (int64_t)INT32_MAX) return fail(SPMM_ERR_UNSUPPORTED, "too many work units in one group");
     ++k;
   }
   hipStream_t strm = (hipStream_t)stream;
   const unsigned lds = any_heavy ? group_split_lds(p0->b) : 0u;
+  const bool persist = use_persist();
+  const int32_t grid = group_persist_grid((int32_t)real_units, p0->b == 16 ? 4 : 3);
   if (inline_table) {
     group_args_header(g->args.data(), used, (int32_t)total);
+    if (persist)
+      return launch_spmm_row_grouped_persist(p0->x, p0->y, p0->b, g->args.data(), nullptr, used, grid, lds, strm);
     if (!use_graphs())
       return launch_spmm_row_grouped_args(p0->x, p0->y, p0->b, g->args.data(), (int32_t)total, lds, strm);
     spmm_group_s::Graph* gr = nullptr;
@@ -233,8 +247,9 @@ spmm_status_t spmm_group_run(spmm_group_t g, int32_t count, const spmm_plan_t* p
     return SPMM_OK;
   }
   SPMM_HIP(hipMemcpyAsync(g->dev[s], g->host[s], (size_t)used * g->desc_bytes, hipMemcpyHostToDevice, strm));
-  if ((st = launch_spmm_row_grouped(p0->x, p0->y, p0->b, g->dev[s], used, (int32_t)total, lds, strm)) != SPMM_OK)
-    return st;
+  st = persist ? launch_spmm_row_grouped_persist(p0->x, p0->y, p0->b, nullptr, g->dev[s], used, grid, lds, strm)
+               : launch_spmm_row_grouped(p0->x, p0->y, p0->b, g->dev[s], used, (int32_t)total, lds, strm);
+  if (st != SPMM_OK) return st;
   SPMM_HIP(hipEventRecord(g->done[s], strm));
   g->pending[s] = true;
   g->slot = (s + 1) % kSlots;

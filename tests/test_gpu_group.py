@@ -1,4 +1,5 @@
-"""GPU tests of the tile variants, the autotuner and the grouped persistent launch."""
+"""GPU tests of the tile variants, the autotuner and the grouped launch in both
+its forms (one workgroup per unit; persistent workgroups walking the units on a static schedule)."""
 import numpy as np
 import pytest
 import torch
@@ -56,8 +57,10 @@ def _group_cases(b, w, y, ns, seed):
     return cases
 
 
+@pytest.mark.parametrize("persist", ["0", "1"])
 @pytest.mark.parametrize("b,w,y", [(16, "f16", "f16"), (32, "bf16", "f32"), (16, "bf16", "bf16")])
-def test_group_matches_single_launches_and_oracle(b, w, y):
+def test_group_matches_single_launches_and_oracle(b, w, y, persist, monkeypatch):
+    monkeypatch.setenv("SPMM_GROUP_PERSIST", persist)
     ns = [1, 17, 64, 200, 513, 0, 33]
     cases = _group_cases(b, w, y, ns, seed=70)
     relu = [i % 2 for i in range(len(cases))]
@@ -133,8 +136,10 @@ def test_group_rejects_mixed_plans():
     assert e.value.status == spmm.ERR_INVALID_ARG
 
 
-def test_group_device_table_form_matches_single_launches():
+@pytest.mark.parametrize("persist", ["0", "1"])
+def test_group_device_table_form_matches_single_launches(persist, monkeypatch):
     """More problems than fit in the kernel arguments: the table goes through device memory."""
+    monkeypatch.setenv("SPMM_GROUP_PERSIST", persist)
     b = 16
     cases = [Case((3 + i % 5) * b, (4 + i % 3) * b + i % 2, 1 + (i * 37) % 150, b, 0.3, w="f16", seed=200 + i)
              for i in range(40)]
@@ -153,13 +158,16 @@ def test_group_device_table_form_matches_single_launches():
             assert torch.equal(Ys[i][:, : c.n], singles[i]), (rep, i)
 
 
-@pytest.mark.parametrize("count,graph", [(3, "0"), (40, "0"), (3, "1")])  # argument table, device table, graph
-def test_group_back_to_back_calls_keep_their_own_tables(count, graph, monkeypatch):
+# argument table, device table, graph; then both tables in the persistent form
+@pytest.mark.parametrize("count,graph,persist", [(3, "0", "0"), (40, "0", "0"), (3, "1", "0"), (3, "0", "1"),
+                                                 (40, "0", "1")])
+def test_group_back_to_back_calls_keep_their_own_tables(count, graph, persist, monkeypatch):
     """Calls issued without synchronising in between, each with other n, X and Y:
     every output must be the one its own call asked for. With
     SPMM_GROUP_GRAPH=1 the captured graph's node is updated while the previous
     replay of the same executable may still be running."""
     monkeypatch.setenv("SPMM_GROUP_GRAPH", graph)
+    monkeypatch.setenv("SPMM_GROUP_PERSIST", persist)
     b = 16
     cases = [Case((3 + i % 4) * b, (5 + i % 3) * b, 64 + 8 * (i % 7), b, 0.3, w="f16", seed=300 + i)
              for i in range(count)]
@@ -179,3 +187,28 @@ def test_group_back_to_back_calls_keep_their_own_tables(count, graph, monkeypatc
             plans[i].run(Xs[i], Yr, n=ns[i])
             torch.cuda.synchronize()
             assert torch.equal(Ys[i][:, : ns[i]], Yr[:, : ns[i]]), i
+
+
+def test_group_persistent_form_large_and_small_calls_in_turn(monkeypatch):
+    """The persistent form's grid follows each call: a call with many units per
+    workgroup, one with fewer units than workgroups, then the first again,
+    unsynchronised, all equal to single launches."""
+    monkeypatch.setenv("SPMM_GROUP_PERSIST", "1")
+    b = 16
+    big = [Case(256 * b // 4, 128 * b // 4, 4096, b, 1 / 8, w="f16", seed=400 + i) for i in range(3)]
+    small = [Case(3 * b, 5 * b, 9, b, 0.5, w="f16", seed=410)]
+    g = spmm.Group(8)
+    calls = []
+    for cases in (big, small, big, small):
+        plans = [c.run_static()[0] for c in cases]
+        Xs = [c.device_inputs()[1] for c in cases]
+        Ys = [c.new_Y() for c in cases]
+        g.run(plans, Xs, Ys, ns=[c.n for c in cases])
+        calls.append((cases, plans, Xs, Ys))
+    torch.cuda.synchronize()
+    for cases, plans, Xs, Ys in calls:
+        for i, c in enumerate(cases):
+            Yr = c.new_Y()
+            plans[i].run(Xs[i], Yr, n=c.n)
+            torch.cuda.synchronize()
+            assert torch.equal(Ys[i][:, : c.n], Yr[:, : c.n]), i

@@ -59,8 +59,10 @@ def test_split_and_unsplit_plans_agree_and_variants_are_bitwise(monkeypatch):
     assert O.rel_fro(y_f64(outs[0], c), c.oracle()) <= 5e-3
 
 
+@pytest.mark.parametrize("persist", ["0", "1"])
 @pytest.mark.parametrize("count", [3, 40])
-def test_grouped_launch_with_split_rows_equals_single_launches(count):
+def test_grouped_launch_with_split_rows_equals_single_launches(count, persist, monkeypatch):
+    monkeypatch.setenv("SPMM_GROUP_PERSIST", persist)
     # rows are split when longer than max(64, 4 x mean) blocks: k spans 200+ block columns
     cases = [_skewed_case("power" if i % 2 else "concentrated", (40 + 7 * (i % 3)) * 16, (200 + 10 * (i % 4)) * 16,
                           50 + 37 * (i % 5), 1 / 16, w="f16", seed=40 + i) for i in range(count)]
