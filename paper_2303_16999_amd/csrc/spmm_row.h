@@ -525,9 +525,31 @@ __device__ __forceinline__ void row_tile(const RowProblem& p, int32_t r, int32_t
   row_store<YT, B, NS>(p, r, n0, lane, acc);
 }
 
+// Block row r and first column n0 of a wave in light unit lu. Where the
+// columns span more than one tile of 16*ns, a unit is two block rows times two
+// adjacent column tiles (waves 0, 1 on the first row, 2, 3 on the second): the
+// two waves of a row read the same W fragments, close in time, and a unit's
+// time is the longer of two rows rather than of four. Otherwise a unit is four
+// block rows, one per wave, on the one tile. Consecutive units step through
+// the rows first, so the waves resident on an XCD share a few column tiles of
+// X. False: no work for this wave (past the last row or column).
+__device__ __forceinline__ bool light_unit(const RowProblem& p, int32_t lu, int wave, int ns, int32_t& r, int32_t& n0) {
+  const int32_t tile = 16 * ns;
+  if (p.n > tile) {
+    const int32_t rg = (p.mb + 1) >> 1;
+    r = (lu % rg) * 2 + (wave >> 1);
+    n0 = ((lu / rg) * 2 + (wave & 1)) * tile;
+  } else {
+    const int32_t rg = (p.mb + kRowsPerWg - 1) / kRowsPerWg;
+    r = (lu % rg) * kRowsPerWg + wave;
+    n0 = (lu / rg) * tile;
+  }
+  return r < p.mb && n0 < p.n;
+}
+
 // Work units of a problem: heavy units first (one split row times a column
-// tile, so the longest units start early), then light units (4 block rows,
-// one per wave, times a column tile; split rows are skipped there).
+// tile, so the longest units start early), then light units (light_unit;
+// split rows are skipped there).
 __device__ __forceinline__ int32_t heavy_units(const RowProblem& p, int ns) {
   return p.num_heavy * ((p.n + 16 * ns - 1) / (16 * ns));
 }
@@ -549,20 +571,17 @@ __device__ __forceinline__ void row_unit(const RowProblem& p, int32_t unit, int 
     row_tile_b64<XT, WT, YT, NS>(p, unit % p.mb, wave, (unit / p.mb) * (16 * NS), lane);
     return;
   } else if constexpr (!SPLIT) {
-    const int32_t rgroups = (p.mb + kRowsPerWg - 1) / kRowsPerWg;
-    const int32_t r = (unit % rgroups) * kRowsPerWg + wave;
-    if (r >= p.mb) return;
-    row_tile_whole<XT, WT, YT, B, NS>(p, r, (unit / rgroups) * (16 * NS), lane);
+    int32_t r, n0;
+    if (!light_unit(p, unit, wave, NS, r, n0)) return;
+    row_tile_whole<XT, WT, YT, B, NS>(p, r, n0, lane);
     return;
   }
   const int32_t hus = heavy_units(p, NS);
   if (unit >= hus) {
-    const int32_t lu = unit - hus;
-    const int32_t rgroups = (p.mb + kRowsPerWg - 1) / kRowsPerWg;
-    const int32_t r = (lu % rgroups) * kRowsPerWg + wave;
-    if (r >= p.mb) return;
+    int32_t r, n0;
+    if (!light_unit(p, unit - hus, wave, NS, r, n0)) return;
     if (p.num_heavy && p.heavy_flag[r]) return;
-    row_tile<XT, WT, YT, B, NS>(p, r, (lu / rgroups) * (16 * NS), lane);
+    row_tile<XT, WT, YT, B, NS>(p, r, n0, lane);
     return;
   }
   if constexpr (SPLIT) {
@@ -648,7 +667,9 @@ inline RowProblem row_problem(const RunArgs& a, const int32_t* row_ptr, const in
 
 // Work units of a problem (light and heavy) for a column-tile variant.
 inline int64_t problem_units(int32_t mb, int64_t n, int32_t ns, int32_t num_heavy) {
-  return (ceil_div(mb, kRowsPerWg) + num_heavy) * ceil_div(n, 16 * ns);
+  const int64_t light =
+      n > 16 * ns ? ceil_div(mb, 2) * ceil_div(n, 32 * ns) : ceil_div(mb, kRowsPerWg) * ceil_div(n, 16 * ns);
+  return light + (int64_t)num_heavy * ceil_div(n, 16 * ns);
 }
 
 template <typename XT, typename WT, typename YT, int B>
