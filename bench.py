@@ -796,10 +796,10 @@ def mode_skew(args):
 
 def mode_train(args):
     """The three products of a training step of one block-sparse layer at
-    m = k = 8192, n = 4096, b = 16, FP16 (densities 1/16 and 1/4): forward
-    Y = (M o W) X, data gradient dX = (M o W)^T dY on the transposed plan,
-    weight gradient dW = (dY X^T) o M (FP32 blocks), next to the three dense
-    FP16 GEMMs of the same step."""
+    m = k = 8192, n = 4096, FP16 (b = 16 at densities 1/16 and 1/4; b = 8, 4
+    and 1 at 1/16): forward Y = (M o W) X, data gradient dX = (M o W)^T dY on
+    the transposed plan, weight gradient dW = (dY X^T) o M (FP32 blocks), next
+    to the three dense FP16 GEMMs of the same step."""
     import torch
     m = k = 8192
     n = 4096
@@ -815,11 +815,11 @@ def mode_train(args):
              "weight_grad": time_steps(lambda: torch.matmul(dYd, Xd.t(), out=dWd), args.steps, args.warmup)}
     del A, Xd, dYd, Yd, dXd, dWd
     torch.cuda.empty_cache()
-    for d in (1 / 16, 1 / 4):
-        prob = StaticProblem(m, k, n, 16, d, "f16", seed=0)
+    for b, d in ((16, 1 / 16), (16, 1 / 4), (8, 1 / 16), (4, 1 / 16), (1, 1 / 16)):
+        prob = StaticProblem(m, k, n, b, d, "f16", seed=0)
         dY = torch.randn((m, n), device="cuda", dtype=torch.float16, generator=g)
         dX = torch.empty((k, n), device="cuda", dtype=torch.float16)
-        G = torch.empty((prob.nnzb, 16, 16), device="cuda", dtype=torch.float32)
+        G = torch.empty((prob.nnzb, b, b), device="cuda", dtype=torch.float32)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         tp = prob.plan.transpose(n_hint=n)
@@ -828,7 +828,7 @@ def mode_train(args):
         steps = {"forward": prob.step, "data_grad": lambda: tp.run(dY, dX),
                  "weight_grad": lambda: prob.plan.sddmm(dY, prob.X, G)}
         flops = prob.flops()
-        rec = {"mode": "train", "m": m, "k": k, "n": n, "b": 16, "density": d, "nnz_blocks": prob.nnzb,
+        rec = {"mode": "train", "m": m, "k": k, "n": n, "b": b, "density": d, "nnz_blocks": prob.nnzb,
                "transpose_plan_ms": round(transpose_ms, 3)}
         total_s = total_d = 0.0
         for name, fn in steps.items():
@@ -838,7 +838,7 @@ def mode_train(args):
             rec[name] = {"ms": round(ms, 5), "tflops": round(flops / (ms * 1e-3) / 1e12, 3),
                          "dense_ms": round(dense[name], 5), "speedup_vs_dense": round(dense[name] / ms, 3)}
         # weight gradient: reads dY and X, writes the FP32 blocks
-        wg_bytes = 2.0 * (m + k) * n + 4.0 * prob.nnzb * 256
+        wg_bytes = 2.0 * (m + k) * n + 4.0 * prob.nnzb * b * b
         rec["weight_grad"]["alg_gbs"] = round(wg_bytes / (rec["weight_grad"]["ms"] * 1e-3) / 1e9, 1)
         rec["step_ms"] = round(total_s, 5)
         rec["dense_step_ms"] = round(total_d, 5)

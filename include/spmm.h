@@ -201,10 +201,10 @@ spmm_status_t spmm_plan_destroy(spmm_plan_t plan);
  * spmm_plan_set_values). dY is m x n with the plan's y dtype, X is k x n with
  * its x dtype (both FP16 or both BF16), row-major, leading dimensions lddy and
  * ldx; G is FP32 [nnzb][b][b] row-major on the device (caller-owned). Rows
- * and columns of edge blocks outside m x k come out 0. b = 16 or 32. FP32
- * accumulation over n.
- * Errors: INVALID_ARG (NULL, ld < n, alignment), UNSUPPORTED (block size,
- * dtypes), HIP. */
+ * and columns of edge blocks outside m x k come out 0. b = 1, 4, 8, 16 or
+ * 32. FP32 accumulation over n.
+ * Errors: INVALID_ARG (NULL, ld < n, alignment), UNSUPPORTED (block size
+ * 64, dtypes), HIP. */
 spmm_status_t spmm_plan_transpose(spmm_plan_t plan, const spmm_plan_opts* opts, spmm_plan_t* out);
 spmm_status_t spmm_sddmm(spmm_plan_t plan, int64_t n, const void* dY, int64_t lddy, const void* X, int64_t ldx,
                          float* G, void* stream);

@@ -152,7 +152,7 @@ spmm_status_t launch_spmm_row_grouped_persist(spmm_dtype_t xt, spmm_dtype_t yt, 
 // LDS bytes of a grouped launch with split rows; work units of one problem.
 unsigned group_split_lds(int32_t b);
 int64_t group_problem_units(int32_t mb, int64_t n, int32_t ns, int32_t num_heavy);
-// SDDMM (b = 16/32, FP16/BF16 dY and X): G[e] = dY[rows of r] X[rows of c]^T
+// SDDMM (b <= 32, FP16/BF16 dY and X): G[e] = dY[rows of r] X[rows of c]^T
 // for the tasks of a plan (block row, first entry, up to sddmm_task_blocks(b)
 // blocks each), FP32 output in CSR order.
 int32_t sddmm_task_blocks(int32_t b);

@@ -264,8 +264,8 @@ spmm_status_t run_dynamic_kernel(RunArgs& a, const int32_t* row_ptr, const int32
 // waves of a workgroup by the row-wise kernel for b = 16 (a long row would
 // otherwise be one wave's serial chain). SPMM_SPLIT=0 turns this off (for
 // comparisons).
-// SDDMM tasks of a plan with b = 16/32: (block row, first entry) for every run
-// of up to sddmm_task_blocks(b) consecutive blocks of one row.
+// SDDMM tasks of a plan: (block row, first entry) for every run of up to
+// sddmm_task_blocks(b) consecutive blocks of one row.
 static spmm_status_t build_sddmm_tasks(spmm_plan_s* p, const std::vector<int32_t>& rp) {
   const int32_t per = sddmm_task_blocks(p->b);
   std::vector<int32_t> tasks;
@@ -375,13 +375,14 @@ spmm_status_t spmm_plan_static(int64_t m, int64_t k, int32_t b, const uint8_t* b
     st = fail_hip(e, "mask upload");
   if (st == SPMM_OK) st = build_static_plan(mask_dev, (int32_t)mb, (int32_t)kb, p->geo, p->pb, s);
   if (st == SPMM_OK && (e = hipStreamSynchronize(s)) != hipSuccess) st = fail_hip(e, "plan build");
-  if (st == SPMM_OK && b >= 16) {
+  const bool sddmm = b <= 32 && (x == SPMM_F16 || x == SPMM_BF16);
+  if (st == SPMM_OK && (b >= 16 || sddmm)) {
     // host copy of the row pointers: long rows to split, SDDMM tasks
     std::vector<int32_t> rp((size_t)mb + 1);
     e = hipMemcpy(rp.data(), p->pb.row_ptr, sizeof(int32_t) * rp.size(), hipMemcpyDeviceToHost);
     if (e != hipSuccess) st = fail_hip(e, "row pointer download");
     if (st == SPMM_OK && b == 16 && x != SPMM_F32) st = classify_heavy_rows(p, rp);
-    if (st == SPMM_OK && b <= 32) st = build_sddmm_tasks(p, rp);
+    if (st == SPMM_OK && sddmm) st = build_sddmm_tasks(p, rp);
   }
   if (s) (void)hipStreamDestroy(s);
   if (mask_dev) (void)hipFree(mask_dev);

@@ -3,19 +3,24 @@
 // block (r, c) of a plan (the derivative of Y = (M o W) X with respect to the
 // kept weights; PopSparse, Sections 1 and 3).
 //
-// A task is (block row r, up to G consecutive blocks of that row in CSR
-// order). With few tasks, one runs on a workgroup of 4 waves and the
-// reduction over n, in steps of 64 (two 16x16x32 MFMAs), is cut into 4
+// A task is (block row r, up to a fixed number of consecutive blocks of that
+// row in CSR order). With few tasks, one runs on a workgroup of 4 waves and
+// the reduction over n, in steps of 64 (two 16x16x32 MFMAs), is cut into 4
 // contiguous ranges, one per wave; with many, each wave runs a task over all
 // of n.
 // The A operand is 16 rows of dY (lane (g, i): 8 consecutive n values of row
 // i, one 16-byte load), the B operand 16 rows of X (lane (g, j): 8 n values of
-// row j), so no transpose is needed; the A fragment is reused by the task's G
-// blocks, and each wave loads the next step's fragments before the MFMAs of
-// the current one. Split partial sums meet in LDS and are added in wave
-// order, so the result does not depend on timing. b = 32 blocks are 2 x 2
-// tiles of 16. Rows past m or k read as zero (buffer loads), and n values past
-// n are zeroed in registers, so edge blocks come out zero outside the matrix.
+// row j), so no transpose is needed; the A fragment is reused by all of the
+// task's blocks, and each wave loads the next step's fragments before the
+// MFMAs of the current one. Split partial sums meet in LDS and are added in
+// wave order, so the result does not depend on timing. b = 32 blocks are
+// 2 x 2 tiles of 16. For b = 1, 4 and 8 one MFMA computes 16 / b blocks of
+// the row at once: A holds the b rows of dY (rows b .. 15 zero), B the b rows
+// of X of each of the 16 / b blocks side by side, and the first b rows of the
+// 16 x 16 result are those blocks; the MFMA does more arithmetic than needed,
+// but the product is bound by its loads, which carry no padding.
+// Rows past m or k read as zero (buffer loads), and n values past n are zeroed
+// in registers, so edge blocks come out zero outside the matrix.
 // G is FP32, [nnzb][b][b] row-major, in the plan's CSR order.
 #include "common.h"
 
@@ -28,11 +33,17 @@ typedef float float4_t __attribute__((ext_vector_type(4)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr uint32_t kOOB = 0x80000000u;
-// Blocks of one row per task: 4 for b = 16 (8 measured no faster: the dY
+// MFMA column groups per task: 4 for b = 16 (8 measured no faster: the dY
 // fragment's reuse gains less than the halved occupancy costs), 2 for b = 32
-// (16% faster than 1 at m = k = 8192, n = 4096, d = 1/16).
+// (16% faster than 1 at m = k = 8192, n = 4096, d = 1/16), 4 for b < 16.
 template <int B>
-__host__ __device__ constexpr int task_blocks() { return B == 16 ? 4 : 2; }
+__host__ __device__ constexpr int task_groups() { return B == 32 ? 2 : 4; }
+// Blocks of one MFMA column group: 16 / b for b < 16, else one.
+template <int B>
+__host__ __device__ constexpr int group_blocks() { return B < 16 ? 16 / B : 1; }
+// Blocks of one row per task.
+template <int B>
+__host__ __device__ constexpr int task_blocks() { return task_groups<B>() * group_blocks<B>(); }
 
 struct SddmmParams {
   const int32_t* row_ptr;
@@ -96,14 +107,19 @@ __device__ __forceinline__ int32_t xcd_task(int32_t w, int32_t U) {
 }
 
 template <int B>
+__host__ __device__ constexpr int tiles() { return B < 16 ? 1 : B / 16; }
+
+template <int B>
 __host__ __device__ constexpr int sddmm_lds_bytes() {
-  return 4 * task_blocks<B>() * (B / 16) * (B / 16) * 64 * 16;
+  return 4 * task_groups<B>() * tiles<B>() * tiles<B>() * 64 * 16;
 }
 
 template <typename T, int B, bool SPLIT>
 __global__ __launch_bounds__(256) void k_sddmm(SddmmParams p) {
-  constexpr int H = B / 16;
-  constexpr int G = task_blocks<B>();  // blocks per task
+  constexpr int H = tiles<B>();
+  constexpr int G = task_groups<B>();   // MFMA column groups per task
+  constexpr int BG = group_blocks<B>();  // blocks per group
+  constexpr bool kSmall = B < 16;
   extern __shared__ float4_t sd_red[];      // [wave][G][H][H][64 lanes]
   const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int g = lane >> 4, j = lane & 15;
@@ -115,12 +131,21 @@ __global__ __launch_bounds__(256) void k_sddmm(SddmmParams p) {
     if (t >= p.num_tasks) return;
   }
   const int32_t r = sload(p.tasks, 2 * (int64_t)t), q0 = sload(p.tasks, 2 * (int64_t)t + 1);
-  const int32_t q_end = min(sload(p.row_ptr, r + 1), q0 + G);
+  const int32_t q_end = min(sload(p.row_ptr, r + 1), q0 + G * BG);
   __amdgpu_buffer_rsrc_t dyr = __builtin_amdgcn_make_buffer_rsrc((void*)p.dY, (short)0, (int)p.dy_bytes, 0x00020000);
   __amdgpu_buffer_rsrc_t xr = __builtin_amdgcn_make_buffer_rsrc((void*)p.X, (short)0, (int)p.x_bytes, 0x00020000);
+  // c[e]: block column of group e (b >= 16: wave-uniform; b < 16: of this
+  // lane's block j / b in the group); -1 past the task's last block
   int32_t c[G];
 #pragma unroll
-  for (int e = 0; e < G; ++e) c[e] = q0 + e < q_end ? sload(p.col_idx, q0 + e) : -1;
+  for (int e = 0; e < G; ++e) {
+    if constexpr (kSmall) {
+      const int32_t q = q0 + e * BG + j / B;
+      c[e] = q < q_end ? p.col_idx[q] : -1;
+    } else {
+      c[e] = q0 + e < q_end ? sload(p.col_idx, q0 + e) : -1;
+    }
+  }
   float4_t acc[G][H][H];
 #pragma unroll
   for (int e = 0; e < G; ++e)
@@ -134,17 +159,25 @@ __global__ __launch_bounds__(256) void k_sddmm(SddmmParams p) {
   // one whole 128-byte line per step.
   const int32_t steps = (p.n + 63) / 64, per = SPLIT ? (steps + 3) / 4 : steps;
   const int32_t s_lo = SPLIT ? min(steps, wave * per) : 0, s_hi = min(steps, s_lo + per);
+  // rows of dY and X this lane loads (past the matrix: zero)
+  const int64_t dy_row0 = kSmall ? (j < B ? (int64_t)r * B + j : (int64_t)p.m) : (int64_t)r * B + j;
+  auto x_row = [&](int e, int bb) -> int64_t {
+    if constexpr (kSmall) return c[e] >= 0 ? (int64_t)c[e] * B + (j % B) : (int64_t)p.k;
+    else return (int64_t)c[e] * B + 16 * bb + j;
+  };
   auto load = [&](int32_t s, u32x4 (&av)[2][H], u32x4 (&bv)[2][G][H]) {
 #pragma unroll
     for (int t = 0; t < 2; ++t) {
       const int32_t c0 = 64 * s + 16 * g + 8 * t;
 #pragma unroll
-      for (int a = 0; a < H; ++a) av[t][a] = load8(dyr, (int64_t)r * B + 16 * a + j, p.m, p.lddy, c0, p.n);
+      for (int a = 0; a < H; ++a) av[t][a] = load8(dyr, dy_row0 + 16 * a, p.m, p.lddy, c0, p.n);
 #pragma unroll
       for (int e = 0; e < G; ++e)
 #pragma unroll
-        for (int bb = 0; bb < H; ++bb)
-          bv[t][e][bb] = c[e] >= 0 ? load8(xr, (int64_t)c[e] * B + 16 * bb + j, p.k, p.ldx, c0, p.n) : u32x4{0, 0, 0, 0};
+        for (int bb = 0; bb < H; ++bb) {
+          if constexpr (kSmall) bv[t][e][bb] = load8(xr, x_row(e, bb), p.k, p.ldx, c0, p.n);
+          else bv[t][e][bb] = c[e] >= 0 ? load8(xr, x_row(e, bb), p.k, p.ldx, c0, p.n) : u32x4{0, 0, 0, 0};
+        }
     }
   };
   auto mma = [&](const u32x4 (&av)[2][H], const u32x4 (&bv)[2][G][H]) {
@@ -152,7 +185,7 @@ __global__ __launch_bounds__(256) void k_sddmm(SddmmParams p) {
     for (int t = 0; t < 2; ++t)
 #pragma unroll
       for (int e = 0; e < G; ++e) {
-        if (c[e] < 0) continue;
+        if (q0 + e * BG >= q_end) continue;
 #pragma unroll
         for (int bb = 0; bb < H; ++bb)
 #pragma unroll
@@ -180,18 +213,31 @@ __global__ __launch_bounds__(256) void k_sddmm(SddmmParams p) {
       }
     }
   }
+  // D[4g + i][j] of tile (a, bb) of group e: b >= 16, element (16a + 4g + i,
+  // 16bb + j) of block e; b < 16, element (4g + i, j % b) of block
+  // e * 16 / b + j / b, for rows 4g + i < b only
+  auto store = [&](int e, int a, int bb, const float4_t& v) {
+    if constexpr (kSmall) {
+      const int32_t q = q0 + e * BG + j / B;
+      if (q >= q_end || 4 * g >= B) return;
+      float* out = p.G + (int64_t)q * B * B;
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        if (4 * g + i < B) out[(4 * g + i) * B + (j % B)] = v[i];
+    } else {
+      if (q0 + e >= q_end) return;
+      float* out = p.G + (int64_t)(q0 + e) * B * B;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) out[(16 * a + 4 * g + i) * B + 16 * bb + j] = v[i];
+    }
+  };
   if constexpr (!SPLIT) {
 #pragma unroll
-    for (int e = 0; e < G; ++e) {
-      if (q0 + e >= q_end) break;
-      float* out = p.G + (int64_t)(q0 + e) * B * B;
+    for (int e = 0; e < G; ++e)
 #pragma unroll
       for (int a = 0; a < H; ++a)
 #pragma unroll
-        for (int bb = 0; bb < H; ++bb)
-#pragma unroll
-          for (int i = 0; i < 4; ++i) out[(16 * a + 4 * g + i) * B + 16 * bb + j] = acc[e][a][bb][i];
-    }
+        for (int bb = 0; bb < H; ++bb) store(e, a, bb, acc[e][a][bb]);
     return;
   }
 #pragma unroll
@@ -201,11 +247,8 @@ __global__ __launch_bounds__(256) void k_sddmm(SddmmParams p) {
 #pragma unroll
       for (int bb = 0; bb < H; ++bb) sd_red[(((wave * G + e) * H + a) * H + bb) * 64 + lane] = acc[e][a][bb];
   __syncthreads();
-  // wave w finishes blocks w, w + 4, ...: D[4g + i][j] of tile (a, bb) is
-  // element (16a + 4g + i, 16bb + j) of the block
+  // wave w finishes groups w, w + 4, ...
   for (int e = wave; e < G; e += 4) {
-    if (q0 + e >= q_end) break;
-    float* out = p.G + (int64_t)(q0 + e) * B * B;
 #pragma unroll
     for (int a = 0; a < H; ++a)
 #pragma unroll
@@ -213,8 +256,7 @@ __global__ __launch_bounds__(256) void k_sddmm(SddmmParams p) {
         float4_t v = sd_red[(((0 * G + e) * H + a) * H + bb) * 64 + lane];
 #pragma unroll
         for (int w = 1; w < 4; ++w) v += sd_red[(((w * G + e) * H + a) * H + bb) * 64 + lane];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) out[(16 * a + 4 * g + i) * B + 16 * bb + j] = v[i];
+        store(e, a, bb, v);
       }
   }
 }
@@ -231,11 +273,17 @@ spmm_status_t launch_t(const SddmmParams& p, int32_t b, hipStream_t s) {
   }();
   if (p.num_tasks <= 32 * cus) {
     const unsigned grid = (unsigned)p.num_tasks;
-    if (b == 16) hipLaunchKernelGGL((k_sddmm<T, 16, true>), dim3(grid), dim3(256), sddmm_lds_bytes<16>(), s, p);
+    if (b == 1) hipLaunchKernelGGL((k_sddmm<T, 1, true>), dim3(grid), dim3(256), sddmm_lds_bytes<1>(), s, p);
+    else if (b == 4) hipLaunchKernelGGL((k_sddmm<T, 4, true>), dim3(grid), dim3(256), sddmm_lds_bytes<4>(), s, p);
+    else if (b == 8) hipLaunchKernelGGL((k_sddmm<T, 8, true>), dim3(grid), dim3(256), sddmm_lds_bytes<8>(), s, p);
+    else if (b == 16) hipLaunchKernelGGL((k_sddmm<T, 16, true>), dim3(grid), dim3(256), sddmm_lds_bytes<16>(), s, p);
     else hipLaunchKernelGGL((k_sddmm<T, 32, true>), dim3(grid), dim3(256), sddmm_lds_bytes<32>(), s, p);
   } else {
     const unsigned grid = (unsigned)ceil_div(p.num_tasks, 4);
-    if (b == 16) hipLaunchKernelGGL((k_sddmm<T, 16, false>), dim3(grid), dim3(256), 0, s, p);
+    if (b == 1) hipLaunchKernelGGL((k_sddmm<T, 1, false>), dim3(grid), dim3(256), 0, s, p);
+    else if (b == 4) hipLaunchKernelGGL((k_sddmm<T, 4, false>), dim3(grid), dim3(256), 0, s, p);
+    else if (b == 8) hipLaunchKernelGGL((k_sddmm<T, 8, false>), dim3(grid), dim3(256), 0, s, p);
+    else if (b == 16) hipLaunchKernelGGL((k_sddmm<T, 16, false>), dim3(grid), dim3(256), 0, s, p);
     else hipLaunchKernelGGL((k_sddmm<T, 32, false>), dim3(grid), dim3(256), 0, s, p);
   }
   SPMM_HIP(hipGetLastError());
@@ -244,12 +292,21 @@ spmm_status_t launch_t(const SddmmParams& p, int32_t b, hipStream_t s) {
 
 }  // namespace
 
-int32_t sddmm_task_blocks(int32_t b) { return b == 16 ? task_blocks<16>() : task_blocks<32>(); }
+int32_t sddmm_task_blocks(int32_t b) {
+  switch (b) {
+    case 1: return task_blocks<1>();
+    case 4: return task_blocks<4>();
+    case 8: return task_blocks<8>();
+    case 16: return task_blocks<16>();
+    default: return task_blocks<32>();
+  }
+}
 
 spmm_status_t launch_sddmm(spmm_dtype_t t, int32_t b, const int32_t* row_ptr, const int32_t* col_idx,
                            const int32_t* tasks, int32_t num_tasks, int64_t m, int64_t k, int64_t n, const void* dY,
                            int64_t lddy, const void* X, int64_t ldx, float* G, hipStream_t s) {
-  if (b != 16 && b != 32) return fail(SPMM_ERR_UNSUPPORTED, "SDDMM handles block sizes 16 and 32");
+  if (b != 1 && b != 4 && b != 8 && b != 16 && b != 32)
+    return fail(SPMM_ERR_UNSUPPORTED, "SDDMM handles block sizes 1, 4, 8, 16 and 32");
   if (num_tasks == 0 || n == 0) return SPMM_OK;
   const int64_t dyb = m * lddy * 2, xb = k * ldx * 2;
   if (dyb >= (int64_t)INT32_MAX || xb >= (int64_t)INT32_MAX)

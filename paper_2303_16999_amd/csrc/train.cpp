@@ -109,7 +109,7 @@ spmm_status_t spmm_sddmm(spmm_plan_t p, int64_t n, const void* dY, int64_t lddy,
   clear_error();
   if (!p) return fail(SPMM_ERR_INVALID_ARG, "plan is NULL");
   if (n < 0) return fail(SPMM_ERR_INVALID_ARG, "n is negative");
-  if (p->b != 16 && p->b != 32) return fail(SPMM_ERR_UNSUPPORTED, "SDDMM handles block sizes 16 and 32");
+  if (p->b > 32) return fail(SPMM_ERR_UNSUPPORTED, "SDDMM handles block sizes 1, 4, 8, 16 and 32");
   if (p->x != p->y || (p->x != SPMM_F16 && p->x != SPMM_BF16))
     return fail(SPMM_ERR_UNSUPPORTED, "SDDMM needs a plan with FP16 or BF16 X and Y");
   if (p->nnzb > 0 && !G) return fail(SPMM_ERR_INVALID_ARG, "G is NULL");

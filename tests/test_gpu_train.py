@@ -127,7 +127,7 @@ def _sddmm(c, plan, dY, X, n=None):
     return G[:nnzb].cpu().numpy().astype(np.float64)
 
 
-@pytest.mark.parametrize("b", [16, 32])
+@pytest.mark.parametrize("b", [1, 4, 8, 16, 32])
 @pytest.mark.parametrize("dt", ["f16", "bf16"])
 @pytest.mark.parametrize("n", [1, 31, 77, 300])
 def test_sddmm_matches_oracle(b, dt, n):
@@ -148,7 +148,7 @@ def test_sddmm_matches_oracle(b, dt, n):
             assert not G[e, :, kk:].any()
 
 
-@pytest.mark.parametrize("b", [16, 32])
+@pytest.mark.parametrize("b", [1, 4, 8, 16, 32])
 def test_sddmm_integer_data_bit_exact(b):
     c = Case(17 * b + 7, 19 * b + 2, 250, b, 1 / 4, w="bf16", seed=70, integer=True)
     plan = _plan(c)
@@ -171,6 +171,44 @@ def test_sddmm_long_rows_and_dense_blocks():
     G = _sddmm(c, plan, dY, X)
     ref = TR.sddmm_blockwise(c.m, c.k, b, c.rows, c.cols, dY64, c.X64)
     assert O.rel_fro(G, ref) <= 1e-5
+
+
+@pytest.mark.parametrize("b", [1, 4, 8])
+def test_sddmm_small_blocks_long_rows_ragged(b):
+    # rows of several tasks (a task holds 64 / 16 / 8 blocks for b = 1 / 4 / 8),
+    # a full row, partly filled MFMA groups, ragged m, k and n
+    mb, kb = 9, 300 // b + 7
+    mask = synth.block_mask(mb, kb, 0.35, 130 + b)
+    mask[4, :] = 1
+    mask[6, :] = 0
+    c = Case(mb * b - (b > 1), kb * b - (b // 2), 203, b, 0.0, w="f16", seed=131 + b, mask=mask)
+    plan = _plan(c)
+    _, X, _ = c.device_inputs()
+    dY, dY64 = _dY(c, 132 + b)
+    G = _sddmm(c, plan, dY, X)
+    ref = TR.sddmm_blockwise(c.m, c.k, b, c.rows, c.cols, dY64, c.X64)
+    assert O.rel_fro(G, ref) <= 1e-5
+    assert np.abs(G - ref).max() <= 1e-5 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("b", [1, 4, 8])
+def test_sddmm_small_blocks_many_tasks_sampled(b):
+    # more than 32 tasks per compute unit (one task per wave over all of n), sampled blocks
+    m = k = 4096
+    c = Case(m, k, 64, b, {1: 1 / 8, 4: 1 / 4, 8: 1 / 3}[b], w="bf16", seed=140 + b)
+    plan = _plan(c)
+    nnzb = plan.info()["nnzb"]
+    assert nnzb / {1: 64, 4: 16, 8: 8}[b] > 32 * 256
+    _, X, _ = c.device_inputs()
+    dY, dY64 = _dY(c, 141 + b)
+    G = torch.empty((nnzb, b, b), dtype=torch.float32, device="cuda")
+    plan.sddmm(dY, X, G)
+    torch.cuda.synchronize()
+    pick = np.random.default_rng(142).choice(nnzb, 3000, replace=False)
+    got = G[torch.from_numpy(pick).cuda()].cpu().numpy().astype(np.float64)
+    ref = TR.sddmm_blockwise(c.m, c.k, b, c.rows[pick], c.cols[pick], dY64, c.X64)
+    assert O.rel_fro(got, ref) <= 1e-5
+    assert np.abs(got - ref).max() <= 1e-5 * np.abs(ref).max()
 
 
 def test_sddmm_n_zero_and_empty_plan():
@@ -197,9 +235,10 @@ def test_sddmm_with_fp8_weights():
     assert O.rel_fro(G, TR.sddmm_blockwise(c.m, c.k, 16, c.rows, c.cols, dY64, c.X64)) <= 1e-5
 
 
-@pytest.mark.parametrize("b,w,x,y", [(8, "f16", "f16", "f16"), (16, "f32", "f32", "f32"), (16, "f16", "f16", "f32")])
+@pytest.mark.parametrize("b,w,x,y", [(64, "f16", "f16", "f16"), (16, "f32", "f32", "f32"), (16, "f16", "f16", "f32"),
+                                     (4, "f32", "f32", "f32")])
 def test_sddmm_rejects_unsupported_plans(b, w, x, y):
-    c = Case(64, 64, 32, b, 1 / 2, w=w, x=x, y=y, seed=95)
+    c = Case(128, 128, 32, b, 1 / 2, w=w, x=x, y=y, seed=95)
     plan = _plan(c)
     G = torch.zeros((plan.info()["nnzb"], b, b), device="cuda")
     X = torch.zeros((c.k, 32), dtype=spmm.torch_dtype(spmm.DTYPE_CODES[x]), device="cuda")
