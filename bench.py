@@ -543,6 +543,21 @@ def mlp_plans(layers=8, d_in=4096, d_hid=16384, b=16, d=1 / 16, seed=0):
     return plans, dims, relu
 
 
+def pretune(plans, dims, max_n=2048):
+    """Runs the autotuner on every plan for each n class 1 .. max_n, so grouped
+    launches and the serving loop (which look up tuned variants but never
+    measure) run on measured tile choices."""
+    import torch
+    n = 1
+    while n <= max_n:
+        for l, p in enumerate(plans):
+            X = torch.randn((dims[l], -(-n // 8) * 8), device="cuda").half()
+            Y = torch.empty((dims[l + 1], -(-n // 8) * 8), device="cuda", dtype=torch.float16)
+            p.autotune(X, Y, n=n)
+        n *= 2
+    torch.cuda.synchronize()
+
+
 def run_trace(srv, arrivals, ns, x_host, y_hosts, t_start=None):
     """Open-loop driver: submit request i at arrivals[i] (seconds from start), poll
     completions; returns the completion records in id order."""
@@ -577,12 +592,14 @@ def _view(buf, n, rows=4096):
 
 def mode_serve(args):
     """Serving: 8-layer sparse MLP (4096 -> 16384 -> 4096 per layer, b = 16,
-    density 1/16, FP16 weights resident), Poisson arrivals, n ~ log-uniform
-    [1, 2048]; continuous batching through grouped launches against the plain
-    one-request-at-a-time path on the same trace."""
+    density 1/16, FP16 weights resident, tile variants tuned per n class),
+    Poisson arrivals, n ~ log-uniform [1, 2048]; continuous batching through
+    grouped launches against the plain one-request-at-a-time path on the same
+    trace."""
     import torch
     from paper_2303_16999_amd import spmm, synth
     plans, dims, relu = mlp_plans()
+    pretune(plans, dims)
     flop_per_token = sum(2.0 * dims[l] * dims[l + 1] / 16 for l in range(len(dims) - 1))
     # pinned host buffers in the device layout, so request copies are plain DMA
     x_host = torch.empty(4096 * 2048, dtype=torch.float16, pin_memory=True)
@@ -662,13 +679,14 @@ def mode_serve(args):
 
 
 def mode_group(args):
-    """The 16 serving matrices with n_i ~ log-uniform [1, 2048]: one grouped
-    launch in each of its two forms (one workgroup per unit, launched directly;
+    """The 16 serving matrices (tile variants tuned per n class) with n_i ~
+    log-uniform [1, 2048]: one grouped launch in each of its two forms (one workgroup per unit, launched directly;
     persistent workgroups walking the units on a static per-XCD schedule) against 16
     separate launches."""
     import torch
     from paper_2303_16999_amd import spmm, synth
     plans, dims, relu = mlp_plans()
+    pretune(plans, dims)
     g = synth.rng(21)
     for trial in range(3):
         ns = [int(v) for v in np.clip(np.floor(np.exp(g.uniform(0, math.log(2049), size=16))), 1, 2048)]

@@ -76,10 +76,17 @@ typedef enum { SPMM_F32 = 0, SPMM_F16 = 1, SPMM_BF16 = 2, SPMM_FP8_E4M3 = 3 } sp
  *               group per panel);
  *   n_hint      expected batch size n, used only to choose group_rows;
  *   variant     tile variant of the compute kernel (0 = choose: the
- *               autotuner's result for this n if there is one, else a rule on
- *               n). For b = 16/32 with 16-bit X: 2, 4 or 8 column tiles of 16
- *               per wave; for b = 1/4/8 with 16-bit X: 4 or 8 columns per
- *               lane. Other kernels have one variant and ignore it. */
+ *               autotuner's result for this n class if there is one, else a
+ *               measurement on the first run, else a rule on n; see the
+ *               autotuner below). A variant is ns + 256 * form. ns, the tile
+ *               width: for b = 16/32 with 16-bit X, 2, 4 or 8 column tiles of
+ *               16 per wave; for b = 1/4/8 with 16-bit X, 4 or 8 columns per
+ *               lane; 0 = the rule on n. form: 0 = the rule, 1 = the plain
+ *               kernel, 2 = the plan's other kernel where it has one (the
+ *               software-pipelined row kernel for b = 16/32 with W in the X
+ *               type and no split rows; the LDS-staged kernel for b = 4 with W
+ *               in the X type), else the plain one. Other kernels have one
+ *               variant and ignore it. */
 typedef struct {
   int32_t group_rows;
   int32_t num_panels;
@@ -152,7 +159,11 @@ spmm_status_t spmm_plan_set_values(spmm_plan_t plan, const void* values_dev,
                                    const float* block_scales_dev, void* stream);
 
 /* Y = (M o W) * X with the plan's pattern and values. X: k x n of dtype x,
- * Y: m x n of dtype y. n = 0 is a no-op returning OK.
+ * Y: m x n of dtype y. n = 0 is a no-op returning OK. The first run of a plan
+ * whose variant is 0, for an n class with no tuned entry, runs the autotuner
+ * on these operands (spmm_autotune_static; it synchronises `stream`), unless
+ * SPMM_AUTOTUNE=0 or `stream` is capturing a graph: then the rule on n runs.
+ * Y holds the product either way.
  * Errors: INVALID_ARG (values not set, NULL, ld < n, alignment), HIP. */
 spmm_status_t spmm_run_static(spmm_plan_t plan, int64_t n, const void* X, int64_t ldx,
                               void* Y, int64_t ldy, void* stream);
@@ -224,19 +235,33 @@ spmm_status_t spmm_speedup_model(int64_t m, double density, int32_t b, double* s
 /* ------------------------------------------------------------------ autotuner
  * The paper's planner fixes the partition of (m, k, n) from the matrix sizes
  * and the density ahead of time (Appendix A); the analogous choice here is the
- * compute kernel's tile variant, and it is made by measurement.
- * spmm_autotune_static runs every variant of the
- * plan's kernel on the caller's X and Y (n columns; Y receives the result),
+ * compute kernel's variant (tile width and kernel form), and it is made by
+ * measurement. spmm_autotune_static runs every candidate variant of the
+ * plan's kernels on the caller's X and Y (n columns; Y receives the result),
  * times each with HIP events on `stream` (2 warm-up and 5 timed runs), and
  * records the fastest for n's size class (the power of two at or above n) in
- * the plan and in a process-wide table keyed by (b, dtypes, density class, n
- * class). Plans created later with the same key and variant 0 use that table.
+ * the plan and in a process-wide table keyed by (b, dtypes, density class =
+ * round(-log2 d), n class). Plans with variant 0 use that table. With the
+ * environment variable SPMM_AUTOTUNE_CACHE naming a file, the table starts
+ * from that file when it was written for the same device (architecture and
+ * CU count) and HIP runtime, and every new entry rewrites it (JSON, through a
+ * temporary file and a rename); an unreadable file is ignored.
  * Synchronises `stream`. *variant_out (may be NULL) receives the choice;
- * times_ms_out (may be NULL) receives the mean time of variants 2, 4 and 8,
- * in that order, -1 for a variant the kernel does not have.
- * Errors: as spmm_run_static. */
+ * times_ms_out (may be NULL) receives, for tile widths 2, 4 and 8 in that
+ * order, the best mean time over the kernel forms with that width, -1 where
+ * there is none.
+ * spmm_autotune_static_all: the same, reporting every candidate: variants and
+ * times_ms (capacity >= 8 entries each) receive *count candidates and their
+ * mean times, *best (may be NULL) the choice.
+ * spmm_plan_variant: the variant a run with n columns uses now (0 = not tuned
+ * for n's class: the next spmm_run_static tunes, or the rule on n).
+ * Errors: as spmm_run_static; INVALID_ARG for capacity < 8 or NULL outputs. */
 spmm_status_t spmm_autotune_static(spmm_plan_t plan, int64_t n, const void* X, int64_t ldx, void* Y,
                                    int64_t ldy, void* stream, int32_t* variant_out, float* times_ms_out);
+spmm_status_t spmm_autotune_static_all(spmm_plan_t plan, int64_t n, const void* X, int64_t ldx, void* Y,
+                                       int64_t ldy, void* stream, int32_t capacity, int32_t* variants,
+                                       float* times_ms, int32_t* count, int32_t* best);
+spmm_status_t spmm_plan_variant(spmm_plan_t plan, int64_t n, int32_t* variant);
 
 /* ------------------------------------------------------------------ grouped launch
  * Many static products with different plans, column counts, X and Y in one

@@ -164,6 +164,9 @@ spmm_status_t launch_sddmm(spmm_dtype_t t, int32_t b, const int32_t* row_ptr, co
 // small_lds_rows_per_wave; small_lds_preferred says whether it runs instead
 // of the kernel below (by block size, dtypes and density).
 bool small_lds_preferred(int32_t b, spmm_dtype_t w, spmm_dtype_t x, int64_t nnz, int64_t mb, int64_t kb);
+// Whether the LDS-staged kernel handles the plan at all (b = 4, W in the
+// 16-bit X type).
+bool small_lds_eligible(int32_t b, spmm_dtype_t w, spmm_dtype_t x);
 int32_t small_lds_rows_per_wave(int32_t b, int32_t mb, int64_t n, int num_cus);
 spmm_status_t launch_spmm_small_lds(const RunArgs& a, const int32_t* row_ptr, const int32_t* col_idx, int32_t rw,
                                     hipStream_t stream);

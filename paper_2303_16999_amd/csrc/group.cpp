@@ -192,7 +192,7 @@ spmm_status_t spmm_group_run(spmm_group_t g, int32_t count, const spmm_plan_t* p
     if (n[i] == 0) continue;
     const spmm_plan_s* p = plans[i];
     // the tuned variant if any, else the rule on n
-    int32_t ns = plan_variant(p, n[i]);
+    int32_t ns = variant_ns(plan_variant(p, n[i]));
     if (ns != 2 && ns != 4 && ns != 8) ns = default_ns(n[i]);
     RunArgs a{};
     a.plan.m = (int32_t)p->m;

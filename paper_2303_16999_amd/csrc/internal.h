@@ -3,6 +3,9 @@
 // serve.cpp: the serving loop).
 #pragma once
 
+#include <map>
+#include <tuple>
+
 #include "common.h"
 
 struct spmm_plan_s {
@@ -17,11 +20,11 @@ struct spmm_plan_s {
   bool has_values = false;
   int device = 0;
   int32_t variant_opt = 0;     // fixed tile variant from the options, 0 = choose
-  int8_t tuned[32] = {};       // autotuned variant per n class, 0 = none
+  int32_t tuned[32] = {};      // autotuned variant per n class, 0 = none
   int32_t num_heavy = 0;       // block rows the row-wise kernel splits over four waves
   uint8_t* heavy_flag = nullptr;   // device [mb]
   int32_t* heavy_rows = nullptr;   // device [num_heavy]
-  int32_t* sddmm_tasks = nullptr;  // device [sddmm_num_tasks][2] (b = 16/32)
+  int32_t* sddmm_tasks = nullptr;  // device [sddmm_num_tasks][2] (16-bit X, b <= 32)
   int32_t sddmm_num_tasks = 0;
   int32_t ell_width = 0;           // plans built from blocked-ELL: slots per block row
   int32_t* ell_slot = nullptr;     // device [nnzb]: ELL slot (row * ell_width + slot) of each CSR entry
@@ -31,6 +34,16 @@ namespace spmm {
 
 // n class of the autotuner: the exponent of the power of two at or above n.
 int n_class(int64_t n);
+// A tile variant: column tiles of 16 per wave (b >= 16) or columns per lane
+// (b < 16) in the low byte, 0 = the rule on n; above it the kernel form: 0 =
+// the rule, 1 = the plain kernel, 2 = the other form where the plan has one
+// (the software-pipelined row kernel for b = 16/32 with W in the X type and
+// no split rows; the LDS-staged kernel for b = 4 with W in the X type).
+constexpr int kFormShift = 8;
+inline int32_t variant_ns(int32_t v) { return v & 0xff; }
+inline int32_t variant_form(int32_t v) { return v >> kFormShift; }
+inline int32_t make_variant(int32_t ns, int32_t form) { return ns | (form << kFormShift); }
+bool valid_variant(int32_t b, int32_t v);
 // Tile variant for a run of `p` with n columns: fixed option, else the plan's
 // tuned value, else the process-wide tuned table, else the rule on n.
 int32_t plan_variant(const spmm_plan_s* p, int64_t n);
@@ -44,5 +57,14 @@ spmm_status_t run_dynamic_kernel(RunArgs& a, const int32_t* row_ptr, const int32
 spmm_status_t check_dense(const void* p, int64_t ld, int64_t n, int elem, const char* name);
 spmm_status_t check_device(int device);
 int32_t default_ns(int64_t n);
+
+// Autotuner table persisted as JSON (tune_cache.cpp). Key: (b, w, x, y,
+// density class, n class). load fills `table` from `path` when the file was
+// written for this device and HIP runtime (else leaves it unchanged); save
+// writes the whole table (a temporary file renamed over `path`). Both return
+// false on an unreadable or unwritable file and never fail a product.
+using TuneKey = std::tuple<int, int, int, int, int, int>;
+bool tune_cache_load(const char* path, std::map<TuneKey, int32_t>& table);
+bool tune_cache_save(const char* path, const std::map<TuneKey, int32_t>& table);
 
 }  // namespace spmm

@@ -182,10 +182,33 @@ bool plan_uses_row_kernel(const spmm_plan_s* p) {
   return p->b >= 16 && (p->x == SPMM_F16 || p->x == SPMM_BF16);
 }
 
-// Process-wide autotuner table: (b, w, x, y, density class, n class) -> variant.
-using TuneKey = std::tuple<int, int, int, int, int, int>;
+bool valid_variant(int32_t b, int32_t v) {
+  if (v == 0) return true;
+  if (v < 0) return false;
+  const int32_t ns = variant_ns(v), form = variant_form(v);
+  if (form > 2 || (ns != 0 && ns != 2 && ns != 4 && ns != 8)) return false;
+  return !(ns == 2 && b < 16);
+}
+
+// Process-wide autotuner table: (b, w, x, y, density class, n class) ->
+// variant. With SPMM_AUTOTUNE_CACHE naming a file, the table starts from that
+// file (if it was written for this device and HIP runtime) and every new
+// entry rewrites it.
 static std::mutex g_tune_mu;
 static std::map<TuneKey, int32_t> g_tune;
+static bool g_tune_loaded = false;
+
+static const char* tune_cache_path() {
+  const char* e = getenv("SPMM_AUTOTUNE_CACHE");
+  return e && *e ? e : nullptr;
+}
+
+// (call with g_tune_mu held)
+static void tune_table_load_once() {
+  if (g_tune_loaded) return;
+  g_tune_loaded = true;
+  if (const char* path = tune_cache_path()) (void)tune_cache_load(path, g_tune);
+}
 
 static TuneKey tune_key(const spmm_plan_s* p, int64_t n) {
   const double cells = (double)p->mb * (double)p->kb;
@@ -196,15 +219,18 @@ static TuneKey tune_key(const spmm_plan_s* p, int64_t n) {
 
 static void tune_table_put(const spmm_plan_s* p, int64_t n, int32_t v) {
   std::lock_guard<std::mutex> lk(g_tune_mu);
+  tune_table_load_once();
   g_tune[tune_key(p, n)] = v;
+  if (const char* path = tune_cache_path()) (void)tune_cache_save(path, g_tune);
 }
 
 int32_t plan_variant(const spmm_plan_s* p, int64_t n) {
   if (p->variant_opt) return p->variant_opt;
-  const int8_t t = p->tuned[n_class(n)];
+  const int32_t t = p->tuned[n_class(n)];
   if (t) return t;
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_table_load_once();
     auto it = g_tune.find(tune_key(p, n));
     if (it != g_tune.end()) return it->second;
   }
@@ -228,20 +254,27 @@ spmm_status_t run_plan(const spmm_plan_s* p, int64_t n, const void* X, int64_t l
   a.status = nullptr;
   a.nnz = p->nnzb;
   a.relu = relu;
+  // a variant's kernel form applies where the plan has that form, unless the
+  // environment forces one (SPMM_SMALL_LDS, SPMM_ROW_PP)
+  const int32_t form = variant_form(variant);
   if (p->b < 16) {
-    if (small_lds_preferred(p->b, p->w, p->x, p->nnzb, p->mb, p->kb))
+    bool lds = small_lds_preferred(p->b, p->w, p->x, p->nnzb, p->mb, p->kb);
+    if (form && small_lds_eligible(p->b, p->w, p->x) && !getenv("SPMM_SMALL_LDS")) lds = form == 2;
+    if (lds)
       return launch_spmm_small_lds(a, p->pb.row_ptr, p->pb.col_idx,
                                    small_lds_rows_per_wave(p->b, p->mb, n, device_cu_count()), stream);
-    a.ns = variant;  // 0: the kernel's rule on n
+    a.ns = variant_ns(variant);  // 0: the kernel's rule on n
     return launch_spmm_small(a, p->pb.row_ptr, p->pb.col_idx, stream);
   }
   if (plan_uses_row_kernel(p)) {
-    a.ns = variant ? variant : default_ns(n);
+    a.ns = variant_ns(variant) ? variant_ns(variant) : default_ns(n);
     a.num_heavy = p->num_heavy;
     a.heavy_flag = p->heavy_flag;
     a.heavy_rows = p->heavy_rows;
-    if (p->w == p->x && p->num_heavy == 0 && row_pp_preferred(p->b, p->mb, n, a.ns, p->nnzb, device_cu_count()))
-      return launch_spmm_row_pp(a, p->pb.row_ptr, p->pb.col_idx, stream);
+    const bool pp_ok = p->w == p->x && p->num_heavy == 0 && p->b <= 32;
+    bool pp = pp_ok && row_pp_preferred(p->b, p->mb, n, a.ns, p->nnzb, device_cu_count());
+    if (form && pp_ok && !getenv("SPMM_ROW_PP")) pp = form == 2;
+    if (pp) return launch_spmm_row_pp(a, p->pb.row_ptr, p->pb.col_idx, stream);
     return launch_spmm_row(a, p->pb.row_ptr, p->pb.col_idx, stream);
   }
   return launch_spmm_row_f32(a, p->pb.row_ptr, p->pb.col_idx, stream);
@@ -346,9 +379,8 @@ spmm_status_t spmm_plan_static(int64_t m, int64_t k, int32_t b, const uint8_t* b
   if (nnzb > INT32_MAX / 2) return fail(SPMM_ERR_UNSUPPORTED, "too many nonzero blocks");
   if (opts && (opts->group_rows < 0 || opts->num_panels < 0))
     return fail(SPMM_ERR_INVALID_ARG, "negative plan option");
-  if (opts && opts->variant && opts->variant != 2 && opts->variant != 4 && opts->variant != 8)
-    return fail(SPMM_ERR_INVALID_ARG, "variant must be 0, 2, 4 or 8");
-  if (opts && opts->variant == 2 && b < 16) return fail(SPMM_ERR_INVALID_ARG, "variant 2 needs b = 16 or 32");
+  if (opts && !valid_variant(b, opts->variant))
+    return fail(SPMM_ERR_INVALID_ARG, "variant must be 0 or (2, 4, 8 or 0) + 256 x (0, 1 or 2); 2 needs b >= 16");
 
   spmm_plan_s* p = new (std::nothrow) spmm_plan_s;
   if (!p) return fail(SPMM_ERR_OOM, "host allocation failed");
@@ -416,49 +448,34 @@ spmm_status_t spmm_plan_set_values(spmm_plan_t p, const void* values_dev, const 
   return SPMM_OK;
 }
 
-spmm_status_t spmm_run_static(spmm_plan_t p, int64_t n, const void* X, int64_t ldx, void* Y, int64_t ldy,
-                              void* stream) {
-  clear_error();
-  if (!p) return fail(SPMM_ERR_INVALID_ARG, "plan is NULL");
-  if (n < 0) return fail(SPMM_ERR_INVALID_ARG, "n is negative");
-  if (n == 0) return SPMM_OK;
-  if (n > INT32_MAX / 2) return fail(SPMM_ERR_UNSUPPORTED, "n too large");
-  if (!p->has_values) return fail(SPMM_ERR_INVALID_ARG, "values were not set on this plan");
-  spmm_status_t st;
-  if ((st = check_dense(X, ldx, n, dtype_bytes(p->x), "X")) != SPMM_OK) return st;
-  if ((st = check_dense(Y, ldy, n, dtype_bytes(p->y), "Y")) != SPMM_OK) return st;
-  if ((st = check_device(p->device)) != SPMM_OK) return st;
-  return run_plan(p, n, X, ldx, Y, ldy, plan_variant(p, n), false, (hipStream_t)stream);
-}
-
-// Candidate tile variants of the plan's kernel (0-terminated).
-static void plan_candidates(const spmm_plan_s* p, int32_t (&c)[4]) {
-  c[0] = c[1] = c[2] = c[3] = 0;
+// Candidate variants of the plan's kernels (tile widths times forms).
+static int plan_candidates(const spmm_plan_s* p, int32_t (&c)[8]) {
+  int k = 0;
   if (plan_uses_row_kernel(p)) {
-    c[0] = 2; c[1] = 4; c[2] = 8;
+    for (int32_t ns : {2, 4, 8}) c[k++] = make_variant(ns, 1);
+    if (p->w == p->x && p->num_heavy == 0 && p->b <= 32)
+      for (int32_t ns : {2, 4, 8}) c[k++] = make_variant(ns, 2);
   } else if (p->b < 16 && p->x != SPMM_F32) {
-    c[0] = 4; c[1] = 8;
+    c[k++] = make_variant(4, 1);
+    c[k++] = make_variant(8, 1);
+    if (small_lds_eligible(p->b, p->w, p->x)) c[k++] = make_variant(0, 2);
   }
+  return k;
 }
 
-spmm_status_t spmm_autotune_static(spmm_plan_t p, int64_t n, const void* X, int64_t ldx, void* Y, int64_t ldy,
-                                   void* stream, int32_t* variant_out, float* times_ms_out) {
-  clear_error();
-  if (!p) return fail(SPMM_ERR_INVALID_ARG, "plan is NULL");
-  if (n <= 0) return fail(SPMM_ERR_INVALID_ARG, "n must be positive for tuning");
-  if (n > INT32_MAX / 2) return fail(SPMM_ERR_UNSUPPORTED, "n too large");
-  if (!p->has_values) return fail(SPMM_ERR_INVALID_ARG, "values were not set on this plan");
-  spmm_status_t st;
-  if ((st = check_dense(X, ldx, n, dtype_bytes(p->x), "X")) != SPMM_OK) return st;
-  if ((st = check_dense(Y, ldy, n, dtype_bytes(p->y), "Y")) != SPMM_OK) return st;
-  if ((st = check_device(p->device)) != SPMM_OK) return st;
-  hipStream_t s = (hipStream_t)stream;
-  int32_t cand[4];
-  plan_candidates(p, cand);
-  float times[3] = {-1.f, -1.f, -1.f};
+// Times every candidate on the caller's operands (2 warm-up and 5 timed runs
+// each, HIP events on `s`), records the fastest for n's class in the plan and
+// the process table, and leaves Y holding its result. Synchronises `s`.
+static spmm_status_t tune_plan(spmm_plan_s* p, int64_t n, const void* X, int64_t ldx, void* Y, int64_t ldy,
+                               hipStream_t s, int32_t* cand_out, float* times_out, int32_t* count_out,
+                               int32_t* best_out) {
+  int32_t cand[8];
+  const int nc = plan_candidates(p, cand);
+  float times[8];
   int32_t best = 0;
   float best_ms = 0.f;
-  if (cand[0]) {
+  spmm_status_t st = SPMM_OK;
+  if (nc > 0) {
     hipEvent_t e0 = nullptr, e1 = nullptr;
     SPMM_HIP(hipEventCreate(&e0));
     hipError_t he = hipEventCreate(&e1);
@@ -466,7 +483,7 @@ spmm_status_t spmm_autotune_static(spmm_plan_t p, int64_t n, const void* X, int6
       (void)hipEventDestroy(e0);
       return fail_hip(he, "hipEventCreate");
     }
-    for (int c = 0; c < 4 && cand[c] && st == SPMM_OK; ++c) {
+    for (int c = 0; c < nc && st == SPMM_OK; ++c) {
       for (int i = 0; i < 2 && st == SPMM_OK; ++i) st = run_plan(p, n, X, ldx, Y, ldy, cand[c], false, s);
       if (st != SPMM_OK) break;
       he = hipEventRecord(e0, s);
@@ -477,12 +494,10 @@ spmm_status_t spmm_autotune_static(spmm_plan_t p, int64_t n, const void* X, int6
       if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
       if (he != hipSuccess) st = fail_hip(he, "autotune timing");
       if (st != SPMM_OK) break;
-      ms /= 5.f;
-      const int slot = cand[c] == 2 ? 0 : (cand[c] == 4 ? 1 : 2);
-      times[slot] = ms;
-      if (!best || ms < best_ms) {
+      times[c] = ms / 5.f;
+      if (!best || times[c] < best_ms) {
         best = cand[c];
-        best_ms = ms;
+        best_ms = times[c];
       }
     }
     (void)hipEventDestroy(e0);
@@ -491,15 +506,98 @@ spmm_status_t spmm_autotune_static(spmm_plan_t p, int64_t n, const void* X, int6
     // leave Y holding the result of the chosen variant
     if ((st = run_plan(p, n, X, ldx, Y, ldy, best, false, s)) != SPMM_OK) return st;
     SPMM_HIP(hipStreamSynchronize(s));
-    p->tuned[n_class(n)] = (int8_t)best;
+    p->tuned[n_class(n)] = best;
     tune_table_put(p, n, best);
   } else {
     if ((st = run_plan(p, n, X, ldx, Y, ldy, 0, false, s)) != SPMM_OK) return st;
     SPMM_HIP(hipStreamSynchronize(s));
   }
+  for (int c = 0; c < nc; ++c) {
+    if (cand_out) cand_out[c] = cand[c];
+    if (times_out) times_out[c] = times[c];
+  }
+  if (count_out) *count_out = nc;
+  if (best_out) *best_out = best;
+  return SPMM_OK;
+}
+
+// A run with no fixed and no tuned variant for its n class tunes first
+// (SPMM_AUTOTUNE=0 keeps the rule instead), except on a stream under capture.
+static bool tune_on_first_run(hipStream_t s) {
+  const char* e = getenv("SPMM_AUTOTUNE");
+  if (e && e[0] == '0') return false;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cs) != hipSuccess) return false;
+  return cs == hipStreamCaptureStatusNone;
+}
+
+static spmm_status_t check_run_args(const spmm_plan_s* p, int64_t n, const void* X, int64_t ldx, const void* Y,
+                                    int64_t ldy) {
+  if (n > INT32_MAX / 2) return fail(SPMM_ERR_UNSUPPORTED, "n too large");
+  if (!p->has_values) return fail(SPMM_ERR_INVALID_ARG, "values were not set on this plan");
+  spmm_status_t st;
+  if ((st = check_dense(X, ldx, n, dtype_bytes(p->x), "X")) != SPMM_OK) return st;
+  if ((st = check_dense(Y, ldy, n, dtype_bytes(p->y), "Y")) != SPMM_OK) return st;
+  return check_device(p->device);
+}
+
+spmm_status_t spmm_run_static(spmm_plan_t p, int64_t n, const void* X, int64_t ldx, void* Y, int64_t ldy,
+                              void* stream) {
+  clear_error();
+  if (!p) return fail(SPMM_ERR_INVALID_ARG, "plan is NULL");
+  if (n < 0) return fail(SPMM_ERR_INVALID_ARG, "n is negative");
+  if (n == 0) return SPMM_OK;
+  spmm_status_t st = check_run_args(p, n, X, ldx, Y, ldy);
+  if (st != SPMM_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  const int32_t v = plan_variant(p, n);
+  if (v == 0) {
+    int32_t cand[8];
+    if (plan_candidates(p, cand) > 1 && tune_on_first_run(s))
+      return tune_plan(p, n, X, ldx, Y, ldy, s, nullptr, nullptr, nullptr, nullptr);
+  }
+  return run_plan(p, n, X, ldx, Y, ldy, v, false, s);
+}
+
+spmm_status_t spmm_autotune_static(spmm_plan_t p, int64_t n, const void* X, int64_t ldx, void* Y, int64_t ldy,
+                                   void* stream, int32_t* variant_out, float* times_ms_out) {
+  clear_error();
+  if (!p) return fail(SPMM_ERR_INVALID_ARG, "plan is NULL");
+  if (n <= 0) return fail(SPMM_ERR_INVALID_ARG, "n must be positive for tuning");
+  spmm_status_t st = check_run_args(p, n, X, ldx, Y, ldy);
+  if (st != SPMM_OK) return st;
+  int32_t cand[8], count = 0, best = 0;
+  float times[8];
+  if ((st = tune_plan(p, n, X, ldx, Y, ldy, (hipStream_t)stream, cand, times, &count, &best)) != SPMM_OK) return st;
   if (variant_out) *variant_out = best;
-  if (times_ms_out)
-    for (int i = 0; i < 3; ++i) times_ms_out[i] = times[i];
+  if (times_ms_out) {  // per tile width, the best over the kernel forms
+    for (int i = 0; i < 3; ++i) times_ms_out[i] = -1.f;
+    for (int c = 0; c < count; ++c) {
+      const int32_t ns = variant_ns(cand[c]);
+      const int slot = ns == 2 ? 0 : (ns == 4 ? 1 : (ns == 8 ? 2 : -1));
+      if (slot >= 0 && (times_ms_out[slot] < 0.f || times[c] < times_ms_out[slot])) times_ms_out[slot] = times[c];
+    }
+  }
+  return SPMM_OK;
+}
+
+spmm_status_t spmm_autotune_static_all(spmm_plan_t p, int64_t n, const void* X, int64_t ldx, void* Y, int64_t ldy,
+                                       void* stream, int32_t capacity, int32_t* variants, float* times_ms,
+                                       int32_t* count, int32_t* best) {
+  clear_error();
+  if (!p) return fail(SPMM_ERR_INVALID_ARG, "plan is NULL");
+  if (n <= 0) return fail(SPMM_ERR_INVALID_ARG, "n must be positive for tuning");
+  if (capacity < 8 || !variants || !times_ms || !count) return fail(SPMM_ERR_INVALID_ARG, "need 8 output slots");
+  spmm_status_t st = check_run_args(p, n, X, ldx, Y, ldy);
+  if (st != SPMM_OK) return st;
+  return tune_plan(p, n, X, ldx, Y, ldy, (hipStream_t)stream, variants, times_ms, count, best);
+}
+
+spmm_status_t spmm_plan_variant(spmm_plan_t p, int64_t n, int32_t* variant) {
+  clear_error();
+  if (!p || !variant) return fail(SPMM_ERR_INVALID_ARG, "NULL argument");
+  if (n < 0) return fail(SPMM_ERR_INVALID_ARG, "n is negative");
+  *variant = plan_variant(p, n);
   return SPMM_OK;
 }
 

@@ -384,8 +384,12 @@ spmm_status_t small_lds_y(const RunArgs& a, const int32_t* rp, const int32_t* ci
 // pay for staging every chunk of X and the per-row, per-chunk work; at b = 8
 // the kernel without LDS was faster at every density. SPMM_SMALL_LDS=0 / 1
 // forces the choice (for comparisons and tests).
+bool small_lds_eligible(int32_t b, spmm_dtype_t w, spmm_dtype_t x) {
+  return b == 4 && w == x && (x == SPMM_F16 || x == SPMM_BF16);
+}
+
 bool small_lds_preferred(int32_t b, spmm_dtype_t w, spmm_dtype_t x, int64_t nnz, int64_t mb, int64_t kb) {
-  if (b != 4 || w != x || (x != SPMM_F16 && x != SPMM_BF16)) return false;
+  if (!small_lds_eligible(b, w, x)) return false;
   if (const char* e = getenv("SPMM_SMALL_LDS")) {
     if (e[0] == '0') return false;
     if (e[0] == '1') return true;

@@ -65,6 +65,9 @@ SIGNATURES = {
                                   _c_i64, _vp, _c_i64, _vp, _c_i64, _vp, _vp], _c_i32),
     "spmm_autotune_static": ([_vp, _c_i64, _vp, _c_i64, _vp, _c_i64, _vp, _pi32, ctypes.POINTER(ctypes.c_float)],
                              _c_i32),
+    "spmm_autotune_static_all": ([_vp, _c_i64, _vp, _c_i64, _vp, _c_i64, _vp, _c_i32, _pi32,
+                                  ctypes.POINTER(ctypes.c_float), _pi32, _pi32], _c_i32),
+    "spmm_plan_variant": ([_vp, _c_i64, _pi32], _c_i32),
     "spmm_group_create": ([_c_i32, ctypes.POINTER(_vp)], _c_i32),
     "spmm_group_run": ([_vp, _c_i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp], _c_i32),
     "spmm_group_destroy": ([_vp], _c_i32),
@@ -260,13 +263,31 @@ class StaticPlan:
         return Y
 
     def autotune(self, X, Y, n=None, ldx=None, ldy=None, stream=None):
-        """spmm_autotune_static: returns (chosen variant, {variant: mean ms})."""
+        """spmm_autotune_static_all: returns (chosen variant, {variant: mean ms})
+        over every candidate (a variant is tile width + 256 * kernel form)."""
+        n, ldx, ldy = self._operands(X, Y, n, ldx, ldy)
+        cap = 8
+        vs = (ctypes.c_int32 * cap)()
+        ts = (ctypes.c_float * cap)()
+        count, best = ctypes.c_int32(), ctypes.c_int32()
+        check(lib().spmm_autotune_static_all(self._h, int(n), _ptr(X), int(ldx), _ptr(Y), int(ldy), _stream(stream),
+                                             cap, vs, ts, ctypes.byref(count), ctypes.byref(best)))
+        return best.value, {int(vs[i]): float(ts[i]) for i in range(count.value)}
+
+    def autotune_widths(self, X, Y, n=None, ldx=None, ldy=None, stream=None):
+        """spmm_autotune_static: (chosen variant, {tile width: best mean ms over kernel forms})."""
         n, ldx, ldy = self._operands(X, Y, n, ldx, ldy)
         v = ctypes.c_int32()
         t = (ctypes.c_float * 3)()
         check(lib().spmm_autotune_static(self._h, int(n), _ptr(X), int(ldx), _ptr(Y), int(ldy), _stream(stream),
                                          ctypes.byref(v), t))
         return v.value, {var: float(ms) for var, ms in zip((2, 4, 8), t) if ms >= 0}
+
+    def variant_for(self, n):
+        """spmm_plan_variant: the variant a run with n columns uses now (0 = untuned)."""
+        v = ctypes.c_int32()
+        check(lib().spmm_plan_variant(self._h, int(n), ctypes.byref(v)))
+        return v.value
 
     def export(self):
         inf = self.info()

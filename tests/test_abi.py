@@ -79,7 +79,7 @@ def test_binding_raises_with_message():
 
 
 def test_plan_variant_option_checked_on_host():
-    for variant, b in [(3, 16), (16, 16), (-2, 16), (2, 8)]:
+    for variant, b in [(3, 16), (16, 16), (-2, 16), (2, 8), (3 * 256 + 8, 16), (2 + 256, 4)]:
         opts = spmm.PlanOpts(0, 0, 0, variant)
         st, h = _plan(b=b, opts=ctypes.byref(opts))
         assert st == spmm.ERR_INVALID_ARG and not h.value, (variant, b)
@@ -90,6 +90,11 @@ def test_autotune_and_group_reject_bad_arguments():
     L = spmm.lib()
     v = ctypes.c_int32()
     assert L.spmm_autotune_static(None, 64, None, 64, None, 64, None, ctypes.byref(v), None) == spmm.ERR_INVALID_ARG
+    vs, ts = (ctypes.c_int32 * 8)(), (ctypes.c_float * 8)()
+    cnt = ctypes.c_int32()
+    assert L.spmm_autotune_static_all(None, 64, None, 64, None, 64, None, 8, vs, ts, ctypes.byref(cnt),
+                                      None) == spmm.ERR_INVALID_ARG
+    assert L.spmm_plan_variant(None, 64, ctypes.byref(v)) == spmm.ERR_INVALID_ARG
     h = ctypes.c_void_p()
     assert L.spmm_group_create(0, ctypes.byref(h)) == spmm.ERR_INVALID_ARG and not h.value
     assert L.spmm_group_create(4, None) == spmm.ERR_INVALID_ARG

@@ -145,7 +145,8 @@ def test_b64_autotune_and_transposed_plan():
     plan.set_values(vals)
     Y = c.new_Y()
     best, times = plan.autotune(X, Y, n=c.n)
-    assert best in (2, 4, 8) and sorted(times) == [2, 4, 8]
+    # three tile widths of the plain row kernel (b = 64 has no pipelined form)
+    assert best in times and sorted(times) == [2 + 256, 4 + 256, 8 + 256]
     # the transposed b = 64 plan against the oracle
     from oracle import train_ref as TR
     t = plan.transpose()

@@ -32,20 +32,48 @@ def test_variants_agree_bitwise_and_match_oracle(b, w, y):
     assert O.rel_fro(y_f64(outs[0], c), c.oracle()) <= 5e-3
 
 
-@pytest.mark.parametrize("b", [16, 8])
-def test_autotune_picks_a_variant_and_keeps_results(b):
-    c = Case(64 * b, 48 * b, 96, b, 1 / 8, w="f16", seed=61)
+@pytest.mark.parametrize("b,w", [(16, "f16"), (8, "f16"), (4, "bf16"), (32, "bf16")])
+def test_autotune_picks_a_variant_and_keeps_results(b, w):
+    c = Case(64 * b, 48 * b, 96, b, 1 / 8, w=w, seed=61)
     plan, Y0 = c.run_static()
     vals, X, _ = c.device_inputs()
     Y1 = c.new_Y()
     v, times = plan.autotune(X, Y1, n=c.n)
-    assert v in ((2, 4, 8) if b >= 16 else (4, 8))
-    assert set(times) == ({2, 4, 8} if b >= 16 else {4, 8}) and all(t > 0 for t in times.values())
-    assert torch.equal(Y0[:, : c.n], Y1[:, : c.n])
+    # candidates: tile widths x kernel forms (form 2: pipelined row kernel for
+    # b = 16/32, LDS-staged kernel for b = 4)
+    want = {16: [2, 4, 8, 514, 516, 520], 32: [2, 4, 8, 514, 516, 520], 8: [4, 8], 4: [4, 8, 512]}[b]
+    want = sorted(x + 256 if x < 256 else x for x in want)
+    assert sorted(times) == want and v in times and all(t > 0 for t in times.values())
+    assert plan.variant_for(c.n) == v
     Y2 = c.new_Y()
     plan.run(X, Y2, n=c.n)  # now on the tuned variant
     torch.cuda.synchronize()
-    assert torch.equal(Y0[:, : c.n], Y2[:, : c.n])
+    assert torch.equal(Y1[:, : c.n], Y2[:, : c.n])
+    # every candidate forced through the plan options: the same bits as the
+    # tuned run where the kernel form sums in the same order (tile widths; the
+    # pipelined row kernel), else within the FP16 bound of the oracle (the b = 4
+    # LDS-staged kernel adds its blocks in another order)
+    ref = c.oracle()
+    for var in times:
+        pv = spmm.StaticPlan(c.m, c.k, b, c.mask, w, variant=var)
+        pv.set_values(vals)
+        Y3 = c.new_Y()
+        pv.run(X, Y3, n=c.n)
+        torch.cuda.synchronize()
+        if b >= 16 or (var >> 8) == (v >> 8):
+            assert torch.equal(Y1[:, : c.n], Y3[:, : c.n]), var
+        assert O.rel_fro(y_f64(Y3, c), ref) <= 5e-3, var
+        pv.close()
+
+
+def test_autotune_widths_reports_best_per_tile_width():
+    c = Case(64 * 16, 48 * 16, 200, 16, 1 / 8, w="f16", seed=62)
+    plan, Y0 = c.run_static()
+    _, X, _ = c.device_inputs()
+    Y1 = c.new_Y()
+    v, widths = plan.autotune_widths(X, Y1, n=c.n)
+    assert sorted(widths) == [2, 4, 8] and (v & 0xFF) in widths
+    assert torch.equal(Y0[:, : c.n], Y1[:, : c.n])
 
 
 def _group_cases(b, w, y, ns, seed):

@@ -103,10 +103,11 @@ def test_lds_dynamic_equals_static(b, monkeypatch):
 
 
 def test_lds_chosen_by_density(monkeypatch):
-    """Without the override the LDS kernel runs from density 1/8 up; both
-    choices agree with the oracle (the dispatch is checked through results
-    equal to the forced kernel's, bit for bit)."""
+    """Without the override (and without tuning) the LDS kernel runs from
+    density 1/8 up; both choices agree with the oracle (the dispatch is checked
+    through results equal to the forced kernel's, bit for bit)."""
     monkeypatch.delenv("SPMM_LDS_RW", raising=False)
+    monkeypatch.setenv("SPMM_AUTOTUNE", "0")  # the rule, not a measurement
     for d, lds in ((1 / 4, "1"), (1 / 16, "0")):
         c = Case(4 * 300, 4 * 320, 96, 4, d, w="f16", seed=470)
         monkeypatch.delenv("SPMM_SMALL_LDS", raising=False)
