@@ -57,7 +57,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--mode", default="headline",
                     choices=["headline", "sweep", "dynamic", "precision", "copy", "serve", "group", "table3", "small",
-                             "skew", "train", "grid", "ell", "peaks"])
+                             "skew", "train", "grid", "ell", "peaks", "dispatch"])
     ap.add_argument("--requests", type=int, default=2000, help="serve mode: measured requests per run")
     ap.add_argument("--rho", default="0.5,0.8", help="serve mode: offered load as fractions of the saturated rate")
     ap.add_argument("--rate-base", type=float, default=0.0,
@@ -866,6 +866,34 @@ def mode_train(args):
         torch.cuda.empty_cache()
 
 
+def mode_dispatch(args):
+    """Dense dispatch at m = k = 8192, n = 4096, FP16: for each (b, d) the
+    speedup model's predicted sparse/dense ratio, the measured best sparse
+    variant and the dense GEMM on the plan's dense copy (both through the
+    autotuner), and the variant a plan with dense dispatch runs."""
+    import torch
+    from paper_2303_16999_amd import spmm
+    m = k = 8192
+    n = 4096
+    for b, d in ((1, 1 / 16), (4, 1 / 16), (4, 1 / 4), (8, 1 / 16), (16, 1 / 16), (16, 1 / 4), (16, 1 / 2)):
+        prob = StaticProblem(m, k, n, b, d, "f16", seed=0)
+        plan = spmm.StaticPlan(m, k, b, prob.mask, "f16", n_hint=n, dense_dispatch=2)
+        plan.set_values(prob.values_dev)
+        ratio, _ = plan.dispatch()
+        best, times = plan.autotune(prob.X, prob.Y, n=n)
+        dense_ms = times.pop(3 * 256)
+        sparse_v = min(times, key=times.get)
+        rec = {"mode": "dispatch", "m": m, "k": k, "n": n, "b": b, "density": d,
+               "model_ratio": round(ratio, 3), "model_picks": "dense" if ratio < 1 else "sparse",
+               "sparse_best_ms": round(times[sparse_v], 5), "sparse_best_variant": sparse_v,
+               "dense_ms": round(dense_ms, 5), "measured_ratio": round(dense_ms / times[sparse_v], 3),
+               "tuner_picks": "dense" if best == 3 * 256 else "sparse"}
+        emit(rec, args.out)
+        plan.close()
+        del prob
+        torch.cuda.empty_cache()
+
+
 def mode_grid(args):
     """The paper's static sweep grid (Table 1 of Section 4: m = k in 2^8..2^13,
     n in 2^2..2^16 by powers of 4, b in {1, 4, 8, 16}, d in {1/4 .. 1/32},
@@ -1042,7 +1070,7 @@ def main():
     {"headline": mode_headline, "sweep": mode_sweep, "precision": mode_precision, "copy": mode_copy,
      "dynamic": mode_dynamic, "serve": mode_serve, "group": mode_group, "table3": mode_table3,
      "small": mode_small, "skew": mode_skew, "train": mode_train, "grid": mode_grid,
-     "ell": mode_ell, "peaks": mode_peaks}[args.mode](args)
+     "ell": mode_ell, "peaks": mode_peaks, "dispatch": mode_dispatch}[args.mode](args)
 
 
 if __name__ == "__main__":

@@ -85,13 +85,29 @@ typedef enum { SPMM_F32 = 0, SPMM_F16 = 1, SPMM_BF16 = 2, SPMM_FP8_E4M3 = 3 } sp
  *               kernel, 2 = the plan's other kernel where it has one (the
  *               software-pipelined row kernel for b = 16/32 with W in the X
  *               type and no split rows; the LDS-staged kernel for b = 4 with W
- *               in the X type), else the plain one. Other kernels have one
- *               variant and ignore it. */
+ *               in the X type), else the plain one; 3 = the dense GEMM on
+ *               the plan's dense copy (needs dense_dispatch that keeps one).
+ *               Other kernels have one variant and ignore it.
+ *   dense_dispatch  static plans with W in the 16-bit X type and Y in it or
+ *               FP32 (dynamic handles ignore it). 0 = never dense. 1 = ask the
+ *               speedup model (spmm_speedup_model at feature size sqrt(m k),
+ *               the plan's density and b) when the plan is built; where it
+ *               predicts the sparse product slower than dense (ratio < 1),
+ *               the plan keeps a dense copy of M o W (m x k, built by
+ *               spmm_plan_set_values) and runs with variant 0 use a library
+ *               GEMM on it, unless the autotuner measures a sparse variant
+ *               faster. 2 = always keep the copy (runs still follow the model
+ *               or the tuner). A fused ReLU (grouped and serving launches)
+ *               always takes the sparse kernels. The dense GEMM's summation
+ *               order is the library's: its results are within the FP32
+ *               accumulation bound but not promised bit for bit from run to
+ *               run, unlike the sparse kernels'. */
 typedef struct {
   int32_t group_rows;
   int32_t num_panels;
   int32_t n_hint;
   int32_t variant;
+  int32_t dense_dispatch;
 } spmm_plan_opts;
 
 typedef struct spmm_plan_s* spmm_plan_t;
@@ -176,6 +192,12 @@ spmm_status_t spmm_run_static(spmm_plan_t plan, int64_t n, const void* X, int64_
  * reproducible (and equal between spmm_run_static and spmm_group_run), but a
  * dynamic call of the same pattern, which never splits, may differ from it in
  * the last bits. Any pointer may be NULL. */
+/* Dense dispatch facts: *predicted_speedup (may be NULL) receives the speedup
+ * model's sparse/dense ratio for the plan's shape (0 for an empty pattern);
+ * *has_dense (may be NULL) whether the plan keeps a dense copy of M o W.
+ * Errors: INVALID_ARG (NULL plan). */
+spmm_status_t spmm_plan_dispatch(spmm_plan_t plan, double* predicted_speedup, int32_t* has_dense);
+
 spmm_status_t spmm_plan_info(spmm_plan_t plan, int64_t* nnzb, int32_t* group_rows,
                              int32_t* num_groups, int32_t* num_panels, int32_t* num_split_rows);
 

@@ -26,6 +26,9 @@ struct spmm_plan_s {
   int32_t* heavy_rows = nullptr;   // device [num_heavy]
   int32_t* sddmm_tasks = nullptr;  // device [sddmm_num_tasks][2] (16-bit X, b <= 32)
   int32_t sddmm_num_tasks = 0;
+  double predicted_speedup = 0.0;  // speedup model's sparse/dense ratio for this plan's shape
+  int32_t dense_mode = 0;          // dense dispatch option (0 off, 1 where the model favours dense, 2 always)
+  void* dense_w = nullptr;         // dense copy of M o W (m x k, row-major) when the plan keeps one
   int32_t ell_width = 0;           // plans built from blocked-ELL: slots per block row
   int32_t* ell_slot = nullptr;     // device [nnzb]: ELL slot (row * ell_width + slot) of each CSR entry
 };
@@ -38,7 +41,8 @@ int n_class(int64_t n);
 // (b < 16) in the low byte, 0 = the rule on n; above it the kernel form: 0 =
 // the rule, 1 = the plain kernel, 2 = the other form where the plan has one
 // (the software-pipelined row kernel for b = 16/32 with W in the X type and
-// no split rows; the LDS-staged kernel for b = 4 with W in the X type).
+// no split rows; the LDS-staged kernel for b = 4 with W in the X type), 3 =
+// the dense GEMM on the plan's dense copy (plans with dense dispatch).
 constexpr int kFormShift = 8;
 inline int32_t variant_ns(int32_t v) { return v & 0xff; }
 inline int32_t variant_form(int32_t v) { return v >> kFormShift; }
@@ -57,6 +61,14 @@ spmm_status_t run_dynamic_kernel(RunArgs& a, const int32_t* row_ptr, const int32
 spmm_status_t check_dense(const void* p, int64_t ld, int64_t n, int elem, const char* name);
 spmm_status_t check_device(int device);
 int32_t default_ns(int64_t n);
+
+// Dense dispatch (dense.hip): whether a plan with these dtypes can keep a
+// dense copy; (re)builds the copy from the plan's CSR values on `s`; runs
+// Y = Wd X with a library GEMM on `s`.
+bool dense_dispatch_eligible(spmm_dtype_t w, spmm_dtype_t x, spmm_dtype_t y);
+spmm_status_t build_dense_copy(spmm_plan_s* p, hipStream_t s);
+spmm_status_t run_dense(const spmm_plan_s* p, int64_t n, const void* X, int64_t ldx, void* Y, int64_t ldy,
+                        hipStream_t s);
 
 // Autotuner table persisted as JSON (tune_cache.cpp). Key: (b, w, x, y,
 // density class, n class). load fills `table` from `path` when the file was

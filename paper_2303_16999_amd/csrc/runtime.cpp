@@ -186,7 +186,7 @@ bool valid_variant(int32_t b, int32_t v) {
   if (v == 0) return true;
   if (v < 0) return false;
   const int32_t ns = variant_ns(v), form = variant_form(v);
-  if (form > 2 || (ns != 0 && ns != 2 && ns != 4 && ns != 8)) return false;
+  if (form > 3 || (ns != 0 && ns != 2 && ns != 4 && ns != 8)) return false;
   return !(ns == 2 && b < 16);
 }
 
@@ -257,6 +257,10 @@ spmm_status_t run_plan(const spmm_plan_s* p, int64_t n, const void* X, int64_t l
   // a variant's kernel form applies where the plan has that form, unless the
   // environment forces one (SPMM_SMALL_LDS, SPMM_ROW_PP)
   const int32_t form = variant_form(variant);
+  // the dense copy: when asked for, or by the rule where the model favours it
+  // (never with a fused ReLU)
+  if (p->dense_w && !relu && (form == 3 || (form == 0 && p->predicted_speedup < 1.0)))
+    return run_dense(p, n, X, ldx, Y, ldy, stream);
   if (p->b < 16) {
     bool lds = small_lds_preferred(p->b, p->w, p->x, p->nnzb, p->mb, p->kb);
     if (form && small_lds_eligible(p->b, p->w, p->x) && !getenv("SPMM_SMALL_LDS")) lds = form == 2;
@@ -380,13 +384,30 @@ spmm_status_t spmm_plan_static(int64_t m, int64_t k, int32_t b, const uint8_t* b
   if (opts && (opts->group_rows < 0 || opts->num_panels < 0))
     return fail(SPMM_ERR_INVALID_ARG, "negative plan option");
   if (opts && !valid_variant(b, opts->variant))
-    return fail(SPMM_ERR_INVALID_ARG, "variant must be 0 or (2, 4, 8 or 0) + 256 x (0, 1 or 2); 2 needs b >= 16");
+    return fail(SPMM_ERR_INVALID_ARG, "variant must be 0 or (2, 4, 8 or 0) + 256 x (0 .. 3); 2 needs b >= 16");
+  if (opts && (opts->dense_dispatch < 0 || opts->dense_dispatch > 2))
+    return fail(SPMM_ERR_INVALID_ARG, "dense_dispatch must be 0, 1 or 2");
+  const int32_t dense_opt = opts ? opts->dense_dispatch : 0;
+  if (dense_opt && !dense_dispatch_eligible(w, x, y))
+    return fail(SPMM_ERR_UNSUPPORTED, "dense dispatch needs W in the 16-bit X type and Y in it or FP32");
+  double predicted = 0.0;
+  {
+    const double d = mb * kb > 0 ? (double)nnzb / ((double)mb * (double)kb) : 0.0;
+    const int64_t feat = std::max<int64_t>(1, std::llround(std::sqrt((double)m * (double)k)));
+    if (d > 0.0 && spmm_speedup_model(feat, d, b, &predicted) != SPMM_OK) predicted = 0.0;
+    clear_error();
+  }
+  const bool keep_dense = dense_opt == 2 || (dense_opt == 1 && nnzb > 0 && predicted < 1.0);
+  if (opts && variant_form(opts->variant) == 3 && !keep_dense)
+    return fail(SPMM_ERR_INVALID_ARG, "variant form 3 (dense) needs a plan that keeps a dense copy");
 
   spmm_plan_s* p = new (std::nothrow) spmm_plan_s;
   if (!p) return fail(SPMM_ERR_OOM, "host allocation failed");
   p->m = m; p->k = k; p->b = b; p->mb = (int32_t)mb; p->kb = (int32_t)kb; p->nnzb = nnzb;
   p->w = w; p->x = x; p->y = y;
   p->variant_opt = opts ? opts->variant : 0;
+  p->predicted_speedup = predicted;
+  p->dense_mode = keep_dense ? dense_opt : 0;
   p->geo = choose_geometry(m, k, b, nnzb, opts ? opts->n_hint : 0, opts, device_cu_count(), x);
   spmm_status_t st = SPMM_OK;
   uint8_t* mask_dev = nullptr;
@@ -444,6 +465,7 @@ spmm_status_t spmm_plan_set_values(spmm_plan_t p, const void* values_dev, const 
   st = copy_values_csr(p->pb.col_idx, p->nnzb, p->b, (int32_t)p->k, values_dev, p->values, dtype_bytes(p->w),
                        scales_dev, p->scales, (hipStream_t)stream);
   if (st != SPMM_OK) return st;
+  if (p->dense_mode && (st = build_dense_copy(p, (hipStream_t)stream)) != SPMM_OK) return st;
   p->has_values = true;
   return SPMM_OK;
 }
@@ -460,6 +482,7 @@ static int plan_candidates(const spmm_plan_s* p, int32_t (&c)[8]) {
     c[k++] = make_variant(8, 1);
     if (small_lds_eligible(p->b, p->w, p->x)) c[k++] = make_variant(0, 2);
   }
+  if (p->dense_w) c[k++] = make_variant(0, 3);
   return k;
 }
 
@@ -639,7 +662,16 @@ spmm_status_t spmm_plan_destroy(spmm_plan_t p) {
   if (p->heavy_rows) (void)hipFree(p->heavy_rows);
   if (p->sddmm_tasks) (void)hipFree(p->sddmm_tasks);
   if (p->ell_slot) (void)hipFree(p->ell_slot);
+  if (p->dense_w) (void)hipFree(p->dense_w);
   delete p;
+  return SPMM_OK;
+}
+
+spmm_status_t spmm_plan_dispatch(spmm_plan_t p, double* predicted_speedup, int32_t* has_dense) {
+  clear_error();
+  if (!p) return fail(SPMM_ERR_INVALID_ARG, "plan is NULL");
+  if (predicted_speedup) *predicted_speedup = p->predicted_speedup;
+  if (has_dense) *has_dense = p->dense_mode ? 1 : 0;
   return SPMM_OK;
 }
 

@@ -24,7 +24,7 @@ _pi32, _pi64 = ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64)
 
 class PlanOpts(ctypes.Structure):
     _fields_ = [("group_rows", ctypes.c_int32), ("num_panels", ctypes.c_int32),
-                ("n_hint", ctypes.c_int32), ("variant", ctypes.c_int32)]
+                ("n_hint", ctypes.c_int32), ("variant", ctypes.c_int32), ("dense_dispatch", ctypes.c_int32)]
 
 
 class ServeOpts(ctypes.Structure):
@@ -68,6 +68,7 @@ SIGNATURES = {
     "spmm_autotune_static_all": ([_vp, _c_i64, _vp, _c_i64, _vp, _c_i64, _vp, _c_i32, _pi32,
                                   ctypes.POINTER(ctypes.c_float), _pi32, _pi32], _c_i32),
     "spmm_plan_variant": ([_vp, _c_i64, _pi32], _c_i32),
+    "spmm_plan_dispatch": ([_vp, ctypes.POINTER(ctypes.c_double), _pi32], _c_i32),
     "spmm_group_create": ([_c_i32, ctypes.POINTER(_vp)], _c_i32),
     "spmm_group_run": ([_vp, _c_i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp], _c_i32),
     "spmm_group_destroy": ([_vp], _c_i32),
@@ -133,8 +134,8 @@ def _stream(stream):
     return stream.cuda_stream
 
 
-def _opts(group_rows=0, num_panels=0, n_hint=0, variant=0):
-    return PlanOpts(int(group_rows), int(num_panels), int(n_hint), int(variant))
+def _opts(group_rows=0, num_panels=0, n_hint=0, variant=0, dense_dispatch=0):
+    return PlanOpts(int(group_rows), int(num_panels), int(n_hint), int(variant), int(dense_dispatch))
 
 
 def torch_dtype(code):
@@ -209,7 +210,7 @@ class StaticPlan:
     """spmm_plan_static / spmm_plan_set_values / spmm_run_static."""
 
     def __init__(self, m, k, b, block_mask, w="f16", x=None, y=None, group_rows=0, num_panels=0, n_hint=0,
-                 variant=0):
+                 variant=0, dense_dispatch=0):
         x = x or ("f16" if w == "fp8" else w)
         y = y or x
         mask = np.ascontiguousarray(np.asarray(block_mask, dtype=np.uint8))
@@ -218,7 +219,7 @@ class StaticPlan:
         self.m, self.k, self.b = int(m), int(k), int(b)
         self.w, self.x, self.y = DTYPE_CODES[w], DTYPE_CODES[x], DTYPE_CODES[y]
         h = _vp()
-        opts = _opts(group_rows, num_panels, n_hint, variant)
+        opts = _opts(group_rows, num_panels, n_hint, variant, dense_dispatch)
         check(lib().spmm_plan_static(self.m, self.k, self.b, mask.ctypes.data_as(_vp), self.w, self.x, self.y,
                                      ctypes.byref(opts), ctypes.byref(h)))
         self._h = h
@@ -230,6 +231,12 @@ class StaticPlan:
                                    ctypes.byref(nh)))
         return {"nnzb": nnz.value, "group_rows": gr.value, "num_groups": ng.value, "num_panels": npn.value,
                 "num_split_rows": nh.value}
+
+    def dispatch(self):
+        """spmm_plan_dispatch: (speedup model's sparse/dense ratio, keeps a dense copy)."""
+        pr, hd = ctypes.c_double(), ctypes.c_int32()
+        check(lib().spmm_plan_dispatch(self._h, ctypes.byref(pr), ctypes.byref(hd)))
+        return pr.value, bool(hd.value)
 
     def _nnzb(self):
         if getattr(self, "_nnzb_cache", None) is None:

@@ -86,6 +86,21 @@ def test_plan_variant_option_checked_on_host():
         assert b"variant" in spmm.lib().spmm_last_error()
 
 
+def test_dense_dispatch_option_checked_on_host():
+    mask = np.ones((4, 4), np.uint8)
+    cases = [((0, 0, 0, 0, 3), spmm.DTYPE_CODES["f16"], spmm.ERR_INVALID_ARG, b"dense_dispatch"),
+             ((0, 0, 0, 3 * 256, 0), spmm.DTYPE_CODES["f16"], spmm.ERR_INVALID_ARG, b"dense copy"),
+             ((0, 0, 0, 0, 1), spmm.DTYPE_CODES["f32"], spmm.ERR_UNSUPPORTED, b"dense dispatch")]
+    for fields, dt, want, msg in cases:
+        opts = spmm.PlanOpts(*fields)
+        h = ctypes.c_void_p()
+        st = spmm.lib().spmm_plan_static(64, 64, 16, mask.ctypes.data_as(ctypes.c_void_p), dt, dt, dt,
+                                         ctypes.byref(opts), ctypes.byref(h))
+        assert st == want and not h.value, fields
+        assert msg in spmm.lib().spmm_last_error(), fields
+    assert spmm.lib().spmm_plan_dispatch(None, None, None) == spmm.ERR_INVALID_ARG
+
+
 def test_autotune_and_group_reject_bad_arguments():
     L = spmm.lib()
     v = ctypes.c_int32()
