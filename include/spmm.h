@@ -86,7 +86,12 @@ typedef enum { SPMM_F32 = 0, SPMM_F16 = 1, SPMM_BF16 = 2, SPMM_FP8_E4M3 = 3 } sp
  *               software-pipelined row kernel for b = 16/32 with W in the X
  *               type and no split rows; the LDS-staged kernel for b = 4 with W
  *               in the X type), else the plain one; 3 = the dense GEMM on
- *               the plan's dense copy (needs dense_dispatch that keeps one).
+ *               the plan's dense copy (needs dense_dispatch that keeps one);
+ *               4 = the row kernel with every block row split over the four
+ *               waves of a workgroup, partial sums added in wave order (b =
+ *               16 with 16-bit X; the rule takes it for launches too small to
+ *               fill the chip with one wave per row, SPMM_SPLIT_ALL=0/1
+ *               forces it; it sums in another order than forms 1 and 2).
  *               Other kernels have one variant and ignore it.
  *   dense_dispatch  static plans with W in the 16-bit X type and Y in it or
  *               FP32 (dynamic handles ignore it). 0 = never dense. 1 = ask the
@@ -263,7 +268,8 @@ spmm_status_t spmm_speedup_model(int64_t m, double density, int32_t b, double* s
  * times each with HIP events on `stream` (2 warm-up and 5 timed runs), and
  * records the fastest for n's size class (the power of two at or above n) in
  * the plan and in a process-wide table keyed by (b, dtypes, density class =
- * round(-log2 d), n class). Plans with variant 0 use that table. With the
+ * round(-log2 d), n class, whether the plan keeps a dense copy). Plans with
+ * variant 0 use that table. With the
  * environment variable SPMM_AUTOTUNE_CACHE naming a file, the table starts
  * from that file when it was written for the same device (architecture and
  * CU count) and HIP runtime, and every new entry rewrites it (JSON, through a
@@ -271,12 +277,15 @@ spmm_status_t spmm_speedup_model(int64_t m, double density, int32_t b, double* s
  * Synchronises `stream`. *variant_out (may be NULL) receives the choice;
  * times_ms_out (may be NULL) receives, for tile widths 2, 4 and 8 in that
  * order, the best mean time over the kernel forms with that width, -1 where
- * there is none.
+ * there is none (forms without a width of their own, ns = 0, appear only in
+ * spmm_autotune_static_all).
  * spmm_autotune_static_all: the same, reporting every candidate: variants and
  * times_ms (capacity >= 8 entries each) receive *count candidates and their
  * mean times, *best (may be NULL) the choice.
  * spmm_plan_variant: the variant a run with n columns uses now (0 = not tuned
  * for n's class: the next spmm_run_static tunes, or the rule on n).
+ * spmm_autotune_clear: forgets the process-wide table (not the plans' own
+ * choices, not the cache file, which is not read again in this process).
  * Errors: as spmm_run_static; INVALID_ARG for capacity < 8 or NULL outputs. */
 spmm_status_t spmm_autotune_static(spmm_plan_t plan, int64_t n, const void* X, int64_t ldx, void* Y,
                                    int64_t ldy, void* stream, int32_t* variant_out, float* times_ms_out);
@@ -284,6 +293,7 @@ spmm_status_t spmm_autotune_static_all(spmm_plan_t plan, int64_t n, const void* 
                                        int64_t ldy, void* stream, int32_t capacity, int32_t* variants,
                                        float* times_ms, int32_t* count, int32_t* best);
 spmm_status_t spmm_plan_variant(spmm_plan_t plan, int64_t n, int32_t* variant);
+spmm_status_t spmm_autotune_clear(void);
 
 /* ------------------------------------------------------------------ grouped launch
  * Many static products with different plans, column counts, X and Y in one
@@ -304,9 +314,10 @@ spmm_status_t spmm_plan_variant(spmm_plan_t plan, int64_t n, int32_t* variant);
  * applies max(0, .) before rounding when relu is non-NULL and relu[i] != 0.
  * Every plan must have values set and share block size (16 or 32) and dtype
  * triple, with 16-bit W and X (FP8 weights: UNSUPPORTED). Each problem uses
- * its plan's tile variant for its n, so its result equals its own
- * spmm_run_static bit for bit. Calls on one handle must not overlap on
- * different streams.
+ * the variant its plan holds for its n (fixed, tuned, else the rule; a
+ * grouped launch never tunes), so its result equals, bit for bit, a
+ * spmm_run_static of that plan that runs the same variant. Calls on one
+ * handle must not overlap on different streams.
  * Errors: INVALID_ARG (count > max_problems, NULL, alignment, ld < n, values
  * not set, mixed block size or dtypes), UNSUPPORTED, HIP. */
 spmm_status_t spmm_group_create(int32_t max_problems, spmm_group_t* out);

@@ -90,6 +90,15 @@ spmm_status_t build_dynamic_csr(const int32_t* nnz_dev, const int32_t* rows, con
 // and panels only; the values stay where the caller put them and the kernels
 // read them through csr_src). Applies when dynamic_small_fits().
 bool dynamic_small_fits(int32_t max_nnz, int32_t mb, int32_t kb, int32_t num_groups);
+// Row-range encoder: one launch, one workgroup per range of block rows, each
+// reading the whole COO list; block-CSR, input indices, status and entry count
+// as build_dynamic_csr_small, without panels (dyn_panels derives them from
+// row_ptr). Applies when dynamic_rows_fits().
+bool dynamic_rows_fits(int32_t max_nnz, int32_t mb, int32_t kb);
+spmm_status_t build_dynamic_csr_rows(const int32_t* nnz_dev, const int32_t* rows, const int32_t* cols,
+                                     int32_t max_nnz, int32_t mb, int32_t kb, PlanBuffers& pb, int32_t* status,
+                                     int32_t* status_out, int32_t* nnz_last, hipStream_t s);
+spmm_status_t dyn_panels(const Geometry& geo, int32_t mb, PlanBuffers& pb, const int32_t* status, hipStream_t s);
 spmm_status_t build_dynamic_csr_small(const int32_t* nnz_dev, const int32_t* rows, const int32_t* cols,
                                       int32_t max_nnz, int32_t mb, int32_t kb, const Geometry& geo, PlanBuffers& pb,
                                       int32_t* status, int32_t* status_out, int32_t* nnz_last, hipStream_t stream);
@@ -115,6 +124,7 @@ struct RunArgs {
   const uint8_t* heavy_flag = nullptr;  // [mb] nonzero for a split row
   const int32_t* heavy_rows = nullptr;  // [num_heavy]
   int32_t ns = 8;         // row-wise kernel: column tiles of 16 per wave (2, 4 or 8)
+  bool split_all = false;  // row-wise kernel, b = 16: split every block row (heavy_* unused)
 };
 // Row-wise kernel (16-bit X, b = 16 or 32): W and scales in block-CSR order.
 spmm_status_t launch_spmm_row(const RunArgs& a, const int32_t* row_ptr, const int32_t* col_idx, hipStream_t stream);
@@ -122,6 +132,10 @@ spmm_status_t launch_spmm_row(const RunArgs& a, const int32_t* row_ptr, const in
 // most two workgroups per CU (b = 16 or 32, W in the X type; no split rows).
 // The same results as launch_spmm_row, bit for bit.
 bool row_pp_preferred(int32_t b, int32_t mb, int64_t n, int32_t ns, int64_t nnz, int num_cus);
+// Whether the rule splits every block row over a workgroup's four waves (b =
+// 16, 16-bit X): launches too small to fill the chip with one wave per row,
+// rows long enough to share. SPMM_SPLIT_ALL=0/1 forces the choice.
+bool split_all_preferred(int32_t b, int32_t mb, int64_t n, int32_t ns, int64_t nnz, int num_cus);
 spmm_status_t launch_spmm_row_pp(const RunArgs& a, const int32_t* row_ptr, const int32_t* col_idx,
                                  hipStream_t stream);
 // Row-wise FP32 kernel (FP32 W, X, Y; b = 16 or 32): W in block-CSR order.

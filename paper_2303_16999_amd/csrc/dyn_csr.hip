@@ -595,6 +595,9 @@ __global__ __launch_bounds__(1024) void k_dyn_tail(const int32_t* __restrict__ r
   }
 }
 
+// LDS of the row-range encoder: kept entries' keys and rows, per-row counts.
+constexpr size_t kDynRowsLdsMax = 128 * 1024;
+
 // LDS of the one-workgroup builder; with bm_words > 0 the staged-entry region
 // also holds the bitmap form's column bitmaps (bm_words words), their scanned
 // bit counts (bm_words + 1) and the packed block-CSR (max_nnz words).
@@ -643,6 +646,160 @@ spmm_status_t build_dynamic_csr_small(const int32_t* nnz_dev, const int32_t* row
 }
 
 
+
+// ------------------------------------------------------------------ row-range encoder
+// One launch, one workgroup per range of R block rows. Every workgroup reads
+// the whole COO list (validating it, so all reach the same verdict), counts
+// the entries above its range (its first CSR position) and keeps its own
+// entries in LDS as (row in range, column, input index) keys; an entry's CSR
+// place is its range's first position plus the number of kept keys below its
+// own, so the rows come out in order, each in (column, input index) order, the
+// canonical order of every other encoder.
+// No workgroup waits for another. Panels are not built here (no product
+// kernel reads them); dyn_panels derives them when a plan is exported.
+constexpr int kRowsThreads = 1024;  // with kRowsU, 8192 entries in one round of loads
+constexpr int kRowsU = 8;           // entries per thread loaded together
+
+__global__ __launch_bounds__(kRowsThreads) void k_dyn_rows(const int32_t* __restrict__ nnz_dev, int32_t max_nnz,
+                                                           const int32_t* __restrict__ rows,
+                                                           const int32_t* __restrict__ cols, int32_t mb, int32_t kb,
+                                                           int32_t R, int32_t* __restrict__ row_ptr,
+                                                           int32_t* __restrict__ col_idx, int32_t* __restrict__ src,
+                                                           int32_t* __restrict__ status,
+                                                           int32_t* __restrict__ status_out,
+                                                           int32_t* __restrict__ nnz_last) {
+  extern __shared__ uint64_t rows_lds[];
+  uint64_t* skey = rows_lds;                        // [max_nnz] (row in range << 53) | (column << 32) | input index
+  int32_t* cnt = (int32_t*)(skey + max_nnz);        // [R + 1] entries per own row, then their offsets
+  __shared__ int32_t flag[3];                       // [0] error, [1] kept entries, [2] nnz
+  __shared__ int32_t wsum[kRowsThreads / 64];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int32_t r0 = blockIdx.x * R, nr = min(mb - r0, R);
+  if (tid == 0) {
+    const int32_t nnz = *nnz_dev;
+    flag[0] = (nnz < 0 || nnz > max_nnz) ? (int32_t)SPMM_ERR_CAPACITY : 0;
+    flag[1] = 0;
+    flag[2] = nnz;
+  }
+  for (int32_t i = tid; i <= R; i += kRowsThreads) cnt[i] = 0;
+  __syncthreads();
+  const int32_t nnz = flag[2];
+  int32_t above = 0;  // entries of rows before r0 seen by this thread
+  if (flag[0] == 0) {
+    for (int32_t base = 0; base < nnz; base += kRowsThreads * kRowsU) {
+      int32_t er[kRowsU], ec[kRowsU];
+#pragma unroll
+      for (int u = 0; u < kRowsU; ++u) {
+        const int32_t e = base + u * kRowsThreads + tid;
+        er[u] = e < nnz ? rows[e] : 0;
+        ec[u] = e < nnz ? cols[e] : 0;
+      }
+#pragma unroll
+      for (int u = 0; u < kRowsU; ++u) {
+        const int32_t e = base + u * kRowsThreads + tid;
+        if (e >= nnz) continue;
+        const int32_t r = er[u], c = ec[u];
+        if (r < 0 || r >= mb || c < 0 || c >= kb) {
+          atomicMax(&flag[0], (int32_t)SPMM_ERR_BAD_INDEX);
+          continue;
+        }
+        if (r < r0) {
+          ++above;
+        } else if (r < r0 + nr) {
+          const int32_t slot = atomicAdd(&flag[1], 1);
+          skey[slot] = ((uint64_t)(uint32_t)(r - r0) << 53) | ((uint64_t)(uint32_t)c << 32) | (uint32_t)e;
+          atomicAdd(&cnt[r - r0], 1);
+        }
+      }
+    }
+  }
+  // the workgroup's count of entries above its rows
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) above += __shfl_xor(above, off);
+  if (lane == 0) wsum[wave] = above;
+  __syncthreads();
+  const int32_t err = flag[0];
+  if (err) {  // every workgroup read the same entries: the same verdict
+    if (blockIdx.x == 0 && tid == 0) {
+      *status = err;
+      if (status_out) *status_out = err;
+    }
+    return;
+  }
+  int32_t first = 0;
+#pragma unroll
+  for (int w = 0; w < kRowsThreads / 64; ++w) first += wsum[w];
+  // exclusive scan of the own rows' counts (R <= kRowsThreads: one per thread)
+  const int32_t v = tid < nr ? cnt[tid] : 0;
+  int32_t incl = v;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int32_t t = __shfl_up(incl, off);
+    if (lane >= off) incl += t;
+  }
+  __syncthreads();  // every thread has read cnt and the wave sums
+  if (lane == 63) wsum[wave] = incl;
+  __syncthreads();
+  int32_t wpre = 0;
+  for (int w = 0; w < wave; ++w) wpre += wsum[w];
+  if (tid < nr) cnt[tid] = wpre + incl - v;
+  if (tid == 0) cnt[nr] = flag[1];
+  __syncthreads();
+  for (int32_t i = tid; i < nr; i += kRowsThreads) row_ptr[r0 + i] = first + cnt[i];
+  if (r0 + nr == mb && tid == 0) row_ptr[mb] = first + flag[1];
+  if (blockIdx.x == 0 && tid == 0) {
+    *status = 0;
+    if (status_out) *status_out = 0;
+    if (nnz_last) *nnz_last = nnz;
+  }
+  const int32_t kept = flag[1];
+  for (int32_t i = tid; i < kept; i += kRowsThreads) {
+    const uint64_t key = skey[i];
+    int32_t rank = 0;
+#pragma unroll 8
+    for (int32_t j = 0; j < kept; ++j) rank += skey[j] < key ? 1 : 0;
+    col_idx[first + rank] = (int32_t)((key >> 32) & 0x1FFFFFu);
+    src[first + rank] = (int32_t)(uint32_t)key;
+  }
+}
+
+int32_t dyn_rows_per_wg(int32_t mb) { return std::max<int32_t>(1, std::min<int32_t>(kRowsThreads, (mb + 127) / 128)); }
+
+size_t dyn_rows_lds_bytes(int32_t max_nnz, int32_t mb) {
+  const int32_t R = dyn_rows_per_wg(mb);
+  return sizeof(uint64_t) * (size_t)max_nnz + sizeof(int32_t) * (size_t)(R + 1);
+}
+
+// The key packs a row of the range in 11 bits and a block column in 21.
+bool dynamic_rows_fits(int32_t max_nnz, int32_t mb, int32_t kb) {
+  return max_nnz >= 1 && kb <= (1 << 21) && dyn_rows_per_wg(mb) <= 1024 &&
+         dyn_rows_lds_bytes(max_nnz, mb) <= kDynRowsLdsMax;
+}
+
+spmm_status_t build_dynamic_csr_rows(const int32_t* nnz_dev, const int32_t* rows, const int32_t* cols,
+                                     int32_t max_nnz, int32_t mb, int32_t kb, PlanBuffers& pb, int32_t* status,
+                                     int32_t* status_out, int32_t* nnz_last, hipStream_t s) {
+  if (!dynamic_rows_fits(max_nnz, mb, kb)) return fail(SPMM_ERR_UNSUPPORTED, "capacity beyond the row-range encoder");
+  const int32_t R = dyn_rows_per_wg(mb);
+  const size_t lds = dyn_rows_lds_bytes(max_nnz, mb);
+  static bool attr_set = false;
+  if (!attr_set) {
+    SPMM_HIP(hipFuncSetAttribute((const void*)k_dyn_rows, hipFuncAttributeMaxDynamicSharedMemorySize, kDynRowsLdsMax));
+    attr_set = true;
+  }
+  hipLaunchKernelGGL(k_dyn_rows, dim3((unsigned)ceil_div(mb, R)), dim3(kRowsThreads), lds, s, nnz_dev, max_nnz, rows,
+                     cols, mb, kb, R, pb.row_ptr, pb.col_idx, pb.csr_src, status, status_out, nnz_last);
+  SPMM_HIP(hipGetLastError());
+  return SPMM_OK;
+}
+
+spmm_status_t dyn_panels(const Geometry& geo, int32_t mb, PlanBuffers& pb, const int32_t* status, hipStream_t s) {
+  hipLaunchKernelGGL(k_dyn_tail, dim3(1), dim3(kSmallThreads), 0, s, pb.row_ptr, geo.num_groups, geo.group_rows, mb,
+                     geo.num_panels, pb.cost_prefix, pb.panel_ptr, (const int32_t*)nullptr, status, (int32_t*)nullptr,
+                     (int32_t*)nullptr);
+  SPMM_HIP(hipGetLastError());
+  return SPMM_OK;
+}
 
 spmm_status_t build_dynamic_csr(const int32_t* nnz_dev, const int32_t* rows, const int32_t* cols, int32_t max_nnz,
                                 int32_t mb, int32_t kb, int32_t b, int32_t k, const Geometry& geo, PlanBuffers& pb,

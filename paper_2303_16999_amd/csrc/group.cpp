@@ -192,7 +192,8 @@ spmm_status_t spmm_group_run(spmm_group_t g, int32_t count, const spmm_plan_t* p
     if (n[i] == 0) continue;
     const spmm_plan_s* p = plans[i];
     // the tuned variant if any, else the rule on n
-    int32_t ns = variant_ns(plan_variant(p, n[i]));
+    const int32_t var = plan_variant(p, n[i]);
+    int32_t ns = variant_ns(var);
     if (ns != 2 && ns != 4 && ns != 8) ns = default_ns(n[i]);
     RunArgs a{};
     a.plan.m = (int32_t)p->m;
@@ -212,9 +213,10 @@ spmm_status_t spmm_group_run(spmm_group_t g, int32_t count, const spmm_plan_t* p
     a.num_heavy = p->num_heavy;
     a.heavy_flag = p->heavy_flag;
     a.heavy_rows = p->heavy_rows;
-    any_heavy = any_heavy || p->num_heavy > 0;
+    a.split_all = plan_split_all(p, n[i], ns, var);  // as the problem's own spmm_run_static would
+    any_heavy = any_heavy || p->num_heavy > 0 || a.split_all;
     void* dst = inline_table ? group_args_problem(g->args.data(), k) : (void*)(g->host[s] + (size_t)k * g->desc_bytes);
-    const int64_t units = group_problem_units(p->mb, n[i], ns, p->num_heavy);
+    const int64_t units = group_problem_units(p->mb, n[i], ns, a.split_all ? p->mb : p->num_heavy);
     if (units >= (int64_t)INT32_MAX) return fail(SPMM_ERR_UNSUPPORTED, "too many work units in one group");
     fill_row_problem(dst, a, p->pb.row_ptr, p->pb.col_idx, (int32_t)total, (int32_t)units);
     real_units += units;

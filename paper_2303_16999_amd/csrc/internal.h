@@ -42,7 +42,9 @@ int n_class(int64_t n);
 // the rule, 1 = the plain kernel, 2 = the other form where the plan has one
 // (the software-pipelined row kernel for b = 16/32 with W in the X type and
 // no split rows; the LDS-staged kernel for b = 4 with W in the X type), 3 =
-// the dense GEMM on the plan's dense copy (plans with dense dispatch).
+// the dense GEMM on the plan's dense copy (plans with dense dispatch), 4 = the
+// row kernel with every block row split over a workgroup's four waves (b =
+// 16, 16-bit X).
 constexpr int kFormShift = 8;
 inline int32_t variant_ns(int32_t v) { return v & 0xff; }
 inline int32_t variant_form(int32_t v) { return v >> kFormShift; }
@@ -53,6 +55,9 @@ bool valid_variant(int32_t b, int32_t v);
 int32_t plan_variant(const spmm_plan_s* p, int64_t n);
 // Whether the plan runs on the row-wise MFMA kernel (b = 16/32/64, 16-bit X).
 bool plan_uses_row_kernel(const spmm_plan_s* p);
+// Whether a run with n columns, tile width ns and this variant splits every
+// block row (form 4, else the rule split_all_preferred; SPMM_SPLIT_ALL forces).
+bool plan_split_all(const spmm_plan_s* p, int64_t n, int32_t ns, int32_t variant);
 // Enqueues Y = (M o W) X for a validated plan (no argument checks).
 spmm_status_t run_plan(const spmm_plan_s* p, int64_t n, const void* X, int64_t ldx, void* Y, int64_t ldy,
                        int32_t variant, bool relu, hipStream_t stream);
@@ -71,11 +76,12 @@ spmm_status_t run_dense(const spmm_plan_s* p, int64_t n, const void* X, int64_t 
                         hipStream_t s);
 
 // Autotuner table persisted as JSON (tune_cache.cpp). Key: (b, w, x, y,
-// density class, n class). load fills `table` from `path` when the file was
+// density class, n class, dense copy kept: its candidates include the dense
+// GEMM). load fills `table` from `path` when the file was
 // written for this device and HIP runtime (else leaves it unchanged); save
 // writes the whole table (a temporary file renamed over `path`). Both return
 // false on an unreadable or unwritable file and never fail a product.
-using TuneKey = std::tuple<int, int, int, int, int, int>;
+using TuneKey = std::tuple<int, int, int, int, int, int, int>;
 bool tune_cache_load(const char* path, std::map<TuneKey, int32_t>& table);
 bool tune_cache_save(const char* path, const std::map<TuneKey, int32_t>& table);
 

@@ -94,11 +94,20 @@ Geometry choose_geometry(int64_t m, int64_t k, int32_t b, int64_t nnz_hint, int6
 // re-read the weights more often than the extra occupancy pays back.)
 int32_t default_ns(int64_t n) { return n > 64 ? 8 : (n > 32 ? 4 : 2); }
 
-// Dynamic encode: the one-workgroup builder where it applies, unless
-// SPMM_DYN_BUILDER=multi asks for the multi-kernel one (for comparisons).
-static bool use_one_wg_builder() {
+// Dynamic encoders, in order of preference where they apply: the row-range
+// encoder (one launch, many workgroups), the one-workgroup encoder, the
+// multi-kernel one. Both single-launch encoders need b to divide k (values are
+// read in place). SPMM_DYN_BUILDER=rows|one|multi asks for one of them (for
+// comparisons; a builder that does not apply falls through to the next).
+enum DynBuilder { kBuilderNone = 0, kBuilderRows = 1, kBuilderOne = 2, kBuilderMulti = 3 };
+static int requested_builder() {
   const char* e = getenv("SPMM_DYN_BUILDER");
-  return !(e && std::string(e) == "multi");
+  if (!e) return kBuilderNone;
+  const std::string v(e);
+  if (v == "rows") return kBuilderRows;
+  if (v == "one") return kBuilderOne;
+  if (v == "multi") return kBuilderMulti;
+  return kBuilderNone;
 }
 
 static void free_plan_buffers(PlanBuffers& pb) {
@@ -186,7 +195,7 @@ bool valid_variant(int32_t b, int32_t v) {
   if (v == 0) return true;
   if (v < 0) return false;
   const int32_t ns = variant_ns(v), form = variant_form(v);
-  if (form > 3 || (ns != 0 && ns != 2 && ns != 4 && ns != 8)) return false;
+  if (form > 4 || (ns != 0 && ns != 2 && ns != 4 && ns != 8)) return false;
   return !(ns == 2 && b < 16);
 }
 
@@ -214,7 +223,7 @@ static TuneKey tune_key(const spmm_plan_s* p, int64_t n) {
   const double cells = (double)p->mb * (double)p->kb;
   const double d = cells > 0 ? (double)p->nnzb / cells : 0.0;
   const int dclass = d > 0 ? (int)std::lround(-std::log2(d)) : 64;
-  return TuneKey(p->b, (int)p->w, (int)p->x, (int)p->y, dclass, n_class(n));
+  return TuneKey(p->b, (int)p->w, (int)p->x, (int)p->y, dclass, n_class(n), p->dense_w ? 1 : 0);
 }
 
 static void tune_table_put(const spmm_plan_s* p, int64_t n, int32_t v) {
@@ -235,6 +244,13 @@ int32_t plan_variant(const spmm_plan_s* p, int64_t n) {
     if (it != g_tune.end()) return it->second;
   }
   return 0;
+}
+
+bool plan_split_all(const spmm_plan_s* p, int64_t n, int32_t ns, int32_t variant) {
+  if (p->b != 16 || !plan_uses_row_kernel(p)) return false;
+  const int32_t form = variant_form(variant);
+  if (form && !getenv("SPMM_SPLIT_ALL")) return form == 4;
+  return split_all_preferred(p->b, p->mb, n, ns, p->nnzb, device_cu_count());
 }
 
 spmm_status_t run_plan(const spmm_plan_s* p, int64_t n, const void* X, int64_t ldx, void* Y, int64_t ldy,
@@ -275,6 +291,8 @@ spmm_status_t run_plan(const spmm_plan_s* p, int64_t n, const void* X, int64_t l
     a.num_heavy = p->num_heavy;
     a.heavy_flag = p->heavy_flag;
     a.heavy_rows = p->heavy_rows;
+    a.split_all = plan_split_all(p, n, a.ns, variant);
+    if (a.split_all) return launch_spmm_row(a, p->pb.row_ptr, p->pb.col_idx, stream);
     const bool pp_ok = p->w == p->x && p->num_heavy == 0 && p->b <= 32;
     bool pp = pp_ok && row_pp_preferred(p->b, p->mb, n, a.ns, p->nnzb, device_cu_count());
     if (form && pp_ok && !getenv("SPMM_ROW_PP")) pp = form == 2;
@@ -292,6 +310,10 @@ spmm_status_t run_dynamic_kernel(RunArgs& a, const int32_t* row_ptr, const int32
     return launch_spmm_small_lds(a, row_ptr, col_idx, small_lds_rows_per_wave(b, a.plan.mb, a.n, device_cu_count()), s);
   if (b < 16) return launch_spmm_small(a, row_ptr, col_idx, s);
   if (a.xt == SPMM_F32) return launch_spmm_row_f32(a, row_ptr, col_idx, s);
+  if (split_all_preferred(b, a.plan.mb, a.n, a.ns, a.nnz, device_cu_count())) {
+    a.split_all = true;
+    return launch_spmm_row(a, row_ptr, col_idx, s);
+  }
   if (a.wt == a.xt && row_pp_preferred(b, a.plan.mb, a.n, a.ns, a.nnz, device_cu_count()))
     return launch_spmm_row_pp(a, row_ptr, col_idx, s);
   return launch_spmm_row(a, row_ptr, col_idx, s);
@@ -360,6 +382,7 @@ struct spmm_dyn_s {
   float* packed_scales = nullptr;
   int device = 0;
   bool ran = false;
+  bool panels_current = false;  // panel_ptr matches the last call's row_ptr
 };
 
 extern "C" {
@@ -384,7 +407,7 @@ spmm_status_t spmm_plan_static(int64_t m, int64_t k, int32_t b, const uint8_t* b
   if (opts && (opts->group_rows < 0 || opts->num_panels < 0))
     return fail(SPMM_ERR_INVALID_ARG, "negative plan option");
   if (opts && !valid_variant(b, opts->variant))
-    return fail(SPMM_ERR_INVALID_ARG, "variant must be 0 or (2, 4, 8 or 0) + 256 x (0 .. 3); 2 needs b >= 16");
+    return fail(SPMM_ERR_INVALID_ARG, "variant must be 0 or (2, 4, 8 or 0) + 256 x (0 .. 4); 2 needs b >= 16");
   if (opts && (opts->dense_dispatch < 0 || opts->dense_dispatch > 2))
     return fail(SPMM_ERR_INVALID_ARG, "dense_dispatch must be 0, 1 or 2");
   const int32_t dense_opt = opts ? opts->dense_dispatch : 0;
@@ -477,6 +500,7 @@ static int plan_candidates(const spmm_plan_s* p, int32_t (&c)[8]) {
     for (int32_t ns : {2, 4, 8}) c[k++] = make_variant(ns, 1);
     if (p->w == p->x && p->num_heavy == 0 && p->b <= 32)
       for (int32_t ns : {2, 4, 8}) c[k++] = make_variant(ns, 2);
+    if (p->b == 16) c[k++] = make_variant(0, 4);
   } else if (p->b < 16 && p->x != SPMM_F32) {
     c[k++] = make_variant(4, 1);
     c[k++] = make_variant(8, 1);
@@ -616,6 +640,14 @@ spmm_status_t spmm_autotune_static_all(spmm_plan_t p, int64_t n, const void* X, 
   return tune_plan(p, n, X, ldx, Y, ldy, (hipStream_t)stream, variants, times_ms, count, best);
 }
 
+spmm_status_t spmm_autotune_clear(void) {
+  clear_error();
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune.clear();
+  g_tune_loaded = true;  // not reloaded from the cache file
+  return SPMM_OK;
+}
+
 spmm_status_t spmm_plan_variant(spmm_plan_t p, int64_t n, int32_t* variant) {
   clear_error();
   if (!p || !variant) return fail(SPMM_ERR_INVALID_ARG, "NULL argument");
@@ -748,9 +780,19 @@ spmm_status_t spmm_run_dynamic(spmm_dyn_t h, const int32_t* nnzb_dev, const int3
   // order as a static plan of the same pattern). Small capacities encode in
   // one workgroup and leave the values in place (read through csr_src); edge
   // blocks that cross k need the copying path, which zeroes their tail.
-  const bool one_wg = h->k % h->b == 0 && use_one_wg_builder() &&
-                      dynamic_small_fits((int32_t)h->max_nnzb, h->mb, h->kb, h->geo.num_groups);
-  if (one_wg) {
+  const int want = requested_builder();
+  const bool in_place = h->k % h->b == 0 && want != kBuilderMulti;
+  const bool rows_fit = dynamic_rows_fits((int32_t)h->max_nnzb, h->mb, h->kb);
+  const bool one_fit = dynamic_small_fits((int32_t)h->max_nnzb, h->mb, h->kb, h->geo.num_groups);
+  int builder = kBuilderMulti;
+  if (in_place && rows_fit && want != kBuilderOne) builder = kBuilderRows;
+  else if (in_place && one_fit) builder = kBuilderOne;
+  else if (in_place && rows_fit) builder = kBuilderRows;
+  const bool one_wg = builder != kBuilderMulti;  // values read in place through csr_src
+  if (builder == kBuilderRows) {
+    st = build_dynamic_csr_rows(nnzb_dev, rows, cols, (int32_t)h->max_nnzb, h->mb, h->kb, h->pb, h->status,
+                                status_dev, h->nnz_last, s);
+  } else if (builder == kBuilderOne) {
     st = build_dynamic_csr_small(nnzb_dev, rows, cols, (int32_t)h->max_nnzb, h->mb, h->kb, h->geo, h->pb, h->status,
                                  status_dev, h->nnz_last, s);
   } else {
@@ -760,6 +802,7 @@ spmm_status_t spmm_run_dynamic(spmm_dyn_t h, const int32_t* nnzb_dev, const int3
   }
   if (st != SPMM_OK) return st;
   h->ran = true;
+  h->panels_current = builder != kBuilderRows;
   if (n == 0) return SPMM_OK;
   RunArgs a{};
   a.plan = kernel_plan(h->m, h->k, h->b, h->mb, h->kb, h->geo, h->pb);
@@ -786,6 +829,11 @@ spmm_status_t spmm_dynamic_export(spmm_dyn_t h, int32_t* row_ptr, int32_t* col_i
   if (!h->ran) return fail(SPMM_ERR_INVALID_ARG, "no dynamic call has run on this handle");
   spmm_status_t st = check_device(h->device);
   if (st != SPMM_OK) return st;
+  if (!h->panels_current && panel_ptr) {  // the row-range encoder leaves the panels to the export
+    SPMM_HIP(hipDeviceSynchronize());
+    if ((st = dyn_panels(h->geo, h->mb, h->pb, h->status, nullptr)) != SPMM_OK) return st;
+    h->panels_current = true;
+  }
   SPMM_HIP(hipDeviceSynchronize());
   int32_t status = 0, nnz = 0;
   SPMM_HIP(hipMemcpy(&status, h->status, sizeof(int32_t), hipMemcpyDeviceToHost));

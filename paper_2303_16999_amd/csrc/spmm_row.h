@@ -55,7 +55,7 @@ struct RowProblem {
   int32_t num_heavy;       // block rows split over the 4 waves of a workgroup
   int32_t num_units;       // grouped launch: work units of this problem
   const uint8_t* heavy_flag;  // [mb] nonzero for a split row (nullptr when num_heavy == 0)
-  const int32_t* heavy_rows;  // [num_heavy] the split rows
+  const int32_t* heavy_rows;  // [num_heavy] the split rows; nullptr with num_heavy == mb: every row, in order
 };
 
 struct Params {
@@ -586,7 +586,7 @@ __device__ __forceinline__ void row_unit(const RowProblem& p, int32_t unit, int 
   }
   if constexpr (SPLIT) {
   const int32_t hu = unit;
-  const int32_t r = sload(p.heavy_rows, hu % p.num_heavy);
+  const int32_t r = p.heavy_rows ? sload(p.heavy_rows, hu % p.num_heavy) : hu % p.num_heavy;  // no table: every row
   const int32_t n0 = (hu / p.num_heavy) * (16 * NS);
   const int32_t lo = sload(p.row_ptr, r), hi = sload(p.row_ptr, r + 1);
   const int32_t seg = (((hi - lo) + 7) / 8) * 2;  // a quarter of the row, rounded up to whole pairs
@@ -662,11 +662,17 @@ inline RowProblem row_problem(const RunArgs& a, const int32_t* row_ptr, const in
   p.num_heavy = a.heavy_rows ? a.num_heavy : 0;
   p.heavy_flag = p.num_heavy ? a.heavy_flag : nullptr;
   p.heavy_rows = p.num_heavy ? a.heavy_rows : nullptr;
+  if (a.split_all && a.plan.b == 16) {  // every row split, rows taken in order
+    p.num_heavy = a.plan.mb;
+    p.heavy_flag = nullptr;
+    p.heavy_rows = nullptr;
+  }
   return p;
 }
 
 // Work units of a problem (light and heavy) for a column-tile variant.
 inline int64_t problem_units(int32_t mb, int64_t n, int32_t ns, int32_t num_heavy) {
+  if (num_heavy >= mb) return (int64_t)num_heavy * ceil_div(n, 16 * ns);  // every row split: no light units
   const int64_t light =
       n > 16 * ns ? ceil_div(mb, 2) * ceil_div(n, 32 * ns) : ceil_div(mb, kRowsPerWg) * ceil_div(n, 16 * ns);
   return light + (int64_t)num_heavy * ceil_div(n, 16 * ns);

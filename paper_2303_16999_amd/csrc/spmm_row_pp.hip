@@ -207,6 +207,12 @@ bool row_pp_preferred(int32_t b, int32_t mb, int64_t n, int32_t ns, int64_t nnz,
          nnz >= (b == 16 ? 16 : 8) * (int64_t)mb;
 }
 
+bool split_all_preferred(int32_t b, int32_t mb, int64_t n, int32_t ns, int64_t nnz, int num_cus) {
+  if (b != 16) return false;
+  if (const char* e = getenv("SPMM_SPLIT_ALL")) return e[0] == '1';
+  return ceil_div(mb, kRowsPerWg) * ceil_div(n, 16 * ns) <= 2 * (int64_t)num_cus && nnz >= 16 * (int64_t)mb;
+}
+
 spmm_status_t launch_spmm_row_pp(const RunArgs& a, const int32_t* row_ptr, const int32_t* col_idx, hipStream_t s) {
   if (a.plan.b != 16 && a.plan.b != 32) return fail(SPMM_ERR_UNSUPPORTED, "pipelined row-wise kernel handles b = 16 and 32");
   if (a.wt == SPMM_FP8_E4M3 || a.wt != a.xt) return fail(SPMM_ERR_UNSUPPORTED, "pipelined row-wise kernel needs W in the X type");

@@ -1,13 +1,14 @@
 // The autotuner's table on disk: a small JSON file, written and read only by
 // this library.
 //
-//   {"format": "spmm-autotune-1", "device": "<arch>/<CUs>", "hip_runtime": N,
+//   {"format": "spmm-autotune-2", "device": "<arch>/<CUs>", "hip_runtime": N,
 //    "entries": [{"b": 16, "w": 1, "x": 1, "y": 1, "density_class": 4,
-//                 "n_class": 12, "variant": 264}, ...]}
+//                 "n_class": 12, "dense": 0, "variant": 264}, ...]}
 //
 // An entry maps a plan class (block size, dtypes as spmm_dtype_t codes,
 // density class = round(-log2 d), n class = exponent of the power of two at
-// or above n) to the variant code the tuner chose. A file written for another
+// or above n, whether the plan keeps a dense copy) to the variant code the
+// tuner chose. A file written for another
 // device or HIP runtime is ignored, as is one this reader cannot parse: the
 // tuner then measures again and overwrites it.
 #include <hip/hip_runtime.h>
@@ -25,7 +26,7 @@
 namespace spmm {
 namespace {
 
-constexpr const char* kFormat = "spmm-autotune-1";
+constexpr const char* kFormat = "spmm-autotune-2";
 
 bool device_identity(std::string* device, int* runtime) {
   int dev = 0;
@@ -89,12 +90,13 @@ bool tune_cache_load(const char* path, std::map<TuneKey, int32_t>& table) {
   while ((p = text.find('{', p + 1)) != std::string::npos) {
     const size_t q = text.find('}', p);
     if (q == std::string::npos) return false;
-    long long v[7];
-    const char* keys[7] = {"b", "w", "x", "y", "density_class", "n_class", "variant"};
-    for (int i = 0; i < 7; ++i)
+    long long v[8];
+    const char* keys[8] = {"b", "w", "x", "y", "density_class", "n_class", "dense", "variant"};
+    for (int i = 0; i < 8; ++i)
       if (!find_int(text, p, q, keys[i], &v[i])) return false;
-    if (!valid_variant((int32_t)v[0], (int32_t)v[6]) || v[6] == 0) return false;
-    got[TuneKey((int)v[0], (int)v[1], (int)v[2], (int)v[3], (int)v[4], (int)v[5])] = (int32_t)v[6];
+    if (!valid_variant((int32_t)v[0], (int32_t)v[7]) || v[7] == 0 || (v[6] != 0 && v[6] != 1)) return false;
+    if (v[6] == 0 && (v[7] >> kFormShift) == 3) return false;  // the dense form needs a dense copy
+    got[TuneKey((int)v[0], (int)v[1], (int)v[2], (int)v[3], (int)v[4], (int)v[5], (int)v[6])] = (int32_t)v[7];
     p = q;
   }
   for (const auto& kv : got) table.emplace(kv.first, kv.second);  // entries measured here win
@@ -113,7 +115,8 @@ bool tune_cache_save(const char* path, const std::map<TuneKey, int32_t>& table) 
     const TuneKey& k = kv.first;
     o << (first ? "\n  " : ",\n  ") << "{\"b\": " << std::get<0>(k) << ", \"w\": " << std::get<1>(k)
       << ", \"x\": " << std::get<2>(k) << ", \"y\": " << std::get<3>(k) << ", \"density_class\": " << std::get<4>(k)
-      << ", \"n_class\": " << std::get<5>(k) << ", \"variant\": " << kv.second << "}";
+      << ", \"n_class\": " << std::get<5>(k) << ", \"dense\": " << std::get<6>(k)
+      << ", \"variant\": " << kv.second << "}";
     first = false;
   }
   o << "\n]}\n";

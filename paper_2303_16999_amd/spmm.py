@@ -68,6 +68,7 @@ SIGNATURES = {
     "spmm_autotune_static_all": ([_vp, _c_i64, _vp, _c_i64, _vp, _c_i64, _vp, _c_i32, _pi32,
                                   ctypes.POINTER(ctypes.c_float), _pi32, _pi32], _c_i32),
     "spmm_plan_variant": ([_vp, _c_i64, _pi32], _c_i32),
+    "spmm_autotune_clear": ([], _c_i32),
     "spmm_plan_dispatch": ([_vp, ctypes.POINTER(ctypes.c_double), _pi32], _c_i32),
     "spmm_group_create": ([_c_i32, ctypes.POINTER(_vp)], _c_i32),
     "spmm_group_run": ([_vp, _c_i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp], _c_i32),
@@ -204,6 +205,11 @@ def _ld(t, ld, name):
     if int(ld) != int(t.stride(0)):
         raise ValueError("leading dimension of %s must be its row stride %d" % (name, t.stride(0)))
     return int(ld)
+
+
+def autotune_clear():
+    """spmm_autotune_clear: forget the process-wide table of tuned variants."""
+    check(lib().spmm_autotune_clear())
 
 
 class StaticPlan:

@@ -31,7 +31,7 @@ Y = torch.empty((mb * b, n), dtype=torch.float16, device="cuda")
 plan.run(X, Y)
 torch.cuda.synchronize()
 after = plan.variant_for(n)
-ref = spmm.StaticPlan(mb * b, kb * b, b, mask, "f16", variant=8 + 256)
+ref = spmm.StaticPlan(mb * b, kb * b, b, mask, "f16", variant=after or 8 + 256)  # the variant that ran
 ref.set_values(vals)
 Yr = torch.empty_like(Y)
 ref.run(X, Yr)
@@ -55,7 +55,7 @@ def test_first_run_tunes_and_cache_carries_the_choice(tmp_path):
     first = _child({"SPMM_AUTOTUNE_CACHE": cache})
     assert first["before"] == 0 and first["after"] != 0 and first["same"]
     doc = json.load(open(cache))
-    assert doc["format"] == "spmm-autotune-1" and doc["device"].startswith("gfx")
+    assert doc["format"] == "spmm-autotune-2" and doc["device"].startswith("gfx")
     assert any(e["b"] == 16 and e["variant"] == first["after"] for e in doc["entries"])
     second = _child({"SPMM_AUTOTUNE_CACHE": cache})
     assert second["before"] == first["after"] == second["after"] and second["same"]
@@ -68,9 +68,9 @@ def test_autotune_off_keeps_the_rule(tmp_path):
     assert not os.path.exists(cache)
 
 
-@pytest.mark.parametrize("content", ["not json at all", '{"format": "spmm-autotune-1", "device": "other/1", '
+@pytest.mark.parametrize("content", ["not json at all", '{"format": "spmm-autotune-2", "device": "other/1", '
                                      '"hip_runtime": 1, "entries": [{"b": 16, "w": 1, "x": 1, "y": 1, '
-                                     '"density_class": 3, "n_class": 9, "variant": 520}]}'])
+                                     '"density_class": 3, "n_class": 9, "dense": 0, "variant": 520}]}'])
 def test_foreign_or_broken_cache_is_ignored_and_rewritten(tmp_path, content):
     cache = tmp_path / "tune.json"
     cache.write_text(content)

@@ -65,6 +65,7 @@ def test_model_keeps_sparse_where_it_wins():
     assert O.rel_fro(got, c.oracle()) <= TOL["f16"]
 
 
+@pytest.mark.first_run_tuning
 def test_first_run_tuning_chooses_between_dense_and_sparse():
     c = Case(2048, 2048, 512, 4, 1 / 8, w="f16", seed=502)
     plan = _plan(c, 2)

@@ -20,8 +20,15 @@ def _dyn_inputs(rows, cols, vals_store, max_nnz, b):
 
 
 def test_dynamic_matches_oracle_and_static_bitwise():
+    # the static plan by the rule a dynamic call follows (tile width 8 for n =
+    # 256, kernel form by rule), whatever a tuned table holds
     c = Case(48 * 16, 40 * 16, 256, 16, 1 / 8, w="f16", seed=21)
-    plan, Ys = c.run_static(group_rows=8)
+    plan = spmm.StaticPlan(c.m, c.k, 16, c.mask, "f16", group_rows=8, variant=8)
+    vals, X0, _ = c.device_inputs()
+    plan.set_values(vals)
+    Ys = c.new_Y()
+    plan.run(X0, Ys, n=c.n)
+    torch.cuda.synchronize()
     max_nnz = len(c.rows) + 17
     perm = np.random.default_rng(5).permutation(len(c.rows))  # COO in random order
     r, col, v, nnz = _dyn_inputs(c.rows[perm], c.cols[perm], c.vals_store[perm], max_nnz, 16)
@@ -149,7 +156,7 @@ def test_one_workgroup_encoder_equals_multi_kernel_encoder(w, b, monkeypatch):
         r, c, v, nnz = _dyn_inputs(rows, cols, vals, max_nnz, b)
     X = dev(synth.to_storage(synth.normal((k, 192), 3), x or w))
     outs, exports = [], []
-    for builder in (None, "multi"):
+    for builder in (None, "one", "multi"):
         if builder:
             monkeypatch.setenv("SPMM_DYN_BUILDER", builder)
         else:
@@ -161,11 +168,91 @@ def test_one_workgroup_encoder_equals_multi_kernel_encoder(w, b, monkeypatch):
         assert status.item() == 0
         outs.append(Y)
         exports.append(h.export())
-    assert torch.equal(outs[0], outs[1])
+    assert torch.equal(outs[0], outs[1]) and torch.equal(outs[0], outs[2])
     ref = plan_ref.plan_from_coo(mb, kb, rows, cols, h.info()["group_rows"], h.info()["num_panels"])
     for ex in exports:
         for key in ("row_ptr", "col_idx", "src", "panel_ptr"):
             assert np.array_equal(ex[key], ref[key]), key
+
+
+@pytest.mark.parametrize("case", ["config3", "skewed", "ragged", "empty", "wide"])
+def test_row_range_encoder_equals_one_workgroup_encoder(case, monkeypatch):
+    """The row-range encoder (one workgroup per range of block rows) gives the
+    oracle's plan and the one-workgroup encoder's Y bit for bit: the dynamic
+    benchmark's grid, every entry in the first rows with repeated pairs (one
+    workgroup ranks them all), a block-row count its ranges do not divide,
+    an empty call, and more block columns than the bitmap form takes."""
+    b, n = 16, 80
+    g = np.random.default_rng(31)
+    if case == "config3":
+        mb, kb, max_nnz = 256, 256, 8192
+        rows, cols, vals = synth.dynamic_call(mb, kb, b, max_nnz, seed=32)
+    elif case == "skewed":
+        mb, kb, max_nnz = 300, 64, 3000
+        rows = g.integers(0, 3, 2900).astype(np.int32)
+        cols = g.integers(0, kb, 2900).astype(np.int32)
+        vals = synth.to_storage(synth.normal((2900, b, b), 33), "f16")
+    elif case == "ragged":
+        mb, kb, max_nnz = 301, 50, 4000
+        rows, cols, vals = synth.dynamic_call(mb, kb, b, max_nnz, seed=34)
+    elif case == "empty":
+        mb, kb, max_nnz = 40, 30, 100
+        rows, cols = np.zeros(0, np.int32), np.zeros(0, np.int32)
+        vals = np.zeros((0, b, b), np.float16)
+    else:
+        mb, kb, max_nnz = 8, 1100, 2000
+        rows, cols, vals = synth.dynamic_call(mb, kb, b, max_nnz, seed=35)
+    m, k = mb * b, kb * b
+    h = spmm.DynamicHandle(m, k, b, max_nnz, "f16", num_panels=5)
+    r, c, v, nnz = _dyn_inputs(rows, cols, vals, max_nnz, b)
+    X = dev(synth.to_storage(synth.normal((k, n), 36), "f16"))
+    outs, exports = [], []
+    for builder in ("rows", "one"):
+        monkeypatch.setenv("SPMM_DYN_BUILDER", builder)
+        Y = torch.full((m, n), float("nan"), dtype=torch.float16, device="cuda")
+        status = torch.full((1,), -1, dtype=torch.int32, device="cuda")
+        h.run(nnz, r, c, v, X, Y, status)
+        torch.cuda.synchronize()
+        assert status.item() == 0
+        outs.append(Y)
+        exports.append(h.export())
+    assert torch.equal(outs[0], outs[1])
+    ref = plan_ref.plan_from_coo(mb, kb, rows, cols, h.info()["group_rows"], h.info()["num_panels"])
+    for ex in exports:
+        assert ex["nnzb"] == len(rows)
+        for key in ("row_ptr", "col_idx", "src", "panel_ptr"):
+            assert np.array_equal(ex[key], ref[key]), key
+    if case == "empty":
+        assert torch.all(outs[0] == 0).item()
+
+
+def test_row_range_encoder_status_words(monkeypatch):
+    monkeypatch.setenv("SPMM_DYN_BUILDER", "rows")
+    b, m, k, n = 16, 64 * 16, 64 * 16, 32
+    h = spmm.DynamicHandle(m, k, b, 100, "f16")
+    X = torch.ones((k, n), dtype=torch.float16, device="cuda")
+    v = torch.ones((100, b, b), dtype=torch.float16, device="cuda")
+    status = torch.zeros(1, dtype=torch.int32, device="cuda")
+    base_r = list(range(50)) + [0] * 50
+    for rows, cols, nnz, want in [(base_r, [1] * 100, 101, spmm.ERR_CAPACITY),
+                                  (base_r[:49] + [64] + [0] * 50, [1] * 100, 50, spmm.ERR_BAD_INDEX),
+                                  (base_r, [1] * 30 + [70] + [1] * 69, 50, spmm.ERR_BAD_INDEX)]:
+        Y = torch.full((m, n), 7.0, dtype=torch.float16, device="cuda")
+        r = torch.tensor(rows, dtype=torch.int32, device="cuda")
+        c = torch.tensor(cols, dtype=torch.int32, device="cuda")
+        nz = torch.tensor([nnz], dtype=torch.int32, device="cuda")
+        h.run(nz, r, c, v, X, Y, status)
+        torch.cuda.synchronize()
+        assert status.item() == want
+        assert torch.all(Y == 7.0).item()
+    nz = torch.tensor([50], dtype=torch.int32, device="cuda")
+    r = torch.tensor(base_r, dtype=torch.int32, device="cuda")
+    c = torch.ones(100, dtype=torch.int32, device="cuda")
+    Y = torch.full((m, n), 7.0, dtype=torch.float16, device="cuda")
+    h.run(nz, r, c, v, X, Y, status)
+    torch.cuda.synchronize()
+    assert status.item() == 0
+    assert torch.all(Y[: 50 * b] == 16.0).item() and torch.all(Y[50 * b:] == 0).item()
 
 
 @pytest.mark.parametrize("b", [16, 32])
@@ -237,6 +324,7 @@ def test_bitmap_rank_equals_pairwise_rank(case, monkeypatch):
     r, c, v, nnz = _dyn_inputs(rows, cols, vals, max_nnz, b)
     X = dev(synth.to_storage(synth.normal((k, n), 96), "f16"))
     outs, exports = [], []
+    monkeypatch.setenv("SPMM_DYN_BUILDER", "one")
     for rank in (None, "pairwise"):
         if rank:
             monkeypatch.setenv("SPMM_DYN_RANK", rank)
