@@ -25,6 +25,8 @@ Other modes print their own JSON lines:
   --mode grid       the paper's sweep grid best over n and its power-law fit
   --mode copy       a 256 MiB device copy (counter calibration)
   --mode peaks      measured HBM bandwidth (copy, read) and dense FP16/BF16 GEMM rate
+  --mode dispatch   the speedup model's sparse-or-dense choice against measurement
+  --mode point      one static product (--point m,k,n,b,1/d,w,x,y), for profiling
 """
 import argparse
 import hashlib
@@ -57,7 +59,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--mode", default="headline",
                     choices=["headline", "sweep", "dynamic", "precision", "copy", "serve", "group", "table3", "small",
-                             "skew", "train", "grid", "ell", "peaks", "dispatch"])
+                             "skew", "train", "grid", "ell", "peaks", "dispatch", "point"])
     ap.add_argument("--requests", type=int, default=2000, help="serve mode: measured requests per run")
     ap.add_argument("--rho", default="0.5,0.8", help="serve mode: offered load as fractions of the saturated rate")
     ap.add_argument("--rate-base", type=float, default=0.0,
@@ -70,6 +72,8 @@ def parse():
     ap.add_argument("--calls", type=int, default=1000, help="dynamic mode: number of calls")
     ap.add_argument("--sweep-b", default="1,4,8,16,32", help="sweep mode: block sizes")
     ap.add_argument("--sweep-n", default="256,1024,4096", help="sweep mode: column counts")
+    ap.add_argument("--point", default="8192,8192,4096,16,16,f16,f16,f16",
+                    help="point mode: m,k,n,b,1/density,w,x,y of one static product")
     ap.add_argument("--grid-m", default="256,512,1024,2048,4096,8192", help="grid mode: feature sizes m = k")
     ap.add_argument("--grid-n", default="4,16,64,256,1024,4096,16384,65536", help="grid mode: batch sizes n")
     return ap.parse_args()
@@ -323,6 +327,8 @@ def mode_headline(args):
         "plan_build_ms": round(prob.plan_ms, 3),
         "plan_build_ms_warm": round(plan_build_warm_ms(prob), 3),
         "kernel_source_sha256_16": kernel_source_hash(),
+        "variant": prob.plan.variant_for(4096),
+        "kernel": variant_kernel(prob.plan.variant_for(4096), 16),
     }
     if dn is not None:
         rec["dense_fp16"] = {k: round(v, 4) for k, v in dn.items()}
@@ -380,6 +386,28 @@ def crossover_density(pts):
     if all(s < 1.0 for _, s in pts):
         return "below %g" % pts[0][0]
     return None
+
+
+def variant_kernel(variant, b):
+    """The kernel a static run of a row-kernel plan launches for a variant code."""
+    form = variant >> 8
+    if b >= 16:
+        return {2: "k_spmm_row_pp", 4: "k_spmm_row (every block row split)"}.get(form, "k_spmm_row")
+    return "k_spmm_small_lds" if form == 2 else "k_spmm_small"
+
+
+def mode_point(args):
+    """One static product (--point m,k,n,b,1/d,w,x,y), tuned on its first run
+    like any plan, then timed: for profiling a single configuration."""
+    m, k, n, b, dinv = (int(v) for v in args.point.split(",")[:5])
+    w, x, y = args.point.split(",")[5:8]
+    prob = StaticProblem(m, k, n, b, 1.0 / dinv, w, x=x, y=y, seed=0, scaled=(w == "fp8"))
+    ms = time_steps(prob.step, args.steps, args.warmup)
+    v = prob.plan.variant_for(n)
+    emit({"mode": "point", "m": m, "k": k, "n": n, "b": b, "density": 1.0 / dinv, "w": w, "x": x, "y": y,
+          "variant": v, "kernel": variant_kernel(v, b), "ms": round(ms, 5),
+          "tflops": round(prob.flops() / (ms * 1e-3) / 1e12, 3),
+          "alg_gbs": round(prob.alg_bytes() / (ms * 1e-3) / 1e9, 1)}, args.out)
 
 
 def mode_precision(args):
@@ -1070,7 +1098,7 @@ def main():
     {"headline": mode_headline, "sweep": mode_sweep, "precision": mode_precision, "copy": mode_copy,
      "dynamic": mode_dynamic, "serve": mode_serve, "group": mode_group, "table3": mode_table3,
      "small": mode_small, "skew": mode_skew, "train": mode_train, "grid": mode_grid,
-     "ell": mode_ell, "peaks": mode_peaks, "dispatch": mode_dispatch}[args.mode](args)
+     "ell": mode_ell, "peaks": mode_peaks, "dispatch": mode_dispatch, "point": mode_point}[args.mode](args)
 
 
 if __name__ == "__main__":
