@@ -203,6 +203,13 @@ spmm_status_t spmm_run_static(spmm_plan_t plan, int64_t n, const void* X, int64_
  * Errors: INVALID_ARG (NULL plan). */
 spmm_status_t spmm_plan_dispatch(spmm_plan_t plan, double* predicted_speedup, int32_t* has_dense);
 
+/* Device memory the plan holds: *device_bytes (may be NULL) all of its
+ * buffers (plan arrays, values, scales, split-row and SDDMM task lists, ELL
+ * slots, the dense copy), *value_bytes (may be NULL) its one copy of the block
+ * values and FP8 scales. Host bookkeeping only.
+ * Errors: INVALID_ARG (NULL plan). */
+spmm_status_t spmm_plan_memory(spmm_plan_t plan, int64_t* device_bytes, int64_t* value_bytes);
+
 spmm_status_t spmm_plan_info(spmm_plan_t plan, int64_t* nnzb, int32_t* group_rows,
                              int32_t* num_groups, int32_t* num_panels, int32_t* num_split_rows);
 
@@ -347,7 +354,13 @@ spmm_status_t spmm_dynamic_create(int64_t m, int64_t k, int32_t b, int64_t max_n
  * int32 that receives SPMM_OK, SPMM_ERR_CAPACITY (nnzb > max_nnzb or < 0) or
  * SPMM_ERR_BAD_INDEX (an index outside the block grid); on a non-OK status Y
  * is left untouched. The index and value buffers must hold max_nnzb entries'
- * worth of readable memory only up to the nnzb actually used. */
+ * worth of readable memory only up to the nnzb actually used. The first call
+ * of a handle for an n class (the power of two at or above n) times the
+ * compute kernel's variants on its own operands, as spmm_run_static does for
+ * a plan (it synchronises `stream`; not with SPMM_AUTOTUNE=0 or on a stream
+ * under capture, where the rules choose); later calls of that class run the
+ * fastest. Results equal a static plan's of the same pattern bit for bit when
+ * both run the same variant. */
 spmm_status_t spmm_run_dynamic(spmm_dyn_t h, const int32_t* nnzb_dev, const int32_t* block_row_dev,
                                const int32_t* block_col_dev, const void* values_dev,
                                const float* scales_dev, int64_t n, const void* X, int64_t ldx,

@@ -62,7 +62,8 @@ bool plan_split_all(const spmm_plan_s* p, int64_t n, int32_t ns, int32_t variant
 spmm_status_t run_plan(const spmm_plan_s* p, int64_t n, const void* X, int64_t ldx, void* Y, int64_t ldy,
                        int32_t variant, bool relu, hipStream_t stream);
 // The compute kernel of a dynamic call (a.plan, a.n, dtypes, W, status set).
-spmm_status_t run_dynamic_kernel(RunArgs& a, const int32_t* row_ptr, const int32_t* col_idx, hipStream_t s);
+spmm_status_t run_dynamic_kernel(RunArgs& a, const int32_t* row_ptr, const int32_t* col_idx, hipStream_t s,
+                                 int32_t variant = 0);
 spmm_status_t check_dense(const void* p, int64_t ld, int64_t n, int elem, const char* name);
 spmm_status_t check_device(int device);
 int32_t default_ns(int64_t n);

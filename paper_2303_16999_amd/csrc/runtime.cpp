@@ -302,21 +302,63 @@ spmm_status_t run_plan(const spmm_plan_s* p, int64_t n, const void* X, int64_t l
   return launch_spmm_row_f32(a, p->pb.row_ptr, p->pb.col_idx, stream);
 }
 
-// The compute kernel of a dynamic call on its block-CSR (never split rows).
-spmm_status_t run_dynamic_kernel(RunArgs& a, const int32_t* row_ptr, const int32_t* col_idx, hipStream_t s) {
+// The compute kernel of a dynamic call on its block-CSR (no split-row table):
+// variant 0 takes the rules, else its tile width and kernel form (forms 1
+// plain, 2 pipelined row kernel or LDS-staged b = 4 kernel, 4 every row split)
+// where the call's kernel has them; SPMM_SMALL_LDS, SPMM_ROW_PP and
+// SPMM_SPLIT_ALL still force their choice.
+spmm_status_t run_dynamic_kernel(RunArgs& a, const int32_t* row_ptr, const int32_t* col_idx, hipStream_t s,
+                                 int32_t variant) {
   const int32_t b = a.plan.b;
-  a.ns = b < 16 ? 0 : default_ns(a.n);
-  if (b < 16 && small_lds_preferred(b, a.wt, a.xt, a.nnz, a.plan.mb, a.plan.kb))
-    return launch_spmm_small_lds(a, row_ptr, col_idx, small_lds_rows_per_wave(b, a.plan.mb, a.n, device_cu_count()), s);
-  if (b < 16) return launch_spmm_small(a, row_ptr, col_idx, s);
+  const int32_t form = variant_form(variant);
+  const int cus = device_cu_count();
+  if (b < 16) {
+    bool lds = small_lds_preferred(b, a.wt, a.xt, a.nnz, a.plan.mb, a.plan.kb);
+    if (form && small_lds_eligible(b, a.wt, a.xt) && !getenv("SPMM_SMALL_LDS")) lds = form == 2;
+    if (lds) return launch_spmm_small_lds(a, row_ptr, col_idx, small_lds_rows_per_wave(b, a.plan.mb, a.n, cus), s);
+    a.ns = variant_ns(variant);
+    return launch_spmm_small(a, row_ptr, col_idx, s);
+  }
+  a.ns = variant_ns(variant) ? variant_ns(variant) : default_ns(a.n);
   if (a.xt == SPMM_F32) return launch_spmm_row_f32(a, row_ptr, col_idx, s);
-  if (split_all_preferred(b, a.plan.mb, a.n, a.ns, a.nnz, device_cu_count())) {
+  bool split = split_all_preferred(b, a.plan.mb, a.n, a.ns, a.nnz, cus);
+  if (form && b == 16 && !getenv("SPMM_SPLIT_ALL")) split = form == 4;
+  if (split) {
     a.split_all = true;
     return launch_spmm_row(a, row_ptr, col_idx, s);
   }
-  if (a.wt == a.xt && row_pp_preferred(b, a.plan.mb, a.n, a.ns, a.nnz, device_cu_count()))
-    return launch_spmm_row_pp(a, row_ptr, col_idx, s);
+  const bool pp_ok = a.wt == a.xt && b <= 32;
+  bool pp = pp_ok && row_pp_preferred(b, a.plan.mb, a.n, a.ns, a.nnz, cus);
+  if (form && pp_ok && !getenv("SPMM_ROW_PP")) pp = form == 2;
+  if (pp) return launch_spmm_row_pp(a, row_ptr, col_idx, s);
   return launch_spmm_row(a, row_ptr, col_idx, s);
+}
+
+// A run with no fixed and no tuned variant for its n class tunes first
+// (SPMM_AUTOTUNE=0 keeps the rule instead), except on a stream under capture.
+static bool tune_on_first_run(hipStream_t s) {
+  const char* e = getenv("SPMM_AUTOTUNE");
+  if (e && e[0] == '0') return false;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cs) != hipSuccess) return false;
+  return cs == hipStreamCaptureStatusNone;
+}
+
+
+// Candidate variants of a dynamic handle's compute kernel.
+static int dynamic_candidates(int32_t b, spmm_dtype_t w, spmm_dtype_t x, int32_t (&c)[8]) {
+  int k = 0;
+  if (b >= 16 && (x == SPMM_F16 || x == SPMM_BF16)) {
+    for (int32_t ns : {2, 4, 8}) c[k++] = make_variant(ns, 1);
+    if (w == x && b <= 32)
+      for (int32_t ns : {2, 4, 8}) c[k++] = make_variant(ns, 2);
+    if (b == 16) c[k++] = make_variant(0, 4);
+  } else if (b < 16 && x != SPMM_F32) {
+    c[k++] = make_variant(4, 1);
+    c[k++] = make_variant(8, 1);
+    if (small_lds_eligible(b, w, x)) c[k++] = make_variant(0, 2);
+  }
+  return k;
 }
 
 // Block rows longer than max(64, 4 x the mean row) are split over the four
@@ -383,6 +425,7 @@ struct spmm_dyn_s {
   int device = 0;
   bool ran = false;
   bool panels_current = false;  // panel_ptr matches the last call's row_ptr
+  int32_t tuned[32] = {};       // tuned compute variant per n class, 0 = none
 };
 
 extern "C" {
@@ -568,16 +611,6 @@ static spmm_status_t tune_plan(spmm_plan_s* p, int64_t n, const void* X, int64_t
   return SPMM_OK;
 }
 
-// A run with no fixed and no tuned variant for its n class tunes first
-// (SPMM_AUTOTUNE=0 keeps the rule instead), except on a stream under capture.
-static bool tune_on_first_run(hipStream_t s) {
-  const char* e = getenv("SPMM_AUTOTUNE");
-  if (e && e[0] == '0') return false;
-  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-  if (hipStreamIsCapturing(s, &cs) != hipSuccess) return false;
-  return cs == hipStreamCaptureStatusNone;
-}
-
 static spmm_status_t check_run_args(const spmm_plan_s* p, int64_t n, const void* X, int64_t ldx, const void* Y,
                                     int64_t ldy) {
   if (n > INT32_MAX / 2) return fail(SPMM_ERR_UNSUPPORTED, "n too large");
@@ -696,6 +729,25 @@ spmm_status_t spmm_plan_destroy(spmm_plan_t p) {
   if (p->ell_slot) (void)hipFree(p->ell_slot);
   if (p->dense_w) (void)hipFree(p->dense_w);
   delete p;
+  return SPMM_OK;
+}
+
+spmm_status_t spmm_plan_memory(spmm_plan_t p, int64_t* device_bytes, int64_t* value_bytes) {
+  clear_error();
+  if (!p) return fail(SPMM_ERR_INVALID_ARG, "plan is NULL");
+  auto n1 = [](int64_t c) { return std::max<int64_t>(c, 1); };  // as dev_alloc rounds
+  const int64_t nnz = p->nnzb;
+  int64_t idx = 4 * n1((int64_t)p->geo.num_panels + 1) + 4 * n1((int64_t)p->mb + 1) + 4 * n1(nnz) +
+                4 * (p->pb.order ? n1(nnz) : 0) + 4 * n1(p->pb.scratch_ints) + 8 * n1((int64_t)p->geo.num_groups + 1);
+  if (p->heavy_flag) idx += p->mb;
+  if (p->heavy_rows) idx += 4 * n1(p->num_heavy);
+  if (p->sddmm_tasks) idx += 8 * n1(p->sddmm_num_tasks);
+  if (p->ell_slot) idx += 4 * n1(nnz);
+  const int64_t vals = std::max<int64_t>(nnz * (int64_t)p->b * p->b * dtype_bytes(p->w), 16) +
+                       (p->scales ? 4 * n1(nnz) : 0);
+  const int64_t dense = p->dense_w ? p->m * p->k * (int64_t)dtype_bytes(p->w) : 0;
+  if (device_bytes) *device_bytes = idx + vals + dense;
+  if (value_bytes) *value_bytes = vals;
   return SPMM_OK;
 }
 
@@ -819,7 +871,49 @@ spmm_status_t spmm_run_dynamic(spmm_dyn_t h, const int32_t* nnzb_dev, const int3
   a.yt = h->y;
   a.status = h->status;
   a.nnz = h->max_nnzb;
-  return run_dynamic_kernel(a, h->pb.row_ptr, h->pb.col_idx, s);
+  // the first call of an n class times the compute kernel's variants on this
+  // call's block-CSR (the product is idempotent; the status word makes every
+  // candidate skip a failed encode alike), as a static plan's first run does
+  const int nc = n_class(n);
+  if (!h->tuned[nc] && tune_on_first_run(s)) {
+    int32_t cand[8];
+    const int ncand = dynamic_candidates(h->b, h->w, h->x, cand);
+    if (ncand > 1) {
+      hipEvent_t e0 = nullptr, e1 = nullptr;
+      SPMM_HIP(hipEventCreate(&e0));
+      hipError_t he = hipEventCreate(&e1);
+      int32_t best = 0;
+      float best_ms = 0.f;
+      for (int c = 0; c < ncand && he == hipSuccess && st == SPMM_OK; ++c) {
+        for (int i = 0; i < 2 && st == SPMM_OK; ++i) {
+          RunArgs t = a;
+          st = run_dynamic_kernel(t, h->pb.row_ptr, h->pb.col_idx, s, cand[c]);
+        }
+        if (st != SPMM_OK) break;
+        he = hipEventRecord(e0, s);
+        for (int i = 0; i < 5 && st == SPMM_OK && he == hipSuccess; ++i) {
+          RunArgs t = a;
+          st = run_dynamic_kernel(t, h->pb.row_ptr, h->pb.col_idx, s, cand[c]);
+        }
+        if (he == hipSuccess) he = hipEventRecord(e1, s);
+        if (he == hipSuccess) he = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+        if (he == hipSuccess && (!best || ms < best_ms)) {
+          best = cand[c];
+          best_ms = ms;
+        }
+      }
+      (void)hipEventDestroy(e0);
+      if (e1) (void)hipEventDestroy(e1);
+      if (st != SPMM_OK) return st;
+      if (he != hipSuccess) return fail_hip(he, "dynamic tuning");
+      int32_t enc = 0;  // a failed encode skipped every candidate: nothing was measured
+      SPMM_HIP(hipMemcpy(&enc, h->status, sizeof(int32_t), hipMemcpyDeviceToHost));
+      if (enc == 0) h->tuned[nc] = best;
+    }
+  }
+  return run_dynamic_kernel(a, h->pb.row_ptr, h->pb.col_idx, s, h->tuned[nc]);
 }
 
 spmm_status_t spmm_dynamic_export(spmm_dyn_t h, int32_t* row_ptr, int32_t* col_idx, int32_t* src, int32_t* panel_ptr,

@@ -369,7 +369,7 @@ __device__ __forceinline__ void row_tile_whole(const RowProblem& p, int32_t r, i
           acc[0][s] = Mma<XT>::k32(a[f], u32x4{b1[f][s].x, b1[f][s].y, b2[f][s].x, b2[f][s].y}, acc[0][s]);
       }
     }
-  } else if constexpr (!kFp8) {  // B == 32: k slots 0-3 and 4-7 are rows 8g..8g+3 and 8g+4..8g+7 k slots 0-3 and 4-7 are rows 8g..8g+3 and 8g+4..8g+7
+  } else if constexpr (!kFp8) {  // B == 32: k slots 0-3 and 4-7 are rows 8g..8g+3 and 8g+4..8g+7
     for (int32_t q = q_lo; q < q_hi; ++q) {
       const int32_t c = uniform(p.col_idx[q]);
       u32x2 b1[NS], b2[NS];

@@ -70,6 +70,7 @@ SIGNATURES = {
     "spmm_plan_variant": ([_vp, _c_i64, _pi32], _c_i32),
     "spmm_autotune_clear": ([], _c_i32),
     "spmm_plan_dispatch": ([_vp, ctypes.POINTER(ctypes.c_double), _pi32], _c_i32),
+    "spmm_plan_memory": ([_vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)], _c_i32),
     "spmm_group_create": ([_c_i32, ctypes.POINTER(_vp)], _c_i32),
     "spmm_group_run": ([_vp, _c_i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp], _c_i32),
     "spmm_group_destroy": ([_vp], _c_i32),
@@ -237,6 +238,12 @@ class StaticPlan:
                                    ctypes.byref(nh)))
         return {"nnzb": nnz.value, "group_rows": gr.value, "num_groups": ng.value, "num_panels": npn.value,
                 "num_split_rows": nh.value}
+
+    def memory(self):
+        """spmm_plan_memory: (device bytes of all the plan's buffers, bytes of its one value copy)."""
+        db, vb = ctypes.c_int64(), ctypes.c_int64()
+        check(lib().spmm_plan_memory(self._h, ctypes.byref(db), ctypes.byref(vb)))
+        return db.value, vb.value
 
     def dispatch(self):
         """spmm_plan_dispatch: (speedup model's sparse/dense ratio, keeps a dense copy)."""

@@ -5,7 +5,7 @@ import torch
 
 from oracle import plan_ref
 from oracle import spmm_ref as O
-from paper_2303_16999_amd import spmm
+from paper_2303_16999_amd import spmm, synth
 from gpu_cases import assert_elementwise, TOL, Case, dev, round_like, y_f64
 
 pytestmark = pytest.mark.gpu
@@ -138,3 +138,26 @@ def test_headline_shape_sampled_columns():
     assert err <= 5e-3, err
     assert_elementwise(got, ref, c.abs_oracle(cols), c.k, "f16")
     assert torch.isfinite(Y).all().item()
+
+
+def test_default_plan_holds_one_copy_of_the_values():
+    # b = 16, FP16, the headline pattern: values once, plus int32 indices
+    m = k = 8192
+    b = 16
+    mask = synth.block_mask(m // b, k // b, 1 / 16, 0)
+    nnzb = int(mask.sum())
+    vals = torch.zeros((nnzb, b, b), dtype=torch.float16, device="cuda")
+    torch.cuda.synchronize()
+    free0 = torch.cuda.mem_get_info()[0]
+    plan = spmm.StaticPlan(m, k, b, mask, "f16")
+    plan.set_values(vals)
+    torch.cuda.synchronize()
+    free1 = torch.cuda.mem_get_info()[0]
+    dev_bytes, val_bytes = plan.memory()
+    assert val_bytes == nnzb * b * b * 2
+    # indices: col_idx and the in-group order (4 + 4 bytes per block), row
+    # pointers, panels, scratch and the SDDMM task list: under 64 KiB + 12 B/block
+    assert val_bytes < dev_bytes <= val_bytes + 12 * nnzb + 64 * 1024
+    # what the device lost to the plan: one copy, never two (allocation rounding aside)
+    assert free0 - free1 < 1.5 * val_bytes + 4 * 2**20
+    plan.close()
