@@ -832,6 +832,7 @@ def mode_skew(args):
             ms = time_steps(prob.step, args.steps, args.warmup)
             rl = mask.sum(1)
             emit({"mode": "skew", "pattern": name, "split_long_rows": split,
+                  "variant": prob.plan.variant_for(4096),
                   "split_rows": prob.plan.info()["num_split_rows"], "max_row_blocks": int(rl.max()),
                   "mean_row_blocks": float(rl.mean()), "ms": round(ms, 5),
                   "tflops": round(prob.flops() / (ms * 1e-3) / 1e12, 3), "dense_ms": round(dn, 5),

@@ -170,6 +170,15 @@ int64_t group_problem_units(int32_t mb, int64_t n, int32_t ns, int32_t num_heavy
 // for the tasks of a plan (block row, first entry, up to sddmm_task_blocks(b)
 // blocks each), FP32 output in CSR order.
 int32_t sddmm_task_blocks(int32_t b);
+// Tiled SDDMM (b = 16/32): tasks of up to sddmm_tiled_task_blocks(b) blocks of
+// one tile of sddmm_tiled_tile_blocks(b) x sddmm_tiled_tile_blocks(b) blocks;
+// tasks [num_tasks][4] (tile row, tile column, first entry, count), entries
+// [nnz][2] (CSR index, block row in tile << 16 | block column in tile).
+int32_t sddmm_tiled_tile_blocks(int32_t b);
+int32_t sddmm_tiled_task_blocks(int32_t b);
+spmm_status_t launch_sddmm_tiled(spmm_dtype_t t, int32_t b, const int32_t* tasks, const int32_t* ent,
+                                 int32_t num_tasks, int64_t m, int64_t k, int64_t n, const void* dY, int64_t lddy,
+                                 const void* X, int64_t ldx, float* G, hipStream_t s);
 spmm_status_t launch_sddmm(spmm_dtype_t t, int32_t b, const int32_t* row_ptr, const int32_t* col_idx,
                            const int32_t* tasks, int32_t num_tasks, int64_t m, int64_t k, int64_t n, const void* dY,
                            int64_t lddy, const void* X, int64_t ldx, float* G, hipStream_t stream);

@@ -26,6 +26,9 @@ struct spmm_plan_s {
   int32_t* heavy_rows = nullptr;   // device [num_heavy]
   int32_t* sddmm_tasks = nullptr;  // device [sddmm_num_tasks][2] (16-bit X, b <= 32)
   int32_t sddmm_num_tasks = 0;
+  int32_t* sddmm_tiled_tasks = nullptr;  // device [n][4] (b = 16/32): tile row, tile column, first, count
+  int32_t* sddmm_tiled_ent = nullptr;    // device [nnzb][2]: CSR index, packed block position in its tile
+  int32_t sddmm_tiled_num = 0;
   double predicted_speedup = 0.0;  // speedup model's sparse/dense ratio for this plan's shape
   int32_t dense_mode = 0;          // dense dispatch option (0 off, 1 where the model favours dense, 2 always)
   void* dense_w = nullptr;         // dense copy of M o W (m x k, row-major) when the plan keeps one

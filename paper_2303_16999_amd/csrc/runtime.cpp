@@ -365,6 +365,50 @@ static int dynamic_candidates(int32_t b, spmm_dtype_t w, spmm_dtype_t x, int32_t
 // waves of a workgroup by the row-wise kernel for b = 16 (a long row would
 // otherwise be one wave's serial chain). SPMM_SPLIT=0 turns this off (for
 // comparisons).
+// Tiled SDDMM tasks (b = 16/32): the blocks of each tile of T x T blocks (T =
+// sddmm_tiled_tile_blocks), listed by block row then column, in tasks of at
+// most sddmm_tiled_task_blocks; tiles in (tile row, tile column) order.
+static spmm_status_t build_sddmm_tiled(spmm_plan_s* p, const std::vector<int32_t>& rp) {
+  if (p->b != 16 && p->b != 32) return SPMM_OK;
+  const int64_t nnz = p->nnzb;
+  if (nnz == 0) return SPMM_OK;
+  std::vector<int32_t> ci((size_t)nnz);
+  SPMM_HIP(hipMemcpy(ci.data(), p->pb.col_idx, sizeof(int32_t) * nnz, hipMemcpyDeviceToHost));
+  const int32_t T = sddmm_tiled_tile_blocks(p->b), cap = sddmm_tiled_task_blocks(p->b);
+  const int32_t tcols = (int32_t)ceil_div(p->kb, T);
+  std::vector<int32_t> ent, tasks;
+  ent.reserve((size_t)nnz * 2);
+  std::vector<std::vector<int32_t>> tile((size_t)tcols);  // CSR indices per tile column of one tile row
+  for (int32_t tr = 0; tr * T < p->mb; ++tr) {
+    for (auto& v : tile) v.clear();
+    for (int32_t r = tr * T; r < std::min(p->mb, (tr + 1) * T); ++r)
+      for (int32_t q = rp[r]; q < rp[r + 1]; ++q) tile[ci[q] / T].push_back(q);
+    for (int32_t tc = 0; tc < tcols; ++tc) {
+      const std::vector<int32_t>& v = tile[tc];
+      for (size_t o = 0; o < v.size(); o += cap) {
+        tasks.push_back(tr);
+        tasks.push_back(tc);
+        tasks.push_back((int32_t)(ent.size() / 2));
+        tasks.push_back((int32_t)std::min<size_t>(cap, v.size() - o));
+        for (size_t e = o; e < std::min(v.size(), o + cap); ++e) {
+          const int32_t q = v[e];
+          int32_t r = 0;  // block row of entry q: the row whose range holds it
+          r = (int32_t)(std::upper_bound(rp.begin(), rp.end(), q) - rp.begin()) - 1;
+          ent.push_back(q);
+          ent.push_back(((r - tr * T) << 16) | (ci[q] - tc * T));
+        }
+      }
+    }
+  }
+  p->sddmm_tiled_num = (int32_t)(tasks.size() / 4);
+  spmm_status_t st = dev_alloc(&p->sddmm_tiled_tasks, (int64_t)tasks.size());
+  if (st == SPMM_OK) st = dev_alloc(&p->sddmm_tiled_ent, (int64_t)ent.size());
+  if (st != SPMM_OK) return st;
+  SPMM_HIP(hipMemcpy(p->sddmm_tiled_tasks, tasks.data(), sizeof(int32_t) * tasks.size(), hipMemcpyHostToDevice));
+  SPMM_HIP(hipMemcpy(p->sddmm_tiled_ent, ent.data(), sizeof(int32_t) * ent.size(), hipMemcpyHostToDevice));
+  return SPMM_OK;
+}
+
 // SDDMM tasks of a plan: (block row, first entry) for every run of up to
 // sddmm_task_blocks(b) consecutive blocks of one row.
 static spmm_status_t build_sddmm_tasks(spmm_plan_s* p, const std::vector<int32_t>& rp) {
@@ -502,6 +546,7 @@ spmm_status_t spmm_plan_static(int64_t m, int64_t k, int32_t b, const uint8_t* b
     if (e != hipSuccess) st = fail_hip(e, "row pointer download");
     if (st == SPMM_OK && b == 16 && x != SPMM_F32) st = classify_heavy_rows(p, rp);
     if (st == SPMM_OK && sddmm) st = build_sddmm_tasks(p, rp);
+    if (st == SPMM_OK && sddmm) st = build_sddmm_tiled(p, rp);
   }
   if (s) (void)hipStreamDestroy(s);
   if (mask_dev) (void)hipFree(mask_dev);
@@ -512,6 +557,8 @@ spmm_status_t spmm_plan_static(int64_t m, int64_t k, int32_t b, const uint8_t* b
     if (p->heavy_flag) (void)hipFree(p->heavy_flag);
     if (p->heavy_rows) (void)hipFree(p->heavy_rows);
     if (p->sddmm_tasks) (void)hipFree(p->sddmm_tasks);
+    if (p->sddmm_tiled_tasks) (void)hipFree(p->sddmm_tiled_tasks);
+    if (p->sddmm_tiled_ent) (void)hipFree(p->sddmm_tiled_ent);
     if (p->ell_slot) (void)hipFree(p->ell_slot);
     delete p;
     return st;
@@ -728,6 +775,8 @@ spmm_status_t spmm_plan_destroy(spmm_plan_t p) {
   if (p->sddmm_tasks) (void)hipFree(p->sddmm_tasks);
   if (p->ell_slot) (void)hipFree(p->ell_slot);
   if (p->dense_w) (void)hipFree(p->dense_w);
+  if (p->sddmm_tiled_tasks) (void)hipFree(p->sddmm_tiled_tasks);
+  if (p->sddmm_tiled_ent) (void)hipFree(p->sddmm_tiled_ent);
   delete p;
   return SPMM_OK;
 }
@@ -742,6 +791,7 @@ spmm_status_t spmm_plan_memory(spmm_plan_t p, int64_t* device_bytes, int64_t* va
   if (p->heavy_flag) idx += p->mb;
   if (p->heavy_rows) idx += 4 * n1(p->num_heavy);
   if (p->sddmm_tasks) idx += 8 * n1(p->sddmm_num_tasks);
+  if (p->sddmm_tiled_tasks) idx += 16 * n1(p->sddmm_tiled_num) + 8 * n1(nnz);
   if (p->ell_slot) idx += 4 * n1(nnz);
   const int64_t vals = std::max<int64_t>(nnz * (int64_t)p->b * p->b * dtype_bytes(p->w), 16) +
                        (p->scales ? 4 * n1(nnz) : 0);

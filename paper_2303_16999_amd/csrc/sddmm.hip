@@ -261,6 +261,157 @@ __global__ __launch_bounds__(256) void k_sddmm(SddmmParams p) {
   }
 }
 
+// ------------------------------------------------------------------ tiled form
+// For b = 16 and 32: a task is up to 64 MFMA tiles (16 x 16) of the nonzero
+// blocks of one tile of kTile rows of dY by kTile rows of X (kTile / b block
+// rows by kTile / b block columns). The workgroup walks n in chunks of kNK:
+// each thread brings one dY row and one X row of the chunk into LDS (two
+// buffers: the next chunk's loads are in flight while the current one is
+// multiplied), and each wave multiplies its blocks' fragments out of LDS.
+// Every dY and X row of the tile is read from memory once per task instead of
+// once per block, which pays where a tile holds many blocks.
+constexpr int kTile = 256;                 // rows of dY and of X per tile (one per thread)
+constexpr int kNK = 32;                    // n values per chunk: one K = 32 MFMA step
+constexpr int kLdw = kNK + 8;              // LDS row stride in elements (16-byte aligned, spreads banks)
+constexpr int kTileMfmas = 16;             // MFMA tiles per wave
+constexpr int kTiledLds = 2 * 2 * kTile * kLdw * 2;  // two buffers of dY and X rows: 80 KiB
+
+struct TiledParams {
+  const int32_t* tasks;  // [num_tasks][4]: tile row, tile column, first entry, count
+  const int32_t* ent;    // [nnz][2]: CSR index, (block row in tile << 16) | block column in tile
+  int32_t num_tasks;
+  const void* dY;
+  const void* X;
+  float* G;
+  int64_t lddy, ldx;
+  int32_t m, k, n;
+  uint32_t dy_bytes, x_bytes;
+};
+
+__device__ __forceinline__ void sync_lds() {
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0) only: the next chunk's global loads stay in flight
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+}
+
+// The chunk's loads: 512 rows (the tile's 256 dY rows, then its 256 X rows)
+// of 32 values, four 16-byte segments per row; thread t takes segment t % 4
+// of rows t / 4 + 64 i (i = 0 .. 7), so four consecutive lanes read one row's
+// 64 contiguous bytes. Zero past m or k (buffer bounds) and past n (masked).
+__device__ __forceinline__ void load_chunk(__amdgpu_buffer_rsrc_t dyr, __amdgpu_buffer_rsrc_t xr, const TiledParams& p,
+                                           int64_t dy0, int64_t x0, int32_t c0, int tid, u32x4 (&v)[8]) {
+  const int seg = tid & 3, r0 = tid >> 2;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const int row = r0 + 64 * i;  // 0 .. 511
+    if (i < 4) v[i] = load8(dyr, dy0 + row, p.m, p.lddy, c0 + 8 * seg, p.n);
+    else v[i] = load8(xr, x0 + (row - kTile), p.k, p.ldx, c0 + 8 * seg, p.n);
+  }
+}
+
+template <typename T, int B>
+__global__ __launch_bounds__(256) void k_sddmm_tiled(TiledParams p) {
+  constexpr int H = B / 16;
+  constexpr int BW = kTileMfmas / (H * H);  // blocks per wave
+  extern __shared__ uint4 tl_lds[];
+  uint16_t* lds = (uint16_t*)tl_lds;  // [buf][dY, X][kTile][kLdw]
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int g = lane >> 4, j = lane & 15;
+  const int32_t t = xcd_task(blockIdx.x, p.num_tasks);
+  const int32_t tr = sload(p.tasks, 4 * (int64_t)t), tc = sload(p.tasks, 4 * (int64_t)t + 1);
+  const int32_t first = sload(p.tasks, 4 * (int64_t)t + 2), count = sload(p.tasks, 4 * (int64_t)t + 3);
+  // this wave's blocks: entries first + wave * BW .. (fewer in the last wave)
+  const int32_t w0 = wave * BW, nb = max(0, min(BW, count - w0));
+  int32_t q[BW], rl[BW], cl[BW];
+#pragma unroll
+  for (int e = 0; e < BW; ++e) {
+    const bool on = e < nb;
+    q[e] = on ? sload(p.ent, 2 * (int64_t)(first + w0 + e)) : 0;
+    const int32_t rc = on ? sload(p.ent, 2 * (int64_t)(first + w0 + e) + 1) : 0;
+    rl[e] = rc >> 16;
+    cl[e] = rc & 0xFFFF;
+  }
+  __amdgpu_buffer_rsrc_t dyr = __builtin_amdgcn_make_buffer_rsrc((void*)p.dY, (short)0, (int)p.dy_bytes, 0x00020000);
+  __amdgpu_buffer_rsrc_t xr = __builtin_amdgcn_make_buffer_rsrc((void*)p.X, (short)0, (int)p.x_bytes, 0x00020000);
+  const int64_t dy0 = (int64_t)tr * kTile, x0 = (int64_t)tc * kTile;
+  float4_t acc[BW][H][H];
+#pragma unroll
+  for (int e = 0; e < BW; ++e)
+#pragma unroll
+    for (int a = 0; a < H; ++a)
+#pragma unroll
+      for (int bb = 0; bb < H; ++bb) acc[e][a][bb] = float4_t{0.f, 0.f, 0.f, 0.f};
+  auto stage = [&](int buf, const u32x4 (&v)[8]) {
+    const int seg = tid & 3, r0 = tid >> 2;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) *(u32x4*)(lds + (buf * 2 * kTile + r0 + 64 * i) * kLdw + 8 * seg) = v[i];
+  };
+  const int32_t chunks = (p.n + kNK - 1) / kNK;
+  u32x4 v[8];
+  load_chunk(dyr, xr, p, dy0, x0, 0, tid, v);
+  stage(0, v);
+  if (chunks > 1) load_chunk(dyr, xr, p, dy0, x0, kNK, tid, v);
+  sync_lds();
+  for (int32_t ch = 0; ch < chunks; ++ch) {
+    const int buf = ch & 1;
+    const uint16_t* ly = lds + (buf * 2 + 0) * kTile * kLdw;
+    const uint16_t* lx = lds + (buf * 2 + 1) * kTile * kLdw;
+    // a task lists its blocks by row, so consecutive blocks of a wave often
+    // share their dY fragments: loaded once per run of one row
+    u32x4 av[H];
+#pragma unroll
+    for (int e = 0; e < BW; ++e) {
+      if (e < nb) {
+        if (e == 0 || rl[e] != rl[e - 1]) {
+#pragma unroll
+          for (int a = 0; a < H; ++a) av[a] = *(const u32x4*)(ly + (rl[e] * B + 16 * a + j) * kLdw + 8 * g);
+        }
+#pragma unroll
+        for (int bb = 0; bb < H; ++bb) {
+          const u32x4 bv = *(const u32x4*)(lx + (cl[e] * B + 16 * bb + j) * kLdw + 8 * g);
+#pragma unroll
+          for (int a = 0; a < H; ++a) acc[e][a][bb] = Mfma<T>::k32(av[a], bv, acc[e][a][bb]);
+        }
+      }
+    }
+    if (ch + 1 < chunks) {
+      stage(buf ^ 1, v);  // chunk ch + 1 (its loads were issued one chunk ago)
+      if (ch + 2 < chunks) load_chunk(dyr, xr, p, dy0, x0, (ch + 2) * kNK, tid, v);
+    }
+    sync_lds();  // chunk ch consumed by every wave; chunk ch + 1 staged
+  }
+  // D[4g + i][j] of tile (a, bb): element (16a + 4g + i, 16bb + j) of the block
+#pragma unroll
+  for (int e = 0; e < BW; ++e) {
+    if (e < nb) {
+      float* out = p.G + (int64_t)q[e] * B * B;
+#pragma unroll
+      for (int a = 0; a < H; ++a)
+#pragma unroll
+        for (int bb = 0; bb < H; ++bb)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) out[(16 * a + 4 * g + i) * B + 16 * bb + j] = acc[e][a][bb][i];
+    }
+  }
+}
+
+template <typename T>
+spmm_status_t launch_tiled_t(const TiledParams& p, int32_t b, hipStream_t s) {
+  static bool attr = false;
+  if (!attr) {
+    SPMM_HIP(hipFuncSetAttribute((const void*)k_sddmm_tiled<T, 16>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 kTiledLds));
+    SPMM_HIP(hipFuncSetAttribute((const void*)k_sddmm_tiled<T, 32>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 kTiledLds));
+    attr = true;
+  }
+  if (b == 16) hipLaunchKernelGGL((k_sddmm_tiled<T, 16>), dim3((unsigned)p.num_tasks), dim3(256), kTiledLds, s, p);
+  else hipLaunchKernelGGL((k_sddmm_tiled<T, 32>), dim3((unsigned)p.num_tasks), dim3(256), kTiledLds, s, p);
+  SPMM_HIP(hipGetLastError());
+  return SPMM_OK;
+}
+
 template <typename T>
 spmm_status_t launch_t(const SddmmParams& p, int32_t b, hipStream_t s) {
   // Few tasks: split n over the 4 waves of a workgroup so the chip fills;
@@ -291,6 +442,36 @@ spmm_status_t launch_t(const SddmmParams& p, int32_t b, hipStream_t s) {
 }
 
 }  // namespace
+
+int32_t sddmm_tiled_tile_blocks(int32_t b) { return kTile / b; }
+int32_t sddmm_tiled_task_blocks(int32_t b) { return 4 * kTileMfmas / ((b / 16) * (b / 16)); }
+
+spmm_status_t launch_sddmm_tiled(spmm_dtype_t t, int32_t b, const int32_t* tasks, const int32_t* ent,
+                                 int32_t num_tasks, int64_t m, int64_t k, int64_t n, const void* dY, int64_t lddy,
+                                 const void* X, int64_t ldx, float* G, hipStream_t s) {
+  if (b != 16 && b != 32) return fail(SPMM_ERR_UNSUPPORTED, "the tiled SDDMM handles block sizes 16 and 32");
+  if (num_tasks == 0 || n == 0) return SPMM_OK;
+  const int64_t dyb = m * lddy * 2, xb = k * ldx * 2;
+  if (dyb >= (int64_t)INT32_MAX || xb >= (int64_t)INT32_MAX)
+    return fail(SPMM_ERR_UNSUPPORTED, "dY or X larger than 2 GiB is not supported");
+  TiledParams p;
+  p.tasks = tasks;
+  p.ent = ent;
+  p.num_tasks = num_tasks;
+  p.dY = dY;
+  p.X = X;
+  p.G = G;
+  p.lddy = lddy;
+  p.ldx = ldx;
+  p.m = (int32_t)m;
+  p.k = (int32_t)k;
+  p.n = (int32_t)n;
+  p.dy_bytes = (uint32_t)dyb;
+  p.x_bytes = (uint32_t)xb;
+  if (t == SPMM_F16) return launch_tiled_t<_Float16>(p, b, s);
+  if (t == SPMM_BF16) return launch_tiled_t<__bf16>(p, b, s);
+  return fail(SPMM_ERR_UNSUPPORTED, "SDDMM needs FP16 or BF16 dY and X");
+}
 
 int32_t sddmm_task_blocks(int32_t b) {
   switch (b) {

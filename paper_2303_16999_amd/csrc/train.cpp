@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 #include <numeric>
 #include <vector>
 
@@ -26,6 +27,17 @@ __global__ void k_transpose_blocks(const int32_t* __restrict__ map, int64_t nnz,
     dst[i] = src[s * bb + (int64_t)c * b + r];
     if (w == 0 && ssrc) sdst[e] = ssrc[s];
   }
+}
+
+// The tiled SDDMM reads a tile's dY and X rows once per task (2 kTile rows)
+// where the per-block form reads each block's X rows and its row's dY rows
+// (about 1.25 row slabs of 16 per b = 16 block, 3 per b = 32 block): it pays
+// from about 24 blocks of 16 (8 of 32) per task. SPMM_SDDMM_TILED=0/1 forces
+// the choice.
+bool sddmm_tiled_preferred(const spmm_plan_s* p) {
+  if (!p->sddmm_tiled_tasks || p->sddmm_tiled_num == 0) return false;
+  if (const char* e = getenv("SPMM_SDDMM_TILED")) return e[0] == '1';
+  return p->nnzb >= (int64_t)p->sddmm_tiled_num * (p->b == 16 ? 24 : 8);
 }
 
 }  // namespace
@@ -123,6 +135,9 @@ spmm_status_t spmm_sddmm(spmm_plan_t p, int64_t n, const void* dY, int64_t lddy,
   }
   if ((st = check_dense(dY, lddy, n, 2, "dY")) != SPMM_OK) return st;
   if ((st = check_dense(X, ldx, n, 2, "X")) != SPMM_OK) return st;
+  if (sddmm_tiled_preferred(p))
+    return launch_sddmm_tiled(p->x, p->b, p->sddmm_tiled_tasks, p->sddmm_tiled_ent, p->sddmm_tiled_num, p->m, p->k, n,
+                              dY, lddy, X, ldx, G, (hipStream_t)stream);
   return launch_sddmm(p->x, p->b, p->pb.row_ptr, p->pb.col_idx, p->sddmm_tasks, p->sddmm_num_tasks, p->m, p->k, n, dY,
                       lddy, X, ldx, G, (hipStream_t)stream);
 }

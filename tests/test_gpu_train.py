@@ -127,10 +127,12 @@ def _sddmm(c, plan, dY, X, n=None):
     return G[:nnzb].cpu().numpy().astype(np.float64)
 
 
-@pytest.mark.parametrize("b", [1, 4, 8, 16, 32])
+@pytest.mark.parametrize("b,tiled", [(1, "0"), (4, "0"), (8, "0"), (16, "0"), (16, "1"), (32, "0"), (32, "1")])
 @pytest.mark.parametrize("dt", ["f16", "bf16"])
 @pytest.mark.parametrize("n", [1, 31, 77, 300])
-def test_sddmm_matches_oracle(b, dt, n):
+def test_sddmm_matches_oracle(b, tiled, dt, n, monkeypatch):
+    # tiled: the form that stages a tile's dY and X rows in LDS (b = 16/32)
+    monkeypatch.setenv("SPMM_SDDMM_TILED", tiled)
     c = Case(23 * b + 5, 31 * b + 11, n, b, 1 / 5, w=dt, seed=50 + b + n)
     plan = _plan(c)
     _, X, _ = c.device_inputs()
@@ -148,8 +150,9 @@ def test_sddmm_matches_oracle(b, dt, n):
             assert not G[e, :, kk:].any()
 
 
-@pytest.mark.parametrize("b", [1, 4, 8, 16, 32])
-def test_sddmm_integer_data_bit_exact(b):
+@pytest.mark.parametrize("b,tiled", [(1, "0"), (4, "0"), (8, "0"), (16, "0"), (16, "1"), (32, "0"), (32, "1")])
+def test_sddmm_integer_data_bit_exact(b, tiled, monkeypatch):
+    monkeypatch.setenv("SPMM_SDDMM_TILED", tiled)
     c = Case(17 * b + 7, 19 * b + 2, 250, b, 1 / 4, w="bf16", seed=70, integer=True)
     plan = _plan(c)
     _, X, _ = c.device_inputs()
@@ -159,7 +162,9 @@ def test_sddmm_integer_data_bit_exact(b):
     assert np.array_equal(G, ref)
 
 
-def test_sddmm_long_rows_and_dense_blocks():
+@pytest.mark.parametrize("tiled", ["0", "1"])
+def test_sddmm_long_rows_and_dense_blocks(tiled, monkeypatch):
+    monkeypatch.setenv("SPMM_SDDMM_TILED", tiled)
     # rows with more blocks than one task holds, a fully dense row, n spanning many 32-steps
     mb, kb, b = 12, 40, 16
     mask = synth.block_mask(mb, kb, 1 / 3, 80)
@@ -307,3 +312,45 @@ def test_sddmm_on_concentrated_rows():
     dY, dY64 = _dY(c, 132)
     G = _sddmm(c, plan, dY, X)
     assert O.rel_fro(G, TR.sddmm_blockwise(c.m, c.k, b, c.rows, c.cols, dY64, c.X64)) <= 1e-5
+
+
+@pytest.mark.parametrize("b", [16, 32])
+def test_tiled_sddmm_dense_tiles_ragged_edges_and_repeats(b, monkeypatch):
+    """The tiled form: a tile full of blocks (more than one task per tile),
+    tiles cut by m and k, n not a multiple of its 32-value chunks; the result
+    against the oracle, repeatable bit for bit, and the rule's choice taken
+    from density 1/4 at this size."""
+    mb, kb = 512 // b * 2 + 3, 512 // b * 2 + 1
+    mask = synth.block_mask(mb, kb, 1 / 3, 150 + b)
+    mask[: 256 // b, : 256 // b] = 1  # one full tile
+    c = Case(mb * b - 5, kb * b - 3, 333, b, 0.0, w="bf16", seed=151 + b, mask=mask)
+    plan = _plan(c)
+    _, X, _ = c.device_inputs()
+    dY, dY64 = _dY(c, 152 + b)
+    monkeypatch.setenv("SPMM_SDDMM_TILED", "1")
+    G1 = _sddmm(c, plan, dY, X)
+    G2 = _sddmm(c, plan, dY, X)
+    assert np.array_equal(G1, G2)
+    ref = TR.sddmm_blockwise(c.m, c.k, b, c.rows, c.cols, dY64, c.X64)
+    assert O.rel_fro(G1, ref) <= 1e-5
+    assert np.abs(G1 - ref).max() <= 1e-5 * np.abs(ref).max()
+    monkeypatch.delenv("SPMM_SDDMM_TILED", raising=False)
+    G3 = _sddmm(c, plan, dY, X)  # the rule: tiled at this density
+    assert np.array_equal(G1, G3)
+
+
+def test_tiled_sddmm_at_full_size_sampled(monkeypatch):
+    # m = k = 8192, n = 4096, b = 16, density 1/4: sampled blocks against the oracle
+    monkeypatch.setenv("SPMM_SDDMM_TILED", "1")
+    c = Case(8192, 8192, 4096, 16, 1 / 4, w="f16", seed=160)
+    plan = _plan(c)
+    _, X, _ = c.device_inputs()
+    dY, dY64 = _dY(c, 161)
+    nnzb = plan.info()["nnzb"]
+    G = torch.empty((nnzb, 16, 16), dtype=torch.float32, device="cuda")
+    plan.sddmm(dY, X, G)
+    torch.cuda.synchronize()
+    pick = np.random.default_rng(162).choice(nnzb, 256, replace=False)
+    got = G[torch.from_numpy(pick).cuda()].cpu().numpy().astype(np.float64)
+    ref = TR.sddmm_blockwise(c.m, c.k, 16, c.rows[pick], c.cols[pick], dY64, c.X64)
+    assert O.rel_fro(got, ref) <= 1e-5
