@@ -184,7 +184,13 @@ spmm_status_t spmm_plan_set_values(spmm_plan_t plan, const void* values_dev,
  * whose variant is 0, for an n class with no tuned entry, runs the autotuner
  * on these operands (spmm_autotune_static; it synchronises `stream`), unless
  * SPMM_AUTOTUNE=0 or `stream` is capturing a graph: then the rule on n runs.
- * Y holds the product either way.
+ * Y holds the product either way. A plan that cuts long rows into pieces
+ * (spmm_plan_info) keeps a workspace for them, allocated on the first run
+ * with more columns than it holds (after a device synchronisation); a run
+ * captured in a graph that would need it to grow splits those rows over one
+ * workgroup each instead, which may change the last bits. Runs of one such
+ * plan share its workspace: runs that overlap in time (different streams or
+ * threads) race and must be ordered by the caller.
  * Errors: INVALID_ARG (values not set, NULL, ld < n, alignment), HIP. */
 spmm_status_t spmm_run_static(spmm_plan_t plan, int64_t n, const void* X, int64_t ldx,
                               void* Y, int64_t ldy, void* stream);
@@ -192,11 +198,17 @@ spmm_status_t spmm_run_static(spmm_plan_t plan, int64_t n, const void* X, int64_
 /* Plan facts: nonzero blocks, block rows per group, number of groups, panels,
  * and the number of block rows the row-wise kernel (b = 16, 16-bit X)
  * splits over the four waves of a workgroup: rows with more than
- * max(64, 4 x the mean) blocks, found when the plan is built. A split row's
- * four partial sums are added in a fixed order, so results stay bitwise
- * reproducible (and equal between spmm_run_static and spmm_group_run), but a
- * dynamic call of the same pattern, which never splits, may differ from it in
- * the last bits. Any pointer may be NULL. */
+ * max(64, 4 x the mean) blocks, found when the plan is built (Appendix A.2's
+ * worst case is a partition whose nonzeros all sit in one row). Rows longer
+ * than max(128, that limit) are also cut into pieces of about that many
+ * blocks, one workgroup each; the workgroup that finishes a row's last piece
+ * adds the pieces' FP32 partial sums in piece order. Both reductions are in a
+ * fixed order, so results stay bitwise reproducible (and equal between
+ * spmm_run_static and spmm_group_run), but a dynamic call of the same
+ * pattern, which never splits, may differ from it in the last bits. The
+ * remaining rows are taken longest first where the pattern is skewed (a row
+ * over twice the mean, or any split row), which changes no result. Any
+ * pointer may be NULL. */
 /* Dense dispatch facts: *predicted_speedup (may be NULL) receives the speedup
  * model's sparse/dense ratio for the plan's shape (0 for an empty pattern);
  * *has_dense (may be NULL) whether the plan keeps a dense copy of M o W.
@@ -204,8 +216,8 @@ spmm_status_t spmm_run_static(spmm_plan_t plan, int64_t n, const void* X, int64_
 spmm_status_t spmm_plan_dispatch(spmm_plan_t plan, double* predicted_speedup, int32_t* has_dense);
 
 /* Device memory the plan holds: *device_bytes (may be NULL) all of its
- * buffers (plan arrays, values, scales, split-row and SDDMM task lists, ELL
- * slots, the dense copy), *value_bytes (may be NULL) its one copy of the block
+ * buffers (plan arrays, values, scales, split-row, piece and SDDMM task
+ * lists, ELL slots, the dense copy, the piece workspace), *value_bytes (may be NULL) its one copy of the block
  * values and FP8 scales. Host bookkeeping only.
  * Errors: INVALID_ARG (NULL plan). */
 spmm_status_t spmm_plan_memory(spmm_plan_t plan, int64_t* device_bytes, int64_t* value_bytes);
@@ -307,7 +319,7 @@ spmm_status_t spmm_autotune_clear(void);
  * kernel launch: one workgroup per work unit of all the problems. This goes
  * beyond the paper, whose benchmarks run one product at a time and let n grow
  * to amortise overheads (Sections 4 and 5); here the columns of many small
- * products share one launch instead. Up to 32 problems travel in the kernel
+ * products share one launch instead. Up to 26 problems travel in the kernel
  * arguments of one direct launch (with SPMM_GROUP_GRAPH=1 in the environment,
  * the call instead replays a captured one-node HIP graph after updating that
  * node's arguments and grid). Larger groups go through a ring of
@@ -323,8 +335,10 @@ spmm_status_t spmm_autotune_clear(void);
  * triple, with 16-bit W and X (FP8 weights: UNSUPPORTED). Each problem uses
  * the variant its plan holds for its n (fixed, tuned, else the rule; a
  * grouped launch never tunes), so its result equals, bit for bit, a
- * spmm_run_static of that plan that runs the same variant. Calls on one
- * handle must not overlap on different streams.
+ * spmm_run_static of that plan that runs the same variant. The handle keeps
+ * a workspace for plans that cut long rows into pieces, one range per
+ * problem (a plan may appear several times), grown like a plan's. Calls on
+ * one handle must not overlap on different streams.
  * Errors: INVALID_ARG (count > max_problems, NULL, alignment, ld < n, values
  * not set, mixed block size or dtypes), UNSUPPORTED, HIP. */
 spmm_status_t spmm_group_create(int32_t max_problems, spmm_group_t* out);

@@ -120,11 +120,16 @@ struct RunArgs {
   int64_t nnz;            // entries in W (capacity for dynamic calls)
   bool relu = false;      // max(0, y) before the output cast
   const int32_t* w_index = nullptr;  // values (and scales) of entry q at w_index[q], else q
-  int32_t num_heavy = 0;             // row-wise kernel: block rows split over a workgroup's four waves
-  const uint8_t* heavy_flag = nullptr;  // [mb] nonzero for a split row
-  const int32_t* heavy_rows = nullptr;  // [num_heavy]
+  int32_t num_heavy = 0;             // row-wise kernel: split rows (or pieces, with part set)
+  const int32_t* light_rows = nullptr;  // [num_light] rows of the light units, in order (nullptr: all rows)
+  int32_t num_light = 0;
+  const int32_t* heavy_rows = nullptr;  // [num_heavy] split rows, or [num_heavy][8] pieces with part set
+  float* part = nullptr;     // piece partials (pieces of long rows), else nullptr
+  const int32_t* cut_rows = nullptr;  // [num_cut][4] the rows cut into pieces: row, first slot, C, 0
+  int32_t num_cut = 0;
   int32_t ns = 8;         // row-wise kernel: column tiles of 16 per wave (2, 4 or 8)
-  bool split_all = false;  // row-wise kernel, b = 16: split every block row (heavy_* unused)
+  bool split_all = false;  // row-wise kernel, b = 16: split every block row (heavy_* unused unless part
+                           // is set: then heavy_rows lists the pieces of every row)
 };
 // Row-wise kernel (16-bit X, b = 16 or 32): W and scales in block-CSR order.
 spmm_status_t launch_spmm_row(const RunArgs& a, const int32_t* row_ptr, const int32_t* col_idx, hipStream_t stream);
@@ -165,7 +170,10 @@ spmm_status_t launch_spmm_row_grouped_persist(spmm_dtype_t xt, spmm_dtype_t yt, 
                                               hipStream_t stream);
 // LDS bytes of a grouped launch with split rows; work units of one problem.
 unsigned group_split_lds(int32_t b);
-int64_t group_problem_units(int32_t mb, int64_t n, int32_t ns, int32_t num_heavy);
+int64_t group_problem_units(int32_t num_light, int64_t n, int32_t ns, int32_t num_heavy, bool inter);
+// The fixup launch of a problem's cut rows after its pieces ran (grouped
+// launches; a single launch issues its own).
+spmm_status_t launch_group_fixup(const RunArgs& a, int ns, hipStream_t stream);
 // SDDMM (b <= 32, FP16/BF16 dY and X): G[e] = dY[rows of r] X[rows of c]^T
 // for the tasks of a plan (block row, first entry, up to sddmm_task_blocks(b)
 // blocks each), FP32 output in CSR order.

@@ -10,6 +10,7 @@
 // completed (an event per slot).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdlib>
 #include <cstring>
 #include <map>
@@ -44,6 +45,11 @@ struct spmm_group_s {
     hipGraphNode_t node = nullptr;
   };
   std::map<std::tuple<int, int, int, bool>, Graph> graphs;  // (x, y, b, split rows)
+  // piece workspace of the group's calls: each problem whose plan cuts long
+  // rows into pieces takes its own range, so a plan may appear several times
+  float* part = nullptr;
+  int64_t part_cap = 0;  // bytes
+  std::vector<std::pair<RunArgs, int32_t>> fixups;  // (problem, tile width) of a call's cut rows
 };
 
 static void destroy_group(spmm_group_s* g) {
@@ -58,6 +64,7 @@ static void destroy_group(spmm_group_s* g) {
     if (g->dev[s]) (void)hipFree(g->dev[s]);
   }
   if (g->capture) (void)hipStreamDestroy(g->capture);
+  if (g->part) (void)hipFree(g->part);
   delete g;
 }
 
@@ -105,6 +112,63 @@ static spmm_status_t graph_for(spmm_group_s* g, spmm_dtype_t x, spmm_dtype_t y, 
     return fail_hip(e, "grouped graph");
   }
   *out = &(g->graphs[key] = gr);
+  return SPMM_OK;
+}
+
+// Grows the group's piece workspace to part_bytes, after the device has
+// finished the launches that may still use the old one. False when it cannot
+// grow now (the stream is being captured, or allocation failed): the call
+// then splits long rows over one workgroup each.
+static bool group_piece_workspace(spmm_group_s* g, int64_t part_bytes, hipStream_t s) {
+  if (part_bytes <= g->part_cap) return true;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return false;
+  if (g->part) {
+    if (hipDeviceSynchronize() != hipSuccess) return false;
+    (void)hipFree(g->part);
+    g->part = nullptr;
+    g->part_cap = 0;
+  }
+  const int64_t pb = std::max(part_bytes, 2 * g->part_cap);
+  if (hipMalloc((void**)&g->part, (size_t)pb) != hipSuccess) {
+    g->part = nullptr;
+    return false;
+  }
+  g->part_cap = pb;
+  return true;
+}
+
+// Partial bytes of one problem with pieces at tile width ns, 256-aligned.
+static int64_t piece_bytes(const spmm_plan_s* p, int64_t n, int32_t ns) {
+  return ((int64_t)p->num_slots * ceil_div(n, 16 * ns) * ns * 256 * 4 + 255) & ~(int64_t)255;
+}
+
+// The argument-form launch as a replay of the captured one-node graph, its
+// node's arguments and grid updated.
+static spmm_status_t replay_graph(spmm_group_s* g, const spmm_plan_s* p0, unsigned lds, int32_t total,
+                                  hipStream_t strm) {
+  spmm_group_s::Graph* gr = nullptr;
+  spmm_status_t st = graph_for(g, p0->x, p0->y, p0->b, lds, total, &gr);
+  if (st != SPMM_OK) return st;
+  void* params[1] = {g->args.data()};
+  hipKernelNodeParams kp{};
+  kp.func = const_cast<void*>(row_grouped_args_kernel(p0->x, p0->y, p0->b, lds > 0));
+  kp.gridDim = dim3((unsigned)total);
+  kp.blockDim = dim3(256);
+  kp.sharedMemBytes = lds;
+  kp.kernelParams = params;
+  kp.extra = nullptr;
+  SPMM_HIP(hipGraphExecKernelNodeSetParams(gr->exec, gr->node, &kp));
+  SPMM_HIP(hipGraphLaunch(gr->exec, strm));
+  return SPMM_OK;
+}
+
+// The fixup launches of the call's problems with cut rows, after its launch.
+static spmm_status_t run_fixups(spmm_group_s* g, hipStream_t strm) {
+  for (const auto& f : g->fixups) {
+    const spmm_status_t st = launch_group_fixup(f.first, f.second, strm);
+    if (st != SPMM_OK) return st;
+  }
   return SPMM_OK;
 }
 
@@ -184,6 +248,21 @@ spmm_status_t spmm_group_run(spmm_group_t g, int32_t count, const spmm_plan_t* p
     SPMM_HIP(hipEventSynchronize(g->done[s]));
     g->pending[s] = false;
   }
+  hipStream_t strm = (hipStream_t)stream;
+  // the piece workspace the call needs (problems whose plan cuts long rows)
+  int64_t need_part = 0;
+  for (int32_t i = 0; i < count; ++i) {
+    const spmm_plan_s* p = plans[i];
+    if (n[i] == 0 || !p->num_slots) continue;
+    const int32_t var = plan_variant(p, n[i]);
+    int32_t ns = variant_ns(var);
+    if (ns != 2 && ns != 4 && ns != 8) ns = default_ns(n[i]);
+    if (!plan_pieces(p, n[i], ns, plan_split_all(p, n[i], ns, var))) continue;
+    need_part += piece_bytes(p, n[i], ns);
+  }
+  const bool pieces = need_part > 0 && group_piece_workspace(g, need_part, strm);
+  int64_t part_off = 0;
+  g->fixups.clear();
   // descriptors, in call order, with the prefix of their work units
   int64_t total = 0, real_units = 0;
   int32_t k = 0;
@@ -209,14 +288,30 @@ spmm_status_t spmm_group_run(spmm_group_t g, int32_t count, const spmm_plan_t* p
     a.ldy = ldy[i];
     a.n = (int32_t)n[i];
     a.relu = relu && relu[i];
+    a.wt = p->w;
+    a.xt = p->x;
+    a.yt = p->y;
     a.ns = ns;
     a.num_heavy = p->num_heavy;
-    a.heavy_flag = p->heavy_flag;
+    a.light_rows = p->light_rows;
+    a.num_light = p->mb - p->num_heavy;
     a.heavy_rows = p->heavy_rows;
     a.split_all = plan_split_all(p, n[i], ns, var);  // as the problem's own spmm_run_static would
+    if (pieces && plan_pieces(p, n[i], ns, a.split_all)) {  // long rows cut into pieces, as in a single run
+      a.num_heavy = a.split_all ? p->num_pieces_all : p->num_pieces;
+      a.heavy_rows = a.split_all ? p->pieces_all : p->pieces;
+      a.part = (float*)((uint8_t*)g->part + part_off);
+      a.cut_rows = p->cut_rows;
+      a.num_cut = p->num_cut;
+      part_off += piece_bytes(p, n[i], ns);
+      g->fixups.emplace_back(a, ns);
+    }
     any_heavy = any_heavy || p->num_heavy > 0 || a.split_all;
     void* dst = inline_table ? group_args_problem(g->args.data(), k) : (void*)(g->host[s] + (size_t)k * g->desc_bytes);
-    const int64_t units = group_problem_units(p->mb, n[i], ns, a.split_all ? p->mb : p->num_heavy);
+    const int64_t units =
+        a.split_all ? group_problem_units(0, n[i], ns, a.part ? a.num_heavy : p->mb, false)
+                    : group_problem_units(a.light_rows ? a.num_light : p->mb, n[i], ns, a.num_heavy,
+                                          a.part != nullptr && (a.light_rows ? a.num_light : p->mb) > 0);
     if (units >= (int64_t)INT32_MAX) return fail(SPMM_ERR_UNSUPPORTED, "too many work units in one group");
     fill_row_problem(dst, a, p->pb.row_ptr, p->pb.col_idx, (int32_t)total, (int32_t)units);
     real_units += units;
@@ -224,29 +319,18 @@ spmm_status_t spmm_group_run(spmm_group_t g, int32_t count, const spmm_plan_t* p
     if (total >= (int64_t)INT32_MAX) return fail(SPMM_ERR_UNSUPPORTED, "too many work units in one group");
     ++k;
   }
-  hipStream_t strm = (hipStream_t)stream;
   const unsigned lds = any_heavy ? group_split_lds(p0->b) : 0u;
   const bool persist = use_persist();
   const int32_t grid = group_persist_grid((int32_t)real_units, p0->b == 16 ? 4 : 3);
   if (inline_table) {
     group_args_header(g->args.data(), used, (int32_t)total);
     if (persist)
-      return launch_spmm_row_grouped_persist(p0->x, p0->y, p0->b, g->args.data(), nullptr, used, grid, lds, strm);
-    if (!use_graphs())
-      return launch_spmm_row_grouped_args(p0->x, p0->y, p0->b, g->args.data(), (int32_t)total, lds, strm);
-    spmm_group_s::Graph* gr = nullptr;
-    if ((st = graph_for(g, p0->x, p0->y, p0->b, lds, (int32_t)total, &gr)) != SPMM_OK) return st;
-    void* params[1] = {g->args.data()};
-    hipKernelNodeParams kp{};
-    kp.func = const_cast<void*>(row_grouped_args_kernel(p0->x, p0->y, p0->b, lds > 0));
-    kp.gridDim = dim3((unsigned)total);
-    kp.blockDim = dim3(256);
-    kp.sharedMemBytes = lds;
-    kp.kernelParams = params;
-    kp.extra = nullptr;
-    SPMM_HIP(hipGraphExecKernelNodeSetParams(gr->exec, gr->node, &kp));
-    SPMM_HIP(hipGraphLaunch(gr->exec, strm));
-    return SPMM_OK;
+      st = launch_spmm_row_grouped_persist(p0->x, p0->y, p0->b, g->args.data(), nullptr, used, grid, lds, strm);
+    else if (!use_graphs())
+      st = launch_spmm_row_grouped_args(p0->x, p0->y, p0->b, g->args.data(), (int32_t)total, lds, strm);
+    else
+      st = replay_graph(g, p0, lds, (int32_t)total, strm);
+    return st == SPMM_OK ? run_fixups(g, strm) : st;
   }
   SPMM_HIP(hipMemcpyAsync(g->dev[s], g->host[s], (size_t)used * g->desc_bytes, hipMemcpyHostToDevice, strm));
   st = persist ? launch_spmm_row_grouped_persist(p0->x, p0->y, p0->b, nullptr, g->dev[s], used, grid, lds, strm)
@@ -255,8 +339,9 @@ spmm_status_t spmm_group_run(spmm_group_t g, int32_t count, const spmm_plan_t* p
   SPMM_HIP(hipEventRecord(g->done[s], strm));
   g->pending[s] = true;
   g->slot = (s + 1) % kSlots;
-  return SPMM_OK;
+  return run_fixups(g, strm);
 }
+
 
 spmm_status_t spmm_group_destroy(spmm_group_t g) {
   clear_error();

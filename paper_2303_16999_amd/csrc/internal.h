@@ -22,8 +22,24 @@ struct spmm_plan_s {
   int32_t variant_opt = 0;     // fixed tile variant from the options, 0 = choose
   int32_t tuned[32] = {};      // autotuned variant per n class, 0 = none
   int32_t num_heavy = 0;       // block rows the row-wise kernel splits over four waves
-  uint8_t* heavy_flag = nullptr;   // device [mb]
+  int32_t* light_rows = nullptr;   // device [mb - num_heavy]: rows of the light units, longest first (skewed plans)
   int32_t* heavy_rows = nullptr;   // device [num_heavy]
+  // Long rows cut into pieces (none cut: all zero). Entries [row, first
+  // block, end block, slot, c, C, 0, 0]; slots number the cut pieces in row
+  // order, the same in both tables.
+  int32_t num_pieces = 0;          // pieces of the split rows
+  int32_t* pieces = nullptr;       // device [num_pieces][8]
+  int32_t num_pieces_all = 0;      // pieces of every row (the every-row split form)
+  int32_t* pieces_all = nullptr;   // device [num_pieces_all][8]
+  int32_t num_slots = 0;           // cut pieces: partial slots
+  int32_t num_cut = 0;             // rows cut into pieces
+  bool pieces_spread = false;      // split rows of widely different lengths (plan_pieces)
+  int32_t* cut_rows = nullptr;     // device [num_cut][4]: row, first slot, C, 0
+  // Piece workspace, grown on a run with more columns than it holds: the
+  // partials of num_slots slots for up to piece_ws_n columns.
+  float* piece_part = nullptr;
+  int64_t piece_ws_n = 0;
+  int64_t piece_ws_bytes = 0;
   int32_t* sddmm_tasks = nullptr;  // device [sddmm_num_tasks][2] (16-bit X, b <= 32)
   int32_t sddmm_num_tasks = 0;
   int32_t* sddmm_tiled_tasks = nullptr;  // device [n][4] (b = 16/32): tile row, tile column, first, count
@@ -56,6 +72,9 @@ bool valid_variant(int32_t b, int32_t v);
 // Tile variant for a run of `p` with n columns: fixed option, else the plan's
 // tuned value, else the process-wide tuned table, else the rule on n.
 int32_t plan_variant(const spmm_plan_s* p, int64_t n);
+// Whether a run of n columns at tile width ns uses the plan's pieces of long
+// rows (split_all: in the every-row split form).
+bool plan_pieces(const spmm_plan_s* p, int64_t n, int32_t ns, bool split_all);
 // Whether the plan runs on the row-wise MFMA kernel (b = 16/32/64, 16-bit X).
 bool plan_uses_row_kernel(const spmm_plan_s* p);
 // Whether a run with n columns, tile width ns and this variant splits every

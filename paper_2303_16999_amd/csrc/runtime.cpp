@@ -253,6 +253,22 @@ bool plan_split_all(const spmm_plan_s* p, int64_t n, int32_t ns, int32_t variant
   return split_all_preferred(p->b, p->mb, n, ns, p->nnzb, device_cu_count());
 }
 
+static bool piece_workspace(const spmm_plan_s* cp, int64_t n, hipStream_t s);
+
+// Whether a run of n columns at tile width ns cuts the plan's long rows into
+// pieces (the plan must have some): where its split rows differ widely in
+// length, or where they alone would give fewer than two workgroups per CU
+// (a single long row is the worst case). Otherwise the four-wave split
+// balances them, and pieces would only add their partial sums' traffic and
+// the fixup launch. SPMM_PIECES=0 / 1 forces the choice.
+bool plan_pieces(const spmm_plan_s* p, int64_t n, int32_t ns, bool split_all) {
+  if (!p->num_slots) return false;
+  if (const char* e = getenv("SPMM_PIECES")) return e[0] != '0';
+  if (p->pieces_spread) return true;
+  const int64_t units = (int64_t)(split_all ? p->mb : p->num_heavy) * ceil_div(n, 16 * ns);
+  return units < 2 * (int64_t)device_cu_count();
+}
+
 spmm_status_t run_plan(const spmm_plan_s* p, int64_t n, const void* X, int64_t ldx, void* Y, int64_t ldy,
                        int32_t variant, bool relu, hipStream_t stream) {
   RunArgs a{};
@@ -289,9 +305,17 @@ spmm_status_t run_plan(const spmm_plan_s* p, int64_t n, const void* X, int64_t l
   if (plan_uses_row_kernel(p)) {
     a.ns = variant_ns(variant) ? variant_ns(variant) : default_ns(n);
     a.num_heavy = p->num_heavy;
-    a.heavy_flag = p->heavy_flag;
+    a.light_rows = p->light_rows;
+    a.num_light = p->mb - p->num_heavy;
     a.heavy_rows = p->heavy_rows;
     a.split_all = plan_split_all(p, n, a.ns, variant);
+    if (plan_pieces(p, n, a.ns, a.split_all) && piece_workspace(p, n, stream)) {
+      a.num_heavy = a.split_all ? p->num_pieces_all : p->num_pieces;
+      a.heavy_rows = a.split_all ? p->pieces_all : p->pieces;
+      a.part = p->piece_part;
+      a.cut_rows = p->cut_rows;
+      a.num_cut = p->num_cut;
+    }
     if (a.split_all) return launch_spmm_row(a, p->pb.row_ptr, p->pb.col_idx, stream);
     const bool pp_ok = p->w == p->x && p->num_heavy == 0 && p->b <= 32;
     bool pp = pp_ok && row_pp_preferred(p->b, p->mb, n, a.ns, p->nnzb, device_cu_count());
@@ -427,28 +451,122 @@ static spmm_status_t build_sddmm_tasks(spmm_plan_s* p, const std::vector<int32_t
   return SPMM_OK;
 }
 
+// Long rows to split, and the order in which light units take the others.
+// Rows with more than max(64, 2 x mean) blocks are split over a workgroup's
+// four waves, and rows longer than max(256, 2 x that limit) blocks can also
+// be cut into pieces of about that many blocks, one workgroup each (a fixup
+// launch adds the pieces' partial sums in piece order; plan_pieces decides
+// per run). Where some row is split, or the longest row holds more than
+// twice the mean, the light units take the remaining rows longest first (a
+// unit's waves then hold rows of about the same length, and the long ones
+// start early), else in order. SPMM_SPLIT=0 turns all three off,
+// SPMM_ROW_ORDER=0 the order; SPMM_SPLIT_BLOCKS sets the split limit,
+// SPMM_PIECE_BLOCKS the piece length.
 static spmm_status_t classify_heavy_rows(spmm_plan_s* p, const std::vector<int32_t>& rp) {
   const char* e = getenv("SPMM_SPLIT");
   if (e && std::string(e) == "0") return SPMM_OK;
   if (p->mb == 0 || p->nnzb == 0) return SPMM_OK;
   const int64_t mean = ceil_div(p->nnzb, p->mb);
-  const int64_t limit = std::max<int64_t>(64, 4 * mean);
-  std::vector<int32_t> heavy;
-  std::vector<uint8_t> flag((size_t)p->mb, 0);
-  for (int32_t r = 0; r < p->mb; ++r)
-    if (rp[r + 1] - rp[r] > limit) {
-      heavy.push_back(r);
-      flag[r] = 1;
-    }
+  int64_t limit = std::max<int64_t>(64, 2 * mean);
+  if (const char* sb = getenv("SPMM_SPLIT_BLOCKS")) limit = std::max<int64_t>(8, atoll(sb));
+  std::vector<int32_t> heavy, light;
+  int64_t longest = 0;
+  for (int32_t r = 0; r < p->mb; ++r) {
+    const int64_t len = rp[r + 1] - rp[r];
+    longest = std::max(longest, len);
+    if (len > limit) heavy.push_back(r);
+    else light.push_back(r);
+  }
+  const char* o = getenv("SPMM_ROW_ORDER");
+  const bool order = (o && o[0] == '2') || (!(o && o[0] == '0') && (!heavy.empty() || longest > 2 * mean));
+  spmm_status_t st = SPMM_OK;
+  if (!heavy.empty()) {
+    if ((st = dev_alloc(&p->heavy_rows, (int64_t)heavy.size())) != SPMM_OK) return st;
+    SPMM_HIP(hipMemcpy(p->heavy_rows, heavy.data(), sizeof(int32_t) * heavy.size(), hipMemcpyHostToDevice));
+    p->num_heavy = (int32_t)heavy.size();
+  }
+  if (order || !heavy.empty()) {  // with split rows the list also leaves them out
+    if (order)
+      std::stable_sort(light.begin(), light.end(),
+                       [&](int32_t a, int32_t b) { return rp[a + 1] - rp[a] > rp[b + 1] - rp[b]; });
+    if ((st = dev_alloc(&p->light_rows, (int64_t)light.size())) != SPMM_OK) return st;
+    if (!light.empty())
+      SPMM_HIP(hipMemcpy(p->light_rows, light.data(), sizeof(int32_t) * light.size(), hipMemcpyHostToDevice));
+  }
   if (heavy.empty()) return SPMM_OK;
-  spmm_status_t st = dev_alloc(&p->heavy_rows, (int64_t)heavy.size());
-  if (st != SPMM_OK) return st;
-  hipError_t err = hipMalloc((void**)&p->heavy_flag, (size_t)p->mb);
-  if (err != hipSuccess) return fail_hip(err, "hipMalloc");
-  SPMM_HIP(hipMemcpy(p->heavy_rows, heavy.data(), sizeof(int32_t) * heavy.size(), hipMemcpyHostToDevice));
-  SPMM_HIP(hipMemcpy(p->heavy_flag, flag.data(), flag.size(), hipMemcpyHostToDevice));
-  p->num_heavy = (int32_t)heavy.size();
+  int64_t piece = std::max<int64_t>(256, 2 * limit);
+  if (const char* pb = getenv("SPMM_PIECE_BLOCKS")) piece = std::max<int64_t>(16, atoll(pb));
+  // both tables from one walk over the rows, so a cut piece has one slot
+  std::vector<int32_t> tab, all, cut;
+  std::vector<uint8_t> is_heavy((size_t)p->mb, 0);
+  for (int32_t r : heavy) is_heavy[r] = 1;
+  int32_t slots = 0;
+  for (int32_t r = 0; r < p->mb; ++r) {
+    const int64_t lo = rp[r], len = rp[r + 1] - lo;
+    int64_t C = len > piece ? ceil_div(len, piece) : 1;
+    int64_t sz = C > 1 ? (ceil_div(len, C) + 1) & ~(int64_t)1 : std::max<int64_t>(len, 1);  // whole pairs
+    C = C > 1 ? ceil_div(len, sz) : 1;
+    for (int64_t c = 0; c < C; ++c) {
+      const int32_t e[8] = {r, (int32_t)(lo + c * sz), (int32_t)std::min(lo + len, lo + (c + 1) * sz),
+                            C > 1 ? slots + (int32_t)c : 0, (int32_t)c, (int32_t)C, 0, 0};
+      all.insert(all.end(), e, e + 8);
+      if (is_heavy[r]) tab.insert(tab.end(), e, e + 8);
+    }
+    if (C > 1) {
+      const int32_t e[4] = {r, slots, (int32_t)C, 0};
+      cut.insert(cut.end(), e, e + 4);
+      slots += (int32_t)C;
+    }
+  }
+  if (slots == 0) return SPMM_OK;
+  if ((st = dev_alloc(&p->pieces, (int64_t)tab.size())) != SPMM_OK) return st;
+  if ((st = dev_alloc(&p->pieces_all, (int64_t)all.size())) != SPMM_OK) return st;
+  if ((st = dev_alloc(&p->cut_rows, (int64_t)cut.size())) != SPMM_OK) return st;
+  SPMM_HIP(hipMemcpy(p->cut_rows, cut.data(), sizeof(int32_t) * cut.size(), hipMemcpyHostToDevice));
+  p->num_cut = (int32_t)(cut.size() / 4);
+  SPMM_HIP(hipMemcpy(p->pieces, tab.data(), sizeof(int32_t) * tab.size(), hipMemcpyHostToDevice));
+  SPMM_HIP(hipMemcpy(p->pieces_all, all.data(), sizeof(int32_t) * all.size(), hipMemcpyHostToDevice));
+  p->num_pieces = (int32_t)(tab.size() / 8);
+  // split rows of very different lengths: the four-wave split alone leaves
+  // the longest far behind the others
+  std::vector<int64_t> lens;
+  for (int32_t r : heavy) lens.push_back(rp[r + 1] - rp[r]);
+  std::nth_element(lens.begin(), lens.begin() + lens.size() / 2, lens.end());
+  p->pieces_spread = longest >= 2 * lens[lens.size() / 2];
+  p->num_pieces_all = (int32_t)(all.size() / 8);
+  p->num_slots = slots;
   return SPMM_OK;
+}
+
+// The piece workspace of a plan for runs of up to n columns, at any tile
+// width: partials of num_slots x 16 rows x n (rounded up to 128) FP32. Grows
+// under a lock, after the device has finished the launches that may still
+// use the old one. False when it cannot grow now (the stream is being
+// captured, or allocation failed): the run then splits its long rows over one
+// workgroup each.
+static std::mutex g_piece_mu;
+static bool piece_workspace(const spmm_plan_s* cp, int64_t n, hipStream_t s) {
+  spmm_plan_s* p = const_cast<spmm_plan_s*>(cp);
+  std::lock_guard<std::mutex> lk(g_piece_mu);
+  if (p->piece_ws_n >= n) return true;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return false;
+  const int64_t cap = std::max<int64_t>(n, 2 * p->piece_ws_n);
+  const int64_t part_bytes = (int64_t)p->num_slots * 16 * (ceil_div(cap, 128) * 128) * 4;
+  if (p->piece_part) {
+    if (hipDeviceSynchronize() != hipSuccess) return false;
+    (void)hipFree(p->piece_part);
+    p->piece_part = nullptr;
+    p->piece_ws_n = 0;
+    p->piece_ws_bytes = 0;
+  }
+  if (hipMalloc((void**)&p->piece_part, (size_t)part_bytes) != hipSuccess) {
+    p->piece_part = nullptr;
+    return false;
+  }
+  p->piece_ws_n = cap;
+  p->piece_ws_bytes = part_bytes;
+  return true;
 }
 
 }  // namespace spmm
@@ -554,8 +672,11 @@ spmm_status_t spmm_plan_static(int64_t m, int64_t k, int32_t b, const uint8_t* b
     free_plan_buffers(p->pb);
     if (p->values) (void)hipFree(p->values);
     if (p->scales) (void)hipFree(p->scales);
-    if (p->heavy_flag) (void)hipFree(p->heavy_flag);
+    if (p->light_rows) (void)hipFree(p->light_rows);
     if (p->heavy_rows) (void)hipFree(p->heavy_rows);
+    if (p->pieces) (void)hipFree(p->pieces);
+    if (p->pieces_all) (void)hipFree(p->pieces_all);
+    if (p->cut_rows) (void)hipFree(p->cut_rows);
     if (p->sddmm_tasks) (void)hipFree(p->sddmm_tasks);
     if (p->sddmm_tiled_tasks) (void)hipFree(p->sddmm_tiled_tasks);
     if (p->sddmm_tiled_ent) (void)hipFree(p->sddmm_tiled_ent);
@@ -770,8 +891,12 @@ spmm_status_t spmm_plan_destroy(spmm_plan_t p) {
   free_plan_buffers(p->pb);
   if (p->values) (void)hipFree(p->values);
   if (p->scales) (void)hipFree(p->scales);
-  if (p->heavy_flag) (void)hipFree(p->heavy_flag);
+  if (p->light_rows) (void)hipFree(p->light_rows);
   if (p->heavy_rows) (void)hipFree(p->heavy_rows);
+  if (p->pieces) (void)hipFree(p->pieces);
+  if (p->pieces_all) (void)hipFree(p->pieces_all);
+  if (p->cut_rows) (void)hipFree(p->cut_rows);
+  if (p->piece_part) (void)hipFree(p->piece_part);
   if (p->sddmm_tasks) (void)hipFree(p->sddmm_tasks);
   if (p->ell_slot) (void)hipFree(p->ell_slot);
   if (p->dense_w) (void)hipFree(p->dense_w);
@@ -788,8 +913,10 @@ spmm_status_t spmm_plan_memory(spmm_plan_t p, int64_t* device_bytes, int64_t* va
   const int64_t nnz = p->nnzb;
   int64_t idx = 4 * n1((int64_t)p->geo.num_panels + 1) + 4 * n1((int64_t)p->mb + 1) + 4 * n1(nnz) +
                 4 * (p->pb.order ? n1(nnz) : 0) + 4 * n1(p->pb.scratch_ints) + 8 * n1((int64_t)p->geo.num_groups + 1);
-  if (p->heavy_flag) idx += p->mb;
+  if (p->light_rows) idx += 4 * n1((int64_t)p->mb - p->num_heavy);
   if (p->heavy_rows) idx += 4 * n1(p->num_heavy);
+  if (p->pieces) idx += 32 * (n1(p->num_pieces) + n1(p->num_pieces_all)) + 16 * n1(p->num_cut);
+  idx += p->piece_ws_bytes;
   if (p->sddmm_tasks) idx += 8 * n1(p->sddmm_num_tasks);
   if (p->sddmm_tiled_tasks) idx += 16 * n1(p->sddmm_tiled_num) + 8 * n1(nnz);
   if (p->ell_slot) idx += 4 * n1(nnz);

@@ -52,10 +52,15 @@ struct RowProblem {
   int32_t relu;            // nonzero: max(0, y) before the output cast
   int32_t ns;              // column tiles of 16 per wave: 2, 4 or 8
   int32_t unit_begin;      // grouped launch: first workgroup of this problem (a multiple of 8)
-  int32_t num_heavy;       // block rows split over the 4 waves of a workgroup
+  int32_t num_heavy;       // split rows (or pieces, with part set): heavy units per column tile
   int32_t num_units;       // grouped launch: work units of this problem
-  const uint8_t* heavy_flag;  // [mb] nonzero for a split row (nullptr when num_heavy == 0)
-  const int32_t* heavy_rows;  // [num_heavy] the split rows; nullptr with num_heavy == mb: every row, in order
+  const int32_t* light_rows;  // [num_light] the rows light units take, in that order; nullptr: all rows in order
+  // part == nullptr: [num_heavy] the split rows (nullptr with num_heavy == mb:
+  // every row, in order). part set: [num_heavy][8] pieces (piece_store).
+  const int32_t* heavy_rows;
+  float* part;             // piece partial sums, nullptr: no pieces
+  int32_t num_light;       // rows of the light units
+  int32_t pad_;
 };
 
 struct Params {
@@ -532,31 +537,91 @@ __device__ __forceinline__ void row_tile(const RowProblem& p, int32_t r, int32_t
 // time is the longer of two rows rather than of four. Otherwise a unit is four
 // block rows, one per wave, on the one tile. Consecutive units step through
 // the rows first, so the waves resident on an XCD share a few column tiles of
-// X. False: no work for this wave (past the last row or column).
+// X. With a light-row list the units take its rows in its order (the plan
+// lists them longest first and leaves out split rows), else every row in
+// order. False: no work for this wave (past the last row or column).
 __device__ __forceinline__ bool light_unit(const RowProblem& p, int32_t lu, int wave, int ns, int32_t& r, int32_t& n0) {
   const int32_t tile = 16 * ns;
+  const int32_t nl = p.num_light;
+  int32_t i;
   if (p.n > tile) {
-    const int32_t rg = (p.mb + 1) >> 1;
-    r = (lu % rg) * 2 + (wave >> 1);
+    const int32_t rg = (nl + 1) >> 1;
+    i = (lu % rg) * 2 + (wave >> 1);
     n0 = ((lu / rg) * 2 + (wave & 1)) * tile;
   } else {
-    const int32_t rg = (p.mb + kRowsPerWg - 1) / kRowsPerWg;
-    r = (lu % rg) * kRowsPerWg + wave;
+    const int32_t rg = (nl + kRowsPerWg - 1) / kRowsPerWg;
+    i = (lu % rg) * kRowsPerWg + wave;
     n0 = (lu / rg) * tile;
   }
-  return r < p.mb && n0 < p.n;
+  if (i >= nl || n0 >= p.n) return false;
+  r = p.light_rows ? sload(p.light_rows, i) : i;
+  return true;
 }
 
-// Work units of a problem: heavy units first (one split row times a column
-// tile, so the longest units start early), then light units (light_unit;
-// split rows are skipped there).
+// Work units of a problem: heavy units first (one split row or piece times a
+// column tile, so the longest units start early), then light units
+// (light_unit).
+// With pieces and light rows the units are interleaved instead (row_unit).
+__device__ __forceinline__ bool interleaved(const RowProblem& p) { return p.part && p.num_light > 0; }
 __device__ __forceinline__ int32_t heavy_units(const RowProblem& p, int ns) {
+  if (interleaved(p)) return 0;
   return p.num_heavy * ((p.n + 16 * ns - 1) / (16 * ns));
 }
 
 // Bytes of LDS a workgroup needs to reduce a split row: three waves' partial
 // accumulators (the fourth keeps its own).
 __host__ __device__ constexpr int split_lds_bytes(int B, int NS) { return 3 * (B / 16) * NS * 64 * 16; }
+
+// Long rows cut into pieces (Appendix A.2's worst case, all of a partition's
+// nonzeros in one row, spread over several workgroups). A piece entry is
+// [row, first block, end block, slot, c, C, 0, 0]: piece c of the C pieces of
+// its row (C = 1: a whole row, no slot), the row's pieces in consecutive
+// slots. A piece of a cut row leaves its FP32 partial for column tile t at
+// part[(slot * tiles + t) * 64 NS float4s], in the register layout; the fixup
+// kernel (k_piece_fixup), launched next on the same stream, adds a row's
+// partials in piece order and stores the row. No workgroup waits for another,
+// and the launch boundary makes the partials visible.
+template <int NS>
+__device__ __forceinline__ void piece_store(const RowProblem& p, int32_t slot, int32_t t, int lane,
+                                            const float4_t (&acc)[1][NS]) {
+  const int64_t tiles = (p.n + 16 * NS - 1) / (16 * NS);
+  float4_t* dst = (float4_t*)p.part + ((int64_t)slot * tiles + t) * (NS * 64);
+#pragma unroll
+  for (int s = 0; s < NS; ++s) dst[s * 64 + lane] = acc[0][s];
+}
+
+// Cut rows of a launch: [num_cut][4] row, first slot, C, 0. One wave per (cut
+// row, column tile): Y rows of the block row = the sum of its C partials,
+// added in piece order (then the ReLU and the output cast of row_store).
+struct FixParams {
+  RowProblem pr;
+  const int32_t* cut;
+  int32_t num_cut;
+  int32_t items;  // num_cut x column tiles
+};
+
+template <typename YT, int NS>
+__global__ __launch_bounds__(256) void k_piece_fixup(FixParams f) {
+  const int lane = threadIdx.x & 63;
+  const int32_t item = (int32_t)blockIdx.x * 4 + uniform((int32_t)(threadIdx.x >> 6));
+  if (item >= f.items) return;
+  const RowProblem& p = f.pr;
+  const int64_t tiles = (p.n + 16 * NS - 1) / (16 * NS);
+  const int32_t cr = item % f.num_cut, t = item / f.num_cut;
+  const int32_t r = sload(f.cut, 4 * (int64_t)cr), slot0 = sload(f.cut, 4 * (int64_t)cr + 1);
+  const int32_t C = sload(f.cut, 4 * (int64_t)cr + 2);
+  const float4_t* __restrict__ part = (const float4_t*)p.part;
+  float4_t acc[1][NS];
+  const float4_t* src = part + ((int64_t)slot0 * tiles + t) * (NS * 64);
+#pragma unroll
+  for (int s = 0; s < NS; ++s) acc[0][s] = src[s * 64 + lane];
+  for (int32_t c = 1; c < C; ++c) {
+    src = part + ((int64_t)(slot0 + c) * tiles + t) * (NS * 64);
+#pragma unroll
+    for (int s = 0; s < NS; ++s) acc[0][s] += src[s * 64 + lane];
+  }
+  row_store<YT, 16, NS>(p, r, t * (16 * NS), lane, acc);
+}
 
 // One work unit of problem p (local index `unit`). A split row's blocks are cut
 // into four pair-aligned ranges, one per wave; waves 1-3 leave their partial
@@ -576,19 +641,51 @@ __device__ __forceinline__ void row_unit(const RowProblem& p, int32_t unit, int 
     row_tile_whole<XT, WT, YT, B, NS>(p, r, n0, lane);
     return;
   }
-  const int32_t hus = heavy_units(p, NS);
-  if (unit >= hus) {
-    int32_t r, n0;
-    if (!light_unit(p, unit - hus, wave, NS, r, n0)) return;
-    if (p.num_heavy && p.heavy_flag[r]) return;
-    row_tile<XT, WT, YT, B, NS>(p, r, n0, lane);
-    return;
+  int32_t e, t;  // split row or piece e, column tile t
+  if (interleaved(p)) {
+    // Pieces are short: the units go column step by column step (a light
+    // unit's tile pair, else its one tile), each step's pieces before its
+    // light units, so every XCD works on a few column tiles of X at a time.
+    const int32_t tile = 16 * NS, tiles = (p.n + tile - 1) / tile;
+    const int32_t tps = p.n > tile ? 2 : 1;
+    const int32_t rgl = p.n > tile ? (p.num_light + 1) >> 1 : (p.num_light + kRowsPerWg - 1) / kRowsPerWg;
+    const int32_t ph = p.num_heavy * tps, ss = ph + rgl;
+    const int32_t step = unit / ss, w = unit - step * ss;
+    if (w >= ph) {
+      int32_t r, n0;
+      if (!light_unit(p, step * rgl + (w - ph), wave, NS, r, n0)) return;
+      row_tile<XT, WT, YT, B, NS>(p, r, n0, lane);
+      return;
+    }
+    e = w / tps;
+    t = step * tps + (w - e * tps);
+    if (t >= tiles) return;  // the second tile of an odd last step
+  } else {
+    const int32_t hus = heavy_units(p, NS);
+    if (unit >= hus) {
+      int32_t r, n0;
+      if (!light_unit(p, unit - hus, wave, NS, r, n0)) return;
+      row_tile<XT, WT, YT, B, NS>(p, r, n0, lane);
+      return;
+    }
+    e = unit % p.num_heavy;
+    t = unit / p.num_heavy;
   }
   if constexpr (SPLIT) {
-  const int32_t hu = unit;
-  const int32_t r = p.heavy_rows ? sload(p.heavy_rows, hu % p.num_heavy) : hu % p.num_heavy;  // no table: every row
-  const int32_t n0 = (hu / p.num_heavy) * (16 * NS);
-  const int32_t lo = sload(p.row_ptr, r), hi = sload(p.row_ptr, r + 1);
+  const int32_t n0 = t * (16 * NS);
+  int32_t r, lo, hi, slot = 0, C = 1;
+  if (p.part) {  // a piece of a long row, or a whole row
+    const int32_t* ent = p.heavy_rows + 8 * (int64_t)e;
+    r = sload(ent, 0);
+    lo = sload(ent, 1);
+    hi = sload(ent, 2);
+    slot = sload(ent, 3);
+    C = sload(ent, 5);
+  } else {
+    r = p.heavy_rows ? sload(p.heavy_rows, e) : e;  // no table: every row
+    lo = sload(p.row_ptr, r);
+    hi = sload(p.row_ptr, r + 1);
+  }
   const int32_t seg = (((hi - lo) + 7) / 8) * 2;  // a quarter of the row, rounded up to whole pairs
   const int32_t qa = min(hi, lo + wave * seg), qb = min(hi, qa + seg);
   float4_t acc[H][NS];
@@ -607,13 +704,14 @@ __device__ __forceinline__ void row_unit(const RowProblem& p, int32_t unit, int 
       for (int h = 0; h < H; ++h)
 #pragma unroll
         for (int s = 0; s < NS; ++s) acc[h][s] += red[((w * H + h) * NS + s) * 64 + lane];
-    row_store<YT, B, NS>(p, r, n0, lane, acc);
+    if (C > 1) piece_store<NS>(p, slot, t, lane, acc);  // the fixup kernel stores the row
+    else row_store<YT, B, NS>(p, r, n0, lane, acc);
   }
   }
 }
 
 template <typename XT, typename WT, typename YT, int B, int NS, bool SPLIT>
-__global__ __launch_bounds__(256) void k_spmm_row(Params prm) {
+__global__ __launch_bounds__(256, SPLIT ? 5 : 1) void k_spmm_row(Params prm) {
   if (prm.status && *prm.status) return;
   // (the unsplit form keeps the wave index as a vector value: its row pointer
   // loads then issue as vector loads, which measured faster from cold caches)
@@ -660,22 +758,55 @@ inline RowProblem row_problem(const RunArgs& a, const int32_t* row_ptr, const in
   p.ns = a.ns;
   p.unit_begin = 0;
   p.num_heavy = a.heavy_rows ? a.num_heavy : 0;
-  p.heavy_flag = p.num_heavy ? a.heavy_flag : nullptr;
   p.heavy_rows = p.num_heavy ? a.heavy_rows : nullptr;
+  p.part = p.num_heavy ? a.part : nullptr;
+  p.light_rows = a.light_rows;
+  p.num_light = a.light_rows ? a.num_light : a.plan.mb;
   if (a.split_all && a.plan.b == 16) {  // every row split, rows taken in order
-    p.num_heavy = a.plan.mb;
-    p.heavy_flag = nullptr;
-    p.heavy_rows = nullptr;
+    const bool pieces = a.part && a.heavy_rows;  // a table of every row's pieces
+    p.num_heavy = pieces ? a.num_heavy : a.plan.mb;
+    p.heavy_rows = pieces ? a.heavy_rows : nullptr;
+    p.part = pieces ? a.part : nullptr;
+    p.light_rows = nullptr;
+    p.num_light = 0;
   }
   return p;
 }
 
-// Work units of a problem (light and heavy) for a column-tile variant.
-inline int64_t problem_units(int32_t mb, int64_t n, int32_t ns, int32_t num_heavy) {
-  if (num_heavy >= mb) return (int64_t)num_heavy * ceil_div(n, 16 * ns);  // every row split: no light units
-  const int64_t light =
-      n > 16 * ns ? ceil_div(mb, 2) * ceil_div(n, 32 * ns) : ceil_div(mb, kRowsPerWg) * ceil_div(n, 16 * ns);
+// Work units of a problem for a column-tile variant: light units over
+// num_light rows, heavy units over num_heavy split rows or pieces; inter:
+// pieces interleaved with light units, step by step (row_unit).
+inline int64_t problem_units(int32_t num_light, int64_t n, int32_t ns, int32_t num_heavy, bool inter) {
+  if (inter) {
+    const int64_t tile = 16 * ns, tiles = ceil_div(n, tile), tps = n > tile ? 2 : 1;
+    const int64_t rgl = n > tile ? ceil_div(num_light, 2) : ceil_div(num_light, kRowsPerWg);
+    return ceil_div(tiles, tps) * (num_heavy * tps + rgl);
+  }
+  const int64_t light = n > 16 * ns ? ceil_div(num_light, 2) * ceil_div(n, 32 * ns)
+                                    : ceil_div(num_light, kRowsPerWg) * ceil_div(n, 16 * ns);
   return light + (int64_t)num_heavy * ceil_div(n, 16 * ns);
+}
+
+// The fixup launch of the cut rows of a problem whose pieces ran with tile
+// width ns (the same as its main launch).
+template <typename YT>
+spmm_status_t launch_piece_fixup(const RowProblem& pr, const int32_t* cut_rows, int32_t num_cut, int ns,
+                                 hipStream_t stream) {
+  FixParams f;
+  f.pr = pr;
+  f.cut = cut_rows;
+  f.num_cut = num_cut;
+  const int64_t items = (int64_t)num_cut * ceil_div(pr.n, 16 * ns);
+  if (items == 0) return SPMM_OK;
+  if (items > (int64_t)INT32_MAX) return fail(SPMM_ERR_UNSUPPORTED, "too many work units");
+  f.items = (int32_t)items;
+  const dim3 grid((unsigned)ceil_div(items, 4));
+  if (ns == 8) hipLaunchKernelGGL((k_piece_fixup<YT, 8>), grid, dim3(256), 0, stream, f);
+  else if (ns == 4) hipLaunchKernelGGL((k_piece_fixup<YT, 4>), grid, dim3(256), 0, stream, f);
+  else if (ns == 2) hipLaunchKernelGGL((k_piece_fixup<YT, 2>), grid, dim3(256), 0, stream, f);
+  else return fail(SPMM_ERR_INVALID_ARG, "column tile variant must be 2, 4 or 8");
+  SPMM_HIP(hipGetLastError());
+  return SPMM_OK;
 }
 
 template <typename XT, typename WT, typename YT, int B>
@@ -687,11 +818,13 @@ spmm_status_t launch_row(const RunArgs& a, const int32_t* row_ptr, const int32_t
   prm.status = a.status;
   const int ns = prm.pr.ns;
   const int64_t units = B == 64 ? (int64_t)a.plan.mb * ceil_div(a.n, 16 * ns)
-                                : problem_units(a.plan.mb, a.n, ns, prm.pr.num_heavy);
+                                : problem_units(prm.pr.num_light, a.n, ns, prm.pr.num_heavy,
+                                                prm.pr.part && prm.pr.num_light > 0);
   if (units == 0) return SPMM_OK;
   if (units > (int64_t)INT32_MAX) return fail(SPMM_ERR_UNSUPPORTED, "too many work units");
   prm.num_units = (int32_t)units;
-  const int64_t hus = B == 16 ? (int64_t)prm.pr.num_heavy * ceil_div(a.n, 16 * ns) : 0;
+  const bool inter = prm.pr.part && prm.pr.num_light > 0;
+  const int64_t hus = B == 16 && !inter ? (int64_t)prm.pr.num_heavy * ceil_div(a.n, 16 * ns) : 0;
   const int64_t grid = units + (((hus + 7) & ~(int64_t)7) - hus);
   if (grid > (int64_t)INT32_MAX) return fail(SPMM_ERR_UNSUPPORTED, "too many work units");
   const bool split = B == 16 && prm.pr.num_heavy > 0;
@@ -709,6 +842,9 @@ spmm_status_t launch_row(const RunArgs& a, const int32_t* row_ptr, const int32_t
   else if (ns == 2) hipLaunchKernelGGL((k_spmm_row<XT, WT, YT, B, 2, false>), dim3((unsigned)grid), dim3(256), 0, stream, prm);
   else return fail(SPMM_ERR_INVALID_ARG, "column tile variant must be 2, 4 or 8");
   SPMM_HIP(hipGetLastError());
+  if constexpr (B == 16) {
+    if (prm.pr.part && a.num_cut > 0) return launch_piece_fixup<YT>(prm.pr, a.cut_rows, a.num_cut, ns, stream);
+  }
   return SPMM_OK;
 }
 

@@ -8,10 +8,10 @@
 namespace spmm {
 namespace row {
 
-constexpr int kInlineProblems = 32;
+constexpr int kInlineProblems = 28;
 
 // Problem table passed in the kernel arguments (at most kInlineProblems
-// problems, 3.3 KB): no copy precedes the launch.
+// problems, 4 KB): no copy precedes the launch.
 struct GroupArgs {
   int32_t count, total;
   int32_t pad[2];
@@ -247,8 +247,8 @@ spmm_status_t launch_spmm_row_grouped_args(spmm_dtype_t xt, spmm_dtype_t yt, int
 // LDS of a grouped launch whose problems include split rows.
 unsigned group_split_lds(int32_t b) { return (unsigned)row::split_lds_bytes(b, 8); }
 
-int64_t group_problem_units(int32_t mb, int64_t n, int32_t ns, int32_t num_heavy) {
-  return row::problem_units(mb, n, ns, num_heavy);
+int64_t group_problem_units(int32_t num_light, int64_t n, int32_t ns, int32_t num_heavy, bool inter) {
+  return row::problem_units(num_light, n, ns, num_heavy, inter);
 }
 
 spmm_status_t launch_spmm_row_grouped(spmm_dtype_t xt, spmm_dtype_t yt, int32_t b, const void* probs_dev,
@@ -267,6 +267,17 @@ spmm_status_t launch_spmm_row_grouped(spmm_dtype_t xt, spmm_dtype_t yt, int32_t 
   }
   SPMM_HIP(hipGetLastError());
   return SPMM_OK;
+}
+
+spmm_status_t launch_group_fixup(const RunArgs& a, int ns, hipStream_t stream) {
+  if (!a.part || a.num_cut == 0 || a.n == 0) return SPMM_OK;
+  const row::RowProblem pr = row::row_problem(a, nullptr, nullptr);
+  switch (a.yt) {
+    case SPMM_F16: return row::launch_piece_fixup<_Float16>(pr, a.cut_rows, a.num_cut, ns, stream);
+    case SPMM_BF16: return row::launch_piece_fixup<__bf16>(pr, a.cut_rows, a.num_cut, ns, stream);
+    case SPMM_F32: return row::launch_piece_fixup<float>(pr, a.cut_rows, a.num_cut, ns, stream);
+    default: return fail(SPMM_ERR_UNSUPPORTED, "output dtype");
+  }
 }
 
 }  // namespace spmm

@@ -221,8 +221,10 @@ spmm_status_t launch_spmm_row_pp(const RunArgs& a, const int32_t* row_ptr, const
   Params prm;
   prm.pr = row::row_problem(a, row_ptr, col_idx);
   prm.pr.num_heavy = 0;
-  prm.pr.heavy_flag = nullptr;
+  prm.pr.light_rows = nullptr;
+  prm.pr.num_light = a.plan.mb;
   prm.pr.heavy_rows = nullptr;
+  prm.pr.part = nullptr;
   prm.status = a.status;
   const int ns = a.ns;
   if (ns != 2 && ns != 4 && ns != 8) return fail(SPMM_ERR_INVALID_ARG, "column tile variant must be 2, 4 or 8");

@@ -155,9 +155,12 @@ def test_default_plan_holds_one_copy_of_the_values():
     free1 = torch.cuda.mem_get_info()[0]
     dev_bytes, val_bytes = plan.memory()
     assert val_bytes == nnzb * b * b * 2
-    # indices: col_idx and the in-group order (4 + 4 bytes per block), row
-    # pointers, panels, scratch and the SDDMM task list: under 64 KiB + 12 B/block
-    assert val_bytes < dev_bytes <= val_bytes + 12 * nnzb + 64 * 1024
+    # indices: col_idx and the in-group order (4 + 4 bytes per block), the
+    # tiled SDDMM's entry list (8 bytes per block), row pointers, panels,
+    # scratch and the task lists, 16 B per tiled task (at most one per
+    # 256 x 256 tile plus one per 24 blocks): under 64 KiB + 21 B/block + 16 B/tile
+    tiles = (m // 256) * (k // 256)
+    assert val_bytes < dev_bytes <= val_bytes + 21 * nnzb + 16 * tiles + 64 * 1024
     # what the device lost to the plan: one copy, never two (allocation rounding aside)
     assert free0 - free1 < 1.5 * val_bytes + 4 * 2**20
     plan.close()
