@@ -91,7 +91,9 @@ typedef enum { SPMM_F32 = 0, SPMM_F16 = 1, SPMM_BF16 = 2, SPMM_FP8_E4M3 = 3 } sp
  *               waves of a workgroup, partial sums added in wave order (b =
  *               16 with 16-bit X; the rule takes it for launches too small to
  *               fill the chip with one wave per row, SPMM_SPLIT_ALL=0/1
- *               forces it; it sums in another order than forms 1 and 2).
+ *               forces it; it sums in another order than forms 1 and 2);
+ *               5 = dynamic calls only: form 4's product with the encoding
+ *               in the same launch (a plan option rejects it).
  *               Other kernels have one variant and ignore it.
  *   dense_dispatch  static plans with W in the 16-bit X type and Y in it or
  *               FP32 (dynamic handles ignore it). 0 = never dense. 1 = ask the
@@ -370,11 +372,19 @@ spmm_status_t spmm_dynamic_create(int64_t m, int64_t k, int32_t b, int64_t max_n
  * is left untouched. The index and value buffers must hold max_nnzb entries'
  * worth of readable memory only up to the nnzb actually used. The first call
  * of a handle for an n class (the power of two at or above n) times the
- * compute kernel's variants on its own operands, as spmm_run_static does for
- * a plan (it synchronises `stream`; not with SPMM_AUTOTUNE=0 or on a stream
- * under capture, where the rules choose); later calls of that class run the
- * fastest. Results equal a static plan's of the same pattern bit for bit when
- * both run the same variant. */
+ * call's variants on its own operands, encoding included, as spmm_run_static
+ * does for a plan (it synchronises `stream`; not with SPMM_AUTOTUNE=0 or on a
+ * stream under capture, where the rules choose); later calls of that class
+ * run the fastest. The variants are the compute kernel's forms after an
+ * encoder launch, and, for b = 16 with W in the X type (FP16 or BF16), k a
+ * multiple of 16 and max_nnzb up to 2^16 blocks (keys in 64 KiB of LDS),
+ * form 5: one launch in which every workgroup (a block row and a column
+ * tile) reads the whole COO list, keeps and sorts its row's entries and runs
+ * form 4's product on them, writing the call's block-CSR on the way. The
+ * rule takes form 5 where it takes form 4 and the workgroups' redundant
+ * reads of the list stay under 2^24 entries (SPMM_DYN_FUSED=0/1 forces the
+ * choice). Results equal a static plan's of the same pattern bit for bit when
+ * both run the same variant (form 5 as form 4). */
 spmm_status_t spmm_run_dynamic(spmm_dyn_t h, const int32_t* nnzb_dev, const int32_t* block_row_dev,
                                const int32_t* block_col_dev, const void* values_dev,
                                const float* scales_dev, int64_t n, const void* X, int64_t ldx,

@@ -171,6 +171,17 @@ spmm_status_t launch_spmm_row_grouped_persist(spmm_dtype_t xt, spmm_dtype_t yt, 
 // LDS bytes of a grouped launch with split rows; work units of one problem.
 unsigned group_split_lds(int32_t b);
 int64_t group_problem_units(int32_t num_light, int64_t n, int32_t ns, int32_t num_heavy, bool inter);
+// One-launch dynamic call (b = 16, W in the X type, capacity up to 2^16 blocks
+// within the LDS of a workgroup): encode and multiply together, the every-row
+// split form's result; writes the call's block-CSR, status and count as the
+// encoders do.
+bool dynamic_fused_eligible(int32_t b, spmm_dtype_t w, spmm_dtype_t x, spmm_dtype_t y, int64_t k, int32_t mb,
+                            int32_t kb, int64_t max_nnz);
+bool dynamic_fused_preferred(int32_t mb, int64_t n, int64_t max_nnz);
+int32_t dynamic_fused_ns(int64_t n);
+spmm_status_t launch_dynamic_fused(const RunArgs& a, const int32_t* nnz_dev, const int32_t* rows, const int32_t* cols,
+                                   int32_t max_nnz, int32_t kb, int32_t* row_ptr, int32_t* col_idx, int32_t* src,
+                                   int32_t* status, int32_t* status_out, int32_t* nnz_last, hipStream_t s);
 // The fixup launch of a problem's cut rows after its pieces ran (grouped
 // launches; a single launch issues its own).
 spmm_status_t launch_group_fixup(const RunArgs& a, int ns, hipStream_t stream);

@@ -753,6 +753,23 @@ __global__ __launch_bounds__(kRowsThreads) void k_dyn_rows(const int32_t* __rest
     if (nnz_last) *nnz_last = nnz;
   }
   const int32_t kept = flag[1];
+  if (kept <= 64) {  // one wave ranks its lanes' keys against each other, without LDS round trips
+    if (tid < 64) {
+      const uint64_t key = tid < kept ? skey[tid] : ~(uint64_t)0;
+      const uint32_t hi = (uint32_t)(key >> 32), lo = (uint32_t)key;
+      int32_t rank = 0;
+      for (int32_t j = 0; j < kept; ++j) {
+        const uint32_t hj = (uint32_t)__builtin_amdgcn_readlane((int)hi, j);
+        const uint32_t lj = (uint32_t)__builtin_amdgcn_readlane((int)lo, j);
+        rank += (hj < hi || (hj == hi && lj < lo)) ? 1 : 0;
+      }
+      if (tid < kept) {
+        col_idx[first + rank] = (int32_t)((key >> 32) & 0x1FFFFFu);
+        src[first + rank] = (int32_t)(uint32_t)key;
+      }
+    }
+    return;
+  }
   for (int32_t i = tid; i < kept; i += kRowsThreads) {
     const uint64_t key = skey[i];
     int32_t rank = 0;

@@ -63,7 +63,8 @@ int n_class(int64_t n);
 // no split rows; the LDS-staged kernel for b = 4 with W in the X type), 3 =
 // the dense GEMM on the plan's dense copy (plans with dense dispatch), 4 = the
 // row kernel with every block row split over a workgroup's four waves (b =
-// 16, 16-bit X).
+// 16, 16-bit X), 5 = dynamic calls only: form 4 with the encoding in the same
+// launch.
 constexpr int kFormShift = 8;
 inline int32_t variant_ns(int32_t v) { return v & 0xff; }
 inline int32_t variant_form(int32_t v) { return v >> kFormShift; }

@@ -195,7 +195,8 @@ bool valid_variant(int32_t b, int32_t v) {
   if (v == 0) return true;
   if (v < 0) return false;
   const int32_t ns = variant_ns(v), form = variant_form(v);
-  if (form > 4 || (ns != 0 && ns != 2 && ns != 4 && ns != 8)) return false;
+  if (form > 5 || (ns != 0 && ns != 2 && ns != 4 && ns != 8)) return false;
+  if (form == 5 && b != 16) return false;
   return !(ns == 2 && b < 16);
 }
 
@@ -369,14 +370,17 @@ static bool tune_on_first_run(hipStream_t s) {
 }
 
 
-// Candidate variants of a dynamic handle's compute kernel.
-static int dynamic_candidates(int32_t b, spmm_dtype_t w, spmm_dtype_t x, int32_t (&c)[8]) {
+// Candidate variants of a dynamic call: the compute kernel's forms after the
+// encoder, and the one-launch form where it fits.
+static int dynamic_candidates(int32_t b, spmm_dtype_t w, spmm_dtype_t x, bool fused, int32_t (&c)[10]) {
   int k = 0;
   if (b >= 16 && (x == SPMM_F16 || x == SPMM_BF16)) {
     for (int32_t ns : {2, 4, 8}) c[k++] = make_variant(ns, 1);
     if (w == x && b <= 32)
       for (int32_t ns : {2, 4, 8}) c[k++] = make_variant(ns, 2);
     if (b == 16) c[k++] = make_variant(0, 4);
+    if (fused)
+      for (int32_t ns : {2, 4, 8}) c[k++] = make_variant(ns, 5);
   } else if (b < 16 && x != SPMM_F32) {
     c[k++] = make_variant(4, 1);
     c[k++] = make_variant(8, 1);
@@ -385,10 +389,6 @@ static int dynamic_candidates(int32_t b, spmm_dtype_t w, spmm_dtype_t x, int32_t
   return k;
 }
 
-// Block rows longer than max(64, 4 x the mean row) are split over the four
-// waves of a workgroup by the row-wise kernel for b = 16 (a long row would
-// otherwise be one wave's serial chain). SPMM_SPLIT=0 turns this off (for
-// comparisons).
 // Tiled SDDMM tasks (b = 16/32): the blocks of each tile of T x T blocks (T =
 // sddmm_tiled_tile_blocks), listed by block row then column, in tasks of at
 // most sddmm_tiled_task_blocks; tiles in (tile row, tile column) order.
@@ -611,6 +611,8 @@ spmm_status_t spmm_plan_static(int64_t m, int64_t k, int32_t b, const uint8_t* b
   if (nnzb > INT32_MAX / 2) return fail(SPMM_ERR_UNSUPPORTED, "too many nonzero blocks");
   if (opts && (opts->group_rows < 0 || opts->num_panels < 0))
     return fail(SPMM_ERR_INVALID_ARG, "negative plan option");
+  if (opts && variant_form(opts->variant) == 5)
+    return fail(SPMM_ERR_INVALID_ARG, "variant form 5 (one launch) is for dynamic calls");
   if (opts && !valid_variant(b, opts->variant))
     return fail(SPMM_ERR_INVALID_ARG, "variant must be 0 or (2, 4, 8 or 0) + 256 x (0 .. 4); 2 needs b >= 16");
   if (opts && (opts->dense_dispatch < 0 || opts->dense_dispatch > 2))
@@ -1008,7 +1010,8 @@ spmm_status_t spmm_run_dynamic(spmm_dyn_t h, const int32_t* nnzb_dev, const int3
   // re-bucket into block-CSR and run the block-CSR kernel (the same kernel and
   // order as a static plan of the same pattern). Small capacities encode in
   // one workgroup and leave the values in place (read through csr_src); edge
-  // blocks that cross k need the copying path, which zeroes their tail.
+  // blocks that cross k need the copying path, which zeroes their tail. Or, in
+  // one launch, encode and multiply together (variant form 5).
   const int want = requested_builder();
   const bool in_place = h->k % h->b == 0 && want != kBuilderMulti;
   const bool rows_fit = dynamic_rows_fits((int32_t)h->max_nnzb, h->mb, h->kb);
@@ -1018,21 +1021,25 @@ spmm_status_t spmm_run_dynamic(spmm_dyn_t h, const int32_t* nnzb_dev, const int3
   else if (in_place && one_fit) builder = kBuilderOne;
   else if (in_place && rows_fit) builder = kBuilderRows;
   const bool one_wg = builder != kBuilderMulti;  // values read in place through csr_src
-  if (builder == kBuilderRows) {
-    st = build_dynamic_csr_rows(nnzb_dev, rows, cols, (int32_t)h->max_nnzb, h->mb, h->kb, h->pb, h->status,
-                                status_dev, h->nnz_last, s);
-  } else if (builder == kBuilderOne) {
-    st = build_dynamic_csr_small(nnzb_dev, rows, cols, (int32_t)h->max_nnzb, h->mb, h->kb, h->geo, h->pb, h->status,
-                                 status_dev, h->nnz_last, s);
-  } else {
-    st = build_dynamic_csr(nnzb_dev, rows, cols, (int32_t)h->max_nnzb, h->mb, h->kb, h->b, (int32_t)h->k, h->geo,
-                           h->pb, values_dev, h->packed, dtype_bytes(h->w), scales_dev, h->packed_scales, h->status,
-                           status_dev, h->nnz_last, s);
+  const bool fused_ok = n > 0 && want == kBuilderNone &&
+                        dynamic_fused_eligible(h->b, h->w, h->x, h->y, h->k, h->mb, h->kb, h->max_nnzb);
+  auto encode = [&]() -> spmm_status_t {
+    if (builder == kBuilderRows)
+      return build_dynamic_csr_rows(nnzb_dev, rows, cols, (int32_t)h->max_nnzb, h->mb, h->kb, h->pb, h->status,
+                                    status_dev, h->nnz_last, s);
+    if (builder == kBuilderOne)
+      return build_dynamic_csr_small(nnzb_dev, rows, cols, (int32_t)h->max_nnzb, h->mb, h->kb, h->geo, h->pb,
+                                     h->status, status_dev, h->nnz_last, s);
+    return build_dynamic_csr(nnzb_dev, rows, cols, (int32_t)h->max_nnzb, h->mb, h->kb, h->b, (int32_t)h->k, h->geo,
+                             h->pb, values_dev, h->packed, dtype_bytes(h->w), scales_dev, h->packed_scales, h->status,
+                             status_dev, h->nnz_last, s);
+  };
+  if (n == 0) {  // the encode alone (status, export)
+    if ((st = encode()) != SPMM_OK) return st;
+    h->ran = true;
+    h->panels_current = builder != kBuilderRows;
+    return SPMM_OK;
   }
-  if (st != SPMM_OK) return st;
-  h->ran = true;
-  h->panels_current = builder != kBuilderRows;
-  if (n == 0) return SPMM_OK;
   RunArgs a{};
   a.plan = kernel_plan(h->m, h->k, h->b, h->mb, h->kb, h->geo, h->pb);
   a.W = one_wg ? values_dev : h->packed;
@@ -1048,13 +1055,32 @@ spmm_status_t spmm_run_dynamic(spmm_dyn_t h, const int32_t* nnzb_dev, const int3
   a.yt = h->y;
   a.status = h->status;
   a.nnz = h->max_nnzb;
-  // the first call of an n class times the compute kernel's variants on this
-  // call's block-CSR (the product is idempotent; the status word makes every
-  // candidate skip a failed encode alike), as a static plan's first run does
+  // one call with a variant: the one-launch form, else the encoder and then
+  // the compute kernel's form
+  auto call = [&](int32_t v) -> spmm_status_t {
+    if (variant_form(v) == 5 && fused_ok) {
+      RunArgs f = a;
+      f.W = values_dev;
+      f.ns = variant_ns(v) ? variant_ns(v) : default_ns(n);
+      h->panels_current = false;
+      return launch_dynamic_fused(f, nnzb_dev, rows, cols, (int32_t)h->max_nnzb, h->kb, h->pb.row_ptr,
+                                  h->pb.col_idx, h->pb.csr_src, h->status, status_dev, h->nnz_last, s);
+    }
+    spmm_status_t e = encode();
+    if (e != SPMM_OK) return e;
+    h->panels_current = builder != kBuilderRows;
+    RunArgs t = a;
+    return run_dynamic_kernel(t, h->pb.row_ptr, h->pb.col_idx, s, variant_form(v) == 5 ? 0 : v);
+  };
+  h->ran = true;
+  // the first call of an n class times every candidate on this call's
+  // operands, encoder included (the call is idempotent; the status word makes
+  // every candidate skip a failed encode alike), as a static plan's first run
+  // times its variants
   const int nc = n_class(n);
   if (!h->tuned[nc] && tune_on_first_run(s)) {
-    int32_t cand[8];
-    const int ncand = dynamic_candidates(h->b, h->w, h->x, cand);
+    int32_t cand[10];
+    const int ncand = dynamic_candidates(h->b, h->w, h->x, fused_ok, cand);
     if (ncand > 1) {
       hipEvent_t e0 = nullptr, e1 = nullptr;
       SPMM_HIP(hipEventCreate(&e0));
@@ -1062,16 +1088,10 @@ spmm_status_t spmm_run_dynamic(spmm_dyn_t h, const int32_t* nnzb_dev, const int3
       int32_t best = 0;
       float best_ms = 0.f;
       for (int c = 0; c < ncand && he == hipSuccess && st == SPMM_OK; ++c) {
-        for (int i = 0; i < 2 && st == SPMM_OK; ++i) {
-          RunArgs t = a;
-          st = run_dynamic_kernel(t, h->pb.row_ptr, h->pb.col_idx, s, cand[c]);
-        }
+        for (int i = 0; i < 2 && st == SPMM_OK; ++i) st = call(cand[c]);
         if (st != SPMM_OK) break;
         he = hipEventRecord(e0, s);
-        for (int i = 0; i < 5 && st == SPMM_OK && he == hipSuccess; ++i) {
-          RunArgs t = a;
-          st = run_dynamic_kernel(t, h->pb.row_ptr, h->pb.col_idx, s, cand[c]);
-        }
+        for (int i = 0; i < 5 && st == SPMM_OK && he == hipSuccess; ++i) st = call(cand[c]);
         if (he == hipSuccess) he = hipEventRecord(e1, s);
         if (he == hipSuccess) he = hipEventSynchronize(e1);
         float ms = 0.f;
@@ -1090,7 +1110,17 @@ spmm_status_t spmm_run_dynamic(spmm_dyn_t h, const int32_t* nnzb_dev, const int3
       if (enc == 0) h->tuned[nc] = best;
     }
   }
-  return run_dynamic_kernel(a, h->pb.row_ptr, h->pb.col_idx, s, h->tuned[nc]);
+  int32_t v = h->tuned[nc];
+  if (const char* dv = getenv("SPMM_DYN_VARIANT")) {  // a fixed variant (comparisons, tests)
+    const int32_t fv = (int32_t)atoi(dv);
+    if (valid_variant(h->b, fv)) v = fv;
+  }
+  if (!v && fused_ok) {  // the rule: one launch where the every-row split form is the rule and the grid is small
+    if (split_all_preferred(h->b, h->mb, n, default_ns(n), h->max_nnzb, device_cu_count()) &&
+        dynamic_fused_preferred(h->mb, n, h->max_nnzb))
+      v = make_variant(dynamic_fused_ns(n), 5);
+  }
+  return call(v);
 }
 
 spmm_status_t spmm_dynamic_export(spmm_dyn_t h, int32_t* row_ptr, int32_t* col_idx, int32_t* src, int32_t* panel_ptr,

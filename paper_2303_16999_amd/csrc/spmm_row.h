@@ -164,11 +164,28 @@ __device__ __forceinline__ void xfrag(__amdgpu_buffer_rsrc_t xr, const RowProble
   transpose4<NS>(rows, out);
 }
 
+// Where a wave finds entry q of the row it walks: its block column and the
+// block of W that holds its values. CsrIndex reads the plan's arrays (col_idx,
+// and w_index when the values are not in CSR order); LdsKeys reads a sorted
+// list of (column << 16 | input index) keys in LDS (the one-launch dynamic
+// call, whose values stay in input order).
+struct CsrIndex {
+  const int32_t* col;
+  const int32_t* widx;
+  __device__ __forceinline__ int32_t column(int32_t q) const { return sload(col, q); }
+  __device__ __forceinline__ int64_t block(int32_t q) const { return widx ? (int64_t)sload(widx, q) : (int64_t)q; }
+};
+struct LdsKeys {
+  const uint32_t* keys;
+  __device__ __forceinline__ int32_t column(int32_t q) const { return uniform((int32_t)(keys[q] >> 16)); }
+  __device__ __forceinline__ int64_t block(int32_t q) const { return (int64_t)uniform((int32_t)(keys[q] & 0xffffu)); }
+};
+
 // Accumulates the blocks q_lo .. q_hi of one block row (in CSR order) for
 // columns n0 .. n0 + 16*NS into acc (one wave; acc starts at zero).
-template <typename XT, typename WT, int B, int NS>
+template <typename XT, typename WT, int B, int NS, typename IX = CsrIndex, int PFX = 8 / NS>
 __device__ __forceinline__ void row_acc(const RowProblem& p, int32_t q_lo, int32_t q_hi, int32_t n0, int lane,
-                                        float4_t (&acc)[B / 16][NS]) {
+                                        float4_t (&acc)[B / 16][NS], IX ix = IX{nullptr, nullptr}) {
   static_assert(NS == 2 || NS == 4 || NS == 8, "column tiles per wave");
   constexpr bool kFp8 = __is_same(WT, Fp8);
   constexpr int WB = B * B * (kFp8 ? 1 : 2);  // bytes per block
@@ -180,14 +197,14 @@ __device__ __forceinline__ void row_acc(const RowProblem& p, int32_t q_lo, int32
   for (int h = 0; h < H; ++h)
 #pragma unroll
     for (int s = 0; s < NS; ++s) acc[h][s] = float4_t{0.f, 0.f, 0.f, 0.f};
-  const int32_t* __restrict__ widx = p.w_index;
-  auto wq = [&](int32_t q) -> int64_t { return widx ? (int64_t)sload(widx, q) : (int64_t)q; };
+  if constexpr (__is_same(IX, CsrIndex)) ix = CsrIndex{p.col_idx, p.w_index};
+  auto wq = [&](int32_t q) -> int64_t { return ix.block(q); };
   if constexpr (!kFp8 && B == 16) {
     // pairs of blocks: k slots 0-3 from the first block, 4-7 from the second.
     // PF pairs are loaded before their MFMAs (more loads in flight where the
     // column tile, and so each pair's register footprint, is narrow); the
     // MFMAs still run pair after pair, so the sums do not depend on PF.
-    constexpr int PF = 8 / NS;
+    constexpr int PF = PFX;
     for (int32_t q0 = q_lo; q0 < q_hi; q0 += 2 * PF) {
       u32x4 a[PF];
       u32x2 b1[PF][NS], b2[PF][NS];
@@ -196,8 +213,8 @@ __device__ __forceinline__ void row_acc(const RowProblem& p, int32_t q_lo, int32
         const int32_t q = q0 + 2 * f;
         if (f > 0 && q >= q_hi) break;
         const bool two = q + 1 < q_hi;
-        const int32_t c1 = sload(p.col_idx, q);
-        const int32_t c2 = two ? sload(p.col_idx, q + 1) : c1;
+        const int32_t c1 = ix.column(q);
+        const int32_t c2 = two ? ix.column(q + 1) : c1;
         const u32x2 a1 = *(const u32x2*)(Wb + wq(q) * WB + (j * 16 + g * 4) * 2);
         const u32x2 a2 = two ? *(const u32x2*)(Wb + wq(q + 1) * WB + (j * 16 + g * 4) * 2) : u32x2{0u, 0u};
         a[f] = u32x4{a1.x, a1.y, a2.x, a2.y};
@@ -219,7 +236,7 @@ __device__ __forceinline__ void row_acc(const RowProblem& p, int32_t q_lo, int32
     }
   } else if constexpr (!kFp8) {  // B == 32: k slots 0-3 and 4-7 are rows 8g..8g+3 and 8g+4..8g+7
     for (int32_t q = q_lo; q < q_hi; ++q) {
-      const int32_t c = sload(p.col_idx, q);
+      const int32_t c = ix.column(q);
       u32x2 b1[NS], b2[NS];
       xfrag<NS>(xr, p, c * 32, 2 * g, j, n0, b1);      // rows c*32 + 8g + i
       xfrag<NS>(xr, p, c * 32 + 4, 2 * g, j, n0, b2);  // rows c*32 + 8g + 4 + i
@@ -232,7 +249,7 @@ __device__ __forceinline__ void row_acc(const RowProblem& p, int32_t q_lo, int32
     }
   } else {  // FP8 weights with a per-block scale
     for (int32_t q = q_lo; q < q_hi; ++q) {
-      const int32_t c = sload(p.col_idx, q);
+      const int32_t c = ix.column(q);
       const int64_t qv = wq(q);
       const float sc = p.scales[qv];
       if constexpr (B == 16) {

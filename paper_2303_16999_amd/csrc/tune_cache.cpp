@@ -96,6 +96,7 @@ bool tune_cache_load(const char* path, std::map<TuneKey, int32_t>& table) {
       if (!find_int(text, p, q, keys[i], &v[i])) return false;
     if (!valid_variant((int32_t)v[0], (int32_t)v[7]) || v[7] == 0 || (v[6] != 0 && v[6] != 1)) return false;
     if (v[6] == 0 && (v[7] >> kFormShift) == 3) return false;  // the dense form needs a dense copy
+    if ((v[7] >> kFormShift) == 5) return false;                // the one-launch form is for dynamic calls
     got[TuneKey((int)v[0], (int)v[1], (int)v[2], (int)v[3], (int)v[4], (int)v[5], (int)v[6])] = (int32_t)v[7];
     p = q;
   }

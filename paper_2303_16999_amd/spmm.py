@@ -127,9 +127,24 @@ def _ptr(t):
     return t.data_ptr()
 
 
+_TORCH = None
+
+
+def _torch():
+    """torch, imported on first use (the module itself does not need it)."""
+    global _TORCH
+    if _TORCH is None:
+        import torch
+        _TORCH = torch
+    return _TORCH
+
+
 def _stream(stream):
     if stream is None:
-        import torch
+        torch = _torch()
+        raw = getattr(torch._C, "_cuda_getCurrentRawStream", None)  # the handle, without a Stream object
+        if raw is not None:
+            return raw(torch.cuda.current_device())
         return torch.cuda.current_stream().cuda_stream
     if isinstance(stream, int):
         return stream
@@ -140,9 +155,15 @@ def _opts(group_rows=0, num_panels=0, n_hint=0, variant=0, dense_dispatch=0):
     return PlanOpts(int(group_rows), int(num_panels), int(n_hint), int(variant), int(dense_dispatch))
 
 
+_TORCH_DTYPES = None
+
+
 def torch_dtype(code):
-    import torch
-    return {F32: torch.float32, F16: torch.float16, BF16: torch.bfloat16, FP8_E4M3: torch.uint8}[code]
+    global _TORCH_DTYPES
+    if _TORCH_DTYPES is None:
+        torch = _torch()
+        _TORCH_DTYPES = {F32: torch.float32, F16: torch.float16, BF16: torch.bfloat16, FP8_E4M3: torch.uint8}
+    return _TORCH_DTYPES[code]
 
 
 _ELEM_BYTES = {F32: 4, F16: 2, BF16: 2, FP8_E4M3: 1}
@@ -154,8 +175,7 @@ def check_dense(t, rows, n, code, name, on_gpu=True):
     stride, at least `rows` rows and n columns, on the GPU (on_gpu=False
     leaves that last check to the caller). Only shapes, strides, dtypes and
     the device are looked at."""
-    import torch
-    if not isinstance(t, torch.Tensor):
+    if not isinstance(t, _torch().Tensor):
         raise TypeError("%s must be a torch tensor" % name)
     if t.dim() != 2:
         raise ValueError("%s must be 2-D, got %d dimensions" % (name, t.dim()))
@@ -179,12 +199,12 @@ def check_gpu(t, name):
 def check_flat(t, count, elem_bytes, name, dtype=None, on_gpu=True):
     """Rejects a device buffer of fewer than `count` elements of `elem_bytes`
     bytes (values, scales, indices), of the wrong dtype, or not on the GPU."""
-    import torch
-    if not isinstance(t, torch.Tensor):
+    if not isinstance(t, _torch().Tensor):
         raise TypeError("%s must be a torch tensor" % name)
-    if dtype is not None and t.dtype != dtype:
-        raise ValueError("%s has dtype %s, expected %s" % (name, t.dtype, dtype))
-    if t.element_size() != elem_bytes:
+    if dtype is not None:
+        if t.dtype != dtype:
+            raise ValueError("%s has dtype %s, expected %s" % (name, t.dtype, dtype))
+    elif t.element_size() != elem_bytes:
         raise ValueError("%s has %d-byte elements, expected %d" % (name, t.element_size(), elem_bytes))
     if not t.is_contiguous():
         raise ValueError("%s must be contiguous" % name)
@@ -406,7 +426,7 @@ class DynamicHandle:
 
     def run(self, nnz_dev, rows, cols, values, X, Y, status_dev, scales=None, n=None, ldx=None, ldy=None,
             stream=None):
-        import torch
+        torch = _torch()
         n = _ncols(X) if n is None else int(n)
         check_dense(X, self.k, n, self.x, "X", on_gpu=False)
         check_dense(Y, self.m, n, self.y, "Y", on_gpu=False)

@@ -420,3 +420,125 @@ def test_multi_kernel_encoder_status_words(monkeypatch):
     ex = h.export()
     for key in ("row_ptr", "col_idx", "src", "panel_ptr"):
         assert np.array_equal(ex[key], ref[key]), key
+
+
+# ---- the one-launch form: encode and multiply in one kernel (variant form 5)
+
+def _call(h, nnz, r, c, v, X, Y, n, monkeypatch, fused):
+    monkeypatch.setenv("SPMM_SPLIT_ALL", "1")  # the two-launch call runs the every-row split form
+    monkeypatch.setenv("SPMM_DYN_FUSED", "1" if fused else "0")
+    status = torch.full((1,), -1, dtype=torch.int32, device="cuda")
+    h.run(nnz, r, c, v, X, Y, status, n=n)
+    torch.cuda.synchronize()
+    return status.item()
+
+
+@pytest.mark.parametrize("x,y,n", [("f16", "f16", 512), ("bf16", "f32", 70), ("f16", "f16", 1)])
+def test_one_launch_call_equals_two_launch_call(x, y, n, monkeypatch):
+    # ragged m, COO in random order with duplicates; both forms give the same
+    # Y bit for bit and the same exported block-CSR, and match the oracle
+    b, m, k = 16, 37 * 16 + 5, 48 * 16
+    mb, kb = -(-m // b), k // b
+    g = np.random.default_rng(7)
+    nnz0 = 300
+    rows = g.integers(0, mb, nnz0).astype(np.int32)
+    cols = g.integers(0, kb, nnz0).astype(np.int32)
+    vals = synth.to_storage(synth.normal((nnz0, b, b), 8), x)
+    Xs = synth.to_storage(synth.normal((k, n), 9), x)
+    max_nnz = 320
+    r, c, v, nnz = _dyn_inputs(rows, cols, vals, max_nnz, b)
+    ld = -(-n // 8) * 8  # leading dimensions of 16-byte multiples
+    X = torch.zeros((k, ld), dtype=spmm.torch_dtype(spmm.DTYPE_CODES[x]), device="cuda")
+    X[:, :n] = dev(Xs)
+    outs, exports = [], []
+    for fused in (True, False):
+        h = spmm.DynamicHandle(m, k, b, max_nnz, x, y=y)
+        Y = torch.full((m, ld), float("nan"), dtype=spmm.torch_dtype(spmm.DTYPE_CODES[y]), device="cuda")
+        assert _call(h, nnz, r, c, v, X, Y, n, monkeypatch, fused) == 0
+        outs.append(Y[:, :n])
+        exports.append(h.export())
+    assert torch.equal(outs[0], outs[1])
+    for key in ("row_ptr", "col_idx", "src", "panel_ptr"):
+        assert np.array_equal(exports[0][key], exports[1][key]), key
+    ref = O.spmm_expand(m, k, b, rows, cols, synth.storage_to_f64(vals, x), synth.storage_to_f64(Xs, x))
+    got = outs[0].float().cpu().numpy().astype(np.float64)
+    A = O.spmm_expand(m, k, b, rows, cols, np.abs(synth.storage_to_f64(vals, x)), np.abs(synth.storage_to_f64(Xs, x)))
+    assert_elementwise(got, ref, A, 2 * k, y)
+
+
+def test_one_launch_long_row_sorted_by_network(monkeypatch):
+    # 3000 entries of one block row (duplicates of 64 columns) and a few
+    # elsewhere: more than 8 keys per thread, so the row is sorted by the
+    # bitonic network; equal to the two-launch call and the oracle
+    b, m, k, n = 16, 8 * 16, 64 * 16, 96
+    g = np.random.default_rng(11)
+    rows = np.concatenate([np.full(3000, 5), g.integers(0, 8, 40)]).astype(np.int32)
+    cols = g.integers(0, 64, len(rows)).astype(np.int32)
+    vals = synth.to_storage(synth.integers((len(rows), b, b), 12, -1, 1), "f16")
+    Xs = synth.to_storage(synth.integers((k, n), 13, -1, 1), "f16")
+    max_nnz = 4096
+    r, c, v, nnz = _dyn_inputs(rows, cols, vals, max_nnz, b)
+    X = dev(Xs)
+    outs = []
+    for fused in (True, False):
+        h = spmm.DynamicHandle(m, k, b, max_nnz, "f16", y="f32")
+        Y = torch.full((m, n), float("nan"), dtype=torch.float32, device="cuda")
+        assert _call(h, nnz, r, c, v, X, Y, n, monkeypatch, fused) == 0
+        outs.append(Y)
+    assert torch.equal(outs[0], outs[1])
+    ref = O.spmm_expand(m, k, b, rows, cols, synth.storage_to_f64(vals, "f16"), synth.storage_to_f64(Xs, "f16"))
+    assert np.array_equal(outs[0].cpu().numpy().astype(np.float64), ref)  # integer sums, exact in FP32
+
+
+def test_one_launch_status_words_and_empty_call(monkeypatch):
+    b, m, k, n = 16, 64, 64, 32
+    h = spmm.DynamicHandle(m, k, b, 8, "f16")
+    X = torch.ones((k, n), dtype=torch.float16, device="cuda")
+    v = torch.ones((8, b, b), dtype=torch.float16, device="cuda")
+    for rows, cols, nnz, want in [([0] * 8, [0] * 8, 9, spmm.ERR_CAPACITY), ([0] * 8, [0] * 8, -1, spmm.ERR_CAPACITY),
+                                  ([0, 4] + [0] * 6, [0, 1] + [0] * 6, 2, spmm.ERR_BAD_INDEX),
+                                  ([0, 1] + [0] * 6, [0, -1] + [0] * 6, 2, spmm.ERR_BAD_INDEX)]:
+        Y = torch.full((m, n), 7.0, dtype=torch.float16, device="cuda")
+        r = torch.tensor(rows, dtype=torch.int32, device="cuda")
+        c = torch.tensor(cols, dtype=torch.int32, device="cuda")
+        nz = torch.tensor([nnz], dtype=torch.int32, device="cuda")
+        assert _call(h, nz, r, c, v, X, Y, n, monkeypatch, True) == want
+        assert torch.all(Y == 7.0).item()
+    # an empty call writes zeros; then a valid one
+    r = torch.zeros(8, dtype=torch.int32, device="cuda")
+    Y = torch.full((m, n), 7.0, dtype=torch.float16, device="cuda")
+    assert _call(h, torch.tensor([0], dtype=torch.int32, device="cuda"), r, r, v, X, Y, n, monkeypatch, True) == 0
+    assert torch.all(Y == 0).item()
+    assert h.export()["row_ptr"].tolist() == [0] * (m // b + 1)
+    Y = torch.full((m, n), 7.0, dtype=torch.float16, device="cuda")
+    assert _call(h, torch.tensor([1], dtype=torch.int32, device="cuda"), r, r, v, X, Y, n, monkeypatch, True) == 0
+    assert torch.all(Y[:16] == 16.0).item() and torch.all(Y[16:] == 0).item()
+
+
+def test_one_launch_rule_at_the_dynamic_workload(monkeypatch):
+    # m = k = 4096, n = 512, 8192 blocks at most: the rule runs the one-launch
+    # form (no export of panels is made by it; the export derives them), and
+    # its result equals the two-launch call's bit for bit
+    monkeypatch.delenv("SPMM_DYN_FUSED", raising=False)
+    b, m, k, n = 16, 4096, 4096, 512
+    mb = kb = 256
+    max_nnz = mb * kb // 8
+    rows, cols, vals = synth.dynamic_call(mb, kb, b, max_nnz, seed=5, dtype="f16")
+    r, c, v, nnz = _dyn_inputs(rows, cols, vals, max_nnz, b)
+    X = dev(synth.to_storage(synth.normal((k, n), 2), "f16"))
+    outs = []
+    for env in (None, "0"):
+        if env is None:
+            monkeypatch.delenv("SPMM_DYN_FUSED", raising=False)
+        else:
+            monkeypatch.setenv("SPMM_DYN_FUSED", env)
+        h = spmm.DynamicHandle(m, k, b, max_nnz, "f16")
+        Y = torch.full((m, n), float("nan"), dtype=torch.float16, device="cuda")
+        status = torch.full((1,), -1, dtype=torch.int32, device="cuda")
+        h.run(nnz, r, c, v, X, Y, status)
+        torch.cuda.synchronize()
+        assert status.item() == 0
+        outs.append((Y, h.export()))
+    assert torch.equal(outs[0][0], outs[1][0])
+    for key in ("row_ptr", "col_idx", "src", "panel_ptr"):
+        assert np.array_equal(outs[0][1][key], outs[1][1][key]), key
