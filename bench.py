@@ -70,6 +70,7 @@ def parse():
     ap.add_argument("--no-dense", action="store_true", help="skip the dense FP16 comparator")
     ap.add_argument("--out", default=None, help="also append JSON lines to this file")
     ap.add_argument("--calls", type=int, default=1000, help="dynamic mode: number of calls")
+    ap.add_argument("--dyn-n", type=int, default=512, help="dynamic mode: columns of X")
     ap.add_argument("--sweep-b", default="1,4,8,16,32", help="sweep mode: block sizes")
     ap.add_argument("--sweep-n", default="256,1024,4096", help="sweep mode: column counts")
     ap.add_argument("--point", default="8192,8192,4096,16,16,f16,f16,f16",
@@ -437,13 +438,14 @@ def mode_precision(args):
 
 
 def mode_dynamic(args):
-    """Dynamic mode: m = k = 4096, n = 512, b = 16, max density 1/8; every call
-    brings a fresh pattern (nnz uniform in [max/2, max]) and fresh FP16 values.
-    All call inputs are uploaded before timing; per-call HIP events."""
+    """Dynamic mode: m = k = 4096, n = 512 (--dyn-n), b = 16, max density 1/8;
+    every call brings a fresh pattern (nnz uniform in [max/2, max]) and fresh
+    FP16 values. All call inputs are uploaded before timing; per-call HIP
+    events, and the same calls replayed from a captured HIP graph."""
     import torch
     from paper_2303_16999_amd import spmm, synth
     m = k = 4096
-    n, b = 512, 16
+    n, b = args.dyn_n, 16
     mb = kb = m // b
     max_nnz = mb * kb // 8
     calls = args.calls
@@ -496,6 +498,32 @@ def mode_dynamic(args):
         st_ms.append(time_steps(lambda: plan.run(X, Y), 10, 2))
         dy_ms.append(time_steps(lambda: call(i), 10, 2))
         plan.close()
+    # the same calls captured in one HIP graph (each call's block count is on
+    # the device, so the captured calls take their new patterns on every
+    # replay): device time per call without the host's launch work. Every
+    # replay follows eager work and is checked against the eager result.
+    G = min(64, calls)
+    call(G - 1)
+    torch.cuda.synchronize()
+    Y_ref = Y.clone()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        for i in range(G):
+            call(i)
+    g_ms = []
+    for _ in range(6):
+        Y.fill_(float("nan"))
+        status[:G].fill_(-1)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        graph.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        assert int(status[:G].max().item()) == 0 and int(status[:G].min().item()) == 0, "a replayed call failed"
+        assert torch.equal(Y, Y_ref), "a graph replay differs from the eager call"
+        g_ms.append(e0.elapsed_time(e1) / G)
+    del graph
     # end to end: each call's COO and values come from pinned host memory over PCIe first
     ne = min(32, calls)
     rows_h = torch.empty((ne, max_nnz), dtype=torch.int32, pin_memory=True)
@@ -540,6 +568,7 @@ def mode_dynamic(args):
            "e2e_h2d_gbs": round(float(e2e_bytes.sum() / (per2.sum() * 1e-3) / 1e9), 2),
            "call_ms_mean": round(float(per.mean()), 5), "call_ms_p50": round(float(np.percentile(per, 50)), 5),
            "call_ms_p99": round(float(np.percentile(per, 99)), 5),
+           "graph_call_ms": round(float(np.median(g_ms)), 5), "graph_calls": G,
            "tflops": round(float(flops.sum() / (per.sum() * 1e-3) / 1e12), 3),
            "static_ms_mean_same_patterns": round(float(np.mean(st_ms)), 5),
            "dynamic_ms_mean_same_patterns": round(float(np.mean(dy_ms)), 5),
