@@ -220,3 +220,40 @@ def test_pieces_rule_at_full_size(kind, n, cut, monkeypatch):
     cols = np.arange(0, c.n, 37)
     ref = c.oracle(cols)
     assert_elementwise(y_f64(Y, c)[:, cols], ref, c.abs_oracle(cols), 8192, "f16")
+
+
+def test_pieces_with_fp8_weights_and_block_scales(monkeypatch):
+    # FP8 E4M3 weights with per-block FP32 scales, BF16 X: the pieces' partial
+    # sums carry the scaled products; against the dequantized-input oracle
+    monkeypatch.setenv("SPMM_PIECES", "1")
+    mask = _full_rows_mask(40, 640, [2, 39], 1 / 16, 17)
+    c = Case(40 * 16, 640 * 16, 200, 16, 0.0, w="fp8", x="bf16", y="f32", seed=17, mask=mask, scaled=True)
+    plan, X = _plan_for(c)
+    before = plan.memory()[0]
+    Y = c.new_Y()
+    plan.run(X, Y, n=c.n)
+    torch.cuda.synchronize()
+    assert plan.memory()[0] > before
+    assert_elementwise(y_f64(Y, c), c.oracle(), c.abs_oracle(), 640 * 16, "f32")
+
+
+def test_grouped_pieces_apply_relu_in_the_fixup(monkeypatch):
+    monkeypatch.setenv("SPMM_PIECES", "1")
+    mask = _full_rows_mask(24, 600, [0, 11], 1 / 16, 19)
+    cases = [Case(24 * 16, 600 * 16, n, 16, 0.0, w="f16", seed=19 + i, mask=mask) for i, n in enumerate((96, 130))]
+    plan, _ = _plan_for(cases[0])
+    Xs = [c.device_inputs()[1] for c in cases]
+    singles = []
+    for c, X in zip(cases, Xs):
+        Y = c.new_Y()
+        plan.run(X, Y, n=c.n)
+        torch.cuda.synchronize()
+        singles.append(Y[:, : c.n].clone())
+    g = spmm.Group(4)
+    Ys = [c.new_Y() for c in cases]
+    g.run([plan, plan], Xs, Ys, ns=[c.n for c in cases], relu=[1, 0])
+    torch.cuda.synchronize()
+    assert torch.equal(Ys[0][:, : cases[0].n], torch.clamp(singles[0], min=0))
+    assert torch.equal(Ys[1][:, : cases[1].n], singles[1])
+    assert (singles[0] < 0).any()  # the ReLU had something to clamp, cut rows included
+    assert (Ys[0][:16, : cases[0].n] >= 0).all()  # block row 0 is a cut row
