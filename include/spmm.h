@@ -200,16 +200,17 @@ spmm_status_t spmm_run_static(spmm_plan_t plan, int64_t n, const void* X, int64_
 /* Plan facts: nonzero blocks, block rows per group, number of groups, panels,
  * and the number of block rows the row-wise kernel (b = 16, 16-bit X)
  * splits over the four waves of a workgroup: rows with more than
- * max(64, 4 x the mean) blocks, found when the plan is built (Appendix A.2's
+ * max(64, 2 x the mean) blocks, found when the plan is built (Appendix A.2's
  * worst case is a partition whose nonzeros all sit in one row). Rows longer
- * than max(128, that limit) are also cut into pieces of about that many
- * blocks, one workgroup each; the workgroup that finishes a row's last piece
- * adds the pieces' FP32 partial sums in piece order. Both reductions are in a
- * fixed order, so results stay bitwise reproducible (and equal between
- * spmm_run_static and spmm_group_run), but a dynamic call of the same
- * pattern, which never splits, may differ from it in the last bits. The
- * remaining rows are taken longest first where the pattern is skewed (a row
- * over twice the mean, or any split row), which changes no result. Any
+ * than max(256, 2 x that limit) blocks can also be cut into pieces of at most
+ * that many blocks, one workgroup each, where a run finds their lengths
+ * widely spread or too few workgroups for the chip; a second launch on the
+ * same stream adds the pieces' FP32 partial sums in piece order. Both
+ * reductions are in a fixed order, so results stay bitwise reproducible (and
+ * equal between spmm_run_static and spmm_group_run), but a dynamic call of
+ * the same pattern, which never splits, may differ from it in the last bits.
+ * The remaining rows are taken longest first where the pattern is skewed (a
+ * row over twice the mean, or any split row), which changes no result. Any
  * pointer may be NULL. */
 /* Dense dispatch facts: *predicted_speedup (may be NULL) receives the speedup
  * model's sparse/dense ratio for the plan's shape (0 for an empty pattern);
@@ -321,7 +322,7 @@ spmm_status_t spmm_autotune_clear(void);
  * kernel launch: one workgroup per work unit of all the problems. This goes
  * beyond the paper, whose benchmarks run one product at a time and let n grow
  * to amortise overheads (Sections 4 and 5); here the columns of many small
- * products share one launch instead. Up to 26 problems travel in the kernel
+ * products share one launch instead. Up to 28 problems travel in the kernel
  * arguments of one direct launch (with SPMM_GROUP_GRAPH=1 in the environment,
  * the call instead replays a captured one-node HIP graph after updating that
  * node's arguments and grid). Larger groups go through a ring of
