@@ -262,7 +262,12 @@ spmm_status_t spmm_plan_destroy(spmm_plan_t plan);
  * its x dtype (both FP16 or both BF16), row-major, leading dimensions lddy and
  * ldx; G is FP32 [nnzb][b][b] row-major on the device (caller-owned). Rows
  * and columns of edge blocks outside m x k come out 0. b = 1, 4, 8, 16 or
- * 32. FP32 accumulation over n.
+ * 32. FP32 accumulation over n. Where the mask is dense enough for its block
+ * size (density at least 1/128, 1/32, 1/16, 3/16, 1/4 for b = 1, 4, 8, 16,
+ * 32), the product is a library GEMM of all of dY X^T (FP32, in row panels of
+ * at most 128 MiB that the plan keeps from its first use) and a gather of the
+ * mask's blocks, else kernels that compute only the mask's blocks;
+ * SPMM_SDDMM_DENSE=0/1 forces the choice. The two sum in different orders.
  * Errors: INVALID_ARG (NULL, ld < n, alignment), UNSUPPORTED (block size
  * 64, dtypes), HIP. */
 spmm_status_t spmm_plan_transpose(spmm_plan_t plan, const spmm_plan_opts* opts, spmm_plan_t* out);

@@ -94,3 +94,73 @@ spmm_status_t run_dense(const spmm_plan_s* p, int64_t n, const void* X, int64_t 
 }
 
 }  // namespace spmm
+
+namespace spmm {
+namespace {
+
+// The blocks of block rows [r0, r0 + rb) of a plan, gathered from a dense FP32
+// panel D (rows r0 * b .. of dY X^T, row-major, leading dimension k) into G in
+// CSR order; zero outside m x k.
+__global__ void k_gather_blocks(const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col_idx, int32_t r0,
+                                int32_t rb, int32_t b, int64_t m, int64_t k, const float* __restrict__ D,
+                                float* __restrict__ G) {
+  const int32_t lo = row_ptr[r0], hi = row_ptr[r0 + rb];
+  const int64_t bb = (int64_t)b * b;
+  for (int64_t i = (int64_t)lo * bb + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < (int64_t)hi * bb;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t e = i / bb, w = i - e * bb;
+    int32_t a = r0, z = r0 + rb - 1;  // the block row of entry e: the last row whose first entry is <= e
+    while (a < z) {
+      const int32_t mid = (a + z + 1) >> 1;
+      if (row_ptr[mid] <= e) a = mid;
+      else z = mid - 1;
+    }
+    const int64_t row = (int64_t)a * b + w / b, col = (int64_t)col_idx[e] * b + w % b;
+    G[i] = (row < m && col < k) ? D[(row - (int64_t)r0 * b) * k + col] : 0.f;
+  }
+}
+
+}  // namespace
+
+int64_t sddmm_dense_panel_rows(const spmm_plan_s* p) {
+  const int64_t cap = (int64_t)128 << 20;  // bytes of one FP32 panel
+  int64_t rows = std::max<int64_t>(p->b, cap / (4 * std::max<int64_t>(p->k, 1)));
+  rows = std::min<int64_t>(rows, (int64_t)p->mb * p->b);
+  return rows / p->b * p->b;
+}
+
+spmm_status_t sddmm_dense(const spmm_plan_s* p, int64_t n, const void* dY, int64_t lddy, const void* X, int64_t ldx,
+                          float* G, float* ws, hipStream_t s) {
+  const int64_t P = sddmm_dense_panel_rows(p);
+  const int32_t pb = (int32_t)(P / p->b);
+  std::lock_guard<std::mutex> lk(g_blas_mu);
+  rocblas_handle& h = g_blas[p->device];
+  if (!h && rocblas_create_handle(&h) != rocblas_status_success) {
+    h = nullptr;
+    return fail(SPMM_ERR_HIP, "rocblas_create_handle failed");
+  }
+  if (rocblas_set_stream(h, s) != rocblas_status_success) return fail(SPMM_ERR_HIP, "rocblas_set_stream failed");
+  const float alpha = 1.f, beta = 0.f;
+  const size_t eb = 2;  // FP16 / BF16 dY and X
+  for (int32_t r0 = 0; r0 < p->mb; r0 += pb) {
+    const int32_t rb = std::min<int32_t>(pb, p->mb - r0);
+    const int64_t rows = std::min<int64_t>((int64_t)rb * p->b, p->m - (int64_t)r0 * p->b);
+    // column-major view: the panel's (dY X^T)^T (k x rows) = X (k x n, X^T stored) * dY^T (n x rows)
+    const void* dYp = (const uint8_t*)dY + (size_t)r0 * p->b * lddy * eb;
+    const rocblas_status r =
+        rocblas_gemm_ex(h, rocblas_operation_transpose, rocblas_operation_none, (rocblas_int)p->k, (rocblas_int)rows,
+                        (rocblas_int)n, &alpha, X, rb_type(p->x), (rocblas_int)ldx, dYp, rb_type(p->x),
+                        (rocblas_int)lddy, &beta, ws, rocblas_datatype_f32_r, (rocblas_int)p->k, ws,
+                        rocblas_datatype_f32_r, (rocblas_int)p->k, rocblas_datatype_f32_r, rocblas_gemm_algo_standard, 0,
+                        0);
+    if (r != rocblas_status_success)
+      return fail(SPMM_ERR_HIP, std::string("rocblas_gemm_ex failed: ") + rocblas_status_to_string(r));
+    const unsigned grid = (unsigned)std::min<int64_t>(65536, ceil_div(p->nnzb * p->b * p->b, 256));
+    hipLaunchKernelGGL(k_gather_blocks, dim3(grid), dim3(256), 0, s, p->pb.row_ptr, p->pb.col_idx, r0, rb, p->b, p->m,
+                       p->k, (const float*)ws, G);
+    SPMM_HIP(hipGetLastError());
+  }
+  return SPMM_OK;
+}
+
+}  // namespace spmm

@@ -45,6 +45,8 @@ struct spmm_plan_s {
   int32_t* sddmm_tiled_tasks = nullptr;  // device [n][4] (b = 16/32): tile row, tile column, first, count
   int32_t* sddmm_tiled_ent = nullptr;    // device [nnzb][2]: CSR index, packed block position in its tile
   int32_t sddmm_tiled_num = 0;
+  float* sddmm_dense_ws = nullptr;    // device panel for the dense-GEMM weight gradient, from its first use
+  int64_t sddmm_dense_ws_bytes = 0;
   double predicted_speedup = 0.0;  // speedup model's sparse/dense ratio for this plan's shape
   int32_t dense_mode = 0;          // dense dispatch option (0 off, 1 where the model favours dense, 2 always)
   void* dense_w = nullptr;         // dense copy of M o W (m x k, row-major) when the plan keeps one
@@ -98,6 +100,12 @@ bool dense_dispatch_eligible(spmm_dtype_t w, spmm_dtype_t x, spmm_dtype_t y);
 spmm_status_t build_dense_copy(spmm_plan_s* p, hipStream_t s);
 spmm_status_t run_dense(const spmm_plan_s* p, int64_t n, const void* X, int64_t ldx, void* Y, int64_t ldy,
                         hipStream_t s);
+// Weight gradient by a dense GEMM: dY X^T (FP32, library GEMM) in row panels
+// of sddmm_dense_panel_rows rows in ws (panel rows x k floats), the mask's
+// blocks gathered into G in CSR order.
+int64_t sddmm_dense_panel_rows(const spmm_plan_s* p);
+spmm_status_t sddmm_dense(const spmm_plan_s* p, int64_t n, const void* dY, int64_t lddy, const void* X, int64_t ldx,
+                          float* G, float* ws, hipStream_t s);
 
 // Autotuner table persisted as JSON (tune_cache.cpp). Key: (b, w, x, y,
 // density class, n class, dense copy kept: its candidates include the dense

@@ -899,6 +899,7 @@ spmm_status_t spmm_plan_destroy(spmm_plan_t p) {
   if (p->pieces_all) (void)hipFree(p->pieces_all);
   if (p->cut_rows) (void)hipFree(p->cut_rows);
   if (p->piece_part) (void)hipFree(p->piece_part);
+  if (p->sddmm_dense_ws) (void)hipFree(p->sddmm_dense_ws);
   if (p->sddmm_tasks) (void)hipFree(p->sddmm_tasks);
   if (p->ell_slot) (void)hipFree(p->ell_slot);
   if (p->dense_w) (void)hipFree(p->dense_w);
@@ -918,7 +919,7 @@ spmm_status_t spmm_plan_memory(spmm_plan_t p, int64_t* device_bytes, int64_t* va
   if (p->light_rows) idx += 4 * n1((int64_t)p->mb - p->num_heavy);
   if (p->heavy_rows) idx += 4 * n1(p->num_heavy);
   if (p->pieces) idx += 32 * (n1(p->num_pieces) + n1(p->num_pieces_all)) + 16 * n1(p->num_cut);
-  idx += p->piece_ws_bytes;
+  idx += p->piece_ws_bytes + p->sddmm_dense_ws_bytes;
   if (p->sddmm_tasks) idx += 8 * n1(p->sddmm_num_tasks);
   if (p->sddmm_tiled_tasks) idx += 16 * n1(p->sddmm_tiled_num) + 8 * n1(nnz);
   if (p->ell_slot) idx += 4 * n1(nnz);

@@ -34,6 +34,20 @@ __global__ void k_transpose_blocks(const int32_t* __restrict__ map, int64_t nnz,
 // (about 1.25 row slabs of 16 per b = 16 block, 3 per b = 32 block): it pays
 // from about 24 blocks of 16 (8 of 32) per task. SPMM_SDDMM_TILED=0/1 forces
 // the choice.
+// The dense GEMM for the weight gradient where the mask is dense enough that
+// a library GEMM of all of dY X^T and a gather beat the sampled products: the
+// sampled kernels reach about 7.5, 30, 57, 193 and 240 TFLOP/s at b = 1, 4,
+// 8, 16, 32 (m = k = 8192, n = 4096), the GEMM and gather about 1000 over the
+// whole product, so the crossover densities are near their ratios
+// (SPMM_SDDMM_DENSE=0/1 forces the choice).
+bool sddmm_dense_preferred(const spmm_plan_s* p) {
+  if (const char* e = getenv("SPMM_SDDMM_DENSE")) return e[0] == '1';
+  if (p->mb < 1 || p->kb < 1) return false;
+  const double d = (double)p->nnzb / ((double)p->mb * (double)p->kb);
+  const double th = p->b == 1 ? 1.0 / 128 : p->b == 4 ? 1.0 / 32 : p->b == 8 ? 1.0 / 16 : p->b == 16 ? 3.0 / 16 : 0.25;
+  return d >= th;
+}
+
 bool sddmm_tiled_preferred(const spmm_plan_s* p) {
   if (!p->sddmm_tiled_tasks || p->sddmm_tiled_num == 0) return false;
   if (const char* e = getenv("SPMM_SDDMM_TILED")) return e[0] == '1';
@@ -135,6 +149,29 @@ spmm_status_t spmm_sddmm(spmm_plan_t p, int64_t n, const void* dY, int64_t lddy,
   }
   if ((st = check_dense(dY, lddy, n, 2, "dY")) != SPMM_OK) return st;
   if ((st = check_dense(X, ldx, n, 2, "X")) != SPMM_OK) return st;
+  if (sddmm_dense_preferred(p) && n <= INT32_MAX && p->k <= INT32_MAX) {
+    spmm_plan_s* q = const_cast<spmm_plan_s*>(p);
+    const int64_t bytes = sddmm_dense_panel_rows(p) * p->k * 4;
+    bool ws = q->sddmm_dense_ws_bytes >= bytes;
+    if (!ws) {
+      hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+      if (hipStreamIsCapturing((hipStream_t)stream, &cs) == hipSuccess && cs == hipStreamCaptureStatusNone) {
+        if (q->sddmm_dense_ws) {
+          SPMM_HIP(hipDeviceSynchronize());
+          (void)hipFree(q->sddmm_dense_ws);
+          q->sddmm_dense_ws = nullptr;
+          q->sddmm_dense_ws_bytes = 0;
+        }
+        if (hipMalloc((void**)&q->sddmm_dense_ws, (size_t)bytes) == hipSuccess) {
+          q->sddmm_dense_ws_bytes = bytes;
+          ws = true;
+        } else {
+          q->sddmm_dense_ws = nullptr;
+        }
+      }
+    }
+    if (ws) return sddmm_dense(p, n, dY, lddy, X, ldx, G, q->sddmm_dense_ws, (hipStream_t)stream);
+  }
   if (sddmm_tiled_preferred(p))
     return launch_sddmm_tiled(p->x, p->b, p->sddmm_tiled_tasks, p->sddmm_tiled_ent, p->sddmm_tiled_num, p->m, p->k, n,
                               dY, lddy, X, ldx, G, (hipStream_t)stream);

@@ -13,6 +13,13 @@ from gpu_cases import TOL, Case, dev, round_like, stored_f64
 pytestmark = pytest.mark.gpu
 
 
+@pytest.fixture(autouse=True)
+def _sampled_weight_gradient(monkeypatch):
+    """The SDDMM tests below exercise the sampled kernels unless a test asks
+    for the dense-GEMM form itself (a test's own setenv overrides this)."""
+    monkeypatch.setenv("SPMM_SDDMM_DENSE", "0")
+
+
 def _dY(c, seed, integer=False, code=None):
     """dY (m x n) in the plan's x dtype: device tensor (ld = n rounded to 8) and exact float64 values."""
     code = code or c.x
@@ -354,3 +361,56 @@ def test_tiled_sddmm_at_full_size_sampled(monkeypatch):
     got = G[torch.from_numpy(pick).cuda()].cpu().numpy().astype(np.float64)
     ref = TR.sddmm_blockwise(c.m, c.k, 16, c.rows[pick], c.cols[pick], dY64, c.X64)
     assert O.rel_fro(got, ref) <= 1e-5
+
+
+
+# ---- the weight gradient by a dense GEMM of dY X^T and a gather of the mask's blocks
+
+@pytest.mark.parametrize("b", [1, 4, 8, 16, 32])
+@pytest.mark.parametrize("dt", ["f16", "bf16"])
+@pytest.mark.parametrize("n", [31, 300])
+def test_sddmm_dense_gemm_matches_oracle(b, dt, n, monkeypatch):
+    monkeypatch.setenv("SPMM_SDDMM_DENSE", "1")
+    c = Case(23 * b + 5, 31 * b + 11, n, b, 1 / 5, w=dt, seed=150 + b + n)
+    plan = _plan(c)
+    _, X, _ = c.device_inputs()
+    dY, dY64 = _dY(c, 160 + n)
+    G = _sddmm(c, plan, dY, X)
+    ref = TR.sddmm_blockwise(c.m, c.k, b, c.rows, c.cols, dY64, c.X64)
+    assert O.rel_fro(G, ref) <= 1e-5
+    for e, (r, cc) in enumerate(zip(c.rows, c.cols)):  # edge blocks: exactly zero outside m x k
+        rr, kk = c.m - r * b, c.k - cc * b
+        if rr < b:
+            assert not G[e, rr:, :].any()
+        if kk < b:
+            assert not G[e, :, kk:].any()
+
+
+def test_sddmm_dense_gemm_integer_data_bit_exact_over_several_panels(monkeypatch):
+    # k = 65536: a 128 MiB FP32 panel holds 512 rows, so m = 1300 takes three
+    # GEMMs and gathers; integer data is exact
+    monkeypatch.setenv("SPMM_SDDMM_DENSE", "1")
+    b = 16
+    c = Case(1300, 65536, 24, b, 1 / 64, w="f16", seed=171, integer=True)
+    plan = _plan(c)
+    _, X, _ = c.device_inputs()
+    dY, dY64 = _dY(c, 172, integer=True)
+    G = _sddmm(c, plan, dY, X)
+    ref = TR.sddmm_blockwise(c.m, c.k, b, c.rows, c.cols, dY64, c.X64)
+    assert np.array_equal(G, ref)
+
+
+@pytest.mark.parametrize("b,d,dense", [(16, 1 / 4, True), (16, 1 / 16, False), (4, 1 / 16, True), (32, 1 / 8, False)])
+def test_sddmm_rule_between_dense_gemm_and_sampled(b, d, dense, monkeypatch):
+    # the rule by density and block size: the dense form's panel workspace
+    # appears in the plan's memory only where it ran; both forms agree
+    monkeypatch.delenv("SPMM_SDDMM_DENSE", raising=False)
+    c = Case(64 * b, 48 * b, 200, b, d, w="f16", seed=180 + b)
+    plan = _plan(c)
+    _, X, _ = c.device_inputs()
+    dY, dY64 = _dY(c, 181)
+    before = plan.memory()[0]
+    G = _sddmm(c, plan, dY, X)
+    assert (plan.memory()[0] > before) == dense
+    ref = TR.sddmm_blockwise(c.m, c.k, b, c.rows, c.cols, dY64, c.X64)
+    assert O.rel_fro(G, ref) <= 1e-5
