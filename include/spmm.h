@@ -268,6 +268,8 @@ spmm_status_t spmm_plan_destroy(spmm_plan_t plan);
  * at most 128 MiB that the plan keeps from its first use) and a gather of the
  * mask's blocks, else kernels that compute only the mask's blocks;
  * SPMM_SDDMM_DENSE=0/1 forces the choice. The two sum in different orders.
+ * Calls of one plan share that panel: calls that overlap in time (different
+ * streams or threads) race and must be ordered by the caller.
  * Errors: INVALID_ARG (NULL, ld < n, alignment), UNSUPPORTED (block size
  * 64, dtypes), HIP. */
 spmm_status_t spmm_plan_transpose(spmm_plan_t plan, const spmm_plan_opts* opts, spmm_plan_t* out);
