@@ -394,7 +394,9 @@ def variant_kernel(variant, b):
     form = variant >> 8
     if b >= 16:
         return {2: "k_spmm_row_pp", 4: "k_spmm_row (every block row split)"}.get(form, "k_spmm_row")
-    return "k_spmm_small_lds" if form == 2 else "k_spmm_small"
+    if form == 2:
+        return "k_spmm_b1_lds" if b == 1 else "k_spmm_small_lds"
+    return "k_spmm_small"
 
 
 def mode_point(args):

@@ -1,6 +1,7 @@
-// Block-sparse x dense SpMM for b = 4 with X staged in LDS and shared
-// by a panel of block rows (PopSparse, Section 3: Y = (M o W) * X, FP32
-// accumulation; Section 3.2: the static partition of the known blocks).
+// Block-sparse x dense SpMM for b = 4 (and, further down, b = 1) with X
+// staged in LDS and shared by a panel of block rows (PopSparse, Section 3:
+// Y = (M o W) * X, FP32 accumulation; Section 3.2: the static partition of
+// the known blocks).
 //
 // At b = 4 every block reads b rows of X for only b FLOPs per byte, so a
 // kernel that reads X from L2 per block is bound by the L2 -> CU path. Here a
@@ -376,16 +377,387 @@ spmm_status_t small_lds_y(const RunArgs& a, const int32_t* rp, const int32_t* ci
   return small_lds_b<XT, YT, 4>(a, rp, ci, s, rw);
 }
 
+// ------------------------------------------------------------------ b = 1
+// Unstructured sparsity (b = 1) with X staged in LDS. The kernel without LDS
+// reads one X row from L2 per nonzero: 2 bytes per FMA, which binds it to
+// the L1 -> L2 path. Here a workgroup of NW waves owns a panel of RW x NW
+// rows and a tile of 512 columns, and walks k in chunks of KC rows: the
+// chunk (KC x 512 values) is loaded once, one k row per wave instruction,
+// and stored row-major in LDS (two buffers; two register sets of chunk loads
+// in flight, each chunk loaded three chunks ahead). Each wave owns RW rows and takes, per chunk, the nonzeros of
+// each row that fall in the chunk (a cursor per row: columns ascend, so
+// they are the next entries of the row). Lane L covers columns 8L .. 8L + 7
+// of the tile: per nonzero one 16-byte LDS read; the FMAs run on v_dot2
+// over two nonzeros of the row (their two X values interleaved with v_perm,
+// their two weights packed in one dword), FP32 accumulation. Rows go in
+// pairs, four slots of each at a time; slots past a row's nonzeros read an
+// LDS row of zeros with weight 0. Traffic from L2 per panel is the chunk
+// loads, 2 / (RW x NW x density) bytes per FMA.
+// V values (8 or 4) of 16 bits as dwords: one lane's share of an X row.
+template <int V>
+struct XSeg {
+  static_assert(V == 8 || V == 4, "8 or 4 columns per lane");
+  uint32_t d[V / 2];
+  __device__ __forceinline__ void load(__amdgpu_buffer_rsrc_t xr, uint32_t off) {
+    if constexpr (V == 8) {
+      const u32x4 v = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(xr, off, 0, 0));
+#pragma unroll
+      for (int i = 0; i < 4; ++i) d[i] = v[i];
+    } else {
+      const u32x2 v = __builtin_bit_cast(u32x2, __builtin_amdgcn_raw_buffer_load_b64(xr, off, 0, 0));
+      d[0] = v.x;
+      d[1] = v.y;
+    }
+  }
+  __device__ __forceinline__ void read(const uint16_t* a) {
+    if constexpr (V == 8) {
+      const u32x4 v = *(const u32x4*)a;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) d[i] = v[i];
+    } else {
+      const u32x2 v = *(const u32x2*)a;
+      d[0] = v.x;
+      d[1] = v.y;
+    }
+  }
+  __device__ __forceinline__ void write(uint16_t* a) const {
+    if constexpr (V == 8) *(u32x4*)a = u32x4{d[0], d[1], d[2], d[3]};
+    else *(u32x2*)a = u32x2{d[0], d[1]};
+  }
+};
+
+template <int KC, int NW, int V>
+struct Stage1 {
+  static constexpr int NT = 64 * V;      // columns per tile
+  static constexpr int kRows = KC / NW;  // k rows per wave
+  static_assert(kRows * NW == KC, "waves must tile the chunk");
+  XSeg<V> r[kRows];
+
+  __device__ __forceinline__ void load(__amdgpu_buffer_rsrc_t xr, const LParams& p, int32_t k0, int32_t n0, int wave,
+                                       int lane) {
+#pragma unroll
+    for (int s = 0; s < kRows; ++s) {
+      const int32_t krow = k0 + wave + s * NW;
+      const uint32_t off = krow < p.k ? (uint32_t)(((int64_t)krow * p.ldx + n0 + V * lane) * 2) : kOOB;
+      r[s].load(xr, off);
+    }
+  }
+
+  __device__ __forceinline__ void store(uint16_t* buf, int wave, int lane) const {
+#pragma unroll
+    for (int s = 0; s < kRows; ++s) r[s].write(buf + (wave + s * NW) * NT + V * lane);
+  }
+};
+
+// 64 entries of one row starting at CSR entry q, one per lane: column index
+// and 16-bit weight bits. Lanes past the row's end e load from an offset past
+// the buffer (zero, no memory access); they are masked out of the ballot by
+// valid_lanes(e - q) where the batch is used. Nothing is computed from the
+// loaded values here, so the loads stay in flight until their first use.
+struct Batch1 {
+  int32_t cv;
+  uint32_t wv;
+};
+
+template <bool GATHER>
+__device__ __forceinline__ Batch1 load_batch1(__amdgpu_buffer_rsrc_t cr, __amdgpu_buffer_rsrc_t wr,
+                                              __amdgpu_buffer_rsrc_t ir, int32_t q, int32_t e, int lane) {
+  const int32_t qb = q + lane;
+  const uint32_t off = qb < e ? (uint32_t)qb * 4u : kOOB;
+  Batch1 t;
+  t.cv = __builtin_amdgcn_raw_buffer_load_b32(cr, off, 0, 0);
+  if constexpr (GATHER) {
+    const uint32_t wq = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(ir, off, 0, 0);
+    t.wv = __builtin_amdgcn_raw_buffer_load_b16(wr, qb < e ? wq * 2u : kOOB, 0, 0);
+  } else {
+    t.wv = __builtin_amdgcn_raw_buffer_load_b16(wr, qb < e ? (uint32_t)qb * 2u : kOOB, 0, 0);
+  }
+  return t;
+}
+
+// Lanes 0 .. d - 1 of a batch hold entries of the row (d = entries left).
+__device__ __forceinline__ uint64_t valid_lanes(int32_t d) {
+  return d >= 64 ? ~0ull : (d <= 0 ? 0ull : (1ull << d) - 1ull);
+}
+
+template <typename XT> struct Dot2;
+template <> struct Dot2<_Float16> {
+  static __device__ __forceinline__ float f(uint32_t a, uint32_t b, float c) {
+    typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+    return __builtin_amdgcn_fdot2(__builtin_bit_cast(h2, a), __builtin_bit_cast(h2, b), c, false);
+  }
+};
+template <> struct Dot2<__bf16> {
+  static __device__ __forceinline__ float f(uint32_t a, uint32_t b, float c) {
+    typedef __bf16 b2 __attribute__((ext_vector_type(2)));
+    return __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(b2, a), __builtin_bit_cast(b2, b), c, false);
+  }
+};
+
+// A batch's entries as one dword per lane: weight bits << 16 | column - k0
+// (the column's row in the staged chunk) for the lanes in `live`; the other
+// lanes get weight 0 and row KC, an LDS row of zeros, so that any group of
+// slots can be processed without masks.
+template <int KC>
+__device__ __forceinline__ uint32_t pack_batch(const Batch1& bt, int32_t k0, uint64_t live, int lane) {
+  const bool on = (live >> lane) & 1ull;
+  return on ? (bt.wv << 16) | ((uint32_t)(bt.cv - k0) & 0xFFFFu) : (uint32_t)KC;
+}
+
+// Slots t .. t + 3 of a packed batch (slots past a row's entries read the
+// zero row with weight 0). `row` is this lane's part of LDS row 0 of the chunk.
+template <typename XT, int V>
+__device__ __forceinline__ void b1_group(float (&acc)[V], uint32_t pk, int32_t t, const uint16_t* row) {
+  uint32_t w[4];
+  XSeg<V> x[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const uint32_t e = (uint32_t)__builtin_amdgcn_readlane((int)pk, t + j);
+    w[j] = e >> 16;
+    x[j].read(row + (e & 0xFFFFu) * (64 * V));
+  }
+#pragma unroll
+  for (int pr = 0; pr < 2; ++pr) {
+    const uint32_t wp = w[2 * pr] | (w[2 * pr + 1] << 16);
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      const uint32_t sel = (v & 1) ? 0x07060302u : 0x05040100u;
+      const uint32_t xp = __builtin_amdgcn_perm(x[2 * pr + 1].d[v >> 1], x[2 * pr].d[v >> 1], sel);
+      acc[v] = Dot2<XT>::f(wp, xp, acc[v]);
+    }
+  }
+}
+
+template <typename XT, typename YT, int RW, int NW, int KC, int V, int MINB, bool GATHER>
+__global__ __launch_bounds__(NW * 64, MINB) void k_spmm_b1_lds(LParams p) {
+  constexpr int NT = 64 * V;
+  if (p.status && *p.status) return;
+  extern __shared__ uint16_t lds[];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = uniform(tid >> 6);
+  const int32_t unit = xcd_unit(blockIdx.x, p.num_units);
+  const int32_t panel = unit % p.num_panels, ntile = unit / p.num_panels;
+  const int32_t n0 = ntile * NT;
+  const int32_t nch = (p.k + KC - 1) / KC;
+  __amdgpu_buffer_rsrc_t xr = __builtin_amdgcn_make_buffer_rsrc((void*)p.X, (short)0, (int)p.x_bytes, 0x00020000);
+  __amdgpu_buffer_rsrc_t cr = __builtin_amdgcn_make_buffer_rsrc((void*)p.col_idx, (short)0, (int)p.c_bytes, 0x00020000);
+  __amdgpu_buffer_rsrc_t wr = __builtin_amdgcn_make_buffer_rsrc((void*)p.W, (short)0, (int)p.w_bytes, 0x00020000);
+  // the index map of dynamic calls, as large as the column indices
+  __amdgpu_buffer_rsrc_t ir =
+      __builtin_amdgcn_make_buffer_rsrc((void*)p.w_index, (short)0, GATHER ? (int)p.c_bytes : 0, 0x00020000);
+
+  const int32_t r0 = panel * (RW * NW) + wave * RW;
+  int32_t cur[RW], end[RW];
+#pragma unroll
+  for (int i = 0; i < RW; ++i) {
+    const int32_t r = min(r0 + i, p.mb);  // rows past mb: an empty range
+    cur[i] = uniform(p.row_ptr[r]);
+    end[i] = uniform(p.row_ptr[min(r + 1, p.mb)]);
+  }
+  float acc[RW][V];
+#pragma unroll
+  for (int i = 0; i < RW; ++i)
+#pragma unroll
+    for (int v = 0; v < V; ++v) acc[i][v] = 0.f;
+
+  // A row holds at most one entry per column, so with KC <= 64 one batch of
+  // 64 lanes holds all of a row's entries in a chunk. Dynamic calls may hold
+  // duplicates (summed): there a row can run past its batch, and the code
+  // for that (DUP) reloads it.
+  static_assert(KC <= 64, "a chunk's entries of a row fit one batch");
+  static_assert(RW % 2 == 0, "rows are multiplied in pairs");
+  constexpr bool DUP = GATHER;
+  constexpr int BUF = (KC + 1) * NT;  // halves per LDS buffer: KC rows of X and a row of zeros
+  Batch1 bt[RW];   // each row's entries from position bq (loaded one chunk ahead)
+  int32_t bq[RW];
+  // Two register sets of X in flight: chunk c is loaded during chunk c - 3
+  // (or the prologue), stored into LDS at the start of chunk c - 1 and used in
+  // chunk c. Loads past the last chunk read zeros (offsets past the buffer),
+  // so every load and store is unconditional and each wait is a count of
+  // loads issued later (loads complete in issue order).
+  Stage1<KC, NW, V> sa, sb;
+  sb.load(xr, p, 0, n0, wave, lane);
+#pragma unroll
+  for (int i = 0; i < RW; ++i) {
+    bt[i] = load_batch1<GATHER>(cr, wr, ir, cur[i], end[i], lane);
+    bq[i] = cur[i];
+  }
+  if (wave == 0) {
+    XSeg<V> z;
+#pragma unroll
+    for (int i = 0; i < V / 2; ++i) z.d[i] = 0u;
+    z.write(lds + KC * NT + V * lane);
+    z.write(lds + BUF + KC * NT + V * lane);
+  }
+  sb.store(lds, wave, lane);
+  sa.load(xr, p, KC, n0, wave, lane);
+  sb.load(xr, p, 2 * KC, n0, wave, lane);
+  sync_lds();  // chunk 0 staged; chunks 1 and 2 in flight
+
+  // One chunk: (1) store chunk ch + 1 from `nxt` into the other LDS buffer,
+  // count each row's entries inside chunk ch and pack its batch; (2) load
+  // chunk ch + 3 into `nxt` and the next chunk's batches; (3) multiply from
+  // LDS, two rows at a time (their LDS reads in flight together); a barrier.
+  auto chunk = [&](int32_t ch, Stage1<KC, NW, V>& nxt) {
+    const int32_t k0 = ch * KC, kend = k0 + KC;
+    nxt.store(lds + ((ch + 1) & 1) * BUF, wave, lane);
+    uint32_t pk[RW];
+    int32_t cnt[RW];
+#pragma unroll
+    for (int i = 0; i < RW; ++i) {
+      if constexpr (DUP) {
+        if (bq[i] != cur[i]) {  // the row ran past its batch in the previous chunk
+          bt[i] = load_batch1<GATHER>(cr, wr, ir, cur[i], end[i], lane);
+          bq[i] = cur[i];
+        }
+      }
+      // entries of the batch inside the chunk (columns ascend: a prefix)
+      const uint64_t live = __ballot(bt[i].cv < kend) & valid_lanes(end[i] - cur[i]);
+      cnt[i] = __popcll(live);
+      pk[i] = pack_batch<KC>(bt[i], k0, live, lane);
+    }
+#pragma unroll
+    for (int i = 0; i < RW; ++i) {
+      bq[i] = cur[i] + cnt[i];
+      bt[i] = load_batch1<GATHER>(cr, wr, ir, bq[i], end[i], lane);
+    }
+    nxt.load(xr, p, k0 + 3 * KC, n0, wave, lane);
+    const uint16_t* row = lds + (ch & 1) * BUF + V * lane;
+#pragma unroll
+    for (int i = 0; i < RW; i += 2) {
+      const int32_t nt = max(cnt[i], cnt[i + 1]);
+      for (int32_t t = 0; t < nt; t += 4) {
+        b1_group<XT, V>(acc[i], pk[i], t, row);
+        b1_group<XT, V>(acc[i + 1], pk[i + 1], t, row);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < RW; ++i) {
+      int32_t q = cur[i] + cnt[i];
+      if constexpr (DUP) {
+        if (cnt[i] == 64 && q < end[i]) {
+          for (;;) {
+            const Batch1 x = load_batch1<GATHER>(cr, wr, ir, q, end[i], lane);
+            const uint64_t live = __ballot(x.cv < kend) & valid_lanes(end[i] - q);
+            const int32_t c = __popcll(live);
+            if (c == 0) break;
+            const uint32_t xp = pack_batch<KC>(x, k0, live, lane);
+            for (int32_t t = 0; t < c; t += 4) b1_group<XT, V>(acc[i], xp, t, row);
+            q += c;
+            if (c < 64 || q >= end[i]) break;
+          }
+        }
+      }
+      cur[i] = q;
+    }
+    sync_lds();  // chunk ch consumed; chunk ch + 1 staged
+  };
+  for (int32_t ch = 0; ch < nch; ch += 2) {
+    chunk(ch, sa);                        // chunk 1 (then 3, ...) waits in set a
+    if (ch + 1 < nch) chunk(ch + 1, sb);  // chunk 2 (then 4, ...) in set b
+  }
+
+  // lane holds columns n0 + V lane .. + V - 1 of rows r0 .. r0 + RW - 1
+  const int32_t col0 = n0 + V * lane;
+  if (col0 >= p.n) return;
+  YT* __restrict__ Y = (YT*)p.Y;
+#pragma unroll
+  for (int i = 0; i < RW; ++i) {
+    const int32_t r = r0 + i;
+    if (r >= p.m) break;
+    float v[V];
+#pragma unroll
+    for (int e = 0; e < V; ++e) v[e] = p.relu ? (acc[i][e] > 0.f ? acc[i][e] : 0.f) : acc[i][e];
+    YT* dst = Y + (int64_t)r * p.ldy + col0;
+    if (col0 + V <= p.n) {
+      if constexpr (sizeof(YT) == 4) {
+#pragma unroll
+        for (int e = 0; e < V; e += 4) *(float4_t*)(dst + e) = float4_t{v[e], v[e + 1], v[e + 2], v[e + 3]};
+      } else {
+        XSeg<V> o;
+#pragma unroll
+        for (int e = 0; e < V / 2; ++e)
+          o.d[e] = (uint32_t)__builtin_bit_cast(uint16_t, to_out<YT>(v[2 * e])) |
+                   ((uint32_t)__builtin_bit_cast(uint16_t, to_out<YT>(v[2 * e + 1])) << 16);
+        o.write((uint16_t*)dst);
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < V; ++e)
+        if (col0 + e < p.n) dst[e] = to_out<YT>(v[e]);
+    }
+  }
+}
+
+template <typename XT, typename YT, int RW, int NW, int KC, int V, bool GATHER>
+spmm_status_t launch_b1(const RunArgs& a, const int32_t* row_ptr, const int32_t* col_idx, hipStream_t s) {
+  LParams p;
+  p.row_ptr = row_ptr;
+  p.col_idx = col_idx;
+  p.W = a.W;
+  p.w_index = a.w_index;
+  p.X = a.X;
+  p.Y = a.Y;
+  p.ldx = a.ldx;
+  p.ldy = a.ldy;
+  p.m = a.plan.m;
+  p.k = a.plan.k;
+  p.n = a.n;
+  p.mb = a.plan.mb;
+  p.relu = a.relu ? 1 : 0;
+  p.status = a.status;
+  const int64_t xb = (int64_t)a.plan.k * a.ldx * 2;
+  if (xb >= (int64_t)INT32_MAX) return fail(SPMM_ERR_UNSUPPORTED, "X larger than 2 GiB is not supported");
+  p.x_bytes = (uint32_t)xb;
+  const int64_t cb = a.nnz * 4, wb = a.nnz * 2;
+  if (cb >= (int64_t)INT32_MAX) return fail(SPMM_ERR_UNSUPPORTED, "more than 2 GiB of indices is not supported");
+  p.c_bytes = (uint32_t)std::max<int64_t>(cb, 4);
+  p.w_bytes = (uint32_t)std::max<int64_t>(wb, 4);
+  const int64_t panels = ceil_div(a.plan.mb, (int64_t)RW * NW);
+  const int64_t units = panels * ceil_div(a.n, 64 * V);
+  if (units == 0) return SPMM_OK;
+  if (units > (int64_t)INT32_MAX) return fail(SPMM_ERR_UNSUPPORTED, "too many work units");
+  p.num_panels = (int32_t)panels;
+  p.num_units = (int32_t)units;
+  constexpr size_t lds = 2 * (size_t)(KC + 1) * 64 * V * sizeof(uint16_t);
+  constexpr int MINB = lds <= 80 * 1024 ? 2 : 1;  // workgroups per CU the LDS allows
+  static const hipError_t attr = hipFuncSetAttribute((const void*)k_spmm_b1_lds<XT, YT, RW, NW, KC, V, MINB, GATHER>,
+                                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (attr != hipSuccess) return fail_hip(attr, "LDS limit of the b = 1 kernel");
+  hipLaunchKernelGGL((k_spmm_b1_lds<XT, YT, RW, NW, KC, V, MINB, GATHER>), dim3((unsigned)units), dim3(NW * 64), lds, s,
+                     p);
+  SPMM_HIP(hipGetLastError());
+  return SPMM_OK;
+}
+
+template <typename XT, typename YT, int KC, int V>
+spmm_status_t b1_lds_cfg(const RunArgs& a, const int32_t* rp, const int32_t* ci, hipStream_t s, int rw) {
+  if (a.w_index) {
+    if (rw >= 8) return launch_b1<XT, YT, 8, kNW, KC, V, true>(a, rp, ci, s);
+    return launch_b1<XT, YT, 4, kNW, KC, V, true>(a, rp, ci, s);
+  }
+  if (rw >= 8) return launch_b1<XT, YT, 8, kNW, KC, V, false>(a, rp, ci, s);
+  return launch_b1<XT, YT, 4, kNW, KC, V, false>(a, rp, ci, s);
+}
+
+template <typename XT, typename YT>
+spmm_status_t b1_lds_y(const RunArgs& a, const int32_t* rp, const int32_t* ci, hipStream_t s, int rw) {
+  return b1_lds_cfg<XT, YT, 64, 8>(a, rp, ci, s, rw);
+}
+
 }  // namespace
 
-// Measured on MI355X at m = k = 8192 (FP16): the LDS kernel is faster at
-// b = 4 from density 1/8 up (n = 4096: 85 against 74 TFLOP/s at 1/8, 95
-// against 77 at 1/4) and slower below, where a panel's blocks are too few to
-// pay for staging every chunk of X and the per-row, per-chunk work; at b = 8
-// the kernel without LDS was faster at every density. SPMM_SMALL_LDS=0 / 1
-// forces the choice (for comparisons and tests).
+// Measured on MI355X at m = k = 8192, n = 4096 (FP16): the LDS kernels are
+// faster from density 1/8 up and slower below, where a panel's nonzeros are
+// too few to pay for staging every chunk of X and the per-row, per-chunk
+// work. b = 4: 85 against 74 TFLOP/s at 1/8, 95 against 77 at 1/4. b = 1:
+// 3.27 against 3.59 ms at 1/8 and 5.2 against 6.3 ms at 1/4, but 2.30
+// against 2.08 ms at 1/16 (with few nonzeros per chunk its chunks are bound
+// by the latency of the chunk loads, about 3 us each). At b = 8 the kernel
+// without LDS was faster at every density. SPMM_SMALL_LDS=0 / 1 forces the
+// choice (for comparisons and tests).
 bool small_lds_eligible(int32_t b, spmm_dtype_t w, spmm_dtype_t x) {
-  return b == 4 && w == x && (x == SPMM_F16 || x == SPMM_BF16);
+  return (b == 1 || b == 4) && w == x && (x == SPMM_F16 || x == SPMM_BF16);
 }
 
 bool small_lds_preferred(int32_t b, spmm_dtype_t w, spmm_dtype_t x, int64_t nnz, int64_t mb, int64_t kb) {
@@ -403,6 +775,7 @@ int32_t small_lds_rows_per_wave(int32_t b, int32_t mb, int64_t n, int num_cus) {
     const int v = atoi(e);
     if (v == r0 || v == r0 / 2 || v == r0 / 4) return v;
   }
+  if (b == 1) return ceil_div(mb, (int64_t)r0 * kNW) * ceil_div(n, 512) >= (int64_t)num_cus ? r0 : r0 / 2;
   const int64_t tiles = ceil_div(n, kNT);
   for (int32_t rw = r0; rw > r0 / 4; rw /= 2)
     if (ceil_div(mb, (int64_t)rw * kNW) * tiles >= 2 * (int64_t)num_cus) return rw;
@@ -411,9 +784,17 @@ int32_t small_lds_rows_per_wave(int32_t b, int32_t mb, int64_t n, int num_cus) {
 
 spmm_status_t launch_spmm_small_lds(const RunArgs& a, const int32_t* row_ptr, const int32_t* col_idx, int32_t rw,
                                     hipStream_t s) {
-  if (a.plan.b != 4) return fail(SPMM_ERR_UNSUPPORTED, "LDS small-block kernel: b = 4");
+  if (a.plan.b != 1 && a.plan.b != 4) return fail(SPMM_ERR_UNSUPPORTED, "LDS small-block kernel: b = 1 or 4");
   if (a.wt != a.xt || (a.xt != SPMM_F16 && a.xt != SPMM_BF16))
     return fail(SPMM_ERR_UNSUPPORTED, "LDS small-block kernel: 16-bit W and X of one type");
+  if (a.plan.b == 1) {
+    if (a.xt == SPMM_F16) {
+      if (a.yt == SPMM_F32) return b1_lds_y<_Float16, float>(a, row_ptr, col_idx, s, rw);
+      return b1_lds_y<_Float16, _Float16>(a, row_ptr, col_idx, s, rw);
+    }
+    if (a.yt == SPMM_F32) return b1_lds_y<__bf16, float>(a, row_ptr, col_idx, s, rw);
+    return b1_lds_y<__bf16, __bf16>(a, row_ptr, col_idx, s, rw);
+  }
   if (a.xt == SPMM_F16) {
     if (a.yt == SPMM_F32) return small_lds_y<_Float16, float>(a, row_ptr, col_idx, s, rw);
     return small_lds_y<_Float16, _Float16>(a, row_ptr, col_idx, s, rw);

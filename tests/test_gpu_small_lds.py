@@ -1,7 +1,8 @@
-"""The LDS-staged b = 4 kernel (panels of block rows share each chunk of
-X in LDS; 4 x 4 x 4 matrix-core products) against the FP64 oracle: ragged
-shapes across several chunks and panels, every 16-bit dtype pair, integer data
-bit-exact, its row-per-wave variants bitwise equal to each other, empty rows,
+"""The LDS-staged kernels, b = 4 (panels of block rows share each chunk of
+X in LDS; 4 x 4 x 4 matrix-core products) and b = 1 (panels of 64 rows, 512
+columns per tile, dot products over pairs of nonzeros), against the FP64
+oracle: ragged shapes across several chunks, panels and column tiles, every
+16-bit dtype pair, integer data bit-exact, its row-per-wave variants bitwise equal to each other, empty rows,
 dynamic calls equal to static plans bit for bit, and the kernel without LDS
 within the rounding bound."""
 import numpy as np
@@ -31,10 +32,9 @@ def _run(c, monkeypatch, rw=None, lds=True):
 
 
 @pytest.mark.parametrize("w,y", [("f16", "f16"), ("bf16", "bf16"), ("f16", "f32"), ("bf16", "f32")])
-@pytest.mark.parametrize("b", [4])
-@pytest.mark.parametrize("n", [1, 37, 100])
+@pytest.mark.parametrize("b,n", [(4, 1), (4, 37), (4, 100), (1, 1), (1, 37), (1, 100), (1, 600)])
 def test_lds_ragged_shapes_match_oracle(w, y, b, n, monkeypatch):
-    # k spans three chunks of 512 rows with a ragged tail; m leaves a partial panel
+    # k spans several chunks with a ragged tail; m leaves a partial panel
     c = Case(b * 301 + 3, 1500 + b // 2, n, b, 0.1, w=w, y=y, seed=400 + b + n)
     Y = _run(c, monkeypatch)
     got, ref = y_f64(Y, c), c.oracle()
@@ -43,7 +43,7 @@ def test_lds_ragged_shapes_match_oracle(w, y, b, n, monkeypatch):
     assert torch.isnan(Y[:, c.n:].float()).all().item()  # columns past n untouched
 
 
-@pytest.mark.parametrize("b", [4])
+@pytest.mark.parametrize("b", [1, 4])
 def test_lds_integer_exact_and_row_variants_bitwise(b, monkeypatch):
     c = Case(b * 520, 2100, 130, b, 0.15, w="f16", seed=430 + b, integer=True)
     ref = round_like(c.oracle(), "f16")
@@ -56,7 +56,7 @@ def test_lds_integer_exact_and_row_variants_bitwise(b, monkeypatch):
         assert torch.equal(Y[:, : c.n], outs[0][:, : c.n])
 
 
-@pytest.mark.parametrize("b", [4])
+@pytest.mark.parametrize("b", [1, 4])
 def test_lds_empty_rows_density_zero_and_long_rows(b, monkeypatch):
     c = Case(b * 200, b * 700, 64, b, 0.3, w="bf16", seed=440 + b)
     mask = c.mask.copy()
@@ -70,7 +70,7 @@ def test_lds_empty_rows_density_zero_and_long_rows(b, monkeypatch):
     assert torch.all(_run(z, monkeypatch)[:, : z.n] == 0).item()
 
 
-@pytest.mark.parametrize("b", [4])
+@pytest.mark.parametrize("b", [1, 4])
 def test_lds_against_kernel_without_lds(b, monkeypatch):
     c = Case(b * 260 + 1, b * 300 + 2, 260, b, 1 / 8, w="f16", y="f32", seed=450 + b)
     Yl = _run(c, monkeypatch, lds=True)
@@ -80,7 +80,7 @@ def test_lds_against_kernel_without_lds(b, monkeypatch):
     assert O.rel_fro(a, v) <= 1e-6
 
 
-@pytest.mark.parametrize("b", [4])
+@pytest.mark.parametrize("b", [1, 4])
 def test_lds_dynamic_equals_static(b, monkeypatch):
     monkeypatch.delenv("SPMM_LDS_RW", raising=False)
     c = Case(b * 180, b * 200, 96, b, 1 / 10, w="f16", seed=460 + b)
@@ -102,14 +102,15 @@ def test_lds_dynamic_equals_static(b, monkeypatch):
     assert torch.equal(Ys[:, : c.n], Yd[:, : c.n])
 
 
-def test_lds_chosen_by_density(monkeypatch):
-    """Without the override (and without tuning) the LDS kernel runs from
-    density 1/8 up; both choices agree with the oracle (the dispatch is checked
-    through results equal to the forced kernel's, bit for bit)."""
+@pytest.mark.parametrize("b,dens", [(4, ((1 / 4, "1"), (1 / 16, "0"))), (1, ((1 / 8, "1"), (1 / 16, "0")))])
+def test_lds_chosen_by_density(b, dens, monkeypatch):
+    """Without the override (and without tuning) the LDS kernels run from
+    density 1/8 up; both choices agree with the oracle (the dispatch is checked through results equal to the forced
+    kernel's, bit for bit)."""
     monkeypatch.delenv("SPMM_LDS_RW", raising=False)
     monkeypatch.setenv("SPMM_AUTOTUNE", "0")  # the rule, not a measurement
-    for d, lds in ((1 / 4, "1"), (1 / 16, "0")):
-        c = Case(4 * 300, 4 * 320, 96, 4, d, w="f16", seed=470)
+    for d, lds in dens:
+        c = Case(b * 300, b * 320 if b == 4 else 1280, 96, b, d, w="f16", seed=470)
         monkeypatch.delenv("SPMM_SMALL_LDS", raising=False)
         plan = spmm.StaticPlan(c.m, c.k, c.b, c.mask, c.w, c.x, c.y)
         vals, X, _ = c.device_inputs()
