@@ -652,9 +652,11 @@ __global__ __launch_bounds__(NW * 64, MINB) void k_spmm_b1_lds(LParams p) {
     }
     sync_lds();  // chunk ch consumed; chunk ch + 1 staged
   };
+  // an even number of chunks (the one past k, if any, has no entries), so
+  // that both halves of the loop body always run
   for (int32_t ch = 0; ch < nch; ch += 2) {
-    chunk(ch, sa);                        // chunk 1 (then 3, ...) waits in set a
-    if (ch + 1 < nch) chunk(ch + 1, sb);  // chunk 2 (then 4, ...) in set b
+    chunk(ch, sa);      // chunk 1 (then 3, ...) waits in set a
+    chunk(ch + 1, sb);  // chunk 2 (then 4, ...) in set b
   }
 
   // lane holds columns n0 + V lane .. + V - 1 of rows r0 .. r0 + RW - 1
@@ -752,8 +754,9 @@ spmm_status_t b1_lds_y(const RunArgs& a, const int32_t* rp, const int32_t* ci, h
 // too few to pay for staging every chunk of X and the per-row, per-chunk
 // work. b = 4: 85 against 74 TFLOP/s at 1/8, 95 against 77 at 1/4. b = 1:
 // 3.27 against 3.59 ms at 1/8 and 5.2 against 6.3 ms at 1/4, but 2.30
-// against 2.08 ms at 1/16 (with few nonzeros per chunk its chunks are bound
-// by the latency of the chunk loads, about 3 us each). At b = 8 the kernel
+// against 2.08 ms at 1/16 (with few nonzeros per chunk, the chunk's fixed
+// work and the slots past each row's nonzeros dominate: about 3 us per chunk
+// at 1/32, whether X is loaded one or two chunks ahead). At b = 8 the kernel
 // without LDS was faster at every density. SPMM_SMALL_LDS=0 / 1 forces the
 // choice (for comparisons and tests).
 bool small_lds_eligible(int32_t b, spmm_dtype_t w, spmm_dtype_t x) {
