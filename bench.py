@@ -391,6 +391,8 @@ def crossover_density(pts):
 
 def variant_kernel(variant, b):
     """The kernel a static run of a row-kernel plan launches for a variant code."""
+    if variant == 0:
+        return "the rule's choice"
     form = variant >> 8
     if b >= 16:
         return {2: "k_spmm_row_pp", 4: "k_spmm_row (every block row split)"}.get(form, "k_spmm_row")

@@ -120,3 +120,51 @@ def test_lds_chosen_by_density(b, dens, monkeypatch):
         torch.cuda.synchronize()
         assert torch.equal(Y[:, : c.n], _run(c, monkeypatch, lds=lds == "1")[:, : c.n]), d
         assert O.rel_fro(y_f64(Y, c), c.oracle()) <= TOL["f16"]
+
+
+@pytest.mark.parametrize("w", ["f16", "bf16"])
+def test_b1_lds_dynamic_duplicates_past_one_batch(w, monkeypatch):
+    """Dynamic calls may repeat an entry (summed), so a row can hold more than
+    64 entries inside one chunk of 64 columns: the b = 1 LDS kernel then takes
+    further batches within the chunk and reloads the row's batch at the next
+    chunk. Integer data: exact against the FP64 oracle and equal to the kernel
+    without LDS."""
+    monkeypatch.delenv("SPMM_LDS_RW", raising=False)
+    m, k, n, ldn = 150, 300, 600, 608  # 5 chunks (ragged tail), 2 column tiles (ragged)
+    g = np.random.default_rng(7)
+    base = np.argwhere(g.random((m, k)) < 1 / 8)
+    rows = [base[:, 0]]
+    cols = [base[:, 1]]
+    rows += [np.full(150, 7), np.full(9, 7)]              # row 7: 150 entries in chunk 0, 9 in chunk 2
+    cols += [g.integers(0, 64, 150), g.integers(128, 192, 9)]
+    rows += [np.full(70, 70)]                             # row 70: 70 entries in chunk 1
+    cols += [g.integers(64, 128, 70)]
+    rows = np.concatenate(rows).astype(np.int32)
+    cols = np.concatenate(cols).astype(np.int32)
+    perm = g.permutation(len(rows))
+    rows, cols = rows[perm], cols[perm]
+    nnz_n = len(rows)
+    vals = synth.to_storage(g.integers(-3, 4, (nnz_n, 1, 1)).astype(np.float64), w)
+    X = synth.to_storage(g.integers(-3, 4, (k, n)).astype(np.float64), w)
+    ref = O.spmm_expand(m, k, 1, rows, cols, synth.storage_to_f64(vals, w), synth.storage_to_f64(X, w))
+    max_nnz = nnz_n + 5
+    pad = max_nnz - nnz_n
+    r = dev(np.concatenate([rows, np.zeros(pad, np.int32)]).astype(np.int32))
+    c = dev(np.concatenate([cols, np.zeros(pad, np.int32)]).astype(np.int32))
+    v = dev(np.concatenate([vals, np.zeros((pad, 1, 1), vals.dtype)]))
+    nnz = torch.tensor([nnz_n], dtype=torch.int32, device="cuda")
+    tdt = torch.float16 if w == "f16" else torch.bfloat16
+    Xd = torch.zeros((k, ldn), dtype=tdt, device="cuda")
+    Xd[:, :n] = dev(X)
+    outs = []
+    for lds in ("1", "0"):
+        monkeypatch.setenv("SPMM_SMALL_LDS", lds)
+        h = spmm.DynamicHandle(m, k, 1, max_nnz, w, y="f32")
+        Y = torch.full((m, ldn), float("nan"), dtype=torch.float32, device="cuda")
+        st = torch.full((1,), -1, dtype=torch.int32, device="cuda")
+        h.run(nnz, r, c, v, Xd, Y, st, n=n)
+        torch.cuda.synchronize()
+        assert st.item() == 0
+        assert np.array_equal(Y[:, :n].cpu().numpy().astype(np.float64), ref), lds
+        outs.append(Y)
+    assert torch.equal(outs[0][:, :n], outs[1][:, :n])
