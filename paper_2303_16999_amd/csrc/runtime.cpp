@@ -295,7 +295,7 @@ spmm_status_t run_plan(const spmm_plan_s* p, int64_t n, const void* X, int64_t l
   if (p->dense_w && !relu && (form == 3 || (form == 0 && p->predicted_speedup < 1.0)))
     return run_dense(p, n, X, ldx, Y, ldy, stream);
   if (p->b < 16) {
-    bool lds = small_lds_preferred(p->b, p->w, p->x, p->nnzb, p->mb, p->kb);
+    bool lds = small_lds_preferred(p->b, p->w, p->x, p->nnzb, p->mb, p->kb, n);
     if (form && small_lds_eligible(p->b, p->w, p->x) && !getenv("SPMM_SMALL_LDS")) lds = form == 2;
     if (lds)
       return launch_spmm_small_lds(a, p->pb.row_ptr, p->pb.col_idx,
@@ -338,7 +338,7 @@ spmm_status_t run_dynamic_kernel(RunArgs& a, const int32_t* row_ptr, const int32
   const int32_t form = variant_form(variant);
   const int cus = device_cu_count();
   if (b < 16) {
-    bool lds = small_lds_preferred(b, a.wt, a.xt, a.nnz, a.plan.mb, a.plan.kb);
+    bool lds = small_lds_preferred(b, a.wt, a.xt, a.nnz, a.plan.mb, a.plan.kb, a.n);
     if (form && small_lds_eligible(b, a.wt, a.xt) && !getenv("SPMM_SMALL_LDS")) lds = form == 2;
     if (lds) return launch_spmm_small_lds(a, row_ptr, col_idx, small_lds_rows_per_wave(b, a.plan.mb, a.n, cus), s);
     a.ns = variant_ns(variant);

@@ -749,25 +749,33 @@ spmm_status_t b1_lds_y(const RunArgs& a, const int32_t* rp, const int32_t* ci, h
 
 }  // namespace
 
-// Measured on MI355X at m = k = 8192, n = 4096 (FP16): the LDS kernels are
-// faster from density 1/8 up and slower below, where a panel's nonzeros are
-// too few to pay for staging every chunk of X and the per-row, per-chunk
-// work. b = 4: 85 against 74 TFLOP/s at 1/8, 95 against 77 at 1/4. b = 1:
-// 3.27 against 3.59 ms at 1/8 and 5.2 against 6.3 ms at 1/4, but 2.30
-// against 2.08 ms at 1/16 (with few nonzeros per chunk, the chunk's fixed
-// work and the slots past each row's nonzeros dominate: about 3 us per chunk
-// at 1/32, whether X is loaded one or two chunks ahead). At b = 8 the kernel
+// Measured on MI355X at m = k = 8192 (FP16). b = 4, n = 4096: the LDS kernel
+// is faster from density 1/8 up (85 against 74 TFLOP/s at 1/8, 95 against
+// 77 at 1/4) and slower below, where a panel's blocks are too few to pay for
+// staging every chunk of X and the per-row, per-chunk work. b = 1: the
+// crossover falls with n, because without LDS every nonzero reads its X row
+// from L2, and at large n X no longer stays there. LDS against no LDS: n =
+// 16384, 9.3 against 13.2 ms at 1/16 (at 1/32, 7.1 against 6.7 ms: slower);
+// n = 4096 and 8192, 3.27 against 3.59 and 6.58 against 7.64 ms at 1/8
+// (losing at 1/16); n = 1024 and 2048, 1.32 against 1.39 and 2.60 against
+// 2.99 ms at 1/4 (losing at 1/8); at n <= 512, where most lanes of its
+// 512-column tiles idle, it loses at every density. At b = 8 the kernel
 // without LDS was faster at every density. SPMM_SMALL_LDS=0 / 1 forces the
 // choice (for comparisons and tests).
 bool small_lds_eligible(int32_t b, spmm_dtype_t w, spmm_dtype_t x) {
   return (b == 1 || b == 4) && w == x && (x == SPMM_F16 || x == SPMM_BF16);
 }
 
-bool small_lds_preferred(int32_t b, spmm_dtype_t w, spmm_dtype_t x, int64_t nnz, int64_t mb, int64_t kb) {
+bool small_lds_preferred(int32_t b, spmm_dtype_t w, spmm_dtype_t x, int64_t nnz, int64_t mb, int64_t kb, int64_t n) {
   if (!small_lds_eligible(b, w, x)) return false;
   if (const char* e = getenv("SPMM_SMALL_LDS")) {
     if (e[0] == '0') return false;
     if (e[0] == '1') return true;
+  }
+  if (b == 1) {
+    // the density the kernel needs falls by half at n = 4096 and at n = 16384
+    const int64_t inv = n >= 16384 ? 16 : n >= 4096 ? 8 : n >= 1024 ? 4 : 0;
+    return inv > 0 && nnz * inv >= mb * kb;
   }
   return nnz * 8 >= mb * kb;
 }

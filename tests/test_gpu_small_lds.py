@@ -102,15 +102,19 @@ def test_lds_dynamic_equals_static(b, monkeypatch):
     assert torch.equal(Ys[:, : c.n], Yd[:, : c.n])
 
 
-@pytest.mark.parametrize("b,dens", [(4, ((1 / 4, "1"), (1 / 16, "0"))), (1, ((1 / 8, "1"), (1 / 16, "0")))])
-def test_lds_chosen_by_density(b, dens, monkeypatch):
+@pytest.mark.parametrize("b,n,dens", [(4, 96, ((1 / 4, "1"), (1 / 16, "0"))),
+                                      (1, 1024, ((1 / 4, "1"), (1 / 8, "0"))),
+                                      (1, 256, ((1 / 4, "0"),))])
+def test_lds_chosen_by_density(b, n, dens, monkeypatch):
     """Without the override (and without tuning) the LDS kernels run from
-    density 1/8 up; both choices agree with the oracle (the dispatch is checked through results equal to the forced
-    kernel's, bit for bit)."""
+    density 1/8 up at b = 4; at b = 1 from 1/4 up at n = 1024 (1/8 from n =
+    4096, 1/16 from n = 16384) and never at n below 1024. Both choices agree
+    with the oracle (the dispatch is checked through results equal to the
+    forced kernel's, bit for bit)."""
     monkeypatch.delenv("SPMM_LDS_RW", raising=False)
     monkeypatch.setenv("SPMM_AUTOTUNE", "0")  # the rule, not a measurement
     for d, lds in dens:
-        c = Case(b * 300, b * 320 if b == 4 else 1280, 96, b, d, w="f16", seed=470)
+        c = Case(b * 300, b * 320 if b == 4 else 1280, n, b, d, w="f16", seed=470)
         monkeypatch.delenv("SPMM_SMALL_LDS", raising=False)
         plan = spmm.StaticPlan(c.m, c.k, c.b, c.mask, c.w, c.x, c.y)
         vals, X, _ = c.device_inputs()
