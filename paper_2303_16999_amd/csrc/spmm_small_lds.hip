@@ -749,12 +749,16 @@ spmm_status_t b1_lds_y(const RunArgs& a, const int32_t* rp, const int32_t* ci, h
 
 }  // namespace
 
-// Measured on MI355X at m = k = 8192 (FP16). b = 4, n = 4096: the LDS kernel
-// is faster from density 1/8 up (85 against 74 TFLOP/s at 1/8, 95 against
-// 77 at 1/4) and slower below, where a panel's blocks are too few to pay for
-// staging every chunk of X and the per-row, per-chunk work. b = 1: the
-// crossover falls with n, because without LDS every nonzero reads its X row
-// from L2, and at large n X no longer stays there. LDS against no LDS: n =
+// Measured on MI355X at m = k = 8192 (FP16). For both block sizes the
+// crossover falls with n: without LDS every block reads its X rows from L2,
+// and at large n X no longer stays there. Below the crossover a panel's
+// nonzeros are too few to pay for staging every chunk of X and the per-row,
+// per-chunk work. b = 4, LDS against no LDS: n = 16384, 3.25 against 6.35
+// ms at 1/8 and 2.46 against 3.33 ms at 1/16 (at 1/32, 2.08 against 1.74
+// ms: slower); n = 4096, 85 against 74 TFLOP/s at 1/8, 95 against 77 at 1/4,
+// slower at 1/16 (and at n = 8192, 1.29 against 1.25 ms); n = 1024, 0.239
+// against 0.259 ms at 1/8; n = 256, 0.133 against 0.116 ms at 1/4 (slower).
+// b = 1, LDS against no LDS: n =
 // 16384, 9.3 against 13.2 ms at 1/16 (at 1/32, 7.1 against 6.7 ms: slower);
 // n = 4096 and 8192, 3.27 against 3.59 and 6.58 against 7.64 ms at 1/8
 // (losing at 1/16); n = 1024 and 2048, 1.32 against 1.39 and 2.60 against
@@ -772,12 +776,10 @@ bool small_lds_preferred(int32_t b, spmm_dtype_t w, spmm_dtype_t x, int64_t nnz,
     if (e[0] == '0') return false;
     if (e[0] == '1') return true;
   }
-  if (b == 1) {
-    // the density the kernel needs falls by half at n = 4096 and at n = 16384
-    const int64_t inv = n >= 16384 ? 16 : n >= 4096 ? 8 : n >= 1024 ? 4 : 0;
-    return inv > 0 && nnz * inv >= mb * kb;
-  }
-  return nnz * 8 >= mb * kb;
+  // the least density (as 1 / inv) at which the LDS kernel wins, by n
+  const int64_t inv = b == 1 ? (n >= 16384 ? 16 : n >= 4096 ? 8 : n >= 1024 ? 4 : 0)
+                             : (n >= 16384 ? 16 : n >= 1024 ? 8 : 0);
+  return inv > 0 && nnz * inv >= mb * kb;
 }
 
 int32_t small_lds_rows_per_wave(int32_t b, int32_t mb, int64_t n, int num_cus) {

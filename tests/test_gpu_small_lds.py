@@ -102,13 +102,15 @@ def test_lds_dynamic_equals_static(b, monkeypatch):
     assert torch.equal(Ys[:, : c.n], Yd[:, : c.n])
 
 
-@pytest.mark.parametrize("b,n,dens", [(4, 96, ((1 / 4, "1"), (1 / 16, "0"))),
+@pytest.mark.parametrize("b,n,dens", [(4, 1024, ((1 / 4, "1"), (1 / 16, "0"))),
+                                      (4, 256, ((1 / 4, "0"),)),
                                       (1, 1024, ((1 / 4, "1"), (1 / 8, "0"))),
                                       (1, 256, ((1 / 4, "0"),))])
 def test_lds_chosen_by_density(b, n, dens, monkeypatch):
     """Without the override (and without tuning) the LDS kernels run from
-    density 1/8 up at b = 4; at b = 1 from 1/4 up at n = 1024 (1/8 from n =
-    4096, 1/16 from n = 16384) and never at n below 1024. Both choices agree
+    density 1/8 up at b = 4 and from 1/4 up at b = 1 once n reaches 1024 (b =
+    1: 1/8 from n = 4096; both: 1/16 from n = 16384), never at smaller n.
+    Both choices agree
     with the oracle (the dispatch is checked through results equal to the
     forced kernel's, bit for bit)."""
     monkeypatch.delenv("SPMM_LDS_RW", raising=False)
