@@ -84,8 +84,8 @@ typedef enum { SPMM_F32 = 0, SPMM_F16 = 1, SPMM_BF16 = 2, SPMM_FP8_E4M3 = 3 } sp
  *               lane; 0 = the rule on n. form: 0 = the rule, 1 = the plain
  *               kernel, 2 = the plan's other kernel where it has one (the
  *               software-pipelined row kernel for b = 16/32 with W in the X
- *               type and no split rows; the LDS-staged kernel for b = 1 and
- *               4 with W in the X type), else the plain one; 3 = the dense GEMM on
+ *               type and no split rows; the LDS-staged kernel for b = 1, 4
+ *               and 8 with W in the X type), else the plain one; 3 = the dense GEMM on
  *               the plan's dense copy (needs dense_dispatch that keeps one);
  *               4 = the row kernel with every block row split over the four
  *               waves of a workgroup, partial sums added in wave order (b =

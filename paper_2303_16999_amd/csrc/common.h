@@ -201,13 +201,13 @@ spmm_status_t launch_sddmm_tiled(spmm_dtype_t t, int32_t b, const int32_t* tasks
 spmm_status_t launch_sddmm(spmm_dtype_t t, int32_t b, const int32_t* row_ptr, const int32_t* col_idx,
                            const int32_t* tasks, int32_t num_tasks, int64_t m, int64_t k, int64_t n, const void* dY,
                            int64_t lddy, const void* X, int64_t ldx, float* G, hipStream_t stream);
-// Small-block kernels with X staged in LDS for a panel of block rows (b = 1
-// or 4, 16-bit W and X of one type): rows per wave (8, 4 or 2) from
+// Small-block kernels with X staged in LDS for a panel of block rows (b = 1,
+// 4 or 8, 16-bit W and X of one type): rows per wave (8, 4 or 2) from
 // small_lds_rows_per_wave; small_lds_preferred says whether one runs instead
-// of the kernel below (by block size, dtypes, density and, for b = 1, n).
+// of the kernel below (by block size, dtypes, density and n).
 bool small_lds_preferred(int32_t b, spmm_dtype_t w, spmm_dtype_t x, int64_t nnz, int64_t mb, int64_t kb, int64_t n);
-// Whether an LDS-staged kernel handles the plan at all (b = 1 or 4, W in the
-// 16-bit X type).
+// Whether an LDS-staged kernel handles the plan at all (b = 1, 4 or 8, W in
+// the 16-bit X type).
 bool small_lds_eligible(int32_t b, spmm_dtype_t w, spmm_dtype_t x);
 int32_t small_lds_rows_per_wave(int32_t b, int32_t mb, int64_t n, int num_cus);
 spmm_status_t launch_spmm_small_lds(const RunArgs& a, const int32_t* row_ptr, const int32_t* col_idx, int32_t rw,

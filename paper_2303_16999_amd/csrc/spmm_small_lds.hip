@@ -1,5 +1,5 @@
-// Block-sparse x dense SpMM for b = 4 (and, further down, b = 1) with X
-// staged in LDS and shared by a panel of block rows (PopSparse, Section 3:
+// Block-sparse x dense SpMM for b = 4 and 8 (and, further down, b = 1) with
+// X staged in LDS and shared by a panel of block rows (PopSparse, Section 3:
 // Y = (M o W) * X, FP32 accumulation; Section 3.2: the static partition of
 // the known blocks).
 //
@@ -374,6 +374,7 @@ spmm_status_t small_lds_b(const RunArgs& a, const int32_t* rp, const int32_t* ci
 
 template <typename XT, typename YT>
 spmm_status_t small_lds_y(const RunArgs& a, const int32_t* rp, const int32_t* ci, hipStream_t s, int rw) {
+  if (a.plan.b == 8) return small_lds_b<XT, YT, 8>(a, rp, ci, s, rw);
   return small_lds_b<XT, YT, 4>(a, rp, ci, s, rw);
 }
 
@@ -763,11 +764,13 @@ spmm_status_t b1_lds_y(const RunArgs& a, const int32_t* rp, const int32_t* ci, h
 // n = 4096 and 8192, 3.27 against 3.59 and 6.58 against 7.64 ms at 1/8
 // (losing at 1/16); n = 1024 and 2048, 1.32 against 1.39 and 2.60 against
 // 2.99 ms at 1/4 (losing at 1/8); at n <= 512, where most lanes of its
-// 512-column tiles idle, it loses at every density. At b = 8 the kernel
-// without LDS was faster at every density. SPMM_SMALL_LDS=0 / 1 forces the
-// choice (for comparisons and tests).
+// 512-column tiles idle, it loses at every density. b = 8 (the b = 4 kernel
+// with four 4 x 4 tiles per block): only n = 16384 at 1/8, 2.91 against 3.23
+// ms; slower at 1/16 (1.97 against 1.70 ms) and at every point at n = 4096
+// (0.77 against 0.44 ms at 1/8) and n = 1024. SPMM_SMALL_LDS=0 / 1 forces
+// the choice (for comparisons and tests).
 bool small_lds_eligible(int32_t b, spmm_dtype_t w, spmm_dtype_t x) {
-  return (b == 1 || b == 4) && w == x && (x == SPMM_F16 || x == SPMM_BF16);
+  return (b == 1 || b == 4 || b == 8) && w == x && (x == SPMM_F16 || x == SPMM_BF16);
 }
 
 bool small_lds_preferred(int32_t b, spmm_dtype_t w, spmm_dtype_t x, int64_t nnz, int64_t mb, int64_t kb, int64_t n) {
@@ -777,8 +780,9 @@ bool small_lds_preferred(int32_t b, spmm_dtype_t w, spmm_dtype_t x, int64_t nnz,
     if (e[0] == '1') return true;
   }
   // the least density (as 1 / inv) at which the LDS kernel wins, by n
-  const int64_t inv = b == 1 ? (n >= 16384 ? 16 : n >= 4096 ? 8 : n >= 1024 ? 4 : 0)
-                             : (n >= 16384 ? 16 : n >= 1024 ? 8 : 0);
+  const int64_t inv = b == 1   ? (n >= 16384 ? 16 : n >= 4096 ? 8 : n >= 1024 ? 4 : 0)
+                      : b == 4 ? (n >= 16384 ? 16 : n >= 1024 ? 8 : 0)
+                               : (n >= 16384 ? 8 : 0);
   return inv > 0 && nnz * inv >= mb * kb;
 }
 
@@ -797,7 +801,8 @@ int32_t small_lds_rows_per_wave(int32_t b, int32_t mb, int64_t n, int num_cus) {
 
 spmm_status_t launch_spmm_small_lds(const RunArgs& a, const int32_t* row_ptr, const int32_t* col_idx, int32_t rw,
                                     hipStream_t s) {
-  if (a.plan.b != 1 && a.plan.b != 4) return fail(SPMM_ERR_UNSUPPORTED, "LDS small-block kernel: b = 1 or 4");
+  if (a.plan.b != 1 && a.plan.b != 4 && a.plan.b != 8)
+    return fail(SPMM_ERR_UNSUPPORTED, "LDS small-block kernel: b = 1, 4 or 8");
   if (a.wt != a.xt || (a.xt != SPMM_F16 && a.xt != SPMM_BF16))
     return fail(SPMM_ERR_UNSUPPORTED, "LDS small-block kernel: 16-bit W and X of one type");
   if (a.plan.b == 1) {

@@ -32,7 +32,7 @@ def _run(c, monkeypatch, rw=None, lds=True):
 
 
 @pytest.mark.parametrize("w,y", [("f16", "f16"), ("bf16", "bf16"), ("f16", "f32"), ("bf16", "f32")])
-@pytest.mark.parametrize("b,n", [(4, 1), (4, 37), (4, 100), (1, 1), (1, 37), (1, 100), (1, 600)])
+@pytest.mark.parametrize("b,n", [(4, 1), (4, 37), (4, 100), (8, 37), (8, 100), (1, 1), (1, 37), (1, 100), (1, 600)])
 def test_lds_ragged_shapes_match_oracle(w, y, b, n, monkeypatch):
     # k spans several chunks with a ragged tail; m leaves a partial panel
     c = Case(b * 301 + 3, 1500 + b // 2, n, b, 0.1, w=w, y=y, seed=400 + b + n)
@@ -43,7 +43,7 @@ def test_lds_ragged_shapes_match_oracle(w, y, b, n, monkeypatch):
     assert torch.isnan(Y[:, c.n:].float()).all().item()  # columns past n untouched
 
 
-@pytest.mark.parametrize("b", [1, 4])
+@pytest.mark.parametrize("b", [1, 4, 8])
 def test_lds_integer_exact_and_row_variants_bitwise(b, monkeypatch):
     c = Case(b * 520, 2100, 130, b, 0.15, w="f16", seed=430 + b, integer=True)
     ref = round_like(c.oracle(), "f16")
@@ -56,7 +56,7 @@ def test_lds_integer_exact_and_row_variants_bitwise(b, monkeypatch):
         assert torch.equal(Y[:, : c.n], outs[0][:, : c.n])
 
 
-@pytest.mark.parametrize("b", [1, 4])
+@pytest.mark.parametrize("b", [1, 4, 8])
 def test_lds_empty_rows_density_zero_and_long_rows(b, monkeypatch):
     c = Case(b * 200, b * 700, 64, b, 0.3, w="bf16", seed=440 + b)
     mask = c.mask.copy()
@@ -70,7 +70,7 @@ def test_lds_empty_rows_density_zero_and_long_rows(b, monkeypatch):
     assert torch.all(_run(z, monkeypatch)[:, : z.n] == 0).item()
 
 
-@pytest.mark.parametrize("b", [1, 4])
+@pytest.mark.parametrize("b", [1, 4, 8])
 def test_lds_against_kernel_without_lds(b, monkeypatch):
     c = Case(b * 260 + 1, b * 300 + 2, 260, b, 1 / 8, w="f16", y="f32", seed=450 + b)
     Yl = _run(c, monkeypatch, lds=True)
@@ -80,7 +80,7 @@ def test_lds_against_kernel_without_lds(b, monkeypatch):
     assert O.rel_fro(a, v) <= 1e-6
 
 
-@pytest.mark.parametrize("b", [1, 4])
+@pytest.mark.parametrize("b", [1, 4, 8])
 def test_lds_dynamic_equals_static(b, monkeypatch):
     monkeypatch.delenv("SPMM_LDS_RW", raising=False)
     c = Case(b * 180, b * 200, 96, b, 1 / 10, w="f16", seed=460 + b)
@@ -104,12 +104,14 @@ def test_lds_dynamic_equals_static(b, monkeypatch):
 
 @pytest.mark.parametrize("b,n,dens", [(4, 1024, ((1 / 4, "1"), (1 / 16, "0"))),
                                       (4, 256, ((1 / 4, "0"),)),
+                                      (8, 1024, ((1 / 4, "0"),)),
                                       (1, 1024, ((1 / 4, "1"), (1 / 8, "0"))),
                                       (1, 256, ((1 / 4, "0"),))])
 def test_lds_chosen_by_density(b, n, dens, monkeypatch):
     """Without the override (and without tuning) the LDS kernels run from
     density 1/8 up at b = 4 and from 1/4 up at b = 1 once n reaches 1024 (b =
-    1: 1/8 from n = 4096; both: 1/16 from n = 16384), never at smaller n.
+    1: 1/8 from n = 4096; both: 1/16 from n = 16384), never at smaller n;
+    at b = 8 only from n = 16384.
     Both choices agree
     with the oracle (the dispatch is checked through results equal to the
     forced kernel's, bit for bit)."""
