@@ -649,7 +649,7 @@ spmm_status_t build_dynamic_csr_small(const int32_t* nnz_dev, const int32_t* row
 
 // ------------------------------------------------------------------ row-range encoder
 // One launch, one workgroup per range of R block rows. Every workgroup reads
-// the whole COO list (validating it, so all reach the same verdict), counts
+// the whole COO list (validating it, so all reach the same status), counts
 // the entries above its range (its first CSR position) and keeps its own
 // entries in LDS as (row in range, column, input index) keys; an entry's CSR
 // place is its range's first position plus the number of kept keys below its
@@ -719,7 +719,7 @@ __global__ __launch_bounds__(kRowsThreads) void k_dyn_rows(const int32_t* __rest
   if (lane == 0) wsum[wave] = above;
   __syncthreads();
   const int32_t err = flag[0];
-  if (err) {  // every workgroup read the same entries: the same verdict
+  if (err) {  // every workgroup read the same entries: the same status
     if (blockIdx.x == 0 && tid == 0) {
       *status = err;
       if (status_out) *status_out = err;

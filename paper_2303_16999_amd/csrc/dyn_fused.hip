@@ -5,7 +5,7 @@
 // The encoder and the product share one launch: a workgroup of 16 waves owns
 // block row r and a group of four column tiles, reads the whole COO list of
 // the call in one round of loads, validates it (so every workgroup reaches
-// the same verdict, and on an error all of them skip the product and leave Y
+// the same status, and on an error all of them skip the product and leave Y
 // alone), counts the entries of the rows above r (its row's first CSR
 // position) and keeps its own row's entries in LDS as keys (column << 16 |
 // input index). Sorted, the keys are the row's CSR order, the canonical
@@ -150,7 +150,7 @@ __global__ __launch_bounds__(kFusedThreads) void k_dyn_fused(FusedParams f) {
   if (lane == 0) wsum[wave] = above;
   __syncthreads();
   const int32_t err = flag[0];
-  if (err) {  // every workgroup read the same entries: the same verdict
+  if (err) {  // every workgroup read the same entries: the same status
     if (blockIdx.x == 0 && tid == 0) {
       *f.status = err;
       if (f.status_out) *f.status_out = err;
