@@ -391,7 +391,7 @@ spmm_status_t small_lds_y(const RunArgs& a, const int32_t* rp, const int32_t* ci
 // of the tile: per nonzero one 16-byte LDS read; the FMAs run on v_dot2
 // over two nonzeros of the row (their two X values interleaved with v_perm,
 // their two weights packed in one dword), FP32 accumulation. Rows go in
-// pairs, four slots of each at a time; slots past a row's nonzeros read an
+// pairs, two slots of each at a time; slots past a row's nonzeros read an
 // LDS row of zeros with weight 0. Traffic from L2 per panel is the chunk
 // loads, 2 / (RW x NW x density) bytes per FMA.
 // V values (8 or 4) of 16 bits as dwords: one lane's share of an X row.
@@ -505,20 +505,22 @@ __device__ __forceinline__ uint32_t pack_batch(const Batch1& bt, int32_t k0, uin
   return on ? (bt.wv << 16) | ((uint32_t)(bt.cv - k0) & 0xFFFFu) : (uint32_t)KC;
 }
 
-// Slots t .. t + 3 of a packed batch (slots past a row's entries read the
-// zero row with weight 0). `row` is this lane's part of LDS row 0 of the chunk.
-template <typename XT, int V>
+// Slots t .. t + S - 1 of a packed batch (S = 2 or 4; slots past a row's
+// nonzeros read the zero row with weight 0). `row` is this lane's part of
+// LDS row 0 of the chunk.
+template <typename XT, int V, int S>
 __device__ __forceinline__ void b1_group(float (&acc)[V], uint32_t pk, int32_t t, const uint16_t* row) {
-  uint32_t w[4];
-  XSeg<V> x[4];
+  static_assert(S == 2 || S == 4, "slots in pairs");
+  uint32_t w[S];
+  XSeg<V> x[S];
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
+  for (int j = 0; j < S; ++j) {
     const uint32_t e = (uint32_t)__builtin_amdgcn_readlane((int)pk, t + j);
     w[j] = e >> 16;
     x[j].read(row + (e & 0xFFFFu) * (64 * V));
   }
 #pragma unroll
-  for (int pr = 0; pr < 2; ++pr) {
+  for (int pr = 0; pr < S / 2; ++pr) {
     const uint32_t wp = w[2 * pr] | (w[2 * pr + 1] << 16);
 #pragma unroll
     for (int v = 0; v < V; ++v) {
@@ -567,6 +569,7 @@ __global__ __launch_bounds__(NW * 64, MINB) void k_spmm_b1_lds(LParams p) {
   // for that (DUP) reloads it.
   static_assert(KC <= 64, "a chunk's entries of a row fit one batch");
   static_assert(RW % 2 == 0, "rows are multiplied in pairs");
+  constexpr int SL = 2;  // slots per row per step of the pair loop
   constexpr bool DUP = GATHER;
   constexpr int BUF = (KC + 1) * NT;  // halves per LDS buffer: KC rows of X and a row of zeros
   Batch1 bt[RW];   // each row's entries from position bq (loaded one chunk ahead)
@@ -627,9 +630,9 @@ __global__ __launch_bounds__(NW * 64, MINB) void k_spmm_b1_lds(LParams p) {
 #pragma unroll
     for (int i = 0; i < RW; i += 2) {
       const int32_t nt = max(cnt[i], cnt[i + 1]);
-      for (int32_t t = 0; t < nt; t += 4) {
-        b1_group<XT, V>(acc[i], pk[i], t, row);
-        b1_group<XT, V>(acc[i + 1], pk[i + 1], t, row);
+      for (int32_t t = 0; t < nt; t += SL) {
+        b1_group<XT, V, SL>(acc[i], pk[i], t, row);
+        b1_group<XT, V, SL>(acc[i + 1], pk[i + 1], t, row);
       }
     }
 #pragma unroll
@@ -643,7 +646,7 @@ __global__ __launch_bounds__(NW * 64, MINB) void k_spmm_b1_lds(LParams p) {
             const int32_t c = __popcll(live);
             if (c == 0) break;
             const uint32_t xp = pack_batch<KC>(x, k0, live, lane);
-            for (int32_t t = 0; t < c; t += 4) b1_group<XT, V>(acc[i], xp, t, row);
+            for (int32_t t = 0; t < c; t += 4) b1_group<XT, V, 4>(acc[i], xp, t, row);
             q += c;
             if (c < 64 || q >= end[i]) break;
           }
@@ -760,7 +763,7 @@ spmm_status_t b1_lds_y(const RunArgs& a, const int32_t* rp, const int32_t* ci, h
 // slower at 1/16 (and at n = 8192, 1.29 against 1.25 ms); n = 1024, 0.239
 // against 0.259 ms at 1/8; n = 256, 0.133 against 0.116 ms at 1/4 (slower).
 // b = 1, LDS against no LDS: n =
-// 16384, 9.3 against 13.2 ms at 1/16 (at 1/32, 7.1 against 6.7 ms: slower);
+// 16384, 8.9 against 13.2 ms at 1/16 (at 1/32, 7.1 against 6.7 ms: slower);
 // n = 4096 and 8192, 3.27 against 3.59 and 6.58 against 7.64 ms at 1/8
 // (losing at 1/16); n = 1024 and 2048, 1.32 against 1.39 and 2.60 against
 // 2.99 ms at 1/4 (losing at 1/8); at n <= 512, where most lanes of its
