@@ -60,7 +60,7 @@ struct RowProblem {
   const int32_t* heavy_rows;
   float* part;             // piece partial sums, nullptr: no pieces
   int32_t num_light;       // rows of the light units
-  int32_t pad_;
+  int32_t row_slices;      // nonzero: light units ordered by eighths of their row groups (light_unit)
 };
 
 struct Params {
@@ -547,6 +547,28 @@ __device__ __forceinline__ void row_tile(const RowProblem& p, int32_t r, int32_t
   row_store<YT, B, NS>(p, r, n0, lane, acc);
 }
 
+// Row group and column step of light unit lu among rg row groups and ts
+// column steps. Default: row groups first. With row slices: the row groups
+// in eight balanced slices, each slice's units together (its row groups
+// first, then the next column step), so that the contiguous unit range of an
+// XCD covers about one slice: the W it streams stays small for every column
+// step. Either way a bijection onto (row group, column step).
+__device__ __forceinline__ void unit_place(const RowProblem& p, int32_t lu, int32_t rg, int32_t ts, int32_t& g,
+                                           int32_t& t) {
+  if (!p.row_slices) {
+    g = lu % rg;
+    t = lu / rg;
+    return;
+  }
+  const int32_t q = rg >> 3, rr = rg & 7;
+  const int32_t gi = lu / ts;  // a row group of the slice holding lu
+  const int32_t s = gi < rr * (q + 1) ? gi / (q + 1) : rr + (gi - rr * (q + 1)) / max(q, 1);
+  const int32_t g0 = s * q + min(s, rr), rows = q + (s < rr ? 1 : 0);
+  const int32_t l = lu - g0 * ts;
+  g = g0 + l % rows;
+  t = l / rows;
+}
+
 // Block row r and first column n0 of a wave in light unit lu. Where the
 // columns span more than one tile of 16*ns, a unit is two block rows times two
 // adjacent column tiles (waves 0, 1 on the first row, 2, 3 on the second): the
@@ -554,21 +576,24 @@ __device__ __forceinline__ void row_tile(const RowProblem& p, int32_t r, int32_t
 // time is the longer of two rows rather than of four. Otherwise a unit is four
 // block rows, one per wave, on the one tile. Consecutive units step through
 // the rows first, so the waves resident on an XCD share a few column tiles of
-// X. With a light-row list the units take its rows in its order (the plan
-// lists them longest first and leaves out split rows), else every row in
-// order. False: no work for this wave (past the last row or column).
+// X (with row slices: one eighth of the rows over every column step, see
+// unit_place). With a light-row list the units take its rows in its order
+// (the plan lists them longest first and leaves out split rows), else every
+// row in order. False: no work for this wave (past the last row or column).
 __device__ __forceinline__ bool light_unit(const RowProblem& p, int32_t lu, int wave, int ns, int32_t& r, int32_t& n0) {
   const int32_t tile = 16 * ns;
   const int32_t nl = p.num_light;
-  int32_t i;
+  int32_t i, g, t;
   if (p.n > tile) {
     const int32_t rg = (nl + 1) >> 1;
-    i = (lu % rg) * 2 + (wave >> 1);
-    n0 = ((lu / rg) * 2 + (wave & 1)) * tile;
+    unit_place(p, lu, rg, (p.n + 2 * tile - 1) / (2 * tile), g, t);
+    i = g * 2 + (wave >> 1);
+    n0 = (t * 2 + (wave & 1)) * tile;
   } else {
     const int32_t rg = (nl + kRowsPerWg - 1) / kRowsPerWg;
-    i = (lu % rg) * kRowsPerWg + wave;
-    n0 = (lu / rg) * tile;
+    unit_place(p, lu, rg, (p.n + tile - 1) / tile, g, t);
+    i = g * kRowsPerWg + wave;
+    n0 = t * tile;
   }
   if (i >= nl || n0 >= p.n) return false;
   r = p.light_rows ? sload(p.light_rows, i) : i;
@@ -755,6 +780,17 @@ __global__ __launch_bounds__(256, SPLIT ? 5 : 1) void k_spmm_row(Params prm) {
   }
 }
 
+// Whether light units go by row slices (unit_place): from n = 16384, where X
+// no longer stays in the Infinity Cache and the W that a pass over a column
+// step streams through an XCD's L2 evicts the X slabs between their uses.
+// Measured at m = k = 8192, d = 1/16, b = 16, tuned: n = 16384 0.818 against
+// 0.930 ms, n = 65536 3.42 against 3.69 ms; n = 8192 no better.
+// SPMM_ROW_SLICES=0/1 forces the choice.
+inline bool row_slices_preferred(int64_t n) {
+  if (const char* e = getenv("SPMM_ROW_SLICES")) return e[0] == '1';
+  return n >= 16384;
+}
+
 inline RowProblem row_problem(const RunArgs& a, const int32_t* row_ptr, const int32_t* col_idx) {
   RowProblem p{};
   p.row_ptr = row_ptr;
@@ -779,6 +815,7 @@ inline RowProblem row_problem(const RunArgs& a, const int32_t* row_ptr, const in
   p.part = p.num_heavy ? a.part : nullptr;
   p.light_rows = a.light_rows;
   p.num_light = a.light_rows ? a.num_light : a.plan.mb;
+  p.row_slices = p.num_heavy == 0 && row_slices_preferred(a.n) ? 1 : 0;
   if (a.split_all && a.plan.b == 16) {  // every row split, rows taken in order
     const bool pieces = a.part && a.heavy_rows;  // a table of every row's pieces
     p.num_heavy = pieces ? a.num_heavy : a.plan.mb;

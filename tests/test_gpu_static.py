@@ -164,3 +164,27 @@ def test_default_plan_holds_one_copy_of_the_values():
     # what the device lost to the plan: one copy, never two (allocation rounding aside)
     assert free0 - free1 < 1.5 * val_bytes + 4 * 2**20
     plan.close()
+
+
+@pytest.mark.parametrize("b,mb,n,ns", [(16, 37, 1000, 8), (16, 37, 300, 4), (16, 5, 700, 2), (32, 23, 520, 8),
+                                       (16, 61, 100, 8)])
+def test_row_slices_equal_row_first_order_bitwise(b, mb, n, ns, monkeypatch):
+    """Light units by eighths of the block rows (the default from n = 16384)
+    cover the same (row group, column step) units as the row-first order,
+    each computed the same way: results equal bit for bit, integer data
+    exact against the oracle. Ragged m and n; fewer row groups than eight
+    (mb = 5); one tile (n = 100 with ns = 8: four rows per unit)."""
+    c = Case(mb * b - 3, 41 * b - 5, n, b, 0.2, w="f16", y="f32", seed=900 + mb, integer=True)
+    outs = []
+    for sl in ("0", "1"):
+        monkeypatch.setenv("SPMM_ROW_SLICES", sl)
+        plan = spmm.StaticPlan(c.m, c.k, b, c.mask, "f16", y="f32", variant=ns + 256)
+        vals, X, _ = c.device_inputs()
+        plan.set_values(vals)
+        Y = c.new_Y()
+        plan.run(X, Y, n=c.n)
+        torch.cuda.synchronize()
+        assert np.array_equal(y_f64(Y, c), c.oracle()), sl
+        assert torch.isnan(Y[:, c.n:]).all().item()
+        outs.append(Y)
+    assert torch.equal(outs[0][:, : c.n], outs[1][:, : c.n])
