@@ -46,6 +46,7 @@ struct SParams {
   uint32_t x_bytes;        // k * ldx * sizeof(X element), < 2^31
   int32_t relu;            // nonzero: max(0, y) before the output cast
   const int32_t* status;   // skip when *status != 0 (dynamic), else nullptr
+  int32_t row_slices;      // S > 0: units ordered by S slices of the row groups (unit_place)
 };
 
 constexpr uint32_t kOOB = 0x80000000u;
@@ -57,6 +58,26 @@ __device__ __forceinline__ int32_t xcd_unit(int32_t w, int32_t U) {
   const int32_t q = U >> 3, r = U & 7;
   const int32_t x = w & 7, local = w >> 3;
   return x * q + min(x, r) + local;
+}
+
+// Row group g and column tile t of unit u among rg row groups and ts tiles:
+// row groups first, or, with S row slices, the row groups in S balanced
+// slices whose units come together (row groups first within a slice), so
+// that an XCD's contiguous eighth of the units reads an S-th of the indices
+// and weights for every column tile. A bijection either way.
+__device__ __forceinline__ void unit_place(int32_t u, int32_t rg, int32_t ts, int32_t S, int32_t& g, int32_t& t) {
+  if (S == 0) {
+    g = u % rg;
+    t = u / rg;
+    return;
+  }
+  const int32_t q = rg / S, rr = rg - q * S;
+  const int32_t gi = u / ts;  // a row group of the slice holding u
+  const int32_t s = gi < rr * (q + 1) ? gi / (q + 1) : rr + (gi - rr * (q + 1)) / max(q, 1);
+  const int32_t g0 = s * q + min(s, rr), rows = q + (s < rr ? 1 : 0);
+  const int32_t l = u - g0 * ts;
+  g = g0 + l % rows;
+  t = l / rows;
 }
 
 template <typename T> struct Num;
@@ -129,8 +150,9 @@ __global__ __launch_bounds__(256) void k_spmm_small(SParams p) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int32_t unit = xcd_unit(blockIdx.x, p.num_units);
   const int32_t rgroups = (p.mb + kRowsPerWg - 1) / kRowsPerWg;
-  const int32_t rg = unit % rgroups;
-  const int32_t n0 = (unit / rgroups) * (64 * V);
+  int32_t rg, ct;
+  unit_place(unit, rgroups, (p.n + 64 * V - 1) / (64 * V), p.row_slices, rg, ct);
+  const int32_t n0 = ct * (64 * V);
   const int32_t r = rg * kRowsPerWg + wave;
   if (r >= p.mb) return;
   const int32_t col0 = n0 + V * lane;
@@ -315,8 +337,10 @@ __global__ __launch_bounds__(256) void k_spmm_small_mfma(SParams p) {
   const int g = lane >> 4, j = lane & 15;
   const int32_t unit = xcd_unit(blockIdx.x, p.num_units);
   const int32_t rgroups = (p.mb + kRowsPerWg - 1) / kRowsPerWg;
-  const int32_t r = (unit % rgroups) * kRowsPerWg + wave;
-  const int32_t n0 = (unit / rgroups) * 128;
+  int32_t rgi, ct;
+  unit_place(unit, rgroups, (p.n + 127) / 128, p.row_slices, rgi, ct);
+  const int32_t r = rgi * kRowsPerWg + wave;
+  const int32_t n0 = ct * 128;
   if (r >= p.mb) return;
   __amdgpu_buffer_rsrc_t xr = __builtin_amdgcn_make_buffer_rsrc((void*)p.X, (short)0, (int)p.x_bytes, 0x00020000);
   const uint8_t* __restrict__ Wb = (const uint8_t*)p.W;
@@ -430,8 +454,10 @@ __global__ __launch_bounds__(256) void k_spmm_small_mfma_pp(SParams p) {
   const int g = lane >> 4, j = lane & 15;
   const int32_t unit = xcd_unit(blockIdx.x, p.num_units);
   const int32_t rgroups = (p.mb + kRowsPerWg - 1) / kRowsPerWg;
-  const int32_t r = (unit % rgroups) * kRowsPerWg + wave;
-  const int32_t n0 = (unit / rgroups) * 128;
+  int32_t rgi, ct;
+  unit_place(unit, rgroups, (p.n + 127) / 128, p.row_slices, rgi, ct);
+  const int32_t r = rgi * kRowsPerWg + wave;
+  const int32_t n0 = ct * 128;
   if (r >= p.mb) return;
   __amdgpu_buffer_rsrc_t xr = __builtin_amdgcn_make_buffer_rsrc((void*)p.X, (short)0, (int)p.x_bytes, 0x00020000);
   const uint8_t* __restrict__ Wb = (const uint8_t*)p.W;
@@ -547,6 +573,23 @@ bool small_pp_preferred(int32_t b, int64_t units, int32_t mb, int64_t nnz, int n
   return units <= 8 * (int64_t)num_cus && nnz >= 4 * (32 / b) * (int64_t)mb;
 }
 
+// Row slices of the units (unit_place), 0 for none: eight where X no longer
+// stays in the Infinity Cache and the indices and weights that a pass over a
+// column tile streams through an XCD's L2 evict X between its uses. Measured
+// at m = k = 8192 (FP16, the kernel without LDS), eight slices against none:
+// n = 16384, b = 8 1.22 against 1.70 ms at d = 1/16, b = 4 1.44 against 1.73
+// ms at 1/32, b = 1 6.13 against 6.70 ms at 1/32; n = 8192, d = 1/16, b = 8
+// 0.486 against 0.601 ms, b = 4 1.15 against 1.25 ms, but b = 1 4.63
+// against 4.35 ms; n <= 4096 no better at any block size. SPMM_SMALL_SLICES
+// =0/2/4/8 forces the count.
+int32_t small_row_slices(int64_t n, int32_t b) {
+  if (const char* e = getenv("SPMM_SMALL_SLICES")) {
+    const int v = atoi(e);
+    return (v == 2 || v == 4 || v == 8) ? v : 0;
+  }
+  return n >= (b == 1 ? 16384 : 8192) ? 8 : 0;
+}
+
 template <typename XT, typename WT, typename YT, int B, int V>
 spmm_status_t launch_small(const RunArgs& a, const int32_t* row_ptr, const int32_t* col_idx, hipStream_t s) {
   SParams p;
@@ -565,6 +608,7 @@ spmm_status_t launch_small(const RunArgs& a, const int32_t* row_ptr, const int32
   p.mb = a.plan.mb;
   p.status = a.status;
   p.relu = a.relu ? 1 : 0;
+  p.row_slices = small_row_slices(a.n, B);
   const int64_t xb = (int64_t)a.plan.k * a.ldx * (int64_t)sizeof(XT);
   if (xb >= (int64_t)INT32_MAX) return fail(SPMM_ERR_UNSUPPORTED, "X larger than 2 GiB is not supported");
   p.x_bytes = (uint32_t)xb;

@@ -768,10 +768,15 @@ spmm_status_t b1_lds_y(const RunArgs& a, const int32_t* rp, const int32_t* ci, h
 // (losing at 1/16); n = 1024 and 2048, 1.32 against 1.39 and 2.60 against
 // 2.99 ms at 1/4 (losing at 1/8); at n <= 512, where most lanes of its
 // 512-column tiles idle, it loses at every density. b = 8 (the b = 4 kernel
-// with four 4 x 4 tiles per block): only n = 16384 at 1/8, 2.91 against 3.23
-// ms; slower at 1/16 (1.97 against 1.70 ms) and at every point at n = 4096
-// (0.77 against 0.44 ms at 1/8) and n = 1024. SPMM_SMALL_LDS=0 / 1 forces
-// the choice (for comparisons and tests).
+// with four 4 x 4 tiles per block): slower than the kernel without LDS at
+// every point measured, once that kernel orders its units by row slices at
+// large n (n = 16384: 2.90 against 2.17 ms at 1/8, 1.93 against 1.23 ms at
+// 1/16; n = 4096: 0.77 against 0.44 ms at 1/8), so the rule never takes it;
+// the tuner still times it. The n = 16384 figures for b = 4 and 1 above
+// are against the kernel without LDS in row-first order; with row slices it
+// takes 2.60 and 4.57 ms for b = 4 (1/16, 1/8) and 12.4 and 24.1 ms for
+// b = 1 (1/16, 1/8), so the LDS kernels still win there. SPMM_SMALL_LDS=0 /
+// 1 forces the choice (for comparisons and tests).
 bool small_lds_eligible(int32_t b, spmm_dtype_t w, spmm_dtype_t x) {
   return (b == 1 || b == 4 || b == 8) && w == x && (x == SPMM_F16 || x == SPMM_BF16);
 }
@@ -785,7 +790,7 @@ bool small_lds_preferred(int32_t b, spmm_dtype_t w, spmm_dtype_t x, int64_t nnz,
   // the least density (as 1 / inv) at which the LDS kernel wins, by n
   const int64_t inv = b == 1   ? (n >= 16384 ? 16 : n >= 4096 ? 8 : n >= 1024 ? 4 : 0)
                       : b == 4 ? (n >= 16384 ? 16 : n >= 1024 ? 8 : 0)
-                               : (n >= 16384 ? 8 : 0);
+                               : 0;
   return inv > 0 && nnz * inv >= mb * kb;
 }
 

@@ -145,3 +145,24 @@ def test_small_dynamic_duplicates_summed(b):
     assert status.item() == 0
     ref = O.spmm_expand(m, k, b, rows, cols, synth.storage_to_f64(vals, "f16"), synth.storage_to_f64(X, "f16"))
     assert O.rel_fro(Y[:, :n].cpu().numpy().astype(np.float64), ref) <= 5e-3
+
+
+@pytest.mark.parametrize("b,w,mbr,n", [(1, "f16", 300, 700), (1, "f32", 77, 300), (4, "f16", 90, 600), (8, "bf16", 61, 260),
+                                       (4, "f16", 5, 200)])
+def test_small_row_slices_equal_row_first_order_bitwise(b, w, mbr, n, monkeypatch):
+    """The kernels without LDS order their units by 8, 4 or 2 slices of the
+    row groups at large n; each unit is computed the same way as in the
+    row-first order, so results are equal bit for bit, and integer data is
+    exact against the oracle. Ragged m and n; fewer row groups than slices
+    (mbr = 5)."""
+    monkeypatch.setenv("SPMM_SMALL_LDS", "0")
+    c = Case(mbr * b - (1 if b > 1 else 0), 53 * b + 3, n, b, 0.15, w=w, y="f32", seed=950 + b + mbr, integer=True)
+    outs = []
+    for sl in ("0", "8", "4", "2"):
+        monkeypatch.setenv("SPMM_SMALL_SLICES", sl)
+        plan, Y = c.run_static()
+        assert np.array_equal(y_f64(Y, c), c.oracle()), sl
+        assert torch.isnan(Y[:, c.n:]).all().item()
+        outs.append(Y)
+    for Y in outs[1:]:
+        assert torch.equal(outs[0][:, : c.n], Y[:, : c.n])
