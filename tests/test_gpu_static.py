@@ -188,3 +188,63 @@ def test_row_slices_equal_row_first_order_bitwise(b, mb, n, ns, monkeypatch):
         assert torch.isnan(Y[:, c.n:]).all().item()
         outs.append(Y)
     assert torch.equal(outs[0][:, : c.n], outs[1][:, : c.n])
+
+
+def test_slice_orders_at_large_n_all_paths(monkeypatch):
+    """At the n where units go by row slices (row kernel from n = 16384, the
+    small-block kernels without LDS from n = 8192 or 16384): the static plan
+    is exact on integer data and equal bit for bit to the row-first order; a
+    grouped launch holding such a problem equals its single launch; a dynamic
+    call equals the static plan."""
+    monkeypatch.setenv("SPMM_SMALL_LDS", "0")
+    # row kernel, n = 16384
+    c = Case(37 * 16 - 3, 25 * 16, 16384, 16, 0.2, w="f16", y="f32", seed=960, integer=True)
+    outs = []
+    for sl in ("", "0"):
+        if sl:
+            monkeypatch.setenv("SPMM_ROW_SLICES", sl)
+        plan, Y = c.run_static()
+        assert np.array_equal(y_f64(Y, c), c.oracle()), sl
+        outs.append((plan, Y))
+    monkeypatch.delenv("SPMM_ROW_SLICES", raising=False)
+    assert torch.equal(outs[0][1][:, : c.n], outs[1][1][:, : c.n])
+    # a grouped launch of that plan (n = 16384) and a small problem
+    c2 = Case(37 * 16 - 3, 25 * 16, 300, 16, 0.2, w="f16", y="f32", seed=961, integer=True)
+    p2, Y2 = c2.run_static()
+    _, X1, _ = c.device_inputs()
+    _, X2, _ = c2.device_inputs()
+    G1, G2 = c.new_Y(), c2.new_Y()
+    spmm.Group(4).run([outs[0][0], p2], [X1, X2], [G1, G2], ns=[c.n, c2.n])
+    torch.cuda.synchronize()
+    assert torch.equal(G1[:, : c.n], outs[0][1][:, : c.n])
+    assert torch.equal(G2[:, : c2.n], Y2[:, : c2.n])
+    # small-block kernels without LDS at their slice thresholds
+    for b, n in ((1, 16384), (4, 8192), (8, 8192)):
+        cs = Case(29 * b + 1, 31 * b, n, b, 0.2, w="f16", y="f32", seed=962 + b, integer=True)
+        res = []
+        for sl in ("", "0"):
+            if sl:
+                monkeypatch.setenv("SPMM_SMALL_SLICES", sl)
+            _, Ys = cs.run_static()
+            assert np.array_equal(y_f64(Ys, cs), cs.oracle()), (b, sl)
+            res.append(Ys)
+        monkeypatch.delenv("SPMM_SMALL_SLICES", raising=False)
+        assert torch.equal(res[0][:, : cs.n], res[1][:, : cs.n]), b
+    # a dynamic call at b = 4, n = 8192 against the static plan (both sliced)
+    cd = Case(29 * 4 + 1, 31 * 4, 8192, 4, 0.2, w="f16", seed=970)
+    _, Ys = cd.run_static()
+    max_nnz = len(cd.rows) + 3
+    pad = max_nnz - len(cd.rows)
+    perm = np.random.default_rng(9).permutation(len(cd.rows))
+    r = dev(np.concatenate([cd.rows[perm], np.zeros(pad, np.int32)]).astype(np.int32))
+    col = dev(np.concatenate([cd.cols[perm], np.zeros(pad, np.int32)]).astype(np.int32))
+    v = dev(np.concatenate([cd.vals_store[perm], np.zeros((pad, 4, 4), cd.vals_store.dtype)]))
+    nnz = torch.tensor([len(cd.rows)], dtype=torch.int32, device="cuda")
+    h = spmm.DynamicHandle(cd.m, cd.k, 4, max_nnz, "f16")
+    _, X, _ = cd.device_inputs()
+    Yd = cd.new_Y()
+    st = torch.full((1,), -1, dtype=torch.int32, device="cuda")
+    h.run(nnz, r, col, v, X, Yd, st, n=cd.n)
+    torch.cuda.synchronize()
+    assert st.item() == 0
+    assert torch.equal(Ys[:, : cd.n], Yd[:, : cd.n])
