@@ -294,7 +294,8 @@ spmm_status_t spmm_speedup_model(int64_t m, double density, int32_t b, double* s
  * compute kernel's variant (tile width and kernel form), and it is made by
  * measurement. spmm_autotune_static runs every candidate variant of the
  * plan's kernels on the caller's X and Y (n columns; Y receives the result),
- * times each with HIP events on `stream` (2 warm-up and 5 timed runs), and
+ * times each with HIP events on `stream` (untimed warm-up runs, then five
+ * interleaved rounds of one launch per candidate, the median kept), and
  * records the fastest for n's size class (the power of two at or above n) in
  * the plan and in a process-wide table keyed by (b, dtypes, density class =
  * round(-log2 d), n class, whether the plan keeps a dense copy). Plans with

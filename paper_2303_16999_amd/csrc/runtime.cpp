@@ -723,8 +723,9 @@ static int plan_candidates(const spmm_plan_s* p, int32_t (&c)[8]) {
   return k;
 }
 
-// Times every candidate on the caller's operands (2 warm-up and 5 timed runs
-// each, HIP events on `s`), records the fastest for n's class in the plan and
+// Times every candidate on the caller's operands (after 8 + nc untimed runs,
+// 5 interleaved rounds of one launch per candidate, HIP events on `s`, the
+// median per candidate), records the fastest for n's class in the plan and
 // the process table, and leaves Y holding its result. Synchronises `s`.
 static spmm_status_t tune_plan(spmm_plan_s* p, int64_t n, const void* X, int64_t ldx, void* Y, int64_t ldy,
                                hipStream_t s, int32_t* cand_out, float* times_out, int32_t* count_out,
@@ -736,33 +737,41 @@ static spmm_status_t tune_plan(spmm_plan_s* p, int64_t n, const void* X, int64_t
   float best_ms = 0.f;
   spmm_status_t st = SPMM_OK;
   if (nc > 0) {
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    SPMM_HIP(hipEventCreate(&e0));
-    hipError_t he = hipEventCreate(&e1);
-    if (he != hipSuccess) {
-      (void)hipEventDestroy(e0);
-      return fail_hip(he, "hipEventCreate");
+    // The clocks ramp up over the first launches of a process: warm up with
+    // the first candidate, run every candidate once untimed, then time the
+    // candidates in interleaved rounds (one launch each per round, its own
+    // pair of events) and keep each one's median, so that no candidate is
+    // favoured by running later.
+    constexpr int kRounds = 5;
+    for (int i = 0; i < 8 && st == SPMM_OK; ++i) st = run_plan(p, n, X, ldx, Y, ldy, cand[0], false, s);
+    for (int c = 0; c < nc && st == SPMM_OK; ++c) st = run_plan(p, n, X, ldx, Y, ldy, cand[c], false, s);
+    if (st != SPMM_OK) return st;
+    hipEvent_t ev[16] = {};
+    hipError_t he = hipSuccess;
+    for (int i = 0; i < 2 * nc && he == hipSuccess; ++i) he = hipEventCreate(&ev[i]);
+    float samples[8][kRounds] = {};
+    for (int r = 0; r < kRounds && st == SPMM_OK && he == hipSuccess; ++r) {
+      for (int c = 0; c < nc && st == SPMM_OK && he == hipSuccess; ++c) {
+        he = hipEventRecord(ev[2 * c], s);
+        if (he == hipSuccess) st = run_plan(p, n, X, ldx, Y, ldy, cand[c], false, s);
+        if (he == hipSuccess && st == SPMM_OK) he = hipEventRecord(ev[2 * c + 1], s);
+      }
+      if (he == hipSuccess && st == SPMM_OK) he = hipEventSynchronize(ev[2 * nc - 1]);
+      for (int c = 0; c < nc && he == hipSuccess && st == SPMM_OK; ++c)
+        he = hipEventElapsedTime(&samples[c][r], ev[2 * c], ev[2 * c + 1]);
     }
-    for (int c = 0; c < nc && st == SPMM_OK; ++c) {
-      for (int i = 0; i < 2 && st == SPMM_OK; ++i) st = run_plan(p, n, X, ldx, Y, ldy, cand[c], false, s);
-      if (st != SPMM_OK) break;
-      he = hipEventRecord(e0, s);
-      for (int i = 0; i < 5 && st == SPMM_OK && he == hipSuccess; ++i) st = run_plan(p, n, X, ldx, Y, ldy, cand[c], false, s);
-      if (he == hipSuccess) he = hipEventRecord(e1, s);
-      if (he == hipSuccess) he = hipEventSynchronize(e1);
-      float ms = 0.f;
-      if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
-      if (he != hipSuccess) st = fail_hip(he, "autotune timing");
-      if (st != SPMM_OK) break;
-      times[c] = ms / 5.f;
+    for (int i = 0; i < 2 * nc; ++i)
+      if (ev[i]) (void)hipEventDestroy(ev[i]);
+    if (st != SPMM_OK) return st;
+    if (he != hipSuccess) return fail_hip(he, "autotune timing");
+    for (int c = 0; c < nc; ++c) {
+      std::sort(samples[c], samples[c] + kRounds);
+      times[c] = samples[c][kRounds / 2];
       if (!best || times[c] < best_ms) {
         best = cand[c];
         best_ms = times[c];
       }
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    if (st != SPMM_OK) return st;
     // leave Y holding the result of the chosen variant
     if ((st = run_plan(p, n, X, ldx, Y, ldy, best, false, s)) != SPMM_OK) return st;
     SPMM_HIP(hipStreamSynchronize(s));
