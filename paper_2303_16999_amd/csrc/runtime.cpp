@@ -1092,29 +1092,40 @@ spmm_status_t spmm_run_dynamic(spmm_dyn_t h, const int32_t* nnzb_dev, const int3
     int32_t cand[10];
     const int ncand = dynamic_candidates(h->b, h->w, h->x, fused_ok, cand);
     if (ncand > 1) {
-      hipEvent_t e0 = nullptr, e1 = nullptr;
-      SPMM_HIP(hipEventCreate(&e0));
-      hipError_t he = hipEventCreate(&e1);
+      // as tune_plan: warm-up calls, then interleaved rounds (three calls per
+      // candidate per round, their own pair of events), the median per candidate
+      constexpr int kRounds = 5, kCalls = 3;
+      for (int i = 0; i < 8 && st == SPMM_OK; ++i) st = call(cand[0]);
+      for (int c = 0; c < ncand && st == SPMM_OK; ++c) st = call(cand[c]);
+      if (st != SPMM_OK) return st;
+      hipEvent_t ev[20] = {};
+      hipError_t he = hipSuccess;
+      for (int i = 0; i < 2 * ncand && he == hipSuccess; ++i) he = hipEventCreate(&ev[i]);
+      float samples[10][kRounds] = {};
+      for (int r = 0; r < kRounds && st == SPMM_OK && he == hipSuccess; ++r) {
+        for (int c = 0; c < ncand && st == SPMM_OK && he == hipSuccess; ++c) {
+          he = hipEventRecord(ev[2 * c], s);
+          for (int i = 0; i < kCalls && st == SPMM_OK && he == hipSuccess; ++i) st = call(cand[c]);
+          if (he == hipSuccess && st == SPMM_OK) he = hipEventRecord(ev[2 * c + 1], s);
+        }
+        if (he == hipSuccess && st == SPMM_OK) he = hipEventSynchronize(ev[2 * ncand - 1]);
+        for (int c = 0; c < ncand && he == hipSuccess && st == SPMM_OK; ++c)
+          he = hipEventElapsedTime(&samples[c][r], ev[2 * c], ev[2 * c + 1]);
+      }
+      for (int i = 0; i < 2 * ncand; ++i)
+        if (ev[i]) (void)hipEventDestroy(ev[i]);
+      if (st != SPMM_OK) return st;
+      if (he != hipSuccess) return fail_hip(he, "dynamic tuning");
       int32_t best = 0;
       float best_ms = 0.f;
-      for (int c = 0; c < ncand && he == hipSuccess && st == SPMM_OK; ++c) {
-        for (int i = 0; i < 2 && st == SPMM_OK; ++i) st = call(cand[c]);
-        if (st != SPMM_OK) break;
-        he = hipEventRecord(e0, s);
-        for (int i = 0; i < 5 && st == SPMM_OK && he == hipSuccess; ++i) st = call(cand[c]);
-        if (he == hipSuccess) he = hipEventRecord(e1, s);
-        if (he == hipSuccess) he = hipEventSynchronize(e1);
-        float ms = 0.f;
-        if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
-        if (he == hipSuccess && (!best || ms < best_ms)) {
+      for (int c = 0; c < ncand; ++c) {
+        std::sort(samples[c], samples[c] + kRounds);
+        const float ms = samples[c][kRounds / 2];
+        if (!best || ms < best_ms) {
           best = cand[c];
           best_ms = ms;
         }
       }
-      (void)hipEventDestroy(e0);
-      if (e1) (void)hipEventDestroy(e1);
-      if (st != SPMM_OK) return st;
-      if (he != hipSuccess) return fail_hip(he, "dynamic tuning");
       int32_t enc = 0;  // a failed encode skipped every candidate: nothing was measured
       SPMM_HIP(hipMemcpy(&enc, h->status, sizeof(int32_t), hipMemcpyDeviceToHost));
       if (enc == 0) h->tuned[nc] = best;
