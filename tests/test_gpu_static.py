@@ -248,3 +248,36 @@ def test_slice_orders_at_large_n_all_paths(monkeypatch):
     torch.cuda.synchronize()
     assert st.item() == 0
     assert torch.equal(Ys[:, : cd.n], Yd[:, : cd.n])
+
+
+def test_large_n_full_size_sampled_columns():
+    """m = k = 8192, n = 16384, b = 16, d = 1/16, FP16 (units by row slices):
+    128 seeded columns against the oracle (exact by column separability),
+    every element within its rounding bound; the rest for finiteness."""
+    c = Case(8192, 8192, 16384, 16, 1 / 16, w="f16", seed=3)
+    _, Y = c.run_static()
+    cols = np.sort(np.random.default_rng(321).choice(16384, 128, replace=False))
+    got, ref = y_f64(Y, c)[:, cols], c.oracle(cols)
+    assert O.rel_fro(got, ref) <= 5e-3
+    assert_elementwise(got, ref, c.abs_oracle(cols), c.k, "f16")
+    assert torch.isfinite(Y[:, : c.n]).all().item()
+
+
+def test_b1_lds_full_size_sampled_rows_and_columns():
+    """m = k = 8192, n = 4096, b = 1, d = 1/8, FP16 (the LDS-staged kernel by
+    the rule): 64 seeded rows x 128 seeded columns against the oracle given
+    only those rows' entries (exact by row and column separability), every
+    element within its rounding bound."""
+    c = Case(8192, 8192, 4096, 1, 1 / 8, w="f16", seed=4)
+    _, Y = c.run_static()
+    g = np.random.default_rng(654)
+    rs = np.sort(g.choice(8192, 64, replace=False))
+    cs = np.sort(g.choice(4096, 128, replace=False))
+    sel = np.isin(c.rows, rs)
+    rows, cols, vals = c.rows[sel], c.cols[sel], c.vals64[sel]
+    ref = O.spmm_blockwise_columns(c.m, c.k, 1, rows, cols, vals, c.X64, cs)[rs]
+    bound = O.spmm_blockwise_columns(c.m, c.k, 1, rows, cols, np.abs(vals), np.abs(c.X64), cs)[rs]
+    got = y_f64(Y, c)[rs][:, cs]
+    assert O.rel_fro(got, ref) <= 5e-3
+    assert_elementwise(got, ref, bound, c.k, "f16")
+    assert torch.isfinite(Y[:, : c.n]).all().item()
