@@ -281,3 +281,18 @@ def test_b1_lds_full_size_sampled_rows_and_columns():
     assert O.rel_fro(got, ref) <= 5e-3
     assert_elementwise(got, ref, bound, c.k, "f16")
     assert torch.isfinite(Y[:, : c.n]).all().item()
+
+
+@pytest.mark.parametrize("b,n", [(4, 16384), (8, 8192)])
+def test_small_blocks_large_n_full_size_sampled_columns(b, n):
+    """m = k = 8192, d = 1/16, FP16 at large n: b = 4 at n = 16384 (the
+    LDS-staged kernel by the rule) and b = 8 at n = 8192 (the kernel without
+    LDS, units by row slices): 64 seeded columns against the oracle, every
+    element within its rounding bound."""
+    c = Case(8192, 8192, n, b, 1 / 16, w="f16", seed=5 + b)
+    _, Y = c.run_static()
+    cols = np.sort(np.random.default_rng(77 + b).choice(n, 64, replace=False))
+    got, ref = y_f64(Y, c)[:, cols], c.oracle(cols)
+    assert O.rel_fro(got, ref) <= 5e-3
+    assert_elementwise(got, ref, c.abs_oracle(cols), c.k, "f16")
+    assert torch.isfinite(Y[:, : c.n]).all().item()
